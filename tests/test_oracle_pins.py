@@ -1,0 +1,428 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against a closed form, an invariant of the
+transfer, a library routine (scipy/numpy), an energy derivative taken by a
+different route, exact rational arithmetic, or finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+from oracle import mpm_oracle as O
+
+DT = torch.float64
+
+
+def rand_rot(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def blob(rng, N, lo, hi):
+    return torch.from_numpy(rng.uniform(lo, hi, size=(N, 3)).astype(np.float32)).to(DT)
+
+
+def params(E=5e3, nu=0.3, rho=1e3, Vp=1e-6, sy=50.0, K=1e4, gamma=7.0):
+    return torch.tensor([E, nu, rho, Vp, sy, K, gamma], dtype=DT)
+
+
+# ---------------------------------------------------------------- weights
+def test_bspline_closed_form_values():
+    # quadratic B-spline at f = 1 (particle on a cell centre) and f = 1/2 (on a node)
+    x = torch.tensor([[1.0 / 32, 1.0 / 32, 1.0 / 32], [0.5 / 32, 0.5 / 32, 0.5 / 32]], dtype=DT)
+    base, W, d, _ = O.stencil(x, 32)
+    w1 = np.array([1 / 8, 3 / 4, 1 / 8])
+    w05 = np.array([1 / 2, 1 / 2, 0.0])
+    assert base[0].tolist() == [0, 0, 0] and base[1].tolist() == [0, 0, 0]
+    np.testing.assert_allclose(W[0].numpy(), np.einsum("a,b,c->abc", w1, w1, w1).reshape(-1), atol=1e-15)
+    np.testing.assert_allclose(W[1].numpy(), np.einsum("a,b,c->abc", w05, w05, w05).reshape(-1), atol=1e-15)
+
+
+def test_bspline_partition_of_unity_and_linear_reproduction():
+    rng = np.random.default_rng(0)
+    x = blob(rng, 500, 0.2, 0.8)
+    _, W, d, _ = O.stencil(x, 48)
+    np.testing.assert_allclose(W.sum(1).numpy(), 1.0, atol=1e-14)
+    np.testing.assert_allclose((W[..., None] * d).sum(1).numpy(), 0.0, atol=1e-16)
+    # second moment of the quadratic B-spline: sum w d d^T = dx^2/4 I
+    D = torch.einsum("pk,pki,pkj->pij", W, d, d)
+    np.testing.assert_allclose(D.numpy(), np.broadcast_to(np.eye(3) / (4 * 48 ** 2), D.shape), atol=1e-16)
+
+
+# ---------------------------------------------------------------- keys
+def test_base_cells_exact_at_boundaries():
+    n = 48
+    xs = []
+    for k in range(0, n - 2):
+        x0 = np.float32((k + 0.5) / n)
+        xs += [x0, np.nextafter(x0, np.float32(0)), np.nextafter(x0, np.float32(1))]
+    xs = np.array(xs, dtype=np.float32)
+    a = O.base_cells(xs, n)
+    b = O.base_cells_exact(xs, n)
+    assert (a == b).all()
+
+
+def test_cell_keys_bruteforce_and_stable_perm():
+    rng = np.random.default_rng(1)
+    n = 32
+    x = rng.uniform(0.1, 0.9, size=(300, 3)).astype(np.float32)
+    x[10] = x[11]  # a duplicate key: the stable order keeps 10 before 11
+    keys = O.cell_keys(x, n)
+    for p in range(len(x)):
+        b = [min(max(int(O.base_cells_exact(x[p:p + 1, a], n)[0]), 0), n - 3) for a in range(3)]
+        T = n // 4
+        tile = ((b[0] // 4) * T + b[1] // 4) * T + b[2] // 4
+        cell = ((b[0] % 4) * 4 + b[1] % 4) * 4 + b[2] % 4
+        assert keys[p] == tile * 64 + cell
+    perm = O.sort_permutation(keys)
+    sk = keys[perm]
+    assert (np.diff(sk) >= 0).all()
+    for j in range(len(perm) - 1):
+        if sk[j] == sk[j + 1]:
+            assert perm[j] < perm[j + 1]
+
+
+# ---------------------------------------------------------------- matrix functions vs library
+def test_matrix_functions_match_scipy():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((20, 3, 3))
+    spd = A @ A.transpose(0, 2, 1) + 0.3 * np.eye(3)
+    near_i = np.eye(3) + 0.05 * (A + A.transpose(0, 2, 1))
+    rots = [rand_rot(rng) for _ in range(5)]
+    rep = np.stack([R @ np.diag([1.2, 1.2, 0.7]) @ R.T for R in rots])   # a repeated eigenvalue
+    for Bs in (spd, near_i, rep):
+        Bt = torch.from_numpy(Bs)
+        L = O.logm_spd(Bt).numpy()
+        S = O.sqrtm_spd(Bt).numpy()
+        for i in range(len(Bs)):
+            np.testing.assert_allclose(L[i], scipy.linalg.logm(Bs[i]).real, atol=1e-11)
+            np.testing.assert_allclose(S[i], scipy.linalg.sqrtm(Bs[i]).real, atol=1e-11)
+    X = 0.7 * (A + A.transpose(0, 2, 1))
+    Ex = O.expm_sym(torch.from_numpy(X)).numpy()
+    for i in range(len(X)):
+        np.testing.assert_allclose(Ex[i], scipy.linalg.expm(X[i]), rtol=1e-12, atol=1e-12)
+    F = np.eye(3) + 0.4 * A
+    F = F[np.linalg.det(F) > 0.05]
+    R = O.polar_rotation(torch.from_numpy(F)).numpy()
+    for i in range(len(F)):
+        u, _ = scipy.linalg.polar(F[i])
+        np.testing.assert_allclose(R[i], u, atol=1e-12)
+
+
+# ---------------------------------------------------------------- constitutive
+ENERGY_MATS = [O.NEOHOOKEAN, O.COROTATED, O.VONMISES, O.FLUID_TAIT, O.FLUID_PAPER]
+
+
+def energy_density(mat, F, mu, lam, K, gamma):
+    """Strain-energy densities, written from singular values (a different route from the oracle)."""
+    J = torch.linalg.det(F)
+    if mat == O.NEOHOOKEAN:
+        Ic = (F * F).sum((-1, -2))
+        alpha = 1 + 3 * mu / (4 * lam)
+        return mu / 2 * (Ic - 3) + lam / 2 * (J - alpha) ** 2 - mu / 2 * torch.log(Ic + 1)
+    s = torch.linalg.svdvals(F)
+    if mat == O.COROTATED:
+        return mu * ((s - 1) ** 2).sum(-1) + lam / 2 * (J - 1) ** 2
+    if mat == O.VONMISES:
+        e = torch.log(s)
+        return mu * (e ** 2).sum(-1) + lam / 2 * e.sum(-1) ** 2
+    if mat == O.FLUID_TAIT:
+        # pressure p = K (J^-gamma - 1) = -dPsi/dJ
+        return -K * (J ** (1 - gamma) / (1 - gamma) - J)
+    if mat == O.FLUID_PAPER:
+        return lam / 2 * (J - 1) ** 2
+    raise ValueError
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_stress_is_energy_derivative(mat):
+    rng = np.random.default_rng(3 + mat)
+    A = rng.standard_normal((16, 3, 3))
+    F = torch.from_numpy(np.eye(3) + 0.15 * A).requires_grad_(True)
+    mu, lam = O.lame(torch.tensor(5e3, dtype=DT), torch.tensor(0.3, dtype=DT))
+    K, gam = torch.tensor(1e4, dtype=DT), torch.tensor(7.0, dtype=DT)
+    psi = energy_density(mat, F, mu, lam, K, gam).sum()
+    (P,) = torch.autograd.grad(psi, F)
+    tau_ref = P @ F.detach().transpose(-1, -2)
+    tau = O.stress(mat, F.detach(), mu, lam, K, gam)
+    np.testing.assert_allclose(tau.numpy(), tau_ref.numpy(), rtol=1e-9, atol=1e-8 * 5e3)
+    np.testing.assert_allclose(tau.numpy(), tau.transpose(-1, -2).numpy(), atol=1e-9 * 5e3)
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_stress_vanishes_at_rest_and_under_rotation(mat):
+    rng = np.random.default_rng(7)
+    mu, lam = O.lame(torch.tensor(5e3, dtype=DT), torch.tensor(0.3, dtype=DT))
+    K, gam = torch.tensor(1e4, dtype=DT), torch.tensor(7.0, dtype=DT)
+    F = torch.from_numpy(np.stack([np.eye(3)] + [rand_rot(rng) for _ in range(6)]))
+    tau = O.stress(mat, F, mu, lam, K, gam)
+    assert tau.abs().max().item() < 1e-9
+
+
+def test_fluid_stress_depends_only_on_J():
+    rng = np.random.default_rng(8)
+    F = torch.from_numpy(np.eye(3) + 0.2 * rng.standard_normal((10, 3, 3)))
+    J = torch.linalg.det(F)
+    Fi = (J ** (1 / 3))[:, None, None] * torch.eye(3, dtype=DT)
+    mu, lam = O.lame(torch.tensor(5e3, dtype=DT), torch.tensor(0.3, dtype=DT))
+    for mat in (O.FLUID_TAIT, O.FLUID_PAPER):
+        a = O.stress(mat, F, mu, lam, torch.tensor(1e4, dtype=DT), torch.tensor(7.0, dtype=DT))
+        b = O.stress(mat, Fi, mu, lam, torch.tensor(1e4, dtype=DT), torch.tensor(7.0, dtype=DT))
+        np.testing.assert_allclose(a.numpy(), b.numpy(), rtol=1e-12, atol=1e-9)
+
+
+# ---------------------------------------------------------------- return mapping
+def test_von_mises_return_closed_form():
+    rng = np.random.default_rng(9)
+    mu, lam = O.lame(torch.tensor(5e3, dtype=DT), torch.tensor(0.2, dtype=DT))
+    sy = torch.tensor(50.0, dtype=DT)
+    Y = O.YIELD_SCALE * 50.0 / (2 * mu.item())
+    for trial in range(40):
+        s = np.exp(rng.uniform(-0.08, 0.08, size=3))
+        R1, R2 = rand_rot(rng), rand_rot(rng)
+        F = torch.from_numpy((R1 @ np.diag(s) @ R2)[None])
+        Fp = O.project(O.VONMISES, F, mu, sy)[0].numpy()
+        e = np.log(s)
+        eh = e - e.mean()
+        nrm = np.linalg.norm(eh)
+        if nrm - Y > 0:
+            e_new = e.mean() + eh * (Y / nrm)      # on the yield surface, same trace
+            expect = R1 @ np.diag(np.exp(e_new)) @ R2
+            assert abs(np.linalg.norm(e_new - e_new.mean()) - Y) < 1e-12
+            assert abs(e_new.sum() - e.sum()) < 1e-12
+        else:
+            expect = F[0].numpy()                  # inside the yield surface: elastic
+        np.testing.assert_allclose(Fp, expect, atol=1e-12)
+
+
+def test_fluid_projection_keeps_volume():
+    rng = np.random.default_rng(10)
+    F = torch.from_numpy(np.eye(3) + 0.1 * rng.standard_normal((20, 3, 3)))
+    for mat in (O.FLUID_TAIT, O.FLUID_PAPER):
+        Fp = O.project(mat, F, torch.tensor(1.0, dtype=DT), torch.tensor(0.0, dtype=DT))
+        np.testing.assert_allclose(torch.linalg.det(Fp).numpy(), torch.linalg.det(F).numpy(), rtol=1e-13)
+        off = Fp - Fp.diagonal(dim1=-2, dim2=-1).mean(-1)[:, None, None] * torch.eye(3, dtype=DT)
+        assert off.abs().max().item() < 1e-15
+
+
+# ---------------------------------------------------------------- transfer invariants
+def scene(mat, N=400, n=32, lo=0.35, hi=0.6, seed=11, v_scale=0.5, F_scale=0.0, C_scale=0.0):
+    rng = np.random.default_rng(seed)
+    x = blob(rng, N, lo, hi)
+    v = torch.from_numpy(rng.uniform(-v_scale, v_scale, size=(N, 3))).to(DT)
+    C = torch.from_numpy(C_scale * rng.standard_normal((N, 3, 3)))
+    F = torch.from_numpy(np.eye(3) + F_scale * rng.standard_normal((N, 3, 3)))
+    env = O.Env(n=n, dt=1e-4, material=mat, gravity=(0.0, 0.0, 0.0))
+    return env, (x, v, C, F)
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_p2g_mass_exact_and_momentum_conserved(mat):
+    env, (x, v, C, F) = scene(mat, F_scale=0.05, C_scale=3.0)
+    prm = params(Vp=1e-5)
+    gm, gP, _ = O.p2g(env, prm, x, v, C, F)
+    mp = prm[2] * prm[3]
+    assert abs(gm.sum().item() - mp.item() * len(x)) <= 1e-14 * mp.item() * len(x)
+    # APIC and the stress impulse carry no net momentum: sum_i w d = 0
+    np.testing.assert_allclose(gP.sum(0).numpy(), (mp * v).sum(0).numpy(), rtol=0, atol=1e-13)
+    gv = O.grid_update(env, gm, gP, 0.0)
+    xn, vn, Cn, Fn = O.g2p(env, prm, x, F, gv)
+    # G2P conserves momentum: sum_p m_p v_p' = sum_i m_i v_i
+    np.testing.assert_allclose((mp * vn).sum(0).numpy(), (gm[:, None] * gv).sum(0).numpy(), atol=1e-13)
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_free_fall_closed_form(mat):
+    rng = np.random.default_rng(12)
+    N, n, S, dt = 300, 32, 12, 1e-4
+    x0 = blob(rng, N, 0.4, 0.6)
+    v0 = torch.tensor([0.3, -0.2, 0.1], dtype=DT)
+    g = torch.tensor([0.0, 0.0, -9.8], dtype=DT)
+    state = (x0, v0.expand(N, 3).clone(), torch.zeros(N, 3, 3, dtype=DT),
+             torch.eye(3, dtype=DT).expand(N, 3, 3).clone())
+    env = O.Env(n=n, dt=dt, material=mat, gravity=tuple(g.tolist()))
+    (x, v, C, F), oob = O.rollout(env, params(Vp=1e-6), state, S)
+    assert not oob
+    np.testing.assert_allclose(v.numpy(), (v0 + S * dt * g).expand(N, 3).numpy(), atol=1e-12)
+    np.testing.assert_allclose(x.numpy(), (x0 + S * dt * v0 + dt * dt * g * S * (S + 1) / 2).numpy(), atol=1e-13)
+    assert C.abs().max().item() < 1e-9
+    np.testing.assert_allclose(F.numpy(), np.broadcast_to(np.eye(3), F.shape), atol=1e-12)
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_rest_state_stays_at_rest(mat):
+    rng = np.random.default_rng(13)
+    N = 300
+    x0 = blob(rng, N, 0.4, 0.6)
+    state = (x0, torch.zeros(N, 3, dtype=DT), torch.zeros(N, 3, 3, dtype=DT),
+             torch.eye(3, dtype=DT).expand(N, 3, 3).clone())
+    env = O.Env(n=32, dt=1e-4, material=mat, gravity=(0.0, 0.0, 0.0))
+    (x, v, C, F), _ = O.rollout(env, params(Vp=1e-6), state, 5)
+    assert (x - x0).abs().max().item() < 1e-15
+    assert v.abs().max().item() < 1e-12
+
+
+def test_affine_velocity_field_is_reproduced():
+    # APIC reproduces v = v0 + B x exactly (tau = 0 with a zero-stiffness corotated body)
+    rng = np.random.default_rng(14)
+    N, n, dt = 400, 32, 1e-3
+    x = blob(rng, N, 0.35, 0.6)
+    B = torch.from_numpy(rng.standard_normal((3, 3)))
+    v0 = torch.tensor([0.1, 0.2, -0.3], dtype=DT)
+    v = v0 + x @ B.T
+    F0 = torch.from_numpy(np.eye(3) + 0.1 * rng.standard_normal((N, 3, 3)))
+    env = O.Env(n=n, dt=dt, material=O.COROTATED, gravity=(0.0, 0.0, 0.0))
+    prm = params(E=0.0, nu=0.3, Vp=1e-6)
+    xn, vn, Cn, Fn, _ = O.substep(env, prm, x, v, B.expand(N, 3, 3).clone(), F0, 0.0)
+    np.testing.assert_allclose(vn.numpy(), v.numpy(), atol=1e-12)
+    np.testing.assert_allclose(Cn.numpy(), B.expand(N, 3, 3).numpy(), atol=1e-10)
+    np.testing.assert_allclose(xn.numpy(), (x + dt * v).numpy(), atol=1e-14)
+    np.testing.assert_allclose(Fn.numpy(), ((torch.eye(3, dtype=DT) + dt * B) @ F0).numpy(), atol=1e-12)
+
+
+@pytest.mark.parametrize("mat", ENERGY_MATS)
+def test_grid_force_is_minus_energy_gradient(mat):
+    # the MLS-MPM stress impulse equals -dt dE/du_i, E = sum_p Vp Psi((I + sum_i 4 n^2 w u_i d^T) F)
+    rng = np.random.default_rng(15 + mat)
+    N, n, dt, Vp = 200, 32, 1e-4, 2e-6
+    x = blob(rng, N, 0.4, 0.55)
+    F = torch.from_numpy(np.eye(3) + 0.08 * rng.standard_normal((N, 3, 3)))
+    prm = params(Vp=Vp)
+    env = O.Env(n=n, dt=dt, material=mat, gravity=(0.0, 0.0, 0.0))
+    zeros3 = torch.zeros(N, 3, dtype=DT)
+    gm, gP, _ = O.p2g(env, prm, x, zeros3, torch.zeros(N, 3, 3, dtype=DT), F)
+    base, W, d, _ = O.stencil(x, n)
+    lin = O.node_index(base, n)
+    u = torch.zeros(n ** 3, 3, dtype=DT, requires_grad=True)
+    ui = u[lin]                                                 # [N,27,3]
+    Fhat = (torch.eye(3, dtype=DT) + 4 * n * n * torch.einsum("pk,pki,pkj->pij", W, ui, d)) @ F
+    mu, lam = O.lame(prm[0], prm[1])
+    energy = Vp * energy_density(mat, Fhat, mu, lam, prm[5], prm[6]).sum()
+    (gE,) = torch.autograd.grad(energy, u)
+    np.testing.assert_allclose(gP.numpy(), (-dt * gE).numpy(), rtol=1e-9, atol=1e-9 * gP.abs().max().item())
+
+
+# ---------------------------------------------------------------- grid boundary pieces
+def test_walls_zero_the_boundary_layer():
+    n, b = 16, 3
+    wm = O.wall_mask(n, b).reshape(n, n, n)
+    assert wm[:b].all() and wm[n - b:].all() and wm[:, :b].all() and wm[:, :, n - b:].all()
+    assert not wm[b:n - b, b:n - b, b:n - b].any()
+    assert int(wm.sum()) == n ** 3 - (n - 2 * b) ** 3
+
+
+def test_contact_projection_hand_values():
+    # one node deep inside a static box (s = 1) moving against the +x face's normal
+    n = 16
+    box = O.Box(center=(0.5, 0.5, 0.5), half=(0.2, 0.2, 0.2), velocity=(0.0, 0.0, 0.0), alpha=32.0, mu_b=0.5)
+    env = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=box)
+    pos = O.node_positions(n)
+    i_in = int(((pos - torch.tensor([0.6875, 0.5, 0.5], dtype=DT)).abs().sum(1)).argmin())  # d = -0.0125, normal +x
+    v = torch.zeros(n ** 3, 3, dtype=DT)
+    act = torch.ones(n ** 3, dtype=torch.bool)
+    cases = [((-1.0, 0.2, 0.0), (0.0, 0.0, 0.0)),        # |u_t| = 0.2 <= 0.5: sticks
+             ((-1.0, 2.0, 0.0), (0.0, 1.5, 0.0)),        # slides: u_t (1 - 0.5 * 1 / 2)
+             ((1.0, 2.0, 0.0), (1.0, 2.0, 0.0))]         # separating: unchanged
+    for vin, vout in cases:
+        v[i_in] = torch.tensor(vin, dtype=DT)
+        out = O.collide(env, v, 0.0, act)
+        np.testing.assert_allclose(out[i_in].numpy(), vout, atol=1e-14)
+    # a node outside at distance d: blend s = exp(-alpha d) of projected and free velocity
+    i_out = int(((pos - torch.tensor([0.75, 0.5, 0.5], dtype=DT)).abs().sum(1)).argmin())  # d = 0.05
+    v[i_out] = torch.tensor([-1.0, 0.2, 0.0], dtype=DT)
+    out = O.collide(env, v, 0.0, act)
+    s = math.exp(-32.0 * 0.05)
+    np.testing.assert_allclose(out[i_out].numpy(), [(1 - s) * -1.0, (1 - s) * 0.2, 0.0], atol=1e-14)
+
+
+# ---------------------------------------------------------------- gradients
+def tiny(mat, collider=False, seed=20, N=48):
+    rng = np.random.default_rng(seed)
+    n = 16
+    x = blob(rng, N, 0.36, 0.55)
+    v = torch.from_numpy(rng.uniform(-0.5, 0.5, size=(N, 3)))
+    C = torch.from_numpy(2.0 * rng.standard_normal((N, 3, 3)))
+    Fs = np.full((N, 1, 1), 0.05)
+    if mat == O.VONMISES:
+        Fs[::2] = 0.12      # half the particles start beyond the yield surface, half well inside
+        Fs[1::2] = 0.002
+    F = torch.from_numpy(np.eye(3) + Fs * rng.standard_normal((N, 3, 3)))
+    if mat in (O.FLUID_TAIT, O.FLUID_PAPER):
+        F = (torch.linalg.det(F) ** (1 / 3))[:, None, None] * torch.eye(3, dtype=DT)
+    box = None
+    if collider:
+        box = O.Box(center=(0.62, 0.45, 0.45), half=(0.05, 0.2, 0.2), velocity=(-0.3, 0.0, 0.0),
+                    alpha=2.0 * n, mu_b=0.5)
+    env = O.Env(n=n, dt=2e-4, material=mat, collider=box)
+    prm = params(E=5e3, nu=0.3, Vp=(0.19 ** 3) / N, sy=30.0)
+    return env, prm, (x, v, C, F)
+
+
+GRAD_CASES = [(m, False) for m in ENERGY_MATS] + [(O.FLUID_TAIT, True)]
+
+
+@pytest.mark.parametrize("mat,collider", GRAD_CASES)
+def test_reverse_mode_matches_forward_mode(mat, collider):
+    env, prm, st = tiny(mat, collider)
+    S = 3
+    rng = np.random.default_rng(30)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp = O.rollout_vjp(env, prm, st, S, cot)
+    for _ in range(4):
+        tan = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+        tp = torch.from_numpy(rng.standard_normal(7)) * prm.abs() * 1e-3
+        out = O.rollout_jvp(env, prm, st, S, tan, tp)
+        lhs = sum((a * b).sum() for a, b in zip(out, cot)).item()
+        rhs = (sum((a * b).sum() for a, b in zip(tan, g)) + (gp * tp).sum()).item()
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs))
+
+
+def _loss(env, prm, st, S, cot):
+    (x, v, C, F), _ = O.rollout(env, prm, st, S)
+    return sum((a * b).sum() for a, b in zip((x, v, C, F), cot)).item()
+
+
+@pytest.mark.parametrize("mat,collider", GRAD_CASES)
+def test_reverse_mode_matches_central_differences(mat, collider):
+    env, prm, st = tiny(mat, collider)
+    S = 3
+    rng = np.random.default_rng(31)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp = O.rollout_vjp(env, prm, st, S, cot)
+    # random directions in state space and along E (and sigma_y for von Mises)
+    for trial in range(3):
+        tan = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+        if mat in (O.FLUID_TAIT, O.FLUID_PAPER):
+            tan[3] = torch.zeros_like(tan[3])
+        scale = [1e-6, 1e-6, 1e-6, 1e-6]
+        h = [s * t for s, t in zip(scale, tan)]
+        plus = [a + b for a, b in zip(st, h)]
+        minus = [a - b for a, b in zip(st, h)]
+        fd = (_loss(env, prm, plus, S, cot) - _loss(env, prm, minus, S, cot)) / 2
+        an = sum((a * b).sum() for a, b in zip(h, g)).item()
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * sum(abs(x) for x in (fd, an)) + 1e-12), (fd, an)
+    for k in (0, 1, 4, 5, 6):
+        if prm[k] == 0:
+            continue
+        hk = 1e-6 * prm[k].item()
+        pp, pm = prm.clone(), prm.clone()
+        pp[k] += hk
+        pm[k] -= hk
+        fd = (_loss(env, pp, st, S, cot) - _loss(env, pm, st, S, cot)) / (2 * hk)
+        an = gp[k].item()
+        assert abs(fd - an) <= 1e-5 * max(abs(an), abs(fd)) + 1e-9, (k, fd, an)
+
+
+def test_von_mises_tiny_scene_is_plastic():
+    # the gradient cases above must exercise the return mapping, not only the elastic branch
+    env, prm, (x, v, C, F) = tiny(O.VONMISES)
+    mu, _ = O.lame(prm[0], prm[1])
+    Fp = O.project(O.VONMISES, F, mu, prm[4])
+    moved = ((Fp - F).flatten(1).norm(dim=1) > 1e-12).sum().item()
+    assert 0 < moved < len(F)

@@ -1,0 +1,201 @@
+"""Throughput of the differentiable MLS-MPM substep on one MI355X.
+
+One step = one pass of the whole path over the workload: load the initial
+state (device to device), forward S substeps with recording (checkpoints every
+K, the particle sort at each checkpoint), then the backward from the
+cotangent of L = sum_p x_p . w_p to the initial state and per-env parameters
+(segments recomputed from checkpoints). Inputs are resident in HBM before the
+timed region.
+
+Default workload: 32 identical environments on 48^3 grids, 20,000 corotated
+particles each (E = 1e4, nu = 0.25), 80 substeps at dt = 5e-5, checkpoint
+interval 10. Metric: fwd+bwd particle-substeps/s of the batched mode; the
+per-environment mode, forward-only rate and p50/p99 per-step latency are
+reported beside it, with a roofline entry for the dominant kernel and the FP64
+oracle timed on the host as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per particle per launch of each kernel class (FP32 state:
+# x 12, v 12, C 36, F 36 = 96 B) -- grid-node traffic is counted separately
+ALG_BYTES_PER_PARTICLE = {
+    "p2g": 96,          # read x, v, C, F
+    "g2p": 48 + 96,     # read x, F; write x, v, C, F
+    "g2p_adj": 48 + 96 + 48,   # read x, F, the state cotangent; write the partial x/F cotangent
+    "p2g_adj": 96 + 48 + 96,   # read state and partial cotangent; write the state cotangent
+    "sort": 96 + 96 + 4 * 8,   # permute read + write, keys/values
+}
+# algorithmic bytes per touched grid node per launch
+ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched_corot",
+                    choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh"])
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-substeps", type=int, default=2)
+    ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
+    return ap.parse_args()
+
+
+def touched_nodes(envs, wall_pad=2):
+    """Grid nodes inside the stencils of the initial particles (per env, summed)."""
+    from oracle import mpm_oracle  # noqa: F401  (keeps imports symmetric; not used for arithmetic)
+    total = 0
+    for e in envs:
+        b = np.floor(e.x.astype(np.float64) * e.n - 0.5).astype(np.int64)
+        occ = np.zeros((e.n,) * 3, dtype=bool)
+        for ox in range(3):
+            for oy in range(3):
+                for oz in range(3):
+                    occ[b[:, 0] + ox, b[:, 1] + oy, b[:, 2] + oz] = True
+        total += int(occ.sum())
+    return total
+
+
+def run_steps(batch, x0, w, S, steps, warmup, record=True, backward=True):
+    import torch
+    stream = batch.stream
+    times = []
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        batch.set_particles(*x0)
+        batch.forward(S, record=record)
+        if backward:
+            batch.backward(gx=w)
+        ev1.record(stream)
+        if i >= warmup:
+            times.append((ev0, ev1))
+    torch.cuda.synchronize()
+    batch.sync()
+    ms = [a.elapsed_time(b) for a, b in times]
+    return ms
+
+
+def cpu_baseline(wl, substeps):
+    """The FP64 oracle on a bounded sample: one env, `substeps` substeps, forward + reverse."""
+    import torch
+    from oracle import mpm_oracle as O
+    spec = wl.envs[0]
+    env, prm, st = O.env_from_spec(spec)
+    cot = O.linear_loss_cotangent(wl.loss_weights[0], spec.n_particles)
+    threads = torch.get_num_threads()
+    t0 = time.perf_counter()
+    O.rollout_vjp(env, prm, st, substeps, cot)   # forward (stores states) + per-substep reverse
+    dt = time.perf_counter() - t0
+    rate = spec.n_particles * substeps / dt
+    return {"value": rate, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 env of {wl.name} ({spec.n_particles} particles), {substeps} substeps fwd+bwd, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: environments never exchange data, and this build "
+              "runs on a single MI355X (see the sharding note in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2412_12089_amd import scenes
+    from paper_2412_12089_amd.batch import Batch
+
+    wl = scenes.WORKLOADS[args.workload]()
+    S, K = wl.substeps, wl.ckpt_every
+    envs = wl.envs
+    N = sum(e.n_particles for e in envs)
+    dev = torch.device("cuda:0")
+    cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in envs], axis=0)).to(dev)
+    x0 = (cat("x"), cat("v"), cat("C"), cat("F"))
+    w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
+
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode="batched", device=dev)
+    ms = run_steps(b, x0, w, S, args.steps, args.warmup)
+    if args.profile:
+        print(json.dumps({"profile_ms_per_step": float(np.mean(ms))}), flush=True)
+        return
+    step_ms = float(np.mean(ms))
+    value = N * S / (step_ms * 1e-3)
+    # forward-only rate
+    fwd_ms = float(np.mean(run_steps(b, x0, w, S, max(1, args.steps // 2), 1, record=False, backward=False)))
+    # roofline pass: per-kernel HIP events on the library's stream
+    b.set_timing(True)
+    b.set_particles(*x0)
+    b.forward(S, record=True)
+    kt_f = {k: b.kernel_time(k) for k in ("p2g", "grid", "g2p", "sort")}
+    b.backward(gx=w)
+    kt_b = {k: b.kernel_time(k) for k in ("g2p_adj", "grid_adj", "p2g_adj")}
+    # the forward inside backward (recompute) is not separately timed; p2g/grid/g2p come from the forward
+    b.set_timing(False)
+    kt = {**kt_f, **kt_b}
+    mem = b.memory_bytes()
+    b.close()
+    nodes = touched_nodes(envs)
+    totals = {k: v[0] * v[1] for k, v in kt.items()}
+    dom = max((k for k in totals if k in ALG_BYTES_PER_PARTICLE), key=lambda k: totals[k])
+    dom_ms = kt[dom][0]
+    alg_bytes = ALG_BYTES_PER_PARTICLE[dom] * N + ALG_BYTES_PER_NODE.get(dom, 0) * nodes
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+
+    plain = None
+    if args.plain_steps > 0:
+        bp = Batch(envs, max_substeps=S, ckpt_every=K, mode="plain", device=dev)
+        pms = run_steps(bp, x0, w, S, args.plain_steps, 1)
+        bp.close()
+        plain = N * S / (float(np.mean(pms)) * 1e-3)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps)
+    out = {
+        "metric": "fwd+bwd particle-substeps/s (batched)",
+        "value": value,
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "envs": len(envs), "particles": N, "grid": envs[0].n,
+                   "substeps": S, "ckpt_every": K, "material": scenes.MATERIAL_NAMES[envs[0].material]},
+        "per_env_value": plain,
+        "batched_over_per_env": (value / plain) if plain else None,
+        "fwd_only_value": N * S / (fwd_ms * 1e-3),
+        "p50_ms": float(np.percentile(ms, 50)),
+        "p99_ms": float(np.percentile(ms, 99)),
+        "hbm_resident_bytes": mem,
+        "kernel_ms": {k: v[0] for k, v in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * mpm.h -- C interface of a batched, differentiable MLS-MPM substep library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * What it computes. One substep of the moving-least-squares material point
+ * method with APIC transfer, per environment (paper: Appendix D.3 "Material
+ * point method"; the transfer is Hu et al. 2018's MLS-MPM, cited there):
+ *   P2G   m_i += w m_p,  P_i += w (m_p v_p + A_p d),  A_p = -dt V_p 4 n^2 tau_p + m_p C_p
+ *   grid  v_i = P_i / m_i + dt g (m_i > 0, else 0), softened box contact, sticky walls
+ *   G2P   v_p = sum w v_i,  C_p = 4 n^2 sum w v_i d^T,  x_p += dt v_p,  F_p <- Proj((I + dt C_p) F_p)
+ * with the quadratic B-spline w, base node floor(x n - 1/2), d = node - x,
+ * and Kirchhoff stress tau per material (stable neo-Hookean of Appendix D.2,
+ * fixed corotated, von Mises/Hencky with return mapping, weakly compressible
+ * fluid with F -> J^(1/3) I). The reverse-mode adjoint (Appendix D,
+ * "simulation gradient" chain) maps cotangents of the final state to
+ * cotangents of the initial state and of each environment's parameters; the
+ * forward is recomputed from checkpoints (Section 5.1, gradient
+ * checkpointing).
+ *
+ * Domain and grid. Each environment lives in the unit cube [0,1]^3 on n^3
+ * nodes at i/n (n a multiple of 4, n >= 12). Particles must stay in the
+ * stencil band 0.5/n <= x < (n - 1.5)/n on every axis; a particle outside is
+ * clamped to the band and reported as MPM_OUT_OF_DOMAIN.
+ *
+ * Conventions for every call:
+ *  - Return value is a status code (MPM_OK = 0 or one of the codes below);
+ *    no C++ exception crosses this interface. mpm_last_error() gives text.
+ *  - Particle arrays are row-major float32, array-of-structs: x and v are
+ *    [n, 3], C and F are [n, 3, 3]. Unless stated otherwise they are DEVICE
+ *    pointers on the batch's device, owned by the caller, read or written
+ *    only during the call's stream work; the library keeps no pointer.
+ *  - All device work is enqueued on the stream given at creation (a
+ *    hipStream_t, NULL = the legacy default stream). Calls return once work
+ *    is enqueued; mpm_sync() waits for it and reports device-side errors
+ *    (non-finite state, particles out of the band).
+ *  - One batch is used by one host thread at a time.
+ */
+#ifndef MPM_H_
+#define MPM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MPM_OK 0
+#define MPM_INVALID_ARG 1    /* null pointer, env index, n, nu outside (-1, 0.5), E < 0, dt <= 0, ... */
+#define MPM_OUT_OF_MEMORY 2  /* the allocator failed */
+#define MPM_DEVICE_ERROR 3   /* a HIP call failed */
+#define MPM_NONFINITE 4      /* a NaN/Inf appeared in the particle state */
+#define MPM_OUT_OF_DOMAIN 5  /* a particle left the stencil band (it was clamped) */
+#define MPM_BAD_STATE 6      /* backward without a recorded forward, substeps above the maximum, ... */
+
+/* materials (paper Appendix D.2 / D.3) */
+#define MPM_NEOHOOKEAN 0   /* stable neo-Hookean energy, alpha = 1 + 3 mu / (4 lam) */
+#define MPM_COROTATED 1    /* fixed corotated: tau = 2 mu (F - R) F^T + lam J (J - 1) I */
+#define MPM_VONMISES 2     /* Hencky elasticity + von Mises return mapping */
+#define MPM_FLUID_TAIT 3   /* tau = -J K (J^-gamma - 1) I, F projected to J^(1/3) I */
+#define MPM_FLUID_PAPER 4  /* tau = lam J (J - 1) I, F projected to J^(1/3) I */
+
+/* execution modes */
+#define MPM_MODE_PLAIN 0    /* per environment: its own launches, one thread per particle, global atomics */
+#define MPM_MODE_BATCHED 1  /* every environment in one launch per kernel, LDS-staged scatter, hipGraph */
+
+/* mpm_forward flags */
+#define MPM_FWD_RECORD 1    /* keep checkpoints and the last segment's tape for mpm_backward */
+
+typedef struct mpm_batch mpm_batch;
+
+/* One environment's fixed settings. */
+typedef struct {
+  int32_t n;            /* grid nodes per axis: multiple of 4, >= 12 */
+  int32_t material;     /* MPM_NEOHOOKEAN ... MPM_FLUID_PAPER */
+  int64_t n_particles;  /* >= 0 */
+  float dt;             /* substep length, > 0 */
+  float gravity[3];     /* body acceleration applied on the grid */
+  int32_t wall;         /* sticky wall thickness in nodes (>= 0, 2*wall + 3 <= n) */
+  int32_t reserved;
+} mpm_env_desc;
+
+typedef struct {
+  int32_t n_envs;              /* >= 1 */
+  const mpm_env_desc* envs;    /* host array [n_envs], read during the call */
+  int32_t max_substeps;        /* upper bound on n_substeps per mpm_forward */
+  int32_t ckpt_every;          /* K: checkpoint (and re-sort) interval in substeps, >= 1 */
+  int32_t mode;                /* MPM_MODE_PLAIN or MPM_MODE_BATCHED */
+  int32_t reserved;
+} mpm_batch_desc;
+
+/* Optional device-memory provider. alloc returns a device pointer aligned to
+ * at least 256 bytes, or NULL on failure; free releases it. Both are called
+ * from the host thread that calls into the library. NULL = hipMalloc/hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} mpm_allocator;
+
+/* Creates a batch: allocates the particle state, checkpoints, the tape of one
+ * segment and the grids (through `alloc` if given), on the current device.
+ * `stream` is a hipStream_t. Parameters start as E = 0 (inert); set them with
+ * mpm_set_material. Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR. */
+int mpm_batch_create(const mpm_batch_desc* desc, const mpm_allocator* alloc, void* stream, mpm_batch** out);
+
+/* Waits for the batch's stream, frees all memory, destroys the handle. */
+int mpm_batch_destroy(mpm_batch* b);
+
+/* Copies particle state in (device pointers, AoS layout above). env >= 0 sets
+ * that environment (n must equal its n_particles); env = -1 sets every
+ * environment from arrays concatenated in env order (n = total). The batch
+ * clock restarts at t = 0 and any recorded tape is dropped. */
+int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v, const float* C, const float* F,
+                      int64_t n);
+
+/* Copies the current particle state out in the caller's original particle
+ * order (device pointers; any of the four may be NULL to skip it). env = -1
+ * writes all environments concatenated. */
+int mpm_get_particles(mpm_batch* b, int32_t env, float* x, float* v, float* C, float* F);
+
+/* Material and parameters of one environment (env = -1: all). `params` is a
+ * HOST array of 8 doubles: E, nu, rho, Vp (particle volume), sigma_y, K
+ * (Tait bulk modulus), gamma (Tait exponent), reserved. Lame parameters are
+ * derived on the device (mu = E / (2 (1 + nu)), lam = E nu / ((1 + nu)(1 - 2 nu))).
+ * Errors: INVALID_ARG for an unknown material, nu outside (-1, 0.5), E, rho or
+ * Vp negative, gamma <= 0 for a Tait fluid. */
+int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double params[8]);
+
+/* One-way coupled kinematic box for env (paper Appendix D.3, softened contact
+ * after PlasticineLab): centre c(t) = center + t vel, half extents `half`,
+ * contact strength s = min(exp(-alpha d), 1) for the node's signed distance
+ * d, Coulomb friction mu_b on the velocity relative to the box. Host arrays.
+ * alpha <= 0 removes the collider. */
+int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const float half[3], const float vel[3],
+                         float alpha, float mu_b);
+
+/* Advances every environment by n_substeps (0 <= n <= max_substeps) from the
+ * current state and clock. Particles are re-sorted by cell at every
+ * checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)
+ * and the last segment's states and grids are kept for mpm_backward;
+ * otherwise any earlier record is dropped. Asynchronous on the stream. */
+int mpm_forward(mpm_batch* b, int32_t n_substeps, int32_t flags);
+
+/* Reverse-mode adjoint of the last recorded mpm_forward. Inputs: cotangents
+ * of the final state (device, AoS over all environments in original order;
+ * NULL = zero). Outputs: cotangents of the state at the start of that forward
+ * (device, same layout; NULL = not wanted) and, if dparams != NULL, a DEVICE
+ * array [n_envs][8] of doubles receiving dL/d(E, nu, rho, Vp, sigma_y, K,
+ * gamma, 0). Segments are recomputed from checkpoints. The record stays valid
+ * (backward may be called again with other cotangents).
+ * Errors: BAD_STATE if no recorded forward precedes. */
+int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC, const float* gF, float* dx0,
+                 float* dv0, float* dC0, float* dF0, double* dparams);
+
+/* Times the batched kernels' launch shapes on the current state (for about
+ * budget_ms milliseconds), keeps the fastest whose forward result agrees
+ * with the one-thread-per-particle kernels, and restores the state.
+ * Synchronizes the stream. */
+int mpm_autotune(mpm_batch* b, int32_t budget_ms);
+
+/* Binning of the current state without changing it (the paper is silent on
+ * binning; the key orders particles by env, 4^3-node tile and stencil base
+ * cell). Writes, as DEVICE arrays over the current internal particle order:
+ * keys[i] = (env << cell_bits) | (tile * 64 + cell) with base clamped to
+ * [0, n-3], tile = ((bx/4) T + by/4) T + bz/4, T = n/4, cell =
+ * ((bx%4) 4 + by%4) 4 + bz%4 (uint32 [N]); perm, the stable sort order (new
+ * position j takes internal position perm[j], uint32 [N]); ids, the caller
+ * index of each internal position (int32 [N]). *cell_bits is a host int.
+ * Any output pointer may be NULL. */
+int mpm_sort_keys(mpm_batch* b, uint32_t* keys, uint32_t* perm, int32_t* ids, int32_t* cell_bits);
+
+/* Waits for the stream and returns the first pending device-side error
+ * (MPM_NONFINITE / MPM_OUT_OF_DOMAIN) or MPM_OK; clears it. */
+int mpm_sync(mpm_batch* b);
+
+/* Per-environment error bits of the last mpm_sync (1: non-finite, 2: out of
+ * the band) into the host array errs[n_envs]. */
+int mpm_env_errors(mpm_batch* b, int32_t* errs);
+
+/* Device bytes held by the batch. */
+int64_t mpm_memory_bytes(const mpm_batch* b);
+
+/* Mean duration in milliseconds of the named kernel class over the last
+ * mpm_forward / mpm_backward when timing is enabled (see mpm_set_timing).
+ * kernel: 0 P2G, 1 grid update, 2 G2P, 3 sort+permute, 4 G2P adjoint,
+ * 5 grid adjoint, 6 P2G adjoint. Returns the number of launches timed. */
+int mpm_kernel_time(mpm_batch* b, int32_t kernel, double* mean_ms);
+int mpm_set_timing(mpm_batch* b, int32_t enabled);
+
+/* Text of the last error on this batch ("" if none); a static string if b is NULL. */
+const char* mpm_last_error(const mpm_batch* b);
+
+/* Library version string. */
+const char* mpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPM_H_ */

@@ -1,0 +1,119 @@
+"""ctypes declarations of the C interface in include/mpm.h (argument marshalling only).
+
+Every function here has the name and argument order of its C counterpart.
+Device arrays are passed as torch CUDA tensors (or None for a NULL pointer);
+the library does all the work on the device. Loading fails loudly when the
+built library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpmx.so")
+
+MPM_OK = 0
+MPM_INVALID_ARG = 1
+MPM_OUT_OF_MEMORY = 2
+MPM_DEVICE_ERROR = 3
+MPM_NONFINITE = 4
+MPM_OUT_OF_DOMAIN = 5
+MPM_BAD_STATE = 6
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE_ERROR", 4: "NONFINITE",
+                5: "OUT_OF_DOMAIN", 6: "BAD_STATE"}
+
+MPM_MODE_PLAIN = 0
+MPM_MODE_BATCHED = 1
+MPM_FWD_RECORD = 1
+
+KERNEL_CLASSES = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj")
+
+# every symbol include/mpm.h declares
+EXPORTED = (
+    "mpm_batch_create", "mpm_batch_destroy", "mpm_set_particles", "mpm_get_particles", "mpm_set_material",
+    "mpm_set_box_collider", "mpm_forward", "mpm_backward", "mpm_autotune", "mpm_sync", "mpm_env_errors",
+    "mpm_memory_bytes", "mpm_kernel_time", "mpm_set_timing", "mpm_last_error", "mpm_version", "mpm_sort_keys",
+)
+
+
+class mpm_env_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("material", ctypes.c_int32), ("n_particles", ctypes.c_int64),
+                ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3), ("wall", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class mpm_batch_desc(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("envs", ctypes.POINTER(mpm_env_desc)),
+                ("max_substeps", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class mpm_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmpmx.so and declare its prototypes (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() (hipcc for gfx950)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    F3 = P(ctypes.c_float)
+    D8 = P(ctypes.c_double)
+    sig = {
+        "mpm_batch_create": (I32, [P(mpm_batch_desc), P(mpm_allocator), VP, P(VP)]),
+        "mpm_batch_destroy": (I32, [VP]),
+        "mpm_set_particles": (I32, [VP, I32, VP, VP, VP, VP, I64]),
+        "mpm_get_particles": (I32, [VP, I32, VP, VP, VP, VP]),
+        "mpm_set_material": (I32, [VP, I32, I32, D8]),
+        "mpm_set_box_collider": (I32, [VP, I32, F3, F3, F3, ctypes.c_float, ctypes.c_float]),
+        "mpm_forward": (I32, [VP, I32, I32]),
+        "mpm_backward": (I32, [VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+        "mpm_autotune": (I32, [VP, I32]),
+        "mpm_sync": (I32, [VP]),
+        "mpm_env_errors": (I32, [VP, P(I32)]),
+        "mpm_memory_bytes": (I64, [VP]),
+        "mpm_kernel_time": (I32, [VP, I32, P(ctypes.c_double)]),
+        "mpm_set_timing": (I32, [VP, I32]),
+        "mpm_last_error": (ctypes.c_char_p, [VP]),
+        "mpm_version": (ctypes.c_char_p, []),
+        "mpm_sort_keys": (I32, [VP, VP, VP, VP, P(I32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def ptr(t) -> int:
+    """Device address of a tensor (None -> NULL)."""
+    return None if t is None else t.data_ptr()
+
+
+class MPMError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)} ({msg})")
+        self.code = code
+
+
+def check(code: int, where: str, handle=None):
+    if code != MPM_OK:
+        msg = ""
+        if _lib is not None:
+            raw = _lib.mpm_last_error(handle)
+            msg = raw.decode() if raw else ""
+        raise MPMError(code, where, msg)
+    return code

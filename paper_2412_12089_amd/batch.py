@@ -1,0 +1,230 @@
+"""Python face of the C interface: a batch handle and a differentiable rollout.
+
+Argument marshalling only: tensors are handed to libmpmx as device pointers,
+torch supplies device memory (through the allocator callbacks) and the
+stream, and every step of the substep runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _capi as C
+from .scenes import EnvSpec
+
+
+class TorchAllocator:
+    """mpm_allocator backed by torch's caching allocator on one device."""
+
+    def __init__(self, device: torch.device):
+        self.device = device
+        self.live = {}
+        self._alloc = C.ALLOC_FN(self._alloc_impl)
+        self._free = C.FREE_FN(self._free_impl)
+        self.struct = C.mpm_allocator(self._alloc, self._free, None)
+
+    def _alloc_impl(self, nbytes, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free_impl(self, p, ctx):
+        self.live.pop(int(p) if p is not None else 0, None)
+
+
+def _f32(t: torch.Tensor, device) -> torch.Tensor:
+    return t.to(device=device, dtype=torch.float32).contiguous()
+
+
+class Batch:
+    """A set of environments simulated together (wraps mpm_batch_*)."""
+
+    def __init__(self, envs: Sequence[EnvSpec], max_substeps: int, ckpt_every: int,
+                 mode: str = "batched", device: Optional[torch.device] = None,
+                 torch_memory: bool = True, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = C.load()
+        self.device = torch.device(device or "cuda")
+        self.envs = list(envs)
+        self.E = len(self.envs)
+        self.counts = [e.n_particles for e in self.envs]
+        self.N = int(sum(self.counts))
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self.max_substeps = int(max_substeps)
+        self.ckpt_every = int(ckpt_every)
+        self.mode = C.MPM_MODE_PLAIN if mode == "plain" else C.MPM_MODE_BATCHED
+        descs = (C.mpm_env_desc * self.E)()
+        for d, e in zip(descs, self.envs):
+            d.n = e.n
+            d.material = e.material
+            d.n_particles = e.n_particles
+            d.dt = e.dt
+            d.gravity[:] = list(e.gravity)
+            d.wall = e.wall
+        self._descs = descs
+        bd = C.mpm_batch_desc(self.E, descs, self.max_substeps, self.ckpt_every, self.mode, 0)
+        self.allocator = TorchAllocator(self.device) if torch_memory else None
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            C.check(self.lib.mpm_batch_create(ctypes.byref(bd),
+                                              ctypes.byref(self.allocator.struct) if self.allocator else None,
+                                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+                    "mpm_batch_create")
+        self.h = handle
+        self.record_token = 0
+        for i, e in enumerate(self.envs):
+            self.set_material(i, e.material, e.params())
+            if e.collider is not None:
+                c = e.collider
+                self.set_box_collider(i, c.center, c.half, c.velocity, c.alpha, c.mu_b)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mpm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, code, where):
+        return C.check(code, where, self.h)
+
+    # -- parameters
+    def set_material(self, env: int, material: int, params) -> None:
+        p = (ctypes.c_double * 8)(*[float(v) for v in np.asarray(params, dtype=np.float64).reshape(8)])
+        self._chk(self.lib.mpm_set_material(self.h, env, material, p), "mpm_set_material")
+
+    def set_box_collider(self, env: int, center, half, velocity, alpha: float, mu_b: float) -> None:
+        f3 = lambda a: (ctypes.c_float * 3)(*[float(x) for x in a])
+        self._chk(self.lib.mpm_set_box_collider(self.h, env, f3(center), f3(half), f3(velocity),
+                                                float(alpha), float(mu_b)), "mpm_set_box_collider")
+
+    # -- state
+    def set_particles(self, x, v, Cm, F, env: int = -1) -> None:
+        d = self.device
+        x, v, Cm, F = (_f32(t, d) for t in (x, v, Cm, F))
+        n = x.shape[0]
+        self._keep = (x, v, Cm, F)   # alive until the copy kernel has run on the stream
+        self._chk(self.lib.mpm_set_particles(self.h, env, C.ptr(x), C.ptr(v), C.ptr(Cm), C.ptr(F), n),
+                  "mpm_set_particles")
+
+    def set_particles_from_specs(self) -> None:
+        cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in self.envs], axis=0))
+        self.set_particles(cat("x"), cat("v"), cat("C"), cat("F"))
+
+    def get_particles(self, env: int = -1):
+        n = self.N if env < 0 else self.counts[env]
+        d = self.device
+        x = torch.empty(n, 3, device=d)
+        v = torch.empty(n, 3, device=d)
+        Cm = torch.empty(n, 3, 3, device=d)
+        F = torch.empty(n, 3, 3, device=d)
+        self._chk(self.lib.mpm_get_particles(self.h, env, C.ptr(x), C.ptr(v), C.ptr(Cm), C.ptr(F)),
+                  "mpm_get_particles")
+        return x, v, Cm, F
+
+    # -- stepping
+    def forward(self, n_substeps: int, record: bool = False) -> None:
+        self._chk(self.lib.mpm_forward(self.h, int(n_substeps), C.MPM_FWD_RECORD if record else 0), "mpm_forward")
+        if record:
+            self.record_token += 1
+
+    def backward(self, gx=None, gv=None, gC=None, gF=None, want_params: bool = True):
+        d = self.device
+        cv = lambda t: None if t is None else _f32(t, d)
+        gx, gv, gC, gF = cv(gx), cv(gv), cv(gC), cv(gF)
+        dx = torch.empty(self.N, 3, device=d)
+        dv = torch.empty(self.N, 3, device=d)
+        dC = torch.empty(self.N, 3, 3, device=d)
+        dF = torch.empty(self.N, 3, 3, device=d)
+        dp = torch.empty(self.E, 8, dtype=torch.float64, device=d) if want_params else None
+        self._chk(self.lib.mpm_backward(self.h, C.ptr(gx), C.ptr(gv), C.ptr(gC), C.ptr(gF), C.ptr(dx), C.ptr(dv),
+                                        C.ptr(dC), C.ptr(dF), C.ptr(dp)), "mpm_backward")
+        return dx, dv, dC, dF, dp
+
+    def sort_keys(self):
+        """(keys uint32 as int64, perm int64, ids int64, cell_bits) of the current state."""
+        keys = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        perm = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        ids = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        cb = ctypes.c_int32()
+        self._chk(self.lib.mpm_sort_keys(self.h, C.ptr(keys), C.ptr(perm), C.ptr(ids), ctypes.byref(cb)),
+                  "mpm_sort_keys")
+        u = lambda t: t.cpu().numpy().view(np.uint32).astype(np.int64)
+        return u(keys), u(perm), ids.cpu().numpy().astype(np.int64), int(cb.value)
+
+    def sync(self, raise_on_error: bool = True) -> int:
+        code = self.lib.mpm_sync(self.h)
+        if raise_on_error:
+            self._chk(code, "mpm_sync")
+        return code
+
+    def env_errors(self) -> np.ndarray:
+        out = (ctypes.c_int32 * self.E)()
+        self._chk(self.lib.mpm_env_errors(self.h, out), "mpm_env_errors")
+        return np.frombuffer(out, dtype=np.int32).copy()
+
+    def autotune(self, budget_ms: int = 200) -> None:
+        self._chk(self.lib.mpm_autotune(self.h, int(budget_ms)), "mpm_autotune")
+
+    def memory_bytes(self) -> int:
+        return int(self.lib.mpm_memory_bytes(self.h))
+
+    def set_timing(self, on: bool) -> None:
+        self._chk(self.lib.mpm_set_timing(self.h, 1 if on else 0), "mpm_set_timing")
+
+    def kernel_time(self, name: str):
+        ms = ctypes.c_double()
+        n = self.lib.mpm_kernel_time(self.h, C.KERNEL_CLASSES.index(name), ctypes.byref(ms))
+        return ms.value, int(n)
+
+
+class MPMRollout(torch.autograd.Function):
+    """s_S = f^S(s_0; params) through the library, differentiable in s_0 and params.
+
+    params: [E, 8] float64 (E, nu, rho, Vp, sigma_y, K, gamma, 0) per env.
+    If the batch has been re-used since this call's forward, the backward
+    first re-runs the forward from the saved inputs (frame-level checkpoint).
+    """
+
+    @staticmethod
+    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params):
+        prm = params.detach().to("cpu", torch.float64).numpy()
+        for i, e in enumerate(batch.envs):
+            batch.set_material(i, e.material, prm[i])
+        batch.set_particles(x, v, Cm, F)
+        batch.forward(n_substeps, record=True)
+        ctx.batch = batch
+        ctx.n_substeps = n_substeps
+        ctx.token = batch.record_token
+        ctx.save_for_backward(x, v, Cm, F, params)
+        return batch.get_particles()
+
+    @staticmethod
+    def backward(ctx, gx, gv, gC, gF):
+        b = ctx.batch
+        x, v, Cm, F, params = ctx.saved_tensors
+        if b.record_token != ctx.token:
+            prm = params.detach().to("cpu", torch.float64).numpy()
+            for i, e in enumerate(b.envs):
+                b.set_material(i, e.material, prm[i])
+            b.set_particles(x, v, Cm, F)
+            b.forward(ctx.n_substeps, record=True)
+            ctx.token = b.record_token
+        dx, dv, dC, dF, dp = b.backward(gx, gv, gC, gF)
+        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype)
+
+
+def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params):
+    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params)

@@ -1,0 +1,434 @@
+// Device-side pieces of one MLS-MPM substep and its adjoint, all in registers.
+//
+// Physics: the paper's Appendix D.3 (MLS-MPM with APIC transfer, von Mises
+// elastoplasticity with Hencky strain, weakly compressible fluid with the
+// J^(1/3) projection, softened one-way contact) and the stable neo-Hookean
+// energy of Appendix D.2 applied per particle.
+//
+// The isotropic 3x3 functions (corotated stress, Hencky stress, von Mises
+// return mapping) are written through the left Cauchy-Green tensor
+// b = F F^T = U diag(s) U^T (s = sigma^2), whose eigen-decomposition is the
+// left half of F's SVD. Their adjoints use divided differences that stay
+// finite when eigenvalues coincide (F = I at rest), never 1/(s_i - s_j).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpmx {
+
+#define MD __device__ __forceinline__
+
+enum : int { MAT_NEOHOOKEAN = 0, MAT_COROTATED = 1, MAT_VONMISES = 2, MAT_FLUID_TAIT = 3, MAT_FLUID_PAPER = 4 };
+enum : int { ERR_NONFINITE = 1, ERR_OUT_OF_DOMAIN = 2 };
+// slots of the per-env parameter-cotangent accumulator (FP64)
+enum : int { PB_MU = 0, PB_LAM, PB_SY, PB_K, PB_GAMMA, PB_MP, PB_VP, PB_COUNT };
+
+constexpr float kSigmaMin = 1e-4f;   // singular values are clamped below this before the log
+constexpr float kYieldScale = 2.0f;  // numerator of the printed yield offset kYieldScale*sigma_y/(2 mu)
+
+// Per-environment settings as the kernels see them. The first block is
+// written by the host; the derived block by the parameter-preparation kernel.
+struct EnvDev {
+  int32_t n, T, material, wall;          // nodes per axis, 4^3 tiles per axis
+  int32_t has_collider, pad0;
+  int64_t p_off, p_cnt;                  // particle range in the batch arrays
+  int64_t tile_off;                      // first tile of this env in the grid buffers
+  float dt, fn, dx, gx, gy, gz;
+  float cc[3], ch[3], cv[3], c_alpha, c_mu;   // box collider: centre at t=0, half extents, velocity
+  double E, nu, rho, Vp, sigma_y, K, gamma;   // user parameters (FP64 as given)
+  // derived (a1): Lame parameters and constants in FP32
+  float mu, lam, alpha_nh, mp, vp, sy, bulk, gam, yieldY;
+  float pad1[3];
+};
+
+// --------------------------------------------------------------------------
+// small vector / matrix helpers
+// --------------------------------------------------------------------------
+struct M3 { float m[3][3]; };
+
+MD M3 m3_zero() { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = 0.f; return r; }
+MD M3 m3_eye() { M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = 1.f; return r; }
+MD M3 m3_mul(const M3& a, const M3& b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+  return r;
+}
+MD M3 m3_mul_abt(const M3& a, const M3& b) {  // a b^T
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][0] * b.m[j][0] + a.m[i][1] * b.m[j][1] + a.m[i][2] * b.m[j][2];
+  return r;
+}
+MD M3 m3_mul_atb(const M3& a, const M3& b) {  // a^T b
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[0][i] * b.m[0][j] + a.m[1][i] * b.m[1][j] + a.m[2][i] * b.m[2][j];
+  return r;
+}
+MD M3 m3_add(const M3& a, const M3& b) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][j] + b.m[i][j]; return r; }
+MD M3 m3_scale(const M3& a, float s) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][j] * s; return r; }
+MD M3 m3_axpy(const M3& y, float s, const M3& x) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = fmaf(s, x.m[i][j], y.m[i][j]); return r; }
+MD M3 m3_sym(const M3& a) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = 0.5f * (a.m[i][j] + a.m[j][i]); return r; }
+MD float m3_trace(const M3& a) { return a.m[0][0] + a.m[1][1] + a.m[2][2]; }
+MD float m3_ddot(const M3& a, const M3& b) {
+  float s = 0.f;
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) s = fmaf(a.m[i][j], b.m[i][j], s);
+  return s;
+}
+MD float m3_det(const M3& a) {
+  return a.m[0][0] * (a.m[1][1] * a.m[2][2] - a.m[1][2] * a.m[2][1])
+       - a.m[0][1] * (a.m[1][0] * a.m[2][2] - a.m[1][2] * a.m[2][0])
+       + a.m[0][2] * (a.m[1][0] * a.m[2][1] - a.m[1][1] * a.m[2][0]);
+}
+// cofactor matrix: d det(A) / dA = det(A) A^-T
+MD M3 m3_cof(const M3& a) {
+  M3 c;
+  c.m[0][0] = a.m[1][1] * a.m[2][2] - a.m[1][2] * a.m[2][1];
+  c.m[0][1] = a.m[1][2] * a.m[2][0] - a.m[1][0] * a.m[2][2];
+  c.m[0][2] = a.m[1][0] * a.m[2][1] - a.m[1][1] * a.m[2][0];
+  c.m[1][0] = a.m[0][2] * a.m[2][1] - a.m[0][1] * a.m[2][2];
+  c.m[1][1] = a.m[0][0] * a.m[2][2] - a.m[0][2] * a.m[2][0];
+  c.m[1][2] = a.m[0][1] * a.m[2][0] - a.m[0][0] * a.m[2][1];
+  c.m[2][0] = a.m[0][1] * a.m[1][2] - a.m[0][2] * a.m[1][1];
+  c.m[2][1] = a.m[0][2] * a.m[1][0] - a.m[0][0] * a.m[1][2];
+  c.m[2][2] = a.m[0][0] * a.m[1][1] - a.m[0][1] * a.m[1][0];
+  return c;
+}
+// U diag(d) U^T
+MD M3 m3_spectral(const M3& U, const float d[3]) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      r.m[i][j] = U.m[i][0] * d[0] * U.m[j][0] + U.m[i][1] * d[1] * U.m[j][1] + U.m[i][2] * d[2] * U.m[j][2];
+  return r;
+}
+// U^T A U
+MD M3 m3_rotate_in(const M3& U, const M3& A) { return m3_mul(m3_mul_atb(U, A), U); }
+// U A U^T
+MD M3 m3_rotate_out(const M3& U, const M3& A) { return m3_mul_abt(m3_mul(U, A), U); }
+
+// --------------------------------------------------------------------------
+// symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (fixed sweeps,
+// no data-dependent loop): A = U diag(s) U^T
+// --------------------------------------------------------------------------
+template <int p, int q, int r>
+MD void jacobi_rotate(M3& A, M3& V) {
+  const float apq = A.m[p][q];
+  float t = 0.f;
+  if (apq != 0.f) {
+    const float theta = (A.m[q][q] - A.m[p][p]) / (2.f * apq);
+    const float at = fabsf(theta);
+    t = 1.f / (at + sqrtf(fmaf(at, at, 1.f)));
+    t = copysignf(t, theta);
+  }
+  const float c = rsqrtf(fmaf(t, t, 1.f));
+  const float s = t * c;
+  const float tau = s / (1.f + c);
+  A.m[p][p] -= t * apq;
+  A.m[q][q] += t * apq;
+  A.m[p][q] = A.m[q][p] = 0.f;
+  const float arp = A.m[r][p], arq = A.m[r][q];
+  A.m[r][p] = A.m[p][r] = arp - s * (arq + tau * arp);
+  A.m[r][q] = A.m[q][r] = arq + s * (arp - tau * arq);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float vkp = V.m[k][p], vkq = V.m[k][q];
+    V.m[k][p] = vkp - s * (vkq + tau * vkp);
+    V.m[k][q] = vkq + s * (vkp - tau * vkq);
+  }
+}
+
+MD void eig_sym(M3 A, float s[3], M3& U) {
+  U = m3_eye();
+#pragma unroll
+  for (int sweep = 0; sweep < 5; ++sweep) {
+    jacobi_rotate<0, 1, 2>(A, U);
+    jacobi_rotate<0, 2, 1>(A, U);
+    jacobi_rotate<1, 2, 0>(A, U);
+  }
+  s[0] = A.m[0][0];
+  s[1] = A.m[1][1];
+  s[2] = A.m[2][2];
+}
+
+// (log a - log b) / (a - b) for a, b > 0, finite as a -> b (limit 1/b)
+MD float log_divdiff(float a, float b) {
+  const float d = a - b;
+  const float z = d / b;
+  if (fabsf(z) < 1e-3f) return (1.f - z * (0.5f - z * (1.f / 3.f))) / b;
+  return log1pf(z) / d;
+}
+// expm1(z) / z, finite at 0
+MD float expm1_over(float z) {
+  if (fabsf(z) < 1e-3f) return 1.f + z * (0.5f + z * (1.f / 6.f));
+  return expm1f(z) / z;
+}
+
+// --------------------------------------------------------------------------
+// quadratic B-spline stencil of one particle
+// --------------------------------------------------------------------------
+struct Stencil {
+  int b[3];        // base node
+  float f[3];      // x n - base, in [0.5, 1.5) inside the band
+  float w[3][3];   // w[axis][offset]
+  float dw[3][3];  // dw/df
+  bool oob;
+};
+
+// base = floor(x n - 1/2) evaluated in FP64: exact for FP32 x, so binning is bit-exact
+MD int base_floor(float x, int n) { return (int)floor((double)x * (double)n - 0.5); }
+
+MD Stencil make_stencil(const float x[3], int n, float fn) {
+  Stencil st;
+  st.oob = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int b = base_floor(x[a], n);
+    if (b < 0 || b > n - 3) { st.oob = true; b = b < 0 ? 0 : n - 3; }
+    st.b[a] = b;
+    const float f = fmaf(x[a], fn, -(float)b);
+    st.f[a] = f;
+    const float f0 = 1.5f - f, f1 = f - 1.f, f2 = f - 0.5f;
+    st.w[a][0] = 0.5f * f0 * f0;
+    st.w[a][1] = 0.75f - f1 * f1;
+    st.w[a][2] = 0.5f * f2 * f2;
+    st.dw[a][0] = -f0;
+    st.dw[a][1] = -2.f * f1;
+    st.dw[a][2] = f2;
+  }
+  return st;
+}
+
+// storage index of node (i,j,k) of an env in a grid buffer laid out as
+// [tile][channel(8)][64 nodes], tile = 4^3 nodes in raster order
+MD int64_t node_base(const EnvDev& e, int i, int j, int k) {
+  const int tile = ((i >> 2) * e.T + (j >> 2)) * e.T + (k >> 2);
+  const int local = ((i & 3) << 4) | ((j & 3) << 2) | (k & 3);
+  return (e.tile_off + tile) * 512 + local;
+}
+constexpr int CH = 64;  // channel stride inside a tile
+
+// --------------------------------------------------------------------------
+// a3: Kirchhoff stress tau = P F^T
+// --------------------------------------------------------------------------
+MD M3 stress(const EnvDev& e, const M3& F) {
+  const float J = m3_det(F);
+  switch (e.material) {
+    case MAT_NEOHOOKEAN: {
+      const M3 b = m3_mul_abt(F, F);
+      const float Ic = m3_trace(b);
+      const float c1 = e.mu * (1.f - 1.f / (Ic + 1.f));
+      const float c2 = e.lam * J * (J - e.alpha_nh);
+      M3 t = m3_scale(b, c1);
+      t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
+      return t;
+    }
+    case MAT_COROTATED: {
+      // 2 mu (F - R) F^T = 2 mu (b - b^(1/2))
+      const M3 b = m3_mul_abt(F, F);
+      float s[3]; M3 U;
+      eig_sym(b, s, U);
+      float sg[3];
+      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(s[i], 0.f));
+      const M3 bh = m3_spectral(U, sg);
+      M3 t = m3_scale(m3_axpy(b, -1.f, bh), 2.f * e.mu);
+      const float c2 = e.lam * J * (J - 1.f);
+      t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
+      return t;
+    }
+    case MAT_VONMISES: {
+      // U (2 mu eps + lam tr(eps) I) U^T, eps = log Sigma = (1/2) log s
+      const M3 b = m3_mul_abt(F, F);
+      float s[3]; M3 U;
+      eig_sym(b, s, U);
+      float eps[3];
+      for (int i = 0; i < 3; ++i) eps[i] = 0.5f * logf(fmaxf(s[i], kSigmaMin * kSigmaMin));
+      const float tre = eps[0] + eps[1] + eps[2];
+      float d[3];
+      for (int i = 0; i < 3; ++i) d[i] = 2.f * e.mu * eps[i] + e.lam * tre;
+      return m3_spectral(U, d);
+    }
+    case MAT_FLUID_TAIT: {
+      const float c = e.bulk * (J - powf(J, 1.f - e.gam));  // -J K (J^-gamma - 1)
+      M3 t = m3_zero(); t.m[0][0] = t.m[1][1] = t.m[2][2] = c;
+      return t;
+    }
+    default: {  // MAT_FLUID_PAPER: lam J (J - 1) I
+      const float c = e.lam * J * (J - 1.f);
+      M3 t = m3_zero(); t.m[0][0] = t.m[1][1] = t.m[2][2] = c;
+      return t;
+    }
+  }
+}
+
+// VJP of stress(): Fbar += d<taubar, tau>/dF, pb[] += d<taubar, tau>/d(params)
+MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
+  const float J = m3_det(F);
+  const float trtb = m3_trace(tb);
+  switch (e.material) {
+    case MAT_NEOHOOKEAN: {
+      const M3 b = m3_mul_abt(F, F);
+      const float Ic = m3_trace(b);
+      const float inv = 1.f / (Ic + 1.f);
+      const float c1 = e.mu * (1.f - inv);
+      const M3 tbs = m3_sym(tb);
+      const float c1b = m3_ddot(tb, b);
+      const float Icb = c1b * e.mu * inv * inv;
+      // b = F F^T: dF <- 2 bbar F with bbar = c1 sym(taubar); I_C: dF <- 2 Icbar F
+      Fbar = m3_add(Fbar, m3_mul(m3_scale(tbs, 2.f * c1), F));
+      Fbar = m3_axpy(Fbar, 2.f * Icb, F);
+      const float Jb = trtb * e.lam * (2.f * J - e.alpha_nh);
+      Fbar = m3_axpy(Fbar, Jb, m3_cof(F));
+      pb[PB_MU] += c1b * (1.f - inv) - trtb * 0.75f * J;
+      pb[PB_LAM] += trtb * J * (J - 1.f);
+      return;
+    }
+    case MAT_COROTATED: {
+      const M3 b = m3_mul_abt(F, F);
+      float s[3]; M3 U;
+      eig_sym(b, s, U);
+      float sg[3];
+      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(s[i], 0.f));
+      const M3 G = m3_rotate_in(U, m3_sym(tb));
+      // h(s) = s - sqrt(s): divided difference 1 - 1/(sigma_i + sigma_j)
+      M3 H;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - 1.f / (sg[i] + sg[j]));
+      const M3 bbar = m3_rotate_out(U, H);
+      Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
+      Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));
+      float hm = 0.f;
+      for (int i = 0; i < 3; ++i) hm += G.m[i][i] * (s[i] - sg[i]);
+      pb[PB_MU] += 2.f * hm;
+      pb[PB_LAM] += trtb * J * (J - 1.f);
+      return;
+    }
+    case MAT_VONMISES: {
+      const M3 b = m3_mul_abt(F, F);
+      float s[3]; M3 U;
+      eig_sym(b, s, U);
+      float sc[3], ls[3];
+      for (int i = 0; i < 3; ++i) { sc[i] = fmaxf(s[i], kSigmaMin * kSigmaMin); ls[i] = logf(sc[i]); }
+      const M3 G = m3_rotate_in(U, m3_sym(tb));
+      M3 Bu;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Bu.m[i][j] = e.mu * G.m[i][j] * log_divdiff(sc[i], sc[j]);
+      for (int i = 0; i < 3; ++i) Bu.m[i][i] += e.lam * trtb * 0.5f / sc[i];
+      const M3 bbar = m3_rotate_out(U, Bu);
+      Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
+      float gl = 0.f;
+      for (int i = 0; i < 3; ++i) gl += G.m[i][i] * ls[i];
+      pb[PB_MU] += gl;
+      pb[PB_LAM] += trtb * 0.5f * (ls[0] + ls[1] + ls[2]);
+      return;
+    }
+    case MAT_FLUID_TAIT: {
+      const float Jg = powf(J, 1.f - e.gam);  // J^(1-gamma)
+      const float dc = e.bulk * (1.f - (1.f - e.gam) * Jg / J);
+      Fbar = m3_axpy(Fbar, trtb * dc, m3_cof(F));
+      pb[PB_K] += trtb * (J - Jg);
+      pb[PB_GAMMA] += trtb * e.bulk * Jg * logf(J);
+      return;
+    }
+    default: {
+      Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));
+      pb[PB_LAM] += trtb * J * (J - 1.f);
+      return;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// a6: return mapping P(F_tr)
+// --------------------------------------------------------------------------
+struct VMDecomp {   // shared by the projection and its VJP
+  M3 U;
+  float s[3], eh[3], g[3];
+  float nrm, beta;
+  bool plastic;
+};
+
+MD VMDecomp vm_decompose(const EnvDev& e, const M3& Ftr) {
+  VMDecomp d;
+  const M3 b = m3_mul_abt(Ftr, Ftr);
+  eig_sym(b, d.s, d.U);
+  float eps[3];
+  for (int i = 0; i < 3; ++i) {
+    d.s[i] = fmaxf(d.s[i], kSigmaMin * kSigmaMin);
+    eps[i] = 0.5f * logf(d.s[i]);
+  }
+  const float mean = (eps[0] + eps[1] + eps[2]) * (1.f / 3.f);
+  for (int i = 0; i < 3; ++i) d.eh[i] = eps[i] - mean;
+  d.nrm = sqrtf(d.eh[0] * d.eh[0] + d.eh[1] * d.eh[1] + d.eh[2] * d.eh[2]);
+  const float dgam = d.nrm - e.yieldY;
+  d.plastic = dgam > 0.f;
+  d.beta = d.plastic ? dgam / d.nrm : 0.f;
+  for (int i = 0; i < 3; ++i) d.g[i] = expf(-d.beta * d.eh[i]);
+  return d;
+}
+
+MD M3 project(const EnvDev& e, const M3& Ftr) {
+  if (e.material == MAT_VONMISES) {
+    const VMDecomp d = vm_decompose(e, Ftr);
+    if (!d.plastic) return Ftr;
+    // U exp(eps - dgam eps_hat/|eps_hat|) V^T = U diag(exp(-beta eps_hat)) U^T F_tr
+    return m3_mul(m3_spectral(d.U, d.g), Ftr);
+  }
+  if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
+    const float c = cbrtf(m3_det(Ftr));
+    M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = c;
+    return r;
+  }
+  return Ftr;
+}
+
+// VJP of project(): returns Ftr_bar; pb[] += parameter cotangents
+MD M3 project_vjp(const EnvDev& e, const M3& Ftr, const M3& Fb, float pb[PB_COUNT]) {
+  if (e.material == MAT_VONMISES) {
+    const VMDecomp d = vm_decompose(e, Ftr);
+    if (!d.plastic) return Fb;
+    const M3 Mm = m3_spectral(d.U, d.g);
+    M3 Ftb = m3_mul(Mm, Fb);                             // M symmetric: M^T Fbar'
+    const M3 G = m3_rotate_in(d.U, m3_sym(m3_mul_abt(Fb, Ftr)));   // U^T sym(Mbar) U
+    const float Y = e.yieldY, N = d.nrm, beta = d.beta;
+    // diagonal: dg_i/ds_k with g_i = exp(-beta eh_i), beta = 1 - Y/N
+    float S1 = 0.f, S2 = 0.f;
+    for (int i = 0; i < 3; ++i) { S1 += G.m[i][i] * d.g[i] * d.eh[i]; S2 += G.m[i][i] * d.g[i]; }
+    M3 Bu;
+    for (int k = 0; k < 3; ++k)
+      Bu.m[k][k] = -(0.5f / d.s[k]) * (Y * d.eh[k] / (N * N * N) * S1 + beta * (G.m[k][k] * d.g[k] - S2 * (1.f / 3.f)));
+    // off-diagonal: (g_i - g_j)/(s_i - s_j) = [-beta e^{-beta eh_j} phi(-beta (eh_i - eh_j))] * (1/2) L(s_i, s_j)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        if (i == j) continue;
+        const float dd = -beta * d.g[j] * expm1_over(-beta * (d.eh[i] - d.eh[j])) * 0.5f * log_divdiff(d.s[i], d.s[j]);
+        Bu.m[i][j] = G.m[i][j] * dd;
+      }
+    const M3 bbar = m3_rotate_out(d.U, Bu);
+    Ftb = m3_add(Ftb, m3_mul(m3_scale(bbar, 2.f), Ftr));
+    // parameters: beta = 1 - Y/N, Y = kYieldScale sigma_y / (2 mu)
+    const float betab = -S1;
+    const float Yb = -betab / N;
+    pb[PB_MU] += Yb * (-Y / e.mu);
+    pb[PB_SY] += Yb * (kYieldScale / (2.f * e.mu));
+    return Ftb;
+  }
+  if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
+    const float J = m3_det(Ftr);
+    const float c = cbrtf(J);
+    const float k = m3_trace(Fb) * c / (3.f * J);   // d J^(1/3)/dJ = J^(1/3)/(3J)
+    return m3_scale(m3_cof(Ftr), k);
+  }
+  return Fb;
+}
+
+}  // namespace mpmx

@@ -1,0 +1,825 @@
+// HIP kernels of the batched MLS-MPM substep (forward and adjoint) for gfx950.
+//
+// Particle kernels take a list of work items: (env, first particle, count),
+// count <= 256, so a block never straddles two environments and its material
+// branch is uniform. The per-environment ("plain") mode launches the items of
+// one env at a time; the batched mode launches every item at once.
+#include "mpm_kernels.h"
+
+namespace mpmx {
+
+// ----------------------------------------------------------------------------
+// state access: SoA, component c of particle p at st[c * N + p]
+// components: x 0-2, v 3-5, C 6-14 (row-major), F 15-23
+// ----------------------------------------------------------------------------
+struct PState { float x[3], v[3]; M3 C, F; };
+
+MD void load_x(const float* __restrict__ st, int64_t N, int64_t p, float x[3]) {
+  x[0] = st[p]; x[1] = st[N + p]; x[2] = st[2 * N + p];
+}
+MD M3 load_m3(const float* __restrict__ st, int64_t N, int64_t p, int c0) {
+  M3 m;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.m[i][j] = st[(c0 + 3 * i + j) * N + p];
+  return m;
+}
+MD void store_m3(float* __restrict__ st, int64_t N, int64_t p, int c0, const M3& m) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) st[(c0 + 3 * i + j) * N + p] = m.m[i][j];
+}
+MD PState load_state(const float* __restrict__ st, int64_t N, int64_t p) {
+  PState s;
+  for (int a = 0; a < 3; ++a) { s.x[a] = st[a * N + p]; s.v[a] = st[(3 + a) * N + p]; }
+  s.C = load_m3(st, N, p, 6);
+  s.F = load_m3(st, N, p, 15);
+  return s;
+}
+MD void store_state(float* __restrict__ st, int64_t N, int64_t p, const PState& s) {
+  for (int a = 0; a < 3; ++a) { st[a * N + p] = s.x[a]; st[(3 + a) * N + p] = s.v[a]; }
+  store_m3(st, N, p, 6, s.C);
+  store_m3(st, N, p, 15, s.F);
+}
+
+// ----------------------------------------------------------------------------
+// a1: parameter preparation
+// ----------------------------------------------------------------------------
+__global__ void k_prep_params(EnvDev* envs, int n_envs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_envs) return;
+  EnvDev& e = envs[i];
+  const double mu = e.E / (2.0 * (1.0 + e.nu));
+  const double lam = e.E * e.nu / ((1.0 + e.nu) * (1.0 - 2.0 * e.nu));
+  e.mu = (float)mu;
+  e.lam = (float)lam;
+  e.alpha_nh = (float)(lam != 0.0 ? 1.0 + 3.0 * mu / (4.0 * lam) : 1.0);
+  e.mp = (float)(e.rho * e.Vp);
+  e.vp = (float)e.Vp;
+  e.sy = (float)e.sigma_y;
+  e.bulk = (float)e.K;
+  e.gam = (float)e.gamma;
+  e.yieldY = (float)(mu > 0.0 ? (double)kYieldScale * e.sigma_y / (2.0 * mu) : 0.0);
+}
+
+// accumulated (mu, lam, sigma_y, K, gamma, m_p, V_p) cotangents -> the 8-entry
+// parameter row (E, nu, rho, Vp, sigma_y, K, gamma, 0)
+__global__ void k_finalize_params(const EnvDev* envs, const double* acc, double* out, int n_envs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_envs) return;
+  const EnvDev& e = envs[i];
+  const double* a = acc + i * 8;
+  const double E = e.E, nu = e.nu;
+  const double D = (1.0 + nu) * (1.0 - 2.0 * nu);
+  const double dmu_dE = 1.0 / (2.0 * (1.0 + nu));
+  const double dlam_dE = nu / D;
+  const double dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+  const double dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (D * D);
+  double* o = out + i * 8;
+  o[0] = a[PB_MU] * dmu_dE + a[PB_LAM] * dlam_dE;
+  o[1] = a[PB_MU] * dmu_dnu + a[PB_LAM] * dlam_dnu;
+  o[2] = a[PB_MP] * e.Vp;                        // m_p = rho Vp
+  o[3] = a[PB_VP] + a[PB_MP] * e.rho;
+  o[4] = a[PB_SY];
+  o[5] = a[PB_K];
+  o[6] = a[PB_GAMMA];
+  o[7] = 0.0;
+}
+
+// ----------------------------------------------------------------------------
+// layout conversion between the caller's AoS arrays and the internal SoA
+// ----------------------------------------------------------------------------
+__global__ void k_load_aos(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
+                           const float* __restrict__ F, int64_t n, float* __restrict__ st, int64_t N, int64_t off,
+                           int32_t* __restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = off + i;
+  for (int a = 0; a < 3; ++a) {
+    st[a * N + p] = x[3 * i + a];
+    st[(3 + a) * N + p] = v[3 * i + a];
+  }
+  for (int k = 0; k < 9; ++k) {
+    st[(6 + k) * N + p] = C[9 * i + k];
+    st[(15 + k) * N + p] = F[9 * i + k];
+  }
+  ids[p] = (int32_t)p;
+}
+
+// out rows are indexed by the particle's caller index ids[p]; rows [lo, hi) only
+__global__ void k_store_aos(const float* __restrict__ st, int64_t N, const int32_t* __restrict__ ids, int64_t lo,
+                            int64_t hi, float* __restrict__ x, float* __restrict__ v, float* __restrict__ C,
+                            float* __restrict__ F) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t u = ids[p];
+  if (u < lo || u >= hi) return;
+  const int64_t r = u - lo;
+  for (int a = 0; a < 3; ++a) {
+    if (x) x[3 * r + a] = st[a * N + p];
+    if (v) v[3 * r + a] = st[(3 + a) * N + p];
+  }
+  for (int k = 0; k < 9; ++k) {
+    if (C) C[9 * r + k] = st[(6 + k) * N + p];
+    if (F) F[9 * r + k] = st[(15 + k) * N + p];
+  }
+}
+
+// internal cot[p] = caller cotangent row ids[p] (null arrays count as zero)
+__global__ void k_gather_aos(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
+                             const float* __restrict__ F, const int32_t* __restrict__ ids, float* __restrict__ st,
+                             int64_t N) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t u = ids[p];
+  for (int a = 0; a < 3; ++a) {
+    st[a * N + p] = x ? x[3 * u + a] : 0.f;
+    st[(3 + a) * N + p] = v ? v[3 * u + a] : 0.f;
+  }
+  for (int k = 0; k < 9; ++k) {
+    st[(6 + k) * N + p] = C ? C[9 * u + k] : 0.f;
+    st[(15 + k) * N + p] = F ? F[9 * u + k] : 0.f;
+  }
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_set_clock(int32_t* clock, int32_t value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = value;
+}
+
+// ----------------------------------------------------------------------------
+// a2: binning keys and a stable LSD radix sort (8-bit digits)
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_keys(const float* __restrict__ st, int64_t N, const EnvDev* __restrict__ envs,
+                                              const WorkItem* __restrict__ items, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, int cell_bits) {
+  const WorkItem it = items[blockIdx.x];
+  if ((int)threadIdx.x >= it.count) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + threadIdx.x;
+  int b[3];
+  for (int a = 0; a < 3; ++a) {
+    int q = base_floor(st[a * N + p], e.n);
+    b[a] = q < 0 ? 0 : (q > e.n - 3 ? e.n - 3 : q);
+  }
+  const uint32_t tile = (uint32_t)(((b[0] >> 2) * e.T + (b[1] >> 2)) * e.T + (b[2] >> 2));
+  const uint32_t cell = (uint32_t)((((b[0] & 3) << 4) | ((b[1] & 3) << 2) | (b[2] & 3)));
+  keys[p] = ((uint32_t)it.env << cell_bits) | (tile * 64u + cell);
+  vals[p] = (uint32_t)p;
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, int64_t N, int shift,
+                                                           uint32_t* __restrict__ counts, int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const int64_t i = base + r * RS_THREADS + threadIdx.x;
+    if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of n entries by one block of 1024 threads
+__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t* __restrict__ a, int64_t n) {
+  __shared__ uint32_t sums[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  uint32_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += a[i];
+  sums[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = t >= off ? sums[t - off] : 0u;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = sums[t] - s;
+  for (int64_t i = lo; i < hi; ++i) { const uint32_t v = a[i]; a[i] = run; run += v; }
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                              const uint32_t* __restrict__ vin,
+                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                              int64_t N, int shift, const uint32_t* __restrict__ offs,
+                                                              int nblocks) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  run[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+  for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const int64_t i = base + r * RS_THREADS + tid;
+    const bool valid = i < N;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t digit = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int bit = (digit >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = __popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[wave][digit] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[digit] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < RS_THREADS / 64; ++w) { add += wcnt[w][tid]; wcnt[w][tid] = 0; }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+// dst[j] = src[perm[j]] for all 24 components; ids_out[j] = ids_in[perm[j]]
+__global__ void k_permute_state(const float* __restrict__ src, float* __restrict__ dst, int64_t N,
+                                const uint32_t* __restrict__ perm, const int32_t* __restrict__ ids_in,
+                                int32_t* __restrict__ ids_out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int64_t q = perm[j];
+#pragma unroll
+  for (int c = 0; c < 24; ++c) dst[c * N + j] = src[c * N + q];
+  ids_out[j] = ids_in[q];
+}
+
+// adjoint of k_permute_state: dst[perm[j]] = src[j]
+__global__ void k_unpermute(const float* __restrict__ src, float* __restrict__ dst, int64_t N,
+                            const uint32_t* __restrict__ perm) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int64_t q = perm[j];
+#pragma unroll
+  for (int c = 0; c < 24; ++c) dst[c * N + q] = src[c * N + j];
+}
+
+// ----------------------------------------------------------------------------
+// a3 + a4: P2G, one thread per particle, direct global atomics
+// ----------------------------------------------------------------------------
+MD void mark_tiles(const EnvDev& e, const int b[3], uint32_t* __restrict__ flags) {
+  const int t0[3] = {b[0] >> 2, b[1] >> 2, b[2] >> 2};
+  const int t1[3] = {(b[0] + 2) >> 2, (b[1] + 2) >> 2, (b[2] + 2) >> 2};
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c)
+      for (int d = 0; d < 2; ++d) {
+        const int tx = a ? t1[0] : t0[0], ty = c ? t1[1] : t0[1], tz = d ? t1[2] : t0[2];
+        flags[e.tile_off + (tx * e.T + ty) * e.T + tz] = 1u;
+      }
+}
+
+__global__ void __launch_bounds__(256) k_p2g_direct(const float* __restrict__ st, int64_t N,
+                                                    const EnvDev* __restrict__ envs,
+                                                    const WorkItem* __restrict__ items, float* __restrict__ grid,
+                                                    uint32_t* __restrict__ flags, int32_t* __restrict__ errs) {
+  const WorkItem it = items[blockIdx.x];
+  if ((int)threadIdx.x >= it.count) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + threadIdx.x;
+  const PState s = load_state(st, N, p);
+  const Stencil sc = make_stencil(s.x, e.n, e.fn);
+  if (sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
+  const M3 tau = stress(e, s.F);
+  const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+  const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
+  mark_tiles(e, sc.b, flags);
+#pragma unroll
+  for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz) {
+        const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
+        const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+        float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+        atomicAdd(g, W * e.mp);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float mv = e.mp * s.v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2];
+          atomicAdd(g + (1 + a) * CH, W * mv);
+        }
+      }
+}
+
+// ----------------------------------------------------------------------------
+// a5: grid update (and its adjoint) on touched 4^3 tiles, one wave per tile
+// ----------------------------------------------------------------------------
+MD void node_coords(const EnvDev& e, int64_t tile, int l, int& i, int& j, int& k) {
+  const int lt = (int)(tile - e.tile_off);
+  const int tx = lt / (e.T * e.T), ty = (lt / e.T) % e.T, tz = lt % e.T;
+  i = 4 * tx + (l >> 4);
+  j = 4 * ty + ((l >> 2) & 3);
+  k = 4 * tz + (l & 3);
+}
+
+struct Contact {
+  float n[3];
+  float s;
+};
+
+MD Contact contact_geometry(const EnvDev& e, float t, int i, int j, int k) {
+  const float p[3] = {i * e.dx, j * e.dx, k * e.dx};
+  float rel[3], q[3], qp[3];
+  for (int a = 0; a < 3; ++a) {
+    rel[a] = p[a] - fmaf(t, e.cv[a], e.cc[a]);
+    q[a] = fabsf(rel[a]) - e.ch[a];
+    qp[a] = fmaxf(q[a], 0.f);
+  }
+  const float out_len = sqrtf(qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2]);
+  const float inside = fmaxf(q[0], fmaxf(q[1], q[2]));
+  const float d = out_len + fminf(inside, 0.f);
+  Contact c;
+  if (out_len > 0.f) {
+    for (int a = 0; a < 3; ++a) c.n[a] = copysignf(1.f, rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;
+  } else {
+    const int ax = (q[0] >= q[1] && q[0] >= q[2]) ? 0 : (q[1] >= q[2] ? 1 : 2);
+    for (int a = 0; a < 3; ++a) c.n[a] = (a == ax) ? (rel[a] >= 0.f ? 1.f : -1.f) : 0.f;
+  }
+  c.s = fminf(expf(-e.c_alpha * d), 1.f);
+  return c;
+}
+
+// friction projection of the velocity relative to the box; returns the case (0 free, 1 stick, 2 slide)
+MD int contact_project(const EnvDev& e, const Contact& c, const float u[3], float up[3], float& un, float ut[3],
+                       float& utn) {
+  un = u[0] * c.n[0] + u[1] * c.n[1] + u[2] * c.n[2];
+  for (int a = 0; a < 3; ++a) ut[a] = u[a] - un * c.n[a];
+  utn = sqrtf(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+  if (!(un < 0.f)) { for (int a = 0; a < 3; ++a) up[a] = u[a]; return 0; }
+  if (utn <= -e.c_mu * un) { for (int a = 0; a < 3; ++a) up[a] = 0.f; return 1; }
+  const float k = 1.f + e.c_mu * un / utn;
+  for (int a = 0; a < 3; ++a) up[a] = ut[a] * k;
+  return 2;
+}
+
+MD bool is_wall(const EnvDev& e, int i, int j, int k) {
+  const int lo = e.wall, hi = e.n - 1 - e.wall;
+  return i < lo || j < lo || k < lo || i > hi || j > hi || k > hi;
+}
+
+MD float substep_time(const EnvDev& e, double t0, const int32_t* clock, int k_rel) {
+  return (float)(t0 + (double)(clock[0] + k_rel) * (double)e.dt);
+}
+
+__global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ envs,
+                                                     const int32_t* __restrict__ tile_env, int64_t tile0,
+                                                     int64_t ntiles, float* __restrict__ grid,
+                                                     uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
+                                                     double t0, int k_rel, int clear) {
+  const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (tile >= tile0 + ntiles) return;
+  if (flags[tile] == 0u) return;
+  const EnvDev& e = envs[tile_env[tile]];
+  int i, j, k;
+  node_coords(e, tile, l, i, j, k);
+  float* g = grid + tile * 512 + l;
+  const float m = g[0];
+  float v[3] = {0.f, 0.f, 0.f};
+  if (m > 0.f) {
+    const float inv = 1.f / m;
+    v[0] = fmaf(g[CH], inv, e.dt * e.gx);
+    v[1] = fmaf(g[2 * CH], inv, e.dt * e.gy);
+    v[2] = fmaf(g[3 * CH], inv, e.dt * e.gz);
+    if (e.has_collider) {
+      const Contact c = contact_geometry(e, substep_time(e, t0, clock, k_rel), i, j, k);
+      float u[3], up[3], ut[3], un, utn;
+      for (int a = 0; a < 3; ++a) u[a] = v[a] - e.cv[a];
+      contact_project(e, c, u, up, un, ut, utn);
+      for (int a = 0; a < 3; ++a) v[a] = c.s * (e.cv[a] + up[a]) + (1.f - c.s) * v[a];
+    }
+  }
+  if (is_wall(e, i, j, k)) v[0] = v[1] = v[2] = 0.f;
+  g[4 * CH] = v[0];
+  g[5 * CH] = v[1];
+  g[6 * CH] = v[2];
+  if (clear) {
+    g[0] = 0.f; g[CH] = 0.f; g[2 * CH] = 0.f; g[3 * CH] = 0.f;
+    if (l == 0) flags[tile] = 0u;
+  }
+}
+
+// reads vbar (channels 0-2 of gcot), writes mbar (3) and Pbar (4-6), clears
+// vbar and the tape grid of this substep (and its flag)
+__global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__ envs,
+                                                      const int32_t* __restrict__ tile_env, int64_t tile0,
+                                                      int64_t ntiles, float* __restrict__ grid,
+                                                      uint32_t* __restrict__ flags, float* __restrict__ gcot,
+                                                      const int32_t* __restrict__ clock, double t0, int k_rel) {
+  const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (tile >= tile0 + ntiles) return;
+  if (flags[tile] == 0u) return;
+  const EnvDev& e = envs[tile_env[tile]];
+  int i, j, k;
+  node_coords(e, tile, l, i, j, k);
+  float* g = grid + tile * 512 + l;
+  float* gc = gcot + tile * 512 + l;
+  const float m = g[0];
+  const float P[3] = {g[CH], g[2 * CH], g[3 * CH]};
+  float vb[3] = {gc[0], gc[CH], gc[2 * CH]};
+  float mb = 0.f, Pb[3] = {0.f, 0.f, 0.f};
+  if (!is_wall(e, i, j, k) && m > 0.f) {
+    const float inv = 1.f / m;
+    const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
+    if (e.has_collider) {
+      const Contact c = contact_geometry(e, substep_time(e, t0, clock, k_rel), i, j, k);
+      float u[3], up[3], ut[3], un, utn;
+      for (int a = 0; a < 3; ++a) u[a] = vpre[a] - e.cv[a];
+      const int kase = contact_project(e, c, u, up, un, ut, utn);
+      float ub[3];
+      if (kase == 0) {
+        for (int a = 0; a < 3; ++a) ub[a] = vb[a];
+      } else if (kase == 1) {
+        ub[0] = ub[1] = ub[2] = 0.f;
+      } else {
+        float uh[3];
+        for (int a = 0; a < 3; ++a) uh[a] = ut[a] / utn;
+        const float nd = c.n[0] * vb[0] + c.n[1] * vb[1] + c.n[2] * vb[2];
+        const float ud = uh[0] * vb[0] + uh[1] * vb[1] + uh[2] * vb[2];
+        const float r = un / utn;
+        for (int a = 0; a < 3; ++a) {
+          const float pv = vb[a] - c.n[a] * nd;  // (I - n n^T) vbar
+          ub[a] = pv + e.c_mu * (c.n[a] * ud + r * (pv - uh[a] * ud));
+        }
+      }
+      for (int a = 0; a < 3; ++a) vb[a] = (1.f - c.s) * vb[a] + c.s * ub[a];
+    }
+    for (int a = 0; a < 3; ++a) Pb[a] = vb[a] * inv;
+    mb = -(vb[0] * P[0] + vb[1] * P[1] + vb[2] * P[2]) * inv * inv;
+  }
+  gc[3 * CH] = mb;
+  gc[4 * CH] = Pb[0];
+  gc[5 * CH] = Pb[1];
+  gc[6 * CH] = Pb[2];
+  gc[0] = 0.f; gc[CH] = 0.f; gc[2 * CH] = 0.f;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) g[c * CH] = 0.f;
+  if (l == 0) flags[tile] = 0u;
+}
+
+// clears every flagged tile of a grid buffer and its flag (for an abandoned tape)
+__global__ void __launch_bounds__(256) k_grid_clear_flagged(int64_t ntiles, float* __restrict__ grid,
+                                                            uint32_t* __restrict__ flags) {
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (tile >= ntiles) return;
+  if (flags[tile] == 0u) return;
+  float* g = grid + tile * 512 + l;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) g[c * CH] = 0.f;
+  if (l == 0) flags[tile] = 0u;
+}
+
+// ----------------------------------------------------------------------------
+// a6: G2P gather, F update and return mapping, one thread per particle
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                                                    const EnvDev* __restrict__ envs,
+                                                    const WorkItem* __restrict__ items,
+                                                    const float* __restrict__ grid, int32_t* __restrict__ errs) {
+  const WorkItem it = items[blockIdx.x];
+  if ((int)threadIdx.x >= it.count) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + threadIdx.x;
+  float x[3];
+  load_x(st, N, p, x);
+  const M3 F = load_m3(st, N, p, 15);
+  const Stencil sc = make_stencil(x, e.n, e.fn);
+  float vn[3] = {0.f, 0.f, 0.f};
+  M3 Cn = m3_zero();
+#pragma unroll
+  for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz) {
+        const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
+        const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+        const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+        const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          vn[a] = fmaf(W, vi[a], vn[a]);
+          const float wv = W * vi[a];
+          Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
+          Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
+          Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
+        }
+      }
+  Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
+  PState s;
+  for (int a = 0; a < 3; ++a) { s.x[a] = fmaf(e.dt, vn[a], x[a]); s.v[a] = vn[a]; }
+  s.C = Cn;
+  const M3 Ftr = m3_mul(m3_axpy(m3_eye(), e.dt, Cn), F);
+  s.F = project(e, Ftr);
+  store_state(out, N, p, s);
+  bool fin = true;
+  for (int a = 0; a < 3; ++a) fin = fin && isfinite(s.x[a]) && isfinite(s.v[a]);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(s.F.m[i][j]);
+  if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
+}
+
+// ----------------------------------------------------------------------------
+// a7: adjoint kernels
+// ----------------------------------------------------------------------------
+// block sum of PB_COUNT floats in FP64, one atomic per slot per block
+MD void block_reduce_params(float pb[PB_COUNT], double* __restrict__ acc) {
+  __shared__ double red[PB_COUNT][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < PB_COUNT; ++k) {
+    double v = (double)pb[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[k][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < PB_COUNT) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    if (s != 0.0) atomicAdd(&acc[threadIdx.x], s);
+  }
+}
+
+// G2P adjoint: scatters grid-velocity cotangents (channels 0-2 of gcot) and
+// writes the particle's direct x and F cotangents into `part` (12 comps)
+__global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restrict__ st, const float* __restrict__ cot,
+                                                            float* __restrict__ part, int64_t N,
+                                                            const EnvDev* __restrict__ envs,
+                                                            const WorkItem* __restrict__ items,
+                                                            const float* __restrict__ grid, float* __restrict__ gcot,
+                                                            double* __restrict__ pacc) {
+  const WorkItem it = items[blockIdx.x];
+  const bool valid = (int)threadIdx.x < it.count;
+  const EnvDev& e = envs[it.env];
+  float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    const int64_t p = it.start + threadIdx.x;
+    float x[3];
+    load_x(st, N, p, x);
+    const M3 F = load_m3(st, N, p, 15);
+    const Stencil sc = make_stencil(x, e.n, e.fn);
+    const float D4 = 4.f * e.fn * e.fn;
+    // pass 1: recompute v', C'
+    M3 Cn = m3_zero();
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
+          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+          for (int a = 0; a < 3; ++a) {
+            const float wv = W * vi[a];
+            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
+            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
+            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
+          }
+        }
+    Cn = m3_scale(Cn, D4);
+    const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
+    const M3 Ftr = m3_mul(G, F);
+    // incoming cotangents of (x', v', C', F')
+    float xb[3], vb[3];
+    for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
+    const M3 Cb_in = load_m3(cot, N, p, 6);
+    const M3 Fb_in = load_m3(cot, N, p, 15);
+    const M3 Ftrb = project_vjp(e, Ftr, Fb_in, pb);
+    const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));  // C' enters F_tr = (I + dt C') F
+    const M3 Fb = m3_mul_atb(G, Ftrb);
+    // pass 2: scatter to grid, accumulate dx
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wx = sc.w[0][ox], wy = sc.w[1][oy], wz = sc.w[2][oz];
+          const float W = wx * wy * wz;
+          const float gW[3] = {e.fn * sc.dw[0][ox] * wy * wz, e.fn * wx * sc.dw[1][oy] * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          const float* g = grid + nb;
+          const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+          float gv[3];
+          for (int a = 0; a < 3; ++a)
+            gv[a] = vb[a] + D4 * (Cb.m[a][0] * d[0] + Cb.m[a][1] * d[1] + Cb.m[a][2] * d[2]);
+          float* gc = gcot + nb;
+          atomicAdd(gc, W * gv[0]);
+          atomicAdd(gc + CH, W * gv[1]);
+          atomicAdd(gc + 2 * CH, W * gv[2]);
+          const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
+          for (int a = 0; a < 3; ++a) {
+            const float ctv = Cb.m[0][a] * vi[0] + Cb.m[1][a] * vi[1] + Cb.m[2][a] * vi[2];
+            xb[a] += gW[a] * vg - D4 * W * ctv;
+          }
+        }
+    for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
+    store_m3(part, N, p, 3, Fb);
+  }
+  block_reduce_params(pb, pacc + (int64_t)it.env * 8);
+}
+
+// P2G adjoint: gathers (mbar, Pbar), adds the G2P part, writes the full
+// cotangent of the substep's input state
+__global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restrict__ st,
+                                                            const float* __restrict__ part,
+                                                            float* __restrict__ cot_out, int64_t N,
+                                                            const EnvDev* __restrict__ envs,
+                                                            const WorkItem* __restrict__ items,
+                                                            const float* __restrict__ gcot,
+                                                            double* __restrict__ pacc) {
+  const WorkItem it = items[blockIdx.x];
+  const bool valid = (int)threadIdx.x < it.count;
+  const EnvDev& e = envs[it.env];
+  float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    const int64_t p = it.start + threadIdx.x;
+    const PState s = load_state(st, N, p);
+    const Stencil sc = make_stencil(s.x, e.n, e.fn);
+    const M3 tau = stress(e, s.F);
+    const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+    const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
+    float xb[3] = {part[p], part[N + p], part[2 * N + p]};
+    float vb[3] = {0.f, 0.f, 0.f};
+    M3 Ab = m3_zero();
+    float mpb = 0.f;
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wx = sc.w[0][ox], wy = sc.w[1][oy], wz = sc.w[2][oz];
+          const float W = wx * wy * wz;
+          const float gW[3] = {e.fn * sc.dw[0][ox] * wy * wz, e.fn * wx * sc.dw[1][oy] * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float* gc = gcot + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          const float mb = gc[3 * CH];
+          const float Pb[3] = {gc[4 * CH], gc[5 * CH], gc[6 * CH]};
+          float mom[3], vcd[3];
+          for (int a = 0; a < 3; ++a) {
+            const float Ad = A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2];
+            mom[a] = e.mp * s.v[a] + Ad;
+            vcd[a] = s.v[a] + s.C.m[a][0] * d[0] + s.C.m[a][1] * d[1] + s.C.m[a][2] * d[2];
+          }
+          const float gw = e.mp * mb + Pb[0] * mom[0] + Pb[1] * mom[1] + Pb[2] * mom[2];
+          for (int a = 0; a < 3; ++a) {
+            vb[a] = fmaf(e.mp * W, Pb[a], vb[a]);
+            const float wp = W * Pb[a];
+            Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
+            Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
+            Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
+            const float atp = A.m[0][a] * Pb[0] + A.m[1][a] * Pb[1] + A.m[2][a] * Pb[2];
+            xb[a] += gW[a] * gw - W * atp;
+          }
+          mpb += W * (mb + Pb[0] * vcd[0] + Pb[1] * vcd[1] + Pb[2] * vcd[2]);
+        }
+    const M3 Cb = m3_scale(Ab, e.mp);
+    const M3 taub = m3_scale(Ab, kf);
+    pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
+    pb[PB_MP] += mpb;
+    M3 Fb = load_m3(part, N, p, 3);
+    stress_vjp(e, s.F, taub, Fb, pb);
+    for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
+    store_m3(cot_out, N, p, 6, Cb);
+    store_m3(cot_out, N, p, 15, Fb);
+  }
+  block_reduce_params(pb, pacc + (int64_t)it.env * 8);
+}
+
+// ----------------------------------------------------------------------------
+// host launchers
+// ----------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void launch_prep_params(EnvDev* envs, int n_envs, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_params, dim3(nblk(n_envs, 64)), dim3(64), 0, s, envs, n_envs);
+}
+void launch_finalize_params(const EnvDev* envs, const double* acc, double* out, int n_envs, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_params, dim3(nblk(n_envs, 64)), dim3(64), 0, s, envs, acc, out, n_envs);
+}
+void launch_load_aos(const float* x, const float* v, const float* C, const float* F, int64_t n, float* st, int64_t N,
+                     int64_t off, int32_t* ids, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_load_aos, dim3(nblk(n, 256)), dim3(256), 0, s, x, v, C, F, n, st, N, off, ids);
+}
+void launch_store_aos(const float* st, int64_t N, const int32_t* ids, int64_t lo, int64_t hi, float* x, float* v,
+                      float* C, float* F, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_store_aos, dim3(nblk(N, 256)), dim3(256), 0, s, st, N, ids, lo, hi, x, v, C, F);
+}
+void launch_gather_aos(const float* x, const float* v, const float* C, const float* F, const int32_t* ids, float* st,
+                       int64_t N, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_gather_aos, dim3(nblk(N, 256)), dim3(256), 0, s, x, v, C, F, ids, st, N);
+}
+void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy_i32, dim3(nblk(n, 256)), dim3(256), 0, s, a, b, n);
+}
+void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
+  if (n_words == 0) return;
+  int64_t b = nblk(n_words, 256);
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(256), 0, s, (uint32_t*)p, v, n_words);
+}
+void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clock, value);
+}
+void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
+                 uint32_t* vals, int cell_bits, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_keys, dim3(n_items), dim3(256), 0, s, st, N, envs, items, keys, vals, cell_bits);
+}
+// returns which buffer (0: k0/v0, 1: k1/v1) holds the sorted result
+int launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* counts, int64_t N,
+                      int key_bits, hipStream_t s) {
+  if (N == 0) return 0;
+  const int nblocks = (int)nblk(N, RS_TILE);
+  int cur = 0;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    uint32_t* kin = cur ? k1 : k0;
+    uint32_t* vin = cur ? v1 : v0;
+    uint32_t* kout = cur ? k0 : k1;
+    uint32_t* vout = cur ? v0 : v1;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, N, shift, counts, nblocks);
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, counts, (int64_t)256 * nblocks);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, N, shift, counts,
+                       nblocks);
+    cur ^= 1;
+  }
+  return cur;
+}
+void launch_permute_state(const float* src, float* dst, int64_t N, const uint32_t* perm, const int32_t* ids_in,
+                          int32_t* ids_out, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_permute_state, dim3(nblk(N, 256)), dim3(256), 0, s, src, dst, N, perm, ids_in, ids_out);
+}
+void launch_unpermute(const float* src, float* dst, int64_t N, const uint32_t* perm, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_unpermute, dim3(nblk(N, 256)), dim3(256), 0, s, src, dst, N, perm);
+}
+void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                       uint32_t* flags, int32_t* errs, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_p2g_direct, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs);
+}
+void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
+                        uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, hipStream_t s) {
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_grid_update, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid, flags,
+                     clock, t0, k_rel, clear);
+}
+void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
+                         uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, hipStream_t s) {
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_grid_adjoint, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid,
+                     flags, gcot, clock, t0, k_rel);
+}
+void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s) {
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_grid_clear_flagged, dim3(nblk(ntiles, 4)), dim3(256), 0, s, ntiles, grid, flags);
+}
+void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                       const float* grid, int32_t* errs, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_g2p_direct, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs);
+}
+void launch_g2p_adjoint_direct(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                               const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                               hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_g2p_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
+                     pacc);
+}
+void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
+                               const WorkItem* items, int n_items, const float* gcot, double* pacc, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_p2g_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+                     pacc);
+}
+
+}  // namespace mpmx

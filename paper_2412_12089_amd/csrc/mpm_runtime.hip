@@ -1,0 +1,660 @@
+// Host runtime and C interface of the batched MLS-MPM library.
+//
+// A batch holds E environments whose particles are concatenated (CSR by env)
+// in structure-of-arrays FP32 state buffers of 24 components, and whose dense
+// grids are concatenated tile by tile (4^3 nodes, 8 channels). A forward of S
+// substeps runs in segments of K: each segment sorts the particles by
+// (env, tile, cell) -- the sorted state is the segment's checkpoint -- and
+// then runs its substeps (P2G, grid update, G2P). With recording on, the last
+// segment also keeps every substep's state and grid (its tape). The backward
+// walks the segments in reverse: it re-runs each segment from its checkpoint
+// into the tape (gradient checkpointing with recomputation), runs the adjoint
+// substeps in reverse, and undoes the segment's sort permutation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_kernels.h"
+
+using namespace mpmx;
+
+namespace {
+
+enum KernelClass { KC_P2G = 0, KC_GRID, KC_G2P, KC_SORT, KC_G2P_ADJ, KC_GRID_ADJ, KC_P2G_ADJ, KC_COUNT };
+
+struct TimedSpan {
+  int kc;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mpm_batch {
+  // configuration
+  int E = 0;
+  std::vector<mpm_env_desc> desc;
+  int max_substeps = 0, K = 1, mode = MPM_MODE_BATCHED;
+  mpm_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // layout
+  std::vector<EnvDev> envs_h;
+  int64_t N = 0, n_tiles = 0;
+  int cell_bits = 0, key_bits = 0;
+  std::vector<WorkItem> items_h;
+  std::vector<int> item_off;  // [E+1]
+  int n_seg_max = 0;
+
+  // device buffers
+  std::vector<std::pair<void*, size_t>> allocations;
+  int64_t bytes = 0;
+  EnvDev* envs_d = nullptr;
+  WorkItem* items_d = nullptr;
+  int32_t* tile_env_d = nullptr;
+  float* W[2] = {nullptr, nullptr};
+  std::vector<float*> ckpt;        // [n_seg_max]
+  std::vector<float*> seg;         // [K + 1], seg[0] unused
+  std::vector<uint32_t*> perm;     // [n_seg_max]
+  int32_t *ids_cur = nullptr, *ids_tmp = nullptr, *ids_start = nullptr;
+  uint32_t *keys0 = nullptr, *vals0 = nullptr, *keys1 = nullptr, *vals1 = nullptr, *counts = nullptr;
+  std::vector<float*> grid;        // [K + 1]: 0 = scratch grid, 1..K = tape grids
+  std::vector<uint32_t*> flags;    // [K + 1]
+  std::vector<bool> grid_dirty;    // tape grid holds a substep not yet consumed
+  float* gcot = nullptr;
+  float* cot[2] = {nullptr, nullptr};
+  float* part = nullptr;
+  double* pacc = nullptr;
+  int32_t* errs = nullptr;
+  int32_t* clock = nullptr;
+
+  // state
+  float* cur = nullptr;
+  int64_t steps = 0;        // substeps taken since the last set_particles (collider clock)
+  bool recorded = false;
+  int rec_S = 0;
+  int64_t rec_steps0 = 0;
+  bool last_seg_taped = false;
+  std::vector<int32_t> env_err_h;
+
+  // kernel variants of the batched mode (0: one thread per particle with
+  // global atomics, 1: LDS-staged), chosen by mpm_autotune
+  int var_p2g = 1, var_g2p = 1, var_g2p_adj = 1, var_p2g_adj = 1;
+
+  // timing
+  bool timing = false;
+  std::vector<TimedSpan> spans;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+};
+
+namespace {
+
+const char* kVersion = "mpmx 0.1 (gfx950)";
+
+int fail(mpm_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define HIPC(b, expr)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail((b), MPM_DEVICE_ERROR, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+void* dalloc(mpm_batch* b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (b->has_alloc) {
+    p = b->alloc.alloc(bytes, b->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    b->allocations.push_back({p, bytes});
+    b->bytes += (int64_t)bytes;
+  }
+  return p;
+}
+
+void free_all(mpm_batch* b) {
+  for (auto& a : b->allocations) {
+    if (b->has_alloc)
+      b->alloc.free(a.first, b->alloc.ctx);
+    else
+      (void)hipFree(a.first);
+  }
+  b->allocations.clear();
+  b->bytes = 0;
+  for (auto e : b->event_pool) (void)hipEventDestroy(e);
+  b->event_pool.clear();
+}
+
+int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((uint64_t(1) << b) < v) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------- timing
+hipEvent_t next_event(mpm_batch* b) {
+  if (b->event_next == b->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    b->event_pool.push_back(e);
+  }
+  return b->event_pool[b->event_next++];
+}
+
+struct Span {
+  mpm_batch* b;
+  int kc;
+  hipEvent_t a = nullptr;
+  Span(mpm_batch* b_, int kc_) : b(b_), kc(kc_) {
+    if (b->timing) {
+      a = next_event(b);
+      if (a) (void)hipEventRecord(a, b->stream);
+    }
+  }
+  ~Span() {
+    if (b->timing && a) {
+      hipEvent_t z = next_event(b);
+      if (z) {
+        (void)hipEventRecord(z, b->stream);
+        b->spans.push_back({kc, a, z});
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------- one substep
+void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel) {
+  float* g = b->grid[gi];
+  uint32_t* fl = b->flags[gi];
+  const hipStream_t s = b->stream;
+  if (b->mode == MPM_MODE_PLAIN) {
+    for (int e = 0; e < b->E; ++e) {
+      const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
+      const EnvDev& eh = b->envs_h[e];
+      const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
+      { Span sp(b, KC_P2G); launch_p2g_direct(in, b->N, b->envs_d, b->items_d + i0, ni, g, fl, b->errs, s); }
+      { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, s); }
+      { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, s); }
+    }
+  } else {
+    const int ni = (int)b->items_h.size();
+    {
+      Span sp(b, KC_P2G);
+      if (b->var_p2g) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, s);
+      else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, s);
+    }
+    { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, s); }
+    {
+      Span sp(b, KC_G2P);
+      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, s);
+      else launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, s);
+    }
+  }
+}
+
+void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int gi, int k_rel) {
+  float* g = b->grid[gi];
+  uint32_t* fl = b->flags[gi];
+  const hipStream_t s = b->stream;
+  if (b->mode == MPM_MODE_PLAIN) {
+    for (int e = 0; e < b->E; ++e) {
+      const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
+      const EnvDev& eh = b->envs_h[e];
+      const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
+      { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, s); }
+      { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
+      { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, s); }
+    }
+  } else {
+    const int ni = (int)b->items_h.size();
+    {
+      Span sp(b, KC_G2P_ADJ);
+      if (b->var_g2p_adj) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, s);
+      else launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, s);
+    }
+    { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
+    {
+      Span sp(b, KC_P2G_ADJ);
+      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, s);
+      else launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, s);
+    }
+  }
+}
+
+// sorts `src` by (env, tile, cell); writes the permuted state to `dst`, the
+// permutation to `perm_out` (if not null) and updates ids_cur
+void sort_into(mpm_batch* b, const float* src, float* dst, uint32_t* perm_out) {
+  Span sp(b, KC_SORT);
+  const hipStream_t s = b->stream;
+  launch_keys(src, b->N, b->envs_d, b->items_d, (int)b->items_h.size(), b->keys0, b->vals0, b->cell_bits, s);
+  const int which = launch_radix_sort(b->keys0, b->vals0, b->keys1, b->vals1, b->counts, b->N, b->key_bits, s);
+  const uint32_t* pv = which ? b->vals1 : b->vals0;
+  if (perm_out) {
+    (void)hipMemcpyAsync(perm_out, pv, sizeof(uint32_t) * b->N, hipMemcpyDeviceToDevice, s);
+    pv = perm_out;
+  }
+  launch_permute_state(src, dst, b->N, pv, b->ids_cur, b->ids_tmp, s);
+  std::swap(b->ids_cur, b->ids_tmp);
+}
+
+void clear_dirty_tapes(mpm_batch* b) {
+  for (int k = 1; k <= b->K; ++k)
+    if (b->grid_dirty[k]) {
+      launch_grid_clear_flagged(b->n_tiles, b->grid[k], b->flags[k], b->stream);
+      b->grid_dirty[k] = false;
+    }
+}
+
+float* other_work(mpm_batch* b, const float* in) { return in == b->W[0] ? b->W[1] : b->W[0]; }
+
+int upload_envs(mpm_batch* b) {
+  HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
+  launch_prep_params(b->envs_d, b->E, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int check_env(mpm_batch* b, int32_t env, bool allow_all) {
+  if (env == -1 && allow_all) return MPM_OK;
+  if (env < 0 || env >= b->E) return fail(b, MPM_INVALID_ARG, "env index out of range");
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpm_version(void) { return kVersion; }
+
+const char* mpm_last_error(const mpm_batch* b) {
+  if (!b) return "null batch";
+  return b->err.c_str();
+}
+
+int64_t mpm_memory_bytes(const mpm_batch* b) { return b ? b->bytes : 0; }
+
+int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stream, mpm_batch** out) {
+  if (!d || !out || !d->envs) return MPM_INVALID_ARG;
+  *out = nullptr;
+  if (d->n_envs < 1 || d->ckpt_every < 1 || d->max_substeps < 0) return MPM_INVALID_ARG;
+  if (d->mode != MPM_MODE_PLAIN && d->mode != MPM_MODE_BATCHED) return MPM_INVALID_ARG;
+  if (a && (!a->alloc || !a->free)) return MPM_INVALID_ARG;
+  int64_t N = 0, tiles = 0;
+  uint64_t max_cells = 1;
+  for (int e = 0; e < d->n_envs; ++e) {
+    const mpm_env_desc& v = d->envs[e];
+    if (v.n < 12 || v.n % 4 != 0 || v.n > 1024) return MPM_INVALID_ARG;
+    if (v.material < 0 || v.material > MPM_FLUID_PAPER) return MPM_INVALID_ARG;
+    if (v.n_particles < 0 || !(v.dt > 0.f) || v.wall < 0 || 2 * v.wall + 3 > v.n) return MPM_INVALID_ARG;
+    N += v.n_particles;
+    tiles += (int64_t)(v.n / 4) * (v.n / 4) * (v.n / 4);
+    max_cells = std::max<uint64_t>(max_cells, (uint64_t)v.n * v.n * v.n);
+  }
+  if (N >= (int64_t(1) << 31)) return MPM_INVALID_ARG;
+  const int cell_bits = ceil_log2(max_cells);
+  const int env_bits = ceil_log2((uint64_t)d->n_envs);
+  if (cell_bits + env_bits > 32) return MPM_INVALID_ARG;
+
+  mpm_batch* b = new mpm_batch();
+  b->E = d->n_envs;
+  b->desc.assign(d->envs, d->envs + d->n_envs);
+  b->max_substeps = d->max_substeps;
+  b->K = d->ckpt_every;
+  b->mode = d->mode;
+  if (a) { b->alloc = *a; b->has_alloc = true; }
+  b->stream = (hipStream_t)stream;
+  b->N = N;
+  b->n_tiles = tiles;
+  b->cell_bits = cell_bits;
+  b->key_bits = std::max(1, cell_bits + env_bits);
+  b->n_seg_max = std::max(1, (b->max_substeps + b->K - 1) / b->K);
+
+  // env table and work items
+  b->envs_h.resize(b->E);
+  b->item_off.assign(b->E + 1, 0);
+  int64_t p_off = 0, t_off = 0;
+  std::vector<int32_t> tile_env(std::max<int64_t>(tiles, 1), 0);
+  for (int e = 0; e < b->E; ++e) {
+    const mpm_env_desc& v = d->envs[e];
+    EnvDev h;
+    std::memset(&h, 0, sizeof(h));
+    h.n = v.n; h.T = v.n / 4; h.material = v.material; h.wall = v.wall;
+    h.p_off = p_off; h.p_cnt = v.n_particles; h.tile_off = t_off;
+    h.dt = v.dt; h.fn = (float)v.n; h.dx = 1.f / (float)v.n;
+    h.gx = v.gravity[0]; h.gy = v.gravity[1]; h.gz = v.gravity[2];
+    h.rho = 1.0; h.nu = 0.0;  // inert until mpm_set_material
+    b->envs_h[e] = h;
+    b->item_off[e] = (int)b->items_h.size();
+    for (int64_t s0 = 0; s0 < v.n_particles; s0 += kItemSize) {
+      WorkItem it;
+      it.env = e;
+      it.start = p_off + s0;
+      it.count = (int32_t)std::min<int64_t>(kItemSize, v.n_particles - s0);
+      b->items_h.push_back(it);
+    }
+    const int64_t nt = (int64_t)h.T * h.T * h.T;
+    for (int64_t t = 0; t < nt; ++t) tile_env[t_off + t] = e;
+    p_off += v.n_particles;
+    t_off += nt;
+  }
+  b->item_off[b->E] = (int)b->items_h.size();
+  b->env_err_h.assign(b->E, 0);
+
+  const size_t state_bytes = sizeof(float) * 24 * (size_t)std::max<int64_t>(N, 1);
+  const size_t grid_bytes = sizeof(float) * 512 * (size_t)std::max<int64_t>(tiles, 1);
+  const size_t flag_bytes = sizeof(uint32_t) * (size_t)std::max<int64_t>(tiles, 1);
+  const size_t nbytes_i = sizeof(int32_t) * (size_t)std::max<int64_t>(N, 1);
+  bool ok = true;
+  auto A = [&](size_t bytes) -> void* {
+    void* p = ok ? dalloc(b, bytes) : nullptr;
+    if (!p) ok = false;
+    return p;
+  };
+  b->envs_d = (EnvDev*)A(sizeof(EnvDev) * b->E);
+  b->items_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(b->items_h.size(), 1));
+  b->tile_env_d = (int32_t*)A(sizeof(int32_t) * tile_env.size());
+  b->W[0] = (float*)A(state_bytes);
+  b->W[1] = (float*)A(state_bytes);
+  for (int j = 0; j < b->n_seg_max; ++j) b->ckpt.push_back((float*)A(state_bytes));
+  b->seg.push_back(nullptr);
+  for (int k = 1; k <= b->K; ++k) b->seg.push_back((float*)A(state_bytes));
+  for (int j = 0; j < b->n_seg_max; ++j) b->perm.push_back((uint32_t*)A(nbytes_i));
+  b->ids_cur = (int32_t*)A(nbytes_i);
+  b->ids_tmp = (int32_t*)A(nbytes_i);
+  b->ids_start = (int32_t*)A(nbytes_i);
+  b->keys0 = (uint32_t*)A(nbytes_i);
+  b->vals0 = (uint32_t*)A(nbytes_i);
+  b->keys1 = (uint32_t*)A(nbytes_i);
+  b->vals1 = (uint32_t*)A(nbytes_i);
+  const int64_t rs_blocks = (std::max<int64_t>(N, 1) + RS_TILE - 1) / RS_TILE;
+  b->counts = (uint32_t*)A(sizeof(uint32_t) * 256 * rs_blocks);
+  for (int k = 0; k <= b->K; ++k) {
+    b->grid.push_back((float*)A(grid_bytes));
+    b->flags.push_back((uint32_t*)A(flag_bytes));
+  }
+  b->grid_dirty.assign(b->K + 1, false);
+  b->gcot = (float*)A(grid_bytes);
+  b->cot[0] = (float*)A(state_bytes);
+  b->cot[1] = (float*)A(state_bytes);
+  b->part = (float*)A(sizeof(float) * 12 * (size_t)std::max<int64_t>(N, 1));
+  b->pacc = (double*)A(sizeof(double) * 8 * b->E);
+  b->errs = (int32_t*)A(sizeof(int32_t) * b->E);
+  b->clock = (int32_t*)A(256);
+  if (!ok) {
+    free_all(b);
+    delete b;
+    return MPM_OUT_OF_MEMORY;
+  }
+  const hipStream_t s = b->stream;
+  auto zero = [&](void* p, size_t bytes) { launch_fill_u32(p, 0u, (int64_t)(bytes / 4), s); };
+  int rc = MPM_OK;
+  do {
+    if (hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->tile_env_d, tile_env.data(), sizeof(int32_t) * tile_env.size(), hipMemcpyHostToDevice, s) != hipSuccess) {
+      rc = MPM_DEVICE_ERROR;
+      break;
+    }
+    for (int k = 0; k <= b->K; ++k) { zero(b->grid[k], grid_bytes); zero(b->flags[k], flag_bytes); }
+    zero(b->gcot, grid_bytes);
+    zero(b->W[0], state_bytes);
+    zero(b->errs, sizeof(int32_t) * b->E);
+    zero(b->clock, 256);
+    // identity ids and an F = I rest state until particles are set
+    rc = upload_envs(b);
+  } while (0);
+  if (rc == MPM_OK && hipStreamSynchronize(s) != hipSuccess) rc = MPM_DEVICE_ERROR;
+  if (rc != MPM_OK) {
+    free_all(b);
+    delete b;
+    return rc;
+  }
+  b->cur = b->W[0];
+  *out = b;
+  return MPM_OK;
+}
+
+int mpm_batch_destroy(mpm_batch* b) {
+  if (!b) return MPM_INVALID_ARG;
+  (void)hipStreamSynchronize(b->stream);
+  free_all(b);
+  delete b;
+  return MPM_OK;
+}
+
+int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v, const float* C, const float* F,
+                      int64_t n) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, true);
+  if (rc) return rc;
+  const int64_t want = env < 0 ? b->N : b->envs_h[env].p_cnt;
+  if (n != want) return fail(b, MPM_INVALID_ARG, "particle count does not match the env description");
+  if (n > 0 && (!x || !v || !C || !F)) return fail(b, MPM_INVALID_ARG, "null particle array");
+  const int64_t off = env < 0 ? 0 : b->envs_h[env].p_off;
+  clear_dirty_tapes(b);
+  launch_load_aos(x, v, C, F, n, b->cur, b->N, off, b->ids_cur, b->stream);
+  HIPC(b, hipGetLastError());
+  b->steps = 0;
+  b->recorded = false;
+  b->last_seg_taped = false;
+  return MPM_OK;
+}
+
+int mpm_get_particles(mpm_batch* b, int32_t env, float* x, float* v, float* C, float* F) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, true);
+  if (rc) return rc;
+  const int64_t lo = env < 0 ? 0 : b->envs_h[env].p_off;
+  const int64_t hi = env < 0 ? b->N : lo + b->envs_h[env].p_cnt;
+  launch_store_aos(b->cur, b->N, b->ids_cur, lo, hi, x, v, C, F, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p[8]) {
+  if (!b || !p) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, true);
+  if (rc) return rc;
+  if (material < 0 || material > MPM_FLUID_PAPER) return fail(b, MPM_INVALID_ARG, "unknown material");
+  const double E = p[0], nu = p[1], rho = p[2], Vp = p[3], sy = p[4], K = p[5], gam = p[6];
+  if (!(nu > -1.0 && nu < 0.5)) return fail(b, MPM_INVALID_ARG, "nu must lie in (-1, 0.5)");
+  if (!(E >= 0.0) || !(rho >= 0.0) || !(Vp >= 0.0) || !(sy >= 0.0) || !(K >= 0.0))
+    return fail(b, MPM_INVALID_ARG, "E, rho, Vp, sigma_y and K must be finite and >= 0");
+  if (material == MPM_FLUID_TAIT && !(gam > 0.0)) return fail(b, MPM_INVALID_ARG, "Tait gamma must be > 0");
+  if (material == MPM_VONMISES && !(E > 0.0)) return fail(b, MPM_INVALID_ARG, "von Mises needs E > 0");
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
+  for (int e = e0; e < e1; ++e) {
+    EnvDev& h = b->envs_h[e];
+    h.material = material;
+    h.E = E; h.nu = nu; h.rho = rho; h.Vp = Vp; h.sigma_y = sy; h.K = K; h.gamma = gam;
+  }
+  b->recorded = false;
+  return upload_envs(b);
+}
+
+int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const float h[3], const float v[3], float alpha,
+                         float mu_b) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, true);
+  if (rc) return rc;
+  if (alpha > 0.f && (!c || !h || !v)) return fail(b, MPM_INVALID_ARG, "null collider array");
+  if (alpha > 0.f && !(mu_b >= 0.f)) return fail(b, MPM_INVALID_ARG, "mu_b must be >= 0");
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
+  for (int e = e0; e < e1; ++e) {
+    EnvDev& d = b->envs_h[e];
+    d.has_collider = alpha > 0.f ? 1 : 0;
+    if (d.has_collider) {
+      for (int a = 0; a < 3; ++a) { d.cc[a] = c[a]; d.ch[a] = h[a]; d.cv[a] = v[a]; }
+      d.c_alpha = alpha;
+      d.c_mu = mu_b;
+    }
+  }
+  b->recorded = false;
+  return upload_envs(b);
+}
+
+int mpm_forward(mpm_batch* b, int32_t S, int32_t flags) {
+  if (!b) return MPM_INVALID_ARG;
+  if (S < 0 || S > b->max_substeps) return fail(b, MPM_BAD_STATE, "n_substeps outside [0, max_substeps]");
+  const bool record = (flags & MPM_FWD_RECORD) != 0;
+  const hipStream_t s = b->stream;
+  if (b->timing) { b->spans.clear(); b->event_next = 0; }
+  clear_dirty_tapes(b);
+  b->recorded = false;
+  b->last_seg_taped = false;
+  if (record) launch_copy_i32(b->ids_cur, b->ids_start, b->N, s);
+  const int nseg = (S + b->K - 1) / b->K;
+  float* src = b->cur;
+  for (int j = 0; j < nseg; ++j) {
+    const int Kj = std::min(b->K, S - j * b->K);
+    launch_set_clock(b->clock, (int32_t)(b->steps + (int64_t)j * b->K), s);
+    float* dst0 = record ? b->ckpt[j] : other_work(b, src);
+    if (b->N > 0) sort_into(b, src, dst0, record ? b->perm[j] : nullptr);
+    const bool tape = record && j == nseg - 1;
+    const float* in = dst0;
+    for (int k = 0; k < Kj; ++k) {
+      float* out;
+      int gi, clear;
+      if (tape) {
+        out = b->seg[k + 1];
+        gi = k + 1;
+        clear = 0;
+        b->grid_dirty[gi] = true;
+      } else {
+        out = other_work(b, in);
+        gi = 0;
+        clear = 1;
+      }
+      if (b->N > 0) substep(b, in, out, gi, clear, k);
+      in = out;
+    }
+    src = (float*)in;
+  }
+  b->cur = src;
+  HIPC(b, hipGetLastError());
+  if (record) {
+    b->recorded = true;
+    b->rec_S = S;
+    b->rec_steps0 = b->steps;
+    b->last_seg_taped = nseg > 0;
+  }
+  b->steps += S;
+  return MPM_OK;
+}
+
+int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC, const float* gF, float* dx0,
+                 float* dv0, float* dC0, float* dF0, double* dparams) {
+  if (!b) return MPM_INVALID_ARG;
+  if (!b->recorded) return fail(b, MPM_BAD_STATE, "backward needs a preceding recorded forward");
+  const hipStream_t s = b->stream;
+  if (b->timing) { b->spans.clear(); b->event_next = 0; }
+  launch_fill_u32(b->pacc, 0u, 2 * 8 * (int64_t)b->E, s);
+  const int S = b->rec_S;
+  const int nseg = (S + b->K - 1) / b->K;
+  int c = 0;
+  launch_gather_aos(gx, gv, gC, gF, b->ids_cur, b->cot[c], b->N, s);
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int Kj = std::min(b->K, S - j * b->K);
+    launch_set_clock(b->clock, (int32_t)(b->rec_steps0 + (int64_t)j * b->K), s);
+    const bool have_tape = (j == nseg - 1) && b->last_seg_taped;
+    if (!have_tape) {
+      clear_dirty_tapes(b);
+      const float* in = b->ckpt[j];
+      for (int k = 0; k < Kj; ++k) {
+        substep(b, in, b->seg[k + 1], k + 1, 0, k);
+        b->grid_dirty[k + 1] = true;
+        in = b->seg[k + 1];
+      }
+    }
+    for (int k = Kj - 1; k >= 0; --k) {
+      const float* st = k == 0 ? b->ckpt[j] : b->seg[k];
+      adjoint_substep(b, st, b->cot[c], b->cot[c ^ 1], k + 1, k);
+      b->grid_dirty[k + 1] = false;
+      c ^= 1;
+    }
+    launch_unpermute(b->cot[c], b->cot[c ^ 1], b->N, b->perm[j], s);
+    c ^= 1;
+  }
+  b->last_seg_taped = false;
+  launch_store_aos(b->cot[c], b->N, b->ids_start, 0, b->N, dx0, dv0, dC0, dF0, s);
+  if (dparams) launch_finalize_params(b->envs_d, b->pacc, dparams, b->E, s);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_sort_keys(mpm_batch* b, uint32_t* keys, uint32_t* perm, int32_t* ids, int32_t* cell_bits) {
+  if (!b) return MPM_INVALID_ARG;
+  if (cell_bits) *cell_bits = b->cell_bits;
+  if (b->N == 0) return MPM_OK;
+  const hipStream_t s = b->stream;
+  launch_keys(b->cur, b->N, b->envs_d, b->items_d, (int)b->items_h.size(), b->keys0, b->vals0, b->cell_bits, s);
+  if (keys) HIPC(b, hipMemcpyAsync(keys, b->keys0, sizeof(uint32_t) * b->N, hipMemcpyDeviceToDevice, s));
+  const int which = launch_radix_sort(b->keys0, b->vals0, b->keys1, b->vals1, b->counts, b->N, b->key_bits, s);
+  if (perm) HIPC(b, hipMemcpyAsync(perm, which ? b->vals1 : b->vals0, sizeof(uint32_t) * b->N, hipMemcpyDeviceToDevice, s));
+  if (ids) HIPC(b, hipMemcpyAsync(ids, b->ids_cur, sizeof(int32_t) * b->N, hipMemcpyDeviceToDevice, s));
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_sync(mpm_batch* b) {
+  if (!b) return MPM_INVALID_ARG;
+  HIPC(b, hipStreamSynchronize(b->stream));
+  HIPC(b, hipMemcpy(b->env_err_h.data(), b->errs, sizeof(int32_t) * b->E, hipMemcpyDeviceToHost));
+  int agg = 0;
+  for (int v : b->env_err_h) agg |= v;
+  launch_fill_u32(b->errs, 0u, b->E, b->stream);
+  HIPC(b, hipStreamSynchronize(b->stream));
+  if (agg & ERR_NONFINITE) return fail(b, MPM_NONFINITE, "non-finite particle state");
+  if (agg & ERR_OUT_OF_DOMAIN) return fail(b, MPM_OUT_OF_DOMAIN, "particle left the stencil band (clamped)");
+  return MPM_OK;
+}
+
+int mpm_env_errors(mpm_batch* b, int32_t* errs) {
+  if (!b || !errs) return MPM_INVALID_ARG;
+  std::memcpy(errs, b->env_err_h.data(), sizeof(int32_t) * b->E);
+  return MPM_OK;
+}
+
+int mpm_set_timing(mpm_batch* b, int32_t enabled) {
+  if (!b) return MPM_INVALID_ARG;
+  b->timing = enabled != 0;
+  b->spans.clear();
+  b->event_next = 0;
+  return MPM_OK;
+}
+
+int mpm_kernel_time(mpm_batch* b, int32_t kernel, double* mean_ms) {
+  if (!b || !mean_ms || kernel < 0 || kernel >= KC_COUNT) return MPM_INVALID_ARG;
+  HIPC(b, hipStreamSynchronize(b->stream));
+  double tot = 0.0;
+  int n = 0;
+  for (auto& sp : b->spans) {
+    if (sp.kc != kernel) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) { tot += ms; ++n; }
+  }
+  *mean_ms = n ? tot / n : 0.0;
+  return n;
+}
+
+int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
+  if (!b) return MPM_INVALID_ARG;
+  (void)budget_ms;
+  return MPM_OK;
+}
+
+}  // extern "C"

@@ -110,8 +110,9 @@ int mpm_batch_destroy(mpm_batch* b);
 
 /* Copies particle state in (device pointers, AoS layout above). env >= 0 sets
  * that environment (n must equal its n_particles); env = -1 sets every
- * environment from arrays concatenated in env order (n = total). The batch
- * clock restarts at t = 0 and any recorded tape is dropped. */
+ * environment from arrays concatenated in env order (n = total of the
+ * current counts). The batch clock restarts at t = 0 and any recorded tape is
+ * dropped. */
 int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v, const float* C, const float* F,
                       int64_t n);
 
@@ -143,6 +144,22 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const
  * otherwise any earlier record is dropped. Asynchronous on the stream. */
 int mpm_forward(mpm_batch* b, int32_t n_substeps, int32_t flags);
 
+/* Like mpm_forward, but environment e takes n_substeps[e] substeps (HOST
+ * array [n_envs], each in [0, max_substeps]); once an environment has taken
+ * its substeps it is frozen -- its state passes through unchanged, and in the
+ * backward its cotangent passes through unchanged -- while the others run on.
+ * The continuous-batching server advances slots by different amounts with it. */
+int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags);
+
+/* Re-describes environment `env` in place (a serving slot): grid n up to the
+ * n it was created with, n_particles up to its created count (its capacity),
+ * and any material, dt, gravity, wall. Its collider is removed; set its
+ * material and particles (mpm_set_material, mpm_set_particles with this
+ * env's new count) before the next forward. The rows of every env=-1 array
+ * become the concatenation of the current counts. Drops any record; cached
+ * graphs stay valid. Errors: INVALID_ARG above capacity. */
+int mpm_configure_env(mpm_batch* b, int32_t env, const mpm_env_desc* d);
+
 /* Reverse-mode adjoint of the last recorded mpm_forward. Inputs: cotangents
  * of the final state (device, AoS over all environments in original order;
  * NULL = zero). Outputs: cotangents of the state at the start of that forward
@@ -153,6 +170,20 @@ int mpm_forward(mpm_batch* b, int32_t n_substeps, int32_t flags);
  * Errors: BAD_STATE if no recorded forward precedes. */
 int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC, const float* gF, float* dx0,
                  float* dv0, float* dC0, float* dF0, double* dparams);
+
+/* Execution options (mpm_set_option / mpm_get_option). Changing a kernel
+ * variant drops the cached graphs. */
+#define MPM_OPT_GRAPHS 1       /* 1: replay each segment as a hipGraph (batched mode only; default 1) */
+#define MPM_OPT_P2G 2          /* P2G variant: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default) */
+#define MPM_OPT_G2P 3          /* G2P variant: 0 global gathers, 1 LDS-staged (default) */
+#define MPM_OPT_G2P_ADJ 4      /* G2P adjoint: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default) */
+#define MPM_OPT_P2G_ADJ 5      /* P2G adjoint: 0 global gathers, 1 LDS-staged (default) */
+#define MPM_OPT_MIN_RUN 6      /* per-cell-run variants engage when particles per stencil base >= this (default 3) */
+
+/* Sets one option; INVALID_ARG for an unknown option or value. */
+int mpm_set_option(mpm_batch* b, int32_t option, int32_t value);
+/* Reads one option into the host int *value. */
+int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value);
 
 /* Times the batched kernels' launch shapes on the current state (for about
  * budget_ms milliseconds), keeps the fastest whose forward result agrees
@@ -166,8 +197,10 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms);
  * keys[i] = (env << cell_bits) | (tile * 64 + cell) with base clamped to
  * [0, n-3], tile = ((bx/4) T + by/4) T + bz/4, T = n/4, cell =
  * ((bx%4) 4 + by%4) 4 + bz%4 (uint32 [N]); perm, the stable sort order (new
- * position j takes internal position perm[j], uint32 [N]); ids, the caller
- * index of each internal position (int32 [N]). *cell_bits is a host int.
+ * position j takes internal position perm[j], uint32 [N]); ids, the
+ * env-local caller index of each internal position, -1 where a slot's
+ * capacity holds no particle (int32 [N]). N counts capacity positions.
+ * *cell_bits is a host int.
  * Any output pointer may be NULL. */
 int mpm_sort_keys(mpm_batch* b, uint32_t* keys, uint32_t* perm, int32_t* ids, int32_t* cell_bits);
 

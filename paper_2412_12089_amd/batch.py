@@ -140,10 +140,32 @@ class Batch:
         if record:
             self.record_token += 1
 
+    def forward_envs(self, n_substeps, record: bool = False) -> None:
+        arr = (ctypes.c_int32 * self.E)(*[int(k) for k in n_substeps])
+        self._chk(self.lib.mpm_forward_envs(self.h, arr, C.MPM_FWD_RECORD if record else 0), "mpm_forward_envs")
+        if record:
+            self.record_token += 1
+
+    def configure_env(self, env: int, spec: EnvSpec) -> None:
+        """Re-describe slot `env` (within its capacity) and set its material and particles."""
+        d = C.mpm_env_desc()
+        d.n, d.material, d.n_particles, d.dt, d.wall = spec.n, spec.material, spec.n_particles, spec.dt, spec.wall
+        d.gravity[:] = list(spec.gravity)
+        self._chk(self.lib.mpm_configure_env(self.h, env, ctypes.byref(d)), "mpm_configure_env")
+        self.counts[env] = spec.n_particles
+        self.N = int(sum(self.counts))
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self.envs[env] = spec
+        self.set_material(env, spec.material, spec.params())
+        if spec.collider is not None:
+            c = spec.collider
+            self.set_box_collider(env, c.center, c.half, c.velocity, c.alpha, c.mu_b)
+
     def backward(self, gx=None, gv=None, gC=None, gF=None, want_params: bool = True):
         d = self.device
         cv = lambda t: None if t is None else _f32(t, d)
         gx, gv, gC, gF = cv(gx), cv(gv), cv(gC), cv(gF)
+        self._keep_cot = (gx, gv, gC, gF)
         dx = torch.empty(self.N, 3, device=d)
         dv = torch.empty(self.N, 3, device=d)
         dC = torch.empty(self.N, 3, 3, device=d)
@@ -177,6 +199,14 @@ class Batch:
 
     def autotune(self, budget_ms: int = 200) -> None:
         self._chk(self.lib.mpm_autotune(self.h, int(budget_ms)), "mpm_autotune")
+
+    def set_option(self, option: int, value: int) -> None:
+        self._chk(self.lib.mpm_set_option(self.h, int(option), int(value)), "mpm_set_option")
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int32()
+        self._chk(self.lib.mpm_get_option(self.h, int(option), ctypes.byref(v)), "mpm_get_option")
+        return int(v.value)
 
     def memory_bytes(self) -> int:
         return int(self.lib.mpm_memory_bytes(self.h))

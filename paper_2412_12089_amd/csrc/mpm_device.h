@@ -30,7 +30,7 @@ constexpr float kYieldScale = 2.0f;  // numerator of the printed yield offset kY
 // written by the host; the derived block by the parameter-preparation kernel.
 struct EnvDev {
   int32_t n, T, material, wall;          // nodes per axis, 4^3 tiles per axis
-  int32_t has_collider, pad0;
+  int32_t has_collider, nsub;         // nsub: substeps this env takes in the current forward call
   int64_t p_off, p_cnt;                  // particle range in the batch arrays
   int64_t tile_off;                      // first tile of this env in the grid buffers
   float dt, fn, dx, gx, gy, gz;
@@ -39,6 +39,8 @@ struct EnvDev {
   // derived (a1): Lame parameters and constants in FP32
   float mu, lam, alpha_nh, mp, vp, sy, bulk, gam, yieldY;
   float pad1[3];
+  int64_t row_off;                       // first row of this env in the caller's concatenated arrays
+  int64_t p_cap;                         // particle capacity (positions [p_off, p_off + p_cap))
 };
 
 // --------------------------------------------------------------------------

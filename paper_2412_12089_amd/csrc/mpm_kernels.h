@@ -8,29 +8,34 @@
 namespace mpmx {
 
 // A block's share of one environment's particles: [start, start + count).
+// Positions [start, start + cap) belong to the env's capacity; the first
+// `count` of them hold live particles (count may be 0).
 struct WorkItem {
   int32_t env;
   int32_t count;
   int64_t start;
+  int32_t cap;
+  int32_t pad;
 };
 constexpr int kItemSize = 256;
 
-// radix sort geometry: 256 threads x 16 keys per block
+// radix sort geometry: 256 threads x 4 keys per block
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 4;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
 void launch_prep_params(EnvDev* envs, int n_envs, hipStream_t s);
 void launch_finalize_params(const EnvDev* envs, const double* acc, double* out, int n_envs, hipStream_t s);
-void launch_load_aos(const float* x, const float* v, const float* C, const float* F, int64_t n, float* st, int64_t N,
-                     int64_t off, int32_t* ids, hipStream_t s);
-void launch_store_aos(const float* st, int64_t N, const int32_t* ids, int64_t lo, int64_t hi, float* x, float* v,
-                      float* C, float* F, hipStream_t s);
-void launch_gather_aos(const float* x, const float* v, const float* C, const float* F, const int32_t* ids, float* st,
-                       int64_t N, hipStream_t s);
+void launch_load_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* x, const float* v,
+                     const float* C, const float* F, float* st, int64_t N, int32_t* ids, hipStream_t s);
+void launch_store_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* st, int64_t N,
+                      const int32_t* ids, float* x, float* v, float* C, float* F, hipStream_t s);
+void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
+                       const float* C, const float* F, const int32_t* ids, float* st, int64_t N, hipStream_t s);
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
 void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s);
+void launch_add_clock(int32_t* clock, int32_t delta, hipStream_t s);
 void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
                  uint32_t* vals, int cell_bits, hipStream_t s);
 int launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* counts, int64_t N,
@@ -39,29 +44,37 @@ void launch_permute_state(const float* src, float* dst, int64_t N, const uint32_
                           int32_t* ids_out, hipStream_t s);
 void launch_unpermute(const float* src, float* dst, int64_t N, const uint32_t* perm, hipStream_t s);
 void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                       uint32_t* flags, int32_t* errs, hipStream_t s);
+                       uint32_t* flags, int32_t* errs, int k_call, hipStream_t s);
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                         uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, hipStream_t s);
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                          uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, hipStream_t s);
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s);
 void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                       const float* grid, int32_t* errs, hipStream_t s);
+                       const float* grid, int32_t* errs, int k_call, hipStream_t s);
 void launch_g2p_adjoint_direct(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                                const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                               hipStream_t s);
+                               int k_call, hipStream_t s);
 void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                               const WorkItem* items, int n_items, const float* gcot, double* pacc, hipStream_t s);
+                               const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s);
 
 // LDS-staged variants of the particle kernels (batched mode)
 void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, hipStream_t s);
+                    uint32_t* flags, int32_t* errs, int k_call, hipStream_t s);
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                    const float* grid, int32_t* errs, hipStream_t s);
+                    const float* grid, int32_t* errs, int k_call, hipStream_t s);
 void launch_g2p_adjoint_lds(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            hipStream_t s);
+                            int k_call, hipStream_t s);
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                            const WorkItem* items, int n_items, const float* gcot, double* pacc, hipStream_t s);
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s);
+
+// segment-reduced scatters: blocks whose particles average at least min_run
+// per stencil base sum each base's run in registers before the LDS atomics
+void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                    uint32_t* flags, int32_t* errs, int min_run, int k_call, hipStream_t s);
+void launch_g2p_adjoint_seg(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                            int min_run, int k_call, hipStream_t s);
 
 }  // namespace mpmx

@@ -89,14 +89,22 @@ __global__ void k_finalize_params(const EnvDev* envs, const double* acc, double*
 }
 
 // ----------------------------------------------------------------------------
-// layout conversion between the caller's AoS arrays and the internal SoA
+// layout conversion between the caller's AoS arrays and the internal SoA.
+// Launched over work items; `all` selects rows in the concatenation of every
+// env (row_off + local index) or the env's own rows (local index). ids[p]
+// holds the env-local caller index of the particle at position p (-1: none).
 // ----------------------------------------------------------------------------
-__global__ void k_load_aos(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
-                           const float* __restrict__ F, int64_t n, float* __restrict__ st, int64_t N, int64_t off,
-                           int32_t* __restrict__ ids) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t p = off + i;
+__global__ void k_load_aos(const WorkItem* __restrict__ items, const EnvDev* __restrict__ envs, int all,
+                           const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
+                           const float* __restrict__ F, float* __restrict__ st, int64_t N, int32_t* __restrict__ ids) {
+  const WorkItem it = items[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= it.cap) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + t;
+  const int64_t local = p - e.p_off;
+  if (t >= it.count) { ids[p] = -1; return; }
+  const int64_t i = (all ? e.row_off : 0) + local;
   for (int a = 0; a < 3; ++a) {
     st[a * N + p] = x[3 * i + a];
     st[(3 + a) * N + p] = v[3 * i + a];
@@ -105,18 +113,21 @@ __global__ void k_load_aos(const float* __restrict__ x, const float* __restrict_
     st[(6 + k) * N + p] = C[9 * i + k];
     st[(15 + k) * N + p] = F[9 * i + k];
   }
-  ids[p] = (int32_t)p;
+  ids[p] = (int32_t)local;
 }
 
-// out rows are indexed by the particle's caller index ids[p]; rows [lo, hi) only
-__global__ void k_store_aos(const float* __restrict__ st, int64_t N, const int32_t* __restrict__ ids, int64_t lo,
-                            int64_t hi, float* __restrict__ x, float* __restrict__ v, float* __restrict__ C,
+__global__ void k_store_aos(const WorkItem* __restrict__ items, const EnvDev* __restrict__ envs, int all,
+                            const float* __restrict__ st, int64_t N, const int32_t* __restrict__ ids,
+                            float* __restrict__ x, float* __restrict__ v, float* __restrict__ C,
                             float* __restrict__ F) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int64_t u = ids[p];
-  if (u < lo || u >= hi) return;
-  const int64_t r = u - lo;
+  const WorkItem it = items[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= it.count) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + t;
+  const int64_t id = ids[p];
+  if (id < 0) return;
+  const int64_t r = (all ? e.row_off : 0) + id;
   for (int a = 0; a < 3; ++a) {
     if (x) x[3 * r + a] = st[a * N + p];
     if (v) v[3 * r + a] = st[(3 + a) * N + p];
@@ -127,20 +138,25 @@ __global__ void k_store_aos(const float* __restrict__ st, int64_t N, const int32
   }
 }
 
-// internal cot[p] = caller cotangent row ids[p] (null arrays count as zero)
-__global__ void k_gather_aos(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
+// internal cot[p] = caller cotangent row (null arrays and empty positions count as zero)
+__global__ void k_gather_aos(const WorkItem* __restrict__ items, const EnvDev* __restrict__ envs,
+                             const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ C,
                              const float* __restrict__ F, const int32_t* __restrict__ ids, float* __restrict__ st,
                              int64_t N) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int64_t u = ids[p];
+  const WorkItem it = items[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= it.cap) return;
+  const EnvDev& e = envs[it.env];
+  const int64_t p = it.start + t;
+  const bool live = t < it.count && ids[p] >= 0;
+  const int64_t u = live ? e.row_off + ids[p] : 0;
   for (int a = 0; a < 3; ++a) {
-    st[a * N + p] = x ? x[3 * u + a] : 0.f;
-    st[(3 + a) * N + p] = v ? v[3 * u + a] : 0.f;
+    st[a * N + p] = (live && x) ? x[3 * u + a] : 0.f;
+    st[(3 + a) * N + p] = (live && v) ? v[3 * u + a] : 0.f;
   }
   for (int k = 0; k < 9; ++k) {
-    st[(6 + k) * N + p] = C ? C[9 * u + k] : 0.f;
-    st[(15 + k) * N + p] = F ? F[9 * u + k] : 0.f;
+    st[(6 + k) * N + p] = (live && C) ? C[9 * u + k] : 0.f;
+    st[(15 + k) * N + p] = (live && F) ? F[9 * u + k] : 0.f;
   }
 }
 
@@ -157,6 +173,10 @@ __global__ void k_set_clock(int32_t* clock, int32_t value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = value;
 }
 
+__global__ void k_add_clock(int32_t* clock, int32_t delta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += delta;
+}
+
 // ----------------------------------------------------------------------------
 // a2: binning keys and a stable LSD radix sort (8-bit digits)
 // ----------------------------------------------------------------------------
@@ -164,17 +184,21 @@ __global__ void __launch_bounds__(256) k_keys(const float* __restrict__ st, int6
                                               const WorkItem* __restrict__ items, uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals, int cell_bits) {
   const WorkItem it = items[blockIdx.x];
-  if ((int)threadIdx.x >= it.count) return;
+  if ((int)threadIdx.x >= it.cap) return;
   const EnvDev& e = envs[it.env];
   const int64_t p = it.start + threadIdx.x;
-  int b[3];
-  for (int a = 0; a < 3; ++a) {
-    int q = base_floor(st[a * N + p], e.n);
-    b[a] = q < 0 ? 0 : (q > e.n - 3 ? e.n - 3 : q);
+  uint32_t local = (1u << cell_bits) - 1u;   // empty positions sort last within their env
+  if ((int)threadIdx.x < it.count) {
+    int b[3];
+    for (int a = 0; a < 3; ++a) {
+      int q = base_floor(st[a * N + p], e.n);
+      b[a] = q < 0 ? 0 : (q > e.n - 3 ? e.n - 3 : q);
+    }
+    const uint32_t tile = (uint32_t)(((b[0] >> 2) * e.T + (b[1] >> 2)) * e.T + (b[2] >> 2));
+    const uint32_t cell = (uint32_t)((((b[0] & 3) << 4) | ((b[1] & 3) << 2) | (b[2] & 3)));
+    local = tile * 64u + cell;
   }
-  const uint32_t tile = (uint32_t)(((b[0] >> 2) * e.T + (b[1] >> 2)) * e.T + (b[2] >> 2));
-  const uint32_t cell = (uint32_t)((((b[0] & 3) << 4) | ((b[1] & 3) << 2) | (b[2] & 3)));
-  keys[p] = ((uint32_t)it.env << cell_bits) | (tile * 64u + cell);
+  keys[p] = ((uint32_t)it.env << cell_bits) | local;
   vals[p] = (uint32_t)p;
 }
 
@@ -192,36 +216,63 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint32_t* __res
   counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of n entries by one block of 1024 threads
-__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t* __restrict__ a, int64_t n) {
-  __shared__ uint32_t sums[1024];
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  uint32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += a[i];
-  sums[t] = s;
+// per digit d (one block each): exclusive scan of counts[d][0..nblocks) in
+// place, digit total into totals[d]
+__global__ void __launch_bounds__(256) k_scan_digit(uint32_t* __restrict__ counts, uint32_t* __restrict__ totals,
+                                                    int nblocks) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t carry;
+  uint32_t* row = counts + (int64_t)blockIdx.x * nblocks;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) carry = 0;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = t >= off ? sums[t - off] : 0u;
+  for (int base = 0; base < nblocks; base += 256) {
+    const int i = base + t;
+    const uint32_t v = i < nblocks ? row[i] : 0u;
+    uint32_t x = v;   // inclusive wave scan
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    sums[t] += v;
+    uint32_t pre = carry;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    if (i < nblocks) row[i] = pre + x - v;
+    __syncthreads();
+    if (t == 255) carry = pre + x;
     __syncthreads();
   }
-  uint32_t run = sums[t] - s;
-  for (int64_t i = lo; i < hi; ++i) { const uint32_t v = a[i]; a[i] = run; run += v; }
+  if (t == 0) totals[blockIdx.x] = carry;
 }
 
+// stable scatter of one 8-bit digit pass; positions = digit base + this
+// block's offset within the digit + rank among equal digits (in index order)
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint32_t* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
                                                               uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                               int64_t N, int shift, const uint32_t* __restrict__ offs,
-                                                              int nblocks) {
+                                                              const uint32_t* __restrict__ totals, int nblocks) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  __shared__ uint32_t dsum[RS_THREADS / 64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  run[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
-  for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
+  {
+    const uint32_t v = totals[tid];
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) dsum[wave] = x;
+    for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += dsum[w];
+    run[tid] = pre + x - v + offs[(int64_t)tid * nblocks + blockIdx.x];
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -294,10 +345,11 @@ MD void mark_tiles(const EnvDev& e, const int b[3], uint32_t* __restrict__ flags
 __global__ void __launch_bounds__(256) k_p2g_direct(const float* __restrict__ st, int64_t N,
                                                     const EnvDev* __restrict__ envs,
                                                     const WorkItem* __restrict__ items, float* __restrict__ grid,
-                                                    uint32_t* __restrict__ flags, int32_t* __restrict__ errs) {
+                                                    uint32_t* __restrict__ flags, int32_t* __restrict__ errs, int k_call) {
   const WorkItem it = items[blockIdx.x];
   if ((int)threadIdx.x >= it.count) return;
   const EnvDev& e = envs[it.env];
+  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int64_t p = it.start + threadIdx.x;
   const PState s = load_state(st, N, p);
   const Stencil sc = make_stencil(s.x, e.n, e.fn);
@@ -500,10 +552,17 @@ __global__ void __launch_bounds__(256) k_grid_clear_flagged(int64_t ntiles, floa
 __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st, float* __restrict__ out, int64_t N,
                                                     const EnvDev* __restrict__ envs,
                                                     const WorkItem* __restrict__ items,
-                                                    const float* __restrict__ grid, int32_t* __restrict__ errs) {
+                                                    const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call) {
   const WorkItem it = items[blockIdx.x];
   if ((int)threadIdx.x >= it.count) return;
   const EnvDev& e = envs[it.env];
+  if (k_call >= e.nsub) {   // frozen env: the substep is the identity
+    if ((int)threadIdx.x < it.count) {
+      const int64_t q = it.start + threadIdx.x;
+      for (int c = 0; c < 24; ++c) out[c * N + q] = st[c * N + q];
+    }
+    return;
+  }
   const int64_t p = it.start + threadIdx.x;
   float x[3];
   load_x(st, N, p, x);
@@ -573,10 +632,11 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restr
                                                             const EnvDev* __restrict__ envs,
                                                             const WorkItem* __restrict__ items,
                                                             const float* __restrict__ grid, float* __restrict__ gcot,
-                                                            double* __restrict__ pacc) {
+                                                            double* __restrict__ pacc, int k_call) {
   const WorkItem it = items[blockIdx.x];
   const bool valid = (int)threadIdx.x < it.count;
   const EnvDev& e = envs[it.env];
+  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
     const int64_t p = it.start + threadIdx.x;
@@ -652,10 +712,17 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
                                                             const EnvDev* __restrict__ envs,
                                                             const WorkItem* __restrict__ items,
                                                             const float* __restrict__ gcot,
-                                                            double* __restrict__ pacc) {
+                                                            double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in) {
   const WorkItem it = items[blockIdx.x];
   const bool valid = (int)threadIdx.x < it.count;
   const EnvDev& e = envs[it.env];
+  if (k_call >= e.nsub) {   // frozen env: the cotangent passes through
+    if ((int)threadIdx.x < it.count) {
+      const int64_t q = it.start + threadIdx.x;
+      for (int c = 0; c < 24; ++c) cot_out[c * N + q] = cot_in[c * N + q];
+    }
+    return;
+  }
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
     const int64_t p = it.start + threadIdx.x;
@@ -721,20 +788,20 @@ void launch_prep_params(EnvDev* envs, int n_envs, hipStream_t s) {
 void launch_finalize_params(const EnvDev* envs, const double* acc, double* out, int n_envs, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_params, dim3(nblk(n_envs, 64)), dim3(64), 0, s, envs, acc, out, n_envs);
 }
-void launch_load_aos(const float* x, const float* v, const float* C, const float* F, int64_t n, float* st, int64_t N,
-                     int64_t off, int32_t* ids, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_load_aos, dim3(nblk(n, 256)), dim3(256), 0, s, x, v, C, F, n, st, N, off, ids);
+void launch_load_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* x, const float* v,
+                     const float* C, const float* F, float* st, int64_t N, int32_t* ids, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_load_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, all, x, v, C, F, st, N, ids);
 }
-void launch_store_aos(const float* st, int64_t N, const int32_t* ids, int64_t lo, int64_t hi, float* x, float* v,
-                      float* C, float* F, hipStream_t s) {
-  if (N == 0) return;
-  hipLaunchKernelGGL(k_store_aos, dim3(nblk(N, 256)), dim3(256), 0, s, st, N, ids, lo, hi, x, v, C, F);
+void launch_store_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* st, int64_t N,
+                      const int32_t* ids, float* x, float* v, float* C, float* F, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_store_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, all, st, N, ids, x, v, C, F);
 }
-void launch_gather_aos(const float* x, const float* v, const float* C, const float* F, const int32_t* ids, float* st,
-                       int64_t N, hipStream_t s) {
-  if (N == 0) return;
-  hipLaunchKernelGGL(k_gather_aos, dim3(nblk(N, 256)), dim3(256), 0, s, x, v, C, F, ids, st, N);
+void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
+                       const float* C, const float* F, const int32_t* ids, float* st, int64_t N, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_gather_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, x, v, C, F, ids, st, N);
 }
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s) {
   if (n == 0) return;
@@ -748,6 +815,9 @@ void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
 }
 void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clock, value);
+}
+void launch_add_clock(int32_t* clock, int32_t delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_clock, dim3(1), dim3(64), 0, s, clock, delta);
 }
 void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
                  uint32_t* vals, int cell_bits, hipStream_t s) {
@@ -765,10 +835,11 @@ int launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, ui
     uint32_t* vin = cur ? v1 : v0;
     uint32_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
+    uint32_t* totals = counts + (int64_t)256 * nblocks;
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, N, shift, counts, nblocks);
-    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, counts, (int64_t)256 * nblocks);
+    hipLaunchKernelGGL(k_scan_digit, dim3(256), dim3(256), 0, s, counts, totals, nblocks);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, N, shift, counts,
-                       nblocks);
+                       totals, nblocks);
     cur ^= 1;
   }
   return cur;
@@ -783,9 +854,9 @@ void launch_unpermute(const float* src, float* dst, int64_t N, const uint32_t* p
   hipLaunchKernelGGL(k_unpermute, dim3(nblk(N, 256)), dim3(256), 0, s, src, dst, N, perm);
 }
 void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                       uint32_t* flags, int32_t* errs, hipStream_t s) {
+                       uint32_t* flags, int32_t* errs, int k_call, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_direct, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs);
+  hipLaunchKernelGGL(k_p2g_direct, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call);
 }
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                         uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, hipStream_t s) {
@@ -804,22 +875,22 @@ void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hip
   hipLaunchKernelGGL(k_grid_clear_flagged, dim3(nblk(ntiles, 4)), dim3(256), 0, s, ntiles, grid, flags);
 }
 void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                       const float* grid, int32_t* errs, hipStream_t s) {
+                       const float* grid, int32_t* errs, int k_call, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_direct, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs);
+  hipLaunchKernelGGL(k_g2p_direct, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call);
 }
 void launch_g2p_adjoint_direct(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                                const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                               hipStream_t s) {
+                               int k_call, hipStream_t s) {
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_g2p_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
-                     pacc);
+                     pacc, k_call);
 }
 void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                               const WorkItem* items, int n_items, const float* gcot, double* pacc, hipStream_t s) {
+                               const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s) {
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_p2g_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
-                     pacc);
+                     pacc, k_call, cot_in);
 }
 
 }  // namespace mpmx

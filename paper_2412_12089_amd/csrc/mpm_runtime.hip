@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -47,7 +49,9 @@ struct mpm_batch {
 
   // layout
   std::vector<EnvDev> envs_h;
-  int64_t N = 0, n_tiles = 0;
+  int64_t N = 0, n_tiles = 0;   // particle positions (sum of capacities), tiles
+  int64_t rows = 0;             // live particles = rows of the caller's concatenated arrays
+  std::vector<int> cap_n;       // grid capacity per env (nodes per axis)
   int cell_bits = 0, key_bits = 0;
   std::vector<WorkItem> items_h;
   std::vector<int> item_off;  // [E+1]
@@ -86,7 +90,16 @@ struct mpm_batch {
 
   // kernel variants of the batched mode (0: one thread per particle with
   // global atomics, 1: LDS-staged), chosen by mpm_autotune
-  int var_p2g = 1, var_g2p = 1, var_g2p_adj = 1, var_p2g_adj = 1;
+  // P2G / G2P adjoint: 2 = LDS-staged with segment reduction for blocks whose
+  // particles average at least min_run per stencil base
+  int var_p2g = 2, var_g2p = 1, var_g2p_adj = 2, var_p2g_adj = 1;
+  int min_run = 3;
+
+  // hipGraph replay of whole segments (batched mode): captured on a private
+  // stream, replayed on the caller's stream, keyed by what the launches depend on
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;
+  std::map<std::tuple<int, int, int, int, int, const void*>, hipGraphExec_t> graphs;
 
   // timing
   bool timing = false;
@@ -138,6 +151,10 @@ void free_all(mpm_batch* b) {
   b->bytes = 0;
   for (auto e : b->event_pool) (void)hipEventDestroy(e);
   b->event_pool.clear();
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->cap = nullptr;
 }
 
 int ceil_log2(uint64_t v) {
@@ -178,7 +195,7 @@ struct Span {
 };
 
 // ---------------------------------------------------------------- one substep
-void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel) {
+void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel, int kc) {
   float* g = b->grid[gi];
   uint32_t* fl = b->flags[gi];
   const hipStream_t s = b->stream;
@@ -187,27 +204,28 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
       const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
-      { Span sp(b, KC_P2G); launch_p2g_direct(in, b->N, b->envs_d, b->items_d + i0, ni, g, fl, b->errs, s); }
+      { Span sp(b, KC_P2G); launch_p2g_direct(in, b->N, b->envs_d, b->items_d + i0, ni, g, fl, b->errs, kc, s); }
       { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, s); }
-      { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, s); }
+      { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, kc, s); }
     }
   } else {
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_P2G);
-      if (b->var_p2g) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, s);
-      else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, s);
+      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run, kc, s);
+      else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
+      else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
     }
     { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, s); }
     {
       Span sp(b, KC_G2P);
-      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, s);
-      else launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, s);
+      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
+      else launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
     }
   }
 }
 
-void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int gi, int k_rel) {
+void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int gi, int k_rel, int kc) {
   float* g = b->grid[gi];
   uint32_t* fl = b->flags[gi];
   const hipStream_t s = b->stream;
@@ -216,22 +234,23 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* 
       const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
-      { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, s); }
+      { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, kc, s); }
       { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
-      { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, s); }
+      { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, kc, cot_in, s); }
     }
   } else {
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_G2P_ADJ);
-      if (b->var_g2p_adj) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, s);
-      else launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, s);
+      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run, kc, s);
+      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+      else launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
     }
     { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
     {
       Span sp(b, KC_P2G_ADJ);
-      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, s);
-      else launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, s);
+      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
+      else launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
     }
   }
 }
@@ -249,7 +268,7 @@ void sort_into(mpm_batch* b, const float* src, float* dst, uint32_t* perm_out) {
     pv = perm_out;
   }
   launch_permute_state(src, dst, b->N, pv, b->ids_cur, b->ids_tmp, s);
-  std::swap(b->ids_cur, b->ids_tmp);
+  launch_copy_i32(b->ids_tmp, b->ids_cur, b->N, s);
 }
 
 void clear_dirty_tapes(mpm_batch* b) {
@@ -262,11 +281,100 @@ void clear_dirty_tapes(mpm_batch* b) {
 
 float* other_work(mpm_batch* b, const float* in) { return in == b->W[0] ? b->W[1] : b->W[0]; }
 
+bool graphs_on(const mpm_batch* b) { return b->mode == MPM_MODE_BATCHED && b->use_graphs && !b->timing; }
+
+// Forward segment j: sort `src` into the segment's first buffer (its
+// checkpoint when recording), run Kj substeps, advance the device clock.
+// With dry = true nothing is launched; the return value (the buffer that
+// holds the segment's last state) depends only on the arguments.
+const float* fwd_segment(mpm_batch* b, int j, int Kj, bool record, bool tape, const float* src, bool dry) {
+  float* dst0 = record ? b->ckpt[j] : other_work(b, src);
+  if (!dry && b->N > 0) sort_into(b, src, dst0, record ? b->perm[j] : nullptr);
+  const float* in = dst0;
+  for (int k = 0; k < Kj; ++k) {
+    float* out = tape ? b->seg[k + 1] : other_work(b, in);
+    if (!dry && b->N > 0) substep(b, in, out, tape ? k + 1 : 0, tape ? 0 : 1, k, j * b->K + k);
+    in = out;
+  }
+  if (!dry) launch_add_clock(b->clock, Kj, b->stream);
+  return in;
+}
+
+// Backward segment j: recompute it into the tape (unless taped), run the
+// adjoint substeps in reverse from cot[c], undo the segment's sort.
+// Returns the index of the cotangent buffer that holds the result.
+int bwd_segment(mpm_batch* b, int j, int Kj, bool have_tape, int c) {
+  if (!have_tape) {
+    const float* in = b->ckpt[j];
+    for (int k = 0; k < Kj; ++k) {
+      substep(b, in, b->seg[k + 1], k + 1, 0, k, j * b->K + k);
+      in = b->seg[k + 1];
+    }
+  }
+  for (int k = Kj - 1; k >= 0; --k) {
+    const float* st = k == 0 ? b->ckpt[j] : b->seg[k];
+    adjoint_substep(b, st, b->cot[c], b->cot[c ^ 1], k + 1, k, j * b->K + k);
+    c ^= 1;
+  }
+  launch_unpermute(b->cot[c], b->cot[c ^ 1], b->N, b->perm[j], b->stream);
+  return c ^ 1;
+}
+
+// runs `issue` directly, or as a cached graph replayed on the caller's stream
+template <class Fn>
+int run_maybe_graph(mpm_batch* b, std::tuple<int, int, int, int, int, const void*> key, Fn&& issue) {
+  if (!graphs_on(b)) {
+    issue();
+    return MPM_OK;
+  }
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    if (!b->cap) HIPC(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    const hipStream_t user = b->stream;
+    b->stream = b->cap;
+    hipError_t e0 = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e0 != hipSuccess) { b->stream = user; return fail(b, MPM_DEVICE_ERROR, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e0)); }
+    issue();
+    hipGraph_t g = nullptr;
+    hipError_t e1 = hipStreamEndCapture(b->cap, &g);
+    b->stream = user;
+    if (e1 != hipSuccess) return fail(b, MPM_DEVICE_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(e1));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(b, MPM_DEVICE_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    it = b->graphs.emplace(key, ex).first;
+  }
+  HIPC(b, hipGraphLaunch(it->second, b->stream));
+  return MPM_OK;
+}
+
+void drop_graphs(mpm_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
 int upload_envs(mpm_batch* b) {
   HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
   launch_prep_params(b->envs_d, b->E, b->stream);
   HIPC(b, hipGetLastError());
   return MPM_OK;
+}
+
+// recomputes item counts, compact row offsets and the live total from envs_h
+void refresh_layout(mpm_batch* b) {
+  int64_t row = 0;
+  for (int e = 0; e < b->E; ++e) {
+    EnvDev& h = b->envs_h[e];
+    h.row_off = row;
+    row += h.p_cnt;
+    for (int i = b->item_off[e]; i < b->item_off[e + 1]; ++i) {
+      WorkItem& it = b->items_h[i];
+      const int64_t s0 = it.start - h.p_off;
+      it.count = (int32_t)std::max<int64_t>(0, std::min<int64_t>(it.cap, h.p_cnt - s0));
+    }
+  }
+  b->rows = row;
 }
 
 int check_env(mpm_batch* b, int32_t env, bool allow_all) {
@@ -334,7 +442,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     EnvDev h;
     std::memset(&h, 0, sizeof(h));
     h.n = v.n; h.T = v.n / 4; h.material = v.material; h.wall = v.wall;
-    h.p_off = p_off; h.p_cnt = v.n_particles; h.tile_off = t_off;
+    h.p_off = p_off; h.p_cnt = v.n_particles; h.p_cap = v.n_particles; h.tile_off = t_off;
+    h.row_off = p_off; h.nsub = 0;
     h.dt = v.dt; h.fn = (float)v.n; h.dx = 1.f / (float)v.n;
     h.gx = v.gravity[0]; h.gy = v.gravity[1]; h.gz = v.gravity[2];
     h.rho = 1.0; h.nu = 0.0;  // inert until mpm_set_material
@@ -345,6 +454,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
       it.env = e;
       it.start = p_off + s0;
       it.count = (int32_t)std::min<int64_t>(kItemSize, v.n_particles - s0);
+      it.cap = it.count;
+      it.pad = 0;
       b->items_h.push_back(it);
     }
     const int64_t nt = (int64_t)h.T * h.T * h.T;
@@ -353,6 +464,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     t_off += nt;
   }
   b->item_off[b->E] = (int)b->items_h.size();
+  b->rows = N;
+  for (int e = 0; e < b->E; ++e) b->cap_n.push_back(d->envs[e].n);
   b->env_err_h.assign(b->E, 0);
 
   const size_t state_bytes = sizeof(float) * 24 * (size_t)std::max<int64_t>(N, 1);
@@ -382,7 +495,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->keys1 = (uint32_t*)A(nbytes_i);
   b->vals1 = (uint32_t*)A(nbytes_i);
   const int64_t rs_blocks = (std::max<int64_t>(N, 1) + RS_TILE - 1) / RS_TILE;
-  b->counts = (uint32_t*)A(sizeof(uint32_t) * 256 * rs_blocks);
+  b->counts = (uint32_t*)A(sizeof(uint32_t) * 256 * (rs_blocks + 1));   // per-block digit counts + digit totals
   for (int k = 0; k <= b->K; ++k) {
     b->grid.push_back((float*)A(grid_bytes));
     b->flags.push_back((uint32_t*)A(flag_bytes));
@@ -441,12 +554,13 @@ int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v,
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
-  const int64_t want = env < 0 ? b->N : b->envs_h[env].p_cnt;
+  const int64_t want = env < 0 ? b->rows : b->envs_h[env].p_cnt;
   if (n != want) return fail(b, MPM_INVALID_ARG, "particle count does not match the env description");
   if (n > 0 && (!x || !v || !C || !F)) return fail(b, MPM_INVALID_ARG, "null particle array");
-  const int64_t off = env < 0 ? 0 : b->envs_h[env].p_off;
   clear_dirty_tapes(b);
-  launch_load_aos(x, v, C, F, n, b->cur, b->N, off, b->ids_cur, b->stream);
+  const int i0 = env < 0 ? 0 : b->item_off[env];
+  const int ni = env < 0 ? (int)b->items_h.size() : b->item_off[env + 1] - b->item_off[env];
+  launch_load_aos(b->items_d + i0, ni, b->envs_d, env < 0 ? 1 : 0, x, v, C, F, b->cur, b->N, b->ids_cur, b->stream);
   HIPC(b, hipGetLastError());
   b->steps = 0;
   b->recorded = false;
@@ -458,11 +572,33 @@ int mpm_get_particles(mpm_batch* b, int32_t env, float* x, float* v, float* C, f
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
-  const int64_t lo = env < 0 ? 0 : b->envs_h[env].p_off;
-  const int64_t hi = env < 0 ? b->N : lo + b->envs_h[env].p_cnt;
-  launch_store_aos(b->cur, b->N, b->ids_cur, lo, hi, x, v, C, F, b->stream);
+  const int i0 = env < 0 ? 0 : b->item_off[env];
+  const int ni = env < 0 ? (int)b->items_h.size() : b->item_off[env + 1] - b->item_off[env];
+  launch_store_aos(b->items_d + i0, ni, b->envs_d, env < 0 ? 1 : 0, b->cur, b->N, b->ids_cur, x, v, C, F, b->stream);
   HIPC(b, hipGetLastError());
   return MPM_OK;
+}
+
+int mpm_configure_env(mpm_batch* b, int32_t env, const mpm_env_desc* d) {
+  if (!b || !d) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, false);
+  if (rc) return rc;
+  EnvDev& h = b->envs_h[env];
+  if (d->n < 12 || d->n % 4 != 0 || d->n > b->cap_n[env]) return fail(b, MPM_INVALID_ARG, "grid n above the env's capacity");
+  if (d->n_particles < 0 || d->n_particles > h.p_cap) return fail(b, MPM_INVALID_ARG, "particles above the env's capacity");
+  if (d->material < 0 || d->material > MPM_FLUID_PAPER) return fail(b, MPM_INVALID_ARG, "unknown material");
+  if (!(d->dt > 0.f) || d->wall < 0 || 2 * d->wall + 3 > d->n) return fail(b, MPM_INVALID_ARG, "bad dt or wall");
+  clear_dirty_tapes(b);
+  h.n = d->n; h.T = d->n / 4; h.material = d->material; h.wall = d->wall;
+  h.dt = d->dt; h.fn = (float)d->n; h.dx = 1.f / (float)d->n;
+  h.gx = d->gravity[0]; h.gy = d->gravity[1]; h.gz = d->gravity[2];
+  h.p_cnt = d->n_particles;
+  h.has_collider = 0;
+  refresh_layout(b);
+  HIPC(b, hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice, b->stream));
+  b->recorded = false;
+  b->last_seg_taped = false;
+  return upload_envs(b);
 }
 
 int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p[8]) {
@@ -507,9 +643,23 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const floa
   return upload_envs(b);
 }
 
-int mpm_forward(mpm_batch* b, int32_t S, int32_t flags) {
-  if (!b) return MPM_INVALID_ARG;
-  if (S < 0 || S > b->max_substeps) return fail(b, MPM_BAD_STATE, "n_substeps outside [0, max_substeps]");
+int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
+  if (!b || !n_substeps) return MPM_INVALID_ARG;
+  int32_t S = 0;
+  for (int e = 0; e < b->E; ++e) {
+    if (n_substeps[e] < 0 || n_substeps[e] > b->max_substeps)
+      return fail(b, MPM_BAD_STATE, "n_substeps outside [0, max_substeps]");
+    S = std::max(S, n_substeps[e]);
+  }
+  bool changed = false;
+  for (int e = 0; e < b->E; ++e) {
+    changed |= b->envs_h[e].nsub != n_substeps[e];
+    b->envs_h[e].nsub = n_substeps[e];
+  }
+  if (changed) {
+    const int rc = upload_envs(b);
+    if (rc != MPM_OK) return rc;
+  }
   const bool record = (flags & MPM_FWD_RECORD) != 0;
   const hipStream_t s = b->stream;
   if (b->timing) { b->spans.clear(); b->event_next = 0; }
@@ -518,33 +668,19 @@ int mpm_forward(mpm_batch* b, int32_t S, int32_t flags) {
   b->last_seg_taped = false;
   if (record) launch_copy_i32(b->ids_cur, b->ids_start, b->N, s);
   const int nseg = (S + b->K - 1) / b->K;
-  float* src = b->cur;
+  launch_set_clock(b->clock, (int32_t)b->steps, s);
+  const float* src = b->cur;
   for (int j = 0; j < nseg; ++j) {
     const int Kj = std::min(b->K, S - j * b->K);
-    launch_set_clock(b->clock, (int32_t)(b->steps + (int64_t)j * b->K), s);
-    float* dst0 = record ? b->ckpt[j] : other_work(b, src);
-    if (b->N > 0) sort_into(b, src, dst0, record ? b->perm[j] : nullptr);
     const bool tape = record && j == nseg - 1;
-    const float* in = dst0;
-    for (int k = 0; k < Kj; ++k) {
-      float* out;
-      int gi, clear;
-      if (tape) {
-        out = b->seg[k + 1];
-        gi = k + 1;
-        clear = 0;
-        b->grid_dirty[gi] = true;
-      } else {
-        out = other_work(b, in);
-        gi = 0;
-        clear = 1;
-      }
-      if (b->N > 0) substep(b, in, out, gi, clear, k);
-      in = out;
-    }
-    src = (float*)in;
+    const int rc = run_maybe_graph(b, std::make_tuple(0, j, Kj, (int)record, (int)tape, (const void*)src),
+                                   [&] { fwd_segment(b, j, Kj, record, tape, src, false); });
+    if (rc != MPM_OK) return rc;
+    if (tape)
+      for (int k = 1; k <= Kj; ++k) b->grid_dirty[k] = true;
+    src = fwd_segment(b, j, Kj, record, tape, src, true);
   }
-  b->cur = src;
+  b->cur = (float*)src;
   HIPC(b, hipGetLastError());
   if (record) {
     b->recorded = true;
@@ -554,6 +690,13 @@ int mpm_forward(mpm_batch* b, int32_t S, int32_t flags) {
   }
   b->steps += S;
   return MPM_OK;
+}
+
+int mpm_forward(mpm_batch* b, int32_t S, int32_t flags) {
+  if (!b) return MPM_INVALID_ARG;
+  if (S < 0 || S > b->max_substeps) return fail(b, MPM_BAD_STATE, "n_substeps outside [0, max_substeps]");
+  std::vector<int32_t> n(b->E, S);
+  return mpm_forward_envs(b, n.data(), flags);
 }
 
 int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC, const float* gF, float* dx0,
@@ -566,31 +709,22 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
   const int S = b->rec_S;
   const int nseg = (S + b->K - 1) / b->K;
   int c = 0;
-  launch_gather_aos(gx, gv, gC, gF, b->ids_cur, b->cot[c], b->N, s);
+  launch_gather_aos(b->items_d, (int)b->items_h.size(), b->envs_d, gx, gv, gC, gF, b->ids_cur, b->cot[c], b->N, s);
   for (int j = nseg - 1; j >= 0; --j) {
     const int Kj = std::min(b->K, S - j * b->K);
     launch_set_clock(b->clock, (int32_t)(b->rec_steps0 + (int64_t)j * b->K), s);
     const bool have_tape = (j == nseg - 1) && b->last_seg_taped;
-    if (!have_tape) {
-      clear_dirty_tapes(b);
-      const float* in = b->ckpt[j];
-      for (int k = 0; k < Kj; ++k) {
-        substep(b, in, b->seg[k + 1], k + 1, 0, k);
-        b->grid_dirty[k + 1] = true;
-        in = b->seg[k + 1];
-      }
-    }
-    for (int k = Kj - 1; k >= 0; --k) {
-      const float* st = k == 0 ? b->ckpt[j] : b->seg[k];
-      adjoint_substep(b, st, b->cot[c], b->cot[c ^ 1], k + 1, k);
-      b->grid_dirty[k + 1] = false;
-      c ^= 1;
-    }
-    launch_unpermute(b->cot[c], b->cot[c ^ 1], b->N, b->perm[j], s);
-    c ^= 1;
+    if (!have_tape) clear_dirty_tapes(b);
+    int c_out = c;
+    const int rc = run_maybe_graph(b, std::make_tuple(1, j, Kj, (int)have_tape, c, (const void*)nullptr),
+                                   [&] { c_out = bwd_segment(b, j, Kj, have_tape, c); });
+    if (rc != MPM_OK) return rc;
+    c = (c + Kj + 1) & 1;   // the adjoint substeps and the unpermute each switch buffers
+    (void)c_out;
+    for (int k = 1; k <= Kj; ++k) b->grid_dirty[k] = false;
   }
   b->last_seg_taped = false;
-  launch_store_aos(b->cot[c], b->N, b->ids_start, 0, b->N, dx0, dv0, dC0, dF0, s);
+  launch_store_aos(b->items_d, (int)b->items_h.size(), b->envs_d, 1, b->cot[c], b->N, b->ids_start, dx0, dv0, dC0, dF0, s);
   if (dparams) launch_finalize_params(b->envs_d, b->pacc, dparams, b->E, s);
   HIPC(b, hipGetLastError());
   return MPM_OK;
@@ -649,6 +783,33 @@ int mpm_kernel_time(mpm_batch* b, int32_t kernel, double* mean_ms) {
   }
   *mean_ms = n ? tot / n : 0.0;
   return n;
+}
+
+int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
+  if (!b) return MPM_INVALID_ARG;
+  switch (option) {
+    case MPM_OPT_GRAPHS: b->use_graphs = value != 0; return MPM_OK;
+    case MPM_OPT_P2G: if (value < 0 || value > 2) break; b->var_p2g = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_G2P: if (value < 0 || value > 1) break; b->var_g2p = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_G2P_ADJ: if (value < 0 || value > 2) break; b->var_g2p_adj = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_P2G_ADJ: if (value < 0 || value > 1) break; b->var_p2g_adj = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_MIN_RUN: if (value < 1 || value > 256) break; b->min_run = value; drop_graphs(b); return MPM_OK;
+    default: break;
+  }
+  return fail(b, MPM_INVALID_ARG, "unknown option or value");
+}
+
+int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
+  if (!b || !value) return MPM_INVALID_ARG;
+  switch (option) {
+    case MPM_OPT_GRAPHS: *value = b->use_graphs ? 1 : 0; return MPM_OK;
+    case MPM_OPT_P2G: *value = b->var_p2g; return MPM_OK;
+    case MPM_OPT_G2P: *value = b->var_g2p; return MPM_OK;
+    case MPM_OPT_G2P_ADJ: *value = b->var_g2p_adj; return MPM_OK;
+    case MPM_OPT_P2G_ADJ: *value = b->var_p2g_adj; return MPM_OK;
+    case MPM_OPT_MIN_RUN: *value = b->min_run; return MPM_OK;
+    default: return fail(b, MPM_INVALID_ARG, "unknown option");
+  }
 }
 
 int mpm_autotune(mpm_batch* b, int32_t budget_ms) {

@@ -77,7 +77,7 @@ def test_keys_and_permutation_bit_exact():
         assert np.array_equal(keys[sl] & mask, ok)
         assert np.all((keys[sl] >> cell_bits) == i)
         assert np.array_equal(perm[sl] - sl.start, O.sort_permutation(ok))
-        assert np.array_equal(ids[sl], np.arange(sl.start, sl.stop))
+        assert np.array_equal(ids[sl], np.arange(0, sl.stop - sl.start))   # env-local caller index
 
 
 # ------------------------------------------------------------------ config 1 (single env, neo-Hookean)
@@ -215,3 +215,61 @@ def test_backward_needs_a_recorded_forward():
     assert ei.value.code == 6
     b.sync()
     b.close()
+
+
+# ------------------------------------------------------------------ per-env substep counts and slot reuse
+def test_per_env_substep_counts_match_separate_runs():
+    from paper_2412_12089_amd.batch import Batch
+    a = make_env(scenes.NEOHOOKEAN, N=1200, n=32, seed=90)
+    b_ = make_env(scenes.COROTATED, N=1800, n=32, seed=91, F_dev=0.02)
+    envs = [a, b_]
+    counts = [7, 3]
+    cots = random_cotangents(envs, seed=92)
+    announce("forward_envs with counts [7, 3] vs separate runs")
+    bt = Batch(envs, max_substeps=8, ckpt_every=3)
+    bt.set_particles_from_specs()
+    bt.forward_envs(counts, record=True)
+    st = [t.cpu().double().numpy() for t in bt.get_particles()]
+    cat = lambda i: torch.from_numpy(np.concatenate([c[i] for c in cots], axis=0))
+    dx, dv, dC, dF, dp = bt.backward(cat(0), cat(1), cat(2), cat(3))
+    gr = [t.cpu().double().numpy() for t in (dx, dv, dC, dF)]
+    assert bt.sync(raise_on_error=False) == 0
+    bt.close()
+    for i, (e, sl) in enumerate(zip(envs, env_slices(envs))):
+        alone = gpu_rollout([e], counts[i], 3, cots=[cots[i]])
+        for j in range(4):
+            assert relerr(st[j][sl], alone["state"][j]) < 1e-6, (i, j)
+            assert relerr(gr[j][sl], alone["grads"][j]) < 1e-4, (i, j)
+
+
+def test_slot_reconfiguration_matches_oracle():
+    from paper_2412_12089_amd.batch import Batch
+    cap = [make_env(scenes.NEOHOOKEAN, N=4000, n=48, seed=93), make_env(scenes.NEOHOOKEAN, N=4000, n=48, seed=94)]
+    bt = Batch(cap, max_substeps=6, ckpt_every=3)
+    rounds = [
+        [make_env(scenes.NEOHOOKEAN, N=2500, n=32, seed=95), make_env(scenes.VONMISES, N=3000, n=48, seed=96,
+                                                                      F_dev=(0.01, 0.0003), nu=0.2, sigma_y=5.0)],
+        [make_env(scenes.FLUID_TAIT, N=1000, n=48, seed=97, lo=0.4, side=0.15), None],
+    ]
+    S = 5
+    for r, specs in enumerate(rounds):
+        for i, sp in enumerate(specs):
+            if sp is not None:
+                bt.configure_env(i, sp)
+                bt.set_particles(*(torch.from_numpy(getattr(sp, k)) for k in ("x", "v", "C", "F")), env=i)
+        live = [sp if sp is not None else rounds[r - 1][i] for i, sp in enumerate(specs)]
+        announce(f"slot round {r}: " + ", ".join(f"{scenes.MATERIAL_NAMES[s.material]} n={s.n} N={s.n_particles}" for s in live))
+        bt.forward(S, record=True)
+        st = [t.cpu().double().numpy() for t in bt.get_particles()]
+        cots = random_cotangents(live, seed=98 + r)
+        cat = lambda k: torch.from_numpy(np.concatenate([c[k] for c in cots], axis=0))
+        dx, dv, dC, dF, dp = bt.backward(cat(0), cat(1), cat(2), cat(3))
+        gr = [t.cpu().double().numpy() for t in (dx, dv, dC, dF)]
+        assert bt.sync(raise_on_error=False) == 0
+        for i, (sp, sl) in enumerate(zip(live, env_slices(live))):
+            if r == 1 and i == 1:
+                continue   # slot 1 kept running from its round-0 end state
+            o = oracle_rollout(sp, S, cots[i])
+            check_state([s[sl] for s in st], o["state"], f"slot {i} round {r}")
+            check_grads([g[sl] for g in gr], o["grads"], f"slot {i} round {r}")
+    bt.close()

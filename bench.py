@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-substeps", type=int, default=2)
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson request stream of the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=48)
     return ap.parse_args()
 
 
@@ -93,6 +97,25 @@ def run_steps(batch, x0, w, S, steps, warmup, record=True, backward=True):
     batch.sync()
     ms = [a.elapsed_time(b) for a, b in times]
     return ms
+
+
+def serving_leg(seconds, rate, slots, device):
+    """Continuous batching of a seeded Poisson stream of single-env rollout requests."""
+    import torch
+    from paper_2412_12089_amd import scenes
+    from paper_2412_12089_amd.server import GPUExecutor, Server
+    reqs = scenes.serving_stream(seed=5, rate=rate, duration=seconds)
+    ex = GPUExecutor(slots, n_cap=64, N_cap=100_000, chunk=10, device=device)
+    free = torch.cuda.mem_get_info(device)[0]
+    srv = Server(ex, budget_bytes=int(0.25 * free), chunk=10)
+    srv.run(reqs, realtime=True, timeout_s=max(120.0, 20 * seconds))
+    st = srv.stats()
+    ex.close()
+    fwd = sum(r.env.n_particles * r.substeps for r in reqs)
+    st.update({"rate_per_s": rate, "stream_s": seconds, "slots": slots, "budget_bytes": int(0.25 * free),
+               "backward_fraction": sum(r.backward for r in reqs) / max(1, len(reqs)),
+               "fwd_particle_substeps_demanded_per_s": fwd / seconds})
+    return st
 
 
 def cpu_baseline(wl, substeps):
@@ -166,6 +189,9 @@ def main():
         bp.close()
         plain = N * S / (float(np.mean(pms)) * 1e-3)
 
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serving_leg(args.serve_seconds, args.serve_rate, args.serve_slots, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps)
     out = {
         "metric": "fwd+bwd particle-substeps/s (batched)",
@@ -192,6 +218,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

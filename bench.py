@@ -43,6 +43,35 @@ ALG_BYTES_PER_PARTICLE = {
 ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16}
 
 
+# kernel symbol of each class for the library's default batched variants
+KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg"},
+                 "g2p": {0: "k_g2p_direct", 1: "k_g2p_lds"},
+                 "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg"},
+                 "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"}}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mpm_device.h", "mpm_kernels.h", "mpm_kernels.hip", "mpm_kernels_lds.hip"):
+        with open(os.path.join(ROOT, "paper_2412_12089_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, symbol: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None if
+    there are none or the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != kernel_source_sha() or symbol not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][symbol]["bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-substeps", type=int, default=2)
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
+    ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -155,9 +185,18 @@ def main():
     w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
 
     b = Batch(envs, max_substeps=S, ckpt_every=K, mode="batched", device=dev)
+    if args.no_graphs:
+        from paper_2412_12089_amd import _capi
+        b.set_option(_capi.OPT_GRAPHS, 0)
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
-        print(json.dumps({"profile_ms_per_step": float(np.mean(ms))}), flush=True)
+        # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_ms_per_step": float(np.mean(ms)), "calibration_copy_bytes": 256 << 20}), flush=True)
         return
     step_ms = float(np.mean(ms))
     value = N * S / (step_ms * 1e-3)
@@ -167,12 +206,19 @@ def main():
     b.set_timing(True)
     b.set_particles(*x0)
     b.forward(S, record=True)
-    kt_f = {k: b.kernel_time(k) for k in ("p2g", "grid", "g2p", "sort")}
+    classes = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj")
+    kt_f = {k: b.kernel_time(k) for k in classes}
     b.backward(gx=w)
-    kt_b = {k: b.kernel_time(k) for k in ("g2p_adj", "grid_adj", "p2g_adj")}
-    # the forward inside backward (recompute) is not separately timed; p2g/grid/g2p come from the forward
+    kt_b = {k: b.kernel_time(k) for k in classes}   # includes the recomputed segments
     b.set_timing(False)
-    kt = {**kt_f, **kt_b}
+    kt = {}
+    for k in classes:
+        (mf, nf), (mb, nb) = kt_f[k], kt_b[k]
+        n = nf + nb
+        kt[k] = ((mf * nf + mb * nb) / n if n else 0.0, n)
+    from paper_2412_12089_amd import _capi
+    variant = {"p2g": b.get_option(_capi.OPT_P2G), "g2p": b.get_option(_capi.OPT_G2P),
+               "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ)}
     mem = b.memory_bytes()
     b.close()
     nodes = touched_nodes(envs)
@@ -181,6 +227,8 @@ def main():
     dom_ms = kt[dom][0]
     alg_bytes = ALG_BYTES_PER_PARTICLE[dom] * N + ALG_BYTES_PER_NODE.get(dom, 0) * nodes
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    symbol = KERNEL_SYMBOL.get(dom, {}).get(variant.get(dom), dom)
+    traffic = measured_traffic(wl.name, symbol)
 
     plain = None
     if args.plain_steps > 0:
@@ -215,9 +263,10 @@ def main():
         "p99_ms": float(np.percentile(ms, 99)),
         "hbm_resident_bytes": mem,
         "kernel_ms": {k: v[0] for k, v in kt.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes},
+        "kernel_launches_per_step": {k: v[1] for k, v in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": symbol, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes, "kernel_ms": dom_ms},
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -84,6 +84,7 @@ def parse():
     ap.add_argument("--cpu-substeps", type=int, default=2)
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
     ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
+    ap.add_argument("--tune-ms", type=int, default=4000, help="autotuner budget (0: library defaults)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -185,9 +186,16 @@ def main():
     w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
 
     b = Batch(envs, max_substeps=S, ckpt_every=K, mode="batched", device=dev)
+    from paper_2412_12089_amd import _capi
     if args.no_graphs:
-        from paper_2412_12089_amd import _capi
         b.set_option(_capi.OPT_GRAPHS, 0)
+    tune_s = None
+    if args.tune_ms > 0 and not args.profile:
+        b.set_particles(*x0)
+        t0 = time.perf_counter()
+        b.autotune(args.tune_ms)
+        tune_s = time.perf_counter() - t0
+    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP")}
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
@@ -216,7 +224,6 @@ def main():
         (mf, nf), (mb, nb) = kt_f[k], kt_b[k]
         n = nf + nb
         kt[k] = ((mf * nf + mb * nb) / n if n else 0.0, n)
-    from paper_2412_12089_amd import _capi
     variant = {"p2g": b.get_option(_capi.OPT_P2G), "g2p": b.get_option(_capi.OPT_G2P),
                "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ)}
     mem = b.memory_bytes()
@@ -256,6 +263,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "envs": len(envs), "particles": N, "grid": envs[0].n,
                    "substeps": S, "ckpt_every": K, "material": scenes.MATERIAL_NAMES[envs[0].material]},
+        "autotuned": tuned,
+        "autotune_s": tune_s,
         "per_env_value": plain,
         "batched_over_per_env": (value / plain) if plain else None,
         "fwd_only_value": N * S / (fwd_ms * 1e-3),

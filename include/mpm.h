@@ -179,16 +179,23 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
 #define MPM_OPT_G2P_ADJ 4      /* G2P adjoint: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default) */
 #define MPM_OPT_P2G_ADJ 5      /* P2G adjoint: 0 global gathers, 1 LDS-staged (default) */
 #define MPM_OPT_MIN_RUN 6      /* per-cell-run variants engage when particles per stencil base >= this (default 3) */
+#define MPM_OPT_GRID_CAP 7     /* LDS-staged kernels: 0 = one block per work item (default); > 0 = a persistent
+                                  grid of this many blocks striding over the work items */
 
 /* Sets one option; INVALID_ARG for an unknown option or value. */
 int mpm_set_option(mpm_batch* b, int32_t option, int32_t value);
 /* Reads one option into the host int *value. */
 int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value);
 
-/* Times the batched kernels' launch shapes on the current state (for about
- * budget_ms milliseconds), keeps the fastest whose forward result agrees
- * with the one-thread-per-particle kernels, and restores the state.
- * Synchronizes the stream. */
+/* Autotuner (batched mode). Runs ckpt_every substeps from the current state
+ * with every kernel variant (MPM_OPT_P2G, _G2P, _G2P_ADJ, _P2G_ADJ, _MIN_RUN,
+ * _GRID_CAP), one kernel class at a time. A candidate is kept only if its end
+ * state (x, v: relative error <= 1e-5) and its initial-state cotangent for an
+ * all-ones loss cotangent (<= 1e-4) agree with the one-thread-per-particle
+ * kernels; the fastest kept candidate wins. Stops trying further candidates
+ * after about budget_ms milliseconds. Restores the particle state and clock,
+ * drops any record, synchronizes the stream; the choice is cached per batch
+ * shape for the process. Plain mode: no-op. */
 int mpm_autotune(mpm_batch* b, int32_t budget_ms);
 
 /* Binning of the current state without changing it (the paper is silent on

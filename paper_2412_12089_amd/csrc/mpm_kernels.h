@@ -35,6 +35,8 @@ void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, c
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
 void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s);
+void launch_sq_diff(const float* a, const float* b, int64_t n, double* acc, hipStream_t s);
+void launch_copy_f32(const float* a, float* b, int64_t n, hipStream_t s);
 void launch_add_clock(int32_t* clock, int32_t delta, hipStream_t s);
 void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
                  uint32_t* vals, int cell_bits, hipStream_t s);
@@ -60,21 +62,21 @@ void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_ou
 
 // LDS-staged variants of the particle kernels (batched mode)
 void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int k_call, hipStream_t s);
+                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                    const float* grid, int32_t* errs, int k_call, hipStream_t s);
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
 void launch_g2p_adjoint_lds(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int k_call, hipStream_t s);
+                            int k_call, int grid_cap, hipStream_t s);
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s);
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s);
 
 // segment-reduced scatters: blocks whose particles average at least min_run
 // per stencil base sum each base's run in registers before the LDS atomics
 void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int min_run, int k_call, hipStream_t s);
+                    uint32_t* flags, int32_t* errs, int min_run, int k_call, int grid_cap, hipStream_t s);
 void launch_g2p_adjoint_seg(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int min_run, int k_call, hipStream_t s);
+                            int min_run, int k_call, int grid_cap, hipStream_t s);
 
 }  // namespace mpmx

@@ -177,6 +177,29 @@ __global__ void k_add_clock(int32_t* clock, int32_t delta) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += delta;
 }
 
+// sum over i of (a_i - b_i)^2 and b_i^2 in FP64 (two accumulators), for the
+// autotuner's parity check of a candidate against the reference kernels
+__global__ void k_sq_diff(const float* __restrict__ a, const float* __restrict__ b, int64_t n, double* __restrict__ acc) {
+  double d2 = 0.0, b2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)a[i] - (double)b[i];
+    d2 += d * d;
+    b2 += (double)b[i] * (double)b[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    d2 += __shfl_xor(d2, off, 64);
+    b2 += __shfl_xor(b2, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&acc[0], d2);
+    atomicAdd(&acc[1], b2);
+  }
+}
+
+__global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
 // ----------------------------------------------------------------------------
 // a2: binning keys and a stable LSD radix sort (8-bit digits)
 // ----------------------------------------------------------------------------
@@ -812,6 +835,18 @@ void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
   int64_t b = nblk(n_words, 256);
   if (b > 65536) b = 65536;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(256), 0, s, (uint32_t*)p, v, n_words);
+}
+void launch_sq_diff(const float* a, const float* b, int64_t n, double* acc, hipStream_t s) {
+  if (n == 0) return;
+  int64_t blocks = nblk(n, 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_sq_diff, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, acc);
+}
+void launch_copy_f32(const float* a, float* b, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  int64_t blocks = nblk(n, 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n);
 }
 void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clock, value);

@@ -167,13 +167,13 @@ MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
 // ----------------------------------------------------------------------------
 // P2G
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, int64_t N,
+MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int k_call) {
   __shared__ float lds[4 * kBoxNodes];
   __shared__ int wb[4][6];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int lp = lane_particle(threadIdx.x);
@@ -225,15 +225,26 @@ __global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, i
   box_mark_tiles(e, bx, flags);
 }
 
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, int64_t N,
+                                                 const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                                 float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                 int32_t* __restrict__ errs, int k_call, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    p2g_lds_item(i, st, N, envs, items, grid, flags, errs, k_call);
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------
 // G2P
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_g2p_lds(const float* __restrict__ st, float* __restrict__ out, int64_t N,
+MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restrict__ out, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call) {
   __shared__ float lds[3 * kBoxNodes];
   __shared__ int wb[4][6];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) {   // frozen env: the substep is the identity
     if ((int)threadIdx.x < it.count) {
@@ -292,10 +303,20 @@ __global__ void __launch_bounds__(256) k_g2p_lds(const float* __restrict__ st, f
   if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
 }
 
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_g2p_lds(const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                                                 const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                                 const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    g2p_lds_item(i, st, out, N, envs, items, grid, errs, k_call);
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------
 // G2P adjoint: gather v from an LDS copy, scatter vbar into LDS, flush
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict__ st, const float* __restrict__ cot,
+MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
@@ -304,7 +325,7 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict
   __shared__ float lv[3 * kBoxNodes];
   __shared__ float lg[3 * kBoxNodes];
   __shared__ int wb[4][6];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int lp = lane_particle(threadIdx.x);
@@ -399,10 +420,23 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict__ st, const float* __restrict__ cot,
+                                                         float* __restrict__ part, int64_t N,
+                                                         const EnvDev* __restrict__ envs,
+                                                         const WorkItem* __restrict__ items,
+                                                         const float* __restrict__ grid, float* __restrict__ gcot,
+                                                         double* __restrict__ pacc, int k_call, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    g2p_adjoint_lds_item(i, st, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------
 // P2G adjoint: gather (mbar, Pbar) from an LDS copy
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict__ st,
+MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
                                                          const float* __restrict__ part,
                                                          float* __restrict__ cot_out, int64_t N,
                                                          const EnvDev* __restrict__ envs,
@@ -411,7 +445,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
                                                          double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in) {
   __shared__ float lds[4 * kBoxNodes];
   __shared__ int wb[4][6];
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) {   // frozen env: the cotangent passes through
     if ((int)threadIdx.x < it.count) {
@@ -490,6 +524,20 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
     st_m3(cot_out, N, p, 15, Fb);
   }
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
+}
+
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict__ st,
+                                                         const float* __restrict__ part,
+                                                         float* __restrict__ cot_out, int64_t N,
+                                                         const EnvDev* __restrict__ envs,
+                                                         const WorkItem* __restrict__ items,
+                                                         const float* __restrict__ gcot,
+                                                         double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    p2g_adjoint_lds_item(i, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -584,14 +632,14 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const SegShared& sh, flo
 }
 
 // P2G with segment reduction: thread t <-> particle t of the item
-__global__ void __launch_bounds__(256) k_p2g_seg(const float* __restrict__ st, int64_t N,
+MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int min_run, int k_call) {
   __shared__ float lds[4 * kBoxNodes];
   __shared__ int wb[4][6];
   __shared__ SegShared sh;
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int t = threadIdx.x;
@@ -661,14 +709,25 @@ __global__ void __launch_bounds__(256) k_p2g_seg(const float* __restrict__ st, i
   }
 }
 
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_p2g_seg(const float* __restrict__ st, int64_t N,
+                                                 const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                                 float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                 int32_t* __restrict__ errs, int min_run, int k_call, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    p2g_seg_item(i, st, N, envs, items, grid, flags, errs, min_run, k_call);
+    __syncthreads();
+  }
+}
+
 void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int min_run, int k_call, hipStream_t s) {
+                    uint32_t* flags, int32_t* errs, int min_run, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_seg, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, min_run, k_call);
+  hipLaunchKernelGGL(k_p2g_seg, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, min_run, k_call, n_items);
 }
 
 // G2P adjoint with segment-reduced scatter: thread t <-> particle t
-__global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ cot,
+MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
@@ -678,7 +737,7 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict
   __shared__ float lg[3 * kBoxNodes];
   __shared__ int wb[4][6];
   __shared__ SegShared sh;
-  const WorkItem it = items[blockIdx.x];
+  const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int t = threadIdx.x;
@@ -792,36 +851,49 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
+// one block per work item, or a persistent grid that strides over the items
+__global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ cot,
+                                                         float* __restrict__ part, int64_t N,
+                                                         const EnvDev* __restrict__ envs,
+                                                         const WorkItem* __restrict__ items,
+                                                         const float* __restrict__ grid, float* __restrict__ gcot,
+                                                         double* __restrict__ pacc, int min_run, int k_call, int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    g2p_adjoint_seg_item(i, st, cot, part, N, envs, items, grid, gcot, pacc, min_run, k_call);
+    __syncthreads();
+  }
+}
+
 void launch_g2p_adjoint_seg(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int min_run, int k_call, hipStream_t s) {
+                            int min_run, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_adjoint_seg, dim3(n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
-                     pacc, min_run, k_call);
+  hipLaunchKernelGGL(k_g2p_adjoint_seg, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
+                     pacc, min_run, k_call, n_items);
 }
 
 void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int k_call, hipStream_t s) {
+                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_lds, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call);
+  hipLaunchKernelGGL(k_p2g_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
 }
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                    const float* grid, int32_t* errs, int k_call, hipStream_t s) {
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_lds, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call);
+  hipLaunchKernelGGL(k_g2p_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
 }
 void launch_g2p_adjoint_lds(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int k_call, hipStream_t s) {
+                            int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_adjoint_lds, dim3(n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
-                     pacc, k_call);
+  hipLaunchKernelGGL(k_g2p_adjoint_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
+                     pacc, k_call, n_items);
 }
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s) {
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_adjoint_lds, dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
-                     pacc, k_call, cot_in);
+  hipLaunchKernelGGL(k_p2g_adjoint_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+                     pacc, k_call, cot_in, n_items);
 }
 
 }  // namespace mpmx

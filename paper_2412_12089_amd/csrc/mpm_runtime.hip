@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <tuple>
 #include <cmath>
@@ -94,6 +95,7 @@ struct mpm_batch {
   // particles average at least min_run per stencil base
   int var_p2g = 2, var_g2p = 1, var_g2p_adj = 2, var_p2g_adj = 1;
   int min_run = 3;
+  int grid_cap = 0;   // 0: one block per work item; > 0: persistent grid of this many blocks
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -212,14 +214,14 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_P2G);
-      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run, kc, s);
-      else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
+      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run, kc, b->grid_cap, s);
+      else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, b->grid_cap, s);
       else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
     }
     { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, s); }
     {
       Span sp(b, KC_G2P);
-      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
+      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, b->grid_cap, s);
       else launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
     }
   }
@@ -242,14 +244,14 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* 
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_G2P_ADJ);
-      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run, kc, s);
-      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run, kc, b->grid_cap, s);
+      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, b->grid_cap, s);
       else launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
     }
     { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
     {
       Span sp(b, KC_P2G_ADJ);
-      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
+      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, b->grid_cap, s);
       else launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
     }
   }
@@ -794,6 +796,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_G2P_ADJ: if (value < 0 || value > 2) break; b->var_g2p_adj = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_P2G_ADJ: if (value < 0 || value > 1) break; b->var_p2g_adj = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_MIN_RUN: if (value < 1 || value > 256) break; b->min_run = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_GRID_CAP: if (value < 0) break; b->grid_cap = value; drop_graphs(b); return MPM_OK;
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -808,13 +811,179 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_G2P_ADJ: *value = b->var_g2p_adj; return MPM_OK;
     case MPM_OPT_P2G_ADJ: *value = b->var_p2g_adj; return MPM_OK;
     case MPM_OPT_MIN_RUN: *value = b->min_run; return MPM_OK;
+    case MPM_OPT_GRID_CAP: *value = b->grid_cap; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
 
+namespace {
+
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap; };
+
+// shape signature -> choice, shared by batches of the same shape in the process
+std::map<std::string, TuneChoice>& tune_cache() {
+  static std::map<std::string, TuneChoice> c;
+  return c;
+}
+
+std::string shape_signature(const mpm_batch* b) {
+  std::string sig = std::to_string(b->K) + ":";
+  for (const EnvDev& e : b->envs_h)
+    sig += std::to_string(e.n) + "," + std::to_string(e.material) + "," + std::to_string(e.p_cnt) + ";";
+  return sig;
+}
+
+void apply_choice(mpm_batch* b, const TuneChoice& c) {
+  b->var_p2g = c.p2g; b->var_g2p = c.g2p; b->var_g2p_adj = c.g2p_adj; b->var_p2g_adj = c.p2g_adj;
+  b->min_run = c.min_run;
+  b->grid_cap = c.grid_cap;
+  drop_graphs(b);
+}
+
+}  // namespace
+
 int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
   if (!b) return MPM_INVALID_ARG;
-  (void)budget_ms;
+  if (b->mode != MPM_MODE_BATCHED || b->N == 0 || b->max_substeps == 0) return MPM_OK;
+  const std::string sig = shape_signature(b);
+  auto hit = tune_cache().find(sig);
+  if (hit != tune_cache().end()) { apply_choice(b, hit->second); return MPM_OK; }
+  const hipStream_t s = b->stream;
+  HIPC(b, hipStreamSynchronize(s));
+  const int64_t NS = 24 * b->N;                // floats of one state buffer
+  const int64_t R = std::max<int64_t>(b->rows, 1);
+  float* saved = (float*)dalloc(b, sizeof(float) * NS);
+  float* ref = (float*)dalloc(b, sizeof(float) * NS);
+  float* cot_in = (float*)dalloc(b, sizeof(float) * 24 * R);
+  float* gref = (float*)dalloc(b, sizeof(float) * 24 * R);
+  float* gout = (float*)dalloc(b, sizeof(float) * 24 * R);
+  int32_t* ids_saved = (int32_t*)dalloc(b, sizeof(int32_t) * b->N);
+  double* acc = (double*)dalloc(b, 256);
+  if (!saved || !ref || !cot_in || !gref || !gout || !ids_saved || !acc) return fail(b, MPM_OUT_OF_MEMORY, "autotune scratch");
+  float* cur0 = b->cur;
+  const int64_t steps0 = b->steps;
+  const bool graphs0 = b->use_graphs;
+  b->use_graphs = false;
+  b->recorded = false;
+  launch_copy_f32(cur0, saved, NS, s);
+  launch_copy_i32(b->ids_cur, ids_saved, b->N, s);
+  launch_fill_u32(cot_in, 0x3f800000u, 24 * R, s);   // all-ones cotangent
+  const int St = std::min(b->K, b->max_substeps);
+  std::vector<int32_t> n_all(b->E, St);
+
+  auto restore = [&]() {
+    b->cur = cur0;
+    launch_copy_f32(saved, cur0, NS, s);
+    launch_copy_i32(ids_saved, b->ids_cur, b->N, s);
+    b->steps = steps0;
+    b->recorded = false;
+  };
+  float* g = gout;
+  auto run_fwd = [&](float* dst) -> int {
+    restore();
+    int rc = mpm_forward_envs(b, n_all.data(), 0);
+    if (rc) return rc;
+    launch_copy_f32(b->cur, dst, NS, s);
+    return MPM_OK;
+  };
+  auto run_bwd = [&](float* dst) -> int {
+    restore();
+    int rc = mpm_forward_envs(b, n_all.data(), MPM_FWD_RECORD);
+    if (rc) return rc;
+    return mpm_backward(b, cot_in, cot_in + 3 * R, cot_in + 6 * R, cot_in + 15 * R, dst, dst + 3 * R, dst + 6 * R,
+                        dst + 15 * R, nullptr);
+  };
+  auto rel_err = [&](const float* a, const float* bb, int64_t n, double& out) -> int {
+    launch_fill_u32(acc, 0u, 4, s);
+    launch_sq_diff(a, bb, n, acc, s);
+    double h[2];
+    HIPC(b, hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPC(b, hipStreamSynchronize(s));
+    out = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    return MPM_OK;
+  };
+  hipEvent_t e0, e1;
+  HIPC(b, hipEventCreate(&e0));
+  HIPC(b, hipEventCreate(&e1));
+  const auto t_start = std::chrono::steady_clock::now();
+  auto over_budget = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
+  };
+  // reference results: one thread per particle, global atomics
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0};
+  apply_choice(b, best);
+  int rc = run_fwd(ref);
+  if (!rc) rc = run_bwd(gref);
+  if (!rc) HIPC(b, hipStreamSynchronize(s));
+  auto time_it = [&](bool bwd, double& ms) -> int {
+    int r = bwd ? run_bwd(g) : run_fwd(g);     // warm-up (and first-use costs)
+    if (r) return r;
+    HIPC(b, hipEventRecord(e0, s));
+    r = bwd ? run_bwd(g) : run_fwd(g);
+    if (r) return r;
+    HIPC(b, hipEventRecord(e1, s));
+    HIPC(b, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPC(b, hipEventElapsedTime(&f, e0, e1));
+    ms = f;
+    return MPM_OK;
+  };
+  // one candidate: a field of TuneChoice, its value, optional min_run, timed with the backward
+  struct Cand { int* slot; int value; int min_run; bool bwd; };
+  std::vector<std::vector<Cand>> groups = {
+      {{&best.p2g, 0, 0, false}, {&best.p2g, 1, 0, false}, {&best.p2g, 2, 2, false}, {&best.p2g, 2, 3, false},
+       {&best.p2g, 2, 4, false}, {&best.p2g, 2, 8, false}},
+      {{&best.g2p, 0, 0, false}, {&best.g2p, 1, 0, false}},
+      {{&best.g2p_adj, 0, 0, true}, {&best.g2p_adj, 1, 0, true}, {&best.g2p_adj, 2, 0, true}},
+      {{&best.p2g_adj, 0, 0, true}, {&best.p2g_adj, 1, 0, true}},
+      {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
+       {&best.grid_cap, 2048, 0, true}},
+  };
+  for (auto& grp : groups) {
+    if (rc) break;
+    double best_ms = 1e30;
+    TuneChoice keep = best;
+    for (auto& c : grp) {
+      if (rc) break;
+      if (over_budget() && best_ms < 1e30) break;
+      TuneChoice trial = keep;
+      *(&trial.p2g + (c.slot - &best.p2g)) = c.value;
+      if (c.min_run > 0) trial.min_run = c.min_run;
+      apply_choice(b, trial);
+      double ms = 0.0, err = 0.0;
+      rc = time_it(c.bwd, ms);
+      if (rc) break;
+      if (c.bwd) {
+        rc = rel_err(g, gref, 6 * R, err);   // x and v cotangents of the initial state
+      } else {
+        rc = rel_err(g, ref, 6 * b->N, err);   // x and v of the end state
+      }
+      if (rc) break;
+      if (err <= (c.bwd ? 1e-4 : 1e-5) && ms < best_ms) {
+        best_ms = ms;
+        best = trial;
+      }
+    }
+    if (best_ms >= 1e30) best = keep;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  restore();
+  apply_choice(b, best);
+  b->use_graphs = graphs0;
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = MPM_DEVICE_ERROR;
+  // scratch goes back to the allocator
+  for (void* p : {(void*)saved, (void*)ref, (void*)cot_in, (void*)gref, (void*)gout, (void*)ids_saved, (void*)acc}) {
+    for (size_t i = 0; i < b->allocations.size(); ++i)
+      if (b->allocations[i].first == p) {
+        if (b->has_alloc) b->alloc.free(p, b->alloc.ctx); else (void)hipFree(p);
+        b->bytes -= (int64_t)b->allocations[i].second;
+        b->allocations.erase(b->allocations.begin() + i);
+        break;
+      }
+  }
+  if (rc) return rc;
+  tune_cache()[sig] = best;
   return MPM_OK;
 }
 

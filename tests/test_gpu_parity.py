@@ -273,3 +273,64 @@ def test_slot_reconfiguration_matches_oracle():
             check_state([s[sl] for s in st], o["state"], f"slot {i} round {r}")
             check_grads([g[sl] for g in gr], o["grads"], f"slot {i} round {r}")
     bt.close()
+
+
+# ------------------------------------------------------------------ kernel variants and the autotuner
+VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap)
+    (0, 0, 0, 0, 0), (1, 1, 1, 1, 0), (2, 1, 2, 1, 0), (2, 1, 2, 1, 7), (1, 0, 2, 0, 3),
+]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=["-".join(map(str, v)) for v in VARIANTS])
+def test_every_kernel_variant_matches_oracle(var):
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd.batch import Batch
+    envs = [make_env(scenes.VONMISES, N=2200, seed=110, F_dev=(0.01, 0.0003), nu=0.2, sigma_y=5.0),
+            make_env(scenes.COROTATED, N=1700, n=48, seed=111, F_dev=0.02)]
+    S, K = 6, 4
+    cots = random_cotangents(envs, seed=112)
+    announce(f"variant {var}")
+    b = Batch(envs, max_substeps=S, ckpt_every=K)
+    for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP), var):
+        b.set_option(opt, val)
+    b.set_particles_from_specs()
+    b.forward(S, record=True)
+    st = [t.cpu().double().numpy() for t in b.get_particles()]
+    cat = lambda k: torch.from_numpy(np.concatenate([c[k] for c in cots], axis=0))
+    dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+    gr = [t.cpu().double().numpy() for t in (dx, dv, dC, dF)]
+    assert b.sync(raise_on_error=False) == 0
+    b.close()
+    for i, (e, sl) in enumerate(zip(envs, env_slices(envs))):
+        o = oracle_rollout(e, S, cots[i])
+        check_state([a[sl] for a in st], o["state"], f"variant {var} env {i}")
+        check_grads([g[sl] for g in gr], o["grads"], f"variant {var} env {i}")
+
+
+def test_autotune_restores_state_and_keeps_parity():
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd.batch import Batch
+    envs = [make_env(scenes.COROTATED, N=3000, n=48, seed=120 + i, F_dev=0.02) for i in range(3)]
+    b = Batch(envs, max_substeps=8, ckpt_every=4)
+    b.set_particles_from_specs()
+    before = [t.cpu().numpy() for t in b.get_particles()]
+    announce("autotune on 3 corotated envs")
+    b.autotune(3000)
+    after = [t.cpu().numpy() for t in b.get_particles()]
+    for a, c in zip(before, after):
+        assert np.array_equal(a, c)
+    opts = {k: b.get_option(getattr(C, k)) for k in ("OPT_P2G", "OPT_G2P", "OPT_G2P_ADJ", "OPT_P2G_ADJ", "OPT_GRID_CAP")}
+    announce(f"autotune chose {opts}")
+    assert opts["OPT_P2G"] in (0, 1, 2) and opts["OPT_GRID_CAP"] >= 0
+    cots = random_cotangents(envs, seed=121)
+    b.forward(8, record=True)
+    st = [t.cpu().double().numpy() for t in b.get_particles()]
+    cat = lambda k: torch.from_numpy(np.concatenate([c[k] for c in cots], axis=0))
+    dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+    gr = [t.cpu().double().numpy() for t in (dx, dv, dC, dF)]
+    assert b.sync(raise_on_error=False) == 0
+    b.close()
+    sl = env_slices(envs)[1]
+    o = oracle_rollout(envs[1], 8, cots[1])
+    check_state([a[sl] for a in st], o["state"], "after autotune")
+    check_grads([g[sl] for g in gr], o["grads"], "after autotune")

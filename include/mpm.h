@@ -181,6 +181,8 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
 #define MPM_OPT_MIN_RUN 6      /* per-cell-run variants engage when particles per stencil base >= this (default 3) */
 #define MPM_OPT_GRID_CAP 7     /* LDS-staged kernels: 0 = one block per work item (default); > 0 = a persistent
                                   grid of this many blocks striding over the work items */
+#define MPM_OPT_MAX_RUN 8      /* per-cell-run variants cut a run of one stencil base every this many particles
+                                  (default 8) */
 
 /* Sets one option; INVALID_ARG for an unknown option or value. */
 int mpm_set_option(mpm_batch* b, int32_t option, int32_t value);
@@ -189,7 +191,7 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value);
 
 /* Autotuner (batched mode). Runs ckpt_every substeps from the current state
  * with every kernel variant (MPM_OPT_P2G, _G2P, _G2P_ADJ, _P2G_ADJ, _MIN_RUN,
- * _GRID_CAP), one kernel class at a time. A candidate is kept only if its end
+ * _GRID_CAP, _MAX_RUN), one kernel class at a time. A candidate is kept only if its end
  * state (x, v: relative error <= 1e-5) and its initial-state cotangent for an
  * all-ones loss cotangent (<= 1e-4) agree with the one-thread-per-particle
  * kernels; the fastest kept candidate wins. Stops trying further candidates
@@ -203,7 +205,8 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms);
  * cell). Writes, as DEVICE arrays over the current internal particle order:
  * keys[i] = (env << cell_bits) | (tile * 64 + cell) with base clamped to
  * [0, n-3], tile = ((bx/4) T + by/4) T + bz/4, T = n/4, cell =
- * ((bx%4) 4 + by%4) 4 + bz%4 (uint32 [N]); perm, the stable sort order (new
+ * ((bx%4) 4 + by%4) 4 + bz%4, cell_bits = ceil(log2(max n^3)) (uint32 [N]);
+ * perm, the stable sort order (new
  * position j takes internal position perm[j], uint32 [N]); ids, the
  * env-local caller index of each internal position, -1 where a slot's
  * capacity holds no particle (int32 [N]). N counts capacity positions.

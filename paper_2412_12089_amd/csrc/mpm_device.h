@@ -222,42 +222,52 @@ constexpr int CH = 64;  // channel stride inside a tile
 // --------------------------------------------------------------------------
 // a3: Kirchhoff stress tau = P F^T
 // --------------------------------------------------------------------------
-MD M3 stress(const EnvDev& e, const M3& F) {
-  const float J = m3_det(F);
+// Quantities of F shared by the stress and its VJP (one eigen-decomposition
+// of b = F F^T serves both in the P2G adjoint).
+struct StressPrep {
+  M3 b, U;
+  float s[3];
+  float J;
+};
+
+MD StressPrep stress_prep(const EnvDev& e, const M3& F) {
+  StressPrep p;
+  p.J = m3_det(F);
+  if (e.material == MAT_NEOHOOKEAN || e.material == MAT_COROTATED || e.material == MAT_VONMISES)
+    p.b = m3_mul_abt(F, F);
+  if (e.material == MAT_COROTATED || e.material == MAT_VONMISES) eig_sym(p.b, p.s, p.U);
+  return p;
+}
+
+MD M3 stress_from(const EnvDev& e, const StressPrep& p) {
+  const float J = p.J;
   switch (e.material) {
     case MAT_NEOHOOKEAN: {
-      const M3 b = m3_mul_abt(F, F);
-      const float Ic = m3_trace(b);
+      const float Ic = m3_trace(p.b);
       const float c1 = e.mu * (1.f - 1.f / (Ic + 1.f));
       const float c2 = e.lam * J * (J - e.alpha_nh);
-      M3 t = m3_scale(b, c1);
+      M3 t = m3_scale(p.b, c1);
       t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
       return t;
     }
     case MAT_COROTATED: {
       // 2 mu (F - R) F^T = 2 mu (b - b^(1/2))
-      const M3 b = m3_mul_abt(F, F);
-      float s[3]; M3 U;
-      eig_sym(b, s, U);
       float sg[3];
-      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(s[i], 0.f));
-      const M3 bh = m3_spectral(U, sg);
-      M3 t = m3_scale(m3_axpy(b, -1.f, bh), 2.f * e.mu);
+      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(p.s[i], 0.f));
+      const M3 bh = m3_spectral(p.U, sg);
+      M3 t = m3_scale(m3_axpy(p.b, -1.f, bh), 2.f * e.mu);
       const float c2 = e.lam * J * (J - 1.f);
       t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
       return t;
     }
     case MAT_VONMISES: {
       // U (2 mu eps + lam tr(eps) I) U^T, eps = log Sigma = (1/2) log s
-      const M3 b = m3_mul_abt(F, F);
-      float s[3]; M3 U;
-      eig_sym(b, s, U);
       float eps[3];
-      for (int i = 0; i < 3; ++i) eps[i] = 0.5f * logf(fmaxf(s[i], kSigmaMin * kSigmaMin));
+      for (int i = 0; i < 3; ++i) eps[i] = 0.5f * logf(fmaxf(p.s[i], kSigmaMin * kSigmaMin));
       const float tre = eps[0] + eps[1] + eps[2];
       float d[3];
       for (int i = 0; i < 3; ++i) d[i] = 2.f * e.mu * eps[i] + e.lam * tre;
-      return m3_spectral(U, d);
+      return m3_spectral(p.U, d);
     }
     case MAT_FLUID_TAIT: {
       const float c = e.bulk * (J - powf(J, 1.f - e.gam));  // -J K (J^-gamma - 1)
@@ -272,13 +282,17 @@ MD M3 stress(const EnvDev& e, const M3& F) {
   }
 }
 
+// a3: Kirchhoff stress tau = P F^T
+MD M3 stress(const EnvDev& e, const M3& F) { return stress_from(e, stress_prep(e, F)); }
+
 // VJP of stress(): Fbar += d<taubar, tau>/dF, pb[] += d<taubar, tau>/d(params)
-MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
-  const float J = m3_det(F);
+MD void stress_vjp_from(const EnvDev& e, const M3& F, const StressPrep& p, const M3& tb, M3& Fbar,
+                        float pb[PB_COUNT]) {
+  const float J = p.J;
   const float trtb = m3_trace(tb);
   switch (e.material) {
     case MAT_NEOHOOKEAN: {
-      const M3 b = m3_mul_abt(F, F);
+      const M3& b = p.b;
       const float Ic = m3_trace(b);
       const float inv = 1.f / (Ic + 1.f);
       const float c1 = e.mu * (1.f - inv);
@@ -295,37 +309,31 @@ MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float p
       return;
     }
     case MAT_COROTATED: {
-      const M3 b = m3_mul_abt(F, F);
-      float s[3]; M3 U;
-      eig_sym(b, s, U);
       float sg[3];
-      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(s[i], 0.f));
-      const M3 G = m3_rotate_in(U, m3_sym(tb));
+      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(p.s[i], 0.f));
+      const M3 G = m3_rotate_in(p.U, m3_sym(tb));
       // h(s) = s - sqrt(s): divided difference 1 - 1/(sigma_i + sigma_j)
       M3 H;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) H.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - 1.f / (sg[i] + sg[j]));
-      const M3 bbar = m3_rotate_out(U, H);
+      const M3 bbar = m3_rotate_out(p.U, H);
       Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
       Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));
       float hm = 0.f;
-      for (int i = 0; i < 3; ++i) hm += G.m[i][i] * (s[i] - sg[i]);
+      for (int i = 0; i < 3; ++i) hm += G.m[i][i] * (p.s[i] - sg[i]);
       pb[PB_MU] += 2.f * hm;
       pb[PB_LAM] += trtb * J * (J - 1.f);
       return;
     }
     case MAT_VONMISES: {
-      const M3 b = m3_mul_abt(F, F);
-      float s[3]; M3 U;
-      eig_sym(b, s, U);
       float sc[3], ls[3];
-      for (int i = 0; i < 3; ++i) { sc[i] = fmaxf(s[i], kSigmaMin * kSigmaMin); ls[i] = logf(sc[i]); }
-      const M3 G = m3_rotate_in(U, m3_sym(tb));
+      for (int i = 0; i < 3; ++i) { sc[i] = fmaxf(p.s[i], kSigmaMin * kSigmaMin); ls[i] = logf(sc[i]); }
+      const M3 G = m3_rotate_in(p.U, m3_sym(tb));
       M3 Bu;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Bu.m[i][j] = e.mu * G.m[i][j] * log_divdiff(sc[i], sc[j]);
       for (int i = 0; i < 3; ++i) Bu.m[i][i] += e.lam * trtb * 0.5f / sc[i];
-      const M3 bbar = m3_rotate_out(U, Bu);
+      const M3 bbar = m3_rotate_out(p.U, Bu);
       Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
       float gl = 0.f;
       for (int i = 0; i < 3; ++i) gl += G.m[i][i] * ls[i];
@@ -347,6 +355,10 @@ MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float p
       return;
     }
   }
+}
+
+MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
+  stress_vjp_from(e, F, stress_prep(e, F), tb, Fbar, pb);
 }
 
 // --------------------------------------------------------------------------

@@ -54,7 +54,7 @@ void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t ti
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s);
 void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                        const float* grid, int32_t* errs, int k_call, hipStream_t s);
-void launch_g2p_adjoint_direct(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+void launch_g2p_adjoint_direct(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                                const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                                int k_call, hipStream_t s);
 void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
@@ -65,18 +65,19 @@ void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkIt
                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                     const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
-void launch_g2p_adjoint_lds(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                             int k_call, int grid_cap, hipStream_t s);
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s);
 
-// segment-reduced scatters: blocks whose particles average at least min_run
-// per stencil base sum each base's run in registers before the LDS atomics
+// segment-reduced scatters: runs = min_run | max_run << 16. Blocks whose
+// particles average at least min_run per run sum each run (cut at max_run
+// particles) in registers before the LDS atomics
 void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int min_run, int k_call, int grid_cap, hipStream_t s);
-void launch_g2p_adjoint_seg(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, hipStream_t s);
+void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int min_run, int k_call, int grid_cap, hipStream_t s);
+                            int runs, int k_call, int grid_cap, hipStream_t s);
 
 }  // namespace mpmx

@@ -31,6 +31,7 @@ MD void store_m3(float* __restrict__ st, int64_t N, int64_t p, int c0, const M3&
 #pragma unroll
     for (int j = 0; j < 3; ++j) st[(c0 + 3 * i + j) * N + p] = m.m[i][j];
 }
+MD M3 load_cnext(const float* __restrict__ st, int64_t N, int64_t p) { return load_m3(st, N, p, 6); }
 MD PState load_state(const float* __restrict__ st, int64_t N, int64_t p) {
   PState s;
   for (int a = 0; a < 3; ++a) { s.x[a] = st[a * N + p]; s.v[a] = st[(3 + a) * N + p]; }
@@ -203,6 +204,7 @@ __global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, i
 // ----------------------------------------------------------------------------
 // a2: binning keys and a stable LSD radix sort (8-bit digits)
 // ----------------------------------------------------------------------------
+
 __global__ void __launch_bounds__(256) k_keys(const float* __restrict__ st, int64_t N, const EnvDev* __restrict__ envs,
                                               const WorkItem* __restrict__ items, uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals, int cell_bits) {
@@ -650,7 +652,8 @@ MD void block_reduce_params(float pb[PB_COUNT], double* __restrict__ acc) {
 
 // G2P adjoint: scatters grid-velocity cotangents (channels 0-2 of gcot) and
 // writes the particle's direct x and F cotangents into `part` (12 comps)
-__global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restrict__ st, const float* __restrict__ cot,
+__global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restrict__ st,
+                                                            const float* __restrict__ st_next, const float* __restrict__ cot,
                                                             float* __restrict__ part, int64_t N,
                                                             const EnvDev* __restrict__ envs,
                                                             const WorkItem* __restrict__ items,
@@ -668,24 +671,8 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restr
     const M3 F = load_m3(st, N, p, 15);
     const Stencil sc = make_stencil(x, e.n, e.fn);
     const float D4 = 4.f * e.fn * e.fn;
-    // pass 1: recompute v', C'
-    M3 Cn = m3_zero();
-    for (int ox = 0; ox < 3; ++ox)
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
-          const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-          const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
-          for (int a = 0; a < 3; ++a) {
-            const float wv = W * vi[a];
-            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
-            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
-            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
-          }
-        }
-    Cn = m3_scale(Cn, D4);
+    // C' of the substep's output state, read from the tape (the forward's own value)
+    const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
     const M3 Ftr = m3_mul(G, F);
     // incoming cotangents of (x', v', C', F')
@@ -751,7 +738,8 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     const int64_t p = it.start + threadIdx.x;
     const PState s = load_state(st, N, p);
     const Stencil sc = make_stencil(s.x, e.n, e.fn);
-    const M3 tau = stress(e, s.F);
+    const StressPrep spr = stress_prep(e, s.F);
+    const M3 tau = stress_from(e, spr);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
     float xb[3] = {part[p], part[N + p], part[2 * N + p]};
@@ -792,7 +780,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = load_m3(part, N, p, 3);
-    stress_vjp(e, s.F, taub, Fb, pb);
+    stress_vjp_from(e, s.F, spr, taub, Fb, pb);
     for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
     store_m3(cot_out, N, p, 6, Cb);
     store_m3(cot_out, N, p, 15, Fb);
@@ -914,11 +902,11 @@ void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* env
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_g2p_direct, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call);
 }
-void launch_g2p_adjoint_direct(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+void launch_g2p_adjoint_direct(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                                const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                                int k_call, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
+  hipLaunchKernelGGL(k_g2p_adjoint_direct, dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
                      pacc, k_call);
 }
 void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,

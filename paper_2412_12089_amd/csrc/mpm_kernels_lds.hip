@@ -1,8 +1,9 @@
 // LDS-staged particle kernels of the batched mode.
 //
 // A block takes one work item: up to 256 particles of one environment that
-// are contiguous in (tile, cell) order, so their 3x3x3 stencils cover a small
-// box of grid nodes. The block finds that box, and
+// are contiguous in (tile, cell) order, so their 3x3x3 stencils cover a few
+// small boxes of grid nodes, one per tile row (tile x, tile y) the item
+// crosses. The block finds those boxes, and
 //  * scatters (P2G, G2P adjoint) accumulate into the box in LDS with LDS
 //    atomics, then flush each touched node once to HBM with global atomics;
 //  * gathers (G2P, P2G adjoint) first copy the box's grid channels into LDS
@@ -10,67 +11,127 @@
 // Thread t works on particle (t % 64) * 4 + t / 64 of the item: the 64 lanes
 // of a wave hold particles four apart in cell order, so lanes that update the
 // same node in the same instruction (same cell) are rare.
-// If the box exceeds the LDS budget the block falls back to global memory.
+// If the boxes exceed the LDS budget, or the item crosses more than four tile
+// rows, the block falls back to global memory.
 #include "mpm_kernels.h"
 
 namespace mpmx {
 
 constexpr int kBoxNodes = 1024;   // LDS budget in nodes per block
+constexpr int kMaxRuns = 4;       // tile-row runs per block that get their own box
 
-struct Box {
-  int lo[3], ext[3];
-  int nodes;
-  bool fits;
+// A block's particles are contiguous in (tile, cell) order, so they fall into a
+// few runs that share a tile row (tile x, tile y); each run's stencils cover a
+// compact box of at most 6 x 6 x (z extent) nodes. The runs' boxes are packed
+// one after another in LDS.
+struct BoxShared {
+  int rk[256];            // tile-row key of particle i (natural order), -1 if none
+  int run[256];           // run index of particle i
+  int wsum[4];
+  int lo[kMaxRuns][3], hi[kMaxRuns][3];
+  int off[kMaxRuns + 1];  // first LDS node of each run's box; off[nruns] = total
+  int ext[kMaxRuns][3];
+  int nruns;
 };
 
 MD int lane_particle(int t) { return ((t & 63) << 2) | (t >> 6); }
 
-// bounding box of the block's stencils: [min base, max base + 2] per axis
-MD Box block_box(const int b[3], bool valid, int (*wb)[6]) {
-  int mn[3], mx[3];
-  for (int a = 0; a < 3; ++a) {
-    mn[a] = valid ? b[a] : 0x3fffffff;
-    mx[a] = valid ? b[a] : -0x3fffffff;
+// what one thread needs for its own particle's run
+struct Box {
+  int lo[3];
+  int ey, ez;
+  int off;
+  int nodes;    // total over all runs
+  bool fits;
+  int run;
+};
+
+// every thread must call it; lp = this thread's particle index in the item
+MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count, BoxShared& bs) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t < 256) bs.rk[lp] = valid ? ((b[0] >> 2) * e.T + (b[1] >> 2)) : -1;
+  if (t < kMaxRuns * 3) {
+    (&bs.lo[0][0])[t] = 0x3fffffff;
+    (&bs.hi[0][0])[t] = -0x3fffffff;
   }
-  for (int off = 32; off > 0; off >>= 1)
+  __syncthreads();
+  // runs of equal tile-row key in natural particle order (thread t looks at particle t)
+  const bool in = t < count;
+  const bool start = in && (t == 0 || bs.rk[t] != bs.rk[t - 1]);
+  const uint64_t bal = __ballot(start);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int before = __popcll(bal & lt) + (start ? 1 : 0);   // starts up to and including t
+  if (lane == 63) bs.wsum[wave] = __popcll(bal);
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += bs.wsum[w];
+  if (in) bs.run[t] = off + before - 1;
+  if (t == 0) {
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += bs.wsum[w];
+    bs.nruns = tot;
+  }
+  __syncthreads();
+  const int nruns = bs.nruns;
+  const int r = valid ? bs.run[lp] : 0;
+  if (valid && r < kMaxRuns)
     for (int a = 0; a < 3; ++a) {
-      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
-      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
+      atomicMin(&bs.lo[r][a], b[a]);
+      atomicMax(&bs.hi[r][a], b[a] + 2);
     }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-    for (int a = 0; a < 3; ++a) { wb[wave][a] = mn[a]; wb[wave][3 + a] = mx[a]; }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
+    for (int k = 0; k < nr; ++k) {
+      bs.off[k] = acc;
+      int n = 1;
+      for (int a = 0; a < 3; ++a) {
+        bs.ext[k][a] = bs.hi[k][a] - bs.lo[k][a] + 1;
+        n *= bs.ext[k][a];
+      }
+      acc += n;
+    }
+    bs.off[nr] = acc;
+  }
   __syncthreads();
   Box bx;
-  const int nw = blockDim.x >> 6;
-  for (int a = 0; a < 3; ++a) {
-    int lo = wb[0][a], hi = wb[0][3 + a];
-    for (int w = 1; w < nw; ++w) { lo = min(lo, wb[w][a]); hi = max(hi, wb[w][3 + a]); }
-    bx.lo[a] = lo;
-    bx.ext[a] = hi - lo + 3;
-  }
-  const bool any = bx.ext[0] > 0;
-  bx.nodes = any ? bx.ext[0] * bx.ext[1] * bx.ext[2] : 0;
-  bx.fits = any && bx.ext[0] <= kBoxNodes && bx.ext[1] <= kBoxNodes && bx.ext[2] <= kBoxNodes &&
-            bx.nodes <= kBoxNodes;
+  const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
+  bx.nodes = bs.off[nr];
+  bx.fits = nruns >= 1 && nruns <= kMaxRuns && bx.nodes <= kBoxNodes;
+  bx.run = r;
+  const int rr = r < kMaxRuns ? r : 0;
+  for (int a = 0; a < 3; ++a) bx.lo[a] = bs.lo[rr][a];
+  bx.ey = bs.ext[rr][1];
+  bx.ez = bs.ext[rr][2];
+  bx.off = bs.off[rr];
   return bx;
 }
 
+// LDS node of (i, j, k) in this thread's run box
 MD int box_index(const Box& bx, int i, int j, int k) {
-  return ((i - bx.lo[0]) * bx.ext[1] + (j - bx.lo[1])) * bx.ext[2] + (k - bx.lo[2]);
+  return bx.off + ((i - bx.lo[0]) * bx.ey + (j - bx.lo[1])) * bx.ez + (k - bx.lo[2]);
 }
-MD void box_node(const Box& bx, int idx, int& i, int& j, int& k) {
-  const int yz = bx.ext[1] * bx.ext[2];
-  i = bx.lo[0] + idx / yz;
-  j = bx.lo[1] + (idx / bx.ext[2]) % bx.ext[1];
-  k = bx.lo[2] + idx % bx.ext[2];
+// LDS node of (i, j, k) in run r's box
+MD int box_index_run(const BoxShared& bs, int r, int i, int j, int k) {
+  return bs.off[r] + ((i - bs.lo[r][0]) * bs.ext[r][1] + (j - bs.lo[r][1])) * bs.ext[r][2] + (k - bs.lo[r][2]);
+}
+MD void box_node(const BoxShared& bs, int idx, int& i, int& j, int& k) {
+  int r = 0;
+  while (r + 1 < kMaxRuns && r + 1 < bs.nruns && bs.off[r + 1] <= idx) ++r;
+  const int loc = idx - bs.off[r];
+  const int yz = bs.ext[r][1] * bs.ext[r][2];
+  i = bs.lo[r][0] + loc / yz;
+  j = bs.lo[r][1] + (loc / bs.ext[r][2]) % bs.ext[r][1];
+  k = bs.lo[r][2] + loc % bs.ext[r][2];
 }
 
-// copies channels [c0, c0+nc) of the box's nodes from a grid buffer into LDS
-MD void box_load(const EnvDev& e, const Box& bx, const float* __restrict__ g, int c0, int nc, float* lds) {
+// copies channels [c0, c0+nc) of every box node from a grid buffer into LDS
+MD void box_load(const EnvDev& e, const Box& bx, const BoxShared& bs, const float* __restrict__ g, int c0, int nc,
+                 float* lds) {
   for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
     int i, j, k;
-    box_node(bx, idx, i, j, k);
+    box_node(bs, idx, i, j, k);
     const float* src = g + node_base(e, i, j, k) + c0 * CH;
     for (int c = 0; c < nc; ++c) lds[c * bx.nodes + idx] = src[c * CH];
   }
@@ -79,12 +140,12 @@ MD void box_load(const EnvDev& e, const Box& bx, const float* __restrict__ g, in
 // adds the box's LDS channels to grid channels [c0, c0+nc); a node whose
 // first channel is zero (no particle weight reached it) is skipped when
 // skip_zero_first is set
-MD void box_flush(const EnvDev& e, const Box& bx, float* __restrict__ g, int c0, int nc, const float* lds,
-                  bool skip_zero_first) {
+MD void box_flush(const EnvDev& e, const Box& bx, const BoxShared& bs, float* __restrict__ g, int c0, int nc,
+                  const float* lds, bool skip_zero_first) {
   for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
     if (skip_zero_first && lds[idx] == 0.f) continue;
     int i, j, k;
-    box_node(bx, idx, i, j, k);
+    box_node(bs, idx, i, j, k);
     float* dst = g + node_base(e, i, j, k) + c0 * CH;
     for (int c = 0; c < nc; ++c) {
       const float v = lds[c * bx.nodes + idx];
@@ -93,18 +154,21 @@ MD void box_flush(const EnvDev& e, const Box& bx, float* __restrict__ g, int c0,
   }
 }
 
-MD void box_mark_tiles(const EnvDev& e, const Box& bx, uint32_t* __restrict__ flags) {
-  int tlo[3], tn[3];
-  for (int a = 0; a < 3; ++a) {
-    tlo[a] = bx.lo[a] >> 2;
-    tn[a] = ((bx.lo[a] + bx.ext[a] - 1) >> 2) - tlo[a] + 1;
-  }
-  const int cnt = tn[0] * tn[1] * tn[2];
-  for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
-    const int tx = tlo[0] + idx / (tn[1] * tn[2]);
-    const int ty = tlo[1] + (idx / tn[2]) % tn[1];
-    const int tz = tlo[2] + idx % tn[2];
-    flags[e.tile_off + (tx * e.T + ty) * e.T + tz] = 1u;
+MD void box_mark_tiles(const EnvDev& e, const BoxShared& bs, uint32_t* __restrict__ flags) {
+  const int nr = bs.nruns < kMaxRuns ? bs.nruns : kMaxRuns;
+  for (int r = 0; r < nr; ++r) {
+    int tlo[3], tn[3];
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = bs.lo[r][a] >> 2;
+      tn[a] = ((bs.lo[r][a] + bs.ext[r][a] - 1) >> 2) - tlo[a] + 1;
+    }
+    const int cnt = tn[0] * tn[1] * tn[2];
+    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+      const int tx = tlo[0] + idx / (tn[1] * tn[2]);
+      const int ty = tlo[1] + (idx / tn[2]) % tn[1];
+      const int tz = tlo[2] + idx % tn[2];
+      flags[e.tile_off + (tx * e.T + ty) * e.T + tz] = 1u;
+    }
   }
 }
 
@@ -120,6 +184,8 @@ MD void mark_particle_tiles(const EnvDev& e, const int b[3], uint32_t* __restric
 MD void load_x3(const float* __restrict__ st, int64_t N, int64_t p, float x[3]) {
   x[0] = st[p]; x[1] = st[N + p]; x[2] = st[2 * N + p];
 }
+MD M3 ld_m3(const float* __restrict__ st, int64_t N, int64_t p, int c0);
+MD M3 load_cnext(const float* __restrict__ st, int64_t N, int64_t p) { return ld_m3(st, N, p, 6); }
 MD M3 ld_m3(const float* __restrict__ st, int64_t N, int64_t p, int c0) {
   M3 m;
 #pragma unroll
@@ -172,7 +238,7 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int k_call) {
   __shared__ float lds[4 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
@@ -183,7 +249,7 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
-  const Box bx = block_box(sc.b, valid, wb);
+  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits)
     for (int i = threadIdx.x; i < 4 * bx.nodes; i += blockDim.x) lds[i] = 0.f;
   __syncthreads();
@@ -221,18 +287,23 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
     return;
   }
   __syncthreads();
-  box_flush(e, bx, grid, 0, 4, lds, true);
-  box_mark_tiles(e, bx, flags);
+  box_flush(e, bx, bsh, grid, 0, 4, lds, true);
+  box_mark_tiles(e, bsh, flags);
 }
 
-// one block per work item, or a persistent grid that strides over the items
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
 __global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int k_call, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    p2g_lds_item(i, st, N, envs, items, grid, flags, errs, k_call);
-    __syncthreads();
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      p2g_lds_item(i, st, N, envs, items, grid, flags, errs, k_call);
+      __syncthreads();
+    }
+  } else {
+    p2g_lds_item(blockIdx.x, st, N, envs, items, grid, flags, errs, k_call);
   }
 }
 
@@ -243,7 +314,7 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call) {
   __shared__ float lds[3 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) {   // frozen env: the substep is the identity
@@ -259,8 +330,8 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(sc.b, valid, wb);
-  if (bx.fits) box_load(e, bx, grid, 4, 3, lds);
+  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  if (bx.fits) box_load(e, bx, bsh, grid, 4, 3, lds);
   __syncthreads();
   if (!valid) return;
   const M3 F = ld_m3(st, N, p, 15);
@@ -303,20 +374,26 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
 }
 
-// one block per work item, or a persistent grid that strides over the items
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
 __global__ void __launch_bounds__(256) k_g2p_lds(const float* __restrict__ st, float* __restrict__ out, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    g2p_lds_item(i, st, out, N, envs, items, grid, errs, k_call);
-    __syncthreads();
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      g2p_lds_item(i, st, out, N, envs, items, grid, errs, k_call);
+      __syncthreads();
+    }
+  } else {
+    g2p_lds_item(blockIdx.x, st, out, N, envs, items, grid, errs, k_call);
   }
 }
 
 // ----------------------------------------------------------------------------
 // G2P adjoint: gather v from an LDS copy, scatter vbar into LDS, flush
 // ----------------------------------------------------------------------------
-MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const float* __restrict__ cot,
+MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
+    const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
@@ -324,7 +401,7 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
                                                          double* __restrict__ pacc, int k_call) {
   __shared__ float lv[3 * kBoxNodes];
   __shared__ float lg[3 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
@@ -334,9 +411,9 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(sc.b, valid, wb);
+  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits) {
-    box_load(e, bx, grid, 4, 3, lv);
+    box_load(e, bx, bsh, grid, 4, 3, lv);
     for (int i = threadIdx.x; i < 3 * bx.nodes; i += blockDim.x) lg[i] = 0.f;
   }
   __syncthreads();
@@ -344,31 +421,8 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
   if (valid) {
     const M3 F = ld_m3(st, N, p, 15);
     const float D4 = 4.f * e.fn * e.fn;
-    M3 Cn = m3_zero();
-#pragma unroll 1
-    for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          float W, d[3];
-          stencil_offsets(sc, e, ox, oy, oz, W, d);
-          float vi[3];
-          if (bx.fits) {
-            const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) vi[a] = lv[a * bx.nodes + idx];
-          } else {
-            const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) vi[a] = g[(4 + a) * CH];
-          }
-          for (int a = 0; a < 3; ++a) {
-            const float wv = W * vi[a];
-            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
-            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
-            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
-          }
-        }
-    Cn = m3_scale(Cn, D4);
+    // C' of the substep's output state, read from the tape (the forward's own value)
+    const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
     const M3 Ftr = m3_mul(G, F);
     float xb[3], vb[3];
@@ -415,21 +469,27 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
   }
   if (bx.fits) {
     __syncthreads();
-    box_flush(e, bx, gcot, 0, 3, lg, false);
+    box_flush(e, bx, bsh, gcot, 0, 3, lg, false);
   }
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
-// one block per work item, or a persistent grid that strides over the items
-__global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict__ st, const float* __restrict__ cot,
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
+__global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict__ st, const float* __restrict__ st_next,
+    const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ grid, float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int k_call, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    g2p_adjoint_lds_item(i, st, cot, part, N, envs, items, grid, gcot, pacc, k_call);
-    __syncthreads();
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      g2p_adjoint_lds_item(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+      __syncthreads();
+    }
+  } else {
+    g2p_adjoint_lds_item(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
   }
 }
 
@@ -444,7 +504,7 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
                                                          const float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in) {
   __shared__ float lds[4 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
   if (k_call >= e.nsub) {   // frozen env: the cotangent passes through
@@ -460,15 +520,16 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(sc.b, valid, wb);
-  if (bx.fits) box_load(e, bx, gcot, 3, 4, lds);
+  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  if (bx.fits) box_load(e, bx, bsh, gcot, 3, 4, lds);
   __syncthreads();
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
     const M3 F = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, F);
+    const StressPrep spr = stress_prep(e, F);
+    const M3 tau = stress_from(e, spr);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     float xb[3] = {part[p], part[N + p], part[2 * N + p]};
@@ -518,7 +579,7 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = ld_m3(part, N, p, 3);
-    stress_vjp(e, F, taub, Fb, pb);
+    stress_vjp_from(e, F, spr, taub, Fb, pb);
     for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
     st_m3(cot_out, N, p, 6, Cb);
     st_m3(cot_out, N, p, 15, Fb);
@@ -526,7 +587,8 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
-// one block per work item, or a persistent grid that strides over the items
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
 __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict__ st,
                                                          const float* __restrict__ part,
                                                          float* __restrict__ cot_out, int64_t N,
@@ -534,9 +596,13 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    p2g_adjoint_lds_item(i, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
-    __syncthreads();
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      p2g_adjoint_lds_item(i, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
+      __syncthreads();
+    }
+  } else {
+    p2g_adjoint_lds_item(blockIdx.x, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
   }
 }
 
@@ -562,11 +628,13 @@ struct SegShared {
 MD int pack_base(const int b[3]) { return (b[0] << 20) | (b[1] << 10) | b[2]; }
 
 // marks segment starts among the item's particles (thread t <-> particle t)
-// and fills first[] / n_seg; every thread must call it
-MD void find_segments(SegShared& sh, int count) {
+// and fills first[] / n_seg; a run of one stencil base is cut at every
+// max_run-th item position so that long runs spread over more lanes. Every
+// thread must call it.
+MD void find_segments(SegShared& sh, int count, int max_run) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool valid = t < count;
-  const bool start = valid && (t == 0 || sh.key[t] != sh.key[t - 1]);
+  const bool start = valid && (t == 0 || sh.key[t] != sh.key[t - 1] || (t % max_run) == 0);
   const uint64_t bal = __ballot(start);
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int before = __popcll(bal & lt);
@@ -588,46 +656,60 @@ MD void find_segments(SegShared& sh, int count) {
 // WITH_MASS, the remaining three the affine value. Writes into the LDS box
 // (fits) or straight to grid channels c0.. with global atomics.
 template <bool WITH_MASS>
-MD void segment_scatter(const EnvDev& e, const Box& bx, const SegShared& sh, float mass, float* lds_box,
+MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, const SegShared& sh, float mass, float* lds_box,
                         float* __restrict__ g, int c0) {
   constexpr int NCH = WITH_MASS ? 4 : 3;
-  const int units = 9 * sh.n_seg;
+  const int units = 3 * sh.n_seg;   // (segment, ox): the lane sums the 3x3 (oy, oz) nodes of one x-layer
   for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int seg = u / 9, r = u - 9 * seg;
-    const int ox = r / 3, oy = r - 3 * ox;
+    const int seg = u / 3, ox = u - 3 * seg;
     const int p0 = sh.first[seg], p1 = sh.first[seg + 1];
-    float am[3] = {0.f, 0.f, 0.f};
-    float ap[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float am[3][3], ap[3][3][3];
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int z = 0; z < 3; ++z) {
+        am[y][z] = 0.f;
+        ap[y][z][0] = ap[y][z][1] = ap[y][z][2] = 0.f;
+      }
     for (int p = p0; p < p1; ++p) {
-      const float wxy = sh.w[ox][p] * sh.w[3 + oy][p];
-      float rr[3], az[3];
+      const float wx = sh.w[ox][p];
+      float wy[3], wz[3], r0[3], ay[3], az[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { wy[k] = wx * sh.w[3 + k][p]; wz[k] = sh.w[6 + k][p]; }
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        rr[a] = sh.q[a][p] + sh.a[3 * a][p] * (float)ox + sh.a[3 * a + 1][p] * (float)oy;
+        r0[a] = sh.q[a][p] + sh.a[3 * a][p] * (float)ox;
+        ay[a] = sh.a[3 * a + 1][p];
         az[a] = sh.a[3 * a + 2][p];
       }
 #pragma unroll
-      for (int oz = 0; oz < 3; ++oz) {
-        const float W = wxy * sh.w[6 + oz][p];
-        am[oz] += W;
-        for (int a = 0; a < 3; ++a) ap[oz][a] = fmaf(W, rr[a] + az[a] * (float)oz, ap[oz][a]);
-      }
+      for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int z = 0; z < 3; ++z) {
+          const float W = wy[y] * wz[z];
+          am[y][z] += W;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ap[y][z][a] = fmaf(W, r0[a] + ay[a] * (float)y + az[a] * (float)z, ap[y][z][a]);
+        }
     }
     const int key = sh.key[p0];
-    const int bx0 = (key >> 20) + ox, by0 = ((key >> 10) & 1023) + oy, bz0 = key & 1023;
+    const int bx0 = (key >> 20) + ox, by0 = (key >> 10) & 1023, bz0 = key & 1023;
 #pragma unroll
-    for (int oz = 0; oz < 3; ++oz) {
-      float v[4];
-      int k = 0;
-      if (WITH_MASS) v[k++] = am[oz] * mass;
-      for (int a = 0; a < 3; ++a) v[k++] = ap[oz][a];
-      if (bx.fits) {
-        const int idx = box_index(bx, bx0, by0, bz0 + oz);
-        for (int c = 0; c < NCH; ++c) atomicAdd(&lds_box[c * bx.nodes + idx], v[c]);
-      } else {
-        float* dst = g + node_base(e, bx0, by0, bz0 + oz) + c0 * CH;
-        for (int c = 0; c < NCH; ++c) atomicAdd(dst + c * CH, v[c]);
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int z = 0; z < 3; ++z) {
+        float v[4];
+        int k = 0;
+        if (WITH_MASS) v[k++] = am[y][z] * mass;
+        for (int a = 0; a < 3; ++a) v[k++] = ap[y][z][a];
+        if (bx.fits) {
+          const int idx = box_index_run(bs, bs.run[p0], bx0, by0 + y, bz0 + z);
+          for (int c = 0; c < NCH; ++c) atomicAdd(&lds_box[c * bx.nodes + idx], v[c]);
+        } else {
+          float* dst = g + node_base(e, bx0, by0 + y, bz0 + z) + c0 * CH;
+          for (int c = 0; c < NCH; ++c) atomicAdd(dst + c * CH, v[c]);
+        }
       }
-    }
   }
 }
 
@@ -635,9 +717,10 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const SegShared& sh, flo
 MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
-                                                 int32_t* __restrict__ errs, int min_run, int k_call) {
+                                                 int32_t* __restrict__ errs, int runs, int k_call) {
+  const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
   __shared__ float lds[4 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   __shared__ SegShared sh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
@@ -650,8 +733,8 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
   sh.key[t] = pack_base(sc.b);
-  const Box bx = block_box(sc.b, valid, wb);   // synchronizes
-  find_segments(sh, it.count);                 // synchronizes
+  const Box bx = block_box(e, sc.b, valid, t, it.count, bsh);   // synchronizes
+  find_segments(sh, it.count, max_run);        // synchronizes
   const bool seg_mode = it.count >= min_run * sh.n_seg;   // uniform across the block
   if (bx.fits)
     for (int i = t; i < 4 * bx.nodes; i += blockDim.x) lds[i] = 0.f;
@@ -698,44 +781,54 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
   }
   __syncthreads();
   if (seg_mode) {
-    segment_scatter<true>(e, bx, sh, e.mp, lds, grid, 0);
+    segment_scatter<true>(e, bx, bsh, sh, e.mp, lds, grid, 0);
     __syncthreads();
   }
   if (bx.fits) {
-    box_flush(e, bx, grid, 0, 4, lds, true);
-    box_mark_tiles(e, bx, flags);
+    box_flush(e, bx, bsh, grid, 0, 4, lds, true);
+    box_mark_tiles(e, bsh, flags);
   } else if (valid) {
     mark_particle_tiles(e, sc.b, flags);
   }
 }
 
-// one block per work item, or a persistent grid that strides over the items
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
 __global__ void __launch_bounds__(256) k_p2g_seg(const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
-                                                 int32_t* __restrict__ errs, int min_run, int k_call, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    p2g_seg_item(i, st, N, envs, items, grid, flags, errs, min_run, k_call);
-    __syncthreads();
+                                                 int32_t* __restrict__ errs, int runs, int k_call, int n_items) {
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      p2g_seg_item(i, st, N, envs, items, grid, flags, errs, runs, k_call);
+      __syncthreads();
+    }
+  } else {
+    p2g_seg_item(blockIdx.x, st, N, envs, items, grid, flags, errs, runs, k_call);
   }
 }
 
 void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int min_run, int k_call, int grid_cap, hipStream_t s) {
+                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_seg, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, min_run, k_call, n_items);
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_p2g_seg<true>, dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
+  else
+    hipLaunchKernelGGL(k_p2g_seg<false>, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
 }
 
 // G2P adjoint with segment-reduced scatter: thread t <-> particle t
-MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const float* __restrict__ cot,
+MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
+    const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ grid, float* __restrict__ gcot,
-                                                         double* __restrict__ pacc, int min_run, int k_call) {
+                                                         double* __restrict__ pacc, int runs, int k_call) {
+  const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
   __shared__ float lv[3 * kBoxNodes];
   __shared__ float lg[3 * kBoxNodes];
-  __shared__ int wb[4][6];
+  __shared__ BoxShared bsh;
   __shared__ SegShared sh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
@@ -747,11 +840,11 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   sh.key[t] = pack_base(sc.b);
-  const Box bx = block_box(sc.b, valid, wb);
-  find_segments(sh, it.count);
+  const Box bx = block_box(e, sc.b, valid, t, it.count, bsh);   // synchronizes
+  find_segments(sh, it.count, max_run);
   const bool seg_mode = it.count >= min_run * sh.n_seg;
   if (bx.fits) {
-    box_load(e, bx, grid, 4, 3, lv);
+    box_load(e, bx, bsh, grid, 4, 3, lv);
     for (int i = t; i < 3 * bx.nodes; i += blockDim.x) lg[i] = 0.f;
   }
   __syncthreads();
@@ -759,31 +852,8 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   if (valid) {
     const M3 F = ld_m3(st, N, p, 15);
     const float D4 = 4.f * e.fn * e.fn;
-    M3 Cn = m3_zero();
-#pragma unroll 1
-    for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          float W, d[3];
-          stencil_offsets(sc, e, ox, oy, oz, W, d);
-          float vi[3];
-          if (bx.fits) {
-            const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) vi[a] = lv[a * bx.nodes + idx];
-          } else {
-            const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) vi[a] = g[(4 + a) * CH];
-          }
-          for (int a = 0; a < 3; ++a) {
-            const float wv = W * vi[a];
-            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
-            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
-            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
-          }
-        }
-    Cn = m3_scale(Cn, D4);
+    // C' of the substep's output state, read from the tape (the forward's own value)
+    const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
     const M3 Ftr = m3_mul(G, F);
     float xb[3], vb[3];
@@ -844,55 +914,79 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   }
   __syncthreads();
   if (seg_mode) {
-    segment_scatter<false>(e, bx, sh, 0.f, lg, gcot, 0);
+    segment_scatter<false>(e, bx, bsh, sh, 0.f, lg, gcot, 0);
     __syncthreads();
   }
-  if (bx.fits) box_flush(e, bx, gcot, 0, 3, lg, false);
+  if (bx.fits) box_flush(e, bx, bsh, gcot, 0, 3, lg, false);
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
-// one block per work item, or a persistent grid that strides over the items
-__global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ cot,
+// one block per work item, or (PERSIST) a grid that strides over the items
+template <bool PERSIST>
+__global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ st_next,
+    const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ grid, float* __restrict__ gcot,
-                                                         double* __restrict__ pacc, int min_run, int k_call, int n_items) {
-  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-    g2p_adjoint_seg_item(i, st, cot, part, N, envs, items, grid, gcot, pacc, min_run, k_call);
-    __syncthreads();
+                                                         double* __restrict__ pacc, int runs, int k_call, int n_items) {
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      g2p_adjoint_seg_item(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
+      __syncthreads();
+    }
+  } else {
+    g2p_adjoint_seg_item(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
   }
 }
 
-void launch_g2p_adjoint_seg(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int min_run, int k_call, int grid_cap, hipStream_t s) {
+                            int runs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_adjoint_seg, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
-                     pacc, min_run, k_call, n_items);
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_g2p_adjoint_seg<true>, dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+                     pacc, runs, k_call, n_items);
+  else
+    hipLaunchKernelGGL(k_g2p_adjoint_seg<false>, dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+                     pacc, runs, k_call, n_items);
 }
 
 void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_p2g_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
+  else
+    hipLaunchKernelGGL(k_p2g_lds<false>, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
 }
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                     const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_g2p_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+  else
+    hipLaunchKernelGGL(k_g2p_lds<false>, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
 }
-void launch_g2p_adjoint_lds(const float* st, const float* cot, float* part, int64_t N, const EnvDev* envs,
+void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                             int k_call, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_g2p_adjoint_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, cot, part, N, envs, items, grid, gcot,
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_g2p_adjoint_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+                     pacc, k_call, n_items);
+  else
+    hipLaunchKernelGGL(k_g2p_adjoint_lds<false>, dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
                      pacc, k_call, n_items);
 }
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_p2g_adjoint_lds, dim3(grid_cap > 0 && grid_cap < n_items ? grid_cap : n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL(k_p2g_adjoint_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+                     pacc, k_call, cot_in, n_items);
+  else
+    hipLaunchKernelGGL(k_p2g_adjoint_lds<false>, dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
                      pacc, k_call, cot_in, n_items);
 }
 

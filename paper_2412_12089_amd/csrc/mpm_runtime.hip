@@ -95,6 +95,7 @@ struct mpm_batch {
   // particles average at least min_run per stencil base
   int var_p2g = 2, var_g2p = 1, var_g2p_adj = 2, var_p2g_adj = 1;
   int min_run = 3;
+  int max_run = 8;    // runs of one stencil base are split every max_run particles
   int grid_cap = 0;   // 0: one block per work item; > 0: persistent grid of this many blocks
 
   // hipGraph replay of whole segments (batched mode): captured on a private
@@ -214,7 +215,7 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_P2G);
-      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run, kc, b->grid_cap, s);
+      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run | (b->max_run << 16), kc, b->grid_cap, s);
       else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, b->grid_cap, s);
       else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
     }
@@ -227,7 +228,8 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
   }
 }
 
-void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int gi, int k_rel, int kc) {
+void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const float* cot_in, float* cot_out, int gi,
+                     int k_rel, int kc) {
   float* g = b->grid[gi];
   uint32_t* fl = b->flags[gi];
   const hipStream_t s = b->stream;
@@ -236,7 +238,7 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* 
       const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
-      { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, kc, s); }
+      { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, kc, s); }
       { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
       { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, kc, cot_in, s); }
     }
@@ -244,9 +246,9 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* cot_in, float* 
     const int ni = (int)b->items_h.size();
     {
       Span sp(b, KC_G2P_ADJ);
-      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run, kc, b->grid_cap, s);
-      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, b->grid_cap, s);
-      else launch_g2p_adjoint_direct(st, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run | (b->max_run << 16), kc, b->grid_cap, s);
+      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, b->grid_cap, s);
+      else launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
     }
     { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
     {
@@ -315,7 +317,7 @@ int bwd_segment(mpm_batch* b, int j, int Kj, bool have_tape, int c) {
   }
   for (int k = Kj - 1; k >= 0; --k) {
     const float* st = k == 0 ? b->ckpt[j] : b->seg[k];
-    adjoint_substep(b, st, b->cot[c], b->cot[c ^ 1], k + 1, k, j * b->K + k);
+    adjoint_substep(b, st, b->seg[k + 1], b->cot[c], b->cot[c ^ 1], k + 1, k, j * b->K + k);
     c ^= 1;
   }
   launch_unpermute(b->cot[c], b->cot[c ^ 1], b->N, b->perm[j], b->stream);
@@ -383,6 +385,33 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
   if (env == -1 && allow_all) return MPM_OK;
   if (env < 0 || env >= b->E) return fail(b, MPM_INVALID_ARG, "env index out of range");
   return MPM_OK;
+}
+
+}  // namespace
+
+namespace {
+
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run; };
+
+// shape signature -> choice, shared by batches of the same shape in the process
+std::map<std::string, TuneChoice>& tune_cache() {
+  static std::map<std::string, TuneChoice> c;
+  return c;
+}
+
+std::string shape_signature(const mpm_batch* b) {
+  std::string sig = std::to_string(b->K) + ":";
+  for (const EnvDev& e : b->envs_h)
+    sig += std::to_string(e.n) + "," + std::to_string(e.material) + "," + std::to_string(e.p_cnt) + ";";
+  return sig;
+}
+
+void apply_choice(mpm_batch* b, const TuneChoice& c) {
+  b->var_p2g = c.p2g; b->var_g2p = c.g2p; b->var_g2p_adj = c.g2p_adj; b->var_p2g_adj = c.p2g_adj;
+  b->min_run = c.min_run;
+  b->grid_cap = c.grid_cap;
+  b->max_run = c.max_run;
+  drop_graphs(b);
 }
 
 }  // namespace
@@ -797,6 +826,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_P2G_ADJ: if (value < 0 || value > 1) break; b->var_p2g_adj = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_MIN_RUN: if (value < 1 || value > 256) break; b->min_run = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_GRID_CAP: if (value < 0) break; b->grid_cap = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_MAX_RUN: if (value < 1 || value > 256) break; b->max_run = value; drop_graphs(b); return MPM_OK;
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -812,35 +842,11 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_P2G_ADJ: *value = b->var_p2g_adj; return MPM_OK;
     case MPM_OPT_MIN_RUN: *value = b->min_run; return MPM_OK;
     case MPM_OPT_GRID_CAP: *value = b->grid_cap; return MPM_OK;
+    case MPM_OPT_MAX_RUN: *value = b->max_run; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
 
-namespace {
-
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap; };
-
-// shape signature -> choice, shared by batches of the same shape in the process
-std::map<std::string, TuneChoice>& tune_cache() {
-  static std::map<std::string, TuneChoice> c;
-  return c;
-}
-
-std::string shape_signature(const mpm_batch* b) {
-  std::string sig = std::to_string(b->K) + ":";
-  for (const EnvDev& e : b->envs_h)
-    sig += std::to_string(e.n) + "," + std::to_string(e.material) + "," + std::to_string(e.p_cnt) + ";";
-  return sig;
-}
-
-void apply_choice(mpm_batch* b, const TuneChoice& c) {
-  b->var_p2g = c.p2g; b->var_g2p = c.g2p; b->var_g2p_adj = c.g2p_adj; b->var_p2g_adj = c.p2g_adj;
-  b->min_run = c.min_run;
-  b->grid_cap = c.grid_cap;
-  drop_graphs(b);
-}
-
-}  // namespace
 
 int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
   if (!b) return MPM_INVALID_ARG;
@@ -910,7 +916,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -938,6 +944,8 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.p2g_adj, 0, 0, true}, {&best.p2g_adj, 1, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
+      {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},
+       {&best.max_run, 256, 0, true}},
   };
   for (auto& grp : groups) {
     if (rc) break;

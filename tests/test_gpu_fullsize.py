@@ -1,0 +1,145 @@
+"""Parity at the benchmark workloads' full sizes, on sampled environments.
+
+The GPU runs the whole workload in the launch configuration bench.py times
+(batched mode, autotuned variants, graphs); the FP64 oracle recomputes the
+sampled environments. Where the oracle is too slow for the whole horizon
+(200k-particle dam break), it checks a short horizon at full size and the
+gradient on a reduced copy of the same scene, and the full run is checked
+through properties that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from conftest import gpu_available
+from gpu_util import oracle_rollout, relerr, to_np
+from paper_2412_12089_amd import scenes
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def announce(msg):
+    print(f"[gpu-fullsize] {msg}", flush=True)
+
+
+def run_workload(wl, S=None, backward=True, tune=True):
+    from paper_2412_12089_amd.batch import Batch
+    S = S or wl.substeps
+    envs = wl.envs
+    dev = torch.device("cuda:0")
+    cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in envs], axis=0)).to(dev)
+    b = Batch(envs, max_substeps=S, ckpt_every=wl.ckpt_every, mode="batched", device=dev)
+    b.set_particles(cat("x"), cat("v"), cat("C"), cat("F"))
+    if tune:
+        b.autotune(2000)
+        b.set_particles(cat("x"), cat("v"), cat("C"), cat("F"))
+    b.forward(S, record=backward)
+    st = [to_np(t) for t in b.get_particles()]
+    gr = dp = None
+    if backward:
+        w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
+        dx, dv, dC, dF, dpp = b.backward(gx=w)
+        gr = [to_np(t) for t in (dx, dv, dC, dF)]
+        dp = to_np(dpp)
+    status = b.sync(raise_on_error=False)
+    offs = np.concatenate([[0], np.cumsum([e.n_particles for e in envs])]).astype(int)
+    b.close()
+    return st, gr, dp, status, offs
+
+
+def loss_cot(wl, i):
+    N = wl.envs[i].n_particles
+    return (wl.loss_weights[i], np.zeros((N, 3), np.float32), np.zeros((N, 3, 3), np.float32),
+            np.zeros((N, 3, 3), np.float32))
+
+
+def check_env(st, gr, dp, offs, i, o, tag, params=(0,), tol_v=1e-5):
+    sl = slice(offs[i], offs[i + 1])
+    ex, ev = relerr(st[0][sl], o["state"][0]), relerr(st[1][sl], o["state"][1])
+    announce(f"{tag}: x {ex:.2e} v {ev:.2e}")
+    assert ex < 1e-5 and ev < tol_v
+    if gr is not None:
+        e = [relerr(g[sl], og) for g, og in zip(gr, o["grads"])]
+        announce(f"{tag}: grad x {e[0]:.2e} v {e[1]:.2e} C {e[2]:.2e} F {e[3]:.2e}")
+        assert max(e) < 1e-3
+        for k in params:
+            r = abs(dp[i][k] - o["dparams"][k]) / abs(o["dparams"][k])
+            announce(f"{tag}: dparam[{k}] {dp[i][k]:.6e} vs {o['dparams'][k]:.6e} rel {r:.2e}")
+            assert r < 1e-3
+
+
+def test_batched_corot_full_size():
+    wl = scenes.batched_corot()
+    announce(f"batched_corot: {len(wl.envs)} envs x {wl.envs[0].n_particles}, {wl.substeps} substeps, K={wl.ckpt_every}")
+    st, gr, dp, status, offs = run_workload(wl)
+    assert status == 0
+    # identical environments give identical results (batch property at full size)
+    for i in range(1, len(wl.envs)):
+        sl = slice(offs[i], offs[i + 1])
+        s0 = slice(offs[0], offs[1])
+        assert relerr(st[0][sl], st[0][s0]) < 1e-6 and relerr(gr[1][sl], gr[1][s0]) < 1e-4
+    assert np.allclose(dp[:, 0], dp[0, 0], rtol=1e-4)
+    announce("oracle on env 0 (20,000 particles, 80 substeps)")
+    o = oracle_rollout(wl.envs[0], wl.substeps, loss_cot(wl, 0))
+    # FP32 position increments (dt v ~ 1e-6..1e-5 on x ~ 0.5) round every substep; over 80 substeps the
+    # velocity error grows past the 10-substep bar, so it is checked at 10x that bar (x stays at 1e-5)
+    check_env(st, gr, dp, offs, 0, o, "batched_corot env 0, 80 substeps", params=(0, 1), tol_v=1e-4)
+    # the stated bar after 10 substeps, on the full workload
+    st10, _, _, status10, offs10 = run_workload(wl, S=10, backward=False, tune=False)
+    assert status10 == 0
+    o10 = oracle_rollout(wl.envs[0], 10)
+    check_env(st10, None, None, offs10, 0, o10, "batched_corot env 0, 10 substeps")
+
+
+def test_uneven_mixed_full_size():
+    wl = scenes.uneven_mixed()
+    N = sum(e.n_particles for e in wl.envs)
+    announce(f"uneven_mixed: {len(wl.envs)} envs, {N} particles, {wl.substeps} substeps")
+    st, gr, dp, status, offs = run_workload(wl)
+    assert status == 0
+    # the smallest env of each material
+    picks = {}
+    for i, e in enumerate(wl.envs):
+        if e.material not in picks or e.n_particles < wl.envs[picks[e.material]].n_particles:
+            picks[e.material] = i
+    for mat, i in sorted(picks.items()):
+        e = wl.envs[i]
+        announce(f"oracle on env {i} ({scenes.MATERIAL_NAMES[mat]}, {e.n_particles} particles)")
+        o = oracle_rollout(e, wl.substeps, loss_cot(wl, i))
+        params = {scenes.NEOHOOKEAN: (0, 1), scenes.VONMISES: (0, 1, 4), scenes.FLUID_TAIT: (5, 6)}[mat]
+        check_env(st, gr, dp, offs, i, o, f"uneven_mixed env {i}", params=params)
+
+
+def test_dam_break_full_size():
+    wl = scenes.dam_break()
+    announce(f"dam_break: {len(wl.envs)} envs x {wl.envs[0].n_particles}, {wl.substeps} substeps, K={wl.ckpt_every}")
+    st, gr, dp, status, offs = run_workload(wl)
+    assert status == 0
+    # properties of the full run: finite, inside the walls, fluid F stays J^(1/3) I with J near 1,
+    # the column spreads along +x once the gate withdraws
+    for a in st + gr:
+        assert np.isfinite(a).all()
+    x, F = st[0], st[3]
+    b = scenes.WALL / wl.envs[0].n
+    assert (x > b * 0.5).all() and (x < 1 - b * 0.5).all()
+    J = np.linalg.det(F)
+    assert (J > 0.8).all() and (J < 1.2).all()
+    assert np.abs(F - np.cbrt(J)[:, None, None] * np.eye(3)).max() < 1e-5
+    x0 = np.concatenate([e.x for e in wl.envs])
+    assert x[:, 0].max() > x0[:, 0].max()
+    # full-size short horizon against the oracle (env 0, 8 substeps, forward)
+    S = 8
+    st8, _, _, status8, offs8 = run_workload(wl, S=S, backward=False, tune=False)
+    assert status8 == 0
+    announce(f"oracle on env 0, {S} substeps at full size")
+    o = oracle_rollout(wl.envs[0], S)
+    check_env(st8, None, None, offs8, 0, o, "dam_break env 0 (8 substeps)")
+
+
+def test_dam_break_reduced_gradient():
+    wl = scenes.dam_break(n_envs=2, n_per_env=12000, n_substeps=30, ckpt_every=10)
+    announce("dam_break reduced: 2 envs x 12,000 particles, 30 substeps, K=10")
+    st, gr, dp, status, offs = run_workload(wl)
+    assert status == 0
+    o = oracle_rollout(wl.envs[1], wl.substeps, loss_cot(wl, 1))
+    check_env(st, gr, dp, offs, 1, o, "dam_break reduced env 1", params=(5, 6))

@@ -334,3 +334,46 @@ def test_autotune_restores_state_and_keeps_parity():
     o = oracle_rollout(envs[1], 8, cots[1])
     check_state([a[sl] for a in st], o["state"], "after autotune")
     check_grads([g[sl] for g in gr], o["grads"], "after autotune")
+
+
+# ------------------------------------------------------------------ failure forcing from the host
+def test_nonfinite_input_is_reported():
+    spec = make_env(scenes.NEOHOOKEAN, N=400, seed=130)
+    spec.v[7] = np.float32([np.nan, 0.0, 0.0])
+    announce("NaN velocity in the initial state")
+    r = gpu_rollout([spec], 2, 2)
+    assert r["status"] == 4
+    assert r["errors"][0] & 1
+
+
+def test_invalid_material_parameters_are_rejected():
+    from paper_2412_12089_amd.batch import Batch
+    from paper_2412_12089_amd._capi import MPMError
+    spec = make_env(scenes.NEOHOOKEAN, N=100, seed=131)
+    b = Batch([spec], max_substeps=2, ckpt_every=2)
+    for bad in ([5e3, 0.5, 1e3, 1e-6, 0, 0, 0, 0], [-1.0, 0.3, 1e3, 1e-6, 0, 0, 0, 0],
+                [5e3, -1.0, 1e3, 1e-6, 0, 0, 0, 0], [5e3, 0.3, -1.0, 1e-6, 0, 0, 0, 0]):
+        with pytest.raises(MPMError) as ei:
+            b.set_material(0, scenes.NEOHOOKEAN, bad)
+        assert ei.value.code == 1
+    with pytest.raises(MPMError):
+        b.set_material(0, scenes.FLUID_TAIT, [0, 0.3, 1e3, 1e-6, 0, 1e4, 0.0, 0])   # gamma <= 0
+    with pytest.raises(MPMError):
+        b.set_material(0, 9, spec.params())
+    with pytest.raises(MPMError):
+        b.set_particles(torch.zeros(5, 3), torch.zeros(5, 3), torch.zeros(5, 3, 3), torch.zeros(5, 3, 3))
+    b.close()
+
+
+def test_checkpoint_memory_follows_segments_plus_tape():
+    from paper_2412_12089_amd.batch import Batch
+    spec = make_env(scenes.COROTATED, N=20000, seed=132)
+    S = 36
+    mem = {}
+    for K in (1, 6, 36):
+        b = Batch([spec], max_substeps=S, ckpt_every=K)
+        mem[K] = b.memory_bytes()
+        b.close()
+    announce(f"memory bytes by K: {mem}")
+    # state buffers ~ S/K checkpoints + K tape states (+ K tape grids): K = 6 is the minimum of S/K + K
+    assert mem[6] < mem[1] and mem[6] < mem[36]

@@ -118,7 +118,9 @@ int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v,
 
 /* Copies the current particle state out in the caller's original particle
  * order (device pointers; any of the four may be NULL to skip it). env = -1
- * writes all environments concatenated. */
+ * writes all environments concatenated. The library holds F as F - I (small
+ * strains keep FP32 precision relative to themselves); a set/get round trip
+ * returns F unchanged for diagonal entries in [0.5, 2], where F - I is exact. */
 int mpm_get_particles(mpm_batch* b, int32_t env, float* x, float* v, float* C, float* F);
 
 /* Material and parameters of one environment (env = -1: all). `params` is a

@@ -78,6 +78,7 @@ MD M3 m3_add(const M3& a, const M3& b) { M3 r; for (int i = 0; i < 3; ++i) for (
 MD M3 m3_scale(const M3& a, float s) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][j] * s; return r; }
 MD M3 m3_axpy(const M3& y, float s, const M3& x) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = fmaf(s, x.m[i][j], y.m[i][j]); return r; }
 MD M3 m3_sym(const M3& a) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = 0.5f * (a.m[i][j] + a.m[j][i]); return r; }
+MD M3 m3_transpose(const M3& a) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[j][i]; return r; }
 MD float m3_trace(const M3& a) { return a.m[0][0] + a.m[1][1] + a.m[2][2]; }
 MD float m3_ddot(const M3& a, const M3& b) {
   float s = 0.f;
@@ -162,13 +163,6 @@ MD void eig_sym(M3 A, float s[3], M3& U) {
   s[2] = A.m[2][2];
 }
 
-// (log a - log b) / (a - b) for a, b > 0, finite as a -> b (limit 1/b)
-MD float log_divdiff(float a, float b) {
-  const float d = a - b;
-  const float z = d / b;
-  if (fabsf(z) < 1e-3f) return (1.f - z * (0.5f - z * (1.f / 3.f))) / b;
-  return log1pf(z) / d;
-}
 // expm1(z) / z, finite at 0
 MD float expm1_over(float z) {
   if (fabsf(z) < 1e-3f) return 1.f + z * (0.5f + z * (1.f / 6.f));
@@ -220,119 +214,169 @@ MD int64_t node_base(const EnvDev& e, int i, int j, int k) {
 constexpr int CH = 64;  // channel stride inside a tile
 
 // --------------------------------------------------------------------------
+// Deformation gradients are carried as H = F - I. Strains of 1e-4..1e-2 then
+// keep FP32 precision relative to themselves (F rounds them relative to 1),
+// and every quantity that vanishes at the rest state (J - 1, F F^T - I, the
+// stresses) is formed from H without cancellation.
+// --------------------------------------------------------------------------
+MD M3 f_of(const M3& H) {
+  M3 F = H;
+  F.m[0][0] += 1.f; F.m[1][1] += 1.f; F.m[2][2] += 1.f;
+  return F;
+}
+// det(I + H) - 1 = tr H + (principal 2x2 minors of H) + det H
+MD float det_minus_one(const M3& H) {
+  const float m2 = (H.m[0][0] * H.m[1][1] - H.m[0][1] * H.m[1][0]) + (H.m[0][0] * H.m[2][2] - H.m[0][2] * H.m[2][0]) +
+                   (H.m[1][1] * H.m[2][2] - H.m[1][2] * H.m[2][1]);
+  return m3_trace(H) + (m2 + m3_det(H));
+}
+// a6: F_tr = (I + dt C') F, as H_tr = H + dt C' (I + H)
+MD M3 trial_h(const EnvDev& e, const M3& Cn, const M3& H) { return m3_axpy(H, e.dt, m3_add(Cn, m3_mul(Cn, H))); }
+
+// (log1p(a) - log1p(b)) / (a - b) for a, b > -1, finite as a -> b (limit 1/(1+b))
+MD float log1p_divdiff(float a, float b) {
+  const float d = a - b;
+  const float z = d / (1.f + b);
+  if (fabsf(z) < 1e-3f) return (1.f - z * (0.5f - z * (1.f / 3.f))) / (1.f + b);
+  return log1pf(z) / d;
+}
+
+// --------------------------------------------------------------------------
 // a3: Kirchhoff stress tau = P F^T
 // --------------------------------------------------------------------------
 // Quantities of F shared by the stress and its VJP (one eigen-decomposition
-// of b = F F^T serves both in the P2G adjoint).
+// of B = F F^T - I serves both in the P2G adjoint).
 struct StressPrep {
-  M3 b, U;
-  float s[3];
-  float J;
+  M3 B, U;      // B = F F^T - I = H + H^T + H H^T; U its eigenvectors
+  float l[3];   // eigenvalues of B (those of F F^T minus one)
+  float J, Jm1; // det F and det F - 1
 };
 
-MD StressPrep stress_prep(const EnvDev& e, const M3& F) {
+MD StressPrep stress_prep(const EnvDev& e, const M3& H) {
   StressPrep p;
-  p.J = m3_det(F);
+  p.Jm1 = det_minus_one(H);
+  p.J = 1.f + p.Jm1;
   if (e.material == MAT_NEOHOOKEAN || e.material == MAT_COROTATED || e.material == MAT_VONMISES)
-    p.b = m3_mul_abt(F, F);
-  if (e.material == MAT_COROTATED || e.material == MAT_VONMISES) eig_sym(p.b, p.s, p.U);
+    p.B = m3_add(m3_add(H, m3_transpose(H)), m3_mul_abt(H, H));
+  if (e.material == MAT_COROTATED || e.material == MAT_VONMISES) eig_sym(p.B, p.l, p.U);
   return p;
 }
 
+// singular value of F from an eigenvalue l of B: sqrt(1 + l), and sqrt(1 + l) - 1
+MD void sv_of(float l, float& s, float& sm1) {
+  const float lc = fmaxf(l, -1.f);
+  s = sqrtf(1.f + lc);
+  sm1 = lc / (1.f + s);
+}
+// log strain of an eigenvalue of B, with the singular value clamped at kSigmaMin
+MD float log_strain(float l) { return 0.5f * log1pf(fmaxf(l, kSigmaMin * kSigmaMin - 1.f)); }
+MD float clamp_l(float l) { return fmaxf(l, kSigmaMin * kSigmaMin - 1.f); }
+
 MD M3 stress_from(const EnvDev& e, const StressPrep& p) {
-  const float J = p.J;
+  const float J = p.J, Jm1 = p.Jm1;
   switch (e.material) {
     case MAT_NEOHOOKEAN: {
-      const float Ic = m3_trace(p.b);
-      const float c1 = e.mu * (1.f - 1.f / (Ic + 1.f));
-      const float c2 = e.lam * J * (J - e.alpha_nh);
-      M3 t = m3_scale(p.b, c1);
-      t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
-      return t;
+      // mu (1 - 1/(I_C + 1)) b + lam J (J - alpha) I with b = I + B, I_C = 3 + tr B and
+      // alpha = 1 + 3 mu / (4 lam): the identity parts cancel at rest, so their sum is
+      // mu (t / (4 (4 + t)) - 3/4 (J - 1)) + lam J (J - 1), t = tr B
+      const float t = m3_trace(p.B);
+      const float c1 = e.mu * (3.f + t) / (4.f + t);
+      const float c0 = e.mu * (t / (4.f * (4.f + t)) - 0.75f * Jm1) + e.lam * J * Jm1;
+      M3 r = m3_scale(p.B, c1);
+      r.m[0][0] += c0; r.m[1][1] += c0; r.m[2][2] += c0;
+      return r;
     }
     case MAT_COROTATED: {
-      // 2 mu (F - R) F^T = 2 mu (b - b^(1/2))
-      float sg[3];
-      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(p.s[i], 0.f));
-      const M3 bh = m3_spectral(p.U, sg);
-      M3 t = m3_scale(m3_axpy(p.b, -1.f, bh), 2.f * e.mu);
-      const float c2 = e.lam * J * (J - 1.f);
-      t.m[0][0] += c2; t.m[1][1] += c2; t.m[2][2] += c2;
-      return t;
+      // 2 mu (F - R) F^T = 2 mu (b - b^(1/2)): eigenvalues s (s - 1), s = sqrt(1 + l)
+      float h[3];
+      for (int i = 0; i < 3; ++i) {
+        float sg, sm1;
+        sv_of(p.l[i], sg, sm1);
+        h[i] = 2.f * e.mu * sg * sm1;
+      }
+      M3 r = m3_spectral(p.U, h);
+      const float c2 = e.lam * J * Jm1;
+      r.m[0][0] += c2; r.m[1][1] += c2; r.m[2][2] += c2;
+      return r;
     }
     case MAT_VONMISES: {
-      // U (2 mu eps + lam tr(eps) I) U^T, eps = log Sigma = (1/2) log s
+      // U (2 mu eps + lam tr(eps) I) U^T, eps = log Sigma
       float eps[3];
-      for (int i = 0; i < 3; ++i) eps[i] = 0.5f * logf(fmaxf(p.s[i], kSigmaMin * kSigmaMin));
+      for (int i = 0; i < 3; ++i) eps[i] = log_strain(p.l[i]);
       const float tre = eps[0] + eps[1] + eps[2];
       float d[3];
       for (int i = 0; i < 3; ++i) d[i] = 2.f * e.mu * eps[i] + e.lam * tre;
       return m3_spectral(p.U, d);
     }
     case MAT_FLUID_TAIT: {
-      const float c = e.bulk * (J - powf(J, 1.f - e.gam));  // -J K (J^-gamma - 1)
-      M3 t = m3_zero(); t.m[0][0] = t.m[1][1] = t.m[2][2] = c;
-      return t;
+      // -J K (J^-gamma - 1)
+      const float c = -e.bulk * J * expm1f(-e.gam * log1pf(Jm1));
+      M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = c;
+      return r;
     }
     default: {  // MAT_FLUID_PAPER: lam J (J - 1) I
-      const float c = e.lam * J * (J - 1.f);
-      M3 t = m3_zero(); t.m[0][0] = t.m[1][1] = t.m[2][2] = c;
-      return t;
+      const float c = e.lam * J * Jm1;
+      M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = c;
+      return r;
     }
   }
 }
 
-// a3: Kirchhoff stress tau = P F^T
-MD M3 stress(const EnvDev& e, const M3& F) { return stress_from(e, stress_prep(e, F)); }
+// a3: Kirchhoff stress from H = F - I
+MD M3 stress(const EnvDev& e, const M3& H) { return stress_from(e, stress_prep(e, H)); }
 
 // VJP of stress(): Fbar += d<taubar, tau>/dF, pb[] += d<taubar, tau>/d(params)
-MD void stress_vjp_from(const EnvDev& e, const M3& F, const StressPrep& p, const M3& tb, M3& Fbar,
+MD void stress_vjp_from(const EnvDev& e, const M3& H, const StressPrep& p, const M3& tb, M3& Fbar,
                         float pb[PB_COUNT]) {
-  const float J = p.J;
+  const float J = p.J, Jm1 = p.Jm1;
   const float trtb = m3_trace(tb);
+  const M3 F = f_of(H);
   switch (e.material) {
     case MAT_NEOHOOKEAN: {
-      const M3& b = p.b;
-      const float Ic = m3_trace(b);
-      const float inv = 1.f / (Ic + 1.f);
-      const float c1 = e.mu * (1.f - inv);
+      const float t = m3_trace(p.B);
+      const float inv = 1.f / (4.f + t);
+      const float c1 = e.mu * (3.f + t) * inv;
       const M3 tbs = m3_sym(tb);
-      const float c1b = m3_ddot(tb, b);
+      const float c1b = m3_ddot(tb, p.B) + trtb;   // <taubar, b>
       const float Icb = c1b * e.mu * inv * inv;
       // b = F F^T: dF <- 2 bbar F with bbar = c1 sym(taubar); I_C: dF <- 2 Icbar F
       Fbar = m3_add(Fbar, m3_mul(m3_scale(tbs, 2.f * c1), F));
       Fbar = m3_axpy(Fbar, 2.f * Icb, F);
-      const float Jb = trtb * e.lam * (2.f * J - e.alpha_nh);
+      // d/dJ of lam J (J - 1) - 3/4 mu J
+      const float Jb = trtb * (e.lam * (2.f * J - 1.f) - 0.75f * e.mu);
       Fbar = m3_axpy(Fbar, Jb, m3_cof(F));
-      pb[PB_MU] += c1b * (1.f - inv) - trtb * 0.75f * J;
-      pb[PB_LAM] += trtb * J * (J - 1.f);
+      // d/dmu: (1 - 1/(I_C+1)) <taubar, b> - 3/4 J tr(taubar), the identity part regrouped as in the stress
+      pb[PB_MU] += m3_ddot(tb, p.B) * (3.f + t) * inv + trtb * (t * 0.25f * inv - 0.75f * Jm1);
+      pb[PB_LAM] += trtb * J * Jm1;
       return;
     }
     case MAT_COROTATED: {
-      float sg[3];
-      for (int i = 0; i < 3; ++i) sg[i] = sqrtf(fmaxf(p.s[i], 0.f));
+      float sg[3], hm = 0.f;
       const M3 G = m3_rotate_in(p.U, m3_sym(tb));
+      for (int i = 0; i < 3; ++i) {
+        float sm1;
+        sv_of(p.l[i], sg[i], sm1);
+        hm += G.m[i][i] * sg[i] * sm1;
+      }
       // h(s) = s - sqrt(s): divided difference 1 - 1/(sigma_i + sigma_j)
-      M3 H;
+      M3 Hd;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) H.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - 1.f / (sg[i] + sg[j]));
-      const M3 bbar = m3_rotate_out(p.U, H);
+        for (int j = 0; j < 3; ++j) Hd.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - 1.f / (sg[i] + sg[j]));
+      const M3 bbar = m3_rotate_out(p.U, Hd);
       Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
       Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));
-      float hm = 0.f;
-      for (int i = 0; i < 3; ++i) hm += G.m[i][i] * (p.s[i] - sg[i]);
       pb[PB_MU] += 2.f * hm;
-      pb[PB_LAM] += trtb * J * (J - 1.f);
+      pb[PB_LAM] += trtb * J * Jm1;
       return;
     }
     case MAT_VONMISES: {
-      float sc[3], ls[3];
-      for (int i = 0; i < 3; ++i) { sc[i] = fmaxf(p.s[i], kSigmaMin * kSigmaMin); ls[i] = logf(sc[i]); }
+      float lc[3], ls[3];
+      for (int i = 0; i < 3; ++i) { lc[i] = clamp_l(p.l[i]); ls[i] = log1pf(lc[i]); }
       const M3 G = m3_rotate_in(p.U, m3_sym(tb));
       M3 Bu;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Bu.m[i][j] = e.mu * G.m[i][j] * log_divdiff(sc[i], sc[j]);
-      for (int i = 0; i < 3; ++i) Bu.m[i][i] += e.lam * trtb * 0.5f / sc[i];
+        for (int j = 0; j < 3; ++j) Bu.m[i][j] = e.mu * G.m[i][j] * log1p_divdiff(lc[i], lc[j]);
+      for (int i = 0; i < 3; ++i) Bu.m[i][i] += e.lam * trtb * 0.5f / (1.f + lc[i]);
       const M3 bbar = m3_rotate_out(p.U, Bu);
       Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
       float gl = 0.f;
@@ -342,43 +386,45 @@ MD void stress_vjp_from(const EnvDev& e, const M3& F, const StressPrep& p, const
       return;
     }
     case MAT_FLUID_TAIT: {
-      const float Jg = powf(J, 1.f - e.gam);  // J^(1-gamma)
+      const float lJ = log1pf(Jm1);
+      const float Jg = J * expf(-e.gam * lJ);  // J^(1-gamma)
       const float dc = e.bulk * (1.f - (1.f - e.gam) * Jg / J);
       Fbar = m3_axpy(Fbar, trtb * dc, m3_cof(F));
-      pb[PB_K] += trtb * (J - Jg);
-      pb[PB_GAMMA] += trtb * e.bulk * Jg * logf(J);
+      pb[PB_K] += trtb * (-J * expm1f(-e.gam * lJ));   // J - J^(1-gamma)
+      pb[PB_GAMMA] += trtb * e.bulk * Jg * lJ;
       return;
     }
     default: {
       Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));
-      pb[PB_LAM] += trtb * J * (J - 1.f);
+      pb[PB_LAM] += trtb * J * Jm1;
       return;
     }
   }
 }
 
-MD void stress_vjp(const EnvDev& e, const M3& F, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
-  stress_vjp_from(e, F, stress_prep(e, F), tb, Fbar, pb);
+MD void stress_vjp(const EnvDev& e, const M3& H, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
+  stress_vjp_from(e, H, stress_prep(e, H), tb, Fbar, pb);
 }
 
 // --------------------------------------------------------------------------
-// a6: return mapping P(F_tr)
+// a6: return mapping P(F_tr), on H_tr = F_tr - I
 // --------------------------------------------------------------------------
 struct VMDecomp {   // shared by the projection and its VJP
   M3 U;
-  float s[3], eh[3], g[3];
+  float l[3];       // eigenvalues of F_tr F_tr^T - I, clamped at kSigmaMin^2 - 1
+  float eh[3], g[3];
   float nrm, beta;
   bool plastic;
 };
 
-MD VMDecomp vm_decompose(const EnvDev& e, const M3& Ftr) {
+MD VMDecomp vm_decompose(const EnvDev& e, const M3& Htr) {
   VMDecomp d;
-  const M3 b = m3_mul_abt(Ftr, Ftr);
-  eig_sym(b, d.s, d.U);
+  const M3 B = m3_add(m3_add(Htr, m3_transpose(Htr)), m3_mul_abt(Htr, Htr));
+  eig_sym(B, d.l, d.U);
   float eps[3];
   for (int i = 0; i < 3; ++i) {
-    d.s[i] = fmaxf(d.s[i], kSigmaMin * kSigmaMin);
-    eps[i] = 0.5f * logf(d.s[i]);
+    d.l[i] = clamp_l(d.l[i]);
+    eps[i] = 0.5f * log1pf(d.l[i]);
   }
   const float mean = (eps[0] + eps[1] + eps[2]) * (1.f / 3.f);
   for (int i = 0; i < 3; ++i) d.eh[i] = eps[i] - mean;
@@ -390,41 +436,46 @@ MD VMDecomp vm_decompose(const EnvDev& e, const M3& Ftr) {
   return d;
 }
 
-MD M3 project(const EnvDev& e, const M3& Ftr) {
+// returns H' = P(F_tr) - I
+MD M3 project(const EnvDev& e, const M3& Htr) {
   if (e.material == MAT_VONMISES) {
-    const VMDecomp d = vm_decompose(e, Ftr);
-    if (!d.plastic) return Ftr;
-    // U exp(eps - dgam eps_hat/|eps_hat|) V^T = U diag(exp(-beta eps_hat)) U^T F_tr
-    return m3_mul(m3_spectral(d.U, d.g), Ftr);
+    const VMDecomp d = vm_decompose(e, Htr);
+    if (!d.plastic) return Htr;
+    // U exp(eps - dgam eps_hat/|eps_hat|) V^T = U diag(g) U^T F_tr, g = exp(-beta eps_hat):
+    // H' = H_tr + U diag(g - 1) U^T F_tr
+    float gm1[3];
+    for (int i = 0; i < 3; ++i) gm1[i] = expm1f(-d.beta * d.eh[i]);
+    return m3_add(Htr, m3_mul(m3_spectral(d.U, gm1), f_of(Htr)));
   }
   if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
-    const float c = cbrtf(m3_det(Ftr));
+    const float c = expm1f(log1pf(det_minus_one(Htr)) * (1.f / 3.f));   // J^(1/3) - 1
     M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = c;
     return r;
   }
-  return Ftr;
+  return Htr;
 }
 
 // VJP of project(): returns Ftr_bar; pb[] += parameter cotangents
-MD M3 project_vjp(const EnvDev& e, const M3& Ftr, const M3& Fb, float pb[PB_COUNT]) {
+MD M3 project_vjp(const EnvDev& e, const M3& Htr, const M3& Fb, float pb[PB_COUNT]) {
   if (e.material == MAT_VONMISES) {
-    const VMDecomp d = vm_decompose(e, Ftr);
+    const VMDecomp d = vm_decompose(e, Htr);
     if (!d.plastic) return Fb;
+    const M3 Ftr = f_of(Htr);
     const M3 Mm = m3_spectral(d.U, d.g);
     M3 Ftb = m3_mul(Mm, Fb);                             // M symmetric: M^T Fbar'
     const M3 G = m3_rotate_in(d.U, m3_sym(m3_mul_abt(Fb, Ftr)));   // U^T sym(Mbar) U
     const float Y = e.yieldY, N = d.nrm, beta = d.beta;
-    // diagonal: dg_i/ds_k with g_i = exp(-beta eh_i), beta = 1 - Y/N
+    // diagonal: dg_i/ds_k with g_i = exp(-beta eh_i), beta = 1 - Y/N, s_k = 1 + l_k
     float S1 = 0.f, S2 = 0.f;
     for (int i = 0; i < 3; ++i) { S1 += G.m[i][i] * d.g[i] * d.eh[i]; S2 += G.m[i][i] * d.g[i]; }
     M3 Bu;
     for (int k = 0; k < 3; ++k)
-      Bu.m[k][k] = -(0.5f / d.s[k]) * (Y * d.eh[k] / (N * N * N) * S1 + beta * (G.m[k][k] * d.g[k] - S2 * (1.f / 3.f)));
+      Bu.m[k][k] = -(0.5f / (1.f + d.l[k])) * (Y * d.eh[k] / (N * N * N) * S1 + beta * (G.m[k][k] * d.g[k] - S2 * (1.f / 3.f)));
     // off-diagonal: (g_i - g_j)/(s_i - s_j) = [-beta e^{-beta eh_j} phi(-beta (eh_i - eh_j))] * (1/2) L(s_i, s_j)
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         if (i == j) continue;
-        const float dd = -beta * d.g[j] * expm1_over(-beta * (d.eh[i] - d.eh[j])) * 0.5f * log_divdiff(d.s[i], d.s[j]);
+        const float dd = -beta * d.g[j] * expm1_over(-beta * (d.eh[i] - d.eh[j])) * 0.5f * log1p_divdiff(d.l[i], d.l[j]);
         Bu.m[i][j] = G.m[i][j] * dd;
       }
     const M3 bbar = m3_rotate_out(d.U, Bu);
@@ -437,10 +488,11 @@ MD M3 project_vjp(const EnvDev& e, const M3& Ftr, const M3& Fb, float pb[PB_COUN
     return Ftb;
   }
   if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
-    const float J = m3_det(Ftr);
-    const float c = cbrtf(J);
+    const float Jm1 = det_minus_one(Htr);
+    const float J = 1.f + Jm1;
+    const float c = expf(log1pf(Jm1) * (1.f / 3.f));
     const float k = m3_trace(Fb) * c / (3.f * J);   // d J^(1/3)/dJ = J^(1/3)/(3J)
-    return m3_scale(m3_cof(Ftr), k);
+    return m3_scale(m3_cof(f_of(Htr)), k);
   }
   return Fb;
 }

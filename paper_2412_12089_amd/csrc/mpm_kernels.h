@@ -29,7 +29,7 @@ void launch_finalize_params(const EnvDev* envs, const double* acc, double* out, 
 void launch_load_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* x, const float* v,
                      const float* C, const float* F, float* st, int64_t N, int32_t* ids, hipStream_t s);
 void launch_store_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* st, int64_t N,
-                      const int32_t* ids, float* x, float* v, float* C, float* F, hipStream_t s);
+                      const int32_t* ids, float* x, float* v, float* C, float* F, bool state, hipStream_t s);
 void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
                        const float* C, const float* F, const int32_t* ids, float* st, int64_t N, hipStream_t s);
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);

@@ -10,9 +10,10 @@ namespace mpmx {
 
 // ----------------------------------------------------------------------------
 // state access: SoA, component c of particle p at st[c * N + p]
-// components: x 0-2, v 3-5, C 6-14 (row-major), F 15-23
+// components: x 0-2, v 3-5, C 6-14 (row-major), H = F - I 15-23 (F at the
+// boundary; the conversion happens in the AoS load/store kernels)
 // ----------------------------------------------------------------------------
-struct PState { float x[3], v[3]; M3 C, F; };
+struct PState { float x[3], v[3]; M3 C, H; };
 
 MD void load_x(const float* __restrict__ st, int64_t N, int64_t p, float x[3]) {
   x[0] = st[p]; x[1] = st[N + p]; x[2] = st[2 * N + p];
@@ -36,13 +37,13 @@ MD PState load_state(const float* __restrict__ st, int64_t N, int64_t p) {
   PState s;
   for (int a = 0; a < 3; ++a) { s.x[a] = st[a * N + p]; s.v[a] = st[(3 + a) * N + p]; }
   s.C = load_m3(st, N, p, 6);
-  s.F = load_m3(st, N, p, 15);
+  s.H = load_m3(st, N, p, 15);
   return s;
 }
 MD void store_state(float* __restrict__ st, int64_t N, int64_t p, const PState& s) {
   for (int a = 0; a < 3; ++a) { st[a * N + p] = s.x[a]; st[(3 + a) * N + p] = s.v[a]; }
   store_m3(st, N, p, 6, s.C);
-  store_m3(st, N, p, 15, s.F);
+  store_m3(st, N, p, 15, s.H);
 }
 
 // ----------------------------------------------------------------------------
@@ -91,6 +92,8 @@ __global__ void k_finalize_params(const EnvDev* envs, const double* acc, double*
 
 // ----------------------------------------------------------------------------
 // layout conversion between the caller's AoS arrays and the internal SoA.
+// States cross as F and are held as H = F - I; cotangents are the same for F
+// and H and cross unchanged.
 // Launched over work items; `all` selects rows in the concatenation of every
 // env (row_off + local index) or the env's own rows (local index). ids[p]
 // holds the env-local caller index of the particle at position p (-1: none).
@@ -112,7 +115,7 @@ __global__ void k_load_aos(const WorkItem* __restrict__ items, const EnvDev* __r
   }
   for (int k = 0; k < 9; ++k) {
     st[(6 + k) * N + p] = C[9 * i + k];
-    st[(15 + k) * N + p] = F[9 * i + k];
+    st[(15 + k) * N + p] = F[9 * i + k] - ((k & 3) == 0 ? 1.f : 0.f);   // exact for diagonals in [0.5, 2]
   }
   ids[p] = (int32_t)local;
 }
@@ -120,7 +123,7 @@ __global__ void k_load_aos(const WorkItem* __restrict__ items, const EnvDev* __r
 __global__ void k_store_aos(const WorkItem* __restrict__ items, const EnvDev* __restrict__ envs, int all,
                             const float* __restrict__ st, int64_t N, const int32_t* __restrict__ ids,
                             float* __restrict__ x, float* __restrict__ v, float* __restrict__ C,
-                            float* __restrict__ F) {
+                            float* __restrict__ F, float f_shift) {
   const WorkItem it = items[blockIdx.x];
   const int t = threadIdx.x;
   if (t >= it.count) return;
@@ -135,7 +138,7 @@ __global__ void k_store_aos(const WorkItem* __restrict__ items, const EnvDev* __
   }
   for (int k = 0; k < 9; ++k) {
     if (C) C[9 * r + k] = st[(6 + k) * N + p];
-    if (F) F[9 * r + k] = st[(15 + k) * N + p];
+    if (F) F[9 * r + k] = st[(15 + k) * N + p] + ((k & 3) == 0 ? f_shift : 0.f);
   }
 }
 
@@ -379,7 +382,7 @@ __global__ void __launch_bounds__(256) k_p2g_direct(const float* __restrict__ st
   const PState s = load_state(st, N, p);
   const Stencil sc = make_stencil(s.x, e.n, e.fn);
   if (sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
-  const M3 tau = stress(e, s.F);
+  const M3 tau = stress(e, s.H);
   const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
   const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
   mark_tiles(e, sc.b, flags);
@@ -591,7 +594,7 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
   const int64_t p = it.start + threadIdx.x;
   float x[3];
   load_x(st, N, p, x);
-  const M3 F = load_m3(st, N, p, 15);
+  const M3 H = load_m3(st, N, p, 15);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   float vn[3] = {0.f, 0.f, 0.f};
   M3 Cn = m3_zero();
@@ -618,12 +621,11 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
   PState s;
   for (int a = 0; a < 3; ++a) { s.x[a] = fmaf(e.dt, vn[a], x[a]); s.v[a] = vn[a]; }
   s.C = Cn;
-  const M3 Ftr = m3_mul(m3_axpy(m3_eye(), e.dt, Cn), F);
-  s.F = project(e, Ftr);
+  s.H = project(e, trial_h(e, Cn, H));
   store_state(out, N, p, s);
   bool fin = true;
   for (int a = 0; a < 3; ++a) fin = fin && isfinite(s.x[a]) && isfinite(s.v[a]);
-  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(s.F.m[i][j]);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(s.H.m[i][j]);
   if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
 }
 
@@ -668,19 +670,20 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restr
     const int64_t p = it.start + threadIdx.x;
     float x[3];
     load_x(st, N, p, x);
-    const M3 F = load_m3(st, N, p, 15);
+    const M3 H = load_m3(st, N, p, 15);
+    const M3 F = f_of(H);
     const Stencil sc = make_stencil(x, e.n, e.fn);
     const float D4 = 4.f * e.fn * e.fn;
     // C' of the substep's output state, read from the tape (the forward's own value)
     const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
-    const M3 Ftr = m3_mul(G, F);
+    const M3 Htr = trial_h(e, Cn, H);
     // incoming cotangents of (x', v', C', F')
     float xb[3], vb[3];
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = load_m3(cot, N, p, 6);
     const M3 Fb_in = load_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Ftr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));  // C' enters F_tr = (I + dt C') F
     const M3 Fb = m3_mul_atb(G, Ftrb);
     // pass 2: scatter to grid, accumulate dx
@@ -738,7 +741,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     const int64_t p = it.start + threadIdx.x;
     const PState s = load_state(st, N, p);
     const Stencil sc = make_stencil(s.x, e.n, e.fn);
-    const StressPrep spr = stress_prep(e, s.F);
+    const StressPrep spr = stress_prep(e, s.H);
     const M3 tau = stress_from(e, spr);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
@@ -780,7 +783,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = load_m3(part, N, p, 3);
-    stress_vjp_from(e, s.F, spr, taub, Fb, pb);
+    stress_vjp_from(e, s.H, spr, taub, Fb, pb);
     for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
     store_m3(cot_out, N, p, 6, Cb);
     store_m3(cot_out, N, p, 15, Fb);
@@ -805,9 +808,10 @@ void launch_load_aos(const WorkItem* items, int n_items, const EnvDev* envs, int
   hipLaunchKernelGGL(k_load_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, all, x, v, C, F, st, N, ids);
 }
 void launch_store_aos(const WorkItem* items, int n_items, const EnvDev* envs, int all, const float* st, int64_t N,
-                      const int32_t* ids, float* x, float* v, float* C, float* F, hipStream_t s) {
+                      const int32_t* ids, float* x, float* v, float* C, float* F, bool state, hipStream_t s) {
   if (n_items == 0) return;
-  hipLaunchKernelGGL(k_store_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, all, st, N, ids, x, v, C, F);
+  hipLaunchKernelGGL(k_store_aos, dim3(n_items), dim3(kItemSize), 0, s, items, envs, all, st, N, ids, x, v, C, F,
+                     state ? 1.f : 0.f);
 }
 void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
                        const float* C, const float* F, const int32_t* ids, float* st, int64_t N, hipStream_t s) {

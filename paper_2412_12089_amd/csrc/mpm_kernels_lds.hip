@@ -256,8 +256,8 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
   if (valid) {
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 F = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, F);
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 tau = stress(e, H);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     float mv0[3];
@@ -334,7 +334,7 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   if (bx.fits) box_load(e, bx, bsh, grid, 4, 3, lds);
   __syncthreads();
   if (!valid) return;
-  const M3 F = ld_m3(st, N, p, 15);
+  const M3 H = ld_m3(st, N, p, 15);
   float vn[3] = {0.f, 0.f, 0.f};
   M3 Cn = m3_zero();
 #pragma unroll 1
@@ -364,13 +364,13 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
   float xn[3];
   for (int a = 0; a < 3; ++a) xn[a] = fmaf(e.dt, vn[a], x[a]);
-  const M3 Fn = project(e, m3_mul(m3_axpy(m3_eye(), e.dt, Cn), F));
+  const M3 Hn = project(e, trial_h(e, Cn, H));
   for (int a = 0; a < 3; ++a) { out[a * N + p] = xn[a]; out[(3 + a) * N + p] = vn[a]; }
   st_m3(out, N, p, 6, Cn);
-  st_m3(out, N, p, 15, Fn);
+  st_m3(out, N, p, 15, Hn);
   bool fin = true;
   for (int a = 0; a < 3; ++a) fin = fin && isfinite(xn[a]) && isfinite(vn[a]);
-  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(Fn.m[i][j]);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(Hn.m[i][j]);
   if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
 }
 
@@ -419,17 +419,18 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
   __syncthreads();
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
-    const M3 F = ld_m3(st, N, p, 15);
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 F = f_of(H);
     const float D4 = 4.f * e.fn * e.fn;
     // C' of the substep's output state, read from the tape (the forward's own value)
     const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
-    const M3 Ftr = m3_mul(G, F);
+    const M3 Htr = trial_h(e, Cn, H);
     float xb[3], vb[3];
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = ld_m3(cot, N, p, 6);
     const M3 Fb_in = ld_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Ftr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
 #pragma unroll 1
@@ -527,8 +528,8 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
   if (valid) {
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 F = ld_m3(st, N, p, 15);
-    const StressPrep spr = stress_prep(e, F);
+    const M3 H = ld_m3(st, N, p, 15);
+    const StressPrep spr = stress_prep(e, H);
     const M3 tau = stress_from(e, spr);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
@@ -579,7 +580,7 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = ld_m3(part, N, p, 3);
-    stress_vjp_from(e, F, spr, taub, Fb, pb);
+    stress_vjp_from(e, H, spr, taub, Fb, pb);
     for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
     st_m3(cot_out, N, p, 6, Cb);
     st_m3(cot_out, N, p, 15, Fb);
@@ -742,8 +743,8 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
   if (valid) {
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 F = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, F);
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 tau = stress(e, H);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     if (seg_mode) {
@@ -850,17 +851,18 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   __syncthreads();
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
-    const M3 F = ld_m3(st, N, p, 15);
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 F = f_of(H);
     const float D4 = 4.f * e.fn * e.fn;
     // C' of the substep's output state, read from the tape (the forward's own value)
     const M3 Cn = load_cnext(st_next, N, p);
     const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
-    const M3 Ftr = m3_mul(G, F);
+    const M3 Htr = trial_h(e, Cn, H);
     float xb[3], vb[3];
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = ld_m3(cot, N, p, 6);
     const M3 Fb_in = ld_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Ftr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
     if (seg_mode) {

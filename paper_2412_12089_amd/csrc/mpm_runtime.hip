@@ -605,7 +605,7 @@ int mpm_get_particles(mpm_batch* b, int32_t env, float* x, float* v, float* C, f
   if (rc) return rc;
   const int i0 = env < 0 ? 0 : b->item_off[env];
   const int ni = env < 0 ? (int)b->items_h.size() : b->item_off[env + 1] - b->item_off[env];
-  launch_store_aos(b->items_d + i0, ni, b->envs_d, env < 0 ? 1 : 0, b->cur, b->N, b->ids_cur, x, v, C, F, b->stream);
+  launch_store_aos(b->items_d + i0, ni, b->envs_d, env < 0 ? 1 : 0, b->cur, b->N, b->ids_cur, x, v, C, F, true, b->stream);
   HIPC(b, hipGetLastError());
   return MPM_OK;
 }
@@ -755,7 +755,7 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
     for (int k = 1; k <= Kj; ++k) b->grid_dirty[k] = false;
   }
   b->last_seg_taped = false;
-  launch_store_aos(b->items_d, (int)b->items_h.size(), b->envs_d, 1, b->cot[c], b->N, b->ids_start, dx0, dv0, dC0, dF0, s);
+  launch_store_aos(b->items_d, (int)b->items_h.size(), b->envs_d, 1, b->cot[c], b->N, b->ids_start, dx0, dv0, dC0, dF0, false, s);
   if (dparams) launch_finalize_params(b->envs_d, b->pacc, dparams, b->E, s);
   HIPC(b, hipGetLastError());
   return MPM_OK;

@@ -63,6 +63,10 @@ def check_env(st, gr, dp, offs, i, o, tag, params=(0,), tol_v=1e-5):
         announce(f"{tag}: grad x {e[0]:.2e} v {e[1]:.2e} C {e[2]:.2e} F {e[3]:.2e}")
         assert max(e) < 1e-3
         for k in params:
+            if o["dparams"][k] == 0.0:   # e.g. no particle yielded: the sigma_y cotangent is exactly zero
+                announce(f"{tag}: dparam[{k}] {dp[i][k]:.6e} vs exact 0")
+                assert dp[i][k] == 0.0
+                continue
             r = abs(dp[i][k] - o["dparams"][k]) / abs(o["dparams"][k])
             announce(f"{tag}: dparam[{k}] {dp[i][k]:.6e} vs {o['dparams'][k]:.6e} rel {r:.2e}")
             assert r < 1e-3
@@ -115,18 +119,32 @@ def test_dam_break_full_size():
     announce(f"dam_break: {len(wl.envs)} envs x {wl.envs[0].n_particles}, {wl.substeps} substeps, K={wl.ckpt_every}")
     st, gr, dp, status, offs = run_workload(wl)
     assert status == 0
-    # properties of the full run: finite, inside the walls, fluid F stays J^(1/3) I with J near 1,
-    # the column spreads along +x once the gate withdraws
+    # properties of the full run: finite, inside the walls, fluid F stays J^(1/3) I with J near 1
     for a in st + gr:
         assert np.isfinite(a).all()
-    x, F = st[0], st[3]
-    b = scenes.WALL / wl.envs[0].n
+    x, v, F = st[0], st[1], st[3]
+    n = wl.envs[0].n
+    dx = 1.0 / n
+    b = scenes.WALL * dx
     assert (x > b * 0.5).all() and (x < 1 - b * 0.5).all()
     J = np.linalg.det(F)
     assert (J > 0.8).all() and (J < 1.2).all()
     assert np.abs(F - np.cbrt(J)[:, None, None] * np.eye(3)).max() < 1e-5
+    # closed form: the compression wave from the floor travels sqrt(K/rho) t (a few mm in the
+    # 2 ms simulated), so the column's upper interior, away from the walls and the gate, is
+    # still in free fall at rest relative to itself: v = g t exactly in the method (a uniform
+    # velocity field is transferred exactly by APIC and J stays 1, so the pressure is zero)
     x0 = np.concatenate([e.x for e in wl.envs])
-    assert x[:, 0].max() > x0[:, 0].max()
+    t = wl.substeps * wl.envs[0].dt
+    vz = -9.8 * t
+    m = 10 * dx
+    sel = ((x0[:, 0] > x0[:, 0].min() + m) & (x0[:, 0] < x0[:, 0].max() - m) & (x0[:, 1] > x0[:, 1].min() + m)
+           & (x0[:, 1] < x0[:, 1].max() - m) & (x0[:, 2] > x0[:, 2].min() + 0.3) & (x0[:, 2] < x0[:, 2].max() - m))
+    announce(f"free-fall check on {int(sel.sum())} particles: v_z {v[sel, 2].min():.6e}..{v[sel, 2].max():.6e} "
+             f"vs {vz:.6e}, |v_xy| max {np.abs(v[sel, :2]).max():.2e}")
+    assert sel.sum() > 100000
+    assert np.abs(v[sel, 2] - vz).max() < 1e-3 * abs(vz)
+    assert np.abs(v[sel, :2]).max() < 1e-3 * abs(vz)
     # full-size short horizon against the oracle (env 0, 8 substeps, forward)
     S = 8
     st8, _, _, status8, offs8 = run_workload(wl, S=S, backward=False, tune=False)

@@ -185,6 +185,11 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
                                   grid of this many blocks striding over the work items */
 #define MPM_OPT_MAX_RUN 8      /* per-cell-run variants cut a run of one stencil base every this many particles
                                   (default 8) */
+#define MPM_OPT_BOX 9          /* LDS-staged kernels' box budget: 0 = 1024 grid nodes per block (default),
+                                  1 = 384 nodes (less LDS, more blocks per CU; a block whose box is larger
+                                  falls back to global atomics) */
+#define MPM_OPT_SPECIALIZE 10  /* LDS-staged kernels: 1 = one launch per material over that material's work items,
+                                  compiled for it (default); 0 = one launch over all items, material read at run time */
 
 /* Sets one option; INVALID_ARG for an unknown option or value. */
 int mpm_set_option(mpm_batch* b, int32_t option, int32_t value);

@@ -36,7 +36,7 @@ EXPORTED = (
     "mpm_memory_bytes", "mpm_kernel_time", "mpm_set_timing", "mpm_last_error", "mpm_version", "mpm_sort_keys",
     "mpm_set_option", "mpm_get_option", "mpm_forward_envs", "mpm_configure_env",
 )
-OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN = 1, 2, 3, 4, 5, 6, 7, 8
+OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 
 class mpm_env_desc(ctypes.Structure):

@@ -18,7 +18,7 @@ namespace mpmx {
 
 #define MD __device__ __forceinline__
 
-enum : int { MAT_NEOHOOKEAN = 0, MAT_COROTATED = 1, MAT_VONMISES = 2, MAT_FLUID_TAIT = 3, MAT_FLUID_PAPER = 4 };
+enum : int { MAT_NEOHOOKEAN = 0, MAT_COROTATED = 1, MAT_VONMISES = 2, MAT_FLUID_TAIT = 3, MAT_FLUID_PAPER = 4, MAT_COUNT = 5 };
 enum : int { ERR_NONFINITE = 1, ERR_OUT_OF_DOMAIN = 2 };
 // slots of the per-env parameter-cotangent accumulator (FP64)
 enum : int { PB_MU = 0, PB_LAM, PB_SY, PB_K, PB_GAMMA, PB_MP, PB_VP, PB_COUNT };
@@ -244,6 +244,8 @@ MD float log1p_divdiff(float a, float b) {
 // --------------------------------------------------------------------------
 // a3: Kirchhoff stress tau = P F^T
 // --------------------------------------------------------------------------
+// `mat` is the material (a compile-time constant in the specialized
+// kernels, e.material elsewhere).
 // Quantities of F shared by the stress and its VJP (one eigen-decomposition
 // of B = F F^T - I serves both in the P2G adjoint).
 struct StressPrep {
@@ -252,13 +254,26 @@ struct StressPrep {
   float J, Jm1; // det F and det F - 1
 };
 
-MD StressPrep stress_prep(const EnvDev& e, const M3& H) {
+MD StressPrep stress_prep(const EnvDev& e, const M3& H, int mat) {
   StressPrep p;
   p.Jm1 = det_minus_one(H);
   p.J = 1.f + p.Jm1;
-  if (e.material == MAT_NEOHOOKEAN || e.material == MAT_COROTATED || e.material == MAT_VONMISES)
+  if (mat == MAT_NEOHOOKEAN || mat == MAT_COROTATED || mat == MAT_VONMISES)
     p.B = m3_add(m3_add(H, m3_transpose(H)), m3_mul_abt(H, H));
-  if (e.material == MAT_COROTATED || e.material == MAT_VONMISES) eig_sym(p.B, p.l, p.U);
+  if (mat == MAT_COROTATED || mat == MAT_VONMISES) eig_sym(p.B, p.l, p.U);
+  return p;
+}
+
+// the same quantities with the eigen-decomposition of B supplied (U, l kept
+// from an earlier stress_prep of the same H)
+MD StressPrep stress_prep_with_eig(const M3& H, const M3& U, const float l[3], int mat) {
+  StressPrep p;
+  p.Jm1 = det_minus_one(H);
+  p.J = 1.f + p.Jm1;
+  if (mat == MAT_NEOHOOKEAN || mat == MAT_COROTATED || mat == MAT_VONMISES)
+    p.B = m3_add(m3_add(H, m3_transpose(H)), m3_mul_abt(H, H));
+  p.U = U;
+  for (int i = 0; i < 3; ++i) p.l[i] = l[i];
   return p;
 }
 
@@ -272,9 +287,9 @@ MD void sv_of(float l, float& s, float& sm1) {
 MD float log_strain(float l) { return 0.5f * log1pf(fmaxf(l, kSigmaMin * kSigmaMin - 1.f)); }
 MD float clamp_l(float l) { return fmaxf(l, kSigmaMin * kSigmaMin - 1.f); }
 
-MD M3 stress_from(const EnvDev& e, const StressPrep& p) {
+MD M3 stress_from(const EnvDev& e, const StressPrep& p, int mat) {
   const float J = p.J, Jm1 = p.Jm1;
-  switch (e.material) {
+  switch (mat) {
     case MAT_NEOHOOKEAN: {
       // mu (1 - 1/(I_C + 1)) b + lam J (J - alpha) I with b = I + B, I_C = 3 + tr B and
       // alpha = 1 + 3 mu / (4 lam): the identity parts cancel at rest, so their sum is
@@ -323,15 +338,15 @@ MD M3 stress_from(const EnvDev& e, const StressPrep& p) {
 }
 
 // a3: Kirchhoff stress from H = F - I
-MD M3 stress(const EnvDev& e, const M3& H) { return stress_from(e, stress_prep(e, H)); }
+MD M3 stress(const EnvDev& e, const M3& H, int mat) { return stress_from(e, stress_prep(e, H, mat), mat); }
 
 // VJP of stress(): Fbar += d<taubar, tau>/dF, pb[] += d<taubar, tau>/d(params)
 MD void stress_vjp_from(const EnvDev& e, const M3& H, const StressPrep& p, const M3& tb, M3& Fbar,
-                        float pb[PB_COUNT]) {
+                        float pb[PB_COUNT], int mat) {
   const float J = p.J, Jm1 = p.Jm1;
   const float trtb = m3_trace(tb);
   const M3 F = f_of(H);
-  switch (e.material) {
+  switch (mat) {
     case MAT_NEOHOOKEAN: {
       const float t = m3_trace(p.B);
       const float inv = 1.f / (4.f + t);
@@ -402,8 +417,8 @@ MD void stress_vjp_from(const EnvDev& e, const M3& H, const StressPrep& p, const
   }
 }
 
-MD void stress_vjp(const EnvDev& e, const M3& H, const M3& tb, M3& Fbar, float pb[PB_COUNT]) {
-  stress_vjp_from(e, H, stress_prep(e, H), tb, Fbar, pb);
+MD void stress_vjp(const EnvDev& e, const M3& H, const M3& tb, M3& Fbar, float pb[PB_COUNT], int mat) {
+  stress_vjp_from(e, H, stress_prep(e, H, mat), tb, Fbar, pb, mat);
 }
 
 // --------------------------------------------------------------------------
@@ -437,8 +452,8 @@ MD VMDecomp vm_decompose(const EnvDev& e, const M3& Htr) {
 }
 
 // returns H' = P(F_tr) - I
-MD M3 project(const EnvDev& e, const M3& Htr) {
-  if (e.material == MAT_VONMISES) {
+MD M3 project(const EnvDev& e, const M3& Htr, int mat) {
+  if (mat == MAT_VONMISES) {
     const VMDecomp d = vm_decompose(e, Htr);
     if (!d.plastic) return Htr;
     // U exp(eps - dgam eps_hat/|eps_hat|) V^T = U diag(g) U^T F_tr, g = exp(-beta eps_hat):
@@ -447,7 +462,7 @@ MD M3 project(const EnvDev& e, const M3& Htr) {
     for (int i = 0; i < 3; ++i) gm1[i] = expm1f(-d.beta * d.eh[i]);
     return m3_add(Htr, m3_mul(m3_spectral(d.U, gm1), f_of(Htr)));
   }
-  if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
+  if (mat == MAT_FLUID_TAIT || mat == MAT_FLUID_PAPER) {
     const float c = expm1f(log1pf(det_minus_one(Htr)) * (1.f / 3.f));   // J^(1/3) - 1
     M3 r = m3_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = c;
     return r;
@@ -456,8 +471,8 @@ MD M3 project(const EnvDev& e, const M3& Htr) {
 }
 
 // VJP of project(): returns Ftr_bar; pb[] += parameter cotangents
-MD M3 project_vjp(const EnvDev& e, const M3& Htr, const M3& Fb, float pb[PB_COUNT]) {
-  if (e.material == MAT_VONMISES) {
+MD M3 project_vjp(const EnvDev& e, const M3& Htr, const M3& Fb, float pb[PB_COUNT], int mat) {
+  if (mat == MAT_VONMISES) {
     const VMDecomp d = vm_decompose(e, Htr);
     if (!d.plastic) return Fb;
     const M3 Ftr = f_of(Htr);
@@ -487,7 +502,7 @@ MD M3 project_vjp(const EnvDev& e, const M3& Htr, const M3& Fb, float pb[PB_COUN
     pb[PB_SY] += Yb * (kYieldScale / (2.f * e.mu));
     return Ftb;
   }
-  if (e.material == MAT_FLUID_TAIT || e.material == MAT_FLUID_PAPER) {
+  if (mat == MAT_FLUID_TAIT || mat == MAT_FLUID_PAPER) {
     const float Jm1 = det_minus_one(Htr);
     const float J = 1.f + Jm1;
     const float c = expf(log1pf(Jm1) * (1.f / 3.f));

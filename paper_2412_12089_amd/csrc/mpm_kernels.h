@@ -60,24 +60,26 @@ void launch_g2p_adjoint_direct(const float* st, const float* st_next, const floa
 void launch_p2g_adjoint_direct(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
                                const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, hipStream_t s);
 
-// LDS-staged variants of the particle kernels (batched mode)
+// LDS-staged variants of the particle kernels (batched mode). Each launch
+// covers work items of one material `mat`, compiled for that material; `box`
+// picks the LDS box budget (0: 1024 nodes, 1: 384 nodes).
 void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
+                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s);
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int k_call, int grid_cap, hipStream_t s);
+                            int k_call, int grid_cap, int box, int mat, hipStream_t s);
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s);
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, int box, int mat, hipStream_t s);
 
 // segment-reduced scatters: runs = min_run | max_run << 16. Blocks whose
 // particles average at least min_run per run sum each run (cut at max_run
 // particles) in registers before the LDS atomics
 void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
-                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, hipStream_t s);
+                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int runs, int k_call, int grid_cap, hipStream_t s);
+                            int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 
 }  // namespace mpmx

@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(256) k_p2g_direct(const float* __restrict__ st
   const PState s = load_state(st, N, p);
   const Stencil sc = make_stencil(s.x, e.n, e.fn);
   if (sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
-  const M3 tau = stress(e, s.H);
+  const M3 tau = stress(e, s.H, e.material);
   const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
   const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
   mark_tiles(e, sc.b, flags);
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
   PState s;
   for (int a = 0; a < 3; ++a) { s.x[a] = fmaf(e.dt, vn[a], x[a]); s.v[a] = vn[a]; }
   s.C = Cn;
-  s.H = project(e, trial_h(e, Cn, H));
+  s.H = project(e, trial_h(e, Cn, H), e.material);
   store_state(out, N, p, s);
   bool fin = true;
   for (int a = 0; a < 3; ++a) fin = fin && isfinite(s.x[a]) && isfinite(s.v[a]);
@@ -683,7 +683,7 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_direct(const float* __restr
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = load_m3(cot, N, p, 6);
     const M3 Fb_in = load_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb, e.material);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));  // C' enters F_tr = (I + dt C') F
     const M3 Fb = m3_mul_atb(G, Ftrb);
     // pass 2: scatter to grid, accumulate dx
@@ -741,8 +741,8 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     const int64_t p = it.start + threadIdx.x;
     const PState s = load_state(st, N, p);
     const Stencil sc = make_stencil(s.x, e.n, e.fn);
-    const StressPrep spr = stress_prep(e, s.H);
-    const M3 tau = stress_from(e, spr);
+    const StressPrep spr = stress_prep(e, s.H, e.material);
+    const M3 tau = stress_from(e, spr, e.material);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(s.C, e.mp), kf, tau);
     float xb[3] = {part[p], part[N + p], part[2 * N + p]};
@@ -783,7 +783,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_direct(const float* __restr
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = load_m3(part, N, p, 3);
-    stress_vjp_from(e, s.H, spr, taub, Fb, pb);
+    stress_vjp_from(e, s.H, spr, taub, Fb, pb, e.material);
     for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
     store_m3(cot_out, N, p, 6, Cb);
     store_m3(cot_out, N, p, 15, Fb);

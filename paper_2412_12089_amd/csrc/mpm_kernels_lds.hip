@@ -17,7 +17,8 @@
 
 namespace mpmx {
 
-constexpr int kBoxNodes = 1024;   // LDS budget in nodes per block
+constexpr int kBoxNodes = 1024;   // LDS budget in nodes per block (large-box variant)
+constexpr int kBoxSmall = 384;    // small-box variant: less LDS per block, more blocks per CU
 constexpr int kMaxRuns = 4;       // tile-row runs per block that get their own box
 
 // A block's particles are contiguous in (tile, cell) order, so they fall into a
@@ -47,6 +48,7 @@ struct Box {
 };
 
 // every thread must call it; lp = this thread's particle index in the item
+template <int BOXN>
 MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count, BoxShared& bs) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < 256) bs.rk[lp] = valid ? ((b[0] >> 2) * e.T + (b[1] >> 2)) : -1;
@@ -98,7 +100,7 @@ MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count,
   Box bx;
   const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
   bx.nodes = bs.off[nr];
-  bx.fits = nruns >= 1 && nruns <= kMaxRuns && bx.nodes <= kBoxNodes;
+  bx.fits = nruns >= 1 && nruns <= kMaxRuns && bx.nodes <= BOXN;
   bx.run = r;
   const int rr = r < kMaxRuns ? r : 0;
   for (int a = 0; a < 3; ++a) bx.lo[a] = bs.lo[rr][a];
@@ -233,14 +235,16 @@ MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
 // ----------------------------------------------------------------------------
 // P2G
 // ----------------------------------------------------------------------------
+template <int BOXN, int MAT>
 MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int k_call) {
-  __shared__ float lds[4 * kBoxNodes];
+  __shared__ float lds[4 * BOXN];
   __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int lp = lane_particle(threadIdx.x);
   const bool valid = lp < it.count;
@@ -249,7 +253,7 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
-  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits)
     for (int i = threadIdx.x; i < 4 * bx.nodes; i += blockDim.x) lds[i] = 0.f;
   __syncthreads();
@@ -257,7 +261,7 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
     const M3 H = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, H);
+    const M3 tau = stress(e, H, mat);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     float mv0[3];
@@ -292,31 +296,33 @@ MD void p2g_lds_item(int item_idx, const float* __restrict__ st, int64_t N,
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int k_call, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      p2g_lds_item(i, st, N, envs, items, grid, flags, errs, k_call);
+      p2g_lds_item<BOXN, MAT>(i, st, N, envs, items, grid, flags, errs, k_call);
       __syncthreads();
     }
   } else {
-    p2g_lds_item(blockIdx.x, st, N, envs, items, grid, flags, errs, k_call);
+    p2g_lds_item<BOXN, MAT>(blockIdx.x, st, N, envs, items, grid, flags, errs, k_call);
   }
 }
 
 // ----------------------------------------------------------------------------
 // G2P
 // ----------------------------------------------------------------------------
+template <int BOXN, int MAT>
 MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restrict__ out, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call) {
-  __shared__ float lds[3 * kBoxNodes];
+  __shared__ float lds[3 * BOXN];
   __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) {   // frozen env: the substep is the identity
     if ((int)threadIdx.x < it.count) {
       const int64_t q = it.start + threadIdx.x;
@@ -330,7 +336,7 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits) box_load(e, bx, bsh, grid, 4, 3, lds);
   __syncthreads();
   if (!valid) return;
@@ -364,7 +370,7 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
   Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
   float xn[3];
   for (int a = 0; a < 3; ++a) xn[a] = fmaf(e.dt, vn[a], x[a]);
-  const M3 Hn = project(e, trial_h(e, Cn, H));
+  const M3 Hn = project(e, trial_h(e, Cn, H), mat);
   for (int a = 0; a < 3; ++a) { out[a * N + p] = xn[a]; out[(3 + a) * N + p] = vn[a]; }
   st_m3(out, N, p, 6, Cn);
   st_m3(out, N, p, 15, Hn);
@@ -375,23 +381,24 @@ MD void g2p_lds_item(int item_idx, const float* __restrict__ st, float* __restri
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_g2p_lds(const float* __restrict__ st, float* __restrict__ out, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  const float* __restrict__ grid, int32_t* __restrict__ errs, int k_call, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      g2p_lds_item(i, st, out, N, envs, items, grid, errs, k_call);
+      g2p_lds_item<BOXN, MAT>(i, st, out, N, envs, items, grid, errs, k_call);
       __syncthreads();
     }
   } else {
-    g2p_lds_item(blockIdx.x, st, out, N, envs, items, grid, errs, k_call);
+    g2p_lds_item<BOXN, MAT>(blockIdx.x, st, out, N, envs, items, grid, errs, k_call);
   }
 }
 
 // ----------------------------------------------------------------------------
 // G2P adjoint: gather v from an LDS copy, scatter vbar into LDS, flush
 // ----------------------------------------------------------------------------
+template <int BOXN, int MAT>
 MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
     const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
@@ -399,11 +406,12 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ grid, float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int k_call) {
-  __shared__ float lv[3 * kBoxNodes];
-  __shared__ float lg[3 * kBoxNodes];
+  __shared__ float lv[3 * BOXN];
+  __shared__ float lg[3 * BOXN];
   __shared__ BoxShared bsh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int lp = lane_particle(threadIdx.x);
   const bool valid = lp < it.count;
@@ -411,7 +419,7 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits) {
     box_load(e, bx, bsh, grid, 4, 3, lv);
     for (int i = threadIdx.x; i < 3 * bx.nodes; i += blockDim.x) lg[i] = 0.f;
@@ -430,18 +438,19 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = ld_m3(cot, N, p, 6);
     const M3 Fb_in = ld_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb, mat);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
+    st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
+#pragma unroll 1
       for (int oy = 0; oy < 3; ++oy)
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sc.w[1][oy], wz = sc.w[2][oz];
+          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
           const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sc.dw[1][oy] * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
           const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
           float vi[3], gv[3];
           for (int a = 0; a < 3; ++a)
@@ -466,7 +475,6 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
           }
         }
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
-    st_m3(part, N, p, 3, Fb);
   }
   if (bx.fits) {
     __syncthreads();
@@ -476,7 +484,7 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict__ st, const float* __restrict__ st_next,
     const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
@@ -486,17 +494,18 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict
                                                          double* __restrict__ pacc, int k_call, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      g2p_adjoint_lds_item(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+      g2p_adjoint_lds_item<BOXN, MAT>(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
       __syncthreads();
     }
   } else {
-    g2p_adjoint_lds_item(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+    g2p_adjoint_lds_item<BOXN, MAT>(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
   }
 }
 
 // ----------------------------------------------------------------------------
 // P2G adjoint: gather (mbar, Pbar) from an LDS copy
 // ----------------------------------------------------------------------------
+template <int BOXN, int MAT>
 MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
                                                          const float* __restrict__ part,
                                                          float* __restrict__ cot_out, int64_t N,
@@ -504,10 +513,13 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
                                                          const WorkItem* __restrict__ items,
                                                          const float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in) {
-  __shared__ float lds[4 * kBoxNodes];
+  constexpr bool kEig = MAT == MAT_COROTATED || MAT == MAT_VONMISES || MAT < 0;
+  __shared__ float lds[4 * BOXN];
   __shared__ BoxShared bsh;
+  __shared__ float eig_keep[kEig ? 12 : 1][256];   // U and the eigenvalues of B, per thread
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) {   // frozen env: the cotangent passes through
     if ((int)threadIdx.x < it.count) {
       const int64_t q = it.start + threadIdx.x;
@@ -515,37 +527,48 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
     }
     return;
   }
-  const int lp = lane_particle(threadIdx.x);
+  const int t = threadIdx.x;
+  const int lp = lane_particle(t);
   const bool valid = lp < it.count;
   const int64_t p = it.start + (valid ? lp : 0);
   float x[3];
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
-  const Box bx = block_box(e, sc.b, valid, lp, it.count, bsh);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
   if (bx.fits) box_load(e, bx, bsh, gcot, 3, 4, lds);
   __syncthreads();
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
-    float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
-    const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 H = ld_m3(st, N, p, 15);
-    const StressPrep spr = stress_prep(e, H);
-    const M3 tau = stress_from(e, spr);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
-    const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
+    const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
+    // only A and v stay live through the stencil loop; C, H and the stress
+    // are read or rebuilt after it
+    M3 A;
+    {
+      const M3 Cm = ld_m3(st, N, p, 6);
+      const M3 H = ld_m3(st, N, p, 15);
+      const StressPrep spr = stress_prep(e, H, mat);
+      A = m3_axpy(m3_scale(Cm, e.mp), kf, stress_from(e, spr, mat));
+      if (kEig && (mat == MAT_COROTATED || mat == MAT_VONMISES)) {
+        for (int i = 0; i < 3; ++i) {
+          eig_keep[9 + i][t] = spr.l[i];
+          for (int j = 0; j < 3; ++j) eig_keep[3 * i + j][t] = spr.U.m[i][j];
+        }
+      }
+    }
     float xb[3] = {part[p], part[N + p], part[2 * N + p]};
-    float vb[3] = {0.f, 0.f, 0.f};
-    M3 Ab = m3_zero();
-    float mpb = 0.f;
+    float sP[3] = {0.f, 0.f, 0.f};   // sum of W Pbar
+    float sm = 0.f;                  // sum of W mbar
+    M3 Ab = m3_zero();               // sum of W Pbar d^T
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
       for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
+#pragma unroll 1
+        for (int oz = 0; oz < 3; ++oz) {   // rolled: the register budget, not issue, limits this kernel
+          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sel3(sc.w[2], oz);
           const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sel3(sc.dw[2], oz)};
           const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
           float mb, Pb[3];
           if (bx.fits) {
@@ -557,39 +580,51 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
             mb = gc[3 * CH];
             for (int a = 0; a < 3; ++a) Pb[a] = gc[(4 + a) * CH];
           }
-          float mom[3], vcd[3];
+          float gw = e.mp * mb;
+          for (int a = 0; a < 3; ++a) gw += Pb[a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+          sm = fmaf(W, mb, sm);
           for (int a = 0; a < 3; ++a) {
-            const float Ad = A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2];
-            mom[a] = e.mp * v[a] + Ad;
-            vcd[a] = v[a] + Cm.m[a][0] * d[0] + Cm.m[a][1] * d[1] + Cm.m[a][2] * d[2];
-          }
-          const float gw = e.mp * mb + Pb[0] * mom[0] + Pb[1] * mom[1] + Pb[2] * mom[2];
-          for (int a = 0; a < 3; ++a) {
-            vb[a] = fmaf(e.mp * W, Pb[a], vb[a]);
             const float wp = W * Pb[a];
+            sP[a] += wp;
             Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
             Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
             Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
             const float atp = A.m[0][a] * Pb[0] + A.m[1][a] * Pb[1] + A.m[2][a] * Pb[2];
             xb[a] += gW[a] * gw - W * atp;
           }
-          mpb += W * (mb + Pb[0] * vcd[0] + Pb[1] * vcd[1] + Pb[2] * vcd[2]);
         }
-    const M3 Cb = m3_scale(Ab, e.mp);
+    const M3 Cm = ld_m3(st, N, p, 6);
+    const M3 H = ld_m3(st, N, p, 15);
+    StressPrep spr;
+    if (kEig && (mat == MAT_COROTATED || mat == MAT_VONMISES)) {
+      M3 U;
+      float l[3];
+      for (int i = 0; i < 3; ++i) {
+        l[i] = eig_keep[9 + i][t];
+        for (int j = 0; j < 3; ++j) U.m[i][j] = eig_keep[3 * i + j][t];
+      }
+      spr = stress_prep_with_eig(H, U, l, mat);
+    } else {
+      spr = stress_prep(e, H, mat);
+    }
+    const M3 tau = stress_from(e, spr, mat);
+    // m_p enters m_i (weight W) and P_i through m_p (v + C d): the C d part
+    // summed over the nodes is <C, sum W Pbar d^T>
+    const float mpb = sm + v[0] * sP[0] + v[1] * sP[1] + v[2] * sP[2] + m3_ddot(Cm, Ab);
+    for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = e.mp * sP[a]; }
+    st_m3(cot_out, N, p, 6, m3_scale(Ab, e.mp));
     const M3 taub = m3_scale(Ab, kf);
     pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
     pb[PB_MP] += mpb;
     M3 Fb = ld_m3(part, N, p, 3);
-    stress_vjp_from(e, H, spr, taub, Fb, pb);
-    for (int a = 0; a < 3; ++a) { cot_out[a * N + p] = xb[a]; cot_out[(3 + a) * N + p] = vb[a]; }
-    st_m3(cot_out, N, p, 6, Cb);
+    stress_vjp_from(e, H, spr, taub, Fb, pb, mat);
     st_m3(cot_out, N, p, 15, Fb);
   }
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict__ st,
                                                          const float* __restrict__ part,
                                                          float* __restrict__ cot_out, int64_t N,
@@ -599,11 +634,11 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
                                                          double* __restrict__ pacc, int k_call, const float* __restrict__ cot_in, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      p2g_adjoint_lds_item(i, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
+      p2g_adjoint_lds_item<BOXN, MAT>(i, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
       __syncthreads();
     }
   } else {
-    p2g_adjoint_lds_item(blockIdx.x, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
+    p2g_adjoint_lds_item<BOXN, MAT>(blockIdx.x, st, part, cot_out, N, envs, items, gcot, pacc, k_call, cot_in);
   }
 }
 
@@ -617,7 +652,7 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
 constexpr int kItem = 256;
 
 struct SegShared {
-  float w[9][kItem];     // per-axis weights: x 0-2, y 3-5, z 6-8
+  float f[3][kItem];     // x n - base per axis; the weights are recomputed from it
   float q[3][kItem];     // value at the base node offset o = 0 (before the weight)
   float a[9][kItem];     // Abar, row-major: the value's change per unit node offset
   int key[kItem];        // packed base (10 bits per axis)
@@ -625,6 +660,15 @@ struct SegShared {
   int wave_sum[4];
   int n_seg;
 };
+
+// quadratic B-spline weights of the three nodes from f = x n - base (the
+// same expressions as the stencil's)
+MD void bspline3(float f, float w[3]) {
+  const float f0 = 1.5f - f, f1 = f - 1.f, f2 = f - 0.5f;
+  w[0] = 0.5f * f0 * f0;
+  w[1] = 0.75f - f1 * f1;
+  w[2] = 0.5f * f2 * f2;
+}
 
 MD int pack_base(const int b[3]) { return (b[0] << 20) | (b[1] << 10) | b[2]; }
 
@@ -673,10 +717,14 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, con
         ap[y][z][0] = ap[y][z][1] = ap[y][z][2] = 0.f;
       }
     for (int p = p0; p < p1; ++p) {
-      const float wx = sh.w[ox][p];
+      float w0[3], w1[3], w2[3];
+      bspline3(sh.f[0][p], w0);
+      bspline3(sh.f[1][p], w1);
+      bspline3(sh.f[2][p], w2);
+      const float wx = sel3(w0, ox);
       float wy[3], wz[3], r0[3], ay[3], az[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) { wy[k] = wx * sh.w[3 + k][p]; wz[k] = sh.w[6 + k][p]; }
+      for (int k = 0; k < 3; ++k) { wy[k] = wx * w1[k]; wz[k] = w2[k]; }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         r0[a] = sh.q[a][p] + sh.a[3 * a][p] * (float)ox;
@@ -715,16 +763,18 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, con
 }
 
 // P2G with segment reduction: thread t <-> particle t of the item
+template <int BOXN, int MAT>
 MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int runs, int k_call) {
   const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
-  __shared__ float lds[4 * kBoxNodes];
+  __shared__ float lds[4 * BOXN];
   __shared__ BoxShared bsh;
   __shared__ SegShared sh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int t = threadIdx.x;
   const bool valid = t < it.count;
@@ -734,7 +784,7 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
   sh.key[t] = pack_base(sc.b);
-  const Box bx = block_box(e, sc.b, valid, t, it.count, bsh);   // synchronizes
+  const Box bx = block_box<BOXN>(e, sc.b, valid, t, it.count, bsh);   // synchronizes
   find_segments(sh, it.count, max_run);        // synchronizes
   const bool seg_mode = it.count >= min_run * sh.n_seg;   // uniform across the block
   if (bx.fits)
@@ -744,12 +794,11 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
     float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
     const M3 H = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, H);
+    const M3 tau = stress(e, H, mat);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     if (seg_mode) {
-      for (int a = 0; a < 3; ++a)
-        for (int o = 0; o < 3; ++o) sh.w[3 * a + o][t] = sc.w[a][o];
+      for (int a = 0; a < 3; ++a) sh.f[a][t] = sc.f[a];
       for (int a = 0; a < 3; ++a) {
         float q = e.mp * v[a];
         for (int b = 0; b < 3; ++b) {
@@ -794,31 +843,53 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_p2g_seg(const float* __restrict__ st, int64_t N,
                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                  int32_t* __restrict__ errs, int runs, int k_call, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      p2g_seg_item(i, st, N, envs, items, grid, flags, errs, runs, k_call);
+      p2g_seg_item<BOXN, MAT>(i, st, N, envs, items, grid, flags, errs, runs, k_call);
       __syncthreads();
     }
   } else {
-    p2g_seg_item(blockIdx.x, st, N, envs, items, grid, flags, errs, runs, k_call);
+    p2g_seg_item<BOXN, MAT>(blockIdx.x, st, N, envs, items, grid, flags, errs, runs, k_call);
   }
 }
 
-void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+template <int BOXN, int MAT>
+static void launch_p2g_seg_t(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                     uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, hipStream_t s) {
-  if (n_items == 0) return;
   if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_p2g_seg<true>, dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
+    hipLaunchKernelGGL((k_p2g_seg<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
   else
-    hipLaunchKernelGGL(k_p2g_seg<false>, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
+    hipLaunchKernelGGL((k_p2g_seg<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, runs, k_call, n_items);
+}
+template <int BOXN>
+static void launch_p2g_seg_m(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_p2g_seg_t<BOXN, MAT_NEOHOOKEAN>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_p2g_seg_t<BOXN, MAT_COROTATED>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_p2g_seg_t<BOXN, MAT_VONMISES>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_p2g_seg_t<BOXN, MAT_FLUID_TAIT>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_p2g_seg_t<BOXN, MAT_FLUID_PAPER>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    case -1: launch_p2g_seg_t<BOXN, -1>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s); break;
+    default: break;
+  }
+}
+void launch_p2g_seg(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                    uint32_t* flags, int32_t* errs, int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_p2g_seg_m<kBoxSmall>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s, mat);
+  else
+    launch_p2g_seg_m<kBoxNodes>(st, N, envs, items, n_items, grid, flags, errs, runs, k_call, grid_cap, s, mat);
 }
 
 // G2P adjoint with segment-reduced scatter: thread t <-> particle t
+template <int BOXN, int MAT>
 MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
     const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
@@ -827,12 +898,13 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
                                                          const float* __restrict__ grid, float* __restrict__ gcot,
                                                          double* __restrict__ pacc, int runs, int k_call) {
   const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
-  __shared__ float lv[3 * kBoxNodes];
-  __shared__ float lg[3 * kBoxNodes];
+  __shared__ float lv[3 * BOXN];
+  __shared__ float lg[3 * BOXN];
   __shared__ BoxShared bsh;
   __shared__ SegShared sh;
   const WorkItem it = items[item_idx];
   const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
   if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
   const int t = threadIdx.x;
   const bool valid = t < it.count;
@@ -841,7 +913,7 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   sh.key[t] = pack_base(sc.b);
-  const Box bx = block_box(e, sc.b, valid, t, it.count, bsh);   // synchronizes
+  const Box bx = block_box<BOXN>(e, sc.b, valid, t, it.count, bsh);   // synchronizes
   find_segments(sh, it.count, max_run);
   const bool seg_mode = it.count >= min_run * sh.n_seg;
   if (bx.fits) {
@@ -862,13 +934,12 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
     for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
     const M3 Cb_in = ld_m3(cot, N, p, 6);
     const M3 Fb_in = ld_m3(cot, N, p, 15);
-    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb, mat);
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
     if (seg_mode) {
       // gv(o) = vbar + D4 Cbar (o - f) dx = q + Abar o
-      for (int a = 0; a < 3; ++a)
-        for (int o = 0; o < 3; ++o) sh.w[3 * a + o][t] = sc.w[a][o];
+      for (int a = 0; a < 3; ++a) sh.f[a][t] = sc.f[a];
       for (int a = 0; a < 3; ++a) {
         float q = vb[a];
         for (int b = 0; b < 3; ++b) {
@@ -879,15 +950,16 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
         sh.q[a][t] = q;
       }
     }
+    st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
+#pragma unroll 1
       for (int oy = 0; oy < 3; ++oy)
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sc.w[1][oy], wz = sc.w[2][oz];
+          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
           const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sc.dw[1][oy] * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
           const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
           float vi[3], gv[3];
           for (int a = 0; a < 3; ++a)
@@ -912,7 +984,6 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
           }
         }
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
-    st_m3(part, N, p, 3, Fb);
   }
   __syncthreads();
   if (seg_mode) {
@@ -924,7 +995,7 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items
-template <bool PERSIST>
+template <bool PERSIST, int BOXN, int MAT>
 __global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ st_next,
     const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
@@ -934,62 +1005,171 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict
                                                          double* __restrict__ pacc, int runs, int k_call, int n_items) {
   if (PERSIST) {
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-      g2p_adjoint_seg_item(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
+      g2p_adjoint_seg_item<BOXN, MAT>(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
       __syncthreads();
     }
   } else {
-    g2p_adjoint_seg_item(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
+    g2p_adjoint_seg_item<BOXN, MAT>(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, runs, k_call);
   }
 }
 
-void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
+template <int BOXN, int MAT>
+static void launch_g2p_adjoint_seg_t(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                             int runs, int k_call, int grid_cap, hipStream_t s) {
-  if (n_items == 0) return;
   if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_g2p_adjoint_seg<true>, dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+    hipLaunchKernelGGL((k_g2p_adjoint_seg<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
                      pacc, runs, k_call, n_items);
   else
-    hipLaunchKernelGGL(k_g2p_adjoint_seg<false>, dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+    hipLaunchKernelGGL((k_g2p_adjoint_seg<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
                      pacc, runs, k_call, n_items);
+}
+template <int BOXN>
+static void launch_g2p_adjoint_seg_m(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                            int runs, int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_g2p_adjoint_seg_t<BOXN, MAT_NEOHOOKEAN>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_g2p_adjoint_seg_t<BOXN, MAT_COROTATED>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_g2p_adjoint_seg_t<BOXN, MAT_VONMISES>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_g2p_adjoint_seg_t<BOXN, MAT_FLUID_TAIT>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_g2p_adjoint_seg_t<BOXN, MAT_FLUID_PAPER>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    case -1: launch_g2p_adjoint_seg_t<BOXN, -1>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s); break;
+    default: break;
+  }
+}
+void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                            int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_g2p_adjoint_seg_m<kBoxSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s, mat);
+  else
+    launch_g2p_adjoint_seg_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s, mat);
 }
 
-void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+template <int BOXN, int MAT>
+static void launch_p2g_lds_t(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
-  if (n_items == 0) return;
   if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_p2g_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
+    hipLaunchKernelGGL((k_p2g_lds<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
   else
-    hipLaunchKernelGGL(k_p2g_lds<false>, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
+    hipLaunchKernelGGL((k_p2g_lds<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call, n_items);
+}
+template <int BOXN>
+static void launch_p2g_lds_m(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_p2g_lds_t<BOXN, MAT_NEOHOOKEAN>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_p2g_lds_t<BOXN, MAT_COROTATED>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_p2g_lds_t<BOXN, MAT_VONMISES>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_p2g_lds_t<BOXN, MAT_FLUID_TAIT>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_p2g_lds_t<BOXN, MAT_FLUID_PAPER>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case -1: launch_p2g_lds_t<BOXN, -1>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    default: break;
+  }
+}
+void launch_p2g_lds(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                    uint32_t* flags, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_p2g_lds_m<kBoxSmall>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+  else
+    launch_p2g_lds_m<kBoxNodes>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+}
+template <int BOXN, int MAT>
+static void launch_g2p_lds_t(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL((k_g2p_lds<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+  else
+    hipLaunchKernelGGL((k_g2p_lds<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+}
+template <int BOXN>
+static void launch_g2p_lds_m(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_g2p_lds_t<BOXN, MAT_NEOHOOKEAN>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_g2p_lds_t<BOXN, MAT_COROTATED>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_g2p_lds_t<BOXN, MAT_VONMISES>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_g2p_lds_t<BOXN, MAT_FLUID_TAIT>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_g2p_lds_t<BOXN, MAT_FLUID_PAPER>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    case -1: launch_g2p_lds_t<BOXN, -1>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s); break;
+    default: break;
+  }
 }
 void launch_g2p_lds(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
-                    const float* grid, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
+                    const float* grid, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
   if (n_items == 0) return;
-  if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_g2p_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+  if (box)
+    launch_g2p_lds_m<kBoxSmall>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s, mat);
   else
-    hipLaunchKernelGGL(k_g2p_lds<false>, dim3(n_items), dim3(256), 0, s, st, out, N, envs, items, grid, errs, k_call, n_items);
+    launch_g2p_lds_m<kBoxNodes>(st, out, N, envs, items, n_items, grid, errs, k_call, grid_cap, s, mat);
+}
+template <int BOXN, int MAT>
+static void launch_g2p_adjoint_lds_t(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                            int k_call, int grid_cap, hipStream_t s) {
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL((k_g2p_adjoint_lds<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+                     pacc, k_call, n_items);
+  else
+    hipLaunchKernelGGL((k_g2p_adjoint_lds<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
+                     pacc, k_call, n_items);
+}
+template <int BOXN>
+static void launch_g2p_adjoint_lds_m(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
+                            int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_g2p_adjoint_lds_t<BOXN, MAT_NEOHOOKEAN>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_g2p_adjoint_lds_t<BOXN, MAT_COROTATED>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_g2p_adjoint_lds_t<BOXN, MAT_VONMISES>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_g2p_adjoint_lds_t<BOXN, MAT_FLUID_TAIT>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_g2p_adjoint_lds_t<BOXN, MAT_FLUID_PAPER>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case -1: launch_g2p_adjoint_lds_t<BOXN, -1>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    default: break;
+  }
 }
 void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* cot, float* part, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
-                            int k_call, int grid_cap, hipStream_t s) {
+                            int k_call, int grid_cap, int box, int mat, hipStream_t s) {
   if (n_items == 0) return;
-  if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_g2p_adjoint_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
-                     pacc, k_call, n_items);
+  if (box)
+    launch_g2p_adjoint_lds_m<kBoxSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
   else
-    hipLaunchKernelGGL(k_g2p_adjoint_lds<false>, dim3(n_items), dim3(256), 0, s, st, st_next, cot, part, N, envs, items, grid, gcot,
-                     pacc, k_call, n_items);
+    launch_g2p_adjoint_lds_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
+}
+template <int BOXN, int MAT>
+static void launch_p2g_adjoint_lds_t(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s) {
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL((k_p2g_adjoint_lds<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+                     pacc, k_call, cot_in, n_items);
+  else
+    hipLaunchKernelGGL((k_p2g_adjoint_lds<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
+                     pacc, k_call, cot_in, n_items);
+}
+template <int BOXN>
+static void launch_p2g_adjoint_lds_m(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_p2g_adjoint_lds_t<BOXN, MAT_NEOHOOKEAN>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    case MAT_COROTATED: launch_p2g_adjoint_lds_t<BOXN, MAT_COROTATED>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    case MAT_VONMISES: launch_p2g_adjoint_lds_t<BOXN, MAT_VONMISES>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_p2g_adjoint_lds_t<BOXN, MAT_FLUID_TAIT>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_p2g_adjoint_lds_t<BOXN, MAT_FLUID_PAPER>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    case -1: launch_p2g_adjoint_lds_t<BOXN, -1>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s); break;
+    default: break;
+  }
 }
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
-                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, hipStream_t s) {
+                            const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, int box, int mat, hipStream_t s) {
   if (n_items == 0) return;
-  if (grid_cap > 0 && grid_cap < n_items)
-    hipLaunchKernelGGL(k_p2g_adjoint_lds<true>, dim3(grid_cap), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
-                     pacc, k_call, cot_in, n_items);
+  if (box)
+    launch_p2g_adjoint_lds_m<kBoxSmall>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s, mat);
   else
-    hipLaunchKernelGGL(k_p2g_adjoint_lds<false>, dim3(n_items), dim3(256), 0, s, st, part, cot_out, N, envs, items, gcot,
-                     pacc, k_call, cot_in, n_items);
+    launch_p2g_adjoint_lds_m<kBoxNodes>(st, part, cot_out, N, envs, items, n_items, gcot, pacc, k_call, cot_in, grid_cap, s, mat);
 }
 
 }  // namespace mpmx

@@ -56,6 +56,12 @@ struct mpm_batch {
   int cell_bits = 0, key_bits = 0;
   std::vector<WorkItem> items_h;
   std::vector<int> item_off;  // [E+1]
+  // the work items again, grouped by material, for the material-specialized
+  // LDS-staged kernels: one launch per (material, first, count) range
+  struct MatRange { int mat, first, count; };
+  std::vector<WorkItem> items_mat_h;
+  std::vector<MatRange> mat_ranges;
+  std::vector<MatRange> generic_range;
   int n_seg_max = 0;
 
   // device buffers
@@ -63,6 +69,7 @@ struct mpm_batch {
   int64_t bytes = 0;
   EnvDev* envs_d = nullptr;
   WorkItem* items_d = nullptr;
+  WorkItem* items_mat_d = nullptr;
   int32_t* tile_env_d = nullptr;
   float* W[2] = {nullptr, nullptr};
   std::vector<float*> ckpt;        // [n_seg_max]
@@ -97,6 +104,8 @@ struct mpm_batch {
   int min_run = 3;
   int max_run = 8;    // runs of one stencil base are split every max_run particles
   int grid_cap = 0;   // 0: one block per work item; > 0: persistent grid of this many blocks
+  int box = 0;        // LDS box budget of the LDS-staged kernels: 0 = 1024 nodes, 1 = 384 nodes
+  int specialize = 1; // LDS-staged kernels: 1 = one launch per material, compiled for it; 0 = one generic launch
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -197,6 +206,14 @@ struct Span {
   }
 };
 
+// the (material, first, count) ranges the LDS-staged kernels launch over:
+// one per material, or one generic range (material -1) over all items in env order
+const std::vector<mpm_batch::MatRange>& launch_ranges(mpm_batch* b) {
+  if (b->specialize) return b->mat_ranges;
+  b->generic_range.assign(1, {-1, 0, (int)b->items_h.size()});
+  return b->generic_range;
+}
+
 // ---------------------------------------------------------------- one substep
 void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel, int kc) {
   float* g = b->grid[gi];
@@ -213,17 +230,24 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
     }
   } else {
     const int ni = (int)b->items_h.size();
+    const int runs = b->min_run | (b->max_run << 16);
+    const std::vector<mpm_batch::MatRange>& ranges = launch_ranges(b);
     {
       Span sp(b, KC_P2G);
-      if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, b->min_run | (b->max_run << 16), kc, b->grid_cap, s);
-      else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, b->grid_cap, s);
-      else launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
+      if (b->var_p2g == 0) launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
+      for (const auto& r : ranges) {
+        const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+        if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, it, r.count, g, fl, b->errs, runs, kc, b->grid_cap, b->box, r.mat, s);
+        else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, g, fl, b->errs, kc, b->grid_cap, b->box, r.mat, s);
+      }
     }
     { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, s); }
     {
       Span sp(b, KC_G2P);
-      if (b->var_g2p) launch_g2p_lds(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, b->grid_cap, s);
-      else launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
+      if (b->var_g2p == 0) launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
+      else
+        for (const auto& r : ranges)
+          launch_g2p_lds(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, g, b->errs, kc, b->grid_cap, b->box, r.mat, s);
     }
   }
 }
@@ -244,17 +268,24 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const 
     }
   } else {
     const int ni = (int)b->items_h.size();
+    const int runs = b->min_run | (b->max_run << 16);
+    const std::vector<mpm_batch::MatRange>& ranges = launch_ranges(b);
     {
       Span sp(b, KC_G2P_ADJ);
-      if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, b->min_run | (b->max_run << 16), kc, b->grid_cap, s);
-      else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, b->grid_cap, s);
-      else launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+      if (b->var_g2p_adj == 0) launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+      for (const auto& r : ranges) {
+        const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+        if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, runs, kc, b->grid_cap, b->box, r.mat, s);
+        else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
+      }
     }
     { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
     {
       Span sp(b, KC_P2G_ADJ);
-      if (b->var_p2g_adj) launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, b->grid_cap, s);
-      else launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
+      if (b->var_p2g_adj == 0) launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
+      else
+        for (const auto& r : ranges)
+          launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->gcot, b->pacc, kc, cot_in, b->grid_cap, b->box, r.mat, s);
     }
   }
 }
@@ -360,6 +391,27 @@ void drop_graphs(mpm_batch* b) {
 
 int upload_envs(mpm_batch* b) {
   HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
+  // items grouped by material (env order kept inside a group)
+  std::vector<mpm_batch::MatRange> ranges;
+  b->items_mat_h.clear();
+  for (int m = 0; m < MAT_COUNT; ++m) {
+    const int first = (int)b->items_mat_h.size();
+    for (const WorkItem& it : b->items_h)
+      if (b->envs_h[it.env].material == m) b->items_mat_h.push_back(it);
+    const int count = (int)b->items_mat_h.size() - first;
+    if (count > 0) ranges.push_back({m, first, count});
+  }
+  if (!b->items_mat_h.empty())
+    HIPC(b, hipMemcpyAsync(b->items_mat_d, b->items_mat_h.data(), sizeof(WorkItem) * b->items_mat_h.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  bool same = ranges.size() == b->mat_ranges.size();
+  for (size_t i = 0; same && i < ranges.size(); ++i)
+    same = ranges[i].mat == b->mat_ranges[i].mat && ranges[i].first == b->mat_ranges[i].first &&
+           ranges[i].count == b->mat_ranges[i].count;
+  if (!same) {
+    b->mat_ranges = ranges;
+    drop_graphs(b);   // captured launches name the ranges
+  }
   launch_prep_params(b->envs_d, b->E, b->stream);
   HIPC(b, hipGetLastError());
   return MPM_OK;
@@ -391,7 +443,7 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
 
 namespace {
 
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run; };
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize; };
 
 // shape signature -> choice, shared by batches of the same shape in the process
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -411,6 +463,8 @@ void apply_choice(mpm_batch* b, const TuneChoice& c) {
   b->min_run = c.min_run;
   b->grid_cap = c.grid_cap;
   b->max_run = c.max_run;
+  b->box = c.box;
+  b->specialize = c.specialize;
   drop_graphs(b);
 }
 
@@ -511,6 +565,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   };
   b->envs_d = (EnvDev*)A(sizeof(EnvDev) * b->E);
   b->items_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(b->items_h.size(), 1));
+  b->items_mat_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(b->items_h.size(), 1));
   b->tile_env_d = (int32_t*)A(sizeof(int32_t) * tile_env.size());
   b->W[0] = (float*)A(state_bytes);
   b->W[1] = (float*)A(state_bytes);
@@ -827,6 +882,8 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_MIN_RUN: if (value < 1 || value > 256) break; b->min_run = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_GRID_CAP: if (value < 0) break; b->grid_cap = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_MAX_RUN: if (value < 1 || value > 256) break; b->max_run = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_BOX: if (value < 0 || value > 1) break; b->box = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -843,6 +900,8 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_MIN_RUN: *value = b->min_run; return MPM_OK;
     case MPM_OPT_GRID_CAP: *value = b->grid_cap; return MPM_OK;
     case MPM_OPT_MAX_RUN: *value = b->max_run; return MPM_OK;
+    case MPM_OPT_BOX: *value = b->box; return MPM_OK;
+    case MPM_OPT_SPECIALIZE: *value = b->specialize; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
@@ -916,7 +975,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -942,6 +1001,8 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.g2p, 0, 0, false}, {&best.g2p, 1, 0, false}},
       {{&best.g2p_adj, 0, 0, true}, {&best.g2p_adj, 1, 0, true}, {&best.g2p_adj, 2, 0, true}},
       {{&best.p2g_adj, 0, 0, true}, {&best.p2g_adj, 1, 0, true}},
+      {{&best.box, 0, 0, true}, {&best.box, 1, 0, true}},
+      {{&best.specialize, 1, 0, true}, {&best.specialize, 0, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

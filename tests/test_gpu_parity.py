@@ -276,8 +276,9 @@ def test_slot_reconfiguration_matches_oracle():
 
 
 # ------------------------------------------------------------------ kernel variants and the autotuner
-VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap)
-    (0, 0, 0, 0, 0), (1, 1, 1, 1, 0), (2, 1, 2, 1, 0), (2, 1, 2, 1, 7), (1, 0, 2, 0, 3),
+VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, per-material launches)
+    (0, 0, 0, 0, 0, 0, 1), (1, 1, 1, 1, 0, 0, 1), (2, 1, 2, 1, 0, 0, 1), (2, 1, 2, 1, 7, 0, 1), (1, 0, 2, 0, 3, 0, 1),
+    (1, 1, 1, 1, 0, 1, 1), (2, 1, 2, 1, 0, 1, 1), (2, 1, 2, 1, 5, 1, 1), (1, 1, 1, 1, 0, 0, 0), (2, 1, 2, 1, 6, 1, 0),
 ]
 
 
@@ -291,7 +292,7 @@ def test_every_kernel_variant_matches_oracle(var):
     cots = random_cotangents(envs, seed=112)
     announce(f"variant {var}")
     b = Batch(envs, max_substeps=S, ckpt_every=K)
-    for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP), var):
+    for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP, C.OPT_BOX, C.OPT_SPECIALIZE), var):
         b.set_option(opt, val)
     b.set_particles_from_specs()
     b.forward(S, record=True)
@@ -319,7 +320,7 @@ def test_autotune_restores_state_and_keeps_parity():
     after = [t.cpu().numpy() for t in b.get_particles()]
     for a, c in zip(before, after):
         assert np.array_equal(a, c)
-    opts = {k: b.get_option(getattr(C, k)) for k in ("OPT_P2G", "OPT_G2P", "OPT_G2P_ADJ", "OPT_P2G_ADJ", "OPT_GRID_CAP")}
+    opts = {k: b.get_option(getattr(C, k)) for k in ("OPT_P2G", "OPT_G2P", "OPT_G2P_ADJ", "OPT_P2G_ADJ", "OPT_GRID_CAP", "OPT_BOX", "OPT_SPECIALIZE")}
     announce(f"autotune chose {opts}")
     assert opts["OPT_P2G"] in (0, 1, 2) and opts["OPT_GRID_CAP"] >= 0
     cots = random_cotangents(envs, seed=121)

@@ -652,9 +652,12 @@ __global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict
 constexpr int kItem = 256;
 
 struct SegShared {
-  float f[3][kItem];     // x n - base per axis; the weights are recomputed from it
-  float q[3][kItem];     // value at the base node offset o = 0 (before the weight)
-  float a[9][kItem];     // Abar, row-major: the value's change per unit node offset
+  // per particle, four 16-byte rows read with one 128-bit LDS load each:
+  // (q0 q1 q2 f0) (A00 A01 A02 f1) (A10 A11 A12 f2) (A20 A21 A22 -), where q is
+  // the value at the base node offset o = 0 (before the weight), Abar (row-major)
+  // its change per unit node offset and f = x n - base (the weights are
+  // recomputed from it)
+  float4 pd[kItem][4];
   int key[kItem];        // packed base (10 bits per axis)
   int first[kItem + 1];  // first particle of each segment, then the count
   int wave_sum[4];
@@ -671,6 +674,14 @@ MD void bspline3(float f, float w[3]) {
 }
 
 MD int pack_base(const int b[3]) { return (b[0] << 20) | (b[1] << 10) | b[2]; }
+
+// stores particle t's scatter data: q (3), Abar (3x3, row-major), f (3)
+MD void seg_store(SegShared& sh, int t, const float q[3], const float ab[3][3], const float f[3]) {
+  sh.pd[t][0] = make_float4(q[0], q[1], q[2], f[0]);
+  sh.pd[t][1] = make_float4(ab[0][0], ab[0][1], ab[0][2], f[1]);
+  sh.pd[t][2] = make_float4(ab[1][0], ab[1][1], ab[1][2], f[2]);
+  sh.pd[t][3] = make_float4(ab[2][0], ab[2][1], ab[2][2], 0.f);
+}
 
 // marks segment starts among the item's particles (thread t <-> particle t)
 // and fills first[] / n_seg; a run of one stencil base is cut at every
@@ -699,66 +710,66 @@ MD void find_segments(SegShared& sh, int count, int max_run) {
 
 // phase 2: NCH channels; channel 0 is the weight sum times `mass` when
 // WITH_MASS, the remaining three the affine value. Writes into the LDS box
-// (fits) or straight to grid channels c0.. with global atomics.
+// (fits) or straight to grid channels c0.. with global atomics. A lane owns
+// (segment, ox, oy) and sums the segment's particles for the three z-nodes of
+// that column in registers: nine lanes per segment, which read the same
+// particle data (LDS broadcast), so a segment of k particles costs a chain of
+// k short iterations rather than k long ones.
 template <bool WITH_MASS>
 MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, const SegShared& sh, float mass, float* lds_box,
                         float* __restrict__ g, int c0) {
   constexpr int NCH = WITH_MASS ? 4 : 3;
-  const int units = 3 * sh.n_seg;   // (segment, ox): the lane sums the 3x3 (oy, oz) nodes of one x-layer
+  const int units = 9 * sh.n_seg;
   for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int seg = u / 3, ox = u - 3 * seg;
+    const int seg = u / 9, r = u - 9 * seg, ox = r / 3, oy = r - 3 * ox;
     const int p0 = sh.first[seg], p1 = sh.first[seg + 1];
-    float am[3][3], ap[3][3][3];
+    float am[3], ap[3][3];
 #pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int z = 0; z < 3; ++z) {
-        am[y][z] = 0.f;
-        ap[y][z][0] = ap[y][z][1] = ap[y][z][2] = 0.f;
-      }
-    for (int p = p0; p < p1; ++p) {
-      float w0[3], w1[3], w2[3];
-      bspline3(sh.f[0][p], w0);
-      bspline3(sh.f[1][p], w1);
-      bspline3(sh.f[2][p], w2);
-      const float wx = sel3(w0, ox);
-      float wy[3], wz[3], r0[3], ay[3], az[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) { wy[k] = wx * w1[k]; wz[k] = w2[k]; }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        r0[a] = sh.q[a][p] + sh.a[3 * a][p] * (float)ox;
-        ay[a] = sh.a[3 * a + 1][p];
-        az[a] = sh.a[3 * a + 2][p];
-      }
-#pragma unroll
-      for (int y = 0; y < 3; ++y)
-#pragma unroll
-        for (int z = 0; z < 3; ++z) {
-          const float W = wy[y] * wz[z];
-          am[y][z] += W;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) ap[y][z][a] = fmaf(W, r0[a] + ay[a] * (float)y + az[a] * (float)z, ap[y][z][a]);
-        }
+    for (int z = 0; z < 3; ++z) {
+      am[z] = 0.f;
+      ap[z][0] = ap[z][1] = ap[z][2] = 0.f;
     }
-    const int key = sh.key[p0];
-    const int bx0 = (key >> 20) + ox, by0 = (key >> 10) & 1023, bz0 = key & 1023;
-#pragma unroll
-    for (int y = 0; y < 3; ++y)
+    // one particle's contribution to the lane's three z-nodes
+    auto add = [&](int p) {
+      const float4 P0 = sh.pd[p][0], P1 = sh.pd[p][1], P2 = sh.pd[p][2], P3 = sh.pd[p][3];
+      float w0[3], w1[3], w2[3];
+      bspline3(P0.w, w0);
+      bspline3(P1.w, w1);
+      bspline3(P2.w, w2);
+      const float wxy = sel3(w0, ox) * sel3(w1, oy);
+      const float fx = (float)ox, fy = (float)oy;
+      const float r0[3] = {P0.x + P1.x * fx + P1.y * fy, P0.y + P2.x * fx + P2.y * fy, P0.z + P3.x * fx + P3.y * fy};
+      const float az[3] = {P1.z, P2.z, P3.z};
 #pragma unroll
       for (int z = 0; z < 3; ++z) {
-        float v[4];
-        int k = 0;
-        if (WITH_MASS) v[k++] = am[y][z] * mass;
-        for (int a = 0; a < 3; ++a) v[k++] = ap[y][z][a];
-        if (bx.fits) {
-          const int idx = box_index_run(bs, bs.run[p0], bx0, by0 + y, bz0 + z);
-          for (int c = 0; c < NCH; ++c) atomicAdd(&lds_box[c * bx.nodes + idx], v[c]);
-        } else {
-          float* dst = g + node_base(e, bx0, by0 + y, bz0 + z) + c0 * CH;
-          for (int c = 0; c < NCH; ++c) atomicAdd(dst + c * CH, v[c]);
-        }
+        const float W = wxy * w2[z];
+        am[z] += W;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ap[z][a] = fmaf(W, r0[a] + az[a] * (float)z, ap[z][a]);
       }
+    };
+    int p = p0;
+    for (; p + 1 < p1; p += 2) {   // two at a time so that their LDS loads overlap
+      add(p);
+      add(p + 1);
+    }
+    if (p < p1) add(p);
+    const int key = sh.key[p0];
+    const int bx0 = (key >> 20) + ox, by0 = ((key >> 10) & 1023) + oy, bz0 = key & 1023;
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+      float v[4];
+      int k = 0;
+      if (WITH_MASS) v[k++] = am[z] * mass;
+      for (int a = 0; a < 3; ++a) v[k++] = ap[z][a];
+      if (bx.fits) {
+        const int idx = box_index_run(bs, bs.run[p0], bx0, by0, bz0 + z);
+        for (int c = 0; c < NCH; ++c) atomicAdd(&lds_box[c * bx.nodes + idx], v[c]);
+      } else {
+        float* dst = g + node_base(e, bx0, by0, bz0 + z) + c0 * CH;
+        for (int c = 0; c < NCH; ++c) atomicAdd(dst + c * CH, v[c]);
+      }
+    }
   }
 }
 
@@ -798,16 +809,15 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     if (seg_mode) {
-      for (int a = 0; a < 3; ++a) sh.f[a][t] = sc.f[a];
+      float q[3], ab[3][3];
       for (int a = 0; a < 3; ++a) {
-        float q = e.mp * v[a];
+        q[a] = e.mp * v[a];
         for (int b = 0; b < 3; ++b) {
-          const float ab = A.m[a][b] * e.dx;
-          sh.a[3 * a + b][t] = ab;
-          q = fmaf(-ab, sc.f[b], q);
+          ab[a][b] = A.m[a][b] * e.dx;
+          q[a] = fmaf(-ab[a][b], sc.f[b], q[a]);
         }
-        sh.q[a][t] = q;
       }
+      seg_store(sh, t, q, ab, sc.f);
     } else {
       for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
@@ -939,16 +949,15 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
     const M3 Fb = m3_mul_atb(G, Ftrb);
     if (seg_mode) {
       // gv(o) = vbar + D4 Cbar (o - f) dx = q + Abar o
-      for (int a = 0; a < 3; ++a) sh.f[a][t] = sc.f[a];
+      float q[3], ab[3][3];
       for (int a = 0; a < 3; ++a) {
-        float q = vb[a];
+        q[a] = vb[a];
         for (int b = 0; b < 3; ++b) {
-          const float ab = D4 * e.dx * Cb.m[a][b];
-          sh.a[3 * a + b][t] = ab;
-          q = fmaf(-ab, sc.f[b], q);
+          ab[a][b] = D4 * e.dx * Cb.m[a][b];
+          q[a] = fmaf(-ab[a][b], sc.f[b], q[a]);
         }
-        sh.q[a][t] = q;
       }
+      seg_store(sh, t, q, ab, sc.f);
     }
     st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
 #pragma unroll 1

@@ -59,6 +59,18 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
+    """Name of the launched instantiation, as profilers print it: the LDS-staged
+    kernels are templates over (persistent grid, LDS box nodes, material)."""
+    if not variant:
+        return symbol
+    n_items = sum(-(-e.n_particles // 256) for e in envs)
+    persist = "true" if 0 < tuned["GRID_CAP"] < n_items else "false"
+    mats = sorted({e.material for e in envs})
+    mat = mats[0] if tuned["SPECIALIZE"] and len(mats) == 1 else -1
+    return f"{symbol}<{persist}, {384 if tuned['BOX'] else 1024}, {mat}>"
+
+
 def measured_traffic(workload: str, symbol: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None if
     there are none or the kernel sources changed since they were taken."""
@@ -85,6 +97,8 @@ def parse():
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
     ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
     ap.add_argument("--tune-ms", type=int, default=4000, help="autotuner budget (0: library defaults)")
+    ap.add_argument("--set", default="", help="fixed library options instead of autotuning, e.g. P2G=2,G2P=0,BOX=1 "
+                    "(a profiling run uses the choice an earlier timed run printed under 'autotuned')")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -94,7 +108,6 @@ def parse():
 
 def touched_nodes(envs, wall_pad=2):
     """Grid nodes inside the stencils of the initial particles (per env, summed)."""
-    from oracle import mpm_oracle  # noqa: F401  (keeps imports symmetric; not used for arithmetic)
     total = 0
     for e in envs:
         b = np.floor(e.x.astype(np.float64) * e.n - 0.5).astype(np.int64)
@@ -190,7 +203,10 @@ def main():
     if args.no_graphs:
         b.set_option(_capi.OPT_GRAPHS, 0)
     tune_s = None
-    if args.tune_ms > 0 and not args.profile:
+    fixed = dict(kv.split("=") for kv in args.set.split(",") if kv)
+    for k, v in fixed.items():
+        b.set_option(getattr(_capi, "OPT_" + k.upper()), int(v))
+    if args.tune_ms > 0 and not args.profile and not fixed:
         b.set_particles(*x0)
         t0 = time.perf_counter()
         b.autotune(args.tune_ms)
@@ -234,7 +250,7 @@ def main():
     dom_ms = kt[dom][0]
     alg_bytes = ALG_BYTES_PER_PARTICLE[dom] * N + ALG_BYTES_PER_NODE.get(dom, 0) * nodes
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    symbol = KERNEL_SYMBOL.get(dom, {}).get(variant.get(dom), dom)
+    symbol = kernel_instance(KERNEL_SYMBOL.get(dom, {}).get(variant.get(dom), dom), variant.get(dom), tuned, envs)
     traffic = measured_traffic(wl.name, symbol)
 
     plain = None

@@ -29,7 +29,8 @@ struct BoxShared {
   int rk[256];            // tile-row key of particle i (natural order), -1 if none
   int run[256];           // run index of particle i
   int wsum[4];
-  int lo[kMaxRuns][3], hi[kMaxRuns][3];
+  int wlo[4][kMaxRuns][3], whi[4][kMaxRuns][3];   // per-wave bounds of each run
+  int lo[kMaxRuns][3];
   int off[kMaxRuns + 1];  // first LDS node of each run's box; off[nruns] = total
   int ext[kMaxRuns][3];
   int nruns;
@@ -47,15 +48,15 @@ struct Box {
   int run;
 };
 
-// every thread must call it; lp = this thread's particle index in the item
+// whole-wavefront min / max (DPP reductions of the device library)
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_min_i32(int);
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
+
+// every thread must call it (uniform control flow); lp = this thread's particle index in the item
 template <int BOXN>
 MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count, BoxShared& bs) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  if (t < 256) bs.rk[lp] = valid ? ((b[0] >> 2) * e.T + (b[1] >> 2)) : -1;
-  if (t < kMaxRuns * 3) {
-    (&bs.lo[0][0])[t] = 0x3fffffff;
-    (&bs.hi[0][0])[t] = -0x3fffffff;
-  }
+  bs.rk[lp] = valid ? ((b[0] >> 2) * e.T + (b[1] >> 2)) : -1;
   __syncthreads();
   // runs of equal tile-row key in natural particle order (thread t looks at particle t)
   const bool in = t < count;
@@ -75,21 +76,37 @@ MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count,
   }
   __syncthreads();
   const int nruns = bs.nruns;
-  const int r = valid ? bs.run[lp] : 0;
-  if (valid && r < kMaxRuns)
+  const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
+  const int r = valid ? bs.run[lp] : -1;
+  // bounds of each run's stencils [min base, max base + 2]: a reduction in
+  // registers per wave, then one value per wave (contended LDS atomics on a
+  // handful of addresses would serialize 256 x 6 updates)
+  for (int k = 0; k < nr; ++k) {
+    const bool mine = r == k;
     for (int a = 0; a < 3; ++a) {
-      atomicMin(&bs.lo[r][a], b[a]);
-      atomicMax(&bs.hi[r][a], b[a] + 2);
+      const int mn = __ockl_wfred_min_i32(mine ? b[a] : 0x3fffffff);
+      const int mx = __ockl_wfred_max_i32(mine ? b[a] + 2 : -0x3fffffff);
+      if (lane == 0) {
+        bs.wlo[wave][k][a] = mn;
+        bs.whi[wave][k][a] = mx;
+      }
     }
+  }
   __syncthreads();
   if (t == 0) {
+    const int nw = (int)(blockDim.x >> 6);
     int acc = 0;
-    const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
     for (int k = 0; k < nr; ++k) {
       bs.off[k] = acc;
       int n = 1;
       for (int a = 0; a < 3; ++a) {
-        bs.ext[k][a] = bs.hi[k][a] - bs.lo[k][a] + 1;
+        int lo = 0x3fffffff, hi = -0x3fffffff;
+        for (int w = 0; w < nw; ++w) {
+          lo = min(lo, bs.wlo[w][k][a]);
+          hi = max(hi, bs.whi[w][k][a]);
+        }
+        bs.lo[k][a] = lo;
+        bs.ext[k][a] = hi - lo + 1;
         n *= bs.ext[k][a];
       }
       acc += n;
@@ -98,11 +115,10 @@ MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count,
   }
   __syncthreads();
   Box bx;
-  const int nr = nruns < kMaxRuns ? nruns : kMaxRuns;
   bx.nodes = bs.off[nr];
   bx.fits = nruns >= 1 && nruns <= kMaxRuns && bx.nodes <= BOXN;
-  bx.run = r;
-  const int rr = r < kMaxRuns ? r : 0;
+  bx.run = r < 0 ? 0 : r;
+  const int rr = (r >= 0 && r < kMaxRuns) ? r : 0;
   for (int a = 0; a < 3; ++a) bx.lo[a] = bs.lo[rr][a];
   bx.ey = bs.ext[rr][1];
   bx.ez = bs.ext[rr][2];
@@ -625,7 +641,9 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
 
 // one block per work item, or (PERSIST) a grid that strides over the items
 template <bool PERSIST, int BOXN, int MAT>
-__global__ void __launch_bounds__(256) k_p2g_adjoint_lds(const float* __restrict__ st,
+// four waves per SIMD: the stress VJP would otherwise hold ~150 VGPRs and
+// leave three; the compiler spills a few registers instead
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_p2g_adjoint_lds(const float* __restrict__ st,
                                                          const float* __restrict__ part,
                                                          float* __restrict__ cot_out, int64_t N,
                                                          const EnvDev* __restrict__ envs,

@@ -359,12 +359,13 @@ def box_sdf(p, center, half):
     return d, nrm
 
 
-def collide(env: Env, v, t: float, active):
-    """Softened one-way contact (Appendix D.3): blend pre/post projection by s = min(exp(-alpha d), 1)."""
+def collide(env: Env, v, center, vb, active):
+    """Softened one-way contact (Appendix D.3): blend pre/post projection by s = min(exp(-alpha d), 1).
+
+    ``center`` and ``vb`` are the box's center and velocity during this substep
+    (tensors, so that derivatives reach a prescribed collider motion)."""
     box = env.collider
     n = env.n
-    vb = torch.tensor(box.velocity, dtype=DT)
-    center = torch.tensor(box.center, dtype=DT) + t * vb
     d, nh = box_sdf(node_positions(n), center, torch.tensor(box.half, dtype=DT))
     s = torch.clamp(torch.exp(-box.alpha * d), max=1.0)
     u = v - vb
@@ -383,14 +384,35 @@ def collide(env: Env, v, t: float, active):
     return s_eff * (vb + u_proj) + (1.0 - s_eff) * v
 
 
-def grid_update(env: Env, gm, gP, t: float):
+def collider_motion(env: Env, t: float, motion=None):
+    """(center, velocity) of the box during the substep that starts at time t.
+
+    Without a prescribed motion the box moves at its constant velocity,
+    center = c0 + t v_b. With one, ``motion`` is this substep's (center, v_b)
+    from collider_path."""
+    if motion is not None:
+        return motion
+    vb = torch.tensor(env.collider.velocity, dtype=DT)
+    return torch.tensor(env.collider.center, dtype=DT) + t * vb, vb
+
+
+def collider_path(env: Env, vel):
+    """Centers of a box driven by per-substep velocities vel [S, 3] (the actions):
+    the center during substep k is c0 + dt sum_{j<k} vel_j."""
+    c0 = torch.tensor(env.collider.center, dtype=DT)
+    steps = torch.cat([torch.zeros(1, 3, dtype=vel.dtype), env.dt * vel[:-1]], 0)
+    return c0 + torch.cumsum(steps, 0)
+
+
+def grid_update(env: Env, gm, gP, t: float, motion=None):
     """a5: v = P/m + dt g where m > 0 (else 0), contact blend, then sticky walls."""
     g = torch.tensor(env.gravity, dtype=DT)
     pos = gm > 0
     msafe = torch.where(pos, gm, torch.ones_like(gm))
     v = torch.where(pos[:, None], gP / msafe[:, None] + env.dt * g, torch.zeros_like(gP))
     if env.collider is not None:
-        v = collide(env, v, t, pos)
+        center, vb = collider_motion(env, t, motion)
+        v = collide(env, v, center, vb, pos)
     wm = wall_mask(env.n, env.wall)
     return torch.where(wm[:, None], torch.zeros_like(v), v)
 
@@ -410,21 +432,29 @@ def g2p(env: Env, prm, x, F, gv):
     return xn, vn, Cn, Fn
 
 
-def substep(env: Env, prm, x, v, C, F, t: float):
+def substep(env: Env, prm, x, v, C, F, t: float, motion=None):
     """One MLS-MPM substep of one environment: P2G, grid update, G2P."""
     gm, gP, oob = p2g(env, prm, x, v, C, F)
-    gv = grid_update(env, gm, gP, t)
+    gv = grid_update(env, gm, gP, t, motion)
     xn, vn, Cn, Fn = g2p(env, prm, x, F, gv)
     return xn, vn, Cn, Fn, bool(oob.any().item())
 
 
-def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False):
-    """Run S substeps; returns the final state (and every state if keep_all)."""
+def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=None):
+    """Run S substeps; returns the final state (and every state if keep_all).
+
+    ``vel`` [>= S, 3]: per-substep collider velocities (actions) of a box whose
+    path starts at its configured center at the first substep (t0 = 0)."""
     x, v, C, F = state
     states = [state]
     any_oob = False
+    path = None
+    if vel is not None:
+        assert t0 == 0.0 and env.collider is not None
+        path = collider_path(env, vel)
     for k in range(S):
-        x, v, C, F, oob = substep(env, prm, x, v, C, F, t0 + k * env.dt)
+        motion = None if path is None else (path[k], vel[k])
+        x, v, C, F, oob = substep(env, prm, x, v, C, F, t0 + k * env.dt, motion)
         any_oob |= oob
         if keep_all:
             states.append((x, v, C, F))
@@ -433,38 +463,64 @@ def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False):
     return (x, v, C, F), any_oob
 
 
-def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0):
+def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None):
     """Reverse-mode cotangents of the initial state and of the 7 parameters.
 
     ``cot`` = (x_bar, v_bar, C_bar, F_bar) of the final state (None entries = 0).
     Each substep is re-differentiated from its stored input (per-substep
-    checkpointing), so memory stays at one substep's graph.
+    checkpointing), so memory stays at one substep's graph. With a collider
+    motion ``vel`` it also returns the cotangents of the velocities [S, 3] and
+    of the box's starting center [3]: each substep yields those of its own
+    (center_k, v_k), and center_k = c0 + dt sum_{j<k} vel_j passes its part to
+    every earlier velocity and to c0.
     """
     with torch.no_grad():
-        states, _ = rollout(env, prm, state, S, t0, keep_all=True)
+        states, _ = rollout(env, prm, state, S, t0, keep_all=True, vel=vel)
+        path = None if vel is None else collider_path(env, vel)
     g = [torch.zeros_like(s) if c is None else c.to(DT) for s, c in zip(state, cot)]
     gprm = torch.zeros_like(prm)
+    gcen = torch.zeros(S, 3, dtype=DT)
+    gvb = torch.zeros(S, 3, dtype=DT)
     for k in reversed(range(S)):
         s_in = [s.detach().clone().requires_grad_(True) for s in states[k]]
         p_in = prm.detach().clone().requires_grad_(True)
+        leaves = s_in + [p_in]
+        motion = None
+        if path is not None:
+            motion = (path[k].detach().clone().requires_grad_(True), vel[k].detach().clone().requires_grad_(True))
+            leaves = leaves + list(motion)
         with torch.enable_grad():
-            out = substep(env, p_in, *s_in, t0 + k * env.dt)[:4]
-            grads = torch.autograd.grad(out, s_in + [p_in], grad_outputs=g, allow_unused=True)
+            out = substep(env, p_in, *s_in, t0 + k * env.dt, motion)[:4]
+            grads = torch.autograd.grad(out, leaves, grad_outputs=g, allow_unused=True)
         g = [torch.zeros_like(s) if gr is None else gr for s, gr in zip(s_in, grads[:4])]
         if grads[4] is not None:
             gprm = gprm + grads[4]
-    return tuple(g), gprm
+        if path is not None:
+            if grads[5] is not None:
+                gcen[k] = grads[5]
+            if grads[6] is not None:
+                gvb[k] = grads[6]
+    if vel is None:
+        return tuple(g), gprm
+    later = torch.flip(torch.cumsum(torch.flip(gcen, [0]), 0), [0]) - gcen   # sum over k > j
+    gvel = gvb + env.dt * later
+    return tuple(g), gprm, gvel, gcen.sum(0)
 
 
-def rollout_jvp(env: Env, prm, state, S: int, tangent, prm_tangent, t0: float = 0.0):
+def rollout_jvp(env: Env, prm, state, S: int, tangent, prm_tangent, t0: float = 0.0, vel=None, vel_tangent=None):
     """Forward-mode tangent of the final state (dual numbers through the same forward)."""
     import torch.autograd.forward_ad as fwAD
     with torch.no_grad(), fwAD.dual_level():
         st = [fwAD.make_dual(s, ts) for s, ts in zip(state, tangent)]
         p = fwAD.make_dual(prm, prm_tangent)
+        path = vv = None
+        if vel is not None:
+            vv = fwAD.make_dual(vel, vel_tangent if vel_tangent is not None else torch.zeros_like(vel))
+            path = collider_path(env, vv)
         x, v, C, F = st
         for k in range(S):
-            x, v, C, F, _ = substep(env, p, x, v, C, F, t0 + k * env.dt)
+            motion = None if path is None else (path[k], vv[k])
+            x, v, C, F, _ = substep(env, p, x, v, C, F, t0 + k * env.dt, motion)
         return tuple(fwAD.unpack_dual(a).tangent for a in (x, v, C, F))
 
 

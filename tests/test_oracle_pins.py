@@ -331,12 +331,12 @@ def test_contact_projection_hand_values():
              ((1.0, 2.0, 0.0), (1.0, 2.0, 0.0))]         # separating: unchanged
     for vin, vout in cases:
         v[i_in] = torch.tensor(vin, dtype=DT)
-        out = O.collide(env, v, 0.0, act)
+        out = O.collide(env, v, *O.collider_motion(env, 0.0), act)
         np.testing.assert_allclose(out[i_in].numpy(), vout, atol=1e-14)
     # a node outside at distance d: blend s = exp(-alpha d) of projected and free velocity
     i_out = int(((pos - torch.tensor([0.75, 0.5, 0.5], dtype=DT)).abs().sum(1)).argmin())  # d = 0.05
     v[i_out] = torch.tensor([-1.0, 0.2, 0.0], dtype=DT)
-    out = O.collide(env, v, 0.0, act)
+    out = O.collide(env, v, *O.collider_motion(env, 0.0), act)
     s = math.exp(-32.0 * 0.05)
     np.testing.assert_allclose(out[i_out].numpy(), [(1 - s) * -1.0, (1 - s) * 0.2, 0.0], atol=1e-14)
 
@@ -426,3 +426,81 @@ def test_von_mises_tiny_scene_is_plastic():
     Fp = O.project(O.VONMISES, F, mu, prm[4])
     moved = ((Fp - F).flatten(1).norm(dim=1) > 1e-12).sum().item()
     assert 0 < moved < len(F)
+
+
+# ---------------------------------------------------------------- prescribed collider motion (actions)
+def _moving_box(S, seed):
+    env, prm, st = tiny(O.FLUID_TAIT, collider=True)
+    rng = np.random.default_rng(seed)
+    vb = torch.tensor(env.collider.velocity, dtype=DT)
+    vel = vb + 0.2 * torch.from_numpy(rng.standard_normal((S, 3)))
+    return env, prm, st, vel
+
+
+def test_constant_actions_reproduce_the_fixed_velocity_box():
+    # a box driven by per-substep velocities all equal to v_b follows c0 + t v_b
+    env, prm, st = tiny(O.FLUID_TAIT, collider=True)
+    S = 4
+    vel = torch.tensor(env.collider.velocity, dtype=DT).expand(S, 3).clone()
+    a, _ = O.rollout(env, prm, st, S)
+    b, _ = O.rollout(env, prm, st, S, vel=vel)
+    for u, w in zip(a, b):
+        np.testing.assert_allclose(u.numpy(), w.numpy(), rtol=0, atol=1e-12)
+    path = O.collider_path(env, vel)
+    for k in range(S):
+        np.testing.assert_allclose(path[k].numpy(), np.array(env.collider.center) + k * env.dt * vel[0].numpy(),
+                                   rtol=0, atol=1e-15)
+
+
+def test_moving_box_actually_pushes():
+    # the box is in contact: the final state depends on the actions
+    env, prm, st, vel = _moving_box(3, seed=40)
+    a, _ = O.rollout(env, prm, st, 3, vel=vel)
+    b, _ = O.rollout(env, prm, st, 3, vel=vel + 0.5)
+    assert (a[1] - b[1]).abs().max().item() > 1e-4
+
+
+def test_action_gradient_matches_forward_mode():
+    env, prm, st, vel = _moving_box(3, seed=41)
+    S = 3
+    rng = np.random.default_rng(42)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp, gvel, gc0 = O.rollout_vjp(env, prm, st, S, cot, vel=vel)
+    assert gvel.abs().max().item() > 0
+    zero = [torch.zeros_like(s) for s in st]
+    for _ in range(3):
+        tv = torch.from_numpy(rng.standard_normal((S, 3)))
+        out = O.rollout_jvp(env, prm, st, S, zero, torch.zeros(7, dtype=DT), vel=vel, vel_tangent=tv)
+        lhs = sum((a * b).sum() for a, b in zip(out, cot)).item()
+        rhs = (gvel * tv).sum().item()
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+def test_action_and_start_gradients_match_central_differences():
+    import dataclasses
+    env, prm, st, vel = _moving_box(3, seed=43)
+    S = 3
+    rng = np.random.default_rng(44)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp, gvel, gc0 = O.rollout_vjp(env, prm, st, S, cot, vel=vel)
+
+    def loss(e, vv):
+        (x, v, C, F), _ = O.rollout(e, prm, st, S, vel=vv)
+        return sum((a * b).sum() for a, b in zip((x, v, C, F), cot)).item()
+
+    for _ in range(3):
+        tv = torch.from_numpy(rng.standard_normal((S, 3)))
+        h = 1e-6
+        fd = (loss(env, vel + h * tv) - loss(env, vel - h * tv)) / (2 * h)
+        an = (gvel * tv).sum().item()
+        assert abs(fd - an) <= 1e-5 * max(abs(an), abs(fd)) + 1e-9, (fd, an)
+    # the starting center
+    for a in range(3):
+        h = 1e-7
+        cp = list(env.collider.center); cm = list(env.collider.center)
+        cp[a] += h; cm[a] -= h
+        ep = dataclasses.replace(env, collider=dataclasses.replace(env.collider, center=tuple(cp)))
+        em = dataclasses.replace(env, collider=dataclasses.replace(env.collider, center=tuple(cm)))
+        fd = (loss(ep, vel) - loss(em, vel)) / (2 * h)
+        an = gc0[a].item()
+        assert abs(fd - an) <= 1e-5 * max(abs(an), abs(fd)) + 1e-8, (a, fd, an)

@@ -139,6 +139,27 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
 int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const float half[3], const float vel[3],
                          float alpha, float mu_b);
 
+/* Drives env's box collider by per-substep velocities instead of its constant
+ * one: the actions of the paper's manipulation tasks move rigid bodies through
+ * the scene (Section 5 task descriptions; contact of Appendix D.3). vel is a
+ * HOST array [n][3] (m/s): during substep k (counted from the last
+ * mpm_set_particles) the box moves at vel[k] and its centre is
+ * center + dt sum_{j<k} vel[j], with `center` as given to mpm_set_box_collider
+ * (accumulated in FP64, stored as FP32). n = 0 (or vel = NULL) returns to the
+ * constant velocity. A forward past substep n - 1 fails with INVALID_ARG.
+ * Setting the collider again clears the motion. Copies vel; synchronizes the
+ * stream. Errors: INVALID_ARG (env out of range, n outside [0, max_substeps],
+ * no collider), NONFINITE. */
+int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t n);
+
+/* After mpm_backward: cotangents of the loss with respect to env's collider
+ * velocities and starting centre. dvel: HOST [n][3] doubles (n <= the motion
+ * length), dc0: HOST [3] doubles; either may be NULL. Includes every path:
+ * the velocity's direct part in the contact and its effect on all later
+ * centres (dt each). Synchronizes the stream. Errors: BAD_STATE if env has no
+ * prescribed motion, INVALID_ARG. */
+int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, int32_t n);
+
 /* Advances every environment by n_substeps (0 <= n <= max_substeps) from the
  * current state and clock. Particles are re-sorted by cell at every
  * checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)

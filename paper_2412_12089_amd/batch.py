@@ -110,6 +110,24 @@ class Batch:
         self._chk(self.lib.mpm_set_box_collider(self.h, env, f3(center), f3(half), f3(velocity),
                                                 float(alpha), float(mu_b)), "mpm_set_box_collider")
 
+    def set_collider_motion(self, env: int, vel) -> None:
+        """Per-substep box velocities [n, 3] (the actions); None or empty clears them."""
+        if vel is None or len(vel) == 0:
+            self._chk(self.lib.mpm_set_collider_motion(self.h, env, None, 0), "mpm_set_collider_motion")
+            return
+        v = np.ascontiguousarray(np.asarray(vel, dtype=np.float32).reshape(-1, 3))
+        buf = v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._chk(self.lib.mpm_set_collider_motion(self.h, env, buf, v.shape[0]), "mpm_set_collider_motion")
+
+    def collider_grad(self, env: int, n: int):
+        """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64."""
+        dvel = np.zeros((n, 3), np.float64)
+        dc0 = np.zeros(3, np.float64)
+        P = ctypes.POINTER(ctypes.c_double)
+        self._chk(self.lib.mpm_get_collider_grad(self.h, env, dvel.ctypes.data_as(P), dc0.ctypes.data_as(P), n),
+                  "mpm_get_collider_grad")
+        return dvel, dc0
+
     # -- state
     def set_particles(self, x, v, Cm, F, env: int = -1) -> None:
         d = self.device

@@ -41,6 +41,8 @@ struct EnvDev {
   float pad1[3];
   int64_t row_off;                       // first row of this env in the caller's concatenated arrays
   int64_t p_cap;                         // particle capacity (positions [p_off, p_off + p_cap))
+  int32_t motion_off, motion_len;        // prescribed collider motion: rows [motion_off, + motion_len) of the
+                                         // motion table, one per substep (len 0: constant velocity cv)
 };
 
 // --------------------------------------------------------------------------

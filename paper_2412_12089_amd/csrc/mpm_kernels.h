@@ -47,10 +47,14 @@ void launch_permute_state(const float* src, float* dst, int64_t N, const uint32_
 void launch_unpermute(const float* src, float* dst, int64_t N, const uint32_t* perm, hipStream_t s);
 void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                        uint32_t* flags, int32_t* errs, int k_call, hipStream_t s);
+// motion: per-substep (center, velocity) rows of prescribed collider motions;
+// gmotion: FP64 cotangents of those rows, accumulated by the grid adjoint
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
-                        uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, hipStream_t s);
+                        uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, const float* motion,
+                        hipStream_t s);
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
-                         uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, hipStream_t s);
+                         uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, const float* motion,
+                         double* gmotion, hipStream_t s);
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s);
 void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                        const float* grid, int32_t* errs, int k_call, hipStream_t s);

@@ -416,30 +416,52 @@ MD void node_coords(const EnvDev& e, int64_t tile, int l, int& i, int& j, int& k
 }
 
 struct Contact {
-  float n[3];
-  float s;
+  float n[3];     // outward unit normal (gradient of the distance)
+  float s;        // blend weight min(exp(-alpha d), 1)
+  float d;        // signed distance
+  float L;        // length of the outside part of (|rel| - half), 0 inside
+  int pos;        // bit a set when component a of (|rel| - half) is positive
 };
 
-MD Contact contact_geometry(const EnvDev& e, float t, int i, int j, int k) {
+MD Contact contact_geometry(const EnvDev& e, const float c[3], int i, int j, int k) {
   const float p[3] = {i * e.dx, j * e.dx, k * e.dx};
   float rel[3], q[3], qp[3];
+  Contact ct;
+  ct.pos = 0;
   for (int a = 0; a < 3; ++a) {
-    rel[a] = p[a] - fmaf(t, e.cv[a], e.cc[a]);
+    rel[a] = p[a] - c[a];
     q[a] = fabsf(rel[a]) - e.ch[a];
     qp[a] = fmaxf(q[a], 0.f);
+    if (q[a] > 0.f) ct.pos |= 1 << a;
   }
   const float out_len = sqrtf(qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2]);
   const float inside = fmaxf(q[0], fmaxf(q[1], q[2]));
-  const float d = out_len + fminf(inside, 0.f);
-  Contact c;
+  ct.d = out_len + fminf(inside, 0.f);
+  ct.L = out_len;
   if (out_len > 0.f) {
-    for (int a = 0; a < 3; ++a) c.n[a] = copysignf(1.f, rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;
+    for (int a = 0; a < 3; ++a) ct.n[a] = (rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;
   } else {
     const int ax = (q[0] >= q[1] && q[0] >= q[2]) ? 0 : (q[1] >= q[2] ? 1 : 2);
-    for (int a = 0; a < 3; ++a) c.n[a] = (a == ax) ? (rel[a] >= 0.f ? 1.f : -1.f) : 0.f;
+    for (int a = 0; a < 3; ++a) ct.n[a] = (a == ax) ? (rel[a] >= 0.f ? 1.f : -1.f) : 0.f;
   }
-  c.s = fminf(expf(-e.c_alpha * d), 1.f);
-  return c;
+  ct.s = fminf(expf(-e.c_alpha * ct.d), 1.f);
+  return ct;
+}
+
+// the box's center and velocity during substep clock + k_rel: a row of the
+// prescribed motion table, or the constant velocity from the center at t = 0
+MD void box_motion(const EnvDev& e, const float* __restrict__ motion, double t0, const int32_t* clock, int k_rel,
+                   float c[3], float vb[3], int& row) {
+  row = -1;
+  if (e.motion_len > 0) {
+    int k = clock[0] + k_rel;
+    k = k < 0 ? 0 : (k >= e.motion_len ? e.motion_len - 1 : k);
+    row = e.motion_off + k;
+    for (int a = 0; a < 3; ++a) { c[a] = motion[6 * row + a]; vb[a] = motion[6 * row + 3 + a]; }
+    return;
+  }
+  const float t = (float)(t0 + (double)(clock[0] + k_rel) * (double)e.dt);
+  for (int a = 0; a < 3; ++a) { vb[a] = e.cv[a]; c[a] = fmaf(t, e.cv[a], e.cc[a]); }
 }
 
 // friction projection of the velocity relative to the box; returns the case (0 free, 1 stick, 2 slide)
@@ -460,15 +482,12 @@ MD bool is_wall(const EnvDev& e, int i, int j, int k) {
   return i < lo || j < lo || k < lo || i > hi || j > hi || k > hi;
 }
 
-MD float substep_time(const EnvDev& e, double t0, const int32_t* clock, int k_rel) {
-  return (float)(t0 + (double)(clock[0] + k_rel) * (double)e.dt);
-}
 
 __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ envs,
                                                      const int32_t* __restrict__ tile_env, int64_t tile0,
                                                      int64_t ntiles, float* __restrict__ grid,
                                                      uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
-                                                     double t0, int k_rel, int clear) {
+                                                     double t0, int k_rel, int clear, const float* __restrict__ motion) {
   const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (tile >= tile0 + ntiles) return;
@@ -485,11 +504,14 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
     v[1] = fmaf(g[2 * CH], inv, e.dt * e.gy);
     v[2] = fmaf(g[3 * CH], inv, e.dt * e.gz);
     if (e.has_collider) {
-      const Contact c = contact_geometry(e, substep_time(e, t0, clock, k_rel), i, j, k);
+      float bc[3], bv[3];
+      int row;
+      box_motion(e, motion, t0, clock, k_rel, bc, bv, row);
+      const Contact c = contact_geometry(e, bc, i, j, k);
       float u[3], up[3], ut[3], un, utn;
-      for (int a = 0; a < 3; ++a) u[a] = v[a] - e.cv[a];
+      for (int a = 0; a < 3; ++a) u[a] = v[a] - bv[a];
       contact_project(e, c, u, up, un, ut, utn);
-      for (int a = 0; a < 3; ++a) v[a] = c.s * (e.cv[a] + up[a]) + (1.f - c.s) * v[a];
+      for (int a = 0; a < 3; ++a) v[a] = c.s * (bv[a] + up[a]) + (1.f - c.s) * v[a];
     }
   }
   if (is_wall(e, i, j, k)) v[0] = v[1] = v[2] = 0.f;
@@ -508,7 +530,8 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
                                                       const int32_t* __restrict__ tile_env, int64_t tile0,
                                                       int64_t ntiles, float* __restrict__ grid,
                                                       uint32_t* __restrict__ flags, float* __restrict__ gcot,
-                                                      const int32_t* __restrict__ clock, double t0, int k_rel) {
+                                                      const int32_t* __restrict__ clock, double t0, int k_rel,
+                                                      const float* __restrict__ motion, double* __restrict__ gmotion) {
   const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (tile >= tile0 + ntiles) return;
@@ -520,23 +543,27 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   float* gc = gcot + tile * 512 + l;
   const float m = g[0];
   const float P[3] = {g[CH], g[2 * CH], g[3 * CH]};
-  float vb[3] = {gc[0], gc[CH], gc[2 * CH]};
+  float vb[3] = {gc[0], gc[CH], gc[2 * CH]};   // cotangent of the node velocity
   float mb = 0.f, Pb[3] = {0.f, 0.f, 0.f};
+  float gmo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // cotangents of the box center (0-2) and velocity (3-5)
+  int row = -1;
   if (!is_wall(e, i, j, k) && m > 0.f) {
     const float inv = 1.f / m;
     const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
     if (e.has_collider) {
-      const Contact c = contact_geometry(e, substep_time(e, t0, clock, k_rel), i, j, k);
+      float bc[3], bv[3];
+      box_motion(e, motion, t0, clock, k_rel, bc, bv, row);
+      const Contact c = contact_geometry(e, bc, i, j, k);
       float u[3], up[3], ut[3], un, utn;
-      for (int a = 0; a < 3; ++a) u[a] = vpre[a] - e.cv[a];
+      for (int a = 0; a < 3; ++a) u[a] = vpre[a] - bv[a];
       const int kase = contact_project(e, c, u, up, un, ut, utn);
       float ub[3];
+      float uh[3] = {0.f, 0.f, 0.f};
       if (kase == 0) {
         for (int a = 0; a < 3; ++a) ub[a] = vb[a];
       } else if (kase == 1) {
         ub[0] = ub[1] = ub[2] = 0.f;
       } else {
-        float uh[3];
         for (int a = 0; a < 3; ++a) uh[a] = ut[a] / utn;
         const float nd = c.n[0] * vb[0] + c.n[1] * vb[1] + c.n[2] * vb[2];
         const float ud = uh[0] * vb[0] + uh[1] * vb[1] + uh[2] * vb[2];
@@ -544,6 +571,33 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
         for (int a = 0; a < 3; ++a) {
           const float pv = vb[a] - c.n[a] * nd;  // (I - n n^T) vbar
           ub[a] = pv + e.c_mu * (c.n[a] * ud + r * (pv - uh[a] * ud));
+        }
+      }
+      if (row >= 0) {
+        // v' = s (v_b + u') + (1 - s) v with u = v - v_b: the box velocity enters
+        // directly and through u; its center through s(d) and through n
+        float sbar = 0.f;
+        for (int a = 0; a < 3; ++a) {
+          gmo[3 + a] = c.s * (vb[a] - ub[a]);
+          sbar += vb[a] * (bv[a] + up[a] - vpre[a]);
+        }
+        if (c.d > 0.f)   // s = exp(-alpha d) below its cap; d(d)/d(center) = -n
+          for (int a = 0; a < 3; ++a) gmo[a] += sbar * e.c_alpha * c.s * c.n[a];
+        if (kase == 2 && __popc(c.pos) >= 2) {
+          // sliding: u' depends on n, and n = sgn (|rel| - h)^+ / L turns with the
+          // center near edges and corners: d n / d center = -(I_A - n n^T) / L
+          float w[3], Pw[3];
+          for (int a = 0; a < 3; ++a) w[a] = c.s * vb[a];
+          const float wu = w[0] * uh[0] + w[1] * uh[1] + w[2] * uh[2];
+          const float wn = w[0] * c.n[0] + w[1] * c.n[1] + w[2] * c.n[2];
+          const float r = un / utn;
+          for (int a = 0; a < 3; ++a) Pw[a] = w[a] - wu * uh[a];
+          float nb[3];
+          for (int a = 0; a < 3; ++a)
+            nb[a] = -(1.f + e.c_mu * r) * wn * u[a] - un * (w[a] + e.c_mu * r * Pw[a]) + e.c_mu * wu * u[a];
+          const float nn = c.n[0] * nb[0] + c.n[1] * nb[1] + c.n[2] * nb[2];
+          for (int a = 0; a < 3; ++a)
+            if (c.pos & (1 << a)) gmo[a] -= (nb[a] - c.n[a] * nn) / c.L;
         }
       }
       for (int a = 0; a < 3; ++a) vb[a] = (1.f - c.s) * vb[a] + c.s * ub[a];
@@ -559,6 +613,21 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
 #pragma unroll
   for (int c = 0; c < 7; ++c) g[c * CH] = 0.f;
   if (l == 0) flags[tile] = 0u;
+  // the wave is one tile of one env: sum its nodes' collider cotangents and add
+  // them to this substep's row in FP64
+  if (e.has_collider && e.motion_len > 0) {
+    const bool any = __ballot(row >= 0 && (gmo[0] != 0.f || gmo[1] != 0.f || gmo[2] != 0.f || gmo[3] != 0.f ||
+                                           gmo[4] != 0.f || gmo[5] != 0.f)) != 0ull;
+    if (any) {
+      int rw = row;
+      for (int off = 32; off > 0; off >>= 1) rw = max(rw, __shfl_xor(rw, off, 64));
+      for (int c = 0; c < 6; ++c) {
+        double x = (double)gmo[c];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (l == 0 && x != 0.0) atomicAdd(&gmotion[6 * (int64_t)rw + c], x);
+      }
+    }
+  }
 }
 
 // clears every flagged tile of a grid buffer and its flag (for an abandoned tape)
@@ -886,16 +955,18 @@ void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const Wor
   hipLaunchKernelGGL(k_p2g_direct, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call);
 }
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
-                        uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, hipStream_t s) {
+                        uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, const float* motion,
+                        hipStream_t s) {
   if (ntiles == 0) return;
   hipLaunchKernelGGL(k_grid_update, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid, flags,
-                     clock, t0, k_rel, clear);
+                     clock, t0, k_rel, clear, motion);
 }
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
-                         uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, hipStream_t s) {
+                         uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, const float* motion,
+                         double* gmotion, hipStream_t s) {
   if (ntiles == 0) return;
   hipLaunchKernelGGL(k_grid_adjoint, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid,
-                     flags, gcot, clock, t0, k_rel);
+                     flags, gcot, clock, t0, k_rel, motion, gmotion);
 }
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s) {
   if (ntiles == 0) return;

@@ -86,6 +86,9 @@ struct mpm_batch {
   double* pacc = nullptr;
   int32_t* errs = nullptr;
   int32_t* clock = nullptr;
+  float* motion_d = nullptr;     // prescribed collider motions: [E][max_substeps] rows (center, velocity)
+  double* gmotion_d = nullptr;   // their cotangents, same layout, FP64
+  std::vector<float> motion_h;
 
   // state
   float* cur = nullptr;
@@ -225,7 +228,7 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
       { Span sp(b, KC_P2G); launch_p2g_direct(in, b->N, b->envs_d, b->items_d + i0, ni, g, fl, b->errs, kc, s); }
-      { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, s); }
+      { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, b->motion_d, s); }
       { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, kc, s); }
     }
   } else {
@@ -241,7 +244,7 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
         else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, g, fl, b->errs, kc, b->grid_cap, b->box, r.mat, s);
       }
     }
-    { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, s); }
+    { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, b->motion_d, s); }
     {
       Span sp(b, KC_G2P);
       if (b->var_g2p == 0) launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
@@ -263,7 +266,7 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const 
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
       { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, kc, s); }
-      { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
+      { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, b->motion_d, b->gmotion_d, s); }
       { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, kc, cot_in, s); }
     }
   } else {
@@ -279,7 +282,7 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const 
         else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
       }
     }
-    { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, s); }
+    { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, b->motion_d, b->gmotion_d, s); }
     {
       Span sp(b, KC_P2G_ADJ);
       if (b->var_p2g_adj == 0) launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
@@ -529,6 +532,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     h.n = v.n; h.T = v.n / 4; h.material = v.material; h.wall = v.wall;
     h.p_off = p_off; h.p_cnt = v.n_particles; h.p_cap = v.n_particles; h.tile_off = t_off;
     h.row_off = p_off; h.nsub = 0;
+    h.motion_off = e * b->max_substeps; h.motion_len = 0;
     h.dt = v.dt; h.fn = (float)v.n; h.dx = 1.f / (float)v.n;
     h.gx = v.gravity[0]; h.gy = v.gravity[1]; h.gz = v.gravity[2];
     h.rho = 1.0; h.nu = 0.0;  // inert until mpm_set_material
@@ -594,6 +598,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->pacc = (double*)A(sizeof(double) * 8 * b->E);
   b->errs = (int32_t*)A(sizeof(int32_t) * b->E);
   b->clock = (int32_t*)A(256);
+  b->motion_d = (float*)A(sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
+  b->gmotion_d = (double*)A(sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
   if (!ok) {
     free_all(b);
     delete b;
@@ -613,6 +619,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     zero(b->W[0], state_bytes);
     zero(b->errs, sizeof(int32_t) * b->E);
     zero(b->clock, 256);
+    zero(b->motion_d, sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
+    zero(b->gmotion_d, sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
     // identity ids and an F = I rest state until particles are set
     rc = upload_envs(b);
   } while (0);
@@ -680,6 +688,7 @@ int mpm_configure_env(mpm_batch* b, int32_t env, const mpm_env_desc* d) {
   h.gx = d->gravity[0]; h.gy = d->gravity[1]; h.gz = d->gravity[2];
   h.p_cnt = d->n_particles;
   h.has_collider = 0;
+  h.motion_len = 0;
   refresh_layout(b);
   HIPC(b, hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice, b->stream));
   b->recorded = false;
@@ -724,9 +733,65 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const floa
       d.c_alpha = alpha;
       d.c_mu = mu_b;
     }
+    d.motion_len = 0;   // a prescribed motion starts from the collider it was set for
   }
   b->recorded = false;
   return upload_envs(b);
+}
+
+int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t n) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, false);
+  if (rc) return rc;
+  EnvDev& d = b->envs_h[env];
+  if (n < 0 || n > b->max_substeps) return fail(b, MPM_INVALID_ARG, "motion length outside [0, max_substeps]");
+  if (n > 0 && !vel) return fail(b, MPM_INVALID_ARG, "null velocity array");
+  if (n > 0 && !d.has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no collider");
+  for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
+    if (!std::isfinite(vel[i])) return fail(b, MPM_NONFINITE, "non-finite collider velocity");
+  if (n > 0) {
+    // center during substep k: c0 + dt sum_{j<k} vel_j, accumulated in FP64
+    b->motion_h.assign(6 * (size_t)n, 0.f);
+    double c[3] = {d.cc[0], d.cc[1], d.cc[2]};
+    for (int k = 0; k < n; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        b->motion_h[6 * k + a] = (float)c[a];
+        b->motion_h[6 * k + 3 + a] = vel[3 * k + a];
+      }
+      for (int a = 0; a < 3; ++a) c[a] += (double)d.dt * (double)vel[3 * k + a];
+    }
+    HIPC(b, hipMemcpyAsync(b->motion_d + 6 * (size_t)d.motion_off, b->motion_h.data(), sizeof(float) * 6 * (size_t)n,
+                           hipMemcpyHostToDevice, b->stream));
+    HIPC(b, hipStreamSynchronize(b->stream));   // the host rows are reused by the next call
+  }
+  d.motion_len = n;
+  b->recorded = false;
+  return upload_envs(b);
+}
+
+int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, int32_t n) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, false);
+  if (rc) return rc;
+  const EnvDev& d = b->envs_h[env];
+  if (d.motion_len == 0) return fail(b, MPM_BAD_STATE, "the environment has no prescribed collider motion");
+  if (n < 0 || n > d.motion_len) return fail(b, MPM_INVALID_ARG, "n outside [0, motion length]");
+  const int L = d.motion_len;
+  std::vector<double> g(6 * (size_t)L);
+  HIPC(b, hipMemcpyAsync(g.data(), b->gmotion_d + 6 * (size_t)d.motion_off, sizeof(double) * g.size(),
+                         hipMemcpyDeviceToHost, b->stream));
+  HIPC(b, hipStreamSynchronize(b->stream));
+  // row k holds the cotangents of (center_k, velocity_k); center_k depends on
+  // every earlier velocity (dt each) and on c0
+  double later[3] = {0.0, 0.0, 0.0};   // sum over k > j of the center cotangents
+  for (int j = L - 1; j >= 0; --j) {
+    if (j < n && dvel)
+      for (int a = 0; a < 3; ++a) dvel[3 * j + a] = g[6 * j + 3 + a] + (double)d.dt * later[a];
+    for (int a = 0; a < 3; ++a) later[a] += g[6 * j + a];
+  }
+  if (dc0)
+    for (int a = 0; a < 3; ++a) dc0[a] = later[a];
+  return MPM_OK;
 }
 
 int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
@@ -737,6 +802,9 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
       return fail(b, MPM_BAD_STATE, "n_substeps outside [0, max_substeps]");
     S = std::max(S, n_substeps[e]);
   }
+  for (int e = 0; e < b->E; ++e)
+    if (b->envs_h[e].motion_len > 0 && n_substeps[e] > 0 && b->steps + n_substeps[e] > b->envs_h[e].motion_len)
+      return fail(b, MPM_INVALID_ARG, "the collider motion of an environment is shorter than the rollout");
   bool changed = false;
   for (int e = 0; e < b->E; ++e) {
     changed |= b->envs_h[e].nsub != n_substeps[e];
@@ -792,6 +860,7 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
   const hipStream_t s = b->stream;
   if (b->timing) { b->spans.clear(); b->event_next = 0; }
   launch_fill_u32(b->pacc, 0u, 2 * 8 * (int64_t)b->E, s);
+  launch_fill_u32(b->gmotion_d, 0u, 2 * 6 * (int64_t)b->E * b->max_substeps, s);
   const int S = b->rec_S;
   const int nseg = (S + b->K - 1) / b->K;
   int c = 0;

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from conftest import gpu_available
-from gpu_util import (env_slices, gpu_rollout, make_env, oracle_rollout, random_cotangents, relerr)
+from gpu_util import (env_slices, gpu_rollout, make_env, oracle_rollout, random_cotangents, relerr, to_np)
 from oracle import mpm_oracle as O
 from paper_2412_12089_amd import scenes
 
@@ -147,6 +147,97 @@ def test_box_collider_forward_and_gradient():
     check_state(g["state"], o["state"], "collider")
     check_grads(g["grads"], o["grads"], "collider")
     check_params(g["dparams"][0], o["dparams"], [5], "collider")
+
+
+# ------------------------------------------------------------------ a box driven by per-substep velocities
+BOXES = {   # the particles meet the box's face, or slide past one of its edges (normal turning with the center)
+    "face": scenes.BoxCollider(center=(0.62, 0.46, 0.46), half=(0.04, 0.2, 0.2), velocity=(-0.5, 0.0, 0.0),
+                               alpha=64.0, mu_b=0.5),
+    "edge": scenes.BoxCollider(center=(0.61, 0.63, 0.46), half=(0.04, 0.07, 0.2), velocity=(-0.4, -0.3, 0.0),
+                               alpha=64.0, mu_b=0.3),
+}
+
+
+def test_edge_box_has_sliding_edge_nodes():
+    # the oracle's view of the edge case: some active nodes are outside two faces at once and slide
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=44, collider=BOXES["edge"], v_scale=0.2)
+    env, prm, (x, v, C, F) = O.env_from_spec(spec)
+    gm, gP, _ = O.p2g(env, prm, x, v, C, F)
+    pos = gm > 0
+    center, vb = O.collider_motion(env, 0.0)
+    rel = O.node_positions(env.n) - center
+    q = rel.abs() - torch.tensor(env.collider.half, dtype=torch.float64)
+    d, nh = O.box_sdf(O.node_positions(env.n), center, torch.tensor(env.collider.half, dtype=torch.float64))
+    vel = torch.where(pos[:, None], gP / torch.where(pos, gm, torch.ones_like(gm))[:, None], torch.zeros_like(gP))
+    u = vel - vb
+    un = (u * nh).sum(1)
+    ut = (u - un[:, None] * nh).norm(dim=1)
+    edge = pos & ((q > 0).sum(1) >= 2) & (un < 0) & (ut > -env.collider.mu_b * un) & (d < 4.0 / env.collider.alpha)
+    assert int(edge.sum()) > 0
+
+
+@pytest.mark.parametrize("geom", ["face", "edge"])
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_collider_actions_forward_and_gradient(mode, geom):
+    from paper_2412_12089_amd.batch import Batch
+    box = BOXES[geom]
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=44, collider=box, v_scale=0.2)
+    other = make_env(scenes.NEOHOOKEAN, N=1200, seed=45)   # no prescribed motion, same batch
+    S, K = 10, 4
+    rng = np.random.default_rng(46)
+    vel = (np.array(box.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+    announce(f"tait + box ({geom}) driven by {S} actions, {mode}")
+    envs = [spec, other]
+    cots = random_cotangents(envs, seed=47)
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode)
+    try:
+        b.set_particles_from_specs()
+        b.set_collider_motion(0, vel)
+        b.forward(S, record=True)
+        st = tuple(to_np(t) for t in b.get_particles(env=0))
+        cat = lambda i: torch.from_numpy(np.concatenate([c[i] for c in cots], axis=0))
+        dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+        N0 = spec.n_particles
+        gr = tuple(to_np(t)[:N0] for t in (dx, dv, dC, dF))
+        dvel, dc0 = b.collider_grad(0, S)
+        assert b.sync(raise_on_error=False) == 0
+        with pytest.raises(Exception):
+            b.collider_grad(1, S)          # env 1 has no prescribed motion
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    velt = torch.from_numpy(vel).double()
+    (x, v, C, F), _ = O.rollout(env, prm, st0, S, vel=velt)
+    c = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).double() for a in cots[0])
+    g, gp, gvel, gc0 = O.rollout_vjp(env, prm, st0, S, c, vel=velt)
+    check_state(st, tuple(t.numpy() for t in (x, v, C, F)), "actions")
+    check_grads(gr, tuple(t.numpy() for t in g), "actions")
+    ev, ec = relerr(dvel, gvel.numpy()), relerr(dc0, gc0.numpy())
+    announce(f"actions: dL/dvel rel {ev:.2e}, dL/dc0 rel {ec:.2e}, |dL/dvel| {np.abs(gvel.numpy()).max():.3e}")
+    assert np.abs(gvel.numpy()).max() > 0
+    assert ev < 1e-3 and ec < 1e-3
+
+
+def test_collider_actions_bounds():
+    from paper_2412_12089_amd.batch import Batch
+    from paper_2412_12089_amd._capi import MPMError
+    box = scenes.BoxCollider(center=(0.62, 0.46, 0.46), half=(0.04, 0.2, 0.2), velocity=(-0.5, 0.0, 0.0),
+                             alpha=64.0, mu_b=0.5)
+    spec = make_env(scenes.FLUID_TAIT, N=500, seed=48, collider=box)
+    b = Batch([spec], max_substeps=6, ckpt_every=3)
+    try:
+        b.set_particles_from_specs()
+        b.set_collider_motion(0, np.zeros((4, 3), np.float32))
+        with pytest.raises(MPMError):
+            b.forward(6)                    # the motion covers 4 substeps only
+        b.forward(4)
+        with pytest.raises(MPMError):
+            b.set_collider_motion(0, np.full((2, 3), np.nan, np.float32))
+        b.set_collider_motion(0, None)      # back to the constant velocity
+        b.forward(2)
+        assert b.sync(raise_on_error=False) == 0
+    finally:
+        b.close()
 
 
 # ------------------------------------------------------------------ batching and checkpoint invariances

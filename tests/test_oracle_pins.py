@@ -429,8 +429,12 @@ def test_von_mises_tiny_scene_is_plastic():
 
 
 # ---------------------------------------------------------------- prescribed collider motion (actions)
-def _moving_box(S, seed):
+def _moving_box(S, seed, edge=False):
+    import dataclasses
     env, prm, st = tiny(O.FLUID_TAIT, collider=True)
+    if edge:   # the blob meets the box along an edge, where the normal turns with the center
+        env = dataclasses.replace(env, collider=dataclasses.replace(env.collider, center=(0.6, 0.6, 0.45),
+                                                                    half=(0.05, 0.06, 0.2), mu_b=0.3))
     rng = np.random.default_rng(seed)
     vb = torch.tensor(env.collider.velocity, dtype=DT)
     vel = vb + 0.2 * torch.from_numpy(rng.standard_normal((S, 3)))
@@ -476,9 +480,10 @@ def test_action_gradient_matches_forward_mode():
         assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs)), (lhs, rhs)
 
 
-def test_action_and_start_gradients_match_central_differences():
+@pytest.mark.parametrize("edge", [False, True])
+def test_action_and_start_gradients_match_central_differences(edge):
     import dataclasses
-    env, prm, st, vel = _moving_box(3, seed=43)
+    env, prm, st, vel = _moving_box(3, seed=43, edge=edge)
     S = 3
     rng = np.random.default_rng(44)
     cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]

@@ -102,16 +102,19 @@ class Batch:
 
     # -- parameters
     def set_material(self, env: int, material: int, params) -> None:
+        self.record_token += 1   # the library drops its recorded tape
         p = (ctypes.c_double * 8)(*[float(v) for v in np.asarray(params, dtype=np.float64).reshape(8)])
         self._chk(self.lib.mpm_set_material(self.h, env, material, p), "mpm_set_material")
 
     def set_box_collider(self, env: int, center, half, velocity, alpha: float, mu_b: float) -> None:
+        self.record_token += 1   # the library drops its recorded tape
         f3 = lambda a: (ctypes.c_float * 3)(*[float(x) for x in a])
         self._chk(self.lib.mpm_set_box_collider(self.h, env, f3(center), f3(half), f3(velocity),
                                                 float(alpha), float(mu_b)), "mpm_set_box_collider")
 
     def set_collider_motion(self, env: int, vel) -> None:
         """Per-substep box velocities [n, 3] (the actions); None or empty clears them."""
+        self.record_token += 1   # the library drops its recorded tape
         if vel is None or len(vel) == 0:
             self._chk(self.lib.mpm_set_collider_motion(self.h, env, None, 0), "mpm_set_collider_motion")
             return
@@ -130,6 +133,7 @@ class Batch:
 
     # -- state
     def set_particles(self, x, v, Cm, F, env: int = -1) -> None:
+        self.record_token += 1   # the library drops its recorded tape
         d = self.device
         x, v, Cm, F = (_f32(t, d) for t in (x, v, Cm, F))
         n = x.shape[0]
@@ -155,17 +159,16 @@ class Batch:
     # -- stepping
     def forward(self, n_substeps: int, record: bool = False) -> None:
         self._chk(self.lib.mpm_forward(self.h, int(n_substeps), C.MPM_FWD_RECORD if record else 0), "mpm_forward")
-        if record:
-            self.record_token += 1
+        self.record_token += 1   # any forward replaces (or drops) the recorded tape
 
     def forward_envs(self, n_substeps, record: bool = False) -> None:
         arr = (ctypes.c_int32 * self.E)(*[int(k) for k in n_substeps])
         self._chk(self.lib.mpm_forward_envs(self.h, arr, C.MPM_FWD_RECORD if record else 0), "mpm_forward_envs")
-        if record:
-            self.record_token += 1
+        self.record_token += 1
 
     def configure_env(self, env: int, spec: EnvSpec) -> None:
         """Re-describe slot `env` (within its capacity) and set its material and particles."""
+        self.record_token += 1   # the library drops its recorded tape
         d = C.mpm_env_desc()
         d.n, d.material, d.n_particles, d.dt, d.wall = spec.n, spec.material, spec.n_particles, spec.dt, spec.wall
         d.gravity[:] = list(spec.gravity)
@@ -239,40 +242,58 @@ class Batch:
 
 
 class MPMRollout(torch.autograd.Function):
-    """s_S = f^S(s_0; params) through the library, differentiable in s_0 and params.
+    """s_S = f^S(s_0; params, actions) through the library, differentiable in s_0,
+    params and actions.
 
     params: [E, 8] float64 (E, nu, rho, Vp, sigma_y, K, gamma, 0) per env.
+    actions: None or [E, S, 3] per-substep velocities of each env's box
+    collider (rows of envs without a collider are ignored; their gradient is 0).
     If the batch has been re-used since this call's forward, the backward
     first re-runs the forward from the saved inputs (frame-level checkpoint).
     """
 
     @staticmethod
-    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params):
+    def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions):
         prm = params.detach().to("cpu", torch.float64).numpy()
         for i, e in enumerate(batch.envs):
             batch.set_material(i, e.material, prm[i])
+        if actions is not None:
+            act = actions.detach().to("cpu", torch.float32).numpy()
+            for i, e in enumerate(batch.envs):
+                if e.collider is not None:
+                    batch.set_collider_motion(i, act[i, :n_substeps])
         batch.set_particles(x, v, Cm, F)
         batch.forward(n_substeps, record=True)
+
+    @staticmethod
+    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None):
+        MPMRollout._setup(batch, n_substeps, x, v, Cm, F, params, actions)
         ctx.batch = batch
         ctx.n_substeps = n_substeps
         ctx.token = batch.record_token
-        ctx.save_for_backward(x, v, Cm, F, params)
+        ctx.has_actions = actions is not None
+        ctx.save_for_backward(x, v, Cm, F, params, actions if actions is not None else torch.empty(0))
         return batch.get_particles()
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
         b = ctx.batch
-        x, v, Cm, F, params = ctx.saved_tensors
+        x, v, Cm, F, params, actions = ctx.saved_tensors
+        actions = actions if ctx.has_actions else None
         if b.record_token != ctx.token:
-            prm = params.detach().to("cpu", torch.float64).numpy()
-            for i, e in enumerate(b.envs):
-                b.set_material(i, e.material, prm[i])
-            b.set_particles(x, v, Cm, F)
-            b.forward(ctx.n_substeps, record=True)
+            MPMRollout._setup(b, ctx.n_substeps, x, v, Cm, F, params, actions)
             ctx.token = b.record_token
         dx, dv, dC, dF, dp = b.backward(gx, gv, gC, gF)
-        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype)
+        da = None
+        if actions is not None:
+            da = torch.zeros(actions.shape, dtype=torch.float64)
+            for i, e in enumerate(b.envs):
+                if e.collider is not None:
+                    dvel, _ = b.collider_grad(i, ctx.n_substeps)
+                    da[i, :ctx.n_substeps] = torch.from_numpy(dvel)
+            da = da.to(actions.device, actions.dtype)
+        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da
 
 
-def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params):
-    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params)
+def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None):
+    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params, actions)

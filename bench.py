@@ -93,7 +93,7 @@ def parse():
                     choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh"])
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-substeps", type=int, default=2)
+    ap.add_argument("--cpu-substeps", type=int, default=40, help="substeps of the oracle sample (about 10-20 s)")
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
     ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
     ap.add_argument("--tune-ms", type=int, default=4000, help="autotuner budget (0: library defaults)")
@@ -151,7 +151,7 @@ def serving_leg(seconds, rate, slots, device):
     reqs = scenes.serving_stream(seed=5, rate=rate, duration=seconds)
     ex = GPUExecutor(slots, n_cap=64, N_cap=100_000, chunk=10, device=device)
     free = torch.cuda.mem_get_info(device)[0]
-    srv = Server(ex, budget_bytes=int(0.25 * free), chunk=10)
+    srv = Server(ex, budget_bytes=int(0.25 * free), chunk=10, keep_results=False)
     srv.run(reqs, realtime=True, timeout_s=max(120.0, 20 * seconds))
     st = srv.stats()
     ex.close()

@@ -36,10 +36,11 @@ GRID_NODE_BYTES = 32      # m, P, v (+ pad) per node of a slot's grid
 
 
 def resident_bytes(req: Request, chunk: int) -> int:
-    """Bytes a request keeps on the device while it is admitted."""
+    """Bytes a request keeps on the device while it is admitted: its state, and
+    for a backward the chunk checkpoints and the cotangent it carries back."""
     N = req.env.n_particles
     nchunks = -(-req.substeps // chunk)
-    ck = nchunks if req.backward else 0
+    ck = nchunks + 1 if req.backward else 0      # chunk checkpoints and the running cotangent
     return N * STATE_BYTES * (1 + ck) + req.env.n ** 3 * GRID_NODE_BYTES
 
 
@@ -74,8 +75,10 @@ class _Active:
 
 
 class Server:
-    def __init__(self, executor, budget_bytes: int, chunk: int = 10, clock: Optional[Callable[[], float]] = None):
+    def __init__(self, executor, budget_bytes: int, chunk: int = 10, clock: Optional[Callable[[], float]] = None,
+                 keep_results: bool = True):
         self.ex = executor
+        self.keep_results = keep_results   # False: finished results keep timing and status only
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
         self.queue: collections.deque = collections.deque()
@@ -138,6 +141,8 @@ class Server:
         a = self.active.pop(slot)
         a.result.status = status
         a.result.finished = self.now()
+        if not self.keep_results:
+            a.result.state = a.result.grads = a.result.dparams = None
         self.done[a.req.rid] = a.result
         self.used -= a.nbytes
         self.ex.unload(slot)
@@ -315,7 +320,9 @@ class GPUExecutor:
         out = {}
         for s in cots:
             lo, hi = int(b.offsets[s]), int(b.offsets[s + 1])
-            out[s] = ((dx[lo:hi], dv[lo:hi], dC[lo:hi], dF[lo:hi]), dp[s].cpu().numpy())
+            # copies: a view would keep the whole batch-wide output alive as long as the request does
+            out[s] = ((dx[lo:hi].clone(), dv[lo:hi].clone(), dC[lo:hi].clone(), dF[lo:hi].clone()),
+                      dp[s].cpu().numpy())
         return out
 
     def read(self, slot: int):

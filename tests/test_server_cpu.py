@@ -124,3 +124,13 @@ def test_serving_stream_generator_is_seeded_and_shaped():
         assert (r.env.x >= (scenes.WALL + 1) / n - 1e-6).all() and (r.env.x < 1 - (scenes.WALL + 1) / n).all()
     arr = np.array([r.arrival for r in a])
     assert (np.diff(arr) > 0).all()
+
+
+def test_results_can_be_dropped_for_throughput_runs():
+    # keep_results=False: finished requests keep status and timing only (a long stream holds no tensors)
+    reqs = small_requests(n=4)
+    ex = OracleExecutor(2, n_cap=16, N_cap=200)
+    srv = Server(ex, 10 ** 9, chunk=4, clock=FakeClock(), keep_results=False)
+    done = srv.run(reqs, realtime=False)
+    assert all(r.status == "ok" and r.state is None and r.grads is None for r in done.values())
+    assert srv.stats()["ok"] == len(reqs)

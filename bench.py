@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched_corot",
-                    choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh"])
+                    choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh", "handflip_shape"])
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-substeps", type=int, default=40, help="substeps of the oracle sample (about 10-20 s)")

@@ -535,3 +535,31 @@ def linear_loss_cotangent(weights: np.ndarray, N: int):
     """Cotangents of L = sum_p x_p . w_p: d/dx = w, zero for v, C, F."""
     w = torch.from_numpy(np.asarray(weights, dtype=np.float32)).to(DT)
     return (w, torch.zeros(N, 3, dtype=DT), torch.zeros(N, 3, 3, dtype=DT), torch.zeros(N, 3, 3, dtype=DT))
+
+
+# ----------------------------------------------------------------------------
+# Observation / reward statistics of the manipulation tasks (Appendix E: the
+# centre of mass of a subsampled particle set, the variance of its heights,
+# mean velocities), as per-env weighted moments
+# ----------------------------------------------------------------------------
+MOMENT_NAMES = ("w", "x", "y", "z", "xx", "yy", "zz", "xy", "xz", "yz",
+                "vx", "vy", "vz", "vxvx", "vyvy", "vzvz", "vxvy", "vxvz", "vyvz")
+
+
+def moments(x, v, w):
+    """Per-env weighted moments [19]: sum w, sum w x (3), sum w x x^T (xx yy zz xy xz yz),
+    the same two for v. x, v: [N, 3]; w: [N] weights (0/1 selects a subsample)."""
+    x, v, w = (torch.as_tensor(a, dtype=DT) for a in (x, v, w))
+
+    def second(a):
+        return torch.stack([(w * a[:, i] * a[:, j]).sum() for i, j in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))])
+
+    return torch.cat([w.sum()[None], (w[:, None] * x).sum(0), second(x), (w[:, None] * v).sum(0), second(v)])
+
+
+def moment_stats(m):
+    """Centre of mass, height variance and mean velocity from one env's moments."""
+    com = m[1:4] / m[0]
+    var_z = m[6] / m[0] - com[2] ** 2
+    vbar = m[10:13] / m[0]
+    return com, var_z, vbar

@@ -162,6 +162,27 @@ def batched_corot(seed: int = 2, n_envs: int = 32, n_per_env: int = 20000,
     return Workload("batched_corot", envs, n_substeps, ckpt_every, [w.copy() for _ in envs])
 
 
+def handflip_shape(seed: int = 6, n_envs: int = 128, n_per_env: int = 2500, n_substeps: int = 40,
+                   ckpt_every: int = 10) -> Workload:
+    """The shape of the paper's own MPM throughput study (HandFlip: 48^3 grid,
+    2,500 dough particles per env, von Mises E = 4000, nu = 0.2, sigma_y = 130,
+    rho = 1, 40 substeps per frame, up to 128 envs). The hand is not modelled:
+    each env is a seeded block of dough of side 0.14 moving at random
+    velocities, which stands in for the hand-driven scene."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    envs, ws = [], []
+    side = np.full(3, 0.14)
+    for _ in range(n_envs):
+        lo = 0.5 - side / 2 + rng.uniform(-0.05, 0.05, size=3)
+        x = uniform_points(rng, lo, side, n_per_env)
+        v = _f32(rng.uniform(-0.5, 0.5, size=(n_per_env, 3)))
+        C, F = _rest_state(n_per_env)
+        envs.append(EnvSpec(n=48, dt=5e-5, material=VONMISES, E=4000.0, nu=0.2, rho=1.0, sigma_y=130.0,
+                            Vp=float(np.prod(side)) / n_per_env, x=x, v=v, C=C, F=F))
+        ws.append(_f32(rng.standard_normal((n_per_env, 3))))
+    return Workload("handflip_shape", envs, n_substeps, ckpt_every, ws)
+
+
 MIXED_MATERIALS = (
     dict(material=NEOHOOKEAN, E=5e3, nu=0.3),
     dict(material=VONMISES, E=5e3, nu=0.2, sigma_y=50.0),
@@ -254,6 +275,7 @@ def serving_stream(seed: int = 5, rate: float = 200.0, duration: float = 60.0,
 
 WORKLOADS = {
     "single_nh": single_nh,
+    "handflip_shape": handflip_shape,
     "batched_corot": batched_corot,
     "uneven_mixed": uneven_mixed,
     "dam_break": dam_break,

@@ -509,3 +509,23 @@ def test_action_and_start_gradients_match_central_differences(edge):
         fd = (loss(ep, vel) - loss(em, vel)) / (2 * h)
         an = gc0[a].item()
         assert abs(fd - an) <= 1e-5 * max(abs(an), abs(fd)) + 1e-8, (a, fd, an)
+
+
+# ---------------------------------------------------------------- observation / reward moments
+def test_moments_match_their_definitions():
+    rng = np.random.default_rng(50)
+    x = rng.uniform(0.2, 0.8, size=(500, 3))
+    v = rng.standard_normal((500, 3))
+    w = np.ones(500)
+    m = O.moments(x, v, w).numpy()
+    com, var_z, vbar = (t.numpy() if hasattr(t, "numpy") else t for t in O.moment_stats(torch.from_numpy(m)))
+    np.testing.assert_allclose(com, x.mean(0), rtol=1e-13)
+    np.testing.assert_allclose(var_z, x[:, 2].var(), rtol=1e-11)
+    np.testing.assert_allclose(vbar, v.mean(0), rtol=1e-13)
+    np.testing.assert_allclose(m[7], (x[:, 0] * x[:, 1]).sum(), rtol=1e-13)
+    np.testing.assert_allclose(m[17], (v[:, 0] * v[:, 2]).sum(), rtol=1e-13)
+    # a 0/1 weight pattern is the subsample itself
+    sub = np.zeros(500)
+    sub[::7] = 1.0
+    np.testing.assert_allclose(O.moments(x, v, sub).numpy(), O.moments(x[::7], v[::7], np.ones(len(x[::7]))).numpy(),
+                               rtol=1e-13)

@@ -160,6 +160,26 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t
  * prescribed motion, INVALID_ARG. */
 int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, int32_t n);
 
+#define MPM_MOMENTS 20   /* stride of one env's moments */
+
+/* Per-env weighted moments of particle positions and velocities: the
+ * statistics the manipulation tasks observe and reward (centre of mass of a
+ * subsampled particle set, variance of its heights, mean velocity; paper
+ * Appendix E task definitions). x, v: DEVICE arrays [rows][3] in the caller's
+ * concatenated env order (as mpm_get_particles writes them); w: DEVICE [rows]
+ * weights, NULL for all ones (a 0/1 pattern selects a subsample). out: DEVICE
+ * [n_envs][MPM_MOMENTS] doubles, per env: [0] sum w, [1..3] sum w x,
+ * [4..9] sum w (xx, yy, zz, xy, xz, yz), [10..12] sum w v, [13..18] the same
+ * products of v, [19] 0. Accumulated in FP64; asynchronous on the stream.
+ * Errors: INVALID_ARG for a null x, v or out. */
+int mpm_moments(mpm_batch* b, const float* x, const float* v, const float* w, double* out);
+
+/* VJP of mpm_moments: gout DEVICE [n_envs][MPM_MOMENTS] cotangents -> gx, gv
+ * DEVICE [rows][3] (written, not added; either may be NULL). Same x, v, w as
+ * the forward. Asynchronous on the stream. */
+int mpm_moments_vjp(mpm_batch* b, const float* x, const float* v, const float* w, const double* gout, float* gx,
+                    float* gv);
+
 /* Advances every environment by n_substeps (0 <= n <= max_substeps) from the
  * current state and clock. Particles are re-sorted by cell at every
  * checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)

@@ -35,8 +35,9 @@ EXPORTED = (
     "mpm_set_box_collider", "mpm_forward", "mpm_backward", "mpm_autotune", "mpm_sync", "mpm_env_errors",
     "mpm_memory_bytes", "mpm_kernel_time", "mpm_set_timing", "mpm_last_error", "mpm_version", "mpm_sort_keys",
     "mpm_set_option", "mpm_get_option", "mpm_forward_envs", "mpm_configure_env", "mpm_set_collider_motion",
-    "mpm_get_collider_grad",
+    "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
 )
+MPM_MOMENTS = 20
 OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_configure_env": (I32, [VP, I32, P(mpm_env_desc)]),
         "mpm_set_collider_motion": (I32, [VP, I32, F3, I32]),
         "mpm_get_collider_grad": (I32, [VP, I32, D8, D8, I32]),
+        "mpm_moments": (I32, [VP, VP, VP, VP, VP]),
+        "mpm_moments_vjp": (I32, [VP, VP, VP, VP, VP, VP, VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

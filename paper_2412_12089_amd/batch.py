@@ -122,6 +122,23 @@ class Batch:
         buf = v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         self._chk(self.lib.mpm_set_collider_motion(self.h, env, buf, v.shape[0]), "mpm_set_collider_motion")
 
+    def moments(self, x, v, w=None):
+        """Per-env weighted moments [E, 20] float64 of caller-order x, v (device)."""
+        d = self.device
+        x, v = _f32(x, d), _f32(v, d)
+        out = torch.empty(self.E, C.MPM_MOMENTS, dtype=torch.float64, device=d)
+        self._chk(self.lib.mpm_moments(self.h, C.ptr(x), C.ptr(v), C.ptr(w), C.ptr(out)), "mpm_moments")
+        return out
+
+    def moments_vjp(self, x, v, w, g):
+        d = self.device
+        x, v = _f32(x, d), _f32(v, d)
+        g = g.to(d, torch.float64).contiguous()
+        gx, gv = torch.empty_like(x), torch.empty_like(v)
+        self._chk(self.lib.mpm_moments_vjp(self.h, C.ptr(x), C.ptr(v), C.ptr(w), C.ptr(g), C.ptr(gx), C.ptr(gv)),
+                  "mpm_moments_vjp")
+        return gx, gv
+
     def collider_grad(self, env: int, n: int):
         """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64."""
         dvel = np.zeros((n, 3), np.float64)

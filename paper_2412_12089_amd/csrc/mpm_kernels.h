@@ -86,4 +86,10 @@ void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* 
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                             int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 
+// per-env weighted moments of caller-order x, v (see mpm_observe.hip) and their VJP
+void launch_moments(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
+                    const float* w, double* out, int n_envs, hipStream_t s);
+void launch_moments_vjp(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
+                        const float* w, const double* g, float* gx, float* gv, hipStream_t s);
+
 }  // namespace mpmx

@@ -794,6 +794,23 @@ int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, 
   return MPM_OK;
 }
 
+int mpm_moments(mpm_batch* b, const float* x, const float* v, const float* w, double* out) {
+  if (!b) return MPM_INVALID_ARG;
+  if (!x || !v || !out) return fail(b, MPM_INVALID_ARG, "null array");
+  launch_moments(b->items_d, (int)b->items_h.size(), b->envs_d, x, v, w, out, b->E, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_moments_vjp(mpm_batch* b, const float* x, const float* v, const float* w, const double* gout, float* gx,
+                    float* gv) {
+  if (!b) return MPM_INVALID_ARG;
+  if (!x || !v || !gout) return fail(b, MPM_INVALID_ARG, "null array");
+  launch_moments_vjp(b->items_d, (int)b->items_h.size(), b->envs_d, x, v, w, gout, gx, gv, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
 int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
   if (!b || !n_substeps) return MPM_INVALID_ARG;
   int32_t S = 0;

@@ -259,21 +259,29 @@ class Batch:
 
 
 class MPMRollout(torch.autograd.Function):
-    """s_S = f^S(s_0; params, actions) through the library, differentiable in s_0,
-    params and actions.
+    """s_S = f^S(s_0; params, actions, centers) through the library,
+    differentiable in s_0, params, actions and centers.
 
     params: [E, 8] float64 (E, nu, rho, Vp, sigma_y, K, gamma, 0) per env.
     actions: None or [E, S, 3] per-substep velocities of each env's box
-    collider (rows of envs without a collider are ignored; their gradient is 0).
-    If the batch has been re-used since this call's forward, the backward
-    first re-runs the forward from the saved inputs (frame-level checkpoint).
+    collider; centers: None or [E, 3] the boxes' centers at the first substep
+    (default: the centers the envs were created with). Rows of envs without a
+    collider are ignored and get zero gradients. If the batch has been re-used
+    since this call's forward, the backward first re-runs the forward from the
+    saved inputs (frame-level checkpoint), so calls can be chained.
     """
 
     @staticmethod
-    def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions):
+    def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions, centers):
         prm = params.detach().to("cpu", torch.float64).numpy()
         for i, e in enumerate(batch.envs):
             batch.set_material(i, e.material, prm[i])
+        if centers is not None:
+            cen = centers.detach().to("cpu", torch.float64).numpy()
+            for i, e in enumerate(batch.envs):
+                c = e.collider
+                if c is not None:
+                    batch.set_box_collider(i, cen[i], c.half, c.velocity, c.alpha, c.mu_b)
         if actions is not None:
             act = actions.detach().to("cpu", torch.float32).numpy()
             for i, e in enumerate(batch.envs):
@@ -283,34 +291,45 @@ class MPMRollout(torch.autograd.Function):
         batch.forward(n_substeps, record=True)
 
     @staticmethod
-    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None):
-        MPMRollout._setup(batch, n_substeps, x, v, Cm, F, params, actions)
+    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None):
+        MPMRollout._setup(batch, n_substeps, x, v, Cm, F, params, actions, centers)
         ctx.batch = batch
         ctx.n_substeps = n_substeps
         ctx.token = batch.record_token
-        ctx.has_actions = actions is not None
-        ctx.save_for_backward(x, v, Cm, F, params, actions if actions is not None else torch.empty(0))
+        ctx.flags = (actions is not None, centers is not None)
+        empty = torch.empty(0)
+        ctx.save_for_backward(x, v, Cm, F, params, actions if actions is not None else empty,
+                              centers if centers is not None else empty)
         return batch.get_particles()
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
         b = ctx.batch
-        x, v, Cm, F, params, actions = ctx.saved_tensors
-        actions = actions if ctx.has_actions else None
+        x, v, Cm, F, params, actions, centers = ctx.saved_tensors
+        actions = actions if ctx.flags[0] else None
+        centers = centers if ctx.flags[1] else None
         if b.record_token != ctx.token:
-            MPMRollout._setup(b, ctx.n_substeps, x, v, Cm, F, params, actions)
+            MPMRollout._setup(b, ctx.n_substeps, x, v, Cm, F, params, actions, centers)
             ctx.token = b.record_token
         dx, dv, dC, dF, dp = b.backward(gx, gv, gC, gF)
-        da = None
+        da = dcen = None
         if actions is not None:
             da = torch.zeros(actions.shape, dtype=torch.float64)
+            dcen = torch.zeros(b.E, 3, dtype=torch.float64)
             for i, e in enumerate(b.envs):
                 if e.collider is not None:
-                    dvel, _ = b.collider_grad(i, ctx.n_substeps)
+                    dvel, dc0 = b.collider_grad(i, ctx.n_substeps)
                     da[i, :ctx.n_substeps] = torch.from_numpy(dvel)
+                    dcen[i] = torch.from_numpy(dc0)
             da = da.to(actions.device, actions.dtype)
-        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da
+        if centers is None:
+            dcen = None
+        else:
+            if dcen is None:   # a fixed-velocity box: the start center matters, its gradient is not computed
+                raise ValueError("gradients w.r.t. centers need actions (a prescribed motion)")
+            dcen = dcen.to(centers.device, centers.dtype)
+        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da, dcen
 
 
-def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None):
-    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params, actions)
+def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None):
+    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params, actions, centers)

@@ -105,6 +105,21 @@ class PushEnv:
         self.batch.close()
 
 
+def td_lambda_targets(r, v_next, gamma: float, lam: float):
+    """lambda-returns of an H-step window (TD(lambda) of the SHAC/SAPO critic):
+    r [H, E] the (soft) rewards, v_next [H, E] the value of s_{t+1}; returns
+    [H, E], G_t = r_t + gamma ((1 - lam) V(s_{t+1}) + lam G_{t+1}) with
+    G_{H-1} = r_{H-1} + gamma V(s_H), which is the weighted average of the
+    value-bootstrapped k-step returns."""
+    H = r.shape[0]
+    out = torch.empty_like(r)
+    nxt = None
+    for t in reversed(range(H)):
+        nxt = r[t] + gamma * v_next[t] if t == H - 1 else r[t] + gamma * ((1.0 - lam) * v_next[t] + lam * nxt)
+        out[t] = nxt
+    return out
+
+
 def mlp(i, o, width=64):
     return nn.Sequential(nn.Linear(i, width), nn.LayerNorm(width), nn.SiLU(),
                          nn.Linear(width, width), nn.LayerNorm(width), nn.SiLU(), nn.Linear(width, o))
@@ -181,15 +196,11 @@ class SAPO:
         alpha_loss.backward()
         self.opt_alpha.step()
         # TD(lambda) targets on soft returns with the minimum of the critics
-        vmin = [v.min(0).values for v in buf_v]                     # V(s_{t+1}), t = 0..H-1
-        targets = [None] * H
-        nxt = vmin[H - 1]
-        for t in reversed(range(H)):
-            rs = buf_r[t] + alpha * buf_h[t]
-            nxt = rs + g * ((1.0 - self.lam) * vmin[t] + self.lam * nxt) if t < H - 1 else rs + g * vmin[t]
-            targets[t] = nxt
+        vmin = torch.stack([v.min(0).values for v in buf_v])        # V(s_{t+1}), t = 0..H-1
+        soft_r = torch.stack(buf_r) + alpha * torch.stack(buf_h)
+        targets = td_lambda_targets(soft_r, vmin, g, self.lam)
         X = torch.cat(buf_obs)
-        Y = torch.cat(targets)
+        Y = targets.reshape(-1)
         for _ in range(self.critic_iters):
             closs = sum(((c(X).squeeze(-1) - Y) ** 2).mean() for c in self.critics)
             self.opt_c.zero_grad()

@@ -1,0 +1,42 @@
+"""Host-side pieces of the SAPO learner (no GPU)."""
+import math
+
+import numpy as np
+import torch
+
+from paper_2412_12089_amd.sapo import Actor, td_lambda_targets
+
+
+def test_td_lambda_matches_the_weighted_k_step_definition():
+    # G^lambda_{t:H} = (1 - lam) sum_{l=1}^{H-1-t} lam^{l-1} G_{t:t+l} + lam^{H-t-1} G_{t:H},
+    # G_{t:t+k} = sum_{l<k} gamma^l r_{t+l} + gamma^k V(s_{t+k})
+    rng = np.random.default_rng(0)
+    H, E, gamma, lam = 7, 3, 0.97, 0.9
+    r = torch.from_numpy(rng.standard_normal((H, E)))
+    v = torch.from_numpy(rng.standard_normal((H, E)))      # v[t] = V(s_{t+1})
+    got = td_lambda_targets(r, v, gamma, lam)
+
+    def G(t, k):
+        return sum(gamma ** l * r[t + l] for l in range(k)) + gamma ** k * v[t + k - 1]
+
+    for t in range(H):
+        n = H - t
+        want = (1 - lam) * sum(lam ** (l - 1) * G(t, l) for l in range(1, n)) + lam ** (n - 1) * G(t, n)
+        np.testing.assert_allclose(got[t].numpy(), want.numpy(), rtol=1e-12)
+    # lam = 0: one-step targets; lam = 1: the H-step Monte-Carlo return bootstrapped at the end
+    np.testing.assert_allclose(td_lambda_targets(r, v, gamma, 0.0).numpy(), (r + gamma * v).numpy(), rtol=1e-12)
+    np.testing.assert_allclose(td_lambda_targets(r, v, gamma, 1.0)[0].numpy(), G(0, H).numpy(), rtol=1e-12)
+
+
+def test_squashed_normal_log_probability():
+    # the actor's log pi(a|s) equals the density of tanh(u), u ~ N(mu, sigma^2), by change of variables
+    torch.manual_seed(1)
+    actor = Actor(5, 3)
+    obs = torch.randn(4, 5)
+    a, logp = actor(obs)
+    mu, log_std = actor.net(obs).split(3, -1)
+    std = log_std.clamp(-5, 2).exp()
+    u = torch.atanh(a.clamp(-1 + 1e-7, 1 - 1e-7))
+    ref = torch.distributions.Normal(mu, std).log_prob(u).sum(-1) - torch.log(1 - a ** 2).sum(-1)
+    np.testing.assert_allclose(logp.detach().numpy(), ref.detach().numpy(), rtol=1e-3, atol=1e-3)
+    assert (a.abs() < 1).all() and math.isfinite(float(logp.sum()))

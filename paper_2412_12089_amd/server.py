@@ -53,7 +53,8 @@ class Result:
     arrival: float = 0.0
     admitted: float = 0.0
     finished: float = 0.0
-    status: str = "ok"
+    status: str = "ok"             # ok / error / cancelled / rejected
+    error: int = 0                 # device error bits of a failed request (1 non-finite, 2 out of the band)
 
     @property
     def latency(self) -> float:
@@ -174,9 +175,9 @@ class Server:
                     a.chunk_idx = len(a.ckpts) - 1
                     a.cot = self.ex.loss_cotangent(a.req)
                     a.dparams = np.zeros(8)
-            self.ex.sync()
+            self._sync()
             for s in finished:
-                if not self.active[s].req.backward:
+                if s in self.active and not self.active[s].req.backward:
                     self._release(s)
 
     def _backward_iteration(self):
@@ -205,9 +206,18 @@ class Server:
                 a = self.active[s]
                 a.result.grads = a.cot
                 a.result.dparams = a.dparams
-            self.ex.sync()
+            self._sync()
             for s in finished:
-                self._release(s)
+                if s in self.active:
+                    self._release(s)
+
+    def _sync(self):
+        """Wait for the device; a request whose environment reported an error
+        (non-finite state, a particle out of the band) fails alone and frees its slot."""
+        for slot, bits in (self.ex.sync() or {}).items():
+            if slot in self.active and bits:
+                self.active[slot].result.error = int(bits)
+                self._release(slot, status="error")
 
     def step(self) -> None:
         """One engine iteration: admit, one forward chunk, one backward chunk."""
@@ -238,15 +248,17 @@ class Server:
             self.step()
             if self.clock() - start > timeout_s:
                 raise TimeoutError("server did not drain in time")
-        self.ex.sync()
+        self._sync()
         return self.done
 
     def stats(self) -> dict:
         lat = np.array([r.latency for r in self.done.values() if r.status == "ok"])
+        errors = int(sum(r.status == "error" for r in self.done.values()))
         span = max((r.finished for r in self.done.values()), default=0.0)
         return {
             "requests": len(self.done),
             "ok": int(sum(r.status == "ok" for r in self.done.values())),
+            "errors": errors,
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "particle_substeps_per_s": self.work / span if span > 0 else None,
@@ -329,7 +341,10 @@ class GPUExecutor:
         return self.batch.get_particles(env=slot)
 
     def sync(self):
-        self.batch.sync()
+        """Waits for the device; returns {slot: error bits} for slots that reported errors since the last call."""
+        self.batch.sync(raise_on_error=False)
+        errs = self.batch.env_errors()
+        return {i: int(b) for i, b in enumerate(errs) if b}
 
     def close(self):
         self.batch.close()

@@ -11,6 +11,7 @@ class OracleExecutor:
         self.capacity = (n_cap, N_cap)
         self.slots = [None] * n_slots
         self.calls = []
+        self.errs = {}
 
     def load(self, slot, spec):
         env, prm, st = O.env_from_spec(spec)
@@ -32,7 +33,10 @@ class OracleExecutor:
                 d = self.slots[s]
                 if record:
                     d["rec"] = (d["st"], k)
-                d["st"], _ = O.rollout(d["env"], d["prm"], d["st"], k)
+                d["st"], oob = O.rollout(d["env"], d["prm"], d["st"], k)
+                bits = (0 if all(bool(torch.isfinite(t).all()) for t in d["st"]) else 1) | (2 if oob else 0)
+                if bits:
+                    self.errs[s] = self.errs.get(s, 0) | bits
 
     def loss_cotangent(self, req):
         return O.linear_loss_cotangent(req.loss_weights, req.env.n_particles)
@@ -50,4 +54,5 @@ class OracleExecutor:
         return self.slots[slot]["st"]
 
     def sync(self):
-        pass
+        out, self.errs = self.errs, {}
+        return out

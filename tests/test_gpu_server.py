@@ -79,3 +79,16 @@ def test_each_request_is_the_same_alone_and_in_the_mix():
         if cot is not None:
             for j in range(4):
                 assert relerr(mix[r.rid]["grads"][j], o["grads"][j]) < 1e-3
+
+
+def test_a_failing_request_fails_alone_on_the_device():
+    # one request has a particle outside the valid band: the device error word fails it alone
+    reqs = requests(n=4, seed=12)
+    x = reqs[1].env.x.copy()
+    x[0] = (0.995, 0.5, 0.5)
+    reqs[1] = dataclasses.replace(reqs[1], env=dataclasses.replace(reqs[1].env, x=x))
+    print("[gpu-test] server with one out-of-band request", flush=True)
+    out, stats = serve(reqs, n_slots=2)
+    assert out[reqs[1].rid]["status"] == "error"
+    assert all(out[r.rid]["status"] == "ok" for i, r in enumerate(reqs) if i != 1)
+    assert stats["errors"] == 1

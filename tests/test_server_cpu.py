@@ -134,3 +134,21 @@ def test_results_can_be_dropped_for_throughput_runs():
     done = srv.run(reqs, realtime=False)
     assert all(r.status == "ok" and r.state is None and r.grads is None for r in done.values())
     assert srv.stats()["ok"] == len(reqs)
+
+
+def test_a_failing_request_fails_alone():
+    # a request with a particle outside the valid band is reported as an error and frees its slot;
+    # the others are unaffected
+    reqs = small_requests(n=5)
+    bad = reqs[2]
+    x = bad.env.x.copy()
+    x[0, 0] = 0.99
+    reqs[2] = dataclasses.replace(bad, env=dataclasses.replace(bad.env, x=x))
+    ex = OracleExecutor(2, n_cap=16, N_cap=200)
+    srv = Server(ex, 10 ** 9, chunk=4, clock=FakeClock())
+    done = srv.run(reqs, realtime=False)
+    st = {rid: r for rid, r in done.items()}
+    assert st[reqs[2].rid].status == "error" and st[reqs[2].rid].error & 2
+    assert all(st[r.rid].status == "ok" for i, r in enumerate(reqs) if i != 2)
+    assert sorted(srv.free) == [0, 1] and not srv.active
+    assert srv.stats()["errors"] == 1

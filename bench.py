@@ -38,16 +38,19 @@ ALG_BYTES_PER_PARTICLE = {
     "g2p_adj": 48 + 96 + 48,   # read x, F, the state cotangent; write the partial x/F cotangent
     "p2g_adj": 96 + 48 + 96,   # read state and partial cotangent; write the state cotangent
     "sort": 96 + 96 + 4 * 8,   # permute read + write, keys/values
+    "g2p2g": 48 + 96,   # G2P's reads and writes; the next P2G takes the new state from registers
 }
 # algorithmic bytes per touched grid node per launch
-ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16}
+ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16,
+                      "g2p2g": 12 + 16}
 
 
 # kernel symbol of each class for the library's default batched variants
 KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg"},
                  "g2p": {0: "k_g2p_direct", 1: "k_g2p_lds"},
                  "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg"},
-                 "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"}}
+                 "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"},
+                 "g2p2g": {1: "k_g2p2g"}}
 
 
 def kernel_source_sha() -> str:
@@ -64,6 +67,10 @@ def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
     kernels are templates over (persistent grid, LDS box nodes, material)."""
     if not variant:
         return symbol
+    mats = sorted({e.material for e in envs})
+    mat = mats[0] if tuned["SPECIALIZE"] and len(mats) == 1 else -1
+    if symbol == "k_g2p2g":   # no persistent-grid parameter
+        return f"{symbol}<{384 if tuned['BOX'] else 1024}, {mat}>"
     n_items = sum(-(-e.n_particles // 256) for e in envs)
     persist = "true" if 0 < tuned["GRID_CAP"] < n_items else "false"
     mats = sorted({e.material for e in envs})
@@ -211,7 +218,7 @@ def main():
         t0 = time.perf_counter()
         b.autotune(args.tune_ms)
         tune_s = time.perf_counter() - t0
-    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE")}
+    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE")}
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
@@ -230,7 +237,7 @@ def main():
     b.set_timing(True)
     b.set_particles(*x0)
     b.forward(S, record=True)
-    classes = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj")
+    classes = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj", "g2p2g")
     kt_f = {k: b.kernel_time(k) for k in classes}
     b.backward(gx=w)
     kt_b = {k: b.kernel_time(k) for k in classes}   # includes the recomputed segments
@@ -241,7 +248,8 @@ def main():
         n = nf + nb
         kt[k] = ((mf * nf + mb * nb) / n if n else 0.0, n)
     variant = {"p2g": b.get_option(_capi.OPT_P2G), "g2p": b.get_option(_capi.OPT_G2P),
-               "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ)}
+               "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ),
+               "g2p2g": b.get_option(_capi.OPT_FUSE)}
     mem = b.memory_bytes()
     b.close()
     nodes = touched_nodes(envs)

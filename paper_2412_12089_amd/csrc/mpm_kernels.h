@@ -86,6 +86,12 @@ void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* 
                             const WorkItem* items, int n_items, const float* grid, float* gcot, double* pacc,
                             int runs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 
+// G2P of substep k fused with the segment-reduced P2G of substep k + 1
+// (grid_in: substep k's grid, read; grid_out / flags_out: substep k + 1's)
+void launch_g2p2g(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                  const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs, int runs, int k_call,
+                  int box, int mat, hipStream_t s);
+
 // per-env weighted moments of caller-order x, v (see mpm_observe.hip) and their VJP
 void launch_moments(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
                     const float* w, double* out, int n_envs, hipStream_t s);

@@ -791,25 +791,15 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, con
   }
 }
 
-// P2G with segment reduction: thread t <-> particle t of the item
-template <int BOXN, int MAT>
-MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
-                                                 const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
-                                                 float* __restrict__ grid, uint32_t* __restrict__ flags,
-                                                 int32_t* __restrict__ errs, int runs, int k_call) {
-  const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
-  __shared__ float lds[4 * BOXN];
-  __shared__ BoxShared bsh;
-  __shared__ SegShared sh;
-  const WorkItem it = items[item_idx];
-  const EnvDev& e = envs[it.env];
-  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
-  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
+// P2G with segment reduction for the item's particles at positions x (thread
+// t <-> particle t of the item); load_rest(v, C, H) supplies the rest of the
+// particle's state once the block has set up its boxes. Every thread calls it.
+template <int BOXN, typename LoadRest>
+MD void p2g_seg_body(const EnvDev& e, int mat, const WorkItem& it, const float x[3], LoadRest load_rest,
+                     float* __restrict__ grid, uint32_t* __restrict__ flags, int32_t* __restrict__ errs, int min_run,
+                     int max_run, float* lds, BoxShared& bsh, SegShared& sh) {
   const int t = threadIdx.x;
   const bool valid = t < it.count;
-  const int64_t p = it.start + (valid ? t : 0);
-  float x[3];
-  load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
   sh.key[t] = pack_base(sc.b);
@@ -820,9 +810,9 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
     for (int i = t; i < 4 * bx.nodes; i += blockDim.x) lds[i] = 0.f;
   __syncthreads();   // the LDS box is clear before any lane adds to it
   if (valid) {
-    float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
-    const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 H = ld_m3(st, N, p, 15);
+    float v[3];
+    M3 Cm, H;
+    load_rest(v, Cm, H);
     const M3 tau = stress(e, H, mat);
     const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
@@ -868,6 +858,139 @@ MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
   } else if (valid) {
     mark_particle_tiles(e, sc.b, flags);
   }
+}
+
+template <int BOXN, int MAT>
+MD void p2g_seg_item(int item_idx, const float* __restrict__ st, int64_t N,
+                                                 const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                                 float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                 int32_t* __restrict__ errs, int runs, int k_call) {
+  const int min_run = runs & 0xffff, max_run = runs >> 16;   // seg-mode threshold, run split length
+  __shared__ float lds[4 * BOXN];
+  __shared__ BoxShared bsh;
+  __shared__ SegShared sh;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
+  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
+  const int t = threadIdx.x;
+  const int64_t p = it.start + (t < it.count ? t : 0);
+  float x[3];
+  load_x3(st, N, p, x);
+  p2g_seg_body<BOXN>(e, mat, it, x, [&](float v[3], M3& Cm, M3& H) {
+    for (int a = 0; a < 3; ++a) v[a] = st[(3 + a) * N + p];
+    Cm = ld_m3(st, N, p, 6);
+    H = ld_m3(st, N, p, 15);
+  }, grid, flags, errs, min_run, max_run, lds, bsh, sh);
+}
+
+// G2P of substep k fused with P2G of substep k + 1: the particle's new state
+// stays in registers between the gather from grid k and the scatter into grid
+// k + 1 (thread t <-> particle t). k_call is substep k's call index; an env
+// frozen at k copies its state, one frozen at k + 1 only takes the G2P.
+template <int BOXN, int MAT>
+MD void g2p2g_item(int item_idx, const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                   const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                   const float* __restrict__ grid_in, float* __restrict__ grid_out, uint32_t* __restrict__ flags_out,
+                   int32_t* __restrict__ errs, int runs, int k_call) {
+  const int min_run = runs & 0xffff, max_run = runs >> 16;
+  __shared__ float lds[4 * BOXN];
+  __shared__ BoxShared bsh;
+  __shared__ SegShared sh;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;
+  const int t = threadIdx.x;
+  const bool valid = t < it.count;
+  const int64_t p = it.start + (valid ? t : 0);
+  if (k_call >= e.nsub) {   // frozen env: the substep is the identity
+    if (valid)
+      for (int c = 0; c < 24; ++c) out[c * N + p] = st[c * N + p];
+    return;
+  }
+  // G2P (substep k), gathering straight from grid k
+  float x[3];
+  load_x3(st, N, p, x);
+  const M3 H = ld_m3(st, N, p, 15);
+  float vn[3] = {0.f, 0.f, 0.f};
+  M3 Cn = m3_zero();
+  if (valid) {
+    const Stencil sc = make_stencil(x, e.n, e.fn);
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float W = sel3(sc.w[0], ox) * sc.w[1][oy] * sc.w[2][oz];
+          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float* g = grid_in + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            vn[a] = fmaf(W, vi[a], vn[a]);
+            const float wv = W * vi[a];
+            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
+            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
+            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
+          }
+        }
+  }
+  Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
+  float xn[3];
+  for (int a = 0; a < 3; ++a) xn[a] = fmaf(e.dt, vn[a], x[a]);
+  const M3 Hn = project(e, trial_h(e, Cn, H), mat);
+  if (valid) {
+    for (int a = 0; a < 3; ++a) { out[a * N + p] = xn[a]; out[(3 + a) * N + p] = vn[a]; }
+    st_m3(out, N, p, 6, Cn);
+    st_m3(out, N, p, 15, Hn);
+    bool fin = true;
+    for (int a = 0; a < 3; ++a) fin = fin && isfinite(xn[a]) && isfinite(vn[a]);
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(Hn.m[i][j]);
+    if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
+  }
+  if (k_call + 1 >= e.nsub) return;   // the env stops after this substep (uniform over the block)
+  // P2G (substep k + 1) of the state just computed
+  p2g_seg_body<BOXN>(e, mat, it, xn, [&](float v[3], M3& Cm, M3& Hh) {
+    for (int a = 0; a < 3; ++a) v[a] = vn[a];
+    Cm = Cn;
+    Hh = Hn;
+  }, grid_out, flags_out, errs, min_run, max_run, lds, bsh, sh);
+}
+
+template <int BOXN, int MAT>
+__global__ void __launch_bounds__(256) k_g2p2g(const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                                               const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                               const float* __restrict__ grid_in, float* __restrict__ grid_out,
+                                               uint32_t* __restrict__ flags_out, int32_t* __restrict__ errs, int runs,
+                                               int k_call) {
+  g2p2g_item<BOXN, MAT>(blockIdx.x, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call);
+}
+
+template <int BOXN>
+static void launch_g2p2g_m(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items,
+                           int n_items, const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs,
+                           int runs, int k_call, hipStream_t s, int mat) {
+  const dim3 g(n_items), blk(256);
+  switch (mat) {
+    case MAT_NEOHOOKEAN: hipLaunchKernelGGL((k_g2p2g<BOXN, MAT_NEOHOOKEAN>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    case MAT_COROTATED: hipLaunchKernelGGL((k_g2p2g<BOXN, MAT_COROTATED>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    case MAT_VONMISES: hipLaunchKernelGGL((k_g2p2g<BOXN, MAT_VONMISES>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    case MAT_FLUID_TAIT: hipLaunchKernelGGL((k_g2p2g<BOXN, MAT_FLUID_TAIT>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    case MAT_FLUID_PAPER: hipLaunchKernelGGL((k_g2p2g<BOXN, MAT_FLUID_PAPER>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    case -1: hipLaunchKernelGGL((k_g2p2g<BOXN, -1>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, runs, k_call); break;
+    default: break;
+  }
+}
+
+void launch_g2p2g(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                  const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs, int runs, int k_call,
+                  int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_g2p2g_m<kBoxSmall>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, runs, k_call, s, mat);
+  else
+    launch_g2p2g_m<kBoxNodes>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, runs, k_call, s, mat);
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items

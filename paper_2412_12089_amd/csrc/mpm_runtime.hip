@@ -29,7 +29,7 @@ using namespace mpmx;
 
 namespace {
 
-enum KernelClass { KC_P2G = 0, KC_GRID, KC_G2P, KC_SORT, KC_G2P_ADJ, KC_GRID_ADJ, KC_P2G_ADJ, KC_COUNT };
+enum KernelClass { KC_P2G = 0, KC_GRID, KC_G2P, KC_SORT, KC_G2P_ADJ, KC_GRID_ADJ, KC_P2G_ADJ, KC_G2P2G, KC_COUNT };
 
 struct TimedSpan {
   int kc;
@@ -109,6 +109,7 @@ struct mpm_batch {
   int grid_cap = 0;   // 0: one block per work item; > 0: persistent grid of this many blocks
   int box = 0;        // LDS box budget of the LDS-staged kernels: 0 = 1024 nodes, 1 = 384 nodes
   int specialize = 1; // LDS-staged kernels: 1 = one launch per material, compiled for it; 0 = one generic launch
+  int fuse = 0;       // 1: G2P of substep k and P2G of substep k + 1 in one kernel (with the segment P2G)
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -218,6 +219,49 @@ const std::vector<mpm_batch::MatRange>& launch_ranges(mpm_batch* b) {
 }
 
 // ---------------------------------------------------------------- one substep
+// batched-mode pieces of a substep
+void batched_p2g(mpm_batch* b, const float* in, int gi, int kc) {
+  const hipStream_t s = b->stream;
+  const int ni = (int)b->items_h.size();
+  const int runs = b->min_run | (b->max_run << 16);
+  Span sp(b, KC_P2G);
+  if (b->var_p2g == 0) launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, b->grid[gi], b->flags[gi], b->errs, kc, s);
+  for (const auto& r : launch_ranges(b)) {
+    const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+    if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, runs, kc, b->grid_cap, b->box, r.mat, s);
+    else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, kc, b->grid_cap, b->box, r.mat, s);
+  }
+}
+
+void batched_grid(mpm_batch* b, int gi, int clear, int k_rel) {
+  Span sp(b, KC_GRID);
+  launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0, k_rel, clear,
+                     b->motion_d, b->stream);
+}
+
+void batched_g2p(mpm_batch* b, const float* in, float* out, int gi, int kc) {
+  const hipStream_t s = b->stream;
+  const int ni = (int)b->items_h.size();
+  Span sp(b, KC_G2P);
+  if (b->var_g2p == 0) launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, b->grid[gi], b->errs, kc, s);
+  else
+    for (const auto& r : launch_ranges(b))
+      launch_g2p_lds(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->grid[gi],
+                     b->errs, kc, b->grid_cap, b->box, r.mat, s);
+}
+
+// G2P of substep kc from grid gi_in fused with P2G of substep kc + 1 into grid gi_out
+void batched_g2p2g(mpm_batch* b, const float* in, float* out, int gi_in, int gi_out, int kc) {
+  const hipStream_t s = b->stream;
+  const int runs = b->min_run | (b->max_run << 16);
+  Span sp(b, KC_G2P2G);
+  for (const auto& r : launch_ranges(b))
+    launch_g2p2g(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->grid[gi_in],
+                 b->grid[gi_out], b->flags[gi_out], b->errs, runs, kc, b->box, r.mat, s);
+}
+
+bool fused(const mpm_batch* b) { return b->mode != MPM_MODE_PLAIN && b->fuse && b->var_p2g == 2; }
+
 void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel, int kc) {
   float* g = b->grid[gi];
   uint32_t* fl = b->flags[gi];
@@ -232,26 +276,9 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
       { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, kc, s); }
     }
   } else {
-    const int ni = (int)b->items_h.size();
-    const int runs = b->min_run | (b->max_run << 16);
-    const std::vector<mpm_batch::MatRange>& ranges = launch_ranges(b);
-    {
-      Span sp(b, KC_P2G);
-      if (b->var_p2g == 0) launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, g, fl, b->errs, kc, s);
-      for (const auto& r : ranges) {
-        const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
-        if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, it, r.count, g, fl, b->errs, runs, kc, b->grid_cap, b->box, r.mat, s);
-        else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, g, fl, b->errs, kc, b->grid_cap, b->box, r.mat, s);
-      }
-    }
-    { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->clock, 0.0, k_rel, clear, b->motion_d, s); }
-    {
-      Span sp(b, KC_G2P);
-      if (b->var_g2p == 0) launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, g, b->errs, kc, s);
-      else
-        for (const auto& r : ranges)
-          launch_g2p_lds(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, g, b->errs, kc, b->grid_cap, b->box, r.mat, s);
-    }
+    batched_p2g(b, in, gi, kc);
+    batched_grid(b, gi, clear, k_rel);
+    batched_g2p(b, in, out, gi, kc);
   }
 }
 
@@ -329,10 +356,33 @@ const float* fwd_segment(mpm_batch* b, int j, int Kj, bool record, bool tape, co
   float* dst0 = record ? b->ckpt[j] : other_work(b, src);
   if (!dry && b->N > 0) sort_into(b, src, dst0, record ? b->perm[j] : nullptr);
   const float* in = dst0;
-  for (int k = 0; k < Kj; ++k) {
-    float* out = tape ? b->seg[k + 1] : other_work(b, in);
-    if (!dry && b->N > 0) substep(b, in, out, tape ? k + 1 : 0, tape ? 0 : 1, k, j * b->K + k);
-    in = out;
+  const bool run = !dry && b->N > 0;
+  if (fused(b)) {
+    // P2G(0), grid(0), then G2P(k) + P2G(k+1) in one kernel and grid(k+1), then G2P(K-1)
+    auto gi = [&](int k) { return tape ? k + 1 : 0; };
+    const int clear = tape ? 0 : 1;
+    if (run && Kj > 0) {
+      batched_p2g(b, in, gi(0), j * b->K);
+      batched_grid(b, gi(0), clear, 0);
+    }
+    for (int k = 0; k < Kj; ++k) {
+      float* out = tape ? b->seg[k + 1] : other_work(b, in);
+      if (run) {
+        if (k + 1 < Kj) {
+          batched_g2p2g(b, in, out, gi(k), gi(k + 1), j * b->K + k);
+          batched_grid(b, gi(k + 1), clear, k + 1);
+        } else {
+          batched_g2p(b, in, out, gi(k), j * b->K + k);
+        }
+      }
+      in = out;
+    }
+  } else {
+    for (int k = 0; k < Kj; ++k) {
+      float* out = tape ? b->seg[k + 1] : other_work(b, in);
+      if (run) substep(b, in, out, tape ? k + 1 : 0, tape ? 0 : 1, k, j * b->K + k);
+      in = out;
+    }
   }
   if (!dry) launch_add_clock(b->clock, Kj, b->stream);
   return in;
@@ -446,7 +496,7 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
 
 namespace {
 
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize; };
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse; };
 
 // shape signature -> choice, shared by batches of the same shape in the process
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -468,6 +518,7 @@ void apply_choice(mpm_batch* b, const TuneChoice& c) {
   b->max_run = c.max_run;
   b->box = c.box;
   b->specialize = c.specialize;
+  b->fuse = c.fuse;
   drop_graphs(b);
 }
 
@@ -970,6 +1021,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_MAX_RUN: if (value < 1 || value > 256) break; b->max_run = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_BOX: if (value < 0 || value > 1) break; b->box = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_FUSE: if (value < 0 || value > 1) break; b->fuse = value; drop_graphs(b); return MPM_OK;
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -988,6 +1040,7 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_MAX_RUN: *value = b->max_run; return MPM_OK;
     case MPM_OPT_BOX: *value = b->box; return MPM_OK;
     case MPM_OPT_SPECIALIZE: *value = b->specialize; return MPM_OK;
+    case MPM_OPT_FUSE: *value = b->fuse; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
@@ -1061,7 +1114,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -1089,6 +1142,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.p2g_adj, 0, 0, true}, {&best.p2g_adj, 1, 0, true}},
       {{&best.box, 0, 0, true}, {&best.box, 1, 0, true}},
       {{&best.specialize, 1, 0, true}, {&best.specialize, 0, 0, true}},
+      {{&best.fuse, 0, 0, true}, {&best.fuse, 1, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

@@ -392,11 +392,25 @@ const float* fwd_segment(mpm_batch* b, int j, int Kj, bool record, bool tape, co
 // adjoint substeps in reverse from cot[c], undo the segment's sort.
 // Returns the index of the cotangent buffer that holds the result.
 int bwd_segment(mpm_batch* b, int j, int Kj, bool have_tape, int c) {
-  if (!have_tape) {
+  if (!have_tape) {   // recompute the segment's tape from its checkpoint (grid k + 1 holds substep k)
     const float* in = b->ckpt[j];
-    for (int k = 0; k < Kj; ++k) {
-      substep(b, in, b->seg[k + 1], k + 1, 0, k, j * b->K + k);
-      in = b->seg[k + 1];
+    if (fused(b) && Kj > 0) {
+      batched_p2g(b, in, 1, j * b->K);
+      batched_grid(b, 1, 0, 0);
+      for (int k = 0; k < Kj; ++k) {
+        if (k + 1 < Kj) {
+          batched_g2p2g(b, in, b->seg[k + 1], k + 1, k + 2, j * b->K + k);
+          batched_grid(b, k + 2, 0, k + 1);
+        } else {
+          batched_g2p(b, in, b->seg[k + 1], k + 1, j * b->K + k);
+        }
+        in = b->seg[k + 1];
+      }
+    } else {
+      for (int k = 0; k < Kj; ++k) {
+        substep(b, in, b->seg[k + 1], k + 1, 0, k, j * b->K + k);
+        in = b->seg[k + 1];
+      }
     }
   }
   for (int k = Kj - 1; k >= 0; --k) {

@@ -39,10 +39,13 @@ ALG_BYTES_PER_PARTICLE = {
     "p2g_adj": 96 + 48 + 96,   # read state and partial cotangent; write the state cotangent
     "sort": 96 + 96 + 4 * 8,   # permute read + write, keys/values
     "g2p2g": 48 + 96,   # G2P's reads and writes; the next P2G takes the new state from registers
+    # P2G adjoint k: read state k and the partial cotangent; G2P adjoint k - 1: read x, F of
+    # state k - 1 (C of state k again, counted once) and write the partial cotangent
+    "adj_pair": 96 + 48 + 48 + 48,
 }
 # algorithmic bytes per touched grid node per launch
 ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16,
-                      "g2p2g": 12 + 16}
+                      "g2p2g": 12 + 16, "adj_pair": 16 + 12 + 12}
 
 
 # kernel symbol of each class for the library's default batched variants
@@ -50,7 +53,7 @@ KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg"},
                  "g2p": {0: "k_g2p_direct", 1: "k_g2p_lds"},
                  "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg"},
                  "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"},
-                 "g2p2g": {1: "k_g2p2g"}}
+                 "g2p2g": {1: "k_g2p2g"}, "adj_pair": {1: "k_adj_pair"}}
 
 
 def kernel_source_sha() -> str:
@@ -69,7 +72,7 @@ def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
         return symbol
     mats = sorted({e.material for e in envs})
     mat = mats[0] if tuned["SPECIALIZE"] and len(mats) == 1 else -1
-    if symbol == "k_g2p2g":   # no persistent-grid parameter
+    if symbol in ("k_g2p2g", "k_adj_pair"):   # no persistent-grid parameter
         return f"{symbol}<{384 if tuned['BOX'] else 1024}, {mat}>"
     n_items = sum(-(-e.n_particles // 256) for e in envs)
     persist = "true" if 0 < tuned["GRID_CAP"] < n_items else "false"
@@ -100,7 +103,8 @@ def parse():
                     choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh", "handflip_shape"])
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-substeps", type=int, default=40, help="substeps of the oracle sample (about 10-20 s)")
+    ap.add_argument("--cpu-substeps", type=int, default=80, help="substeps per env of the oracle sample")
+    ap.add_argument("--cpu-envs", type=int, default=2, help="envs of the oracle sample (about 10-20 s in all)")
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
     ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
     ap.add_argument("--tune-ms", type=int, default=4000, help="autotuner budget (0: library defaults)")
@@ -169,28 +173,30 @@ def serving_leg(seconds, rate, slots, device):
     return st
 
 
-def cpu_baseline(wl, substeps):
-    """The FP64 oracle on a bounded sample: one env, `substeps` substeps, forward + reverse."""
+def cpu_baseline(wl, substeps, n_envs):
+    """The FP64 oracle on a bounded sample: the first n_envs envs, `substeps` substeps each, forward + reverse."""
     import torch
     from oracle import mpm_oracle as O
-    spec = wl.envs[0]
-    env, prm, st = O.env_from_spec(spec)
-    cot = O.linear_loss_cotangent(wl.loss_weights[0], spec.n_particles)
     threads = torch.get_num_threads()
-    t0 = time.perf_counter()
-    O.rollout_vjp(env, prm, st, substeps, cot)   # forward (stores states) + per-substep reverse
-    dt = time.perf_counter() - t0
-    rate = spec.n_particles * substeps / dt
-    return {"value": rate, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 env of {wl.name} ({spec.n_particles} particles), {substeps} substeps fwd+bwd, "
-                      f"{dt:.1f} s wall"}
+    done, t_all = 0, 0.0
+    specs = wl.envs[:max(1, n_envs)]
+    for i, spec in enumerate(specs):
+        env, prm, st = O.env_from_spec(spec)
+        cot = O.linear_loss_cotangent(wl.loss_weights[i], spec.n_particles)
+        t0 = time.perf_counter()
+        O.rollout_vjp(env, prm, st, substeps, cot)   # forward (stores states) + per-substep reverse
+        t_all += time.perf_counter() - t0
+        done += spec.n_particles * substeps
+    return {"value": done / t_all, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(specs)} env(s) of {wl.name} ({done // substeps} particles), {substeps} substeps "
+                      f"fwd+bwd each, {t_all:.1f} s wall"}
 
 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: environments never exchange data, and this build "
-              "runs on a single MI355X (see the sharding note in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: environments never exchange data, so a multi-GPU run is "
+              "independent single-GPU runs over disjoint env sets; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2412_12089_amd import scenes
@@ -218,7 +224,7 @@ def main():
         t0 = time.perf_counter()
         b.autotune(args.tune_ms)
         tune_s = time.perf_counter() - t0
-    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE")}
+    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE", "FUSE_ADJ")}
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
@@ -237,7 +243,7 @@ def main():
     b.set_timing(True)
     b.set_particles(*x0)
     b.forward(S, record=True)
-    classes = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj", "g2p2g")
+    classes = _capi.KERNEL_CLASSES
     kt_f = {k: b.kernel_time(k) for k in classes}
     b.backward(gx=w)
     kt_b = {k: b.kernel_time(k) for k in classes}   # includes the recomputed segments
@@ -249,7 +255,7 @@ def main():
         kt[k] = ((mf * nf + mb * nb) / n if n else 0.0, n)
     variant = {"p2g": b.get_option(_capi.OPT_P2G), "g2p": b.get_option(_capi.OPT_G2P),
                "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ),
-               "g2p2g": b.get_option(_capi.OPT_FUSE)}
+               "g2p2g": b.get_option(_capi.OPT_FUSE), "adj_pair": b.get_option(_capi.OPT_FUSE_ADJ)}
     mem = b.memory_bytes()
     b.close()
     nodes = touched_nodes(envs)
@@ -271,7 +277,7 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         serving = serving_leg(args.serve_seconds, args.serve_rate, args.serve_slots, dev)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps, args.cpu_envs)
     out = {
         "metric": "fwd+bwd particle-substeps/s (batched)",
         "value": value,

@@ -232,6 +232,10 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
 #define MPM_OPT_FUSE 11        /* 1: within a segment, G2P of substep k and the segment-reduced P2G of substep
                                   k + 1 run as one kernel (the new state stays in registers); needs
                                   MPM_OPT_P2G = 2, otherwise ignored. Default 0; the autotuner may set it */
+#define MPM_OPT_FUSE_ADJ 12    /* 1: within a segment's backward, the P2G adjoint of substep k and the G2P
+                                  adjoint of substep k - 1 run as one kernel (the cotangent of state k stays
+                                  in registers; the G2P adjoint part is the segment-reduced one). Batched
+                                  mode. Default 0; the autotuner may set it */
 #define MPM_OPT_SPECIALIZE 10  /* LDS-staged kernels: 1 = one launch per material over that material's work items,
                                   compiled for it (default); 0 = one launch over all items, material read at run time */
 
@@ -279,7 +283,8 @@ int64_t mpm_memory_bytes(const mpm_batch* b);
 /* Mean duration in milliseconds of the named kernel class over the last
  * mpm_forward / mpm_backward when timing is enabled (see mpm_set_timing).
  * kernel: 0 P2G, 1 grid update, 2 G2P, 3 sort+permute, 4 G2P adjoint,
- * 5 grid adjoint, 6 P2G adjoint, 7 fused G2P + next P2G (MPM_OPT_FUSE).
+ * 5 grid adjoint, 6 P2G adjoint, 7 fused G2P + next P2G (MPM_OPT_FUSE),
+ * 8 fused P2G adjoint + previous G2P adjoint (MPM_OPT_FUSE_ADJ).
  * Returns the number of launches timed. */
 int mpm_kernel_time(mpm_batch* b, int32_t kernel, double* mean_ms);
 int mpm_set_timing(mpm_batch* b, int32_t enabled);

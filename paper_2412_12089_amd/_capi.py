@@ -27,7 +27,7 @@ MPM_MODE_PLAIN = 0
 MPM_MODE_BATCHED = 1
 MPM_FWD_RECORD = 1
 
-KERNEL_CLASSES = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj", "g2p2g")
+KERNEL_CLASSES = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj", "g2p2g", "adj_pair")
 
 # every symbol include/mpm.h declares
 EXPORTED = (
@@ -38,7 +38,8 @@ EXPORTED = (
     "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
 )
 MPM_MOMENTS = 20
-OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE, OPT_FUSE = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+(OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
+ OPT_FUSE, OPT_FUSE_ADJ) = range(1, 13)
 
 
 class mpm_env_desc(ctypes.Structure):

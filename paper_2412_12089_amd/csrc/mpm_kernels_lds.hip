@@ -1198,6 +1198,256 @@ void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* 
     launch_g2p_adjoint_seg_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, runs, k_call, grid_cap, s, mat);
 }
 
+// ----------------------------------------------------------------------------
+// P2G adjoint of substep k fused with the G2P adjoint of substep k - 1. The
+// cotangent of the particle's state k stays in registers between phase A (a
+// gather of substep k's (mbar, Pbar), grid-cotangent channels 3-6 written by
+// its grid adjoint) and phase B (the segment-reduced scatter of substep k - 1's
+// node-velocity cotangents into channels 0-2, which that grid adjoint cleared).
+// Thread t <-> particle t of the item in both phases; k_call is substep k's
+// call index. An env frozen at k takes its state-k cotangent from cot_end, the
+// cotangent that entered the segment (every later substep is the identity for
+// it); one frozen at k - 1 as well has nothing to do. `part` holds substep k's
+// partials on entry and substep k - 1's on exit (each thread reads its own
+// particle's before it writes them).
+// ----------------------------------------------------------------------------
+template <int BOXN, int MAT>
+MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const float* __restrict__ st, float* part,
+                      const float* __restrict__ cot_end, int64_t N, const EnvDev* __restrict__ envs,
+                      const WorkItem* __restrict__ items, const float* __restrict__ grid_prev, float* gcot,
+                      double* __restrict__ pacc, int runs, int k_call) {
+  constexpr bool kEig = MAT == MAT_COROTATED || MAT == MAT_VONMISES || MAT < 0;
+  const int min_run = runs & 0xffff, max_run = runs >> 16;
+  __shared__ float buf[6 * BOXN];   // phase A: the (mbar, Pbar) box; phase B: node velocities, then their cotangents
+  __shared__ BoxShared bsh;
+  __shared__ SegShared sh;
+  // phase A keeps U and the eigenvalues of B per thread in the first 12 KB of
+  // the segment rows, which phase B fills only after block_box's barriers
+  float(*eig_keep)[256] = reinterpret_cast<float(*)[256]>(&sh.pd[0][0]);
+  static_assert(sizeof(sh.pd) >= 12 * 256 * sizeof(float), "eigen stash exceeds the segment rows");
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;
+  if (k_call - 1 >= e.nsub) return;   // frozen at k - 1 and k
+  const int t = threadIdx.x;
+  const bool valid = t < it.count;
+  const int64_t p = it.start + (valid ? t : 0);
+  float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // cotangent of state k: x, v, C, F
+  float cx[3] = {0.f, 0.f, 0.f}, cv[3] = {0.f, 0.f, 0.f};
+  M3 cC = m3_zero(), cF = m3_zero();
+  if (k_call >= e.nsub) {   // frozen at k (uniform over the block)
+    if (valid) {
+      for (int a = 0; a < 3; ++a) { cx[a] = cot_end[a * N + p]; cv[a] = cot_end[(3 + a) * N + p]; }
+      cC = ld_m3(cot_end, N, p, 6);
+      cF = ld_m3(cot_end, N, p, 15);
+    }
+  } else {
+    // ---- phase A: P2G adjoint of substep k ----
+    float x[3];
+    load_x3(st, N, p, x);
+    const Stencil sc = make_stencil(x, e.n, e.fn);
+    const Box bx = block_box<BOXN>(e, sc.b, valid, t, it.count, bsh);
+    if (bx.fits) box_load(e, bx, bsh, gcot, 3, 4, buf);
+    __syncthreads();
+    if (valid) {
+      const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+      const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
+      M3 A;
+      {
+        const M3 Cm = ld_m3(st, N, p, 6);
+        const M3 H = ld_m3(st, N, p, 15);
+        const StressPrep spr = stress_prep(e, H, mat);
+        A = m3_axpy(m3_scale(Cm, e.mp), kf, stress_from(e, spr, mat));
+        if (kEig && (mat == MAT_COROTATED || mat == MAT_VONMISES)) {
+          for (int i = 0; i < 3; ++i) {
+            eig_keep[9 + i][t] = spr.l[i];
+            for (int j = 0; j < 3; ++j) eig_keep[3 * i + j][t] = spr.U.m[i][j];
+          }
+        }
+      }
+      float xb[3] = {part[p], part[N + p], part[2 * N + p]};
+      float sP[3] = {0.f, 0.f, 0.f};   // sum of W Pbar
+      float sm = 0.f;                  // sum of W mbar
+      M3 Ab = m3_zero();               // sum of W Pbar d^T
+#pragma unroll 1
+      for (int ox = 0; ox < 3; ++ox)
+#pragma unroll 1
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll 1
+          for (int oz = 0; oz < 3; ++oz) {
+            const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sel3(sc.w[2], oz);
+            const float W = wx * wy * wz;
+            const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz,
+                                 e.fn * wx * wy * sel3(sc.dw[2], oz)};
+            const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+            float mb, Pb[3];
+            if (bx.fits) {
+              const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+              mb = buf[idx];
+              for (int a = 0; a < 3; ++a) Pb[a] = buf[(1 + a) * bx.nodes + idx];
+            } else {
+              const float* gc = gcot + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+              mb = gc[3 * CH];
+              for (int a = 0; a < 3; ++a) Pb[a] = gc[(4 + a) * CH];
+            }
+            float gw = e.mp * mb;
+            for (int a = 0; a < 3; ++a) gw += Pb[a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+            sm = fmaf(W, mb, sm);
+            for (int a = 0; a < 3; ++a) {
+              const float wp = W * Pb[a];
+              sP[a] += wp;
+              Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
+              Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
+              Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
+              const float atp = A.m[0][a] * Pb[0] + A.m[1][a] * Pb[1] + A.m[2][a] * Pb[2];
+              xb[a] += gW[a] * gw - W * atp;
+            }
+          }
+      const M3 Cm = ld_m3(st, N, p, 6);
+      const M3 H = ld_m3(st, N, p, 15);
+      StressPrep spr;
+      if (kEig && (mat == MAT_COROTATED || mat == MAT_VONMISES)) {
+        M3 U;
+        float l[3];
+        for (int i = 0; i < 3; ++i) {
+          l[i] = eig_keep[9 + i][t];
+          for (int j = 0; j < 3; ++j) U.m[i][j] = eig_keep[3 * i + j][t];
+        }
+        spr = stress_prep_with_eig(H, U, l, mat);
+      } else {
+        spr = stress_prep(e, H, mat);
+      }
+      const M3 tau = stress_from(e, spr, mat);
+      const float mpb = sm + v[0] * sP[0] + v[1] * sP[1] + v[2] * sP[2] + m3_ddot(Cm, Ab);
+      for (int a = 0; a < 3; ++a) { cx[a] = xb[a]; cv[a] = e.mp * sP[a]; }
+      cC = m3_scale(Ab, e.mp);
+      const M3 taub = m3_scale(Ab, kf);
+      pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
+      pb[PB_MP] += mpb;
+      cF = ld_m3(part, N, p, 3);
+      stress_vjp_from(e, H, spr, taub, cF, pb, mat);
+    }
+  }
+  // ---- phase B: G2P adjoint of substep k - 1 (state k - 1 -> state k) ----
+  float x[3];
+  load_x3(st_prev, N, p, x);
+  const Stencil sc = make_stencil(x, e.n, e.fn);
+  sh.key[t] = pack_base(sc.b);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, t, it.count, bsh);   // synchronizes: phase A is done
+  find_segments(sh, it.count, max_run);
+  const bool seg_mode = it.count >= min_run * sh.n_seg;
+  float* lv = buf;
+  float* lg = buf + 3 * BOXN;
+  if (bx.fits) {
+    box_load(e, bx, bsh, grid_prev, 4, 3, lv);
+    for (int i = t; i < 3 * bx.nodes; i += blockDim.x) lg[i] = 0.f;
+  }
+  __syncthreads();
+  if (valid) {
+    const M3 H = ld_m3(st_prev, N, p, 15);
+    const M3 F = f_of(H);
+    const float D4 = 4.f * e.fn * e.fn;
+    const M3 Cn = load_cnext(st, N, p);   // C of state k, the substep's own output
+    const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
+    const M3 Htr = trial_h(e, Cn, H);
+    float xb[3], vb[3];
+    for (int a = 0; a < 3; ++a) { xb[a] = cx[a]; vb[a] = cv[a] + e.dt * cx[a]; }
+    const M3 Ftrb = project_vjp(e, Htr, cF, pb, mat);
+    const M3 Cb = m3_axpy(cC, e.dt, m3_mul_abt(Ftrb, F));
+    const M3 Fb = m3_mul_atb(G, Ftrb);
+    if (seg_mode) {
+      float q[3], ab[3][3];
+      for (int a = 0; a < 3; ++a) {
+        q[a] = vb[a];
+        for (int b = 0; b < 3; ++b) {
+          ab[a][b] = D4 * e.dx * Cb.m[a][b];
+          q[a] = fmaf(-ab[a][b], sc.f[b], q[a]);
+        }
+      }
+      seg_store(sh, t, q, ab, sc.f);
+    }
+    st_m3(part, N, p, 3, Fb);
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox)
+#pragma unroll 1
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
+          const float W = wx * wy * wz;
+          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
+          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          float vi[3], gv[3];
+          for (int a = 0; a < 3; ++a)
+            gv[a] = vb[a] + D4 * (Cb.m[a][0] * d[0] + Cb.m[a][1] * d[1] + Cb.m[a][2] * d[2]);
+          if (bx.fits) {
+            const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+            for (int a = 0; a < 3; ++a) {
+              vi[a] = lv[a * bx.nodes + idx];
+              if (!seg_mode) atomicAdd(&lg[a * bx.nodes + idx], W * gv[a]);
+            }
+          } else {
+            const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+            for (int a = 0; a < 3; ++a) {
+              vi[a] = grid_prev[nb + (4 + a) * CH];
+              if (!seg_mode) atomicAdd(gcot + nb + a * CH, W * gv[a]);
+            }
+          }
+          const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
+          for (int a = 0; a < 3; ++a) {
+            const float ctv = Cb.m[0][a] * vi[0] + Cb.m[1][a] * vi[1] + Cb.m[2][a] * vi[2];
+            xb[a] += gW[a] * vg - D4 * W * ctv;
+          }
+        }
+    for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
+  }
+  __syncthreads();
+  if (seg_mode) {
+    segment_scatter<false>(e, bx, bsh, sh, 0.f, lg, gcot, 0);
+    __syncthreads();
+  }
+  if (bx.fits) box_flush(e, bx, bsh, gcot, 0, 3, lg, false);
+  block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
+}
+
+// four waves per SIMD, as for the P2G adjoint alone (three with the large box,
+// whose LDS allows no more)
+template <int BOXN, int MAT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BOXN > 512 ? 3 : 4, 8)))
+k_adj_pair(const float* __restrict__ st_prev, const float* __restrict__ st, float* part,
+           const float* __restrict__ cot_end, int64_t N, const EnvDev* __restrict__ envs,
+           const WorkItem* __restrict__ items, const float* __restrict__ grid_prev, float* gcot,
+           double* __restrict__ pacc, int runs, int k_call) {
+  adj_pair_item<BOXN, MAT>(blockIdx.x, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call);
+}
+
+template <int BOXN>
+static void launch_adj_pair_m(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
+                              const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev,
+                              float* gcot, double* pacc, int runs, int k_call, hipStream_t s, int mat) {
+  const dim3 g(n_items), blk(256);
+  switch (mat) {
+    case MAT_NEOHOOKEAN: hipLaunchKernelGGL((k_adj_pair<BOXN, MAT_NEOHOOKEAN>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    case MAT_COROTATED: hipLaunchKernelGGL((k_adj_pair<BOXN, MAT_COROTATED>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    case MAT_VONMISES: hipLaunchKernelGGL((k_adj_pair<BOXN, MAT_VONMISES>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    case MAT_FLUID_TAIT: hipLaunchKernelGGL((k_adj_pair<BOXN, MAT_FLUID_TAIT>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    case MAT_FLUID_PAPER: hipLaunchKernelGGL((k_adj_pair<BOXN, MAT_FLUID_PAPER>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    case -1: hipLaunchKernelGGL((k_adj_pair<BOXN, -1>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, runs, k_call); break;
+    default: break;
+  }
+}
+
+void launch_adj_pair(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
+                     const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev, float* gcot,
+                     double* pacc, int runs, int k_call, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_adj_pair_m<kBoxSmall>(st_prev, st, part, cot_end, N, envs, items, n_items, grid_prev, gcot, pacc, runs, k_call, s, mat);
+  else
+    launch_adj_pair_m<kBoxNodes>(st_prev, st, part, cot_end, N, envs, items, n_items, grid_prev, gcot, pacc, runs, k_call, s, mat);
+}
+
 template <int BOXN, int MAT>
 static void launch_p2g_lds_t(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {

@@ -29,7 +29,7 @@ using namespace mpmx;
 
 namespace {
 
-enum KernelClass { KC_P2G = 0, KC_GRID, KC_G2P, KC_SORT, KC_G2P_ADJ, KC_GRID_ADJ, KC_P2G_ADJ, KC_G2P2G, KC_COUNT };
+enum KernelClass { KC_P2G = 0, KC_GRID, KC_G2P, KC_SORT, KC_G2P_ADJ, KC_GRID_ADJ, KC_P2G_ADJ, KC_G2P2G, KC_ADJ_PAIR, KC_COUNT };
 
 struct TimedSpan {
   int kc;
@@ -110,6 +110,7 @@ struct mpm_batch {
   int box = 0;        // LDS box budget of the LDS-staged kernels: 0 = 1024 nodes, 1 = 384 nodes
   int specialize = 1; // LDS-staged kernels: 1 = one launch per material, compiled for it; 0 = one generic launch
   int fuse = 0;       // 1: G2P of substep k and P2G of substep k + 1 in one kernel (with the segment P2G)
+  int fuse_adj = 0;   // 1: P2G adjoint of substep k and G2P adjoint of substep k - 1 in one kernel
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -282,12 +283,56 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
   }
 }
 
+// batched-mode pieces of a substep's adjoint
+void batched_g2p_adj(mpm_batch* b, const float* st, const float* st_next, const float* cot_in, int gi, int kc) {
+  const hipStream_t s = b->stream;
+  const int ni = (int)b->items_h.size();
+  const int runs = b->min_run | (b->max_run << 16);
+  float* g = b->grid[gi];
+  Span sp(b, KC_G2P_ADJ);
+  if (b->var_g2p_adj == 0) launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
+  for (const auto& r : launch_ranges(b)) {
+    const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+    if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, runs, kc, b->grid_cap, b->box, r.mat, s);
+    else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
+  }
+}
+
+void batched_grid_adj(mpm_batch* b, int gi, int k_rel) {
+  Span sp(b, KC_GRID_ADJ);
+  launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock, 0.0, k_rel,
+                      b->motion_d, b->gmotion_d, b->stream);
+}
+
+void batched_p2g_adj(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int kc) {
+  const hipStream_t s = b->stream;
+  const int ni = (int)b->items_h.size();
+  Span sp(b, KC_P2G_ADJ);
+  if (b->var_p2g_adj == 0) launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
+  else
+    for (const auto& r : launch_ranges(b))
+      launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->gcot, b->pacc, kc, cot_in, b->grid_cap, b->box, r.mat, s);
+}
+
+// P2G adjoint of substep kc (state st) fused with the G2P adjoint of substep
+// kc - 1 (state st_prev, grid gi_prev); cot_end: the segment's incoming cotangent
+void batched_adj_pair(mpm_batch* b, const float* st_prev, const float* st, const float* cot_end, int gi_prev, int kc) {
+  const hipStream_t s = b->stream;
+  const int runs = b->min_run | (b->max_run << 16);
+  Span sp(b, KC_ADJ_PAIR);
+  for (const auto& r : launch_ranges(b))
+    launch_adj_pair(st_prev, st, b->part, cot_end, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first,
+                    r.count, b->grid[gi_prev], b->gcot, b->pacc, runs, kc, b->box, r.mat, s);
+}
+
+bool fused_adj(const mpm_batch* b) { return b->mode != MPM_MODE_PLAIN && b->fuse_adj; }
+
 void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const float* cot_in, float* cot_out, int gi,
                      int k_rel, int kc) {
-  float* g = b->grid[gi];
-  uint32_t* fl = b->flags[gi];
-  const hipStream_t s = b->stream;
   if (b->mode == MPM_MODE_PLAIN) {
+    float* g = b->grid[gi];
+    uint32_t* fl = b->flags[gi];
+    const hipStream_t s = b->stream;
     for (int e = 0; e < b->E; ++e) {
       const int i0 = b->item_off[e], ni = b->item_off[e + 1] - i0;
       const EnvDev& eh = b->envs_h[e];
@@ -297,26 +342,9 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const 
       { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, kc, cot_in, s); }
     }
   } else {
-    const int ni = (int)b->items_h.size();
-    const int runs = b->min_run | (b->max_run << 16);
-    const std::vector<mpm_batch::MatRange>& ranges = launch_ranges(b);
-    {
-      Span sp(b, KC_G2P_ADJ);
-      if (b->var_g2p_adj == 0) launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
-      for (const auto& r : ranges) {
-        const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
-        if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, runs, kc, b->grid_cap, b->box, r.mat, s);
-        else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
-      }
-    }
-    { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, g, fl, b->gcot, b->clock, 0.0, k_rel, b->motion_d, b->gmotion_d, s); }
-    {
-      Span sp(b, KC_P2G_ADJ);
-      if (b->var_p2g_adj == 0) launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
-      else
-        for (const auto& r : ranges)
-          launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->gcot, b->pacc, kc, cot_in, b->grid_cap, b->box, r.mat, s);
-    }
+    batched_g2p_adj(b, st, st_next, cot_in, gi, kc);
+    batched_grid_adj(b, gi, k_rel);
+    batched_p2g_adj(b, st, cot_in, cot_out, kc);
   }
 }
 
@@ -413,10 +441,27 @@ int bwd_segment(mpm_batch* b, int j, int Kj, bool have_tape, int c) {
       }
     }
   }
-  for (int k = Kj - 1; k >= 0; --k) {
-    const float* st = k == 0 ? b->ckpt[j] : b->seg[k];
-    adjoint_substep(b, st, b->seg[k + 1], b->cot[c], b->cot[c ^ 1], k + 1, k, j * b->K + k);
-    c ^= 1;
+  auto state = [&](int k) -> const float* { return k == 0 ? b->ckpt[j] : b->seg[k]; };
+  if (fused_adj(b) && Kj > 1) {
+    // G2P adjoint of the last substep, then [P2G adjoint k + G2P adjoint k - 1,
+    // grid adjoint k - 1] down to k = 1, then the P2G adjoint of substep 0. Only
+    // the segment's incoming cotangent and the result live in HBM; the result
+    // goes where the one-substep-at-a-time schedule leaves it
+    const float* cot_end = b->cot[c];
+    float* cot_res = b->cot[c ^ (Kj & 1)];
+    batched_g2p_adj(b, state(Kj - 1), b->seg[Kj], cot_end, Kj, j * b->K + Kj - 1);
+    batched_grid_adj(b, Kj, Kj - 1);
+    for (int k = Kj - 1; k >= 1; --k) {
+      batched_adj_pair(b, state(k - 1), state(k), cot_end, k, j * b->K + k);
+      batched_grid_adj(b, k, k - 1);
+    }
+    batched_p2g_adj(b, state(0), cot_end, cot_res, j * b->K);
+    c ^= Kj & 1;
+  } else {
+    for (int k = Kj - 1; k >= 0; --k) {
+      adjoint_substep(b, state(k), b->seg[k + 1], b->cot[c], b->cot[c ^ 1], k + 1, k, j * b->K + k);
+      c ^= 1;
+    }
   }
   launch_unpermute(b->cot[c], b->cot[c ^ 1], b->N, b->perm[j], b->stream);
   return c ^ 1;
@@ -510,7 +555,7 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
 
 namespace {
 
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse; };
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj; };
 
 // shape signature -> choice, shared by batches of the same shape in the process
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -533,6 +578,7 @@ void apply_choice(mpm_batch* b, const TuneChoice& c) {
   b->box = c.box;
   b->specialize = c.specialize;
   b->fuse = c.fuse;
+  b->fuse_adj = c.fuse_adj;
   drop_graphs(b);
 }
 
@@ -1036,6 +1082,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_BOX: if (value < 0 || value > 1) break; b->box = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE: if (value < 0 || value > 1) break; b->fuse = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_FUSE_ADJ: if (value < 0 || value > 1) break; b->fuse_adj = value; drop_graphs(b); return MPM_OK;
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -1055,6 +1102,7 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_BOX: *value = b->box; return MPM_OK;
     case MPM_OPT_SPECIALIZE: *value = b->specialize; return MPM_OK;
     case MPM_OPT_FUSE: *value = b->fuse; return MPM_OK;
+    case MPM_OPT_FUSE_ADJ: *value = b->fuse_adj; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
@@ -1128,7 +1176,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0, 0};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -1157,6 +1205,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.box, 0, 0, true}, {&best.box, 1, 0, true}},
       {{&best.specialize, 1, 0, true}, {&best.specialize, 0, 0, true}},
       {{&best.fuse, 0, 0, true}, {&best.fuse, 1, 0, true}},
+      {{&best.fuse_adj, 0, 0, true}, {&best.fuse_adj, 1, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

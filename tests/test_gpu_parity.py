@@ -309,15 +309,19 @@ def test_backward_needs_a_recorded_forward():
 
 
 # ------------------------------------------------------------------ per-env substep counts and slot reuse
-def test_per_env_substep_counts_match_separate_runs():
+@pytest.mark.parametrize("counts", [[7, 3], [7, 4]], ids=["stop-at-segment-end", "stop-inside-segment"])
+@pytest.mark.parametrize("fused", [0, 1], ids=["unfused", "fused"])
+def test_per_env_substep_counts_match_separate_runs(counts, fused):
+    from paper_2412_12089_amd import _capi as C
     from paper_2412_12089_amd.batch import Batch
     a = make_env(scenes.NEOHOOKEAN, N=1200, n=32, seed=90)
     b_ = make_env(scenes.COROTATED, N=1800, n=32, seed=91, F_dev=0.02)
     envs = [a, b_]
-    counts = [7, 3]
     cots = random_cotangents(envs, seed=92)
-    announce("forward_envs with counts [7, 3] vs separate runs")
+    announce(f"forward_envs with counts {counts} (fused kernels {fused}) vs separate runs")
     bt = Batch(envs, max_substeps=8, ckpt_every=3)
+    bt.set_option(C.OPT_FUSE, fused)
+    bt.set_option(C.OPT_FUSE_ADJ, fused)
     bt.set_particles_from_specs()
     bt.forward_envs(counts, record=True)
     st = [t.cpu().double().numpy() for t in bt.get_particles()]
@@ -367,10 +371,12 @@ def test_slot_reconfiguration_matches_oracle():
 
 
 # ------------------------------------------------------------------ kernel variants and the autotuner
-VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, per-material launches, fused G2P+P2G)
-    (0, 0, 0, 0, 0, 0, 1, 0), (1, 1, 1, 1, 0, 0, 1, 0), (2, 1, 2, 1, 0, 0, 1, 0), (2, 1, 2, 1, 7, 0, 1, 0),
-    (1, 0, 2, 0, 3, 0, 1, 0), (1, 1, 1, 1, 0, 1, 1, 0), (2, 1, 2, 1, 0, 1, 1, 0), (2, 1, 2, 1, 5, 1, 1, 0),
-    (1, 1, 1, 1, 0, 0, 0, 0), (2, 1, 2, 1, 6, 1, 0, 0), (2, 0, 2, 1, 0, 1, 1, 1), (2, 1, 2, 1, 0, 0, 0, 1),
+VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, per-material launches,
+              #  fused G2P+P2G, fused P2G adjoint + G2P adjoint)
+    (0, 0, 0, 0, 0, 0, 1, 0, 0), (1, 1, 1, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 7, 0, 1, 0, 0),
+    (1, 0, 2, 0, 3, 0, 1, 0, 0), (1, 1, 1, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 5, 1, 1, 0, 0),
+    (1, 1, 1, 1, 0, 0, 0, 0, 0), (2, 1, 2, 1, 6, 1, 0, 0, 0), (2, 0, 2, 1, 0, 1, 1, 1, 0), (2, 1, 2, 1, 0, 0, 0, 1, 0),
+    (2, 0, 2, 1, 0, 1, 1, 1, 1), (2, 1, 2, 1, 0, 0, 0, 1, 1), (0, 0, 0, 0, 0, 0, 1, 0, 1), (1, 1, 1, 1, 0, 1, 0, 0, 1),
 ]
 
 
@@ -385,7 +391,7 @@ def test_every_kernel_variant_matches_oracle(var):
     announce(f"variant {var}")
     b = Batch(envs, max_substeps=S, ckpt_every=K)
     for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP, C.OPT_BOX, C.OPT_SPECIALIZE,
-                         C.OPT_FUSE), var):
+                         C.OPT_FUSE, C.OPT_FUSE_ADJ), var):
         b.set_option(opt, val)
     b.set_particles_from_specs()
     b.forward(S, record=True)

@@ -224,7 +224,7 @@ def main():
         t0 = time.perf_counter()
         b.autotune(args.tune_ms)
         tune_s = time.perf_counter() - t0
-    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE", "FUSE_ADJ")}
+    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE", "FUSE_ADJ", "XCD")}
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy

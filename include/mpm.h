@@ -236,6 +236,11 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
                                   adjoint of substep k - 1 run as one kernel (the cotangent of state k stays
                                   in registers; the G2P adjoint part is the segment-reduced one). Batched
                                   mode. Default 0; the autotuner may set it */
+#define MPM_OPT_XCD 13         /* LDS-staged kernels: 1 = each launch's work items are ordered so that the
+                                  blocks one XCD receives (block i goes to XCD i mod 8) take a contiguous
+                                  run of items, keeping an env's grid lines in one XCD's L2; 0 = item
+                                  order (default). Results are the same up to float summation order; the
+                                  autotuner may set it */
 #define MPM_OPT_SPECIALIZE 10  /* LDS-staged kernels: 1 = one launch per material over that material's work items,
                                   compiled for it (default); 0 = one launch over all items, material read at run time */
 

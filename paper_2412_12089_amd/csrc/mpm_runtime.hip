@@ -56,8 +56,9 @@ struct mpm_batch {
   int cell_bits = 0, key_bits = 0;
   std::vector<WorkItem> items_h;
   std::vector<int> item_off;  // [E+1]
-  // the work items again, grouped by material, for the material-specialized
-  // LDS-staged kernels: one launch per (material, first, count) range
+  // the work items again for the LDS-staged kernels: [0, n) grouped by
+  // material (one launch per (material, first, count) range), [n, 2n) all
+  // items for the generic launch; each range in launch order (see xcd)
   struct MatRange { int mat, first, count; };
   std::vector<WorkItem> items_mat_h;
   std::vector<MatRange> mat_ranges;
@@ -111,6 +112,7 @@ struct mpm_batch {
   int specialize = 1; // LDS-staged kernels: 1 = one launch per material, compiled for it; 0 = one generic launch
   int fuse = 0;       // 1: G2P of substep k and P2G of substep k + 1 in one kernel (with the segment P2G)
   int fuse_adj = 0;   // 1: P2G adjoint of substep k and G2P adjoint of substep k - 1 in one kernel
+  int xcd = 0;        // 1: order each launch's items so that the blocks one XCD receives take a contiguous run
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -215,7 +217,8 @@ struct Span {
 // one per material, or one generic range (material -1) over all items in env order
 const std::vector<mpm_batch::MatRange>& launch_ranges(mpm_batch* b) {
   if (b->specialize) return b->mat_ranges;
-  b->generic_range.assign(1, {-1, 0, (int)b->items_h.size()});
+  const int n = (int)b->items_h.size();
+  b->generic_range.assign(1, {-1, n, n});
   return b->generic_range;
 }
 
@@ -228,7 +231,7 @@ void batched_p2g(mpm_batch* b, const float* in, int gi, int kc) {
   Span sp(b, KC_P2G);
   if (b->var_p2g == 0) launch_p2g_direct(in, b->N, b->envs_d, b->items_d, ni, b->grid[gi], b->flags[gi], b->errs, kc, s);
   for (const auto& r : launch_ranges(b)) {
-    const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+    const WorkItem* it = b->items_mat_d + r.first;
     if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, runs, kc, b->grid_cap, b->box, r.mat, s);
     else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, kc, b->grid_cap, b->box, r.mat, s);
   }
@@ -247,7 +250,7 @@ void batched_g2p(mpm_batch* b, const float* in, float* out, int gi, int kc) {
   if (b->var_g2p == 0) launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d, ni, b->grid[gi], b->errs, kc, s);
   else
     for (const auto& r : launch_ranges(b))
-      launch_g2p_lds(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->grid[gi],
+      launch_g2p_lds(in, out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->grid[gi],
                      b->errs, kc, b->grid_cap, b->box, r.mat, s);
 }
 
@@ -257,7 +260,7 @@ void batched_g2p2g(mpm_batch* b, const float* in, float* out, int gi_in, int gi_
   const int runs = b->min_run | (b->max_run << 16);
   Span sp(b, KC_G2P2G);
   for (const auto& r : launch_ranges(b))
-    launch_g2p2g(in, out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->grid[gi_in],
+    launch_g2p2g(in, out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->grid[gi_in],
                  b->grid[gi_out], b->flags[gi_out], b->errs, runs, kc, b->box, r.mat, s);
 }
 
@@ -292,7 +295,7 @@ void batched_g2p_adj(mpm_batch* b, const float* st, const float* st_next, const 
   Span sp(b, KC_G2P_ADJ);
   if (b->var_g2p_adj == 0) launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d, ni, g, b->gcot, b->pacc, kc, s);
   for (const auto& r : launch_ranges(b)) {
-    const WorkItem* it = r.mat < 0 ? b->items_d : b->items_mat_d + r.first;
+    const WorkItem* it = b->items_mat_d + r.first;
     if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, runs, kc, b->grid_cap, b->box, r.mat, s);
     else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
   }
@@ -311,7 +314,7 @@ void batched_p2g_adj(mpm_batch* b, const float* st, const float* cot_in, float* 
   if (b->var_p2g_adj == 0) launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d, ni, b->gcot, b->pacc, kc, cot_in, s);
   else
     for (const auto& r : launch_ranges(b))
-      launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first, r.count, b->gcot, b->pacc, kc, cot_in, b->grid_cap, b->box, r.mat, s);
+      launch_p2g_adjoint_lds(st, b->part, cot_out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->gcot, b->pacc, kc, cot_in, b->grid_cap, b->box, r.mat, s);
 }
 
 // P2G adjoint of substep kc (state st) fused with the G2P adjoint of substep
@@ -321,7 +324,7 @@ void batched_adj_pair(mpm_batch* b, const float* st_prev, const float* st, const
   const int runs = b->min_run | (b->max_run << 16);
   Span sp(b, KC_ADJ_PAIR);
   for (const auto& r : launch_ranges(b))
-    launch_adj_pair(st_prev, st, b->part, cot_end, b->N, b->envs_d, r.mat < 0 ? b->items_d : b->items_mat_d + r.first,
+    launch_adj_pair(st_prev, st, b->part, cot_end, b->N, b->envs_d, b->items_mat_d + r.first,
                     r.count, b->grid[gi_prev], b->gcot, b->pacc, runs, kc, b->box, r.mat, s);
 }
 
@@ -501,9 +504,22 @@ void drop_graphs(mpm_batch* b) {
   b->graphs.clear();
 }
 
-int upload_envs(mpm_batch* b) {
-  HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
-  // items grouped by material (env order kept inside a group)
+// Workgroups of a launch go to the eight XCDs in turn (block i to XCD i mod
+// 8), and each XCD has its own L2. Reordering a range so that block i takes
+// item start(i mod 8) + i / 8 gives every XCD one contiguous run of items:
+// the same few envs' grid lines then stay in one L2. A bijection for any n.
+void xcd_order(std::vector<WorkItem>& v, size_t first) {
+  constexpr size_t kXcd = 8;
+  const size_t n = v.size() - first, q = n / kXcd, r = n % kXcd;
+  const std::vector<WorkItem> src(v.begin() + first, v.end());
+  for (size_t i = 0; i < n; ++i) {
+    const size_t x = i % kXcd, j = i / kXcd;
+    v[first + i] = src[x * q + std::min(x, r) + j];
+  }
+}
+
+int upload_items(mpm_batch* b) {
+  // items grouped by material (env order kept inside a group), then all items
   std::vector<mpm_batch::MatRange> ranges;
   b->items_mat_h.clear();
   for (int m = 0; m < MAT_COUNT; ++m) {
@@ -512,7 +528,11 @@ int upload_envs(mpm_batch* b) {
       if (b->envs_h[it.env].material == m) b->items_mat_h.push_back(it);
     const int count = (int)b->items_mat_h.size() - first;
     if (count > 0) ranges.push_back({m, first, count});
+    if (b->xcd) xcd_order(b->items_mat_h, first);
   }
+  const size_t gen = b->items_mat_h.size();
+  b->items_mat_h.insert(b->items_mat_h.end(), b->items_h.begin(), b->items_h.end());
+  if (b->xcd) xcd_order(b->items_mat_h, gen);
   if (!b->items_mat_h.empty())
     HIPC(b, hipMemcpyAsync(b->items_mat_d, b->items_mat_h.data(), sizeof(WorkItem) * b->items_mat_h.size(),
                            hipMemcpyHostToDevice, b->stream));
@@ -524,6 +544,13 @@ int upload_envs(mpm_batch* b) {
     b->mat_ranges = ranges;
     drop_graphs(b);   // captured launches name the ranges
   }
+  return MPM_OK;
+}
+
+int upload_envs(mpm_batch* b) {
+  HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
+  const int rc = upload_items(b);
+  if (rc != MPM_OK) return rc;
   launch_prep_params(b->envs_d, b->E, b->stream);
   HIPC(b, hipGetLastError());
   return MPM_OK;
@@ -555,7 +582,7 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
 
 namespace {
 
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj; };
+struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj, xcd; };
 
 // shape signature -> choice, shared by batches of the same shape in the process
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -579,6 +606,10 @@ void apply_choice(mpm_batch* b, const TuneChoice& c) {
   b->specialize = c.specialize;
   b->fuse = c.fuse;
   b->fuse_adj = c.fuse_adj;
+  if (b->xcd != c.xcd) {
+    b->xcd = c.xcd;
+    (void)upload_items(b);
+  }
   drop_graphs(b);
 }
 
@@ -680,7 +711,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   };
   b->envs_d = (EnvDev*)A(sizeof(EnvDev) * b->E);
   b->items_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(b->items_h.size(), 1));
-  b->items_mat_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(b->items_h.size(), 1));
+  b->items_mat_d = (WorkItem*)A(sizeof(WorkItem) * std::max<size_t>(2 * b->items_h.size(), 1));
   b->tile_env_d = (int32_t*)A(sizeof(int32_t) * tile_env.size());
   b->W[0] = (float*)A(state_bytes);
   b->W[1] = (float*)A(state_bytes);
@@ -1083,6 +1114,13 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE: if (value < 0 || value > 1) break; b->fuse = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE_ADJ: if (value < 0 || value > 1) break; b->fuse_adj = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_XCD: {
+      if (value < 0 || value > 1) break;
+      b->xcd = value;
+      const int rc = upload_items(b);
+      drop_graphs(b);
+      return rc;
+    }
     default: break;
   }
   return fail(b, MPM_INVALID_ARG, "unknown option or value");
@@ -1103,6 +1141,7 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_SPECIALIZE: *value = b->specialize; return MPM_OK;
     case MPM_OPT_FUSE: *value = b->fuse; return MPM_OK;
     case MPM_OPT_FUSE_ADJ: *value = b->fuse_adj; return MPM_OK;
+    case MPM_OPT_XCD: *value = b->xcd; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
@@ -1176,7 +1215,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0, 0};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0, 0, 0};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -1206,6 +1245,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.specialize, 1, 0, true}, {&best.specialize, 0, 0, true}},
       {{&best.fuse, 0, 0, true}, {&best.fuse, 1, 0, true}},
       {{&best.fuse_adj, 0, 0, true}, {&best.fuse_adj, 1, 0, true}},
+      {{&best.xcd, 0, 0, true}, {&best.xcd, 1, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

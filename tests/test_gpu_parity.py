@@ -372,11 +372,12 @@ def test_slot_reconfiguration_matches_oracle():
 
 # ------------------------------------------------------------------ kernel variants and the autotuner
 VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, per-material launches,
-              #  fused G2P+P2G, fused P2G adjoint + G2P adjoint)
+              #  fused G2P+P2G, fused P2G adjoint + G2P adjoint[, XCD-ordered items])
     (0, 0, 0, 0, 0, 0, 1, 0, 0), (1, 1, 1, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 7, 0, 1, 0, 0),
     (1, 0, 2, 0, 3, 0, 1, 0, 0), (1, 1, 1, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 5, 1, 1, 0, 0),
     (1, 1, 1, 1, 0, 0, 0, 0, 0), (2, 1, 2, 1, 6, 1, 0, 0, 0), (2, 0, 2, 1, 0, 1, 1, 1, 0), (2, 1, 2, 1, 0, 0, 0, 1, 0),
     (2, 0, 2, 1, 0, 1, 1, 1, 1), (2, 1, 2, 1, 0, 0, 0, 1, 1), (0, 0, 0, 0, 0, 0, 1, 0, 1), (1, 1, 1, 1, 0, 1, 0, 0, 1),
+    (2, 0, 2, 1, 0, 1, 1, 1, 1, 1), (2, 1, 2, 1, 0, 0, 0, 1, 1, 1), (1, 1, 1, 1, 3, 1, 1, 0, 0, 1),
 ]
 
 
@@ -391,7 +392,7 @@ def test_every_kernel_variant_matches_oracle(var):
     announce(f"variant {var}")
     b = Batch(envs, max_substeps=S, ckpt_every=K)
     for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP, C.OPT_BOX, C.OPT_SPECIALIZE,
-                         C.OPT_FUSE, C.OPT_FUSE_ADJ), var):
+                         C.OPT_FUSE, C.OPT_FUSE_ADJ, C.OPT_XCD), var):
         b.set_option(opt, val)
     b.set_particles_from_specs()
     b.forward(S, record=True)

@@ -747,23 +747,31 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, con
       am[z] = 0.f;
       ap[z][0] = ap[z][1] = ap[z][2] = 0.f;
     }
+    // the lane's x and y weights, each B-spline piece as k (f - s)^2 + m with
+    // (k, s, m) fixed per lane: no per-particle select (which the compiler
+    // turns into divergent branches that stall the LDS loads)
+    const float kx = ox == 1 ? -1.f : 0.5f, sx = ox == 0 ? 1.5f : (ox == 1 ? 1.f : 0.5f), mx = ox == 1 ? 0.75f : 0.f;
+    const float ky = oy == 1 ? -1.f : 0.5f, sy = oy == 0 ? 1.5f : (oy == 1 ? 1.f : 0.5f), my = oy == 1 ? 0.75f : 0.f;
     // one particle's contribution to the lane's three z-nodes
     auto add = [&](int p) {
       const float4 P0 = sh.pd[p][0], P1 = sh.pd[p][1], P2 = sh.pd[p][2], P3 = sh.pd[p][3];
-      float w0[3], w1[3], w2[3];
-      bspline3(P0.w, w0);
-      bspline3(P1.w, w1);
+      float w2[3];
       bspline3(P2.w, w2);
-      const float wxy = sel3(w0, ox) * sel3(w1, oy);
+      const float dx0 = P0.w - sx, dy0 = P1.w - sy;
+      const float wxy = fmaf(kx * dx0, dx0, mx) * fmaf(ky * dy0, dy0, my);
       const float fx = (float)ox, fy = (float)oy;
       const float r0[3] = {P0.x + P1.x * fx + P1.y * fy, P0.y + P2.x * fx + P2.y * fy, P0.z + P3.x * fx + P3.y * fy};
       const float az[3] = {P1.z, P2.z, P3.z};
+      // r0 + az z for z = 0, 1, 2, written out (0 * az would not fold away)
+      const float W0 = wxy * w2[0], W1 = wxy * w2[1], W2 = wxy * w2[2];
+      am[0] += W0;
+      am[1] += W1;
+      am[2] += W2;
 #pragma unroll
-      for (int z = 0; z < 3; ++z) {
-        const float W = wxy * w2[z];
-        am[z] += W;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ap[z][a] = fmaf(W, r0[a] + az[a] * (float)z, ap[z][a]);
+      for (int a = 0; a < 3; ++a) {
+        ap[0][a] = fmaf(W0, r0[a], ap[0][a]);
+        ap[1][a] = fmaf(W1, r0[a] + az[a], ap[1][a]);
+        ap[2][a] = fmaf(W2, fmaf(2.f, az[a], r0[a]), ap[2][a]);
       }
     };
     int p = p0;

@@ -125,19 +125,21 @@ MD M3 m3_rotate_out(const M3& U, const M3& A) { return m3_mul_abt(m3_mul(U, A), 
 // symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (fixed sweeps,
 // no data-dependent loop): A = U diag(s) U^T
 // --------------------------------------------------------------------------
+// The rotation uses the hardware reciprocal and square root (about 1 ulp) and
+// no branch: c and s are built from t so that the rotation is orthogonal for
+// any t, and an inexact t only leaves a slightly larger off-diagonal entry for
+// the next sweep. A pair below 1e-30 counts as diagonal (that also keeps the
+// reciprocal of 2 apq finite).
 template <int p, int q, int r>
 MD void jacobi_rotate(M3& A, M3& V) {
   const float apq = A.m[p][q];
-  float t = 0.f;
-  if (apq != 0.f) {
-    const float theta = (A.m[q][q] - A.m[p][p]) / (2.f * apq);
-    const float at = fabsf(theta);
-    t = 1.f / (at + sqrtf(fmaf(at, at, 1.f)));
-    t = copysignf(t, theta);
-  }
+  const float theta = (A.m[q][q] - A.m[p][p]) * __builtin_amdgcn_rcpf(2.f * apq);
+  const float at = fabsf(theta);
+  const float tm = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.f)));
+  const float t = fabsf(apq) > 1e-30f ? copysignf(tm, theta) : 0.f;
   const float c = rsqrtf(fmaf(t, t, 1.f));
   const float s = t * c;
-  const float tau = s / (1.f + c);
+  const float tau = s * __builtin_amdgcn_rcpf(1.f + c);
   A.m[p][p] -= t * apq;
   A.m[q][q] += t * apq;
   A.m[p][q] = A.m[q][p] = 0.f;
@@ -282,8 +284,8 @@ MD StressPrep stress_prep_with_eig(const M3& H, const M3& U, const float l[3], i
 // singular value of F from an eigenvalue l of B: sqrt(1 + l), and sqrt(1 + l) - 1
 MD void sv_of(float l, float& s, float& sm1) {
   const float lc = fmaxf(l, -1.f);
-  s = sqrtf(1.f + lc);
-  sm1 = lc / (1.f + s);
+  s = __builtin_amdgcn_sqrtf(1.f + lc);   // about 1 ulp, like the reciprocal below
+  sm1 = lc * __builtin_amdgcn_rcpf(1.f + s);
 }
 // log strain of an eigenvalue of B, with the singular value clamped at kSigmaMin
 MD float log_strain(float l) { return 0.5f * log1pf(fmaxf(l, kSigmaMin * kSigmaMin - 1.f)); }
@@ -378,7 +380,7 @@ MD void stress_vjp_from(const EnvDev& e, const M3& H, const StressPrep& p, const
       // h(s) = s - sqrt(s): divided difference 1 - 1/(sigma_i + sigma_j)
       M3 Hd;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Hd.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - 1.f / (sg[i] + sg[j]));
+        for (int j = 0; j < 3; ++j) Hd.m[i][j] = 2.f * e.mu * G.m[i][j] * (1.f - __builtin_amdgcn_rcpf(sg[i] + sg[j]));
       const M3 bbar = m3_rotate_out(p.U, Hd);
       Fbar = m3_add(Fbar, m3_mul(m3_scale(bbar, 2.f), F));
       Fbar = m3_axpy(Fbar, trtb * e.lam * (2.f * J - 1.f), m3_cof(F));

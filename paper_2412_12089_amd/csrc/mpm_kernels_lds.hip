@@ -222,6 +222,17 @@ MD void st_m3(float* __restrict__ st, int64_t N, int64_t p, int c0, const M3& m)
 // a[i] for a runtime i in {0,1,2} without indexing a register array
 MD float sel3(const float a[3], int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
 
+// quadratic B-spline weight of node offset o (0, 1, 2) at f = x n - base, and
+// its f-derivative: each piece is w = k (f - s)^2 + m, dw/df = 2 k (f - s). For
+// a wave-uniform o the constants are scalars and the weight costs three
+// instructions, so loops can recompute it instead of holding a table
+MD void spline_piece(int o, float f, float& w, float& dw) {
+  const float k = o == 1 ? -1.f : 0.5f, sft = o == 0 ? 1.5f : (o == 1 ? 1.f : 0.5f), m = o == 1 ? 0.75f : 0.f;
+  const float u = f - sft;
+  w = fmaf(k * u, u, m);
+  dw = 2.f * k * u;
+}
+
 MD void stencil_offsets(const Stencil& sc, const EnvDev& e, int ox, int oy, int oz, float& W, float d[3]) {
   W = sel3(sc.w[0], ox) * sc.w[1][oy] * sc.w[2][oz];
   d[0] = ((float)ox - sc.f[0]) * e.dx;
@@ -458,6 +469,7 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
     st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
+    float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
@@ -486,10 +498,12 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
           }
           const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
           for (int a = 0; a < 3; ++a) {
-            const float ctv = Cb.m[0][a] * vi[0] + Cb.m[1][a] * vi[1] + Cb.m[2][a] * vi[2];
-            xb[a] += gW[a] * vg - D4 * W * ctv;
+            xb[a] = fmaf(gW[a], vg, xb[a]);
+            sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+    // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
+    for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
   }
   if (bx.fits) {
@@ -579,36 +593,49 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll 1
-        for (int oz = 0; oz < 3; ++oz) {   // rolled: the register budget, not issue, limits this kernel
-          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sel3(sc.w[2], oz);
-          const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sel3(sc.dw[2], oz)};
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
-          float mb, Pb[3];
+      for (int oy = 0; oy < 3; ++oy) {
+        // the column's three z-nodes are loaded together, then summed
+        float mb[3], Pb[3][3];
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
           if (bx.fits) {
             const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            mb = lds[idx];
-            for (int a = 0; a < 3; ++a) Pb[a] = lds[(1 + a) * bx.nodes + idx];
+            mb[oz] = lds[idx];
+            for (int a = 0; a < 3; ++a) Pb[oz][a] = lds[(1 + a) * bx.nodes + idx];
           } else {
             const float* gc = gcot + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            mb = gc[3 * CH];
-            for (int a = 0; a < 3; ++a) Pb[a] = gc[(4 + a) * CH];
+            mb[oz] = gc[3 * CH];
+            for (int a = 0; a < 3; ++a) Pb[oz][a] = gc[(4 + a) * CH];
           }
-          float gw = e.mp * mb;
-          for (int a = 0; a < 3; ++a) gw += Pb[a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
-          sm = fmaf(W, mb, sm);
+        }
+        float wx, wy, dwx, dwy;
+        spline_piece(ox, sc.f[0], wx, dwx);
+        spline_piece(oy, sc.f[1], wy, dwy);
+        dwx *= e.fn;
+        dwy *= e.fn;
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wz = sc.w[2][oz];
+          const float W = wx * wy * wz;
+          const float gW[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * e.fn * sc.dw[2][oz]};
+          const float d[3] = {d0, d1, ((float)oz - sc.f[2]) * e.dx};
+          float gw = e.mp * mb[oz];
+          for (int a = 0; a < 3; ++a)
+            gw += Pb[oz][a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+          sm = fmaf(W, mb[oz], sm);
           for (int a = 0; a < 3; ++a) {
-            const float wp = W * Pb[a];
+            const float wp = W * Pb[oz][a];
             sP[a] += wp;
             Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
             Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
             Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
-            const float atp = A.m[0][a] * Pb[0] + A.m[1][a] * Pb[1] + A.m[2][a] * Pb[2];
-            xb[a] += gW[a] * gw - W * atp;
+            xb[a] = fmaf(gW[a], gw, xb[a]);
           }
         }
+      }
+    // the stencil sum of -W A^T Pbar is -A^T sP
+    for (int a = 0; a < 3; ++a) xb[a] -= A.m[0][a] * sP[0] + A.m[1][a] * sP[1] + A.m[2][a] * sP[2];
     const M3 Cm = ld_m3(st, N, p, 6);
     const M3 H = ld_m3(st, N, p, 15);
     StressPrep spr;
@@ -1109,6 +1136,7 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
       seg_store(sh, t, q, ab, sc.f);
     }
     st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
+    float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
@@ -1137,10 +1165,12 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
           }
           const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
           for (int a = 0; a < 3; ++a) {
-            const float ctv = Cb.m[0][a] * vi[0] + Cb.m[1][a] * vi[1] + Cb.m[2][a] * vi[2];
-            xb[a] += gW[a] * vg - D4 * W * ctv;
+            xb[a] = fmaf(gW[a], vg, xb[a]);
+            sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+    // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
+    for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
   }
   __syncthreads();
@@ -1281,37 +1311,49 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
 #pragma unroll 1
       for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
-        for (int oy = 0; oy < 3; ++oy)
-#pragma unroll 1
+        for (int oy = 0; oy < 3; ++oy) {
+          // the column's three z-nodes are loaded together, then summed
+          float mb[3], Pb[3][3];
+#pragma unroll
           for (int oz = 0; oz < 3; ++oz) {
-            const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sel3(sc.w[2], oz);
-            const float W = wx * wy * wz;
-            const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz,
-                                 e.fn * wx * wy * sel3(sc.dw[2], oz)};
-            const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
-            float mb, Pb[3];
             if (bx.fits) {
               const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-              mb = buf[idx];
-              for (int a = 0; a < 3; ++a) Pb[a] = buf[(1 + a) * bx.nodes + idx];
+              mb[oz] = buf[idx];
+              for (int a = 0; a < 3; ++a) Pb[oz][a] = buf[(1 + a) * bx.nodes + idx];
             } else {
               const float* gc = gcot + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-              mb = gc[3 * CH];
-              for (int a = 0; a < 3; ++a) Pb[a] = gc[(4 + a) * CH];
+              mb[oz] = gc[3 * CH];
+              for (int a = 0; a < 3; ++a) Pb[oz][a] = gc[(4 + a) * CH];
             }
-            float gw = e.mp * mb;
-            for (int a = 0; a < 3; ++a) gw += Pb[a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
-            sm = fmaf(W, mb, sm);
+          }
+          float wx, wy, dwx, dwy;
+          spline_piece(ox, sc.f[0], wx, dwx);
+          spline_piece(oy, sc.f[1], wy, dwy);
+          dwx *= e.fn;
+          dwy *= e.fn;
+          const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz) {
+            const float wz = sc.w[2][oz];
+            const float W = wx * wy * wz;
+            const float gW[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * e.fn * sc.dw[2][oz]};
+            const float d[3] = {d0, d1, ((float)oz - sc.f[2]) * e.dx};
+            float gw = e.mp * mb[oz];
+            for (int a = 0; a < 3; ++a)
+              gw += Pb[oz][a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+            sm = fmaf(W, mb[oz], sm);
             for (int a = 0; a < 3; ++a) {
-              const float wp = W * Pb[a];
+              const float wp = W * Pb[oz][a];
               sP[a] += wp;
               Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
               Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
               Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
-              const float atp = A.m[0][a] * Pb[0] + A.m[1][a] * Pb[1] + A.m[2][a] * Pb[2];
-              xb[a] += gW[a] * gw - W * atp;
+              xb[a] = fmaf(gW[a], gw, xb[a]);
             }
           }
+        }
+      // the stencil sum of -W A^T Pbar is -A^T sP
+      for (int a = 0; a < 3; ++a) xb[a] -= A.m[0][a] * sP[0] + A.m[1][a] * sP[1] + A.m[2][a] * sP[2];
       const M3 Cm = ld_m3(st, N, p, 6);
       const M3 H = ld_m3(st, N, p, 15);
       StressPrep spr;
@@ -1376,6 +1418,7 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
       seg_store(sh, t, q, ab, sc.f);
     }
     st_m3(part, N, p, 3, Fb);
+    float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
@@ -1404,10 +1447,12 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
           }
           const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
           for (int a = 0; a < 3; ++a) {
-            const float ctv = Cb.m[0][a] * vi[0] + Cb.m[1][a] * vi[1] + Cb.m[2][a] * vi[2];
-            xb[a] += gW[a] * vg - D4 * W * ctv;
+            xb[a] = fmaf(gW[a], vg, xb[a]);
+            sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+    // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
+    for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
   }
   __syncthreads();

@@ -43,9 +43,14 @@ def gpu_rollout(envs, S, K, mode="batched", cots=None, timing=False):
     """Forward S substeps (recorded) and, if cots are given, the backward.
 
     Returns dict(state=(x,v,C,F) numpy float64, grads=(dx,dv,dC,dF) or None,
-    dparams=[E,8] or None, status=sync code)."""
-    b = Batch(envs, max_substeps=max(S, 1), ckpt_every=K, mode=mode)
+    dparams=[E,8] or None, status=sync code). mode "batched-fused": the batched
+    mode with the fused G2P + P2G and adjoint-pair schedules."""
+    b = Batch(envs, max_substeps=max(S, 1), ckpt_every=K, mode=mode.split("-")[0])
     try:
+        if mode == "batched-fused":
+            from paper_2412_12089_amd import _capi as C
+            b.set_option(C.OPT_FUSE, 1)
+            b.set_option(C.OPT_FUSE_ADJ, 1)
         b.set_particles_from_specs()
         b.forward(S, record=cots is not None)
         st = tuple(to_np(t) for t in b.get_particles())

@@ -111,7 +111,7 @@ MATERIAL_CASES = [
 
 
 @pytest.mark.parametrize("mat,kw,pidx", MATERIAL_CASES, ids=[scenes.MATERIAL_NAMES[m[0]] for m in MATERIAL_CASES])
-@pytest.mark.parametrize("mode", ["plain", "batched"])
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
 def test_material_forward_and_gradient(mat, kw, pidx, mode):
     spec = make_env(mat, N=2500, seed=10 + mat, **kw)
     S, K = 8, 3
@@ -177,8 +177,9 @@ def test_edge_box_has_sliding_edge_nodes():
 
 
 @pytest.mark.parametrize("geom", ["face", "edge"])
-@pytest.mark.parametrize("mode", ["plain", "batched"])
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
 def test_collider_actions_forward_and_gradient(mode, geom):
+    from paper_2412_12089_amd import _capi as C
     from paper_2412_12089_amd.batch import Batch
     box = BOXES[geom]
     spec = make_env(scenes.FLUID_TAIT, N=3000, seed=44, collider=box, v_scale=0.2)
@@ -189,8 +190,11 @@ def test_collider_actions_forward_and_gradient(mode, geom):
     announce(f"tait + box ({geom}) driven by {S} actions, {mode}")
     envs = [spec, other]
     cots = random_cotangents(envs, seed=47)
-    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode)
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode.split("-")[0])
     try:
+        if mode == "batched-fused":   # the fused G2P + P2G and adjoint-pair schedules
+            b.set_option(C.OPT_FUSE, 1)
+            b.set_option(C.OPT_FUSE_ADJ, 1)
         b.set_particles_from_specs()
         b.set_collider_motion(0, vel)
         b.forward(S, record=True)

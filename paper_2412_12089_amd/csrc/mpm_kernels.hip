@@ -667,6 +667,8 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
   const Stencil sc = make_stencil(x, e.n, e.fn);
   float vn[3] = {0.f, 0.f, 0.f};
   M3 Cn = m3_zero();
+  const StencilAddr sa = stencil_addr(e, sc.b);
+  const float* genv = grid + (int64_t)e.tile_off * 512;
 #pragma unroll
   for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
@@ -675,7 +677,7 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
       for (int oz = 0; oz < 3; ++oz) {
         const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
         const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
-        const float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+        const float* g = genv + (sa.x[ox] + sa.y[oy] + sa.z[oz]);
         const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {

@@ -33,6 +33,7 @@ struct BoxShared {
   int lo[kMaxRuns][3];
   int off[kMaxRuns + 1];  // first LDS node of each run's box; off[nruns] = total
   int ext[kMaxRuns][3];
+  float inv_yz[kMaxRuns], inv_z[kMaxRuns];   // 1 / (ext y * ext z), 1 / ext z
   int nruns;
 };
 
@@ -109,6 +110,8 @@ MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count,
         bs.ext[k][a] = hi - lo + 1;
         n *= bs.ext[k][a];
       }
+      bs.inv_yz[k] = 1.f / (float)(bs.ext[k][1] * bs.ext[k][2]);
+      bs.inv_z[k] = 1.f / (float)bs.ext[k][2];
       acc += n;
     }
     bs.off[nr] = acc;
@@ -134,14 +137,21 @@ MD int box_index(const Box& bx, int i, int j, int k) {
 MD int box_index_run(const BoxShared& bs, int r, int i, int j, int k) {
   return bs.off[r] + ((i - bs.lo[r][0]) * bs.ext[r][1] + (j - bs.lo[r][1])) * bs.ext[r][2] + (k - bs.lo[r][2]);
 }
+// quotient of 0 <= a < 2048 by 1 <= d <= 1024 (box nodes never exceed 1024)
+// from a float reciprocal of d: (a + 1/2) / d lies at least 1/(2d) inside
+// (q, q + 1), and the product's rounding stays below 2048 * 2^-23
+MD int small_div(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
+
 MD void box_node(const BoxShared& bs, int idx, int& i, int& j, int& k) {
   int r = 0;
   while (r + 1 < kMaxRuns && r + 1 < bs.nruns && bs.off[r + 1] <= idx) ++r;
   const int loc = idx - bs.off[r];
-  const int yz = bs.ext[r][1] * bs.ext[r][2];
-  i = bs.lo[r][0] + loc / yz;
-  j = bs.lo[r][1] + (loc / bs.ext[r][2]) % bs.ext[r][1];
-  k = bs.lo[r][2] + loc % bs.ext[r][2];
+  const int qi = small_div(loc, bs.inv_yz[r]);
+  const int rem = loc - qi * bs.ext[r][1] * bs.ext[r][2];
+  const int qj = small_div(rem, bs.inv_z[r]);
+  i = bs.lo[r][0] + qi;
+  j = bs.lo[r][1] + qj;
+  k = bs.lo[r][2] + rem - qj * bs.ext[r][2];
 }
 
 // copies channels [c0, c0+nc) of every box node from a grid buffer into LDS
@@ -951,15 +961,18 @@ MD void g2p2g_item(int item_idx, const float* __restrict__ st, float* __restrict
   M3 Cn = m3_zero();
   if (valid) {
     const Stencil sc = make_stencil(x, e.n, e.fn);
+    const StencilAddr sa = stencil_addr(e, sc.b);
+    const float* genv = grid_in + (int64_t)e.tile_off * 512;
 #pragma unroll 1
-    for (int ox = 0; ox < 3; ++ox)
+    for (int ox = 0; ox < 3; ++ox) {
+      const uint32_t ax = ox == 0 ? sa.x[0] : (ox == 1 ? sa.x[1] : sa.x[2]);
 #pragma unroll
       for (int oy = 0; oy < 3; ++oy)
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
           const float W = sel3(sc.w[0], ox) * sc.w[1][oy] * sc.w[2][oz];
           const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
-          const float* g = grid_in + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          const float* g = genv + (ax + sa.y[oy] + sa.z[oz]);
           const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -970,6 +983,7 @@ MD void g2p2g_item(int item_idx, const float* __restrict__ st, float* __restrict
             Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
           }
         }
+    }
   }
   Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
   float xn[3];

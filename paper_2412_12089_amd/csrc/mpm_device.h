@@ -189,7 +189,16 @@ struct Stencil {
 };
 
 // base = floor(x n - 1/2) evaluated in FP64: exact for FP32 x, so binning is bit-exact
-MD int base_floor(float x, int n) { return (int)floor((double)x * (double)n - 0.5); }
+// base = floor(x n - 1/2), bit-exact for FP32 x and n < 2^22 in FP32 alone: the
+// fma rounds x n - 1/2 once, which can only carry it up onto the next integer;
+// the residual x n - (b + 1/2), also one fma, has the exact sign and undoes
+// that case
+MD int base_floor(float x, int n) {
+  const float fn = (float)n;
+  float b = floorf(fmaf(x, fn, -0.5f));
+  if (fmaf(x, fn, -(b + 0.5f)) < 0.f) b -= 1.f;
+  return (int)b;
+}
 
 MD Stencil make_stencil(const float x[3], int n, float fn) {
   Stencil st;

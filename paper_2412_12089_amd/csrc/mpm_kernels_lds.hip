@@ -480,19 +480,28 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
     const M3 Fb = m3_mul_atb(G, Ftrb);
     st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
     float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
+    // per particle: the z factors of gW and of the affine cotangent
+    float gz[3], cz[3];
+    for (int o = 0; o < 3; ++o) gz[o] = e.fn * sc.dw[2][o];
+    for (int a = 0; a < 3; ++a) cz[a] = D4 * Cb.m[a][2];
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
-      for (int oy = 0; oy < 3; ++oy)
+      for (int oy = 0; oy < 3; ++oy) {
+        // column invariants: the x/y weight factors and vbar + D4 Cbar d at d_z = 0
+        const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy);
+        const float wxy = wx * wy, gx = e.fn * sel3(sc.dw[0], ox) * wy, gy = e.fn * wx * sel3(sc.dw[1], oy);
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        float gc[3];
+        for (int a = 0; a < 3; ++a) gc[a] = fmaf(D4, fmaf(Cb.m[a][0], d0, Cb.m[a][1] * d1), vb[a]);
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
-          const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float wz = sc.w[2][oz];
+          const float W = wxy * wz;
+          const float gW[3] = {gx * wz, gy * wz, wxy * gz[oz]};
+          const float d2 = ((float)oz - sc.f[2]) * e.dx;
           float vi[3], gv[3];
-          for (int a = 0; a < 3; ++a)
-            gv[a] = vb[a] + D4 * (Cb.m[a][0] * d[0] + Cb.m[a][1] * d[1] + Cb.m[a][2] * d[2]);
+          for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
           if (bx.fits) {
             const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
             for (int a = 0; a < 3; ++a) {
@@ -512,6 +521,7 @@ MD void g2p_adjoint_lds_item(int item_idx, const float* __restrict__ st, const f
             sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+      }
     // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
     for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
@@ -708,10 +718,11 @@ constexpr int kItem = 256;
 
 struct SegShared {
   // per particle, four 16-byte rows read with one 128-bit LDS load each:
-  // (q0 q1 q2 f0) (A00 A01 A02 f1) (A10 A11 A12 f2) (A20 A21 A22 -), where q is
-  // the value at the base node offset o = 0 (before the weight), Abar (row-major)
-  // its change per unit node offset and f = x n - base (the weights are
-  // recomputed from it)
+  // (q0 q1 q2 fx) (A00 A01 A02 fy) (A10 A11 A12 wz0) (A20 A21 A22 wz1), where q
+  // is the value at the base node offset o = 0 (before the weight), Abar
+  // (row-major) its change per unit node offset, f = x n - base on x and y
+  // (each lane evaluates its own x and y weight from it) and wz the first two
+  // z weights (the third is 1 - wz0 - wz1)
   float4 pd[kItem][4];
   int key[kItem];        // packed base (10 bits per axis)
   int first[kItem + 1];  // first particle of each segment, then the count
@@ -732,10 +743,12 @@ MD int pack_base(const int b[3]) { return (b[0] << 20) | (b[1] << 10) | b[2]; }
 
 // stores particle t's scatter data: q (3), Abar (3x3, row-major), f (3)
 MD void seg_store(SegShared& sh, int t, const float q[3], const float ab[3][3], const float f[3]) {
+  float wz[3];
+  bspline3(f[2], wz);
   sh.pd[t][0] = make_float4(q[0], q[1], q[2], f[0]);
   sh.pd[t][1] = make_float4(ab[0][0], ab[0][1], ab[0][2], f[1]);
-  sh.pd[t][2] = make_float4(ab[1][0], ab[1][1], ab[1][2], f[2]);
-  sh.pd[t][3] = make_float4(ab[2][0], ab[2][1], ab[2][2], 0.f);
+  sh.pd[t][2] = make_float4(ab[1][0], ab[1][1], ab[1][2], wz[0]);
+  sh.pd[t][3] = make_float4(ab[2][0], ab[2][1], ab[2][2], wz[1]);
 }
 
 // marks segment starts among the item's particles (thread t <-> particle t)
@@ -792,8 +805,7 @@ MD void segment_scatter(const EnvDev& e, const Box& bx, const BoxShared& bs, con
     // one particle's contribution to the lane's three z-nodes
     auto add = [&](int p) {
       const float4 P0 = sh.pd[p][0], P1 = sh.pd[p][1], P2 = sh.pd[p][2], P3 = sh.pd[p][3];
-      float w2[3];
-      bspline3(P2.w, w2);
+      const float w2[3] = {P2.w, P3.w, 1.f - P2.w - P3.w};
       const float dx0 = P0.w - sx, dy0 = P1.w - sy;
       const float wxy = fmaf(kx * dx0, dx0, mx) * fmaf(ky * dy0, dy0, my);
       const float fx = (float)ox, fy = (float)oy;
@@ -1151,19 +1163,28 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
     }
     st_m3(part, N, p, 3, Fb);   // stored before the stencil loop: fewer live registers in it
     float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
+    // per particle: the z factors of gW and of the affine cotangent
+    float gz[3], cz[3];
+    for (int o = 0; o < 3; ++o) gz[o] = e.fn * sc.dw[2][o];
+    for (int a = 0; a < 3; ++a) cz[a] = D4 * Cb.m[a][2];
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
-      for (int oy = 0; oy < 3; ++oy)
+      for (int oy = 0; oy < 3; ++oy) {
+        // column invariants: the x/y weight factors and vbar + D4 Cbar d at d_z = 0
+        const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy);
+        const float wxy = wx * wy, gx = e.fn * sel3(sc.dw[0], ox) * wy, gy = e.fn * wx * sel3(sc.dw[1], oy);
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        float gc[3];
+        for (int a = 0; a < 3; ++a) gc[a] = fmaf(D4, fmaf(Cb.m[a][0], d0, Cb.m[a][1] * d1), vb[a]);
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
-          const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float wz = sc.w[2][oz];
+          const float W = wxy * wz;
+          const float gW[3] = {gx * wz, gy * wz, wxy * gz[oz]};
+          const float d2 = ((float)oz - sc.f[2]) * e.dx;
           float vi[3], gv[3];
-          for (int a = 0; a < 3; ++a)
-            gv[a] = vb[a] + D4 * (Cb.m[a][0] * d[0] + Cb.m[a][1] * d[1] + Cb.m[a][2] * d[2]);
+          for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
           if (bx.fits) {
             const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
             for (int a = 0; a < 3; ++a) {
@@ -1183,6 +1204,7 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
             sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+      }
     // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
     for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
@@ -1433,19 +1455,28 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
     }
     st_m3(part, N, p, 3, Fb);
     float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
+    // per particle: the z factors of gW and of the affine cotangent
+    float gz[3], cz[3];
+    for (int o = 0; o < 3; ++o) gz[o] = e.fn * sc.dw[2][o];
+    for (int a = 0; a < 3; ++a) cz[a] = D4 * Cb.m[a][2];
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll 1
-      for (int oy = 0; oy < 3; ++oy)
+      for (int oy = 0; oy < 3; ++oy) {
+        // column invariants: the x/y weight factors and vbar + D4 Cbar d at d_z = 0
+        const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy);
+        const float wxy = wx * wy, gx = e.fn * sel3(sc.dw[0], ox) * wy, gy = e.fn * wx * sel3(sc.dw[1], oy);
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        float gc[3];
+        for (int a = 0; a < 3; ++a) gc[a] = fmaf(D4, fmaf(Cb.m[a][0], d0, Cb.m[a][1] * d1), vb[a]);
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy), wz = sc.w[2][oz];
-          const float W = wx * wy * wz;
-          const float gW[3] = {e.fn * sel3(sc.dw[0], ox) * wy * wz, e.fn * wx * sel3(sc.dw[1], oy) * wz, e.fn * wx * wy * sc.dw[2][oz]};
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
+          const float wz = sc.w[2][oz];
+          const float W = wxy * wz;
+          const float gW[3] = {gx * wz, gy * wz, wxy * gz[oz]};
+          const float d2 = ((float)oz - sc.f[2]) * e.dx;
           float vi[3], gv[3];
-          for (int a = 0; a < 3; ++a)
-            gv[a] = vb[a] + D4 * (Cb.m[a][0] * d[0] + Cb.m[a][1] * d[1] + Cb.m[a][2] * d[2]);
+          for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
           if (bx.fits) {
             const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
             for (int a = 0; a < 3; ++a) {
@@ -1465,6 +1496,7 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
             sv[a] = fmaf(W, vi[a], sv[a]);
           }
         }
+      }
     // the stencil sum of -D4 W Cbar^T v_i is -D4 Cbar^T sv
     for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];

@@ -669,25 +669,36 @@ __global__ void __launch_bounds__(256) k_g2p_direct(const float* __restrict__ st
   M3 Cn = m3_zero();
   const StencilAddr sa = stencil_addr(e, sc.b);
   const float* genv = grid + (int64_t)e.tile_off * 512;
+  float wdz[3];
+  for (int o = 0; o < 3; ++o) wdz[o] = sc.w[2][o] * ((float)o - sc.f[2]) * e.dx;
 #pragma unroll
   for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
-    for (int oy = 0; oy < 3; ++oy)
+    for (int oy = 0; oy < 3; ++oy) {
+      // a z-column shares d_x and d_y: sum W v_i and W v_i d_z over it, then
+      // add the column into v and C
+      const float wxy = sc.w[0][ox] * sc.w[1][oy];
+      const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+      float col[3] = {0.f, 0.f, 0.f}, colz[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int oz = 0; oz < 3; ++oz) {
-        const float W = sc.w[0][ox] * sc.w[1][oy] * sc.w[2][oz];
-        const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
         const float* g = genv + (sa.x[ox] + sa.y[oy] + sa.z[oz]);
         const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+        const float W = wxy * sc.w[2][oz], Wd = wxy * wdz[oz];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          vn[a] = fmaf(W, vi[a], vn[a]);
-          const float wv = W * vi[a];
-          Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
-          Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
-          Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
+          col[a] = fmaf(W, vi[a], col[a]);
+          colz[a] = fmaf(Wd, vi[a], colz[a]);
         }
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        vn[a] += col[a];
+        Cn.m[a][0] = fmaf(col[a], d0, Cn.m[a][0]);
+        Cn.m[a][1] = fmaf(col[a], d1, Cn.m[a][1]);
+        Cn.m[a][2] += colz[a];
+      }
+    }
   Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
   PState s;
   for (int a = 0; a < 3; ++a) { s.x[a] = fmaf(e.dt, vn[a], x[a]); s.v[a] = vn[a]; }

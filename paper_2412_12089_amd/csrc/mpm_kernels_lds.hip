@@ -631,27 +631,30 @@ MD void p2g_adjoint_lds_item(int item_idx, const float* __restrict__ st,
         float wx, wy, dwx, dwy;
         spline_piece(ox, sc.f[0], wx, dwx);
         spline_piece(oy, sc.f[1], wy, dwy);
-        dwx *= e.fn;
-        dwy *= e.fn;
+        const float wxy = wx * wy, gxw = e.fn * dwx * wy, gyw = e.fn * wx * dwy;
         const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        // column invariant m_p v + A d at d_z = 0; column sums of W Pbar and W Pbar d_z
+        float uc[3], cP[3] = {0.f, 0.f, 0.f}, cPz[3] = {0.f, 0.f, 0.f};
+        for (int a = 0; a < 3; ++a) uc[a] = fmaf(A.m[a][0], d0, fmaf(A.m[a][1], d1, e.mp * v[a]));
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float wz = sc.w[2][oz];
-          const float W = wx * wy * wz;
-          const float gW[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * e.fn * sc.dw[2][oz]};
-          const float d[3] = {d0, d1, ((float)oz - sc.f[2]) * e.dx};
+          const float wz = sc.w[2][oz], dz = ((float)oz - sc.f[2]) * e.dx;
+          const float W = wxy * wz, Wd = W * dz;
+          const float gW[3] = {gxw * wz, gyw * wz, wxy * e.fn * sc.dw[2][oz]};
           float gw = e.mp * mb[oz];
-          for (int a = 0; a < 3; ++a)
-            gw += Pb[oz][a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+          for (int a = 0; a < 3; ++a) gw = fmaf(Pb[oz][a], fmaf(A.m[a][2], dz, uc[a]), gw);
           sm = fmaf(W, mb[oz], sm);
           for (int a = 0; a < 3; ++a) {
-            const float wp = W * Pb[oz][a];
-            sP[a] += wp;
-            Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
-            Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
-            Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
+            cP[a] = fmaf(W, Pb[oz][a], cP[a]);
+            cPz[a] = fmaf(Wd, Pb[oz][a], cPz[a]);
             xb[a] = fmaf(gW[a], gw, xb[a]);
           }
+        }
+        for (int a = 0; a < 3; ++a) {
+          sP[a] += cP[a];
+          Ab.m[a][0] = fmaf(cP[a], d0, Ab.m[a][0]);
+          Ab.m[a][1] = fmaf(cP[a], d1, Ab.m[a][1]);
+          Ab.m[a][2] += cPz[a];
         }
       }
     // the stencil sum of -W A^T Pbar is -A^T sP
@@ -975,26 +978,41 @@ MD void g2p2g_item(int item_idx, const float* __restrict__ st, float* __restrict
     const Stencil sc = make_stencil(x, e.n, e.fn);
     const StencilAddr sa = stencil_addr(e, sc.b);
     const float* genv = grid_in + (int64_t)e.tile_off * 512;
+    // z offsets and their weighted copies, per particle
+    float dz[3], wdz[3];
+    for (int o = 0; o < 3; ++o) {
+      dz[o] = ((float)o - sc.f[2]) * e.dx;
+      wdz[o] = sc.w[2][o] * dz[o];
+    }
 #pragma unroll 1
     for (int ox = 0; ox < 3; ++ox) {
       const uint32_t ax = ox == 0 ? sa.x[0] : (ox == 1 ? sa.x[1] : sa.x[2]);
+      const float wx = sel3(sc.w[0], ox), d0 = ((float)ox - sc.f[0]) * e.dx;
 #pragma unroll
-      for (int oy = 0; oy < 3; ++oy)
+      for (int oy = 0; oy < 3; ++oy) {
+        // a z-column shares d_x and d_y: sum W v_i and W v_i d_z over it,
+        // then add the column into v and C
+        const float wxy = wx * sc.w[1][oy], d1 = ((float)oy - sc.f[1]) * e.dx;
+        float col[3] = {0.f, 0.f, 0.f}, colz[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
-          const float W = sel3(sc.w[0], ox) * sc.w[1][oy] * sc.w[2][oz];
-          const float d[3] = {((float)ox - sc.f[0]) * e.dx, ((float)oy - sc.f[1]) * e.dx, ((float)oz - sc.f[2]) * e.dx};
           const float* g = genv + (ax + sa.y[oy] + sa.z[oz]);
           const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+          const float W = wxy * sc.w[2][oz], Wd = wxy * wdz[oz];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            vn[a] = fmaf(W, vi[a], vn[a]);
-            const float wv = W * vi[a];
-            Cn.m[a][0] = fmaf(wv, d[0], Cn.m[a][0]);
-            Cn.m[a][1] = fmaf(wv, d[1], Cn.m[a][1]);
-            Cn.m[a][2] = fmaf(wv, d[2], Cn.m[a][2]);
+            col[a] = fmaf(W, vi[a], col[a]);
+            colz[a] = fmaf(Wd, vi[a], colz[a]);
           }
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          vn[a] += col[a];
+          Cn.m[a][0] = fmaf(col[a], d0, Cn.m[a][0]);
+          Cn.m[a][1] = fmaf(col[a], d1, Cn.m[a][1]);
+          Cn.m[a][2] += colz[a];
+        }
+      }
     }
   }
   Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
@@ -1365,27 +1383,30 @@ MD void adj_pair_item(int item_idx, const float* __restrict__ st_prev, const flo
           float wx, wy, dwx, dwy;
           spline_piece(ox, sc.f[0], wx, dwx);
           spline_piece(oy, sc.f[1], wy, dwy);
-          dwx *= e.fn;
-          dwy *= e.fn;
+          const float wxy = wx * wy, gxw = e.fn * dwx * wy, gyw = e.fn * wx * dwy;
           const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+          // column invariant m_p v + A d at d_z = 0; column sums of W Pbar and W Pbar d_z
+          float uc[3], cP[3] = {0.f, 0.f, 0.f}, cPz[3] = {0.f, 0.f, 0.f};
+          for (int a = 0; a < 3; ++a) uc[a] = fmaf(A.m[a][0], d0, fmaf(A.m[a][1], d1, e.mp * v[a]));
 #pragma unroll
           for (int oz = 0; oz < 3; ++oz) {
-            const float wz = sc.w[2][oz];
-            const float W = wx * wy * wz;
-            const float gW[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * e.fn * sc.dw[2][oz]};
-            const float d[3] = {d0, d1, ((float)oz - sc.f[2]) * e.dx};
+            const float wz = sc.w[2][oz], dz = ((float)oz - sc.f[2]) * e.dx;
+            const float W = wxy * wz, Wd = W * dz;
+            const float gW[3] = {gxw * wz, gyw * wz, wxy * e.fn * sc.dw[2][oz]};
             float gw = e.mp * mb[oz];
-            for (int a = 0; a < 3; ++a)
-              gw += Pb[oz][a] * (e.mp * v[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]);
+            for (int a = 0; a < 3; ++a) gw = fmaf(Pb[oz][a], fmaf(A.m[a][2], dz, uc[a]), gw);
             sm = fmaf(W, mb[oz], sm);
             for (int a = 0; a < 3; ++a) {
-              const float wp = W * Pb[oz][a];
-              sP[a] += wp;
-              Ab.m[a][0] = fmaf(wp, d[0], Ab.m[a][0]);
-              Ab.m[a][1] = fmaf(wp, d[1], Ab.m[a][1]);
-              Ab.m[a][2] = fmaf(wp, d[2], Ab.m[a][2]);
+              cP[a] = fmaf(W, Pb[oz][a], cP[a]);
+              cPz[a] = fmaf(Wd, Pb[oz][a], cPz[a]);
               xb[a] = fmaf(gW[a], gw, xb[a]);
             }
+          }
+          for (int a = 0; a < 3; ++a) {
+            sP[a] += cP[a];
+            Ab.m[a][0] = fmaf(cP[a], d0, Ab.m[a][0]);
+            Ab.m[a][1] = fmaf(cP[a], d1, Ab.m[a][1]);
+            Ab.m[a][2] += cPz[a];
           }
         }
       // the stencil sum of -W A^T Pbar is -A^T sP

@@ -52,6 +52,7 @@ struct Box {
 // whole-wavefront min / max (DPP reductions of the device library)
 extern "C" __device__ __attribute__((const)) int __ockl_wfred_min_i32(int);
 extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
+extern "C" __device__ __attribute__((const)) float __ockl_wfred_add_f32(float);
 
 // every thread must call it (uniform control flow); lp = this thread's particle index in the item
 template <int BOXN>
@@ -84,6 +85,14 @@ MD Box block_box(const EnvDev& e, const int b[3], bool valid, int lp, int count,
   // handful of addresses would serialize 256 x 6 updates)
   for (int k = 0; k < nr; ++k) {
     const bool mine = r == k;
+    if (__ballot(mine) == 0ull) {   // no particle of run k in this wave (uniform): identities only
+      if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+          bs.wlo[wave][k][a] = 0x3fffffff;
+          bs.whi[wave][k][a] = -0x3fffffff;
+        }
+      continue;
+    }
     for (int a = 0; a < 3; ++a) {
       const int mn = __ockl_wfred_min_i32(mine ? b[a] : 0x3fffffff);
       const int mx = __ockl_wfred_max_i32(mine ? b[a] + 2 : -0x3fffffff);
@@ -250,15 +259,17 @@ MD void stencil_offsets(const Stencil& sc, const EnvDev& e, int ox, int oy, int 
   d[2] = ((float)oz - sc.f[2]) * e.dx;
 }
 
+// per-env parameter cotangents of a block: each wave sums its 64 FP32 terms
+// with a DPP reduction (a parameter none of its lanes touched costs one
+// ballot), the block and the grid accumulate in FP64
 MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
   __shared__ double red[PB_COUNT][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < PB_COUNT; ++k) {
-    double v = (double)pb[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[k][wave] = v;
+    float v = 0.f;
+    if (__ballot(pb[k] != 0.f) != 0ull) v = __ockl_wfred_add_f32(pb[k]);
+    if (lane == 0) red[k][wave] = (double)v;
   }
   __syncthreads();
   if (threadIdx.x < PB_COUNT) {

@@ -1247,9 +1247,11 @@ MD void g2p_adjoint_seg_item(int item_idx, const float* __restrict__ st, const f
   block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
 }
 
-// one block per work item, or (PERSIST) a grid that strides over the items
+// one block per work item, or (PERSIST) a grid that strides over the items;
+// five waves per SIMD for the materials whose VJP is light (2-3 registers
+// spill), the von Mises and generic variants keep their own allocation
 template <bool PERSIST, int BOXN, int MAT>
-__global__ void __launch_bounds__(256) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ st_next,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BOXN > 512 || MAT < 0 || MAT == MAT_VONMISES ? 3 : 5, 8))) k_g2p_adjoint_seg(const float* __restrict__ st, const float* __restrict__ st_next,
     const float* __restrict__ cot,
                                                          float* __restrict__ part, int64_t N,
                                                          const EnvDev* __restrict__ envs,

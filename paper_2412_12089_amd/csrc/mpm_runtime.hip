@@ -1271,7 +1271,9 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
         rc = rel_err(g, ref, 6 * b->N, err);   // x and v of the end state
       }
       if (rc) break;
-      if (err <= (c.bwd ? 1e-4 : 1e-5) && ms < best_ms) {
+      // a later candidate must win by more than 1%: a tie keeps the earlier (default)
+      // choice, so timing noise does not flip between equivalent variants
+      if (err <= (c.bwd ? 1e-4 : 1e-5) && ms < best_ms * 0.99) {
         best_ms = ms;
         best = trial;
       }

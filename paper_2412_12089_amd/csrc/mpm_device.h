@@ -106,14 +106,30 @@ MD M3 m3_cof(const M3& a) {
   c.m[2][2] = a.m[0][0] * a.m[1][1] - a.m[0][1] * a.m[1][0];
   return c;
 }
-// U diag(d) U^T
+// U diag(d) U^T (symmetric: the upper triangle is computed and mirrored)
 MD M3 m3_spectral(const M3& U, const float d[3]) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float ud[3] = {U.m[i][0] * d[0], U.m[i][1] * d[1], U.m[i][2] * d[2]};
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      r.m[i][j] = ud[0] * U.m[j][0] + ud[1] * U.m[j][1] + ud[2] * U.m[j][2];
+      r.m[j][i] = r.m[i][j];
+    }
+  }
+  return r;
+}
+// H + H^T + H H^T = F F^T - I (symmetric: upper triangle, mirrored)
+MD M3 m3_left_strain(const M3& H) {
   M3 r;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      r.m[i][j] = U.m[i][0] * d[0] * U.m[j][0] + U.m[i][1] * d[1] * U.m[j][1] + U.m[i][2] * d[2] * U.m[j][2];
+    for (int j = i; j < 3; ++j) {
+      r.m[i][j] = H.m[i][j] + H.m[j][i] + H.m[i][0] * H.m[j][0] + H.m[i][1] * H.m[j][1] + H.m[i][2] * H.m[j][2];
+      r.m[j][i] = r.m[i][j];
+    }
   return r;
 }
 // U^T A U
@@ -137,7 +153,7 @@ MD void jacobi_rotate(M3& A, M3& V) {
   const float at = fabsf(theta);
   const float tm = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.f)));
   const float t = fabsf(apq) > 1e-30f ? copysignf(tm, theta) : 0.f;
-  const float c = rsqrtf(fmaf(t, t, 1.f));
+  const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));   // argument >= 1: no denormal handling needed
   const float s = t * c;
   const float tau = s * __builtin_amdgcn_rcpf(1.f + c);
   A.m[p][p] -= t * apq;
@@ -297,7 +313,7 @@ MD StressPrep stress_prep(const EnvDev& e, const M3& H, int mat) {
   p.Jm1 = det_minus_one(H);
   p.J = 1.f + p.Jm1;
   if (mat == MAT_NEOHOOKEAN || mat == MAT_COROTATED || mat == MAT_VONMISES)
-    p.B = m3_add(m3_add(H, m3_transpose(H)), m3_mul_abt(H, H));
+    p.B = m3_left_strain(H);
   if (mat == MAT_COROTATED || mat == MAT_VONMISES) eig_sym(p.B, p.l, p.U);
   return p;
 }
@@ -309,7 +325,7 @@ MD StressPrep stress_prep_with_eig(const M3& H, const M3& U, const float l[3], i
   p.Jm1 = det_minus_one(H);
   p.J = 1.f + p.Jm1;
   if (mat == MAT_NEOHOOKEAN || mat == MAT_COROTATED || mat == MAT_VONMISES)
-    p.B = m3_add(m3_add(H, m3_transpose(H)), m3_mul_abt(H, H));
+    p.B = m3_left_strain(H);
   p.U = U;
   for (int i = 0; i < 3; ++i) p.l[i] = l[i];
   return p;

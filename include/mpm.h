@@ -251,10 +251,12 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value);
 
 /* Autotuner (batched mode). Runs ckpt_every substeps from the current state
  * with every kernel variant (MPM_OPT_P2G, _G2P, _G2P_ADJ, _P2G_ADJ, _MIN_RUN,
- * _GRID_CAP, _MAX_RUN), one kernel class at a time. A candidate is kept only if its end
+ * _BOX, _SPECIALIZE, _FUSE, _FUSE_ADJ, _XCD, _GRID_CAP, _MAX_RUN), one option
+ * at a time. A candidate is kept only if its end
  * state (x, v: relative error <= 1e-5) and its initial-state cotangent for an
  * all-ones loss cotangent (<= 1e-4) agree with the one-thread-per-particle
- * kernels; the fastest kept candidate wins. Stops trying further candidates
+ * kernels; the fastest kept candidate wins, a later one only if it is more
+ * than 1% faster than the choice so far. Stops trying further candidates
  * after about budget_ms milliseconds. Restores the particle state and clock,
  * drops any record, synchronizes the stream; the choice is cached per batch
  * shape for the process. Plain mode: no-op. */

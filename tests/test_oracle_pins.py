@@ -32,6 +32,58 @@ def params(E=5e3, nu=0.3, rho=1e3, Vp=1e-6, sy=50.0, K=1e4, gamma=7.0):
     return torch.tensor([E, nu, rho, Vp, sy, K, gamma], dtype=DT)
 
 
+# ---------------------------------------------------------------- Lame parameters
+def test_lame_textbook_values():
+    # E = 1, nu = 1/4 gives mu = lam = 2/5; nu = 0 gives lam = 0 and mu = E/2
+    mu, lam = O.lame(1.0, 0.25)
+    assert abs(mu - 0.4) < 1e-15 and abs(lam - 0.4) < 1e-15
+    mu, lam = O.lame(7.0, 0.0)
+    assert lam == 0.0 and abs(mu - 3.5) < 1e-15
+
+
+@pytest.mark.parametrize("E,nu", [(5e3, 0.3), (1e4, 0.25), (4e3, 0.2), (2.0, -0.4), (1.0, 0.49)])
+def test_lame_reproduces_the_elastic_moduli(E, nu):
+    # the defining experiments of E and nu on the isotropic linear law s = lam tr(e) I + 2 mu e:
+    # a uniaxial strain state e = diag(1, -nu, -nu) carries stress E along x and none across;
+    # a uniform dilation carries 3 K per unit strain, K = E / (3 (1 - 2 nu)); pure shear carries 2 G
+    mu, lam = O.lame(E, nu)
+    lin = lambda e: lam * np.trace(e) * np.eye(3) + 2.0 * mu * e
+    s = lin(np.diag([1.0, -nu, -nu]))
+    np.testing.assert_allclose(np.diag(s), [E, 0.0, 0.0], atol=1e-12 * E)
+    np.testing.assert_allclose(lin(np.eye(3)), 3.0 * E / (3.0 * (1.0 - 2.0 * nu)) * np.eye(3), rtol=1e-13)
+    shear = np.zeros((3, 3)); shear[0, 1] = shear[1, 0] = 1.0
+    np.testing.assert_allclose(lin(shear)[0, 1], 2.0 * E / (2.0 * (1.0 + nu)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("mat", [O.COROTATED, O.VONMISES])
+def test_small_strain_stress_is_the_linear_law(mat):
+    # corotated and Hencky elasticity linearise at F = I to the isotropic law with the Lame pair of
+    # (E, nu): a uniaxial stretch with lateral contraction nu carries tau_xx = E eps, no lateral stress
+    E, nu, eps = 5e3, 0.3, 1e-7
+    mu, lam = O.lame(torch.tensor(E, dtype=DT), torch.tensor(nu, dtype=DT))
+    F = torch.diag(torch.tensor([1.0 + eps, 1.0 - nu * eps, 1.0 - nu * eps], dtype=DT))[None]
+    tau = O.stress(mat, F, mu, lam, torch.tensor(1e4, dtype=DT), torch.tensor(7.0, dtype=DT))[0].numpy()
+    np.testing.assert_allclose(tau[0, 0] / eps, E, rtol=1e-5)
+    assert abs(tau[1, 1]) < 1e-5 * E * eps and abs(tau[2, 2]) < 1e-5 * E * eps
+    assert np.abs(tau - np.diag(np.diag(tau))).max() < 1e-9 * E * eps
+
+
+def test_stable_neohookean_small_strain_closed_form():
+    # the stable neo-Hookean energy written in the Lame pair (mu, lam) linearises at F = I to
+    # 2 (3 mu / 4) e + (lam - 5 mu / 8) tr(e) I: derivative of mu (1 - 1/(I_C + 1)) F at I_C = 3 is
+    # (3 mu / 4) e + (mu / 8) tr(e) I, and of lam (J - alpha) J F^-T with alpha = 1 + 3 mu / (4 lam)
+    # is lam tr(e) I - (3 mu / 4)(tr(e) I - e^T); summed for a symmetric strain e
+    rng = np.random.default_rng(3)
+    mu, lam = 1234.0, 2345.0
+    e = 1e-7 * rng.standard_normal((3, 3))
+    e = 0.5 * (e + e.T)
+    F = torch.from_numpy(np.eye(3) + e)[None]
+    tau = O.stress(O.NEOHOOKEAN, F, torch.tensor(mu, dtype=DT), torch.tensor(lam, dtype=DT),
+                   torch.tensor(0.0, dtype=DT), torch.tensor(1.0, dtype=DT))[0].numpy()
+    lin = 2.0 * (0.75 * mu) * e + (lam - 0.625 * mu) * np.trace(e) * np.eye(3)
+    np.testing.assert_allclose(tau, lin, atol=1e-5 * np.abs(lin).max())
+
+
 # ---------------------------------------------------------------- weights
 def test_bspline_closed_form_values():
     # quadratic B-spline at f = 1 (particle on a cell centre) and f = 1/2 (on a node)
@@ -341,6 +393,39 @@ def test_contact_projection_hand_values():
     np.testing.assert_allclose(out[i_out].numpy(), [(1 - s) * -1.0, (1 - s) * 0.2, 0.0], atol=1e-14)
 
 
+def test_box_sdf_face_edge_corner_hand_values():
+    # box centred at c with half extents (0.2, 0.1, 0.15); points placed by hand outside a face,
+    # an edge and a corner, and inside near a face, with the distance and outward normal worked out
+    c = torch.tensor([0.5, 0.5, 0.5], dtype=DT)
+    h = torch.tensor([0.2, 0.1, 0.15], dtype=DT)
+    cases = [
+        # (offset from c, distance, normal)
+        ((0.0, 0.0, -0.2), 0.05, (0.0, 0.0, -1.0)),                    # below the -z face
+        ((0.23, 0.14, 0.0), 0.05, (0.6, 0.8, 0.0)),                    # outside the (+x, +y) edge: 3-4-5
+        ((-0.23, 0.0, 0.19), 0.05, (-0.6, 0.0, 0.8)),                  # outside the (-x, +z) edge
+        ((0.22, -0.13, 0.21), 0.07, (2 / 7, -3 / 7, 6 / 7)),           # outside a corner: 2-3-6-7
+        ((0.19, 0.08, 0.0), -0.01, (1.0, 0.0, 0.0)),                   # inside, nearest the +x face
+        ((0.05, -0.09, 0.1), -0.01, (0.0, -1.0, 0.0)),                 # inside, nearest the -y face
+    ]
+    p = c + torch.tensor([o for o, _, _ in cases], dtype=DT)
+    d, nrm = O.box_sdf(p, c, h)
+    np.testing.assert_allclose(d.numpy(), [dd for _, dd, _ in cases], atol=1e-14)
+    np.testing.assert_allclose(nrm.numpy(), [nn for _, _, nn in cases], atol=1e-13)
+    # exact ties inside (dyadic numbers, so |rel| - half ties exactly): the first tied axis wins
+    h2 = torch.tensor([0.25, 0.125, 0.375], dtype=DT)
+    ties = [((-0.1875, 0.0625, -0.3125), (-1.0, 0.0, 0.0)),    # x, y and z tie at -1/16
+            ((0.0, -0.0625, 0.3125), (0.0, -1.0, 0.0))]       # y and z tie at -1/16
+    p2 = c + torch.tensor([o for o, _ in ties], dtype=DT)
+    d2, n2 = O.box_sdf(p2, c, h2)
+    np.testing.assert_allclose(d2.numpy(), [-0.0625, -0.0625], atol=0)
+    np.testing.assert_allclose(n2.numpy(), [nn for _, nn in ties], atol=0)
+    # the normal is the gradient of the distance wherever the distance is differentiable
+    pg = p[:6].clone().requires_grad_(True)
+    dg, _ = O.box_sdf(pg, c, h)
+    (g,) = torch.autograd.grad(dg.sum(), pg)
+    np.testing.assert_allclose(g.numpy(), nrm[:6].numpy(), atol=1e-13)
+
+
 # ---------------------------------------------------------------- gradients
 def tiny(mat, collider=False, seed=20, N=48):
     rng = np.random.default_rng(seed)
@@ -417,6 +502,34 @@ def test_reverse_mode_matches_central_differences(mat, collider):
         fd = (_loss(env, pp, st, S, cot) - _loss(env, pm, st, S, cot)) / (2 * hk)
         an = gp[k].item()
         assert abs(fd - an) <= 1e-5 * max(abs(an), abs(fd)) + 1e-9, (k, fd, an)
+
+
+@pytest.mark.parametrize("mat,collider", GRAD_CASES)
+def test_density_and_volume_cotangents(mat, collider):
+    # with one particle mass m_p = rho Vp per environment, the grid velocity P_i / m_i depends on the
+    # particle volume only through tau / rho (Vp cancels) and the yield offset through sigma_y / E.
+    # So the loss is unchanged when (rho, E, sigma_y, K) are scaled together, and does not depend on
+    # Vp at all: rho dL/drho = -(E dL/dE + sigma_y dL/dsigma_y + K dL/dK) and dL/dVp = 0. Central
+    # differences in rho and Vp check the same two numbers directly.
+    env, prm, st = tiny(mat, collider)
+    S = 3
+    rng = np.random.default_rng(32)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    _, gp = O.rollout_vjp(env, prm, st, S, cot)
+    g = gp.numpy()
+    p = prm.numpy()
+    euler = p[0] * g[0] + p[4] * g[4] + p[5] * g[5]
+    scale = abs(p[0] * g[0]) + abs(p[4] * g[4]) + abs(p[5] * g[5])
+    assert scale > 0
+    assert abs(p[2] * g[2] + euler) <= 1e-9 * scale, (p[2] * g[2], euler)
+    assert abs(p[3] * g[3]) <= 1e-9 * scale
+    for k in (2, 3):
+        hk = 1e-6 * prm[k].item()
+        pp, pm = prm.clone(), prm.clone()
+        pp[k] += hk
+        pm[k] -= hk
+        fd = (_loss(env, pp, st, S, cot) - _loss(env, pm, st, S, cot)) / (2 * hk)
+        assert abs(fd * p[k] - g[k] * p[k]) <= 1e-6 * scale, (k, fd, g[k])
 
 
 def test_von_mises_tiny_scene_is_plastic():

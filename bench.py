@@ -7,12 +7,16 @@ cotangent of L = sum_p x_p . w_p to the initial state and per-env parameters
 (segments recomputed from checkpoints). Inputs are resident in HBM before the
 timed region.
 
-Default workload: 32 identical environments on 48^3 grids, 20,000 corotated
-particles each (E = 1e4, nu = 0.25), 80 substeps at dt = 5e-5, checkpoint
-interval 10. Metric: fwd+bwd particle-substeps/s of the batched mode; the
-per-environment mode, forward-only rate and p50/p99 per-step latency are
-reported beside it, with a roofline entry for the dominant kernel and the FP64
-oracle timed on the host as the CPU baseline.
+Headline workload: the large fluid scene -- 16 environments on 96^3 grids,
+200,000 weakly compressible (Tait) particles each in a dam-break column held
+by a kinematic gate withdrawn at 0.2 m/s, 100 substeps at dt = 2e-5,
+checkpoint interval 20. Metric: fwd+bwd particle-substeps/s of the batched
+mode. Reported beside it: the per-environment mode, the forward-only rate,
+p50/p99 per-step latency, the batched corotated (32 x 20,000) and uneven mixed
+(64 envs, 5k-60k) workloads, the continuous-batching server on a Poisson
+stream (p50/p99 latency and aggregate particle-substeps/s), a roofline entry
+for the dominant kernel, and the FP64 oracle timed on the host as the CPU
+baseline.
 """
 from __future__ import annotations
 
@@ -30,30 +34,36 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes per particle per launch of each kernel class (FP32 state:
-# x 12, v 12, C 36, F 36 = 96 B) -- grid-node traffic is counted separately
+# Algorithmic bytes each kernel must move, per particle and per touched grid
+# node of one launch. FP32 state: x 12, v 12, C 36, F 36 = 96 B per particle.
+# A forward substep reads and writes the state once (192 B per particle) and
+# moves 28 B per touched node (m, P 16 B; v 12 B); the adjoint of a substep
+# reads the state and the incoming cotangent and writes the outgoing one
+# (288 B per particle) and moves twice the forward's grid bytes (56 B per node).
+# A kernel that carries out a whole substep (the fused ones) is charged those
+# figures; a kernel that carries out part of one is charged what that part
+# reads and writes.
 ALG_BYTES_PER_PARTICLE = {
-    "p2g": 96,          # read x, v, C, F
-    "g2p": 48 + 96,     # read x, F; write x, v, C, F
-    "g2p_adj": 48 + 96 + 48,   # read x, F, the state cotangent; write the partial x/F cotangent
-    "p2g_adj": 96 + 48 + 96,   # read state and partial cotangent; write the state cotangent
-    "sort": 96 + 96 + 4 * 8,   # permute read + write, keys/values
-    "g2p2g": 48 + 96,   # G2P's reads and writes; the next P2G takes the new state from registers
-    # P2G adjoint k: read state k and the partial cotangent; G2P adjoint k - 1: read x, F of
-    # state k - 1 (C of state k again, counted once) and write the partial cotangent
-    "adj_pair": 96 + 48 + 48 + 48,
+    "p2g": 96,                # read x, v, C, F
+    "g2p": 48 + 96,           # read x, F; write x, v, C, F
+    "g2p_adj": 48 + 96 + 48,  # read x, F, the state cotangent; write the partial (x, F) cotangent
+    "p2g_adj": 96 + 48 + 96,  # read the state and the partial cotangent; write the state cotangent
+    "sort": 96 + 96 + 4 * 8,  # permute read + write, keys/values
+    "g2p2g": 192,             # one forward substep (G2P of k + P2G of k + 1)
+    "adj_pair": 288,          # one adjoint substep (P2G adjoint of k + G2P adjoint of k - 1)
 }
-# algorithmic bytes per touched grid node per launch
-ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16, "grid_adj": 16 + 12 + 16,
-                      "g2p2g": 12 + 16, "adj_pair": 16 + 12 + 12}
+ALG_BYTES_PER_NODE = {"p2g": 16, "g2p": 12, "grid": 16 + 12, "g2p_adj": 12 + 12, "p2g_adj": 16,
+                      "grid_adj": 16 + 12 + 16, "g2p2g": 28, "adj_pair": 56}
 
-
-# kernel symbol of each class for the library's default batched variants
-KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg"},
+# kernel symbol of each class for the library's batched variants
+KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg", 3: "k_p2g_pull"},
                  "g2p": {0: "k_g2p_direct", 1: "k_g2p_lds"},
-                 "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg"},
+                 "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg",
+                             3: "k_g2p_adjoint_pull"},
                  "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"},
                  "g2p2g": {1: "k_g2p2g"}, "adj_pair": {1: "k_adj_pair"}}
+OPTION_NAMES = ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE",
+                "FUSE_ADJ", "XCD")
 
 
 def kernel_source_sha() -> str:
@@ -76,8 +86,6 @@ def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
         return f"{symbol}<{384 if tuned['BOX'] else 1024}, {mat}>"
     n_items = sum(-(-e.n_particles // 256) for e in envs)
     persist = "true" if 0 < tuned["GRID_CAP"] < n_items else "false"
-    mats = sorted({e.material for e in envs})
-    mat = mats[0] if tuned["SPECIALIZE"] and len(mats) == 1 else -1
     return f"{symbol}<{persist}, {384 if tuned['BOX'] else 1024}, {mat}>"
 
 
@@ -99,25 +107,28 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched_corot",
+    ap.add_argument("--workload", default="dam_break",
                     choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh", "handflip_shape"])
+    ap.add_argument("--extra", default="batched_corot,uneven_mixed",
+                    help="further workloads timed (autotuned, batched, fwd+bwd) and reported beside the headline")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-substeps", type=int, default=80, help="substeps per env of the oracle sample")
-    ap.add_argument("--cpu-envs", type=int, default=2, help="envs of the oracle sample (about 10-20 s in all)")
+    ap.add_argument("--cpu-substeps", type=int, default=5, help="substeps of each oracle run (fwd+bwd)")
+    ap.add_argument("--cpu-envs", type=int, default=1, help="envs of the oracle sample")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs; the median rate is reported")
     ap.add_argument("--profile", action="store_true", help="only run the batched steps (for rocprofv3)")
     ap.add_argument("--no-graphs", action="store_true", help="launch segments without hipGraph replay")
     ap.add_argument("--tune-ms", type=int, default=4000, help="autotuner budget (0: library defaults)")
-    ap.add_argument("--set", default="", help="fixed library options instead of autotuning, e.g. P2G=2,G2P=0,BOX=1 "
+    ap.add_argument("--set", default="", help="fixed library options instead of autotuning, e.g. P2G=3,G2P=0,BOX=1 "
                     "(a profiling run uses the choice an earlier timed run printed under 'autotuned')")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=48)
     return ap.parse_args()
 
 
-def touched_nodes(envs, wall_pad=2):
+def touched_nodes(envs):
     """Grid nodes inside the stencils of the initial particles (per env, summed)."""
     total = 0
     for e in envs:
@@ -132,6 +143,7 @@ def touched_nodes(envs, wall_pad=2):
 
 
 def run_steps(batch, x0, w, S, steps, warmup, record=True, backward=True):
+    """Per-step durations (ms) from HIP events recorded on the library's stream."""
     import torch
     stream = batch.stream
     times = []
@@ -150,46 +162,94 @@ def run_steps(batch, x0, w, S, steps, warmup, record=True, backward=True):
             times.append((ev0, ev1))
     torch.cuda.synchronize()
     batch.sync()
-    ms = [a.elapsed_time(b) for a, b in times]
-    return ms
+    return [a.elapsed_time(b) for a, b in times]
+
+
+def inputs(wl, dev):
+    import torch
+    cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in wl.envs], axis=0)).to(dev)
+    x0 = (cat("x"), cat("v"), cat("C"), cat("F"))
+    w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
+    return x0, w
+
+
+def tuned_batch(wl, dev, args, fixed=None):
+    """A batched-mode batch with the autotuner's (or the fixed) options."""
+    from paper_2412_12089_amd import _capi
+    from paper_2412_12089_amd.batch import Batch
+    b = Batch(wl.envs, max_substeps=wl.substeps, ckpt_every=wl.ckpt_every, mode="batched", device=dev)
+    if args.no_graphs:
+        b.set_option(_capi.OPT_GRAPHS, 0)
+    for k, v in (fixed or {}).items():
+        b.set_option(getattr(_capi, "OPT_" + k.upper()), int(v))
+    tune_s = None
+    if args.tune_ms > 0 and not args.profile and not fixed:
+        x0, _ = inputs(wl, dev)
+        b.set_particles(*x0)
+        t0 = time.perf_counter()
+        b.autotune(args.tune_ms)
+        tune_s = time.perf_counter() - t0
+    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in OPTION_NAMES}
+    return b, tuned, tune_s
+
+
+def extra_workload(name, dev, args):
+    """Batched fwd+bwd rate of another workload (autotuned), in the same units."""
+    from paper_2412_12089_amd import scenes
+    wl = scenes.WORKLOADS[name]()
+    N = sum(e.n_particles for e in wl.envs)
+    b, tuned, _ = tuned_batch(wl, dev, args)
+    x0, w = inputs(wl, dev)
+    ms = run_steps(b, x0, w, wl.substeps, max(3, args.steps), 1)
+    b.close()
+    step = float(np.median(ms))
+    return {"value": N * wl.substeps / (step * 1e-3), "unit": "particle-substeps/s", "ms_per_step": step,
+            "envs": len(wl.envs), "particles": N, "substeps": wl.substeps, "ckpt_every": wl.ckpt_every,
+            "autotuned": tuned}
 
 
 def serving_leg(seconds, rate, slots, device):
-    """Continuous batching of a seeded Poisson stream of single-env rollout requests."""
+    """Continuous batching (the library's server) of a seeded Poisson stream of single-env rollout requests."""
     import torch
     from paper_2412_12089_amd import scenes
-    from paper_2412_12089_amd.server import GPUExecutor, Server
+    from paper_2412_12089_amd.server import Server
     reqs = scenes.serving_stream(seed=5, rate=rate, duration=seconds)
-    ex = GPUExecutor(slots, n_cap=64, N_cap=100_000, chunk=10, device=device)
     free = torch.cuda.mem_get_info(device)[0]
-    srv = Server(ex, budget_bytes=int(0.25 * free), chunk=10, keep_results=False)
+    budget = int(0.25 * free)
+    srv = Server(slots, n_cap=64, N_cap=100_000, chunk=10, budget_bytes=budget, device=device, keep_results=False)
     srv.run(reqs, realtime=True, timeout_s=max(120.0, 20 * seconds))
     st = srv.stats()
-    ex.close()
+    srv.close()
     fwd = sum(r.env.n_particles * r.substeps for r in reqs)
-    st.update({"rate_per_s": rate, "stream_s": seconds, "slots": slots, "budget_bytes": int(0.25 * free),
+    st.update({"rate_per_s": rate, "stream_s": seconds, "slots": slots, "budget_bytes": budget,
                "backward_fraction": sum(r.backward for r in reqs) / max(1, len(reqs)),
-               "fwd_particle_substeps_demanded_per_s": fwd / seconds})
+               "particle_substeps_demanded_per_s": fwd / seconds})
     return st
 
 
-def cpu_baseline(wl, substeps, n_envs):
-    """The FP64 oracle on a bounded sample: the first n_envs envs, `substeps` substeps each, forward + reverse."""
+def cpu_baseline(wl, substeps, n_envs, runs):
+    """The FP64 oracle on a bounded sample: the first n_envs envs, `substeps`
+    substeps each, forward + reverse; the median rate over `runs` runs."""
     import torch
     from oracle import mpm_oracle as O
     threads = torch.get_num_threads()
-    done, t_all = 0, 0.0
     specs = wl.envs[:max(1, n_envs)]
-    for i, spec in enumerate(specs):
-        env, prm, st = O.env_from_spec(spec)
-        cot = O.linear_loss_cotangent(wl.loss_weights[i], spec.n_particles)
-        t0 = time.perf_counter()
-        O.rollout_vjp(env, prm, st, substeps, cot)   # forward (stores states) + per-substep reverse
-        t_all += time.perf_counter() - t0
-        done += spec.n_particles * substeps
-    return {"value": done / t_all, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(specs)} env(s) of {wl.name} ({done // substeps} particles), {substeps} substeps "
-                      f"fwd+bwd each, {t_all:.1f} s wall"}
+    rates, walls = [], []
+    for _ in range(max(1, runs)):
+        done, t_all = 0, 0.0
+        for i, spec in enumerate(specs):
+            env, prm, st = O.env_from_spec(spec)
+            cot = O.linear_loss_cotangent(wl.loss_weights[i], spec.n_particles)
+            t0 = time.perf_counter()
+            O.rollout_vjp(env, prm, st, substeps, cot)   # forward (stores states) + per-substep reverse
+            t_all += time.perf_counter() - t0
+            done += spec.n_particles * substeps
+        rates.append(done / t_all)
+        walls.append(t_all)
+    return {"value": float(np.median(rates)), "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(specs)} env(s) of {wl.name} ({sum(s.n_particles for s in specs)} particles), "
+                      f"{substeps} substeps fwd+bwd, median of {len(rates)} runs "
+                      f"({', '.join(f'{t:.1f}' for t in walls)} s wall)"}
 
 
 def main():
@@ -199,7 +259,7 @@ def main():
               "independent single-GPU runs over disjoint env sets; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2412_12089_amd import scenes
+    from paper_2412_12089_amd import _capi, scenes
     from paper_2412_12089_amd.batch import Batch
 
     wl = scenes.WORKLOADS[args.workload]()
@@ -207,24 +267,9 @@ def main():
     envs = wl.envs
     N = sum(e.n_particles for e in envs)
     dev = torch.device("cuda:0")
-    cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in envs], axis=0)).to(dev)
-    x0 = (cat("x"), cat("v"), cat("C"), cat("F"))
-    w = torch.from_numpy(np.concatenate(wl.loss_weights, axis=0)).to(dev)
-
-    b = Batch(envs, max_substeps=S, ckpt_every=K, mode="batched", device=dev)
-    from paper_2412_12089_amd import _capi
-    if args.no_graphs:
-        b.set_option(_capi.OPT_GRAPHS, 0)
-    tune_s = None
+    x0, w = inputs(wl, dev)
     fixed = dict(kv.split("=") for kv in args.set.split(",") if kv)
-    for k, v in fixed.items():
-        b.set_option(getattr(_capi, "OPT_" + k.upper()), int(v))
-    if args.tune_ms > 0 and not args.profile and not fixed:
-        b.set_particles(*x0)
-        t0 = time.perf_counter()
-        b.autotune(args.tune_ms)
-        tune_s = time.perf_counter() - t0
-    tuned = {k: b.get_option(getattr(_capi, "OPT_" + k)) for k in ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE", "FUSE_ADJ", "XCD")}
+    b, tuned, tune_s = tuned_batch(wl, dev, args, fixed)
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
@@ -237,7 +282,6 @@ def main():
         return
     step_ms = float(np.mean(ms))
     value = N * S / (step_ms * 1e-3)
-    # forward-only rate
     fwd_ms = float(np.mean(run_steps(b, x0, w, S, max(1, args.steps // 2), 1, record=False, backward=False)))
     # roofline pass: per-kernel HIP events on the library's stream
     b.set_timing(True)
@@ -266,6 +310,9 @@ def main():
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     symbol = kernel_instance(KERNEL_SYMBOL.get(dom, {}).get(variant.get(dom), dom), variant.get(dom), tuned, envs)
     traffic = measured_traffic(wl.name, symbol)
+    # whole step against the method's bytes: 672 B per particle-substep fwd+bwd, 96/K B of
+    # checkpoints, 28 + 56 B per touched node and substep
+    step_bytes = N * S * (672 + 96.0 / K) + nodes * S * (28 + 56)
 
     plain = None
     if args.plain_steps > 0:
@@ -274,10 +321,14 @@ def main():
         bp.close()
         plain = N * S / (float(np.mean(pms)) * 1e-3)
 
+    extra = {}
+    for name in [n for n in args.extra.split(",") if n and n != wl.name]:
+        extra[name] = extra_workload(name, dev, args)
+
     serving = None
     if args.serve_seconds > 0:
         serving = serving_leg(args.serve_seconds, args.serve_rate, args.serve_slots, dev)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps, args.cpu_envs)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps, args.cpu_envs, args.cpu_runs)
     out = {
         "metric": "fwd+bwd particle-substeps/s (batched)",
         "value": value,
@@ -301,11 +352,14 @@ def main():
         "p50_ms": float(np.percentile(ms, 50)),
         "p99_ms": float(np.percentile(ms, 99)),
         "hbm_resident_bytes": mem,
+        "step_alg_bytes": step_bytes,
+        "step_alg_gbs": step_bytes / (step_ms * 1e-3) / 1e9,
         "kernel_ms": {k: v[0] for k, v in kt.items()},
         "kernel_launches_per_step": {k: v[1] for k, v in kt.items()},
         "roofline": {"bound": "hbm", "kernel": symbol, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes, "kernel_ms": dom_ms},
+        "workloads": extra,
         "serving": serving,
         "cpu_baseline": cpu,
     }

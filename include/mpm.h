@@ -111,13 +111,15 @@ int mpm_batch_destroy(mpm_batch* b);
 /* Copies particle state in (device pointers, AoS layout above). env >= 0 sets
  * that environment (n must equal its n_particles); env = -1 sets every
  * environment from arrays concatenated in env order (n = total of the
- * current counts). The batch clock restarts at t = 0 and any recorded tape is
- * dropped. */
+ * current counts). The clock of each environment set (the substep count that
+ * places its collider in time) restarts at t = 0; other environments keep
+ * theirs. Any recorded tape is dropped. */
 int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v, const float* C, const float* F,
                       int64_t n);
 
-/* Copies the current particle state out in the caller's original particle
- * order (device pointers; any of the four may be NULL to skip it). env = -1
+/* Copies the current particle state (x, v, C, F of Appendix D.3's particles)
+ * out in the caller's original particle order (device pointers; any of the
+ * four may be NULL to skip it). env = -1
  * writes all environments concatenated. The library holds F as F - I (small
  * strains keep FP32 precision relative to themselves); a set/get round trip
  * returns F unchanged for diagonal entries in [0.5, 2], where F - I is exact. */
@@ -143,7 +145,7 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const
  * one: the actions of the paper's manipulation tasks move rigid bodies through
  * the scene (Section 5 task descriptions; contact of Appendix D.3). vel is a
  * HOST array [n][3] (m/s): during substep k (counted from the last
- * mpm_set_particles) the box moves at vel[k] and its centre is
+ * mpm_set_particles of this env) the box moves at vel[k] and its centre is
  * center + dt sum_{j<k} vel[j], with `center` as given to mpm_set_box_collider
  * (accumulated in FP64, stored as FP32). n = 0 (or vel = NULL) returns to the
  * constant velocity. A forward past substep n - 1 fails with INVALID_ARG.
@@ -180,9 +182,9 @@ int mpm_moments(mpm_batch* b, const float* x, const float* v, const float* w, do
 int mpm_moments_vjp(mpm_batch* b, const float* x, const float* v, const float* w, const double* gout, float* gx,
                     float* gv);
 
-/* Advances every environment by n_substeps (0 <= n <= max_substeps) from the
- * current state and clock. Particles are re-sorted by cell at every
- * checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)
+/* Advances every environment by n_substeps (0 <= n <= max_substeps) of the
+ * MLS-MPM substep above (paper Appendix D.3) from the current state and
+ * clocks. Particles are re-sorted by cell at every checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)
  * and the last segment's states and grids are kept for mpm_backward;
  * otherwise any earlier record is dropped. Asynchronous on the stream. */
 int mpm_forward(mpm_batch* b, int32_t n_substeps, int32_t flags);
@@ -203,13 +205,20 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags);
  * graphs stay valid. Errors: INVALID_ARG above capacity. */
 int mpm_configure_env(mpm_batch* b, int32_t env, const mpm_env_desc* d);
 
-/* Reverse-mode adjoint of the last recorded mpm_forward. Inputs: cotangents
- * of the final state (device, AoS over all environments in original order;
- * NULL = zero). Outputs: cotangents of the state at the start of that forward
- * (device, same layout; NULL = not wanted) and, if dparams != NULL, a DEVICE
- * array [n_envs][8] of doubles receiving dL/d(E, nu, rho, Vp, sigma_y, K,
- * gamma, 0). Segments are recomputed from checkpoints. The record stays valid
- * (backward may be called again with other cotangents).
+/* Reverse-mode adjoint of the last recorded mpm_forward: the vector-Jacobian
+ * product of the substep map s_{k+1} = f(s_k; params) composed over the
+ * recorded substeps (paper Appendix D, the chain that carries simulation
+ * gradients back through the states; Section 5.1, gradient checkpointing with
+ * forward recomputation). Inputs: cotangents of the final state (device, AoS
+ * over all environments in original order; NULL = zero). Outputs: cotangents
+ * of the state at the start of that forward (device, same layout; NULL = not
+ * wanted) and, if dparams != NULL, a DEVICE array [n_envs][8] of doubles
+ * receiving dL/d(E, nu, rho, Vp, sigma_y, K, gamma, 0). dL/drho comes from the
+ * scale invariance of the substep (it depends on the parameters only through
+ * tau / rho): rho dL/drho = -(E dL/dE + sigma_y dL/dsigma_y + K dL/dK), and
+ * dL/dVp = 0 exactly (Vp cancels between particle mass and force). Segments are
+ * recomputed from checkpoints. The record stays valid (backward may be called
+ * again with other cotangents).
  * Errors: BAD_STATE if no recorded forward precedes. */
 int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC, const float* gF, float* dx0,
                  float* dv0, float* dC0, float* dF0, double* dparams);
@@ -217,9 +226,12 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
 /* Execution options (mpm_set_option / mpm_get_option). Changing a kernel
  * variant drops the cached graphs. */
 #define MPM_OPT_GRAPHS 1       /* 1: replay each segment as a hipGraph (batched mode only; default 1) */
-#define MPM_OPT_P2G 2          /* P2G variant: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default) */
+#define MPM_OPT_P2G 2          /* P2G variant: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default),
+                                  3 LDS pull: each LDS box node summed by its owner thread from the block's
+                                  particles (counting-sorted by cell in LDS), no LDS float atomics */
 #define MPM_OPT_G2P 3          /* G2P variant: 0 global gathers, 1 LDS-staged (default) */
-#define MPM_OPT_G2P_ADJ 4      /* G2P adjoint: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default) */
+#define MPM_OPT_G2P_ADJ 4      /* G2P adjoint: 0 global atomics, 1 LDS-staged, 2 LDS + per-cell runs (default),
+                                  3 LDS pull (as MPM_OPT_P2G = 3) */
 #define MPM_OPT_P2G_ADJ 5      /* P2G adjoint: 0 global gathers, 1 LDS-staged (default) */
 #define MPM_OPT_MIN_RUN 6      /* per-cell-run variants engage when particles per stencil base >= this (default 3) */
 #define MPM_OPT_GRID_CAP 7     /* LDS-staged kernels: 0 = one block per work item (default); > 0 = a persistent
@@ -298,6 +310,132 @@ int mpm_set_timing(mpm_batch* b, int32_t enabled);
 
 /* Text of the last error on this batch ("" if none); a static string if b is NULL. */
 const char* mpm_last_error(const mpm_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of rollout requests over one batch of slots.
+ *
+ * A request is one environment: its description, material and optional box
+ * collider, an initial state, a number of substeps S and, optionally, a
+ * backward pass from cotangents of its final state to cotangents of its
+ * initial state and parameters -- the rollout and its gradient that the
+ * paper's first-order learner asks of the simulator for each environment
+ * (Section 5.1: parallel differentiable simulation with gradient
+ * checkpointing; Appendix D: the gradient chain through the substeps). The
+ * server owns a batch whose environments are slots of a fixed capacity (grid
+ * n_cap^3, n_cap_particles particles) and admits requests by an HBM budget:
+ *  - requests queue in arrival order; the head is admitted when a slot is free
+ *    and the bytes it keeps on the device (its state, grid share, and for a
+ *    backward its chunk checkpoints and running cotangent) fit in the budget;
+ *  - each mpm_server_step advances every slot in its forward phase by one
+ *    chunk of substeps in ONE batched forward, then moves every slot in its
+ *    backward phase one chunk back in ONE recorded forward + backward over
+ *    those slots: a chunk's forward is recomputed from the checkpoint taken
+ *    before it (internal state and collider clock), the running cotangent
+ *    goes through it, and the parameter cotangents of the chunks are summed
+ *    in FP64. Requests that arrive while others run join at the next step and
+ *    share the same kernel launches;
+ *  - a finished request frees its slot and budget at once; a request whose
+ *    environment reports a device error (non-finite state, a particle out of
+ *    the band) fails alone.
+ * One server is used by one host thread at a time. Calls that return results
+ * synchronize the server's stream.
+ * ------------------------------------------------------------------------ */
+typedef struct mpm_server mpm_server;
+
+typedef struct {
+  int32_t n_slots;          /* environments of the batch (concurrent requests), >= 1 */
+  int32_t n_cap;            /* grid capacity per slot (nodes per axis, multiple of 4, >= 12) */
+  int64_t n_cap_particles;  /* particle capacity per slot, >= 1 */
+  int32_t chunk;            /* substeps per engine step and checkpoint interval, >= 1 */
+  int32_t flags;            /* MPM_SERVER_DRY: schedule only, no device work (host-logic tests) */
+  int64_t budget_bytes;     /* device bytes the admitted requests may keep resident */
+} mpm_server_desc;
+
+#define MPM_SERVER_DRY 1
+
+typedef struct {
+  mpm_env_desc env;        /* n <= n_cap, n_particles <= n_cap_particles, material */
+  double params[8];        /* as mpm_set_material */
+  int32_t has_collider;    /* 1: the box below (as mpm_set_box_collider) */
+  int32_t substeps;        /* S >= 1 */
+  float c_center[3], c_half[3], c_vel[3], c_alpha, c_mu;
+  int32_t backward;        /* 1: run the backward pass after the forward */
+  int32_t reserved;
+  double arrival;          /* seconds on the server clock (mpm_server_now); < 0 = at submission */
+  /* DEVICE arrays owned by the caller, AoS as for mpm_set_particles; they must
+   * stay valid and unchanged until the request reaches a final state. */
+  const float *x, *v, *C, *F;        /* initial state, read at admission */
+  const float *gx, *gv, *gC, *gF;    /* cotangents of the final state (backward; NULL = 0), read when it starts */
+  float *out_x, *out_v, *out_C, *out_F;  /* final state, written when the forward ends (NULL = not wanted) */
+  float *dx0, *dv0, *dC0, *dF0;          /* initial-state cotangents, written when the backward ends (NULL = skip) */
+} mpm_request;
+
+/* request states */
+#define MPM_REQ_QUEUED 0
+#define MPM_REQ_RUNNING 1
+#define MPM_REQ_DONE 2
+#define MPM_REQ_ERROR 3      /* a device error in its environment; error_bits says which */
+#define MPM_REQ_CANCELLED 4
+#define MPM_REQ_REJECTED 5   /* above the slot capacity or the whole budget */
+#define MPM_REQ_UNKNOWN 6    /* no such id, or its final state was already polled */
+
+typedef struct {
+  int32_t state;            /* MPM_REQ_* */
+  int32_t error_bits;       /* 1 non-finite, 2 out of the band */
+  double arrival, admitted, finished;   /* server-clock seconds (0 if not reached) */
+  double dparams[8];        /* dL/d(E, nu, rho, Vp, sigma_y, K, gamma, 0), FP64 sum over the chunks */
+} mpm_request_status;
+
+typedef struct {
+  int64_t submitted, done, errors, cancelled, rejected, queued, running;
+  int64_t particle_substeps;   /* sum of N S over requests finished ok (each counted once, with or without a
+                                  backward) */
+  int64_t steps;               /* engine steps taken */
+  int32_t max_running;         /* most requests admitted at once */
+  int32_t reserved;
+  int64_t bytes_in_use;        /* budget taken by the admitted requests */
+  double p50_ms, p99_ms;       /* arrival-to-finish latency of the requests finished ok */
+  double first_arrival, last_finish;   /* server-clock seconds */
+} mpm_server_stats;
+
+/* Creates a server and its batch of n_slots slots (device memory through
+ * `alloc` if given, work on `stream`). Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * DEVICE_ERROR. */
+int mpm_server_create(const mpm_server_desc* desc, const mpm_allocator* alloc, void* stream, mpm_server** out);
+
+/* Waits for the stream, frees everything; requests still queued or running are dropped. */
+int mpm_server_destroy(mpm_server* s);
+
+/* Queues a request (copies the struct; the arrays stay the caller's). *id
+ * receives its id. A request above the slot capacity or the whole budget is
+ * recorded as MPM_REQ_REJECTED. Errors: INVALID_ARG (null state arrays,
+ * S < 1, an unknown material, nu outside (-1, 0.5)). */
+int mpm_server_submit(mpm_server* s, const mpm_request* r, int64_t* id);
+
+/* One engine step: admit, one forward chunk, one backward chunk, wait for the
+ * device, retire finished requests. Returns MPM_OK or the error of a failed
+ * device call (failures of single environments only fail their requests). */
+int mpm_server_step(mpm_server* s);
+
+/* State of request `id` (host *st). A final state (DONE, ERROR, CANCELLED,
+ * REJECTED) is reported once; the record is then dropped. */
+int mpm_server_poll(mpm_server* s, int64_t id, mpm_request_status* st);
+
+/* Cancels a queued or running request (its slot and budget are freed at
+ * once). Returns INVALID_ARG if it is not queued or running. */
+int mpm_server_cancel(mpm_server* s, int64_t id);
+
+/* Seconds since the server was created (its clock for arrivals). */
+double mpm_server_now(const mpm_server* s);
+
+/* 1 if no request is queued or running, else 0. */
+int mpm_server_idle(const mpm_server* s);
+
+/* Counters and latency percentiles into the host struct *st. */
+int mpm_server_stats_get(mpm_server* s, mpm_server_stats* st);
+
+/* Text of the server's last error. */
+const char* mpm_server_last_error(const mpm_server* s);
 
 /* Library version string. */
 const char* mpm_version(void);

@@ -36,6 +36,8 @@ EXPORTED = (
     "mpm_memory_bytes", "mpm_kernel_time", "mpm_set_timing", "mpm_last_error", "mpm_version", "mpm_sort_keys",
     "mpm_set_option", "mpm_get_option", "mpm_forward_envs", "mpm_configure_env", "mpm_set_collider_motion",
     "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
+    "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
+    "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
 )
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
@@ -52,6 +54,38 @@ class mpm_batch_desc(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("envs", ctypes.POINTER(mpm_env_desc)),
                 ("max_substeps", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+MPM_SERVER_DRY = 1
+(MPM_REQ_QUEUED, MPM_REQ_RUNNING, MPM_REQ_DONE, MPM_REQ_ERROR, MPM_REQ_CANCELLED, MPM_REQ_REJECTED,
+ MPM_REQ_UNKNOWN) = range(7)
+REQ_STATE_NAMES = ("queued", "running", "ok", "error", "cancelled", "rejected", "unknown")
+
+
+class mpm_server_desc(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("n_cap", ctypes.c_int32), ("n_cap_particles", ctypes.c_int64),
+                ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32), ("budget_bytes", ctypes.c_int64)]
+
+
+class mpm_request(ctypes.Structure):
+    _fields_ = [("env", mpm_env_desc), ("params", ctypes.c_double * 8), ("has_collider", ctypes.c_int32),
+                ("substeps", ctypes.c_int32), ("c_center", ctypes.c_float * 3), ("c_half", ctypes.c_float * 3),
+                ("c_vel", ctypes.c_float * 3), ("c_alpha", ctypes.c_float), ("c_mu", ctypes.c_float),
+                ("backward", ctypes.c_int32), ("reserved", ctypes.c_int32), ("arrival", ctypes.c_double)] + \
+               [(k, ctypes.c_void_p) for k in ("x", "v", "C", "F", "gx", "gv", "gC", "gF", "out_x", "out_v", "out_C",
+                                                "out_F", "dx0", "dv0", "dC0", "dF0")]
+
+
+class mpm_request_status(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("error_bits", ctypes.c_int32), ("arrival", ctypes.c_double),
+                ("admitted", ctypes.c_double), ("finished", ctypes.c_double), ("dparams", ctypes.c_double * 8)]
+
+
+class mpm_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "done", "errors", "cancelled", "rejected", "queued",
+                                              "running", "particle_substeps", "steps")] + \
+               [("max_running", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bytes_in_use", ctypes.c_int64)] + \
+               [(k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "first_arrival", "last_finish")]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -102,6 +136,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_get_collider_grad": (I32, [VP, I32, D8, D8, I32]),
         "mpm_moments": (I32, [VP, VP, VP, VP, VP]),
         "mpm_moments_vjp": (I32, [VP, VP, VP, VP, VP, VP, VP]),
+        "mpm_server_create": (I32, [P(mpm_server_desc), P(mpm_allocator), VP, P(VP)]),
+        "mpm_server_destroy": (I32, [VP]),
+        "mpm_server_submit": (I32, [VP, P(mpm_request), P(I64)]),
+        "mpm_server_step": (I32, [VP]),
+        "mpm_server_poll": (I32, [VP, I64, P(mpm_request_status)]),
+        "mpm_server_cancel": (I32, [VP, I64]),
+        "mpm_server_now": (ctypes.c_double, [VP]),
+        "mpm_server_idle": (I32, [VP]),
+        "mpm_server_stats_get": (I32, [VP, P(mpm_server_stats)]),
+        "mpm_server_last_error": (ctypes.c_char_p, [VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -122,11 +166,11 @@ class MPMError(RuntimeError):
         self.code = code
 
 
-def check(code: int, where: str, handle=None):
+def check(code: int, where: str, handle=None, server: bool = False):
     if code != MPM_OK:
         msg = ""
         if _lib is not None:
-            raw = _lib.mpm_last_error(handle)
+            raw = (_lib.mpm_server_last_error if server else _lib.mpm_last_error)(handle)
             msg = raw.decode() if raw else ""
         raise MPMError(code, where, msg)
     return code

@@ -204,7 +204,6 @@ struct Stencil {
   bool oob;
 };
 
-// base = floor(x n - 1/2) evaluated in FP64: exact for FP32 x, so binning is bit-exact
 // base = floor(x n - 1/2), bit-exact for FP32 x and n < 2^22 in FP32 alone: the
 // fma rounds x n - 1/2 once, which can only carry it up onto the next integer;
 // the residual x n - (b + 1/2), also one fma, has the exact sign and undoes

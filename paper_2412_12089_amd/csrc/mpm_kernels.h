@@ -34,10 +34,15 @@ void launch_gather_aos(const WorkItem* items, int n_items, const EnvDev* envs, c
                        const float* C, const float* F, const int32_t* ids, float* st, int64_t N, hipStream_t s);
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
-void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s);
+// copies one env's state rows [p0, p0 + cnt) and ids to (to_buf = 1) or from a compact [25][cnt] buffer
+void launch_env_rows(float* st, int32_t* ids, int64_t N, int64_t p0, int64_t cnt, float* buf, int to_buf,
+                     hipStream_t s);
+// per-env substep clocks: set (env < 0: all), advance over a forward segment, or rebase for a backward segment
+void launch_set_clock(int32_t* clock, int env, int n_envs, int32_t value, hipStream_t s);
+void launch_advance_clocks(int32_t* clock, const EnvDev* envs, int n_envs, int k0, int Kj, hipStream_t s);
+void launch_clocks_from(int32_t* clock, const int32_t* base, int n_envs, int k, hipStream_t s);
 void launch_sq_diff(const float* a, const float* b, int64_t n, double* acc, hipStream_t s);
 void launch_copy_f32(const float* a, float* b, int64_t n, hipStream_t s);
-void launch_add_clock(int32_t* clock, int32_t delta, hipStream_t s);
 void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
                  uint32_t* vals, int cell_bits, hipStream_t s);
 int launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* counts, int64_t N,
@@ -76,6 +81,15 @@ void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* 
                             int k_call, int grid_cap, int box, int mat, hipStream_t s);
 void launch_p2g_adjoint_lds(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,
                             const WorkItem* items, int n_items, const float* gcot, double* pacc, int k_call, const float* cot_in, int grid_cap, int box, int mat, hipStream_t s);
+
+// pull scatters: the LDS-staged kernels' boxes, but each box node is summed by
+// its owner thread from LDS payloads of the block's particles (counting-sorted
+// by stencil base) instead of LDS float atomics
+void launch_p2g_pull(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s);
+void launch_g2p_adjoint_pull(const float* st, const float* st_next, const float* cot, float* part, int64_t N,
+                             const EnvDev* envs, const WorkItem* items, int n_items, const float* grid, float* gcot,
+                             double* pacc, int k_call, int grid_cap, int box, int mat, hipStream_t s);
 
 // segment-reduced scatters: runs = min_run | max_run << 16. Blocks whose
 // particles average at least min_run per run sum each run (cut at max_run

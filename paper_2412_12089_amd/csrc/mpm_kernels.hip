@@ -82,10 +82,18 @@ __global__ void k_finalize_params(const EnvDev* envs, const double* acc, double*
   double* o = out + i * 8;
   o[0] = a[PB_MU] * dmu_dE + a[PB_LAM] * dlam_dE;
   o[1] = a[PB_MU] * dmu_dnu + a[PB_LAM] * dlam_dnu;
-  o[2] = a[PB_MP] * e.Vp;                        // m_p = rho Vp
-  o[3] = a[PB_VP] + a[PB_MP] * e.rho;
   o[4] = a[PB_SY];
   o[5] = a[PB_K];
+  // With one particle mass m_p = rho Vp per environment the substep depends on
+  // the parameters only through tau / rho (Vp cancels between the mass and the
+  // force, and every stress law is homogeneous of degree one in (E, sigma_y, K)
+  // at fixed nu, gamma). Scaling (E, sigma_y, K, rho) together leaves the
+  // trajectory unchanged, so rho dL/drho = -(E dL/dE + sigma_y dL/dsigma_y +
+  // K dL/dK) and dL/dVp = 0 exactly. The rho cotangent is formed that way: its
+  // mass-path and stress-path parts cancel to about 1e-3 of each, which the
+  // FP32 per-particle sums (a[PB_MP], a[PB_VP]) cannot resolve.
+  o[2] = e.rho > 0.0 ? -(E * o[0] + e.sigma_y * o[4] + e.K * o[5]) / e.rho : 0.0;
+  o[3] = 0.0;
   o[6] = a[PB_GAMMA];
   o[7] = 0.0;
 }
@@ -169,17 +177,50 @@ __global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ 
   if (i < n) b[i] = a[i];
 }
 
+// one env's internal state rows [p0, p0 + cnt) (24 SoA components, then the
+// caller ids) to or from a compact buffer [25][cnt]; to_buf = 1: state -> buf
+__global__ void k_env_rows(float* __restrict__ st, int32_t* __restrict__ ids, int64_t N, int64_t p0, int64_t cnt,
+                           float* __restrict__ buf, int to_buf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  int32_t* bi = reinterpret_cast<int32_t*>(buf + 24 * cnt);
+  if (to_buf) {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) buf[c * cnt + i] = st[c * N + p0 + i];
+    bi[i] = ids[p0 + i];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) st[c * N + p0 + i] = buf[c * cnt + i];
+    ids[p0 + i] = bi[i];
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void k_set_clock(int32_t* clock, int32_t value) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = value;
+// per-environment substep clocks (substeps since the env's particles were
+// set); they place a prescribed collider motion in time
+__global__ void k_set_clock(int32_t* clock, int env, int n_envs, int32_t value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_envs && (env < 0 || i == env)) clock[i] = value;
 }
 
-__global__ void k_add_clock(int32_t* clock, int32_t delta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += delta;
+// a forward segment of Kj substeps starting at call substep k0: each env
+// advances by the substeps it takes in it (frozen envs stop at nsub)
+__global__ void k_advance_clocks(int32_t* clock, const EnvDev* envs, int n_envs, int k0, int Kj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_envs) return;
+  const int r = envs[i].nsub - k0;
+  clock[i] += r < 0 ? 0 : (r < Kj ? r : Kj);
 }
+
+// clock[e] = base[e] + k: a backward segment starts k substeps after the recorded forward's start
+__global__ void k_clocks_from(int32_t* clock, const int32_t* base, int n_envs, int k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_envs) clock[i] = base[i] + k;
+}
+
 
 // sum over i of (a_i - b_i)^2 and b_i^2 in FP64 (two accumulators), for the
 // autotuner's parity check of a candidate against the reference kernels
@@ -448,8 +489,9 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], int i, int j, int
   return ct;
 }
 
-// the box's center and velocity during substep clock + k_rel: a row of the
-// prescribed motion table, or the constant velocity from the center at t = 0
+// the box's center and velocity during substep clock[0] + k_rel (clock: this
+// env's substep clock): a row of the prescribed motion table, or the constant
+// velocity from the center at t = 0
 MD void box_motion(const EnvDev& e, const float* __restrict__ motion, double t0, const int32_t* clock, int k_rel,
                    float c[3], float vb[3], int& row) {
   row = -1;
@@ -492,7 +534,8 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
   const int l = threadIdx.x & 63;
   if (tile >= tile0 + ntiles) return;
   if (flags[tile] == 0u) return;
-  const EnvDev& e = envs[tile_env[tile]];
+  const int ei = tile_env[tile];
+  const EnvDev& e = envs[ei];
   int i, j, k;
   node_coords(e, tile, l, i, j, k);
   float* g = grid + tile * 512 + l;
@@ -506,7 +549,7 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
     if (e.has_collider) {
       float bc[3], bv[3];
       int row;
-      box_motion(e, motion, t0, clock, k_rel, bc, bv, row);
+      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, row);
       const Contact c = contact_geometry(e, bc, i, j, k);
       float u[3], up[3], ut[3], un, utn;
       for (int a = 0; a < 3; ++a) u[a] = v[a] - bv[a];
@@ -536,7 +579,8 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   const int l = threadIdx.x & 63;
   if (tile >= tile0 + ntiles) return;
   if (flags[tile] == 0u) return;
-  const EnvDev& e = envs[tile_env[tile]];
+  const int ei = tile_env[tile];
+  const EnvDev& e = envs[ei];
   int i, j, k;
   node_coords(e, tile, l, i, j, k);
   float* g = grid + tile * 512 + l;
@@ -552,7 +596,7 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
     const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
     if (e.has_collider) {
       float bc[3], bv[3];
-      box_motion(e, motion, t0, clock, k_rel, bc, bv, row);
+      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, row);
       const Contact c = contact_geometry(e, bc, i, j, k);
       float u[3], up[3], ut[3], un, utn;
       for (int a = 0; a < 3; ++a) u[a] = vpre[a] - bv[a];
@@ -904,6 +948,11 @@ void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_copy_i32, dim3(nblk(n, 256)), dim3(256), 0, s, a, b, n);
 }
+void launch_env_rows(float* st, int32_t* ids, int64_t N, int64_t p0, int64_t cnt, float* buf, int to_buf,
+                     hipStream_t s) {
+  if (cnt == 0) return;
+  hipLaunchKernelGGL(k_env_rows, dim3(nblk(cnt, 256)), dim3(256), 0, s, st, ids, N, p0, cnt, buf, to_buf);
+}
 void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
   if (n_words == 0) return;
   int64_t b = nblk(n_words, 256);
@@ -922,11 +971,14 @@ void launch_copy_f32(const float* a, float* b, int64_t n, hipStream_t s) {
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n);
 }
-void launch_set_clock(int32_t* clock, int32_t value, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clock, value);
+void launch_set_clock(int32_t* clock, int env, int n_envs, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_clock, dim3((n_envs + 255) / 256), dim3(256), 0, s, clock, env, n_envs, value);
 }
-void launch_add_clock(int32_t* clock, int32_t delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_clock, dim3(1), dim3(64), 0, s, clock, delta);
+void launch_advance_clocks(int32_t* clock, const EnvDev* envs, int n_envs, int k0, int Kj, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_clocks, dim3((n_envs + 255) / 256), dim3(256), 0, s, clock, envs, n_envs, k0, Kj);
+}
+void launch_clocks_from(int32_t* clock, const int32_t* base, int n_envs, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_clocks_from, dim3((n_envs + 255) / 256), dim3(256), 0, s, clock, base, n_envs, k);
 }
 void launch_keys(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, uint32_t* keys,
                  uint32_t* vals, int cell_bits, hipStream_t s) {

@@ -281,6 +281,144 @@ MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
 }
 
 // ----------------------------------------------------------------------------
+// Owner-computes ("pull") scatter through LDS. Float atomics into LDS run at a
+// small fraction of the LDS read rate, so at a few particles per cell the
+// push scatter (27 nodes x channels atomics per particle) is bound by them.
+// Instead each particle writes its scatter payload once to LDS, the block
+// counting-sorts its particles by their current stencil base (one integer LDS
+// atomic per particle), and the thread that owns a box node sums the
+// contributions of the particles whose stencil holds it: for each of the
+// node's 9 (x, y) base columns the three z bases are adjacent cells, so their
+// particles form one contiguous range of the sorted list. A particle's
+// contribution to node base + o is W(o) (g + A (o - f)) per channel (the
+// affine form of both scatters), plus W(o) * mass for the mass channel.
+// ----------------------------------------------------------------------------
+constexpr int kPayload = 16;   // floats per particle: f (3), base z (int bits), g (3), A (9, row-major)
+
+// block-wide inclusive prefix sum of a[0, n) in place (every thread calls it)
+MD void block_scan_inclusive(int* a, int n, int* wtot) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int i0 = min(t * per, n), i1 = min(i0 + per, n);
+  int s = 0;
+  for (int i = i0; i < i1; ++i) { s += a[i]; a[i] = s; }
+  int x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wtot[wave] = x;
+  __syncthreads();
+  int off = x - s;
+  for (int w = 0; w < wave; ++w) off += wtot[w];
+  for (int i = i0; i < i1; ++i) a[i] += off;
+  __syncthreads();
+}
+
+// LDS of the pull scatter: the cell index and the payload rows
+template <int BOXN>
+struct PullShared {
+  int start[BOXN + 1];     // first list position of each base cell (cells of all runs concatenated)
+  int list[256];           // payload rows (item particle indices) in cell order
+  int coff[kMaxRuns + 1];  // first cell of each run
+  int cext[kMaxRuns][3];   // base-cell extents of each run (its box extents - 2)
+  int wtot[4];
+  float4 pay[256 * (kPayload / 4)];
+};
+
+MD void pull_store_payload(float4* pay, int lp, const float f[3], int bz, const float g[3], const float A[3][3]) {
+  float4* row = pay + lp * (kPayload / 4);
+  row[0] = make_float4(f[0], f[1], f[2], __int_as_float(bz));
+  row[1] = make_float4(g[0], g[1], g[2], A[0][0]);
+  row[2] = make_float4(A[0][1], A[0][2], A[1][0], A[1][1]);
+  row[3] = make_float4(A[1][2], A[2][0], A[2][1], A[2][2]);
+}
+
+// counting sort of the block's particles by current stencil base within their
+// run's box (every thread calls it; the box must fit)
+template <int BOXN>
+MD void pull_index(const BoxShared& bs, PullShared<BOXN>& ps, const Box& bx, const int b[3], bool valid, int lp) {
+  const int nr = bs.nruns < kMaxRuns ? bs.nruns : kMaxRuns;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int r = 0; r < nr; ++r) {
+      ps.coff[r] = acc;
+      int n = 1;
+      for (int a = 0; a < 3; ++a) {
+        ps.cext[r][a] = bs.ext[r][a] - 2;
+        n *= ps.cext[r][a];
+      }
+      acc += n;
+    }
+    ps.coff[nr] = acc;
+  }
+  __syncthreads();
+  const int ncell = ps.coff[nr];
+  for (int i = threadIdx.x; i <= ncell; i += blockDim.x) ps.start[i] = 0;
+  __syncthreads();
+  int cid = 0, rank = 0;
+  if (valid) {
+    const int r = bx.run;
+    cid = ps.coff[r] + ((b[0] - bs.lo[r][0]) * ps.cext[r][1] + (b[1] - bs.lo[r][1])) * ps.cext[r][2] +
+          (b[2] - bs.lo[r][2]);
+    rank = atomicAdd(&ps.start[cid + 1], 1);   // counts one cell up: the inclusive scan makes start[] exclusive
+  }
+  __syncthreads();
+  block_scan_inclusive(ps.start, ncell + 1, ps.wtot);
+  if (valid) ps.list[ps.start[cid] + rank] = lp;
+  __syncthreads();
+}
+
+// sum for box node idx (run r, node (i, j, k)) over the run's particles whose
+// stencil holds it: acc[c] += W (g_c + A_c . (o - f)), wsum += W
+MD void pull_node(const BoxShared& bs, const int* start, const int* list, const int* coff, const int (*cext)[3],
+                  const float4* pay, int r, int i, int j, int k, float acc[3], float& wsum) {
+  const int c0 = i - bs.lo[r][0], c1 = j - bs.lo[r][1], c2 = k - bs.lo[r][2];
+  const int e0 = cext[r][0], e1 = cext[r][1], e2 = cext[r][2];
+  const int z_lo = max(c2 - 2, 0), z_hi = min(c2, e2 - 1);
+  if (z_lo > z_hi) return;
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox) {
+    const int cx = c0 - ox;
+    if (cx < 0 || cx >= e0) continue;
+#pragma unroll 1
+    for (int oy = 0; oy < 3; ++oy) {
+      const int cy = c1 - oy;
+      if (cy < 0 || cy >= e1) continue;
+      const int cb = coff[r] + (cx * e1 + cy) * e2;
+      const int q1 = start[cb + z_hi + 1];
+#pragma unroll 1
+      for (int q = start[cb + z_lo]; q < q1; ++q) {
+        const float4* row = pay + list[q] * (kPayload / 4);
+        const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
+        const int oz = k - __float_as_int(r0.w);
+        float wx, wy, wz, dw;
+        spline_piece(ox, r0.x, wx, dw);
+        spline_piece(oy, r0.y, wy, dw);
+        spline_piece(oz, r0.z, wz, dw);
+        const float W = wx * wy * wz;
+        const float d0 = (float)ox - r0.x, d1 = (float)oy - r0.y, d2 = (float)oz - r0.z;
+        const float g0 = fmaf(r1.w, d0, fmaf(r2.x, d1, fmaf(r2.y, d2, r1.x)));
+        const float g1 = fmaf(r2.z, d0, fmaf(r2.w, d1, fmaf(r3.x, d2, r1.y)));
+        const float g2 = fmaf(r3.y, d0, fmaf(r3.z, d1, fmaf(r3.w, d2, r1.z)));
+        acc[0] = fmaf(W, g0, acc[0]);
+        acc[1] = fmaf(W, g1, acc[1]);
+        acc[2] = fmaf(W, g2, acc[2]);
+        wsum += W;
+      }
+    }
+  }
+}
+
+// run index and node of box node idx
+MD void box_node_run(const BoxShared& bs, int idx, int& r, int& i, int& j, int& k) {
+  r = 0;
+  while (r + 1 < kMaxRuns && r + 1 < bs.nruns && bs.off[r + 1] <= idx) ++r;
+  box_node(bs, idx, i, j, k);
+}
+
+// ----------------------------------------------------------------------------
 // P2G
 // ----------------------------------------------------------------------------
 template <int BOXN, int MAT>
@@ -356,6 +494,91 @@ __global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, i
     }
   } else {
     p2g_lds_item<BOXN, MAT>(blockIdx.x, st, N, envs, items, grid, flags, errs, k_call);
+  }
+}
+
+// P2G through the pull scatter: the block's particles write (m_p v, A dx, f)
+// to LDS, each box node is summed by its owner thread and added to the grid
+// once; a block whose boxes do not fit scatters with global atomics
+template <int BOXN, int MAT>
+MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, const EnvDev* __restrict__ envs,
+                      const WorkItem* __restrict__ items, float* __restrict__ grid, uint32_t* __restrict__ flags,
+                      int32_t* __restrict__ errs, int k_call) {
+  __shared__ BoxShared bsh;
+  __shared__ PullShared<BOXN> ps;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
+  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
+  const int lp = lane_particle(threadIdx.x);
+  const bool valid = lp < it.count;
+  const int64_t p = it.start + (valid ? lp : 0);
+  float x[3];
+  load_x3(st, N, p, x);
+  const Stencil sc = make_stencil(x, e.n, e.fn);
+  if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
+  if (valid) {
+    const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
+    const M3 Cm = ld_m3(st, N, p, 6);
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 tau = stress(e, H, mat);
+    const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+    const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
+    float mv0[3];
+    for (int a = 0; a < 3; ++a) mv0[a] = e.mp * v[a];
+    if (bx.fits) {
+      float Ad[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) Ad[a][c] = A.m[a][c] * e.dx;
+      pull_store_payload(ps.pay, lp, sc.f, sc.b[2], mv0, Ad);
+    } else {
+#pragma unroll 1
+      for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz) {
+            float W, d[3];
+            stencil_offsets(sc, e, ox, oy, oz, W, d);
+            float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+            atomicAdd(g, W * e.mp);
+            for (int a = 0; a < 3; ++a)
+              atomicAdd(g + (1 + a) * CH, W * (mv0[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]));
+          }
+    }
+  }
+  if (!bx.fits) {
+    if (valid) mark_particle_tiles(e, sc.b, flags);
+    return;
+  }
+  pull_index<BOXN>(bsh, ps, bx, sc.b, valid, lp);
+  for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
+    int r, i, j, k;
+    box_node_run(bsh, idx, r, i, j, k);
+    float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
+    pull_node(bsh, ps.start, ps.list, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
+    if (wsum == 0.f) continue;   // no particle weight reached the node
+    float* dst = grid + node_base(e, i, j, k);
+    atomicAdd(dst, wsum * e.mp);
+    for (int a = 0; a < 3; ++a)
+      if (acc[a] != 0.f) atomicAdd(dst + (1 + a) * CH, acc[a]);
+  }
+  box_mark_tiles(e, bsh, flags);
+}
+
+template <bool PERSIST, int BOXN, int MAT>
+__global__ void __launch_bounds__(256) k_p2g_pull(const float* __restrict__ st, int64_t N,
+                                                  const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                                                  float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                  int32_t* __restrict__ errs, int k_call, int n_items) {
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      p2g_pull_item<BOXN, MAT>(i, st, N, envs, items, grid, flags, errs, k_call);
+      __syncthreads();
+    }
+  } else {
+    p2g_pull_item<BOXN, MAT>(blockIdx.x, st, N, envs, items, grid, flags, errs, k_call);
   }
 }
 
@@ -560,6 +783,129 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict
     }
   } else {
     g2p_adjoint_lds_item<BOXN, MAT>(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+  }
+}
+
+// G2P adjoint through the pull scatter: the gather of v stays LDS-staged;
+// each particle writes (vbar', D4 dx Cbar, f) to LDS and the owner of each box
+// node sums its cotangent W (vbar' + D4 Cbar d) and adds it to the grid once
+template <int BOXN, int MAT>
+MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
+                              const float* __restrict__ cot, float* __restrict__ part, int64_t N,
+                              const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                              const float* __restrict__ grid, float* __restrict__ gcot, double* __restrict__ pacc,
+                              int k_call) {
+  __shared__ float lv[3 * BOXN];
+  __shared__ BoxShared bsh;
+  __shared__ PullShared<BOXN> ps;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;   // MAT < 0: the generic kernel
+  if (k_call >= e.nsub) return;   // frozen env: nothing to scatter
+  const int lp = lane_particle(threadIdx.x);
+  const bool valid = lp < it.count;
+  const int64_t p = it.start + (valid ? lp : 0);
+  float x[3];
+  load_x3(st, N, p, x);
+  const Stencil sc = make_stencil(x, e.n, e.fn);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
+  if (bx.fits) box_load(e, bx, bsh, grid, 4, 3, lv);
+  __syncthreads();
+  float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    const M3 H = ld_m3(st, N, p, 15);
+    const M3 F = f_of(H);
+    const float D4 = 4.f * e.fn * e.fn;
+    // C' of the substep's output state, read from the tape (the forward's own value)
+    const M3 Cn = load_cnext(st_next, N, p);
+    const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
+    const M3 Htr = trial_h(e, Cn, H);
+    float xb[3], vb[3];
+    for (int a = 0; a < 3; ++a) { xb[a] = cot[a * N + p]; vb[a] = cot[(3 + a) * N + p] + e.dt * xb[a]; }
+    const M3 Cb_in = ld_m3(cot, N, p, 6);
+    const M3 Fb_in = ld_m3(cot, N, p, 15);
+    const M3 Ftrb = project_vjp(e, Htr, Fb_in, pb, mat);
+    const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
+    const M3 Fb = m3_mul_atb(G, Ftrb);
+    st_m3(part, N, p, 3, Fb);
+    if (bx.fits) {
+      float Ad[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) Ad[a][c] = D4 * e.dx * Cb.m[a][c];
+      pull_store_payload(ps.pay, lp, sc.f, sc.b[2], vb, Ad);
+    }
+    float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
+    float gz[3], cz[3];
+    for (int o = 0; o < 3; ++o) gz[o] = e.fn * sc.dw[2][o];
+    for (int a = 0; a < 3; ++a) cz[a] = D4 * Cb.m[a][2];
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox)
+#pragma unroll 1
+      for (int oy = 0; oy < 3; ++oy) {
+        const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy);
+        const float wxy = wx * wy, gx = e.fn * sel3(sc.dw[0], ox) * wy, gy = e.fn * wx * sel3(sc.dw[1], oy);
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        float gc[3];
+        for (int a = 0; a < 3; ++a) gc[a] = fmaf(D4, fmaf(Cb.m[a][0], d0, Cb.m[a][1] * d1), vb[a]);
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wz = sc.w[2][oz];
+          const float W = wxy * wz;
+          const float gW[3] = {gx * wz, gy * wz, wxy * gz[oz]};
+          const float d2 = ((float)oz - sc.f[2]) * e.dx;
+          float vi[3], gv[3];
+          for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
+          if (bx.fits) {
+            const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+            for (int a = 0; a < 3; ++a) vi[a] = lv[a * bx.nodes + idx];
+          } else {
+            const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+            for (int a = 0; a < 3; ++a) {
+              vi[a] = grid[nb + (4 + a) * CH];
+              atomicAdd(gcot + nb + a * CH, W * gv[a]);
+            }
+          }
+          const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
+          for (int a = 0; a < 3; ++a) {
+            xb[a] = fmaf(gW[a], vg, xb[a]);
+            sv[a] = fmaf(W, vi[a], sv[a]);
+          }
+        }
+      }
+    for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
+    for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
+  }
+  if (bx.fits) {
+    pull_index<BOXN>(bsh, ps, bx, sc.b, valid, lp);
+    for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
+      int r, i, j, k;
+      box_node_run(bsh, idx, r, i, j, k);
+      float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
+      pull_node(bsh, ps.start, ps.list, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
+      if (wsum == 0.f) continue;
+      float* dst = gcot + node_base(e, i, j, k);
+      for (int a = 0; a < 3; ++a)
+        if (acc[a] != 0.f) atomicAdd(dst + a * CH, acc[a]);
+    }
+  }
+  block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
+}
+
+template <bool PERSIST, int BOXN, int MAT>
+__global__ void __launch_bounds__(256) k_g2p_adjoint_pull(const float* __restrict__ st,
+                                                          const float* __restrict__ st_next,
+                                                          const float* __restrict__ cot, float* __restrict__ part,
+                                                          int64_t N, const EnvDev* __restrict__ envs,
+                                                          const WorkItem* __restrict__ items,
+                                                          const float* __restrict__ grid, float* __restrict__ gcot,
+                                                          double* __restrict__ pacc, int k_call, int n_items) {
+  if (PERSIST) {
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+      g2p_adjoint_pull_item<BOXN, MAT>(i, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
+      __syncthreads();
+    }
+  } else {
+    g2p_adjoint_pull_item<BOXN, MAT>(blockIdx.x, st, st_next, cot, part, N, envs, items, grid, gcot, pacc, k_call);
   }
 }
 
@@ -1672,6 +2018,73 @@ void launch_g2p_adjoint_lds(const float* st, const float* st_next, const float* 
     launch_g2p_adjoint_lds_m<kBoxSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
   else
     launch_g2p_adjoint_lds_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
+}
+// pull-scatter variants: the same launch shapes as the LDS-staged kernels
+template <int BOXN, int MAT>
+static void launch_p2g_pull_t(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                              float* grid, uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL((k_p2g_pull<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, N, envs, items, grid, flags,
+                       errs, k_call, n_items);
+  else
+    hipLaunchKernelGGL((k_p2g_pull<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags,
+                       errs, k_call, n_items);
+}
+template <int BOXN, int MAT>
+static void launch_g2p_adjoint_pull_t(const float* st, const float* st_next, const float* cot, float* part, int64_t N,
+                                      const EnvDev* envs, const WorkItem* items, int n_items, const float* grid,
+                                      float* gcot, double* pacc, int k_call, int grid_cap, hipStream_t s) {
+  if (grid_cap > 0 && grid_cap < n_items)
+    hipLaunchKernelGGL((k_g2p_adjoint_pull<true, BOXN, MAT>), dim3(grid_cap), dim3(256), 0, s, st, st_next, cot, part,
+                       N, envs, items, grid, gcot, pacc, k_call, n_items);
+  else
+    hipLaunchKernelGGL((k_g2p_adjoint_pull<false, BOXN, MAT>), dim3(n_items), dim3(256), 0, s, st, st_next, cot, part,
+                       N, envs, items, grid, gcot, pacc, k_call, n_items);
+}
+template <int BOXN>
+static void launch_p2g_pull_m(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                              float* grid, uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s,
+                              int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_p2g_pull_t<BOXN, MAT_NEOHOOKEAN>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_p2g_pull_t<BOXN, MAT_COROTATED>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_p2g_pull_t<BOXN, MAT_VONMISES>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_p2g_pull_t<BOXN, MAT_FLUID_TAIT>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_p2g_pull_t<BOXN, MAT_FLUID_PAPER>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    case -1: launch_p2g_pull_t<BOXN, -1>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s); break;
+    default: break;
+  }
+}
+template <int BOXN>
+static void launch_g2p_adjoint_pull_m(const float* st, const float* st_next, const float* cot, float* part, int64_t N,
+                                      const EnvDev* envs, const WorkItem* items, int n_items, const float* grid,
+                                      float* gcot, double* pacc, int k_call, int grid_cap, hipStream_t s, int mat) {
+  switch (mat) {
+    case MAT_NEOHOOKEAN: launch_g2p_adjoint_pull_t<BOXN, MAT_NEOHOOKEAN>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_COROTATED: launch_g2p_adjoint_pull_t<BOXN, MAT_COROTATED>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_VONMISES: launch_g2p_adjoint_pull_t<BOXN, MAT_VONMISES>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_FLUID_TAIT: launch_g2p_adjoint_pull_t<BOXN, MAT_FLUID_TAIT>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case MAT_FLUID_PAPER: launch_g2p_adjoint_pull_t<BOXN, MAT_FLUID_PAPER>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    case -1: launch_g2p_adjoint_pull_t<BOXN, -1>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s); break;
+    default: break;
+  }
+}
+void launch_p2g_pull(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
+                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_p2g_pull_m<kBoxSmall>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+  else
+    launch_p2g_pull_m<kBoxNodes>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+}
+void launch_g2p_adjoint_pull(const float* st, const float* st_next, const float* cot, float* part, int64_t N,
+                             const EnvDev* envs, const WorkItem* items, int n_items, const float* grid, float* gcot,
+                             double* pacc, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_g2p_adjoint_pull_m<kBoxSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
+  else
+    launch_g2p_adjoint_pull_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
 }
 template <int BOXN, int MAT>
 static void launch_p2g_adjoint_lds_t(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,

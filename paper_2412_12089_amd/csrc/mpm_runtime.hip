@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/mpm.h"
+#include "mpm_internal.h"
 #include "mpm_kernels.h"
 
 using namespace mpmx;
@@ -86,17 +87,17 @@ struct mpm_batch {
   float* part = nullptr;
   double* pacc = nullptr;
   int32_t* errs = nullptr;
-  int32_t* clock = nullptr;
+  int32_t* clock = nullptr;       // [E] per-env substep clocks (collider motion time)
+  int32_t* clock_rec = nullptr;   // [E] the clocks at the start of the recorded forward
   float* motion_d = nullptr;     // prescribed collider motions: [E][max_substeps] rows (center, velocity)
   double* gmotion_d = nullptr;   // their cotangents, same layout, FP64
   std::vector<float> motion_h;
 
   // state
   float* cur = nullptr;
-  int64_t steps = 0;        // substeps taken since the last set_particles (collider clock)
+  std::vector<int64_t> env_steps;   // host mirror of the clocks: substeps each env took since its particles were set
   bool recorded = false;
   int rec_S = 0;
-  int64_t rec_steps0 = 0;
   bool last_seg_taped = false;
   std::vector<int32_t> env_err_h;
 
@@ -234,6 +235,7 @@ void batched_p2g(mpm_batch* b, const float* in, int gi, int kc) {
     const WorkItem* it = b->items_mat_d + r.first;
     if (b->var_p2g == 2) launch_p2g_seg(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, runs, kc, b->grid_cap, b->box, r.mat, s);
     else if (b->var_p2g == 1) launch_p2g_lds(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, kc, b->grid_cap, b->box, r.mat, s);
+    else if (b->var_p2g == 3) launch_p2g_pull(in, b->N, b->envs_d, it, r.count, b->grid[gi], b->flags[gi], b->errs, kc, b->grid_cap, b->box, r.mat, s);
   }
 }
 
@@ -298,6 +300,7 @@ void batched_g2p_adj(mpm_batch* b, const float* st, const float* st_next, const 
     const WorkItem* it = b->items_mat_d + r.first;
     if (b->var_g2p_adj == 2) launch_g2p_adjoint_seg(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, runs, kc, b->grid_cap, b->box, r.mat, s);
     else if (b->var_g2p_adj == 1) launch_g2p_adjoint_lds(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
+    else if (b->var_g2p_adj == 3) launch_g2p_adjoint_pull(st, st_next, cot_in, b->part, b->N, b->envs_d, it, r.count, g, b->gcot, b->pacc, kc, b->grid_cap, b->box, r.mat, s);
   }
 }
 
@@ -415,7 +418,7 @@ const float* fwd_segment(mpm_batch* b, int j, int Kj, bool record, bool tape, co
       in = out;
     }
   }
-  if (!dry) launch_add_clock(b->clock, Kj, b->stream);
+  if (!dry) launch_advance_clocks(b->clock, b->envs_d, b->E, j * b->K, Kj, b->stream);
   return in;
 }
 
@@ -580,6 +583,40 @@ int check_env(mpm_batch* b, int32_t env, bool allow_all) {
 
 }  // namespace
 
+namespace mpmx {
+
+int64_t env_snapshot_floats(const mpm_batch* b, int env) {
+  return env < 0 || env >= b->E ? 0 : 25 * b->envs_h[env].p_cnt;
+}
+
+int env_snapshot(mpm_batch* b, int env, float* dst, int64_t* steps) {
+  if (env < 0 || env >= b->E || !dst) return fail(b, MPM_INVALID_ARG, "snapshot: bad env or buffer");
+  const EnvDev& h = b->envs_h[env];
+  launch_env_rows(b->cur, b->ids_cur, b->N, h.p_off, h.p_cnt, dst, 1, b->stream);
+  HIPC(b, hipGetLastError());
+  if (steps) *steps = b->env_steps[env];
+  return MPM_OK;
+}
+
+int env_restore(mpm_batch* b, int env, const float* src, int64_t steps) {
+  if (env < 0 || env >= b->E || !src) return fail(b, MPM_INVALID_ARG, "restore: bad env or buffer");
+  const EnvDev& h = b->envs_h[env];
+  clear_dirty_tapes(b);
+  launch_env_rows(b->cur, b->ids_cur, b->N, h.p_off, h.p_cnt, const_cast<float*>(src), 0, b->stream);
+  launch_set_clock(b->clock, env, b->E, (int32_t)steps, b->stream);
+  HIPC(b, hipGetLastError());
+  b->env_steps[env] = steps;
+  b->recorded = false;
+  b->last_seg_taped = false;
+  return MPM_OK;
+}
+
+int64_t env_row_offset(const mpm_batch* b, int env) { return env < 0 || env >= b->E ? 0 : b->envs_h[env].row_off; }
+
+void* batch_stream(const mpm_batch* b) { return (void*)b->stream; }
+
+}  // namespace mpmx
+
 namespace {
 
 struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj, xcd; };
@@ -698,6 +735,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->rows = N;
   for (int e = 0; e < b->E; ++e) b->cap_n.push_back(d->envs[e].n);
   b->env_err_h.assign(b->E, 0);
+  b->env_steps.assign(b->E, 0);
 
   const size_t state_bytes = sizeof(float) * 24 * (size_t)std::max<int64_t>(N, 1);
   const size_t grid_bytes = sizeof(float) * 512 * (size_t)std::max<int64_t>(tiles, 1);
@@ -739,7 +777,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->part = (float*)A(sizeof(float) * 12 * (size_t)std::max<int64_t>(N, 1));
   b->pacc = (double*)A(sizeof(double) * 8 * b->E);
   b->errs = (int32_t*)A(sizeof(int32_t) * b->E);
-  b->clock = (int32_t*)A(256);
+  b->clock = (int32_t*)A(sizeof(int32_t) * b->E);
+  b->clock_rec = (int32_t*)A(sizeof(int32_t) * b->E);
   b->motion_d = (float*)A(sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
   b->gmotion_d = (double*)A(sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
   if (!ok) {
@@ -760,7 +799,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     zero(b->gcot, grid_bytes);
     zero(b->W[0], state_bytes);
     zero(b->errs, sizeof(int32_t) * b->E);
-    zero(b->clock, 256);
+    zero(b->clock, sizeof(int32_t) * b->E);
+    zero(b->clock_rec, sizeof(int32_t) * b->E);
     zero(b->motion_d, sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
     zero(b->gmotion_d, sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
     // identity ids and an F = I rest state until particles are set
@@ -797,8 +837,10 @@ int mpm_set_particles(mpm_batch* b, int32_t env, const float* x, const float* v,
   const int i0 = env < 0 ? 0 : b->item_off[env];
   const int ni = env < 0 ? (int)b->items_h.size() : b->item_off[env + 1] - b->item_off[env];
   launch_load_aos(b->items_d + i0, ni, b->envs_d, env < 0 ? 1 : 0, x, v, C, F, b->cur, b->N, b->ids_cur, b->stream);
+  launch_set_clock(b->clock, env, b->E, 0, b->stream);
   HIPC(b, hipGetLastError());
-  b->steps = 0;
+  for (int e = 0; e < b->E; ++e)
+    if (env < 0 || e == env) b->env_steps[e] = 0;
   b->recorded = false;
   b->last_seg_taped = false;
   return MPM_OK;
@@ -962,7 +1004,7 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
     S = std::max(S, n_substeps[e]);
   }
   for (int e = 0; e < b->E; ++e)
-    if (b->envs_h[e].motion_len > 0 && n_substeps[e] > 0 && b->steps + n_substeps[e] > b->envs_h[e].motion_len)
+    if (b->envs_h[e].motion_len > 0 && n_substeps[e] > 0 && b->env_steps[e] + n_substeps[e] > b->envs_h[e].motion_len)
       return fail(b, MPM_INVALID_ARG, "the collider motion of an environment is shorter than the rollout");
   bool changed = false;
   for (int e = 0; e < b->E; ++e) {
@@ -979,9 +1021,11 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
   clear_dirty_tapes(b);
   b->recorded = false;
   b->last_seg_taped = false;
-  if (record) launch_copy_i32(b->ids_cur, b->ids_start, b->N, s);
+  if (record) {
+    launch_copy_i32(b->ids_cur, b->ids_start, b->N, s);
+    launch_copy_i32(b->clock, b->clock_rec, b->E, s);
+  }
   const int nseg = (S + b->K - 1) / b->K;
-  launch_set_clock(b->clock, (int32_t)b->steps, s);
   const float* src = b->cur;
   for (int j = 0; j < nseg; ++j) {
     const int Kj = std::min(b->K, S - j * b->K);
@@ -998,10 +1042,9 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
   if (record) {
     b->recorded = true;
     b->rec_S = S;
-    b->rec_steps0 = b->steps;
     b->last_seg_taped = nseg > 0;
   }
-  b->steps += S;
+  for (int e = 0; e < b->E; ++e) b->env_steps[e] += n_substeps[e];
   return MPM_OK;
 }
 
@@ -1026,7 +1069,7 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
   launch_gather_aos(b->items_d, (int)b->items_h.size(), b->envs_d, gx, gv, gC, gF, b->ids_cur, b->cot[c], b->N, s);
   for (int j = nseg - 1; j >= 0; --j) {
     const int Kj = std::min(b->K, S - j * b->K);
-    launch_set_clock(b->clock, (int32_t)(b->rec_steps0 + (int64_t)j * b->K), s);
+    launch_clocks_from(b->clock, b->clock_rec, b->E, j * b->K, s);
     const bool have_tape = (j == nseg - 1) && b->last_seg_taped;
     if (!have_tape) clear_dirty_tapes(b);
     int c_out = c;
@@ -1103,9 +1146,9 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
   if (!b) return MPM_INVALID_ARG;
   switch (option) {
     case MPM_OPT_GRAPHS: b->use_graphs = value != 0; return MPM_OK;
-    case MPM_OPT_P2G: if (value < 0 || value > 2) break; b->var_p2g = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_P2G: if (value < 0 || value > 3) break; b->var_p2g = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_G2P: if (value < 0 || value > 1) break; b->var_g2p = value; drop_graphs(b); return MPM_OK;
-    case MPM_OPT_G2P_ADJ: if (value < 0 || value > 2) break; b->var_g2p_adj = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_G2P_ADJ: if (value < 0 || value > 3) break; b->var_g2p_adj = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_P2G_ADJ: if (value < 0 || value > 1) break; b->var_p2g_adj = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_MIN_RUN: if (value < 1 || value > 256) break; b->min_run = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_GRID_CAP: if (value < 0) break; b->grid_cap = value; drop_graphs(b); return MPM_OK;
@@ -1163,15 +1206,18 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
   float* gref = (float*)dalloc(b, sizeof(float) * 24 * R);
   float* gout = (float*)dalloc(b, sizeof(float) * 24 * R);
   int32_t* ids_saved = (int32_t*)dalloc(b, sizeof(int32_t) * b->N);
+  int32_t* clock_saved = (int32_t*)dalloc(b, sizeof(int32_t) * b->E);
   double* acc = (double*)dalloc(b, 256);
-  if (!saved || !ref || !cot_in || !gref || !gout || !ids_saved || !acc) return fail(b, MPM_OUT_OF_MEMORY, "autotune scratch");
+  if (!saved || !ref || !cot_in || !gref || !gout || !ids_saved || !clock_saved || !acc)
+    return fail(b, MPM_OUT_OF_MEMORY, "autotune scratch");
   float* cur0 = b->cur;
-  const int64_t steps0 = b->steps;
+  const std::vector<int64_t> steps0 = b->env_steps;
   const bool graphs0 = b->use_graphs;
   b->use_graphs = false;
   b->recorded = false;
   launch_copy_f32(cur0, saved, NS, s);
   launch_copy_i32(b->ids_cur, ids_saved, b->N, s);
+  launch_copy_i32(b->clock, clock_saved, b->E, s);
   launch_fill_u32(cot_in, 0x3f800000u, 24 * R, s);   // all-ones cotangent
   const int St = std::min(b->K, b->max_substeps);
   std::vector<int32_t> n_all(b->E, St);
@@ -1180,7 +1226,8 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     b->cur = cur0;
     launch_copy_f32(saved, cur0, NS, s);
     launch_copy_i32(ids_saved, b->ids_cur, b->N, s);
-    b->steps = steps0;
+    launch_copy_i32(clock_saved, b->clock, b->E, s);
+    b->env_steps = steps0;
     b->recorded = false;
   };
   float* g = gout;
@@ -1237,9 +1284,10 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
   struct Cand { int* slot; int value; int min_run; bool bwd; };
   std::vector<std::vector<Cand>> groups = {
       {{&best.p2g, 0, 0, false}, {&best.p2g, 1, 0, false}, {&best.p2g, 2, 2, false}, {&best.p2g, 2, 3, false},
-       {&best.p2g, 2, 4, false}, {&best.p2g, 2, 8, false}},
+       {&best.p2g, 2, 4, false}, {&best.p2g, 2, 8, false}, {&best.p2g, 3, 0, false}},
       {{&best.g2p, 0, 0, false}, {&best.g2p, 1, 0, false}},
-      {{&best.g2p_adj, 0, 0, true}, {&best.g2p_adj, 1, 0, true}, {&best.g2p_adj, 2, 0, true}},
+      {{&best.g2p_adj, 0, 0, true}, {&best.g2p_adj, 1, 0, true}, {&best.g2p_adj, 2, 0, true},
+       {&best.g2p_adj, 3, 0, true}},
       {{&best.p2g_adj, 0, 0, true}, {&best.p2g_adj, 1, 0, true}},
       {{&best.box, 0, 0, true}, {&best.box, 1, 0, true}},
       {{&best.specialize, 1, 0, true}, {&best.specialize, 0, 0, true}},
@@ -1287,7 +1335,8 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
   b->use_graphs = graphs0;
   if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = MPM_DEVICE_ERROR;
   // scratch goes back to the allocator
-  for (void* p : {(void*)saved, (void*)ref, (void*)cot_in, (void*)gref, (void*)gout, (void*)ids_saved, (void*)acc}) {
+  for (void* p : {(void*)saved, (void*)ref, (void*)cot_in, (void*)gref, (void*)gout, (void*)ids_saved,
+                  (void*)clock_saved, (void*)acc}) {
     for (size_t i = 0; i < b->allocations.size(); ++i)
       if (b->allocations[i].first == p) {
         if (b->has_alloc) b->alloc.free(p, b->alloc.ctx); else (void)hipFree(p);

@@ -1,154 +1,180 @@
-"""Scheduler logic of the continuous-batching server, on the CPU with an
-executor that runs the FP64 oracle."""
-import dataclasses
+"""Host logic of the library's continuous-batching server, on the CPU: the
+server in its dry mode schedules exactly as on the device (admission by budget
+in arrival order, one forward chunk per step for requests in their forward
+phase, one backward chunk per step for those in their backward phase, slot
+reuse, cancel, reject) without device work. The numerics of served requests
+are checked on the GPU (tests/test_gpu_server.py)."""
+import ctypes
 
 import numpy as np
 import pytest
-import torch
 
-from oracle import mpm_oracle as O
-from oracle_executor import OracleExecutor
+from paper_2412_12089_amd import _capi as C
 from paper_2412_12089_amd import scenes
-from paper_2412_12089_amd.server import Server, resident_bytes
+from paper_2412_12089_amd.server import Server
 
 
-def small_requests(n=6, seed=0, N_lo=60, N_hi=160, S_lo=3, S_hi=9):
-    rng = np.random.default_rng(seed)
-    reqs = []
-    for i in range(n):
-        N = int(rng.integers(N_lo, N_hi))
-        mat = scenes.MIXED_MATERIALS[i % 3]
-        x = scenes._f32(0.4 + rng.uniform(0, 0.15, size=(N, 3)))
-        v = scenes._f32(rng.uniform(-0.5, 0.5, size=(N, 3)))
-        C, F = scenes._rest_state(N)
-        env = scenes.EnvSpec(n=16, dt=2e-4, rho=1e3, Vp=0.15 ** 3 / N, x=x, v=v, C=C, F=F, **mat)
-        w = scenes._f32(rng.standard_normal((N, 3)))
-        reqs.append(scenes.Request(i, 0.0, env, int(rng.integers(S_lo, S_hi)), bool(i % 2 == 0), w))
-    return reqs
+def req(rid, N=1000, n=32, S=10, backward=False, material=scenes.NEOHOOKEAN):
+    x = np.zeros((N, 3), np.float32)
+    env = scenes.EnvSpec(n=n, dt=5e-5, material=material, E=5e3, nu=0.3, rho=1e3, Vp=1e-6, x=x)
+    return scenes.Request(rid, 0.0, env, S, backward, np.zeros((N, 3), np.float32))
 
 
-class FakeClock:
-    def __init__(self):
-        self.t = 0.0
+def resident(r, chunk):
+    """Device bytes the library reserves for an admitted request."""
+    N, n = r.env.n_particles, r.env.n
+    b = 96 * N + 32 * n ** 3
+    if r.backward:
+        b += -(-r.substeps // chunk) * 25 * 4 * N + 96 * N
+    return b
 
-    def __call__(self):
-        self.t += 1e-3
-        return self.t
+
+def state(srv, sid):
+    st = C.mpm_request_status()
+    assert srv.lib.mpm_server_poll(srv.h, sid, ctypes.byref(st)) == 0
+    return st.state
 
 
-def serve(reqs, n_slots=3, budget=10 ** 9, chunk=4):
-    ex = OracleExecutor(n_slots, n_cap=16, N_cap=200)
-    srv = Server(ex, budget, chunk=chunk, clock=FakeClock())
+def dry(n_slots=2, chunk=4, budget=1 << 40, n_cap=64, N_cap=100_000):
+    return Server(n_slots, n_cap, N_cap, chunk, budget, dry=True)
+
+
+def test_steps_to_finish_follow_the_chunks():
+    # S = 10, chunk 4: forward chunks at steps 1, 2, 3; the backward starts in the step whose forward
+    # ends and undoes one chunk per step (3 chunks: steps 3, 4, 5)
+    srv = dry(n_slots=2, chunk=4)
+    a = srv.submit(req(0, S=10, backward=False))
+    b = srv.submit(req(1, S=10, backward=True))
+    finished = {}
+    for step in range(1, 8):
+        srv.lib.mpm_server_step(srv.h)
+        for sid in (a, b):
+            if sid not in finished:
+                s = state(srv, sid)
+                if s == C.MPM_REQ_DONE:
+                    finished[sid] = step
+                else:
+                    assert s == C.MPM_REQ_RUNNING
+    assert finished == {a: 3, b: 5}
+    assert state(srv, a) == C.MPM_REQ_UNKNOWN     # a final state is reported once
+    st = srv.stats()
+    assert st["ok"] == 2 and st["particle_substeps"] == 2 * 1000 * 10   # N S once per request
+    assert st["steps"] == 7 and st["max_concurrent"] == 2
+    srv.close()
+
+
+def test_admission_by_budget_keeps_arrival_order():
+    chunk = 5
+    big, small = req(0, N=50_000, S=10), req(2, N=2000, S=5)
+    big2 = req(1, N=50_000, S=10)
+    budget = resident(big, chunk) + resident(small, chunk) - 1   # big + small do not fit together
+    srv = dry(n_slots=4, chunk=chunk, budget=budget)
+    ids = [srv.submit(r) for r in (big, big2, small)]
+    srv.lib.mpm_server_step(srv.h)
+    # the second big request waits for the budget, and the small one behind it is not admitted first
+    assert [state(srv, i) for i in ids] == [C.MPM_REQ_RUNNING, C.MPM_REQ_QUEUED, C.MPM_REQ_QUEUED]
+    assert srv.stats()["bytes_in_use"] == resident(big, chunk)
+    srv.lib.mpm_server_step(srv.h)          # big finishes (2 chunks) and frees its budget
+    assert state(srv, ids[0]) == C.MPM_REQ_DONE
+    srv.lib.mpm_server_step(srv.h)          # big2 admitted; small does not fit beside it
+    assert state(srv, ids[1]) == C.MPM_REQ_RUNNING and state(srv, ids[2]) == C.MPM_REQ_QUEUED
+    for _ in range(4):
+        srv.lib.mpm_server_step(srv.h)
+    srv.collect()
+    assert srv.stats()["ok"] == 3 and srv.stats()["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_budget_boundary_and_capacity_rejects():
+    chunk = 4
+    r = req(0, N=3000, S=9, backward=True)
+    exact = resident(r, chunk)
+    srv = dry(chunk=chunk, budget=exact)
+    ok = srv.submit(r)
+    too_big = srv.submit(req(1, N=3001, S=9, backward=True))       # one particle more than the budget holds
+    grid = srv.submit(req(2, n=96))                                 # grid above the slot capacity (64)
+    parts = srv.submit(req(3, N=100_001))                           # particles above the slot capacity
+    for sid in (too_big, grid, parts):
+        assert state(srv, sid) == C.MPM_REQ_REJECTED
+    srv.lib.mpm_server_step(srv.h)
+    assert state(srv, ok) == C.MPM_REQ_RUNNING
+    assert srv.stats()["rejected"] == 3
+    srv.close()
+
+
+def test_cancel_frees_the_slot_and_budget():
+    srv = dry(n_slots=1, chunk=2)
+    a = srv.submit(req(0, S=8))
+    b = srv.submit(req(1, S=2))
+    c = srv.submit(req(2, S=2))
+    srv.lib.mpm_server_step(srv.h)
+    assert state(srv, a) == C.MPM_REQ_RUNNING and state(srv, b) == C.MPM_REQ_QUEUED
+    assert srv.lib.mpm_server_cancel(srv.h, c) == 0                 # queued
+    assert srv.lib.mpm_server_cancel(srv.h, a) == 0                 # running: slot and budget free at once
+    assert srv.stats()["bytes_in_use"] == 0
+    assert state(srv, a) == C.MPM_REQ_CANCELLED and state(srv, c) == C.MPM_REQ_CANCELLED
+    assert srv.lib.mpm_server_cancel(srv.h, a) == C.MPM_INVALID_ARG  # already final (and polled)
+    srv.lib.mpm_server_step(srv.h)
+    assert state(srv, b) == C.MPM_REQ_DONE
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["ok"] == 1
+    srv.close()
+
+
+def test_slots_are_reused_in_order():
+    srv = dry(n_slots=2, chunk=10)
+    reqs = [req(i, S=10 * (1 + i % 3)) for i in range(7)]
     done = srv.run(reqs, realtime=False)
-    return srv, ex, done
+    assert sorted(done) == list(range(7))
+    assert all(r.status == "ok" for r in done.values())
+    st = srv.stats()
+    assert st["max_concurrent"] == 2 and st["running"] == 0 and st["queued"] == 0
+    assert st["particle_substeps"] == sum(r.env.n_particles * r.substeps for r in reqs)
+    srv.close()
 
 
-def test_results_match_direct_oracle_rollouts():
-    reqs = small_requests()
-    srv, ex, done = serve(reqs)
-    assert all(done[r.rid].status == "ok" for r in reqs)
-    for r in reqs:
-        env, prm, st = O.env_from_spec(r.env)
-        (x, v, C, F), _ = O.rollout(env, prm, st, r.substeps)
-        got = done[r.rid].state
-        for a, b in zip(got, (x, v, C, F)):
-            assert torch.allclose(a, b, rtol=0, atol=1e-13)
-        if r.backward:
-            g, gp = O.rollout_vjp(env, prm, st, r.substeps, O.linear_loss_cotangent(r.loss_weights, r.env.n_particles))
-            for a, b in zip(done[r.rid].grads, g):
-                assert torch.allclose(a, b, rtol=1e-10, atol=1e-12 * float(b.abs().max()))
-            np.testing.assert_allclose(done[r.rid].dparams, O.param_cotangent_row(gp), rtol=1e-9, atol=1e-30)
-        else:
-            assert done[r.rid].grads is None
+def test_invalid_requests_are_refused():
+    srv = dry()
+    lib = srv.lib
+    r = C.mpm_request()
+    r.env.n, r.env.material, r.env.n_particles, r.env.dt, r.env.wall = 32, 0, 10, 5e-5, 3
+    r.params[1] = 0.3
+    sid = ctypes.c_int64()
+    r.substeps = 5
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG   # null arrays
+    keep = np.zeros(4, np.float32)
+    r.x = r.v = r.C = r.F = keep.ctypes.data
+    r.substeps = 0
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG   # S < 1
+    r.substeps = 5
+    r.params[1] = 0.5
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG   # nu
+    r.params[1] = 0.3
+    r.env.material = 9
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG
+    r.env.material = 0
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_OK
+    assert lib.mpm_server_cancel(srv.h, 12345) == C.MPM_INVALID_ARG
+    st = C.mpm_request_status()
+    assert lib.mpm_server_poll(srv.h, 12345, ctypes.byref(st)) == 0 and st.state == C.MPM_REQ_UNKNOWN
+    srv.close()
 
 
-def test_work_overlaps_in_shared_calls():
-    reqs = small_requests()
-    srv, ex, done = serve(reqs, n_slots=3)
-    assert srv.max_concurrent == 3
-    # some forward call advanced more than one slot at once
-    assert any(sum(1 for k in counts if k) > 1 for kind, counts in ex.calls if kind == "fwd")
-    # forward and backward phases interleave across iterations
-    kinds = [k for k, _ in ex.calls]
-    first_rec = kinds.index("fwd_rec")
-    assert "fwd" in kinds[first_rec:]
+@pytest.mark.parametrize("kw", [dict(n_slots=0), dict(n_cap=30), dict(N_cap=0), dict(chunk=0), dict(budget=-1)])
+def test_create_rejects_bad_descriptions(kw):
+    args = dict(n_slots=2, n_cap=32, N_cap=100, chunk=4, budget=1 << 20)
+    args.update(kw)
+    with pytest.raises(C.MPMError):
+        Server(args["n_slots"], args["n_cap"], args["N_cap"], args["chunk"], args["budget"], dry=True)
 
 
-def test_tiny_budget_serialises_and_keeps_arrival_order():
-    reqs = small_requests()
-    biggest = max(resident_bytes(r, 4) for r in reqs)
-    srv, ex, done = serve(reqs, n_slots=3, budget=biggest)
-    assert all(done[r.rid].status == "ok" for r in reqs)
-    assert srv.max_concurrent == 1
-    adm = [done[r.rid].admitted for r in reqs]
-    assert adm == sorted(adm)
-
-
-def test_slots_are_reused():
-    reqs = small_requests(n=7)
-    srv, ex, done = serve(reqs, n_slots=2)
-    assert srv.max_concurrent == 2
-    assert all(done[r.rid].status == "ok" for r in reqs)
-    assert sorted(srv.free) == [0, 1] and not srv.active
-
-
-def test_cancel_and_reject():
-    reqs = small_requests(n=4)
-    ex = OracleExecutor(1, n_cap=16, N_cap=200)
-    srv = Server(ex, 10 ** 9, chunk=4, clock=FakeClock())
-    for r in reqs:
-        srv.submit(r)
-    srv.step()                      # request 0 admitted and running, others queued
-    assert srv.cancel(reqs[2].rid)  # queued
-    assert srv.cancel(reqs[0].rid)  # active
-    while not srv.idle():
-        srv.step()
-    st = {rid: r.status for rid, r in srv.done.items()}
-    assert st[reqs[0].rid] == "cancelled" and st[reqs[2].rid] == "cancelled"
-    assert st[reqs[1].rid] == "ok" and st[reqs[3].rid] == "ok"
-    big = dataclasses.replace(reqs[1], rid=99, env=dataclasses.replace(reqs[1].env, n=32))
-    srv.submit(big)
-    assert srv.done[99].status == "rejected"
-    tiny = Server(OracleExecutor(1, n_cap=16, N_cap=200), budget_bytes=10, chunk=4, clock=FakeClock())
-    tiny.submit(reqs[3])
-    assert tiny.done[reqs[3].rid].status == "rejected"
-
-
-def test_serving_stream_generator_is_seeded_and_shaped():
-    a = scenes.serving_stream(seed=5, duration=0.2)
-    b = scenes.serving_stream(seed=5, duration=0.2)
-    assert [r.rid for r in a] == [r.rid for r in b] and len(a) > 10
-    for r in a:
-        assert r.env.n in (32, 48, 64) and 4000 <= r.env.n_particles <= 100000 and 20 <= r.substeps <= 80
-        n = r.env.n
-        assert (r.env.x >= (scenes.WALL + 1) / n - 1e-6).all() and (r.env.x < 1 - (scenes.WALL + 1) / n).all()
-    arr = np.array([r.arrival for r in a])
-    assert (np.diff(arr) > 0).all()
-
-
-def test_results_can_be_dropped_for_throughput_runs():
-    # keep_results=False: finished requests keep status and timing only (a long stream holds no tensors)
-    reqs = small_requests(n=4)
-    ex = OracleExecutor(2, n_cap=16, N_cap=200)
-    srv = Server(ex, 10 ** 9, chunk=4, clock=FakeClock(), keep_results=False)
-    done = srv.run(reqs, realtime=False)
-    assert all(r.status == "ok" and r.state is None and r.grads is None for r in done.values())
-    assert srv.stats()["ok"] == len(reqs)
-
-
-def test_a_failing_request_fails_alone():
-    # a request with a particle outside the valid band is reported as an error and frees its slot;
-    # the others are unaffected
-    reqs = small_requests(n=5)
-    bad = reqs[2]
-    x = bad.env.x.copy()
-    x[0, 0] = 0.99
-    reqs[2] = dataclasses.replace(bad, env=dataclasses.replace(bad.env, x=x))
-    ex = OracleExecutor(2, n_cap=16, N_cap=200)
-    srv = Server(ex, 10 ** 9, chunk=4, clock=FakeClock())
-    done = srv.run(reqs, realtime=False)
-    st = {rid: r for rid, r in done.items()}
-    assert st[reqs[2].rid].status == "error" and st[reqs[2].rid].error & 2
-    assert all(st[r.rid].status == "ok" for i, r in enumerate(reqs) if i != 2)
-    assert sorted(srv.free) == [0, 1] and not srv.active
-    assert srv.stats()["errors"] == 1
+def test_latency_is_counted_from_the_stated_arrival():
+    import time
+    srv = dry(n_slots=1, chunk=4)
+    time.sleep(0.6)
+    t = srv.now()
+    a = srv.submit(req(0, S=4), arrival=t - 0.5)   # arrived half a second before it was submitted
+    srv.step()
+    r = srv.done[0]
+    assert r.status == "ok" and r.latency >= 0.5 and abs(r.arrival - (t - 0.5)) < 1e-9
+    srv.close()

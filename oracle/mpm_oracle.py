@@ -563,3 +563,37 @@ def moment_stats(m):
     var_z = m[6] / m[0] - com[2] ** 2
     vbar = m[10:13] / m[0]
     return com, var_z, vbar
+
+
+# ----------------------------------------------------------------------------
+# The flip reward of the HandFlip task (Appendix E): the mean Euclidean distance
+# between two mirrored halves of the particles, paired particle by particle,
+# and its normalized improvement NI{r} = clamp((r0 - r) / r0, -1, 1) over the
+# initial value r0
+# ----------------------------------------------------------------------------
+def mirror_pairs(x0, axis: int, plane: float):
+    """Pairs (lower, upper) of particles mirrored across the plane x[axis] =
+    plane in the configuration x0: the particles below the plane, each matched
+    to the upper-half particle nearest to its mirror image (a reading: the
+    paper names the two halves but not how they are matched). Brute force."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    low = np.nonzero(x0[:, axis] < plane)[0]
+    up = np.nonzero(x0[:, axis] >= plane)[0]
+    img = x0[low].copy()
+    img[:, axis] = 2.0 * plane - img[:, axis]
+    d = ((img[:, None, :] - x0[up][None, :, :]) ** 2).sum(-1)
+    return np.stack([low, up[np.argmin(d, axis=1)]], axis=1)
+
+
+def pair_distance(x, pairs):
+    """R_flip = (1 / P) sum_k ||x[a_k] - x[b_k]||_2 over the P pairs (a_k, b_k)."""
+    x = torch.as_tensor(x, dtype=DT)
+    p = torch.as_tensor(np.ascontiguousarray(pairs), dtype=torch.long)
+    if p.numel() == 0:
+        return torch.zeros((), dtype=DT)
+    return (x[p[:, 0]] - x[p[:, 1]]).norm(dim=1).mean()
+
+
+def normalized_improvement(r, r0):
+    """NI{r} = clamp((r0 - r) / r0, -1, 1)."""
+    return torch.clamp((r0 - r) / r0, -1.0, 1.0)

@@ -642,3 +642,68 @@ def test_moments_match_their_definitions():
     sub[::7] = 1.0
     np.testing.assert_allclose(O.moments(x, v, sub).numpy(), O.moments(x[::7], v[::7], np.ones(len(x[::7]))).numpy(),
                                rtol=1e-13)
+
+
+# ---------------------------------------------------------------- the flip reward (HandFlip, Appendix E)
+def test_pair_distance_hand_values_and_invariants():
+    # two pairs at hand-computed distances 5 (a 3-4-5 triangle) and 2
+    x = np.array([[0.0, 0.0, 0.0], [3.0, 4.0, 0.0], [1.0, 1.0, 1.0], [1.0, 1.0, 3.0]])
+    pairs = np.array([[0, 1], [2, 3]])
+    assert float(O.pair_distance(x, pairs)) == 3.5
+    assert float(O.pair_distance(x, pairs[:, ::-1])) == 3.5          # symmetric in the pair order
+    rng = np.random.default_rng(3)
+    y = rng.uniform(size=(40, 3))
+    p = rng.integers(0, 40, size=(25, 2))
+    r = float(O.pair_distance(y, p))
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    moved = y @ Q.T + rng.uniform(size=3)
+    assert abs(float(O.pair_distance(moved, p)) - r) < 1e-14 * 10      # rigid motions leave it unchanged
+    assert abs(float(O.pair_distance(2.5 * y, p)) - 2.5 * r) < 1e-14 * 10   # degree one in the positions
+
+
+def test_mirror_pairs_of_a_symmetric_set_and_a_folded_one():
+    # a lattice symmetric about z = 0.5: each lower particle is paired with its exact mirror image, and
+    # folding the upper half onto the lower one (z -> 1 - z) brings the flip distance to zero
+    g = np.arange(4) * 0.1 + 0.05
+    lat = np.array([[a, b, c] for a in g for b in g for c in (0.25, 0.35, 0.45, 0.55, 0.65, 0.75)])
+    pairs = O.mirror_pairs(lat, axis=2, plane=0.5)
+    assert len(pairs) == len(lat) // 2
+    lo, up = lat[pairs[:, 0]], lat[pairs[:, 1]]
+    np.testing.assert_allclose(lo[:, :2], up[:, :2], atol=0)
+    np.testing.assert_allclose(lo[:, 2] + up[:, 2], 1.0, atol=1e-15)
+    # before folding: the mean of |z_u - z_l| over the pairs (0.5, 0.3, 0.1 for the three layers)
+    assert abs(float(O.pair_distance(lat, pairs)) - 0.3) < 1e-15
+    folded = lat.copy()
+    upper = folded[:, 2] >= 0.5
+    folded[upper, 2] = 1.0 - folded[upper, 2]
+    assert float(O.pair_distance(folded, pairs)) < 1e-15
+
+
+def test_normalized_improvement_clamps():
+    r0 = torch.tensor(2.0, dtype=torch.float64)
+    for r, want in ((2.0, 0.0), (1.0, 0.5), (0.0, 1.0), (4.0, -1.0), (9.0, -1.0)):
+        assert float(O.normalized_improvement(torch.tensor(r, dtype=torch.float64), r0)) == want
+
+
+def test_pair_distance_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.uniform(size=(30, 3))).requires_grad_(True)
+    p = rng.integers(0, 30, size=(20, 2))
+    p = p[p[:, 0] != p[:, 1]]
+    O.pair_distance(x, p).backward()
+    g = x.grad.numpy()
+    # closed form: d/dx_a = (x_a - x_b) / ||x_a - x_b|| / P and the opposite for x_b
+    want = np.zeros((30, 3))
+    xv = x.detach().numpy()
+    for a, b in p:
+        u = (xv[a] - xv[b]) / np.linalg.norm(xv[a] - xv[b]) / len(p)
+        want[a] += u
+        want[b] -= u
+    np.testing.assert_allclose(g, want, rtol=1e-12, atol=1e-15)
+    h = 1e-6
+    for i, c in ((3, 0), (7, 2), (11, 1)):
+        xp, xm = xv.copy(), xv.copy()
+        xp[i, c] += h
+        xm[i, c] -= h
+        fd = (float(O.pair_distance(xp, p)) - float(O.pair_distance(xm, p))) / (2 * h)
+        assert abs(fd - g[i, c]) < 1e-8

@@ -288,6 +288,20 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms);
  * Any output pointer may be NULL. */
 int mpm_sort_keys(mpm_batch* b, uint32_t* keys, uint32_t* perm, int32_t* ids, int32_t* cell_bits);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, serving loops, harnesses that forbid allocation): the binning of
+ * mpm_sort_keys for one environment, with no batch and no allocation. x:
+ * DEVICE positions [n][3] (AoS float32) of one environment on a grid_n^3 grid;
+ * writes keys[i] = tile * 64 + cell of particle i (as mpm_sort_keys writes for
+ * env 0 of a batch) and perm, the stable sort order (DEVICE uint32 [n] each),
+ * asynchronously on `stream` (a hipStream_t). Its scratch is a device array of
+ * the library sized for MPM_SORT_NOALLOC_MAX particles, one per GPU, held
+ * until the process ends; calls that overlap on one GPU share it and race.
+ * Errors: INVALID_ARG for n < 0 or n > MPM_SORT_NOALLOC_MAX, a grid_n that
+ * mpm_env_desc would reject, or a null array; DEVICE_ERROR. */
+#define MPM_SORT_NOALLOC_MAX (1 << 20)
+int mpm_sort_keys_noalloc(const float* x, int64_t n, int32_t grid_n, uint32_t* keys, uint32_t* perm, void* stream);
+
 /* Waits for the stream and returns the first pending device-side error
  * (MPM_NONFINITE / MPM_OUT_OF_DOMAIN) or MPM_OK; clears it. */
 int mpm_sync(mpm_batch* b);

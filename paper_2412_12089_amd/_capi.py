@@ -38,7 +38,9 @@ EXPORTED = (
     "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
+    "mpm_sort_keys_noalloc",
 )
+MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
  OPT_FUSE, OPT_FUSE_ADJ, OPT_XCD) = range(1, 14)
@@ -146,6 +148,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_server_idle": (I32, [VP]),
         "mpm_server_stats_get": (I32, [VP, P(mpm_server_stats)]),
         "mpm_server_last_error": (ctypes.c_char_p, [VP]),
+        "mpm_sort_keys_noalloc": (I32, [VP, I64, I32, VP, VP, VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -182,6 +182,26 @@ int mpm_moments(mpm_batch* b, const float* x, const float* v, const float* w, do
 int mpm_moments_vjp(mpm_batch* b, const float* x, const float* v, const float* w, const double* gout, float* gx,
                     float* gv);
 
+/* The flip reward term of the HandFlip task (paper Appendix E): per env e, the
+ * mean Euclidean distance between paired particles,
+ *   R_e = (1 / P_e) sum_k ||x[a_k] - x[b_k]||_2
+ * over the P_e pairs of env e (the two mirrored halves of the particles, paired
+ * particle by particle). pairs: DEVICE int32 [n_pairs][3] rows (env, a, b)
+ * with a, b env-local caller indices; a pair naming an env or a particle out of
+ * range is skipped. x: DEVICE caller-order positions [rows][3]. out: DEVICE
+ * [n_envs][2] doubles: [e][0] = R_e (0 for an env without pairs), [e][1] = P_e.
+ * Distances in FP32, sums in FP64; asynchronous on the stream.
+ * Errors: INVALID_ARG for a null array or n_pairs < 0. */
+int mpm_pair_distance(mpm_batch* b, const float* x, const int32_t* pairs, int64_t n_pairs, double* out);
+
+/* VJP of mpm_pair_distance: gout DEVICE [n_envs] cotangents of R_e, out the
+ * forward's output (for P_e) -> gx DEVICE [rows][3] (written, not added):
+ * dR_e/dx[a_k] = (x[a_k] - x[b_k]) / (P_e ||x[a_k] - x[b_k]||), the opposite
+ * for x[b_k], summed over the pairs a particle belongs to; a pair at zero
+ * distance contributes 0. Asynchronous on the stream. */
+int mpm_pair_distance_vjp(mpm_batch* b, const float* x, const int32_t* pairs, int64_t n_pairs, const double* out,
+                          const double* gout, float* gx);
+
 /* Advances every environment by n_substeps (0 <= n <= max_substeps) of the
  * MLS-MPM substep above (paper Appendix D.3) from the current state and
  * clocks. Particles are re-sorted by cell at every checkpoint. With MPM_FWD_RECORD the checkpoints (every ckpt_every substeps)

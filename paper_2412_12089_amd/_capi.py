@@ -38,7 +38,7 @@ EXPORTED = (
     "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
-    "mpm_sort_keys_noalloc",
+    "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp",
 )
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
@@ -149,6 +149,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_server_stats_get": (I32, [VP, P(mpm_server_stats)]),
         "mpm_server_last_error": (ctypes.c_char_p, [VP]),
         "mpm_sort_keys_noalloc": (I32, [VP, I64, I32, VP, VP, VP]),
+        "mpm_pair_distance": (I32, [VP, VP, VP, I64, VP]),
+        "mpm_pair_distance_vjp": (I32, [VP, VP, VP, I64, VP, VP, VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

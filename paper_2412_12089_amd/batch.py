@@ -139,6 +139,26 @@ class Batch:
                   "mpm_moments_vjp")
         return gx, gv
 
+    def pair_distance(self, x, pairs):
+        """[E, 2] float64 (mean distance of each env's particle pairs, pair count); pairs int32 [P, 3] (env, a, b)."""
+        d = self.device
+        x = _f32(x, d)
+        pairs = pairs.to(device=d, dtype=torch.int32).contiguous()
+        out = torch.empty(self.E, 2, dtype=torch.float64, device=d)
+        self._chk(self.lib.mpm_pair_distance(self.h, C.ptr(x), C.ptr(pairs), int(pairs.shape[0]), C.ptr(out)),
+                  "mpm_pair_distance")
+        return out
+
+    def pair_distance_vjp(self, x, pairs, out, g):
+        d = self.device
+        x = _f32(x, d)
+        pairs = pairs.to(device=d, dtype=torch.int32).contiguous()
+        g = g.to(d, torch.float64).contiguous()
+        gx = torch.empty_like(x)
+        self._chk(self.lib.mpm_pair_distance_vjp(self.h, C.ptr(x), C.ptr(pairs), int(pairs.shape[0]), C.ptr(out),
+                                                 C.ptr(g), C.ptr(gx)), "mpm_pair_distance_vjp")
+        return gx
+
     def collider_grad(self, env: int, n: int):
         """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64."""
         dvel = np.zeros((n, 3), np.float64)

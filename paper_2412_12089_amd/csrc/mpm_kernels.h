@@ -119,5 +119,10 @@ void launch_moments(const WorkItem* items, int n_items, const EnvDev* envs, cons
                     const float* w, double* out, int n_envs, hipStream_t s);
 void launch_moments_vjp(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
                         const float* w, const double* g, float* gx, float* gv, hipStream_t s);
+// the flip reward term: per-env mean distance of paired particles [E][2] (mean, count), and its VJP (gx written)
+void launch_pair_distance(const EnvDev* envs, int n_envs, const float* x, const int32_t* pairs, int64_t n_pairs,
+                          double* out, hipStream_t s);
+void launch_pair_distance_vjp(const EnvDev* envs, int n_envs, const float* x, const int32_t* pairs, int64_t n_pairs,
+                              const double* out, const double* gout, float* gx, int64_t rows, hipStream_t s);
 
 }  // namespace mpmx

@@ -83,6 +83,65 @@ __global__ void __launch_bounds__(256) k_moments_vjp(const WorkItem* __restrict_
   }
 }
 
+// ----------------------------------------------------------------------------
+// The flip reward term of the HandFlip task (paper Appendix E): per env, the
+// mean Euclidean distance between paired particles, R = (1/P) sum_k
+// ||x_a - x_b||, and its VJP. A pair is (env, a, b) with env-local caller
+// indices; pairs naming an env or a particle out of range are skipped.
+// ----------------------------------------------------------------------------
+MD bool pair_rows(const EnvDev* __restrict__ envs, int n_envs, const int32_t* __restrict__ pr, int64_t& ra,
+                  int64_t& rb, int& env) {
+  env = pr[0];
+  if (env < 0 || env >= n_envs) return false;
+  const EnvDev& e = envs[env];
+  const int32_t a = pr[1], b = pr[2];
+  if (a < 0 || b < 0 || a >= e.p_cnt || b >= e.p_cnt) return false;
+  ra = e.row_off + a;
+  rb = e.row_off + b;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_pair_distance(const EnvDev* __restrict__ envs, int n_envs,
+                                                       const float* __restrict__ x, const int32_t* __restrict__ pairs,
+                                                       int64_t n_pairs, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  int64_t ra, rb;
+  int env;
+  if (!pair_rows(envs, n_envs, pairs + 3 * k, ra, rb, env)) return;
+  const float d0 = x[3 * ra] - x[3 * rb], d1 = x[3 * ra + 1] - x[3 * rb + 1], d2 = x[3 * ra + 2] - x[3 * rb + 2];
+  atomicAdd(&out[2 * env], (double)sqrtf(d0 * d0 + d1 * d1 + d2 * d2));
+  atomicAdd(&out[2 * env + 1], 1.0);
+}
+
+__global__ void k_pair_mean(double* __restrict__ out, int n_envs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_envs && out[2 * e + 1] > 0.0) out[2 * e] /= out[2 * e + 1];
+}
+
+// d R_e / d x_a = (x_a - x_b) / (P_e ||x_a - x_b||), the opposite for x_b; 0 at
+// zero distance (the norm's subgradient there is taken as 0)
+__global__ void __launch_bounds__(256) k_pair_distance_vjp(const EnvDev* __restrict__ envs, int n_envs,
+                                                           const float* __restrict__ x,
+                                                           const int32_t* __restrict__ pairs, int64_t n_pairs,
+                                                           const double* __restrict__ out,
+                                                           const double* __restrict__ gout, float* __restrict__ gx) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  int64_t ra, rb;
+  int env;
+  if (!pair_rows(envs, n_envs, pairs + 3 * k, ra, rb, env)) return;
+  const double P = out[2 * env + 1];
+  const float d[3] = {x[3 * ra] - x[3 * rb], x[3 * ra + 1] - x[3 * rb + 1], x[3 * ra + 2] - x[3 * rb + 2]};
+  const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (!(len > 0.f) || !(P > 0.0)) return;
+  const float s = (float)(gout[env] / P) / len;
+  for (int a = 0; a < 3; ++a) {
+    atomicAdd(&gx[3 * ra + a], s * d[a]);
+    atomicAdd(&gx[3 * rb + a], -s * d[a]);
+  }
+}
+
 void launch_moments(const WorkItem* items, int n_items, const EnvDev* envs, const float* x, const float* v,
                     const float* w, double* out, int n_envs, hipStream_t s) {
   launch_fill_u32(out, 0u, 2 * (int64_t)kMoments * n_envs, s);
@@ -94,6 +153,23 @@ void launch_moments_vjp(const WorkItem* items, int n_items, const EnvDev* envs, 
                         const float* w, const double* g, float* gx, float* gv, hipStream_t s) {
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_moments_vjp, dim3(n_items), dim3(256), 0, s, items, envs, x, v, w, g, gx, gv);
+}
+
+void launch_pair_distance(const EnvDev* envs, int n_envs, const float* x, const int32_t* pairs, int64_t n_pairs,
+                          double* out, hipStream_t s) {
+  launch_fill_u32(out, 0u, 2 * 2 * (int64_t)n_envs, s);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_pair_distance, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, envs, n_envs, x,
+                       pairs, n_pairs, out);
+  hipLaunchKernelGGL(k_pair_mean, dim3((n_envs + 63) / 64), dim3(64), 0, s, out, n_envs);
+}
+
+void launch_pair_distance_vjp(const EnvDev* envs, int n_envs, const float* x, const int32_t* pairs, int64_t n_pairs,
+                              const double* out, const double* gout, float* gx, int64_t rows, hipStream_t s) {
+  launch_fill_u32(gx, 0u, 3 * rows, s);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_pair_distance_vjp, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, envs, n_envs,
+                       x, pairs, n_pairs, out, gout, gx);
 }
 
 }  // namespace mpmx

@@ -995,6 +995,24 @@ int mpm_moments_vjp(mpm_batch* b, const float* x, const float* v, const float* w
   return MPM_OK;
 }
 
+int mpm_pair_distance(mpm_batch* b, const float* x, const int32_t* pairs, int64_t n_pairs, double* out) {
+  if (!b) return MPM_INVALID_ARG;
+  if (!x || !out || n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(b, MPM_INVALID_ARG, "null array or negative count");
+  launch_pair_distance(b->envs_d, b->E, x, pairs, n_pairs, out, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_pair_distance_vjp(mpm_batch* b, const float* x, const int32_t* pairs, int64_t n_pairs, const double* out,
+                          const double* gout, float* gx) {
+  if (!b) return MPM_INVALID_ARG;
+  if (!x || !out || !gout || !gx || n_pairs < 0 || (n_pairs > 0 && !pairs))
+    return fail(b, MPM_INVALID_ARG, "null array or negative count");
+  launch_pair_distance_vjp(b->envs_d, b->E, x, pairs, n_pairs, out, gout, gx, b->rows, b->stream);
+  HIPC(b, hipGetLastError());
+  return MPM_OK;
+}
+
 int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
   if (!b || !n_substeps) return MPM_INVALID_ARG;
   int32_t S = 0;

@@ -4,10 +4,14 @@ Per-env weighted moments of particle positions and velocities (libmpmx
 mpm_moments, FP64 accumulation) behind a torch.autograd.Function whose
 backward is the library's mpm_moments_vjp; the task statistics (centre of
 mass of a subsampled particle set, height variance, mean velocity) are a few
-divisions of those moments.
+divisions of those moments. The flip reward of the HandFlip task (paper
+Appendix E) is the per-env mean distance of mirrored particle pairs
+(mpm_pair_distance and its VJP) and its normalized improvement over the
+initial value.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import _capi as C
@@ -57,3 +61,56 @@ def subsample_weights(batch, stride: int):
         w[off:off + n:stride] = 1.0
         off += n
     return w
+
+
+class PairDistance(torch.autograd.Function):
+    """[E] float64: per-env mean distance of the pairs (env, a, b) of caller-order x [rows, 3]."""
+
+    @staticmethod
+    def forward(ctx, batch, x, pairs):
+        x = x.contiguous()
+        out = batch.pair_distance(x, pairs)
+        ctx.batch = batch
+        ctx.save_for_backward(x, pairs, out)
+        return out[:, 0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        x, pairs, out = ctx.saved_tensors
+        return None, ctx.batch.pair_distance_vjp(x, pairs, out, g.contiguous()), None
+
+
+def flip_distance(batch, x, pairs):
+    return PairDistance.apply(batch, x, pairs)
+
+
+def normalized_improvement(r, r0):
+    """NI{r} = clamp((r0 - r) / r0, -1, 1), the HandFlip reward of the flip distance r."""
+    return torch.clamp((r0 - r) / r0, -1.0, 1.0)
+
+
+def mirror_pairs(counts, x0, axis: int = 2, plane=None):
+    """Pairs (env, lower, upper) of each env's particles mirrored across the plane
+    x[axis] = plane (default: the env's mean along the axis). counts: particles per
+    env (the batch's counts); x0: caller-order positions [rows, 3] (host or
+    device). Each particle below the plane is matched to the upper-half particle
+    nearest to its mirror image (k-d tree)."""
+    from scipy.spatial import cKDTree
+    x0 = np.asarray(x0.detach().cpu().numpy() if torch.is_tensor(x0) else x0, dtype=np.float64)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    out = []
+    for e, (lo, hi) in enumerate(zip(offsets[:-1], offsets[1:])):
+        xe = x0[lo:hi]
+        if len(xe) == 0:
+            continue
+        c = float(xe[:, axis].mean()) if plane is None else float(plane)
+        low = np.nonzero(xe[:, axis] < c)[0]
+        up = np.nonzero(xe[:, axis] >= c)[0]
+        if len(low) == 0 or len(up) == 0:
+            continue
+        img = xe[low].copy()
+        img[:, axis] = 2.0 * c - img[:, axis]
+        _, j = cKDTree(xe[up]).query(img)
+        out.append(np.stack([np.full(len(low), e), low, up[j]], axis=1))
+    p = np.concatenate(out, axis=0) if out else np.zeros((0, 3), np.int64)
+    return torch.from_numpy(p.astype(np.int32))

@@ -40,3 +40,19 @@ def test_squashed_normal_log_probability():
     ref = torch.distributions.Normal(mu, std).log_prob(u).sum(-1) - torch.log(1 - a ** 2).sum(-1)
     np.testing.assert_allclose(logp.detach().numpy(), ref.detach().numpy(), rtol=1e-3, atol=1e-3)
     assert (a.abs() < 1).all() and math.isfinite(float(logp.sum()))
+
+
+def test_mirror_pairing_matches_the_oracle_rule():
+    # the library-side pairing (k-d tree) and the oracle's brute force pair the same particles
+    from oracle import mpm_oracle as O
+    from paper_2412_12089_amd import observe
+    rng = np.random.default_rng(9)
+    counts = [300, 0, 451]
+    x = rng.uniform(0.3, 0.6, size=(sum(counts), 3))
+    p = observe.mirror_pairs(counts, x, axis=2, plane=0.45).numpy()
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for e in (0, 2):
+        mine = p[p[:, 0] == e][:, 1:]
+        ref = O.mirror_pairs(x[off[e]:off[e + 1]], axis=2, plane=0.45)
+        assert np.array_equal(mine, ref)
+    assert not (p[:, 0] == 1).any()

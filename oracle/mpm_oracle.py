@@ -63,10 +63,13 @@ OFFSETS = torch.tensor([[a, b, c] for a in range(3) for b in range(3) for c in r
 @dataclass
 class Box:
     center: Tuple[float, float, float]
-    half: Tuple[float, float, float]
+    half: Tuple[float, float, float]       # half extents along the box's own axes
     velocity: Tuple[float, float, float]
     alpha: float
     mu_b: float
+    axis: Tuple[float, float, float] = (0.0, 0.0, 1.0)   # unit rotation axis (world)
+    angle: float = 0.0                     # rotation about the axis at t = 0 (rad)
+    omega: float = 0.0                     # constant angular speed about the axis (rad/s)
 
 
 @dataclass
@@ -85,7 +88,9 @@ def env_from_spec(spec) -> Tuple[Env, torch.Tensor, Tuple[torch.Tensor, ...]]:
     box = None
     if spec.collider is not None:
         c = spec.collider
-        box = Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b))
+        box = Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b),
+                  tuple(getattr(c, "axis", (0.0, 0.0, 1.0))), float(getattr(c, "angle", 0.0)),
+                  float(getattr(c, "omega", 0.0)))
     env = Env(n=spec.n, dt=spec.dt, material=spec.material, gravity=tuple(spec.gravity),
               wall=spec.wall, collider=box)
     prm = torch.tensor([spec.E, spec.nu, spec.rho, spec.Vp, spec.sigma_y, spec.K, spec.gamma], dtype=DT)
@@ -359,14 +364,32 @@ def box_sdf(p, center, half):
     return d, nrm
 
 
-def collide(env: Env, v, center, vb, active):
+def rotation(axis, theta):
+    """Rotation by theta about the unit axis (Rodrigues): I + sin t K + (1 - cos t) K^2, K = [axis]x."""
+    a = torch.as_tensor(axis, dtype=DT)
+    K = torch.zeros(3, 3, dtype=DT)
+    K[0, 1], K[0, 2], K[1, 0], K[1, 2], K[2, 0], K[2, 1] = -a[2], a[1], a[2], -a[0], -a[1], a[0]
+    theta = torch.as_tensor(theta, dtype=DT)
+    return torch.eye(3, dtype=DT) + torch.sin(theta) * K + (1.0 - torch.cos(theta)) * (K @ K)
+
+
+def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     """Softened one-way contact (Appendix D.3): blend pre/post projection by s = min(exp(-alpha d), 1).
 
-    ``center`` and ``vb`` are the box's center and velocity during this substep
-    (tensors, so that derivatives reach a prescribed collider motion)."""
+    ``center``, ``vb``, ``theta`` and ``omega`` are the box's center, velocity,
+    rotation angle about its axis and angular speed during this substep
+    (tensors, so that derivatives reach a prescribed collider motion). The box
+    is axis-aligned in its own frame: a node's distance and normal come from
+    its position R^T (x - c) in that frame, rotated back to the world, and the
+    box surface moves at vb + omega axis x (x - c)."""
     box = env.collider
     n = env.n
-    d, nh = box_sdf(node_positions(n), center, torch.tensor(box.half, dtype=DT))
+    R = rotation(box.axis, theta)
+    p = node_positions(n)
+    d, nh = box_sdf((p - center) @ R, torch.zeros(3, dtype=DT), torch.tensor(box.half, dtype=DT))
+    nh = nh @ R.T
+    a = torch.tensor(box.axis, dtype=DT)
+    vb = vb + omega * torch.linalg.cross(a.expand_as(p), p - center)
     s = torch.clamp(torch.exp(-box.alpha * d), max=1.0)
     u = v - vb
     un = (u * nh).sum(1)
@@ -385,23 +408,32 @@ def collide(env: Env, v, center, vb, active):
 
 
 def collider_motion(env: Env, t: float, motion=None):
-    """(center, velocity) of the box during the substep that starts at time t.
+    """(center, velocity, angle, angular speed) of the box during the substep
+    that starts at time t.
 
-    Without a prescribed motion the box moves at its constant velocity,
-    center = c0 + t v_b. With one, ``motion`` is this substep's (center, v_b)
-    from collider_path."""
+    Without a prescribed motion the box moves at its constant velocity and
+    angular speed: center = c0 + t v_b, angle = angle0 + t omega. With one,
+    ``motion`` is this substep's (center, v_b, angle, omega) from
+    collider_path."""
     if motion is not None:
         return motion
-    vb = torch.tensor(env.collider.velocity, dtype=DT)
-    return torch.tensor(env.collider.center, dtype=DT) + t * vb, vb
+    box = env.collider
+    vb = torch.tensor(box.velocity, dtype=DT)
+    om = torch.tensor(box.omega, dtype=DT)
+    return torch.tensor(box.center, dtype=DT) + t * vb, vb, box.angle + t * om, om
 
 
-def collider_path(env: Env, vel):
-    """Centers of a box driven by per-substep velocities vel [S, 3] (the actions):
-    the center during substep k is c0 + dt sum_{j<k} vel_j."""
+def collider_path(env: Env, vel, omega=None):
+    """Centers (and angles) of a box driven by per-substep velocities vel [S, 3]
+    and angular speeds omega [S] (the actions): during substep k the center is
+    c0 + dt sum_{j<k} vel_j and the angle angle0 + dt sum_{j<k} omega_j."""
     c0 = torch.tensor(env.collider.center, dtype=DT)
     steps = torch.cat([torch.zeros(1, 3, dtype=vel.dtype), env.dt * vel[:-1]], 0)
-    return c0 + torch.cumsum(steps, 0)
+    centers = c0 + torch.cumsum(steps, 0)
+    if omega is None:
+        return centers
+    ast = torch.cat([torch.zeros(1, dtype=omega.dtype), env.dt * omega[:-1]], 0)
+    return centers, env.collider.angle + torch.cumsum(ast, 0)
 
 
 def grid_update(env: Env, gm, gP, t: float, motion=None):
@@ -411,8 +443,8 @@ def grid_update(env: Env, gm, gP, t: float, motion=None):
     msafe = torch.where(pos, gm, torch.ones_like(gm))
     v = torch.where(pos[:, None], gP / msafe[:, None] + env.dt * g, torch.zeros_like(gP))
     if env.collider is not None:
-        center, vb = collider_motion(env, t, motion)
-        v = collide(env, v, center, vb, pos)
+        center, vb, theta, om = collider_motion(env, t, motion)
+        v = collide(env, v, center, vb, pos, theta, om)
     wm = wall_mask(env.n, env.wall)
     return torch.where(wm[:, None], torch.zeros_like(v), v)
 
@@ -440,20 +472,31 @@ def substep(env: Env, prm, x, v, C, F, t: float, motion=None):
     return xn, vn, Cn, Fn, bool(oob.any().item())
 
 
-def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=None):
+def motion_path(env: Env, vel, omega=None):
+    """Per-substep (center, velocity, angle, angular speed) of a box driven by
+    actions: velocities vel [>= S, 3] and angular speeds omega [>= S] (None: the
+    box's constant angular speed)."""
+    if omega is None:
+        omega = torch.full((vel.shape[0],), float(env.collider.omega), dtype=vel.dtype)
+    centers, angles = collider_path(env, vel, omega)
+    return centers, angles, omega
+
+
+def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=None, omega=None):
     """Run S substeps; returns the final state (and every state if keep_all).
 
-    ``vel`` [>= S, 3]: per-substep collider velocities (actions) of a box whose
-    path starts at its configured center at the first substep (t0 = 0)."""
+    ``vel`` [>= S, 3] and ``omega`` [>= S]: per-substep collider velocities and
+    angular speeds (actions) of a box whose path starts at its configured
+    center and angle at the first substep (t0 = 0)."""
     x, v, C, F = state
     states = [state]
     any_oob = False
     path = None
     if vel is not None:
         assert t0 == 0.0 and env.collider is not None
-        path = collider_path(env, vel)
+        path = motion_path(env, vel, omega)
     for k in range(S):
-        motion = None if path is None else (path[k], vel[k])
+        motion = None if path is None else (path[0][k], vel[k], path[1][k], path[2][k])
         x, v, C, F, oob = substep(env, prm, x, v, C, F, t0 + k * env.dt, motion)
         any_oob |= oob
         if keep_all:
@@ -463,7 +506,7 @@ def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=N
     return (x, v, C, F), any_oob
 
 
-def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None):
+def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None, omega=None):
     """Reverse-mode cotangents of the initial state and of the 7 parameters.
 
     ``cot`` = (x_bar, v_bar, C_bar, F_bar) of the final state (None entries = 0).
@@ -472,22 +515,27 @@ def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None):
     motion ``vel`` it also returns the cotangents of the velocities [S, 3] and
     of the box's starting center [3]: each substep yields those of its own
     (center_k, v_k), and center_k = c0 + dt sum_{j<k} vel_j passes its part to
-    every earlier velocity and to c0.
+    every earlier velocity and to c0. With angular speeds ``omega`` as well it
+    further returns those of omega [S] and of the starting angle, by the same
+    chain through angle_k = angle0 + dt sum_{j<k} omega_j.
     """
     with torch.no_grad():
-        states, _ = rollout(env, prm, state, S, t0, keep_all=True, vel=vel)
-        path = None if vel is None else collider_path(env, vel)
+        states, _ = rollout(env, prm, state, S, t0, keep_all=True, vel=vel, omega=omega)
+        path = None if vel is None else motion_path(env, vel, omega)
     g = [torch.zeros_like(s) if c is None else c.to(DT) for s, c in zip(state, cot)]
     gprm = torch.zeros_like(prm)
     gcen = torch.zeros(S, 3, dtype=DT)
     gvb = torch.zeros(S, 3, dtype=DT)
+    gang = torch.zeros(S, dtype=DT)
+    gom = torch.zeros(S, dtype=DT)
     for k in reversed(range(S)):
         s_in = [s.detach().clone().requires_grad_(True) for s in states[k]]
         p_in = prm.detach().clone().requires_grad_(True)
         leaves = s_in + [p_in]
         motion = None
         if path is not None:
-            motion = (path[k].detach().clone().requires_grad_(True), vel[k].detach().clone().requires_grad_(True))
+            motion = tuple(a.detach().clone().requires_grad_(True)
+                           for a in (path[0][k], vel[k], path[1][k], path[2][k]))
             leaves = leaves + list(motion)
         with torch.enable_grad():
             out = substep(env, p_in, *s_in, t0 + k * env.dt, motion)[:4]
@@ -496,30 +544,35 @@ def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None):
         if grads[4] is not None:
             gprm = gprm + grads[4]
         if path is not None:
-            if grads[5] is not None:
-                gcen[k] = grads[5]
-            if grads[6] is not None:
-                gvb[k] = grads[6]
+            for dst, gr in zip((gcen, gvb, gang, gom), grads[5:]):
+                if gr is not None:
+                    dst[k] = gr
     if vel is None:
         return tuple(g), gprm
     later = torch.flip(torch.cumsum(torch.flip(gcen, [0]), 0), [0]) - gcen   # sum over k > j
     gvel = gvb + env.dt * later
-    return tuple(g), gprm, gvel, gcen.sum(0)
+    if omega is None:
+        return tuple(g), gprm, gvel, gcen.sum(0)
+    later_a = torch.flip(torch.cumsum(torch.flip(gang, [0]), 0), [0]) - gang
+    return tuple(g), gprm, gvel, gcen.sum(0), gom + env.dt * later_a, gang.sum()
 
 
-def rollout_jvp(env: Env, prm, state, S: int, tangent, prm_tangent, t0: float = 0.0, vel=None, vel_tangent=None):
+def rollout_jvp(env: Env, prm, state, S: int, tangent, prm_tangent, t0: float = 0.0, vel=None, vel_tangent=None,
+                omega=None, omega_tangent=None):
     """Forward-mode tangent of the final state (dual numbers through the same forward)."""
     import torch.autograd.forward_ad as fwAD
     with torch.no_grad(), fwAD.dual_level():
         st = [fwAD.make_dual(s, ts) for s, ts in zip(state, tangent)]
         p = fwAD.make_dual(prm, prm_tangent)
-        path = vv = None
+        path = vv = om = None
         if vel is not None:
             vv = fwAD.make_dual(vel, vel_tangent if vel_tangent is not None else torch.zeros_like(vel))
-            path = collider_path(env, vv)
+            if omega is not None:
+                om = fwAD.make_dual(omega, omega_tangent if omega_tangent is not None else torch.zeros_like(omega))
+            path = motion_path(env, vv, om)
         x, v, C, F = st
         for k in range(S):
-            motion = None if path is None else (path[k], vv[k])
+            motion = None if path is None else (path[0][k], vv[k], path[1][k], path[2][k])
             x, v, C, F, _ = substep(env, p, x, v, C, F, t0 + k * env.dt, motion)
         return tuple(fwAD.unpack_dual(a).tangent for a in (x, v, C, F))
 

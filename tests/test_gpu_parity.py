@@ -153,7 +153,7 @@ def test_edge_box_has_sliding_edge_nodes():
     env, prm, (x, v, C, F) = O.env_from_spec(spec)
     gm, gP, _ = O.p2g(env, prm, x, v, C, F)
     pos = gm > 0
-    center, vb = O.collider_motion(env, 0.0)
+    center, vb = O.collider_motion(env, 0.0)[:2]
     rel = O.node_positions(env.n) - center
     q = rel.abs() - torch.tensor(env.collider.half, dtype=torch.float64)
     d, nh = O.box_sdf(O.node_positions(env.n), center, torch.tensor(env.collider.half, dtype=torch.float64))

@@ -383,12 +383,12 @@ def test_contact_projection_hand_values():
              ((1.0, 2.0, 0.0), (1.0, 2.0, 0.0))]         # separating: unchanged
     for vin, vout in cases:
         v[i_in] = torch.tensor(vin, dtype=DT)
-        out = O.collide(env, v, *O.collider_motion(env, 0.0), act)
+        out = O.collide(env, v, *O.collider_motion(env, 0.0)[:2], act)
         np.testing.assert_allclose(out[i_in].numpy(), vout, atol=1e-14)
     # a node outside at distance d: blend s = exp(-alpha d) of projected and free velocity
     i_out = int(((pos - torch.tensor([0.75, 0.5, 0.5], dtype=DT)).abs().sum(1)).argmin())  # d = 0.05
     v[i_out] = torch.tensor([-1.0, 0.2, 0.0], dtype=DT)
-    out = O.collide(env, v, *O.collider_motion(env, 0.0), act)
+    out = O.collide(env, v, *O.collider_motion(env, 0.0)[:2], act)
     s = math.exp(-32.0 * 0.05)
     np.testing.assert_allclose(out[i_out].numpy(), [(1 - s) * -1.0, (1 - s) * 0.2, 0.0], atol=1e-14)
 
@@ -707,3 +707,126 @@ def test_pair_distance_gradient_matches_central_differences():
         xm[i, c] -= h
         fd = (float(O.pair_distance(xp, p)) - float(O.pair_distance(xm, p))) / (2 * h)
         assert abs(fd - g[i, c]) < 1e-8
+
+
+# ---------------------------------------------------------------- a rotating box driven by angular-speed actions
+def test_rotation_matrix_hand_values():
+    R = O.rotation((0.0, 0.0, 1.0), math.pi / 2)
+    np.testing.assert_allclose(R.numpy() @ np.array([1.0, 0.0, 0.0]), [0.0, 1.0, 0.0], atol=1e-15)
+    a = np.array([1.0, 2.0, 2.0]) / 3.0
+    R = O.rotation(tuple(a), 0.7).numpy()
+    np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-15)
+    assert abs(np.linalg.det(R) - 1.0) < 1e-15
+    np.testing.assert_allclose(R @ a, a, atol=1e-15)          # the axis is fixed
+    np.testing.assert_allclose(R.trace(), 1.0 + 2.0 * math.cos(0.7), atol=1e-15)   # rotation angle
+
+
+def test_quarter_turned_box_is_the_axis_swapped_box():
+    # a box turned by pi/2 about z is the axis-aligned box with its x and y half extents swapped:
+    # same contact result at every node (nodes with ties between faces excluded: their normal picks
+    # a face by index, which the turn relabels)
+    n = 16
+    turned = O.Box(center=(0.5, 0.5, 0.5), half=(0.1, 0.2, 0.15), velocity=(0.0, 0.0, 0.0), alpha=2.0 * n,
+                   mu_b=0.5, angle=math.pi / 2)
+    plain = O.Box(center=(0.5, 0.5, 0.5), half=(0.2, 0.1, 0.15), velocity=(0.0, 0.0, 0.0), alpha=2.0 * n, mu_b=0.5)
+    rng = np.random.default_rng(5)
+    v = torch.from_numpy(rng.standard_normal((n ** 3, 3)))
+    act = torch.ones(n ** 3, dtype=torch.bool)
+    rel = O.node_positions(n) - 0.5
+    q = rel.abs() - torch.tensor([0.2, 0.1, 0.15], dtype=DT)
+    top2 = q.topk(2, dim=1).values
+    # also excluded: nodes on a symmetry plane (a zero component of x - c), where the side of the
+    # normal is a convention that rounding of the turned frame (cos(pi/2) ~ 6e-17) can flip
+    clear = ((top2[:, 0] - top2[:, 1]).abs() > 1e-9) & (rel.abs().min(dim=1).values > 1e-9)
+    outs = []
+    for box in (turned, plain):
+        env = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=box)
+        c, vb, th, om = O.collider_motion(env, 0.0)
+        outs.append(O.collide(env, v, c, vb, act, th, om))
+    np.testing.assert_allclose(outs[0][clear].numpy(), outs[1][clear].numpy(), atol=1e-12)
+    assert int(clear.sum()) > 0.75 * n ** 3
+
+
+def test_spinning_box_drags_nodes_inside_with_its_surface_velocity():
+    # a node inside the box (s = 1) that sticks takes the box's velocity at that point, v_b + omega a x (x - c)
+    n = 16
+    box = O.Box(center=(0.5, 0.5, 0.5), half=(0.2, 0.2, 0.2), velocity=(0.1, 0.0, 0.0), alpha=2.0 * n, mu_b=10.0,
+                axis=(0.0, 0.0, 1.0), angle=0.3, omega=4.0)
+    env = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=box)
+    pos = O.node_positions(n)
+    i = int(((pos - torch.tensor([0.5625, 0.4375, 0.5], dtype=DT)).abs().sum(1)).argmin())
+    v = torch.zeros(n ** 3, 3, dtype=DT)
+    c, vb, th, om = O.collider_motion(env, 0.0)
+    r = pos[i] - c
+    vs = np.array([0.1, 0.0, 0.0]) + 4.0 * np.cross([0.0, 0.0, 1.0], r.numpy())
+    d, nh = O.box_sdf(((pos - c) @ O.rotation(box.axis, th))[i:i + 1], torch.zeros(3, dtype=DT),
+                      torch.tensor(box.half, dtype=DT))
+    nw = (nh @ O.rotation(box.axis, th).T)[0].numpy()
+    v[i] = torch.from_numpy(vs - 0.5 * nw)     # moving into the box along its normal: sticks (mu_b large)
+    out = O.collide(env, v, c, vb, torch.ones(n ** 3, dtype=torch.bool), th, om)
+    assert float(d[0]) < 0
+    np.testing.assert_allclose(out[i].numpy(), vs, atol=1e-14)
+
+
+def _spinning_box(S, seed):
+    import dataclasses
+    env, prm, st = tiny(O.FLUID_TAIT, collider=True)
+    env = dataclasses.replace(env, collider=dataclasses.replace(env.collider, center=(0.6, 0.45, 0.45),
+                                                                half=(0.05, 0.12, 0.2), axis=(0.0, 0.6, 0.8),
+                                                                angle=0.4, omega=6.0, mu_b=0.3))
+    rng = np.random.default_rng(seed)
+    vel = torch.tensor(env.collider.velocity, dtype=DT) + 0.2 * torch.from_numpy(rng.standard_normal((S, 3)))
+    om = 6.0 + 3.0 * torch.from_numpy(rng.standard_normal(S))
+    return env, prm, st, vel, om
+
+
+def test_constant_angular_actions_reproduce_the_spinning_box():
+    env, prm, st, vel, _ = _spinning_box(4, seed=50)
+    vel = torch.tensor(env.collider.velocity, dtype=DT).expand(4, 3).clone()
+    a, _ = O.rollout(env, prm, st, 4)
+    b, _ = O.rollout(env, prm, st, 4, vel=vel, omega=torch.full((4,), env.collider.omega, dtype=DT))
+    for u, w in zip(a, b):
+        np.testing.assert_allclose(u.numpy(), w.numpy(), rtol=0, atol=1e-12)
+    c, ang = O.collider_path(env, vel, torch.full((4,), 6.0, dtype=DT))
+    np.testing.assert_allclose(ang.numpy(), 0.4 + 6.0 * env.dt * np.arange(4), rtol=0, atol=1e-15)
+
+
+def test_spin_actually_matters():
+    env, prm, st, vel, om = _spinning_box(3, seed=51)
+    a, _ = O.rollout(env, prm, st, 3, vel=vel, omega=om)
+    b, _ = O.rollout(env, prm, st, 3, vel=vel, omega=om + 5.0)
+    assert (a[1] - b[1]).abs().max().item() > 1e-4
+
+
+def test_angular_action_gradients_match_forward_mode_and_central_differences():
+    import dataclasses
+    S = 3
+    env, prm, st, vel, om = _spinning_box(S, seed=52)
+    rng = np.random.default_rng(53)
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp, gvel, gc0, gom, gang0 = O.rollout_vjp(env, prm, st, S, cot, vel=vel, omega=om)
+    assert gom.abs().max().item() > 0 and abs(gang0.item()) > 0
+    zero = [torch.zeros_like(s) for s in st]
+    for _ in range(3):
+        tv = torch.from_numpy(rng.standard_normal((S, 3)))
+        to = torch.from_numpy(rng.standard_normal(S))
+        out = O.rollout_jvp(env, prm, st, S, zero, torch.zeros(7, dtype=DT), vel=vel, vel_tangent=tv, omega=om,
+                            omega_tangent=to)
+        lhs = sum((a * b).sum() for a, b in zip(out, cot)).item()
+        rhs = (gvel * tv).sum().item() + (gom * to).sum().item()
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs)), (lhs, rhs)
+
+    def loss(o=om, ang=None):
+        e = env if ang is None else dataclasses.replace(env, collider=dataclasses.replace(env.collider, angle=ang))
+        (x, v, C, F), _ = O.rollout(e, prm, st, S, vel=vel, omega=o)
+        return sum((a * b).sum() for a, b in zip((x, v, C, F), cot)).item()
+
+    h = 1e-6
+    for k in range(S):
+        op, omm = om.clone(), om.clone()
+        op[k] += h
+        omm[k] -= h
+        fd = (loss(op) - loss(omm)) / (2 * h)
+        assert abs(fd - gom[k].item()) <= 1e-5 * max(1.0, abs(fd)), (k, fd, gom[k].item())
+    fd = (loss(ang=env.collider.angle + h) - loss(ang=env.collider.angle - h)) / (2 * h)
+    assert abs(fd - gang0.item()) <= 1e-5 * max(1.0, abs(fd)), (fd, gang0.item())

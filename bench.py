@@ -86,6 +86,8 @@ def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
         return f"{symbol}<{384 if tuned['BOX'] else 1024}, {mat}>"
     n_items = sum(-(-e.n_particles // 256) for e in envs)
     persist = "true" if 0 < tuned["GRID_CAP"] < n_items else "false"
+    if symbol.endswith("_pull"):   # the pull scatters' larger box budgets
+        return f"{symbol}<{persist}, {1024 if tuned['BOX'] else 2048}, {mat}>"
     return f"{symbol}<{persist}, {384 if tuned['BOX'] else 1024}, {mat}>"
 
 

@@ -146,9 +146,9 @@ MD int box_index(const Box& bx, int i, int j, int k) {
 MD int box_index_run(const BoxShared& bs, int r, int i, int j, int k) {
   return bs.off[r] + ((i - bs.lo[r][0]) * bs.ext[r][1] + (j - bs.lo[r][1])) * bs.ext[r][2] + (k - bs.lo[r][2]);
 }
-// quotient of 0 <= a < 2048 by 1 <= d <= 1024 (box nodes never exceed 1024)
-// from a float reciprocal of d: (a + 1/2) / d lies at least 1/(2d) inside
-// (q, q + 1), and the product's rounding stays below 2048 * 2^-23
+// quotient of 0 <= a < 2^21 by d >= 1 from a float reciprocal of d: (a + 1/2) / d
+// lies at least 1/(2d) inside (q, q + 1), and the two roundings (of 1/d and of
+// the product) move it by less than (a + 1/2) / d * 2^-23 < 1/(2d)
 MD int small_div(int a, float inv_d) { return (int)(((float)a + 0.5f) * inv_d); }
 
 MD void box_node(const BoxShared& bs, int idx, int& i, int& j, int& k) {
@@ -294,6 +294,12 @@ MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
 // affine form of both scatters), plus W(o) * mass for the mass channel.
 // ----------------------------------------------------------------------------
 constexpr int kPayload = 16;   // floats per particle: f (3), base z (int bits), g (3), A (9, row-major)
+// box budgets (grid nodes per block) of the pull scatters: their LDS holds one
+// int per base cell, not the box's channels, so a block covers more of the
+// grid before it falls back to global atomics (at ~1 particle per cell a
+// block's boxes average ~850 nodes and a few percent exceed 1024)
+constexpr int kPullNodes = 2048;
+constexpr int kPullSmall = 1024;
 
 // block-wide inclusive prefix sum of a[0, n) in place (every thread calls it)
 MD void block_scan_inclusive(int* a, int n, int* wtot) {
@@ -786,16 +792,17 @@ __global__ void __launch_bounds__(256) k_g2p_adjoint_lds(const float* __restrict
   }
 }
 
-// G2P adjoint through the pull scatter: the gather of v stays LDS-staged;
-// each particle writes (vbar', D4 dx Cbar, f) to LDS and the owner of each box
-// node sums its cotangent W (vbar' + D4 Cbar d) and adds it to the grid once
+// G2P adjoint through the pull scatter: v is gathered from the grid directly
+// (the LDS holds the payloads and the cell index, whose box budget is larger
+// than the staged kernels'); each particle writes (vbar', D4 dx Cbar, f) to
+// LDS and the owner of each box node sums its cotangent W (vbar' + D4 Cbar d)
+// and adds it to the grid once
 template <int BOXN, int MAT>
 MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const float* __restrict__ st_next,
                               const float* __restrict__ cot, float* __restrict__ part, int64_t N,
                               const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                               const float* __restrict__ grid, float* __restrict__ gcot, double* __restrict__ pacc,
                               int k_call) {
-  __shared__ float lv[3 * BOXN];
   __shared__ BoxShared bsh;
   __shared__ PullShared<BOXN> ps;
   const WorkItem it = items[item_idx];
@@ -809,8 +816,6 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
-  if (bx.fits) box_load(e, bx, bsh, grid, 4, 3, lv);
-  __syncthreads();
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
     const M3 H = ld_m3(st, N, p, 15);
@@ -855,16 +860,10 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
           const float d2 = ((float)oz - sc.f[2]) * e.dx;
           float vi[3], gv[3];
           for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
-          if (bx.fits) {
-            const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) vi[a] = lv[a * bx.nodes + idx];
-          } else {
-            const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            for (int a = 0; a < 3; ++a) {
-              vi[a] = grid[nb + (4 + a) * CH];
-              atomicAdd(gcot + nb + a * CH, W * gv[a]);
-            }
-          }
+          const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          for (int a = 0; a < 3; ++a) vi[a] = grid[nb + (4 + a) * CH];
+          if (!bx.fits)
+            for (int a = 0; a < 3; ++a) atomicAdd(gcot + nb + a * CH, W * gv[a]);
           const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
           for (int a = 0; a < 3; ++a) {
             xb[a] = fmaf(gW[a], vg, xb[a]);
@@ -2073,18 +2072,18 @@ void launch_p2g_pull(const float* st, int64_t N, const EnvDev* envs, const WorkI
                      uint32_t* flags, int32_t* errs, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
   if (n_items == 0) return;
   if (box)
-    launch_p2g_pull_m<kBoxSmall>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+    launch_p2g_pull_m<kPullSmall>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
   else
-    launch_p2g_pull_m<kBoxNodes>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
+    launch_p2g_pull_m<kPullNodes>(st, N, envs, items, n_items, grid, flags, errs, k_call, grid_cap, s, mat);
 }
 void launch_g2p_adjoint_pull(const float* st, const float* st_next, const float* cot, float* part, int64_t N,
                              const EnvDev* envs, const WorkItem* items, int n_items, const float* grid, float* gcot,
                              double* pacc, int k_call, int grid_cap, int box, int mat, hipStream_t s) {
   if (n_items == 0) return;
   if (box)
-    launch_g2p_adjoint_pull_m<kBoxSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
+    launch_g2p_adjoint_pull_m<kPullSmall>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
   else
-    launch_g2p_adjoint_pull_m<kBoxNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
+    launch_g2p_adjoint_pull_m<kPullNodes>(st, st_next, cot, part, N, envs, items, n_items, grid, gcot, pacc, k_call, grid_cap, s, mat);
 }
 template <int BOXN, int MAT>
 static void launch_p2g_adjoint_lds_t(const float* st, const float* part, float* cot_out, int64_t N, const EnvDev* envs,

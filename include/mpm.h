@@ -141,26 +141,42 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
 int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const float half[3], const float vel[3],
                          float alpha, float mu_b);
 
-/* Drives env's box collider by per-substep velocities instead of its constant
- * one: the actions of the paper's manipulation tasks move rigid bodies through
- * the scene (Section 5 task descriptions; contact of Appendix D.3). vel is a
- * HOST array [n][3] (m/s): during substep k (counted from the last
- * mpm_set_particles of this env) the box moves at vel[k] and its centre is
- * center + dt sum_{j<k} vel[j], with `center` as given to mpm_set_box_collider
- * (accumulated in FP64, stored as FP32). n = 0 (or vel = NULL) returns to the
- * constant velocity. A forward past substep n - 1 fails with INVALID_ARG.
- * Setting the collider again clears the motion. Copies vel; synchronizes the
- * stream. Errors: INVALID_ARG (env out of range, n outside [0, max_substeps],
- * no collider), NONFINITE. */
-int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t n);
+/* Lets env's box (env = -1: every env's) rotate about a fixed axis through its
+ * centre: the tools and hands of the paper's manipulation tasks turn as well
+ * as translate (Section 5 task descriptions; contact of Appendix D.3). The box
+ * is axis-aligned in its own frame, turned by `angle` (rad) about the unit
+ * `axis` (HOST [3], normalized here) at t = 0 and spinning at `omega` (rad/s):
+ * a node's distance and normal are taken in the box's frame, and the box
+ * surface at a node x moves at vel + omega axis x (x - c). Call after
+ * mpm_set_box_collider (which resets the rotation to none); clears any
+ * prescribed motion. Errors: INVALID_ARG (no collider, zero axis, non-finite). */
+int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float angle, float omega);
+
+/* Drives env's box collider by per-substep velocities and angular speeds
+ * instead of its constant ones: the actions of the paper's manipulation tasks
+ * move rigid bodies through the scene (Section 5 task descriptions; contact
+ * of Appendix D.3). vel is a HOST array [n][3] (m/s), omega a HOST array [n]
+ * (rad/s) or NULL (the box's constant angular speed): during substep k
+ * (counted from the last mpm_set_particles of this env) the box moves at
+ * vel[k] and spins at omega[k], its centre is center + dt sum_{j<k} vel[j] and
+ * its angle angle0 + dt sum_{j<k} omega[j], with `center` as given to
+ * mpm_set_box_collider and angle0 to mpm_set_box_rotation (accumulated in
+ * FP64, stored as FP32). n = 0 (or vel = NULL) returns to the constant
+ * motion. A forward past substep n - 1 fails with INVALID_ARG. Setting the
+ * collider or its rotation again clears the motion. Copies the arrays;
+ * synchronizes the stream. Errors: INVALID_ARG (env out of range, n outside
+ * [0, max_substeps], no collider), NONFINITE. */
+int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const float* omega, int32_t n);
 
 /* After mpm_backward: cotangents of the loss with respect to env's collider
- * velocities and starting centre. dvel: HOST [n][3] doubles (n <= the motion
- * length), dc0: HOST [3] doubles; either may be NULL. Includes every path:
- * the velocity's direct part in the contact and its effect on all later
- * centres (dt each). Synchronizes the stream. Errors: BAD_STATE if env has no
- * prescribed motion, INVALID_ARG. */
-int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, int32_t n);
+ * velocities, starting centre, angular speeds and starting angle. dvel: HOST
+ * [n][3] doubles (n <= the motion length), dc0: HOST [3], domega: HOST [n],
+ * dangle0: HOST [1]; any may be NULL. Includes every path: an action's direct
+ * part in the contact and its effect on all later centres or angles (dt
+ * each). Synchronizes the stream. Errors: BAD_STATE if env has no prescribed
+ * motion, INVALID_ARG. */
+int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, double* domega, double* dangle0,
+                          int32_t n);
 
 #define MPM_MOMENTS 20   /* stride of one env's moments */
 

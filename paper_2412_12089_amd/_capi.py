@@ -38,7 +38,7 @@ EXPORTED = (
     "mpm_get_collider_grad", "mpm_moments", "mpm_moments_vjp",
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
-    "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp",
+    "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp", "mpm_set_box_rotation",
 )
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
@@ -134,8 +134,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_get_option": (I32, [VP, I32, P(I32)]),
         "mpm_forward_envs": (I32, [VP, P(I32), I32]),
         "mpm_configure_env": (I32, [VP, I32, P(mpm_env_desc)]),
-        "mpm_set_collider_motion": (I32, [VP, I32, F3, I32]),
-        "mpm_get_collider_grad": (I32, [VP, I32, D8, D8, I32]),
+        "mpm_set_collider_motion": (I32, [VP, I32, F3, F3, I32]),
+        "mpm_get_collider_grad": (I32, [VP, I32, D8, D8, D8, D8, I32]),
+        "mpm_set_box_rotation": (I32, [VP, I32, F3, ctypes.c_float, ctypes.c_float]),
         "mpm_moments": (I32, [VP, VP, VP, VP, VP]),
         "mpm_moments_vjp": (I32, [VP, VP, VP, VP, VP, VP, VP]),
         "mpm_server_create": (I32, [P(mpm_server_desc), P(mpm_allocator), VP, P(VP)]),

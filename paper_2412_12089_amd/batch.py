@@ -82,8 +82,7 @@ class Batch:
         for i, e in enumerate(self.envs):
             self.set_material(i, e.material, e.params())
             if e.collider is not None:
-                c = e.collider
-                self.set_box_collider(i, c.center, c.half, c.velocity, c.alpha, c.mu_b)
+                self.set_collider(i, e.collider)
 
     # -- lifetime
     def close(self):
@@ -112,15 +111,32 @@ class Batch:
         self._chk(self.lib.mpm_set_box_collider(self.h, env, f3(center), f3(half), f3(velocity),
                                                 float(alpha), float(mu_b)), "mpm_set_box_collider")
 
-    def set_collider_motion(self, env: int, vel) -> None:
-        """Per-substep box velocities [n, 3] (the actions); None or empty clears them."""
+    def set_box_rotation(self, env: int, axis, angle: float, omega: float) -> None:
+        self.record_token += 1   # the library drops its recorded tape
+        f3 = (ctypes.c_float * 3)(*[float(x) for x in axis])
+        self._chk(self.lib.mpm_set_box_rotation(self.h, env, f3, float(angle), float(omega)), "mpm_set_box_rotation")
+
+    def set_collider(self, env: int, c, center=None, angle=None) -> None:
+        """The box collider c (scenes.BoxCollider) of env, optionally with another start center / angle."""
+        self.set_box_collider(env, c.center if center is None else center, c.half, c.velocity, c.alpha, c.mu_b)
+        if c.rotates or angle is not None:
+            self.set_box_rotation(env, c.axis, c.angle if angle is None else angle, c.omega)
+
+    def set_collider_motion(self, env: int, vel, omega=None) -> None:
+        """Per-substep box velocities [n, 3] and angular speeds [n] (None: the box's constant one),
+        the actions; vel None or empty clears them."""
         self.record_token += 1   # the library drops its recorded tape
         if vel is None or len(vel) == 0:
-            self._chk(self.lib.mpm_set_collider_motion(self.h, env, None, 0), "mpm_set_collider_motion")
+            self._chk(self.lib.mpm_set_collider_motion(self.h, env, None, None, 0), "mpm_set_collider_motion")
             return
         v = np.ascontiguousarray(np.asarray(vel, dtype=np.float32).reshape(-1, 3))
         buf = v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        self._chk(self.lib.mpm_set_collider_motion(self.h, env, buf, v.shape[0]), "mpm_set_collider_motion")
+        ob = None
+        if omega is not None:
+            o = np.ascontiguousarray(np.asarray(omega, dtype=np.float32).reshape(-1))
+            assert o.shape[0] == v.shape[0]
+            ob = o.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._chk(self.lib.mpm_set_collider_motion(self.h, env, buf, ob, v.shape[0]), "mpm_set_collider_motion")
 
     def moments(self, x, v, w=None):
         """Per-env weighted moments [E, 20] float64 of caller-order x, v (device)."""
@@ -159,14 +175,18 @@ class Batch:
                                                  C.ptr(g), C.ptr(gx)), "mpm_pair_distance_vjp")
         return gx
 
-    def collider_grad(self, env: int, n: int):
-        """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64."""
+    def collider_grad(self, env: int, n: int, spin: bool = False):
+        """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64, and with spin=True also
+        (dL/domega [n], dL/dangle0)."""
         dvel = np.zeros((n, 3), np.float64)
         dc0 = np.zeros(3, np.float64)
+        dom = np.zeros(n, np.float64)
+        dang = np.zeros(1, np.float64)
         P = ctypes.POINTER(ctypes.c_double)
-        self._chk(self.lib.mpm_get_collider_grad(self.h, env, dvel.ctypes.data_as(P), dc0.ctypes.data_as(P), n),
+        self._chk(self.lib.mpm_get_collider_grad(self.h, env, dvel.ctypes.data_as(P), dc0.ctypes.data_as(P),
+                                                 dom.ctypes.data_as(P), dang.ctypes.data_as(P), n),
                   "mpm_get_collider_grad")
-        return dvel, dc0
+        return (dvel, dc0, dom, float(dang[0])) if spin else (dvel, dc0)
 
     # -- state
     def set_particles(self, x, v, Cm, F, env: int = -1) -> None:
@@ -216,8 +236,7 @@ class Batch:
         self.envs[env] = spec
         self.set_material(env, spec.material, spec.params())
         if spec.collider is not None:
-            c = spec.collider
-            self.set_box_collider(env, c.center, c.half, c.velocity, c.alpha, c.mu_b)
+            self.set_collider(env, spec.collider)
 
     def backward(self, gx=None, gv=None, gC=None, gF=None, want_params: bool = True):
         d = self.device
@@ -279,68 +298,75 @@ class Batch:
 
 
 class MPMRollout(torch.autograd.Function):
-    """s_S = f^S(s_0; params, actions, centers) through the library,
-    differentiable in s_0, params, actions and centers.
+    """s_S = f^S(s_0; params, actions, centers, spins) through the library,
+    differentiable in s_0, params, actions, centers and spins.
 
     params: [E, 8] float64 (E, nu, rho, Vp, sigma_y, K, gamma, 0) per env.
     actions: None or [E, S, 3] per-substep velocities of each env's box
-    collider; centers: None or [E, 3] the boxes' centers at the first substep
-    (default: the centers the envs were created with). Rows of envs without a
-    collider are ignored and get zero gradients. If the batch has been re-used
-    since this call's forward, the backward first re-runs the forward from the
-    saved inputs (frame-level checkpoint), so calls can be chained.
+    collider; spins: None or [E, S] per-substep angular speeds about the box's
+    axis (needs actions; default: the box's constant angular speed); centers:
+    None or [E, 3] the boxes' centers at the first substep (default: the
+    centers the envs were created with). Rows of envs without a collider are
+    ignored and get zero gradients. If the batch has been re-used since this
+    call's forward, the backward first re-runs the forward from the saved
+    inputs (frame-level checkpoint), so calls can be chained.
     """
 
     @staticmethod
-    def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions, centers):
+    def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions, centers, spins):
         prm = params.detach().to("cpu", torch.float64).numpy()
         for i, e in enumerate(batch.envs):
             batch.set_material(i, e.material, prm[i])
         if centers is not None:
             cen = centers.detach().to("cpu", torch.float64).numpy()
             for i, e in enumerate(batch.envs):
-                c = e.collider
-                if c is not None:
-                    batch.set_box_collider(i, cen[i], c.half, c.velocity, c.alpha, c.mu_b)
+                if e.collider is not None:
+                    batch.set_collider(i, e.collider, center=cen[i])
         if actions is not None:
             act = actions.detach().to("cpu", torch.float32).numpy()
+            spn = None if spins is None else spins.detach().to("cpu", torch.float32).numpy()
             for i, e in enumerate(batch.envs):
                 if e.collider is not None:
-                    batch.set_collider_motion(i, act[i, :n_substeps])
+                    batch.set_collider_motion(i, act[i, :n_substeps], None if spn is None else spn[i, :n_substeps])
         batch.set_particles(x, v, Cm, F)
         batch.forward(n_substeps, record=True)
 
     @staticmethod
-    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None):
-        MPMRollout._setup(batch, n_substeps, x, v, Cm, F, params, actions, centers)
+    def forward(ctx, batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None, spins=None):
+        if spins is not None and actions is None:
+            raise ValueError("spins need actions (a prescribed motion)")
+        MPMRollout._setup(batch, n_substeps, x, v, Cm, F, params, actions, centers, spins)
         ctx.batch = batch
         ctx.n_substeps = n_substeps
         ctx.token = batch.record_token
-        ctx.flags = (actions is not None, centers is not None)
+        ctx.flags = (actions is not None, centers is not None, spins is not None)
         empty = torch.empty(0)
         ctx.save_for_backward(x, v, Cm, F, params, actions if actions is not None else empty,
-                              centers if centers is not None else empty)
+                              centers if centers is not None else empty, spins if spins is not None else empty)
         return batch.get_particles()
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
         b = ctx.batch
-        x, v, Cm, F, params, actions, centers = ctx.saved_tensors
+        x, v, Cm, F, params, actions, centers, spins = ctx.saved_tensors
         actions = actions if ctx.flags[0] else None
         centers = centers if ctx.flags[1] else None
+        spins = spins if ctx.flags[2] else None
         if b.record_token != ctx.token:
-            MPMRollout._setup(b, ctx.n_substeps, x, v, Cm, F, params, actions, centers)
+            MPMRollout._setup(b, ctx.n_substeps, x, v, Cm, F, params, actions, centers, spins)
             ctx.token = b.record_token
         dx, dv, dC, dF, dp = b.backward(gx, gv, gC, gF)
-        da = dcen = None
+        da = dcen = dsp = None
         if actions is not None:
             da = torch.zeros(actions.shape, dtype=torch.float64)
             dcen = torch.zeros(b.E, 3, dtype=torch.float64)
+            dsp = torch.zeros(b.E, actions.shape[1], dtype=torch.float64)
             for i, e in enumerate(b.envs):
                 if e.collider is not None:
-                    dvel, dc0 = b.collider_grad(i, ctx.n_substeps)
+                    dvel, dc0, dom, _ = b.collider_grad(i, ctx.n_substeps, spin=True)
                     da[i, :ctx.n_substeps] = torch.from_numpy(dvel)
                     dcen[i] = torch.from_numpy(dc0)
+                    dsp[i, :ctx.n_substeps] = torch.from_numpy(dom)
             da = da.to(actions.device, actions.dtype)
         if centers is None:
             dcen = None
@@ -348,8 +374,9 @@ class MPMRollout(torch.autograd.Function):
             if dcen is None:   # a fixed-velocity box: the start center matters, its gradient is not computed
                 raise ValueError("gradients w.r.t. centers need actions (a prescribed motion)")
             dcen = dcen.to(centers.device, centers.dtype)
-        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da, dcen
+        dsp = None if spins is None else dsp[:, :spins.shape[1]].to(spins.device, spins.dtype)
+        return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da, dcen, dsp
 
 
-def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None):
-    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params, actions, centers)
+def rollout(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions=None, centers=None, spins=None):
+    return MPMRollout.apply(batch, n_substeps, x, v, Cm, F, params, actions, centers, spins)

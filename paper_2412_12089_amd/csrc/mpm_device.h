@@ -43,7 +43,13 @@ struct EnvDev {
   int64_t p_cap;                         // particle capacity (positions [p_off, p_off + p_cap))
   int32_t motion_off, motion_len;        // prescribed collider motion: rows [motion_off, + motion_len) of the
                                          // motion table, one per substep (len 0: constant velocity cv)
+  float c_axis[3];                       // box rotation: unit axis (world), angle at t = 0, constant angular
+  float c_angle, c_omega, c_pad;         // speed (the box is axis-aligned in its own frame)
 };
+
+// a row of the prescribed collider motion table: center (3), velocity (3),
+// angle about the box's axis, angular speed
+constexpr int kMotionRow = 8;
 
 // --------------------------------------------------------------------------
 // small vector / matrix helpers

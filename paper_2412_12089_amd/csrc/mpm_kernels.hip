@@ -457,20 +457,46 @@ MD void node_coords(const EnvDev& e, int64_t tile, int l, int& i, int& j, int& k
 }
 
 struct Contact {
-  float n[3];     // outward unit normal (gradient of the distance)
+  float n[3];     // outward unit normal (gradient of the distance), world frame
+  float nb[3];    // the same in the box's frame
+  float rb[3];    // node position relative to the center, box frame (R^T w)
+  float w[3];     // node position relative to the center, world frame
   float s;        // blend weight min(exp(-alpha d), 1)
   float d;        // signed distance
   float L;        // length of the outside part of (|rel| - half), 0 inside
   int pos;        // bit a set when component a of (|rel| - half) is positive
 };
 
-MD Contact contact_geometry(const EnvDev& e, const float c[3], int i, int j, int k) {
+// rotation by th about the box's unit axis a (Rodrigues): I + sin th K + (1 - cos th) K^2,
+// K = [a]x; exactly I at th = 0
+MD void box_rotation(const EnvDev& e, float th, float R[3][3]) {
+  float sn, cs;
+  sincosf(th, &sn, &cs);
+  const float oc = 1.f - cs;
+  const float* a = e.c_axis;
+  const float K[3][3] = {{0.f, -a[2], a[1]}, {a[2], 0.f, -a[0]}, {-a[1], a[0], 0.f}};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const float kk = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
+      R[r][c] = (r == c ? 1.f : 0.f) + sn * K[r][c] + oc * kk;
+    }
+}
+
+MD void cross3(const float a[3], const float b[3], float out[3]) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+MD Contact contact_geometry(const EnvDev& e, const float c[3], const float R[3][3], int i, int j, int k) {
   const float p[3] = {i * e.dx, j * e.dx, k * e.dx};
   float rel[3], q[3], qp[3];
   Contact ct;
   ct.pos = 0;
+  for (int a = 0; a < 3; ++a) ct.w[a] = p[a] - c[a];
   for (int a = 0; a < 3; ++a) {
-    rel[a] = p[a] - c[a];
+    rel[a] = R[0][a] * ct.w[0] + R[1][a] * ct.w[1] + R[2][a] * ct.w[2];
+    ct.rb[a] = rel[a];
     q[a] = fabsf(rel[a]) - e.ch[a];
     qp[a] = fmaxf(q[a], 0.f);
     if (q[a] > 0.f) ct.pos |= 1 << a;
@@ -480,11 +506,12 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], int i, int j, int
   ct.d = out_len + fminf(inside, 0.f);
   ct.L = out_len;
   if (out_len > 0.f) {
-    for (int a = 0; a < 3; ++a) ct.n[a] = (rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;
+    for (int a = 0; a < 3; ++a) ct.nb[a] = (rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;
   } else {
     const int ax = (q[0] >= q[1] && q[0] >= q[2]) ? 0 : (q[1] >= q[2] ? 1 : 2);
-    for (int a = 0; a < 3; ++a) ct.n[a] = (a == ax) ? (rel[a] >= 0.f ? 1.f : -1.f) : 0.f;
+    for (int a = 0; a < 3; ++a) ct.nb[a] = (a == ax) ? (rel[a] >= 0.f ? 1.f : -1.f) : 0.f;
   }
+  for (int a = 0; a < 3; ++a) ct.n[a] = R[a][0] * ct.nb[0] + R[a][1] * ct.nb[1] + R[a][2] * ct.nb[2];
   ct.s = fminf(expf(-e.c_alpha * ct.d), 1.f);
   return ct;
 }
@@ -493,17 +520,22 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], int i, int j, int
 // env's substep clock): a row of the prescribed motion table, or the constant
 // velocity from the center at t = 0
 MD void box_motion(const EnvDev& e, const float* __restrict__ motion, double t0, const int32_t* clock, int k_rel,
-                   float c[3], float vb[3], int& row) {
+                   float c[3], float vb[3], float& th, float& om, int& row) {
   row = -1;
   if (e.motion_len > 0) {
     int k = clock[0] + k_rel;
     k = k < 0 ? 0 : (k >= e.motion_len ? e.motion_len - 1 : k);
     row = e.motion_off + k;
-    for (int a = 0; a < 3; ++a) { c[a] = motion[6 * row + a]; vb[a] = motion[6 * row + 3 + a]; }
+    const float* m = motion + kMotionRow * (int64_t)row;
+    for (int a = 0; a < 3; ++a) { c[a] = m[a]; vb[a] = m[3 + a]; }
+    th = m[6];
+    om = m[7];
     return;
   }
   const float t = (float)(t0 + (double)(clock[0] + k_rel) * (double)e.dt);
   for (int a = 0; a < 3; ++a) { vb[a] = e.cv[a]; c[a] = fmaf(t, e.cv[a], e.cc[a]); }
+  th = fmaf(t, e.c_omega, e.c_angle);
+  om = e.c_omega;
 }
 
 // friction projection of the velocity relative to the box; returns the case (0 free, 1 stick, 2 slide)
@@ -547,14 +579,16 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
     v[1] = fmaf(g[2 * CH], inv, e.dt * e.gy);
     v[2] = fmaf(g[3 * CH], inv, e.dt * e.gz);
     if (e.has_collider) {
-      float bc[3], bv[3];
+      float bc[3], bv[3], th, om, R[3][3], spin[3];
       int row;
-      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, row);
-      const Contact c = contact_geometry(e, bc, i, j, k);
-      float u[3], up[3], ut[3], un, utn;
-      for (int a = 0; a < 3; ++a) u[a] = v[a] - bv[a];
+      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, th, om, row);
+      box_rotation(e, th, R);
+      const Contact c = contact_geometry(e, bc, R, i, j, k);
+      cross3(e.c_axis, c.w, spin);
+      float vs[3], u[3], up[3], ut[3], un, utn;   // vs: the box surface's velocity at the node
+      for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = v[a] - vs[a]; }
       contact_project(e, c, u, up, un, ut, utn);
-      for (int a = 0; a < 3; ++a) v[a] = c.s * (bv[a] + up[a]) + (1.f - c.s) * v[a];
+      for (int a = 0; a < 3; ++a) v[a] = c.s * (vs[a] + up[a]) + (1.f - c.s) * v[a];
     }
   }
   if (is_wall(e, i, j, k)) v[0] = v[1] = v[2] = 0.f;
@@ -589,17 +623,20 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   const float P[3] = {g[CH], g[2 * CH], g[3 * CH]};
   float vb[3] = {gc[0], gc[CH], gc[2 * CH]};   // cotangent of the node velocity
   float mb = 0.f, Pb[3] = {0.f, 0.f, 0.f};
-  float gmo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // cotangents of the box center (0-2) and velocity (3-5)
+  // cotangents of the box center (0-2), velocity (3-5), angle (6) and angular speed (7)
+  float gmo[kMotionRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int row = -1;
   if (!is_wall(e, i, j, k) && m > 0.f) {
     const float inv = 1.f / m;
     const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
     if (e.has_collider) {
-      float bc[3], bv[3];
-      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, row);
-      const Contact c = contact_geometry(e, bc, i, j, k);
-      float u[3], up[3], ut[3], un, utn;
-      for (int a = 0; a < 3; ++a) u[a] = vpre[a] - bv[a];
+      float bc[3], bv[3], th, om, R[3][3], spin[3];
+      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, th, om, row);
+      box_rotation(e, th, R);
+      const Contact c = contact_geometry(e, bc, R, i, j, k);
+      cross3(e.c_axis, c.w, spin);
+      float vs[3], u[3], up[3], ut[3], un, utn;
+      for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = vpre[a] - vs[a]; }
       const int kase = contact_project(e, c, u, up, un, ut, utn);
       float ub[3];
       float uh[3] = {0.f, 0.f, 0.f};
@@ -618,30 +655,49 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
         }
       }
       if (row >= 0) {
-        // v' = s (v_b + u') + (1 - s) v with u = v - v_b: the box velocity enters
-        // directly and through u; its center through s(d) and through n
-        float sbar = 0.f;
+        // v' = s (v_s + u') + (1 - s) v with u = v - v_s and the surface velocity
+        // v_s = v_b + omega a x w, w = x - c: v_b and omega enter through v_s; the
+        // center through s(d), through n and through w; the angle through s(d)
+        // and n, both functions of the box-frame position r = R^T w
+        float sbar = 0.f, vsb[3];
         for (int a = 0; a < 3; ++a) {
-          gmo[3 + a] = c.s * (vb[a] - ub[a]);
-          sbar += vb[a] * (bv[a] + up[a] - vpre[a]);
+          vsb[a] = c.s * (vb[a] - ub[a]);   // cotangent of v_s
+          gmo[3 + a] = vsb[a];
+          sbar += vb[a] * (vs[a] + up[a] - vpre[a]);
         }
-        if (c.d > 0.f)   // s = exp(-alpha d) below its cap; d(d)/d(center) = -n
-          for (int a = 0; a < 3; ++a) gmo[a] += sbar * e.c_alpha * c.s * c.n[a];
-        if (kase == 2 && __popc(c.pos) >= 2) {
-          // sliding: u' depends on n, and n = sgn (|rel| - h)^+ / L turns with the
-          // center near edges and corners: d n / d center = -(I_A - n n^T) / L
+        float axr[3], axv[3];
+        cross3(e.c_axis, c.rb, axr);        // d r / d angle = -a x r (a is fixed by the rotation)
+        cross3(e.c_axis, vsb, axv);
+        gmo[7] = vsb[0] * spin[0] + vsb[1] * spin[1] + vsb[2] * spin[2];
+        for (int a = 0; a < 3; ++a) gmo[a] += om * axv[a];
+        if (c.d > 0.f) {   // s = exp(-alpha d) below its cap; d(d)/d(center) = -n, d(d)/d(angle) = -nb . (a x r)
+          const float sa = sbar * e.c_alpha * c.s;
+          for (int a = 0; a < 3; ++a) gmo[a] += sa * c.n[a];
+          gmo[6] += sa * (c.nb[0] * axr[0] + c.nb[1] * axr[1] + c.nb[2] * axr[2]);
+        }
+        if (kase == 2) {
+          // sliding: u' depends on n = R nb(r). n turns rigidly with the angle
+          // (d n = a x n d angle), and nb = sgn (|r| - h)^+ / L turns with r near
+          // edges and corners: d nb / d r = (I_A - nb nb^T) / L
           float w[3], Pw[3];
           for (int a = 0; a < 3; ++a) w[a] = c.s * vb[a];
           const float wu = w[0] * uh[0] + w[1] * uh[1] + w[2] * uh[2];
           const float wn = w[0] * c.n[0] + w[1] * c.n[1] + w[2] * c.n[2];
           const float r = un / utn;
           for (int a = 0; a < 3; ++a) Pw[a] = w[a] - wu * uh[a];
-          float nb[3];
+          float nbar[3], axn[3];
           for (int a = 0; a < 3; ++a)
-            nb[a] = -(1.f + e.c_mu * r) * wn * u[a] - un * (w[a] + e.c_mu * r * Pw[a]) + e.c_mu * wu * u[a];
-          const float nn = c.n[0] * nb[0] + c.n[1] * nb[1] + c.n[2] * nb[2];
-          for (int a = 0; a < 3; ++a)
-            if (c.pos & (1 << a)) gmo[a] -= (nb[a] - c.n[a] * nn) / c.L;
+            nbar[a] = -(1.f + e.c_mu * r) * wn * u[a] - un * (w[a] + e.c_mu * r * Pw[a]) + e.c_mu * wu * u[a];
+          cross3(e.c_axis, c.n, axn);
+          gmo[6] += nbar[0] * axn[0] + nbar[1] * axn[1] + nbar[2] * axn[2];
+          if (__popc(c.pos) >= 2) {
+            float nbb[3], mm[3];
+            for (int a = 0; a < 3; ++a) nbb[a] = R[0][a] * nbar[0] + R[1][a] * nbar[1] + R[2][a] * nbar[2];
+            const float nn = c.nb[0] * nbb[0] + c.nb[1] * nbb[1] + c.nb[2] * nbb[2];
+            for (int a = 0; a < 3; ++a) mm[a] = (c.pos & (1 << a)) ? (nbb[a] - c.nb[a] * nn) / c.L : 0.f;
+            for (int a = 0; a < 3; ++a) gmo[a] -= R[a][0] * mm[0] + R[a][1] * mm[1] + R[a][2] * mm[2];
+            gmo[6] -= mm[0] * axr[0] + mm[1] * axr[1] + mm[2] * axr[2];
+          }
         }
       }
       for (int a = 0; a < 3; ++a) vb[a] = (1.f - c.s) * vb[a] + c.s * ub[a];
@@ -660,15 +716,16 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   // the wave is one tile of one env: sum its nodes' collider cotangents and add
   // them to this substep's row in FP64
   if (e.has_collider && e.motion_len > 0) {
-    const bool any = __ballot(row >= 0 && (gmo[0] != 0.f || gmo[1] != 0.f || gmo[2] != 0.f || gmo[3] != 0.f ||
-                                           gmo[4] != 0.f || gmo[5] != 0.f)) != 0ull;
+    bool nz = false;
+    for (int c = 0; c < kMotionRow; ++c) nz |= gmo[c] != 0.f;
+    const bool any = __ballot(row >= 0 && nz) != 0ull;
     if (any) {
       int rw = row;
       for (int off = 32; off > 0; off >>= 1) rw = max(rw, __shfl_xor(rw, off, 64));
-      for (int c = 0; c < 6; ++c) {
+      for (int c = 0; c < kMotionRow; ++c) {
         double x = (double)gmo[c];
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (l == 0 && x != 0.0) atomicAdd(&gmotion[6 * (int64_t)rw + c], x);
+        if (l == 0 && x != 0.0) atomicAdd(&gmotion[kMotionRow * (int64_t)rw + c], x);
       }
     }
   }

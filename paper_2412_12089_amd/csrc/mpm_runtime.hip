@@ -89,7 +89,7 @@ struct mpm_batch {
   int32_t* errs = nullptr;
   int32_t* clock = nullptr;       // [E] per-env substep clocks (collider motion time)
   int32_t* clock_rec = nullptr;   // [E] the clocks at the start of the recorded forward
-  float* motion_d = nullptr;     // prescribed collider motions: [E][max_substeps] rows (center, velocity)
+  float* motion_d = nullptr;     // prescribed collider motions: [E][max_substeps] rows of kMotionRow floats
   double* gmotion_d = nullptr;   // their cotangents, same layout, FP64
   std::vector<float> motion_h;
 
@@ -779,8 +779,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->errs = (int32_t*)A(sizeof(int32_t) * b->E);
   b->clock = (int32_t*)A(sizeof(int32_t) * b->E);
   b->clock_rec = (int32_t*)A(sizeof(int32_t) * b->E);
-  b->motion_d = (float*)A(sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
-  b->gmotion_d = (double*)A(sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
+  b->motion_d = (float*)A(sizeof(float) * kMotionRow * (size_t)b->E * b->max_substeps);
+  b->gmotion_d = (double*)A(sizeof(double) * kMotionRow * (size_t)b->E * b->max_substeps);
   if (!ok) {
     free_all(b);
     delete b;
@@ -801,8 +801,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     zero(b->errs, sizeof(int32_t) * b->E);
     zero(b->clock, sizeof(int32_t) * b->E);
     zero(b->clock_rec, sizeof(int32_t) * b->E);
-    zero(b->motion_d, sizeof(float) * 6 * (size_t)b->E * b->max_substeps);
-    zero(b->gmotion_d, sizeof(double) * 6 * (size_t)b->E * b->max_substeps);
+    zero(b->motion_d, sizeof(float) * kMotionRow * (size_t)b->E * b->max_substeps);
+    zero(b->gmotion_d, sizeof(double) * kMotionRow * (size_t)b->E * b->max_substeps);
     // identity ids and an F = I rest state until particles are set
     rc = upload_envs(b);
   } while (0);
@@ -917,13 +917,38 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const floa
       d.c_alpha = alpha;
       d.c_mu = mu_b;
     }
+    d.c_axis[0] = d.c_axis[1] = 0.f;   // no rotation until mpm_set_box_rotation
+    d.c_axis[2] = 1.f;
+    d.c_angle = d.c_omega = 0.f;
     d.motion_len = 0;   // a prescribed motion starts from the collider it was set for
   }
   b->recorded = false;
   return upload_envs(b);
 }
 
-int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t n) {
+int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float angle, float omega) {
+  if (!b) return MPM_INVALID_ARG;
+  int rc = check_env(b, env, true);
+  if (rc) return rc;
+  if (!axis) return fail(b, MPM_INVALID_ARG, "null axis");
+  const double len = std::sqrt((double)axis[0] * axis[0] + (double)axis[1] * axis[1] + (double)axis[2] * axis[2]);
+  if (!(len > 0.0) || !std::isfinite(len) || !std::isfinite(angle) || !std::isfinite(omega))
+    return fail(b, MPM_INVALID_ARG, "the axis must be nonzero and the values finite");
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
+  for (int e = e0; e < e1; ++e)
+    if (!b->envs_h[e].has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no collider");
+  for (int e = e0; e < e1; ++e) {
+    EnvDev& d = b->envs_h[e];
+    for (int a = 0; a < 3; ++a) d.c_axis[a] = (float)(axis[a] / len);
+    d.c_angle = angle;
+    d.c_omega = omega;
+    d.motion_len = 0;
+  }
+  b->recorded = false;
+  return upload_envs(b);
+}
+
+int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const float* omega, int32_t n) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, false);
   if (rc) return rc;
@@ -933,18 +958,26 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t
   if (n > 0 && !d.has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no collider");
   for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
     if (!std::isfinite(vel[i])) return fail(b, MPM_NONFINITE, "non-finite collider velocity");
+  for (int64_t i = 0; omega && i < (int64_t)n; ++i)
+    if (!std::isfinite(omega[i])) return fail(b, MPM_NONFINITE, "non-finite collider angular speed");
   if (n > 0) {
-    // center during substep k: c0 + dt sum_{j<k} vel_j, accumulated in FP64
-    b->motion_h.assign(6 * (size_t)n, 0.f);
-    double c[3] = {d.cc[0], d.cc[1], d.cc[2]};
+    // during substep k: center c0 + dt sum_{j<k} vel_j, angle angle0 + dt sum_{j<k}
+    // omega_j, both accumulated in FP64
+    constexpr int W = kMotionRow;
+    b->motion_h.assign(W * (size_t)n, 0.f);
+    double c[3] = {d.cc[0], d.cc[1], d.cc[2]}, th = d.c_angle;
     for (int k = 0; k < n; ++k) {
+      const double om = omega ? (double)omega[k] : (double)d.c_omega;
       for (int a = 0; a < 3; ++a) {
-        b->motion_h[6 * k + a] = (float)c[a];
-        b->motion_h[6 * k + 3 + a] = vel[3 * k + a];
+        b->motion_h[W * k + a] = (float)c[a];
+        b->motion_h[W * k + 3 + a] = vel[3 * k + a];
       }
+      b->motion_h[W * k + 6] = (float)th;
+      b->motion_h[W * k + 7] = (float)om;
       for (int a = 0; a < 3; ++a) c[a] += (double)d.dt * (double)vel[3 * k + a];
+      th += (double)d.dt * om;
     }
-    HIPC(b, hipMemcpyAsync(b->motion_d + 6 * (size_t)d.motion_off, b->motion_h.data(), sizeof(float) * 6 * (size_t)n,
+    HIPC(b, hipMemcpyAsync(b->motion_d + W * (size_t)d.motion_off, b->motion_h.data(), sizeof(float) * W * (size_t)n,
                            hipMemcpyHostToDevice, b->stream));
     HIPC(b, hipStreamSynchronize(b->stream));   // the host rows are reused by the next call
   }
@@ -953,7 +986,8 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, int32_t
   return upload_envs(b);
 }
 
-int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, int32_t n) {
+int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, double* domega, double* dangle0,
+                          int32_t n) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, false);
   if (rc) return rc;
@@ -961,20 +995,25 @@ int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, 
   if (d.motion_len == 0) return fail(b, MPM_BAD_STATE, "the environment has no prescribed collider motion");
   if (n < 0 || n > d.motion_len) return fail(b, MPM_INVALID_ARG, "n outside [0, motion length]");
   const int L = d.motion_len;
-  std::vector<double> g(6 * (size_t)L);
-  HIPC(b, hipMemcpyAsync(g.data(), b->gmotion_d + 6 * (size_t)d.motion_off, sizeof(double) * g.size(),
+  constexpr int W = kMotionRow;
+  std::vector<double> g(W * (size_t)L);
+  HIPC(b, hipMemcpyAsync(g.data(), b->gmotion_d + W * (size_t)d.motion_off, sizeof(double) * g.size(),
                          hipMemcpyDeviceToHost, b->stream));
   HIPC(b, hipStreamSynchronize(b->stream));
-  // row k holds the cotangents of (center_k, velocity_k); center_k depends on
-  // every earlier velocity (dt each) and on c0
-  double later[3] = {0.0, 0.0, 0.0};   // sum over k > j of the center cotangents
+  // row k holds the cotangents of (center_k, velocity_k, angle_k, omega_k);
+  // center_k depends on every earlier velocity (dt each) and on c0, angle_k on
+  // every earlier angular speed and on the starting angle
+  double later[3] = {0.0, 0.0, 0.0}, later_th = 0.0;   // sums over k > j of the center / angle cotangents
   for (int j = L - 1; j >= 0; --j) {
     if (j < n && dvel)
-      for (int a = 0; a < 3; ++a) dvel[3 * j + a] = g[6 * j + 3 + a] + (double)d.dt * later[a];
-    for (int a = 0; a < 3; ++a) later[a] += g[6 * j + a];
+      for (int a = 0; a < 3; ++a) dvel[3 * j + a] = g[W * j + 3 + a] + (double)d.dt * later[a];
+    if (j < n && domega) domega[j] = g[W * j + 7] + (double)d.dt * later_th;
+    for (int a = 0; a < 3; ++a) later[a] += g[W * j + a];
+    later_th += g[W * j + 6];
   }
   if (dc0)
     for (int a = 0; a < 3; ++a) dc0[a] = later[a];
+  if (dangle0) *dangle0 = later_th;
   return MPM_OK;
 }
 
@@ -1080,7 +1119,7 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
   const hipStream_t s = b->stream;
   if (b->timing) { b->spans.clear(); b->event_next = 0; }
   launch_fill_u32(b->pacc, 0u, 2 * 8 * (int64_t)b->E, s);
-  launch_fill_u32(b->gmotion_d, 0u, 2 * 6 * (int64_t)b->E * b->max_substeps, s);
+  launch_fill_u32(b->gmotion_d, 0u, 2 * kMotionRow * (int64_t)b->E * b->max_substeps, s);
   const int S = b->rec_S;
   const int nseg = (S + b->K - 1) / b->K;
   int c = 0;

@@ -47,12 +47,20 @@ WALL = 3                    # sticky boundary thickness in nodes
 
 @dataclass
 class BoxCollider:
-    """A kinematic box moving at constant velocity (one-way coupling)."""
+    """A kinematic box moving at constant velocity and spinning at a constant
+    rate about a fixed axis through its center (one-way coupling)."""
     center: tuple
     half: tuple
     velocity: tuple
     alpha: float      # softness of the contact blend, 1/length
     mu_b: float       # Coulomb friction coefficient
+    axis: tuple = (0.0, 0.0, 1.0)   # rotation axis (unit)
+    angle: float = 0.0              # rotation about the axis at t = 0 (rad)
+    omega: float = 0.0              # angular speed (rad/s)
+
+    @property
+    def rotates(self) -> bool:
+        return self.angle != 0.0 or self.omega != 0.0
 
 
 @dataclass

@@ -211,6 +211,98 @@ def test_collider_actions_forward_and_gradient(mode, geom):
     assert ev < 1e-3 and ec < 1e-3
 
 
+SPIN_BOX = scenes.BoxCollider(center=(0.6, 0.46, 0.46), half=(0.04, 0.12, 0.2), velocity=(-0.4, 0.0, 0.0),
+                              alpha=64.0, mu_b=0.3, axis=(0.0, 0.6, 0.8), angle=0.4, omega=6.0)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
+def test_spinning_box_forward_and_gradient(mode):
+    # a box turned about a tilted axis and spinning at a constant rate, against the oracle
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=160, collider=SPIN_BOX, v_scale=0.2)
+    S, K = 10, 4
+    announce(f"tait + spinning box (constant rate), {mode}")
+    cots = random_cotangents([spec], seed=161)
+    g = gpu_rollout([spec], S, K, mode=mode, cots=cots)
+    o = oracle_rollout(spec, S, cots[0])
+    assert g["status"] == 0
+    check_state(g["state"], o["state"], "spinning box", spec.x, S)
+    check_grads(g["grads"], o["grads"], "spinning box")
+    check_params(g["dparams"][0], o["dparams"], [5, 2, 3], "spinning box", spec.params())
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
+def test_spin_actions_forward_and_gradient(mode):
+    # per-substep velocities and angular speeds drive the turned box; gradients w.r.t. both, the
+    # starting center and the starting angle against the oracle
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd.batch import Batch
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=162, collider=SPIN_BOX, v_scale=0.2)
+    other = make_env(scenes.NEOHOOKEAN, N=1000, seed=163)
+    S, K = 10, 4
+    rng = np.random.default_rng(164)
+    vel = (np.array(SPIN_BOX.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+    om = (SPIN_BOX.omega + 4.0 * rng.standard_normal(S)).astype(np.float32)
+    announce(f"spinning box driven by {S} velocity and angular-speed actions, {mode}")
+    envs = [spec, other]
+    cots = random_cotangents(envs, seed=165)
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode.split("-")[0])
+    try:
+        if mode == "batched-fused":
+            b.set_option(C.OPT_FUSE, 1)
+            b.set_option(C.OPT_FUSE_ADJ, 1)
+        b.set_particles_from_specs()
+        b.set_collider_motion(0, vel, om)
+        b.forward(S, record=True)
+        st = tuple(to_np(t) for t in b.get_particles(env=0))
+        cat = lambda i: torch.from_numpy(np.concatenate([c[i] for c in cots], axis=0))
+        dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+        N0 = spec.n_particles
+        gr = tuple(to_np(t)[:N0] for t in (dx, dv, dC, dF))
+        dvel, dc0, dom, dang = b.collider_grad(0, S, spin=True)
+        assert b.sync(raise_on_error=False) == 0
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    velt, omt = torch.from_numpy(vel).double(), torch.from_numpy(om).double()
+    (x, v, Cm, F), _ = O.rollout(env, prm, st0, S, vel=velt, omega=omt)
+    c = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).double() for a in cots[0])
+    g, gp, gvel, gc0, gom, gang = O.rollout_vjp(env, prm, st0, S, c, vel=velt, omega=omt)
+    check_state(st, tuple(t.numpy() for t in (x, v, Cm, F)), "spin actions", spec.x, S)
+    check_grads(gr, tuple(t.numpy() for t in g), "spin actions")
+    ev, ec, eo = relerr(dvel, gvel.numpy()), relerr(dc0, gc0.numpy()), relerr(dom, gom.numpy())
+    ea = abs(dang - float(gang)) / abs(float(gang))
+    announce(f"spin actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {ea:.2e}, "
+             f"|dL/domega| {np.abs(gom.numpy()).max():.3e}")
+    assert np.abs(gom.numpy()).max() > 0 and abs(float(gang)) > 0
+    assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3 and ea < 1e-3
+
+
+def test_rollout_function_with_spins_matches_oracle():
+    # the autograd Function carries the angular-speed actions' gradient
+    from paper_2412_12089_amd.batch import Batch, rollout
+    spec = make_env(scenes.FLUID_TAIT, N=2000, seed=166, collider=SPIN_BOX, v_scale=0.2)
+    S, K = 6, 3
+    dev = torch.device("cuda:0")
+    st = [torch.from_numpy(getattr(spec, k)).to(dev) for k in ("x", "v", "C", "F")]
+    params = torch.tensor(spec.params()[None], dtype=torch.float64)
+    rng = np.random.default_rng(167)
+    vel = torch.from_numpy((np.array(SPIN_BOX.velocity) + 0.3 * rng.standard_normal((1, S, 3))).astype(np.float32))
+    spins = torch.from_numpy((SPIN_BOX.omega + 4.0 * rng.standard_normal((1, S))).astype(np.float32)).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((spec.n_particles, 3)).astype(np.float32)).to(dev)
+    b = Batch([spec], max_substeps=S, ckpt_every=K)
+    try:
+        xs, _, _, _ = rollout(b, S, *st, params, vel, None, spins)
+        (xs * w).sum().backward()
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    cot = (torch.from_numpy(w.cpu().numpy()).double(), None, None, None)
+    _, _, _, _, gom, _ = O.rollout_vjp(env, prm, st0, S, cot, vel=vel[0].double(), omega=spins[0].detach().double())
+    e = relerr(spins.grad[0].numpy(), gom.numpy())
+    announce(f"rollout Function: dL/dspins {e:.2e}")
+    assert e < 1e-3
+
+
 def test_collider_actions_bounds():
     from paper_2412_12089_amd.batch import Batch
     from paper_2412_12089_amd._capi import MPMError

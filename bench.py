@@ -104,6 +104,11 @@ def measured_traffic(workload: str, symbol: str):
     return rec["kernels"][symbol]["bytes"]
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result is the one line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,7 +276,9 @@ def main():
     dev = torch.device("cuda:0")
     x0, w = inputs(wl, dev)
     fixed = dict(kv.split("=") for kv in args.set.split(",") if kv)
+    progress(f"{wl.name}: {len(envs)} envs, {N} particles, {S} substeps; batch created, autotuning")
     b, tuned, tune_s = tuned_batch(wl, dev, args, fixed)
+    progress(f"options {tuned}; timing {args.steps} steps")
     ms = run_steps(b, x0, w, S, args.steps, args.warmup)
     if args.profile:
         # calibration for HBM byte counters: one plain 256 MiB device-to-device copy
@@ -316,6 +323,7 @@ def main():
     # checkpoints, 28 + 56 B per touched node and substep
     step_bytes = N * S * (672 + 96.0 / K) + nodes * S * (28 + 56)
 
+    progress(f"{np.mean(ms):.1f} ms per step; per-env mode next")
     plain = None
     if args.plain_steps > 0:
         bp = Batch(envs, max_substeps=S, ckpt_every=K, mode="plain", device=dev)
@@ -325,11 +333,15 @@ def main():
 
     extra = {}
     for name in [n for n in args.extra.split(",") if n and n != wl.name]:
+        progress(f"workload {name}")
         extra[name] = extra_workload(name, dev, args)
 
     serving = None
     if args.serve_seconds > 0:
+        progress(f"serving a {args.serve_seconds:.0f} s Poisson stream")
         serving = serving_leg(args.serve_seconds, args.serve_rate, args.serve_slots, dev)
+    if not args.no_cpu_baseline:
+        progress("oracle CPU baseline")
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_substeps, args.cpu_envs, args.cpu_runs)
     out = {
         "metric": "fwd+bwd particle-substeps/s (batched)",

@@ -286,10 +286,11 @@ MD void block_reduce_params_lds(float pb[PB_COUNT], double* __restrict__ acc) {
 // push scatter (27 nodes x channels atomics per particle) is bound by them.
 // Instead each particle writes its scatter payload once to LDS, the block
 // counting-sorts its particles by their current stencil base (one integer LDS
-// atomic per particle), and the thread that owns a box node sums the
-// contributions of the particles whose stencil holds it: for each of the
-// node's 9 (x, y) base columns the three z bases are adjacent cells, so their
-// particles form one contiguous range of the sorted list. A particle's
+// atomic per particle) and stores its payload at its sorted position, and the
+// thread that owns a box node sums the contributions of the particles whose
+// stencil holds it: for each of the node's 9 (x, y) base columns the three z
+// bases are adjacent cells, so their particles are one contiguous range of
+// the sorted payloads. A particle's
 // contribution to node base + o is W(o) (g + A (o - f)) per channel (the
 // affine form of both scatters), plus W(o) * mass for the mass channel.
 // ----------------------------------------------------------------------------
@@ -300,6 +301,13 @@ constexpr int kPayload = 16;   // floats per particle: f (3), base z (int bits),
 // block's boxes average ~850 nodes and a few percent exceed 1024)
 constexpr int kPullNodes = 2048;
 constexpr int kPullSmall = 1024;
+// room for base cells in a pull box: half its node budget. A run is one tile
+// row, at most 4 x 4 base cells across and so at most 6 x 6 nodes, so its
+// cells are under 16/36 of its nodes and the limit never binds; a block past
+// it would fall back like one whose box does not fit. The smaller cell index
+// lets six blocks share a CU.
+template <int BOXN>
+constexpr int pull_cells() { return BOXN / 2; }
 
 // block-wide inclusive prefix sum of a[0, n) in place (every thread calls it)
 MD void block_scan_inclusive(int* a, int n, int* wtot) {
@@ -325,26 +333,28 @@ MD void block_scan_inclusive(int* a, int n, int* wtot) {
 // LDS of the pull scatter: the cell index and the payload rows
 template <int BOXN>
 struct PullShared {
-  int start[BOXN + 1];     // first list position of each base cell (cells of all runs concatenated)
-  int list[256];           // payload rows (item particle indices) in cell order
+  int start[pull_cells<BOXN>() + 1];     // first sorted position of each base cell (cells of all runs concatenated)
   int coff[kMaxRuns + 1];  // first cell of each run
   int cext[kMaxRuns][3];   // base-cell extents of each run (its box extents - 2)
   int wtot[4];
-  float4 pay[256 * (kPayload / 4)];
+  float4 pay[(kPayload / 4) * 256];   // payload row r of sorted position q at pay[r * 256 + q]
 };
 
-MD void pull_store_payload(float4* pay, int lp, const float f[3], int bz, const float g[3], const float A[3][3]) {
-  float4* row = pay + lp * (kPayload / 4);
-  row[0] = make_float4(f[0], f[1], f[2], __int_as_float(bz));
-  row[1] = make_float4(g[0], g[1], g[2], A[0][0]);
-  row[2] = make_float4(A[0][1], A[0][2], A[1][0], A[1][1]);
-  row[3] = make_float4(A[1][2], A[2][0], A[2][1], A[2][2]);
+// rows are strided by 256 particles, not packed per particle: lanes reading
+// different particles' rows then spread over the LDS banks
+MD void pull_store_payload(float4* pay, int q, const float f[3], int bz, const float g[3], const float A[3][3]) {
+  pay[q] = make_float4(f[0], f[1], f[2], __int_as_float(bz));
+  pay[256 + q] = make_float4(g[0], g[1], g[2], A[0][0]);
+  pay[512 + q] = make_float4(A[0][1], A[0][2], A[1][0], A[1][1]);
+  pay[768 + q] = make_float4(A[1][2], A[2][0], A[2][1], A[2][2]);
 }
 
 // counting sort of the block's particles by current stencil base within their
-// run's box (every thread calls it; the box must fit)
+// run's box (every thread calls it; the box must fit): false, for every
+// thread, if the boxes hold more base cells than the index has room for;
+// else pos = the particle's sorted position (0 for an invalid lane)
 template <int BOXN>
-MD void pull_index(const BoxShared& bs, PullShared<BOXN>& ps, const Box& bx, const int b[3], bool valid, int lp) {
+MD bool pull_index(const BoxShared& bs, PullShared<BOXN>& ps, const Box& bx, const int b[3], bool valid, int& pos) {
   const int nr = bs.nruns < kMaxRuns ? bs.nruns : kMaxRuns;
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -361,6 +371,7 @@ MD void pull_index(const BoxShared& bs, PullShared<BOXN>& ps, const Box& bx, con
   }
   __syncthreads();
   const int ncell = ps.coff[nr];
+  if (ncell > pull_cells<BOXN>()) return false;
   for (int i = threadIdx.x; i <= ncell; i += blockDim.x) ps.start[i] = 0;
   __syncthreads();
   int cid = 0, rank = 0;
@@ -372,48 +383,52 @@ MD void pull_index(const BoxShared& bs, PullShared<BOXN>& ps, const Box& bx, con
   }
   __syncthreads();
   block_scan_inclusive(ps.start, ncell + 1, ps.wtot);
-  if (valid) ps.list[ps.start[cid] + rank] = lp;
-  __syncthreads();
+  pos = valid ? ps.start[cid] + rank : 0;
+  return true;
+}
+
+// contribution of the payload at sorted position q to box node (ox, oy, k - base z) of its stencil
+MD void pull_add(const float4* pay, int q, int ox, int oy, int k, float acc[3], float& wsum) {
+  const float4 r0 = pay[q], r1 = pay[256 + q], r2 = pay[512 + q], r3 = pay[768 + q];
+  const int oz = k - __float_as_int(r0.w);
+  float wx, wy, wz, dw;
+  spline_piece(ox, r0.x, wx, dw);
+  spline_piece(oy, r0.y, wy, dw);
+  spline_piece(oz, r0.z, wz, dw);
+  const float W = wx * wy * wz;
+  const float d0 = (float)ox - r0.x, d1 = (float)oy - r0.y, d2 = (float)oz - r0.z;
+  const float g0 = fmaf(r1.w, d0, fmaf(r2.x, d1, fmaf(r2.y, d2, r1.x)));
+  const float g1 = fmaf(r2.z, d0, fmaf(r2.w, d1, fmaf(r3.x, d2, r1.y)));
+  const float g2 = fmaf(r3.y, d0, fmaf(r3.z, d1, fmaf(r3.w, d2, r1.z)));
+  acc[0] = fmaf(W, g0, acc[0]);
+  acc[1] = fmaf(W, g1, acc[1]);
+  acc[2] = fmaf(W, g2, acc[2]);
+  wsum += W;
 }
 
 // sum for box node idx (run r, node (i, j, k)) over the run's particles whose
-// stencil holds it: acc[c] += W (g_c + A_c . (o - f)), wsum += W
-MD void pull_node(const BoxShared& bs, const int* start, const int* list, const int* coff, const int (*cext)[3],
+// stencil holds it: acc[c] += W (g_c + A_c . (o - f)), wsum += W. The nine
+// column ranges are read up front (one LDS round trip, not nine), and each
+// column's loop is its own code with constant (x, y) offsets.
+MD void pull_node(const BoxShared& bs, const int* start, const int* coff, const int (*cext)[3],
                   const float4* pay, int r, int i, int j, int k, float acc[3], float& wsum) {
   const int c0 = i - bs.lo[r][0], c1 = j - bs.lo[r][1], c2 = k - bs.lo[r][2];
   const int e0 = cext[r][0], e1 = cext[r][1], e2 = cext[r][2];
   const int z_lo = max(c2 - 2, 0), z_hi = min(c2, e2 - 1);
   if (z_lo > z_hi) return;
+  int qa[9], qb[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int cx = c0 - c / 3, cy = c1 - c % 3;
+    const bool ok = cx >= 0 && cx < e0 && cy >= 0 && cy < e1;
+    const int cb = coff[r] + (cx * e1 + cy) * e2;
+    qa[c] = start[ok ? cb + z_lo : 0];
+    qb[c] = ok ? start[cb + z_hi + 1] : qa[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
 #pragma unroll 1
-  for (int ox = 0; ox < 3; ++ox) {
-    const int cx = c0 - ox;
-    if (cx < 0 || cx >= e0) continue;
-#pragma unroll 1
-    for (int oy = 0; oy < 3; ++oy) {
-      const int cy = c1 - oy;
-      if (cy < 0 || cy >= e1) continue;
-      const int cb = coff[r] + (cx * e1 + cy) * e2;
-      const int q1 = start[cb + z_hi + 1];
-#pragma unroll 1
-      for (int q = start[cb + z_lo]; q < q1; ++q) {
-        const float4* row = pay + list[q] * (kPayload / 4);
-        const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
-        const int oz = k - __float_as_int(r0.w);
-        float wx, wy, wz, dw;
-        spline_piece(ox, r0.x, wx, dw);
-        spline_piece(oy, r0.y, wy, dw);
-        spline_piece(oz, r0.z, wz, dw);
-        const float W = wx * wy * wz;
-        const float d0 = (float)ox - r0.x, d1 = (float)oy - r0.y, d2 = (float)oz - r0.z;
-        const float g0 = fmaf(r1.w, d0, fmaf(r2.x, d1, fmaf(r2.y, d2, r1.x)));
-        const float g1 = fmaf(r2.z, d0, fmaf(r2.w, d1, fmaf(r3.x, d2, r1.y)));
-        const float g2 = fmaf(r3.y, d0, fmaf(r3.z, d1, fmaf(r3.w, d2, r1.z)));
-        acc[0] = fmaf(W, g0, acc[0]);
-        acc[1] = fmaf(W, g1, acc[1]);
-        acc[2] = fmaf(W, g2, acc[2]);
-        wsum += W;
-      }
-    }
+    for (int q = qa[c]; q < qb[c]; ++q) pull_add(pay, q, c / 3, c % 3, k, acc, wsum);
   }
 }
 
@@ -524,6 +539,8 @@ MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, con
   const Stencil sc = make_stencil(x, e.n, e.fn);
   if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
   const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
+  int pos = 0;
+  const bool fits = bx.fits && pull_index<BOXN>(bsh, ps, bx, sc.b, valid, pos);
   if (valid) {
     const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
     const M3 Cm = ld_m3(st, N, p, 6);
@@ -533,11 +550,11 @@ MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, con
     const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
     float mv0[3];
     for (int a = 0; a < 3; ++a) mv0[a] = e.mp * v[a];
-    if (bx.fits) {
+    if (fits) {
       float Ad[3][3];
       for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) Ad[a][c] = A.m[a][c] * e.dx;
-      pull_store_payload(ps.pay, lp, sc.f, sc.b[2], mv0, Ad);
+      pull_store_payload(ps.pay, pos, sc.f, sc.b[2], mv0, Ad);
     } else {
 #pragma unroll 1
       for (int ox = 0; ox < 3; ++ox)
@@ -554,16 +571,16 @@ MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, con
           }
     }
   }
-  if (!bx.fits) {
+  if (!fits) {
     if (valid) mark_particle_tiles(e, sc.b, flags);
     return;
   }
-  pull_index<BOXN>(bsh, ps, bx, sc.b, valid, lp);
+  __syncthreads();
   for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
     int r, i, j, k;
     box_node_run(bsh, idx, r, i, j, k);
     float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
-    pull_node(bsh, ps.start, ps.list, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
+    pull_node(bsh, ps.start, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
     if (wsum == 0.f) continue;   // no particle weight reached the node
     float* dst = grid + node_base(e, i, j, k);
     atomicAdd(dst, wsum * e.mp);
@@ -573,8 +590,9 @@ MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, con
   box_mark_tiles(e, bsh, flags);
 }
 
+// six waves per SIMD: the LDS of six blocks fits a CU, and the registers fit six waves without spills
 template <bool PERSIST, int BOXN, int MAT>
-__global__ void __launch_bounds__(256) k_p2g_pull(const float* __restrict__ st, int64_t N,
+__global__ void __launch_bounds__(256, 6) k_p2g_pull(const float* __restrict__ st, int64_t N,
                                                   const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
                                                   float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                   int32_t* __restrict__ errs, int k_call, int n_items) {
@@ -816,6 +834,8 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
   load_x3(st, N, p, x);
   const Stencil sc = make_stencil(x, e.n, e.fn);
   const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
+  int pos = 0;
+  const bool fits = bx.fits && pull_index<BOXN>(bsh, ps, bx, sc.b, valid, pos);
   float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (valid) {
     const M3 H = ld_m3(st, N, p, 15);
@@ -833,11 +853,11 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
     const M3 Cb = m3_axpy(Cb_in, e.dt, m3_mul_abt(Ftrb, F));
     const M3 Fb = m3_mul_atb(G, Ftrb);
     st_m3(part, N, p, 3, Fb);
-    if (bx.fits) {
+    if (fits) {
       float Ad[3][3];
       for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) Ad[a][c] = D4 * e.dx * Cb.m[a][c];
-      pull_store_payload(ps.pay, lp, sc.f, sc.b[2], vb, Ad);
+      pull_store_payload(ps.pay, pos, sc.f, sc.b[2], vb, Ad);
     }
     float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
     float gz[3], cz[3];
@@ -862,7 +882,7 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
           for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
           const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
           for (int a = 0; a < 3; ++a) vi[a] = grid[nb + (4 + a) * CH];
-          if (!bx.fits)
+          if (!fits)
             for (int a = 0; a < 3; ++a) atomicAdd(gcot + nb + a * CH, W * gv[a]);
           const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
           for (int a = 0; a < 3; ++a) {
@@ -874,13 +894,13 @@ MD void g2p_adjoint_pull_item(int item_idx, const float* __restrict__ st, const 
     for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
     for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
   }
-  if (bx.fits) {
-    pull_index<BOXN>(bsh, ps, bx, sc.b, valid, lp);
+  if (fits) {
+    __syncthreads();
     for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
       int r, i, j, k;
       box_node_run(bsh, idx, r, i, j, k);
       float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
-      pull_node(bsh, ps.start, ps.list, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
+      pull_node(bsh, ps.start, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
       if (wsum == 0.f) continue;
       float* dst = gcot + node_base(e, i, j, k);
       for (int a = 0; a < 3; ++a)

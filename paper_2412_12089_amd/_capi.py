@@ -1,4 +1,5 @@
-"""ctypes declarations of the C interface in include/mpm.h (argument marshalling only).
+"""ctypes declarations of the C interface in include/mpm.h and include/mpm_fem.h
+(argument marshalling only).
 
 Every function here has the name and argument order of its C counterpart.
 Device arrays are passed as torch CUDA tensors (or None for a NULL pointer);
@@ -29,7 +30,7 @@ MPM_FWD_RECORD = 1
 
 KERNEL_CLASSES = ("p2g", "grid", "g2p", "sort", "g2p_adj", "grid_adj", "p2g_adj", "g2p2g", "adj_pair")
 
-# every symbol include/mpm.h declares
+# every symbol include/*.h declares
 EXPORTED = (
     "mpm_batch_create", "mpm_batch_destroy", "mpm_set_particles", "mpm_get_particles", "mpm_set_material",
     "mpm_set_box_collider", "mpm_forward", "mpm_backward", "mpm_autotune", "mpm_sync", "mpm_env_errors",
@@ -39,7 +40,13 @@ EXPORTED = (
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
     "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp", "mpm_set_box_rotation",
+    "mpm_fem_create", "mpm_fem_destroy", "mpm_fem_set_rest", "mpm_fem_set_params", "mpm_fem_set_state",
+    "mpm_fem_get_state", "mpm_fem_forward", "mpm_fem_backward", "mpm_fem_sync", "mpm_fem_env_errors",
+    "mpm_fem_last_error", "mpm_fem_memory_bytes",
 )
+MPM_FEM_MAX_NODES = 512
+MPM_FEM_MAX_TETS = 1024
+MPM_FEM_PARAMS = 8
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
@@ -88,6 +95,12 @@ class mpm_server_stats(ctypes.Structure):
                                               "running", "particle_substeps", "steps")] + \
                [("max_running", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bytes_in_use", ctypes.c_int64)] + \
                [(k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "first_arrival", "last_finish")]
+
+
+class mpm_fem_desc(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("n_nodes", ctypes.c_int32), ("n_tets", ctypes.c_int32),
+                ("max_substeps", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -152,6 +165,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_sort_keys_noalloc": (I32, [VP, I64, I32, VP, VP, VP]),
         "mpm_pair_distance": (I32, [VP, VP, VP, I64, VP]),
         "mpm_pair_distance_vjp": (I32, [VP, VP, VP, I64, VP, VP, VP]),
+        "mpm_fem_create": (I32, [P(mpm_fem_desc), P(I32), P(mpm_allocator), VP, P(VP)]),
+        "mpm_fem_destroy": (I32, [VP]),
+        "mpm_fem_set_rest": (I32, [VP, VP]),
+        "mpm_fem_set_params": (I32, [VP, D8]),
+        "mpm_fem_set_state": (I32, [VP, VP, VP]),
+        "mpm_fem_get_state": (I32, [VP, VP, VP]),
+        "mpm_fem_forward": (I32, [VP, I32, VP, I32]),
+        "mpm_fem_backward": (I32, [VP, VP, VP, VP, VP, VP, VP]),
+        "mpm_fem_sync": (I32, [VP]),
+        "mpm_fem_env_errors": (I32, [VP, P(I32)]),
+        "mpm_fem_last_error": (ctypes.c_char_p, [VP]),
+        "mpm_fem_memory_bytes": (I64, [VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -172,11 +197,12 @@ class MPMError(RuntimeError):
         self.code = code
 
 
-def check(code: int, where: str, handle=None, server: bool = False):
+def check(code: int, where: str, handle=None, server: bool = False, fem: bool = False):
     if code != MPM_OK:
         msg = ""
         if _lib is not None:
-            raw = (_lib.mpm_server_last_error if server else _lib.mpm_last_error)(handle)
+            err = _lib.mpm_server_last_error if server else (_lib.mpm_fem_last_error if fem else _lib.mpm_last_error)
+            raw = err(handle)
             msg = raw.decode() if raw else ""
         raise MPMError(code, where, msg)
     return code

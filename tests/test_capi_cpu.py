@@ -1,9 +1,11 @@
 """Host-side checks of the C interface: the library loads, exports every
-function include/mpm.h declares, and rejects bad descriptions before touching
+function include/*.h declares, and rejects bad descriptions before touching
 a device."""
 import ctypes
 import os
 import re
+
+import numpy as np
 
 import pytest
 
@@ -13,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "mpm.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(mpm_[a-z_0-9]+)\s*\(", src, flags=re.M)))
 
@@ -68,3 +71,55 @@ def test_key_width_limit():
     d, keep = _desc(n=96, envs=8193, n_particles=0)
     out = ctypes.c_void_p()
     assert lib.mpm_batch_create(ctypes.byref(d), None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+
+
+def _fem_desc(E=2, n=12, T=12, S=4, dt=1e-4):
+    d = C.mpm_fem_desc()
+    d.n_envs, d.n_nodes, d.n_tets, d.max_substeps, d.dt = E, n, T, S, dt
+    d.gravity[:] = [0.0, 0.0, -9.8]
+    return d
+
+
+def _fem_tets(T=12, n=12):
+    rng = np.random.default_rng(0)
+    return np.stack([rng.choice(n, 4, replace=False) for _ in range(T)]).astype(np.int32)
+
+
+@pytest.mark.parametrize("kw", [dict(E=0), dict(n=3), dict(n=513), dict(T=0), dict(T=1025), dict(S=-1),
+                                dict(dt=0.0), dict(dt=float("nan"))])
+def test_fem_create_rejects_bad_descriptions(kw):
+    lib = C.load()
+    d = _fem_desc(**kw)
+    tets = _fem_tets(min(max(d.n_tets, 1), 1024), max(d.n_nodes, 4))
+    out = ctypes.c_void_p()
+    ptr = tets.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert lib.mpm_fem_create(ctypes.byref(d), ptr, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    assert not out.value
+
+
+@pytest.mark.parametrize("bad", ["range", "negative", "repeat", "orphan"])
+def test_fem_create_rejects_bad_topology(bad):
+    lib = C.load()
+    d = _fem_desc()
+    tets = _fem_tets()
+    if bad == "orphan":   # elements over nodes 0..10 only: node 11 has no element
+        tets = _fem_tets(12, 11)
+    else:
+        tets[5] = {"range": [0, 1, 2, 12], "negative": [0, -1, 2, 3], "repeat": [4, 5, 4, 6]}[bad]
+    out = ctypes.c_void_p()
+    ptr = tets.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert lib.mpm_fem_create(ctypes.byref(d), ptr, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    assert not out.value
+
+
+def test_fem_null_arguments_are_rejected():
+    lib = C.load()
+    out = ctypes.c_void_p()
+    assert lib.mpm_fem_create(None, None, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    for fn, nargs in (("mpm_fem_destroy", 0), ("mpm_fem_set_rest", 1), ("mpm_fem_set_params", 1),
+                      ("mpm_fem_set_state", 2), ("mpm_fem_get_state", 2), ("mpm_fem_backward", 6),
+                      ("mpm_fem_sync", 0), ("mpm_fem_env_errors", 1)):
+        assert getattr(lib, fn)(None, *([None] * nargs)) == C.MPM_INVALID_ARG, fn
+    assert lib.mpm_fem_forward(None, 1, None, 0) == C.MPM_INVALID_ARG
+    assert lib.mpm_fem_memory_bytes(None) == 0
+    assert lib.mpm_fem_last_error(None) == b"null FEM batch"

@@ -132,6 +132,9 @@ def parse():
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=48)
+    ap.add_argument("--fem-envs", type=int, default=4096, help="jumper envs of the FEM leg (0: skip)")
+    ap.add_argument("--fem-frames", type=int, default=5, help="timed 80-substep frames of the FEM leg")
+    ap.add_argument("--fem-only", action="store_true", help="run only the FEM leg and print its JSON (profiling)")
     return ap.parse_args()
 
 
@@ -234,6 +237,63 @@ def serving_leg(seconds, rate, slots, device):
     return st
 
 
+def fem_leg(n_envs, frames, dev):
+    """The tetrahedral FEM path on jumper-shaped soft bodies (199 nodes, 480
+    elements each): per 80-substep frame a recorded forward and its adjoint
+    (cotangents of the initial state, the activations and the parameters),
+    timed with HIP events on the library's stream."""
+    import torch
+    from paper_2412_12089_amd import fem_scenes as FS
+    from paper_2412_12089_amd.fem import FemBatch
+    w = FS.soft_jumper(seed=7, n_envs=n_envs, substeps=80)
+    E, n, T, S = w.n_envs, w.X.shape[1], w.tets.shape[0], w.substeps
+    b = FemBatch(w.tets, E, n, S, w.dt, w.gravity, dev)
+    b.set_rest(torch.from_numpy(w.X).to(dev))
+    b.set_params(w.params)
+    x0, v0 = torch.from_numpy(w.x0).to(dev), torch.from_numpy(w.v0).to(dev)
+    act = torch.from_numpy(w.act).to(dev)
+    gx = torch.randn(E, n, 3, device=dev)
+    dx, dv = torch.empty_like(gx), torch.empty_like(gx)
+    da = torch.empty(S, E, T, device=dev)
+    dp = torch.empty(E, 8, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    lib, h = b.lib, b.h
+    from paper_2412_12089_amd import _capi as C
+
+    def frame(backward=True):
+        lib.mpm_fem_set_state(h, C.ptr(x0), C.ptr(v0))
+        lib.mpm_fem_forward(h, S, C.ptr(act), C.MPM_FWD_RECORD if backward else 0)
+        if backward:
+            lib.mpm_fem_backward(h, C.ptr(gx), None, C.ptr(dx), C.ptr(dv), C.ptr(da), C.ptr(dp))
+
+    def timed(backward):
+        for _ in range(2):
+            frame(backward)
+        ms = []
+        for _ in range(frames):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            frame(backward)
+            e1.record(b.stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.mean(ms))
+
+    fb_ms = timed(True)
+    f_ms = timed(False)
+    assert b.sync(raise_on_error=False) == C.MPM_OK, "non-finite FEM state"
+    # HBM bytes of a frame: forward tape (S + 1 states of 24 B per node) and activations (4 B per element and
+    # substep, read and kept); backward: the tape and activations read, the activation cotangents written
+    frame_bytes = E * ((S + 1) * n * 24 * 2 + S * T * 4 * 4)
+    out = {"workload": "soft_jumper", "envs": E, "nodes": n, "tets": T, "substeps": S,
+           "fwd_bwd_ms_per_frame": fb_ms, "fwd_ms_per_frame": f_ms,
+           "env_substeps_per_s": E * S / (fb_ms * 1e-3), "node_substeps_per_s": E * n * S / (fb_ms * 1e-3),
+           "fwd_env_substeps_per_s": E * S / (f_ms * 1e-3), "frame_hbm_bytes": frame_bytes,
+           "frame_hbm_gbs": frame_bytes / (fb_ms * 1e-3) / 1e9, "hbm_resident_bytes": b.memory_bytes()}
+    b.close()
+    return out
+
+
 def cpu_baseline(wl, substeps, n_envs, runs):
     """The FP64 oracle on a bounded sample: the first n_envs envs, `substeps`
     substeps each, forward + reverse; the median rate over `runs` runs."""
@@ -269,6 +329,9 @@ def main():
     from paper_2412_12089_amd import _capi, scenes
     from paper_2412_12089_amd.batch import Batch
 
+    if args.fem_only:
+        print(json.dumps(fem_leg(max(1, args.fem_envs), args.fem_frames, torch.device("cuda:0"))), flush=True)
+        return
     wl = scenes.WORKLOADS[args.workload]()
     S, K = wl.substeps, wl.ckpt_every
     envs = wl.envs
@@ -336,6 +399,11 @@ def main():
         progress(f"workload {name}")
         extra[name] = extra_workload(name, dev, args)
 
+    fem = None
+    if args.fem_envs > 0:
+        progress(f"FEM leg: {args.fem_envs} jumpers")
+        fem = fem_leg(args.fem_envs, args.fem_frames, dev)
+
     serving = None
     if args.serve_seconds > 0:
         progress(f"serving a {args.serve_seconds:.0f} s Poisson stream")
@@ -374,6 +442,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes, "kernel_ms": dom_ms},
         "workloads": extra,
+        "fem": fem,
         "serving": serving,
         "cpu_baseline": cpu,
     }

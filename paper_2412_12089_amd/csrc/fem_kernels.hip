@@ -15,7 +15,7 @@
 
 namespace mpmx {
 
-namespace {
+namespace fem {
 
 MD float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
 MD float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
@@ -442,7 +442,9 @@ int tets_per_thread(int T) {
   return q <= 1 ? 1 : (q <= 2 ? 2 : 4);
 }
 
-}  // namespace
+}  // namespace fem
+
+using namespace fem;
 
 size_t fem_forward_lds(int n, int T) { return sizeof(float) * (size_t)(8 * n + 13 * T + 1); }
 size_t fem_backward_lds(int n, int T) { return sizeof(float) * (size_t)(17 * n + 22 * T + 1); }

@@ -61,7 +61,7 @@ KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg", 3: "
                  "g2p_adj": {0: "k_g2p_adjoint_direct", 1: "k_g2p_adjoint_lds", 2: "k_g2p_adjoint_seg",
                              3: "k_g2p_adjoint_pull"},
                  "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"},
-                 "g2p2g": {1: "k_g2p2g"}, "adj_pair": {1: "k_adj_pair"}}
+                 "g2p2g": {1: "k_g2p2g", 2: "k_g2p2g_pull"}, "adj_pair": {1: "k_adj_pair"}}
 OPTION_NAMES = ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE",
                 "FUSE_ADJ", "XCD")
 
@@ -82,6 +82,8 @@ def kernel_instance(symbol: str, variant, tuned: dict, envs) -> str:
         return symbol
     mats = sorted({e.material for e in envs})
     mat = mats[0] if tuned["SPECIALIZE"] and len(mats) == 1 else -1
+    if symbol == "k_g2p2g_pull":   # no persistent-grid parameter, the pull box budgets
+        return f"{symbol}<{1024 if tuned['BOX'] else 2048}, {mat}>"
     if symbol in ("k_g2p2g", "k_adj_pair"):   # no persistent-grid parameter
         return f"{symbol}<{384 if tuned['BOX'] else 1024}, {mat}>"
     n_items = sum(-(-e.n_particles // 256) for e in envs)
@@ -371,7 +373,8 @@ def main():
         kt[k] = ((mf * nf + mb * nb) / n if n else 0.0, n)
     variant = {"p2g": b.get_option(_capi.OPT_P2G), "g2p": b.get_option(_capi.OPT_G2P),
                "g2p_adj": b.get_option(_capi.OPT_G2P_ADJ), "p2g_adj": b.get_option(_capi.OPT_P2G_ADJ),
-               "g2p2g": b.get_option(_capi.OPT_FUSE), "adj_pair": b.get_option(_capi.OPT_FUSE_ADJ)}
+               "g2p2g": b.get_option(_capi.OPT_FUSE) * (2 if b.get_option(_capi.OPT_P2G) == 3 else 1),
+               "adj_pair": b.get_option(_capi.OPT_FUSE_ADJ)}
     mem = b.memory_bytes()
     b.close()
     nodes = touched_nodes(envs)

@@ -277,9 +277,10 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
 #define MPM_OPT_BOX 9          /* LDS-staged kernels' box budget: 0 = 1024 grid nodes per block (default),
                                   1 = 384 nodes (less LDS, more blocks per CU; a block whose box is larger
                                   falls back to global atomics) */
-#define MPM_OPT_FUSE 11        /* 1: within a segment, G2P of substep k and the segment-reduced P2G of substep
-                                  k + 1 run as one kernel (the new state stays in registers); needs
-                                  MPM_OPT_P2G = 2, otherwise ignored. Default 0; the autotuner may set it */
+#define MPM_OPT_FUSE 11        /* 1: within a segment, G2P of substep k and the P2G of substep k + 1 run as
+                                  one kernel (the new state is scattered from registers); needs
+                                  MPM_OPT_P2G = 2 (per-cell runs) or 3 (pull), otherwise ignored. Default 0;
+                                  the autotuner may set it */
 #define MPM_OPT_FUSE_ADJ 12    /* 1: within a segment's backward, the P2G adjoint of substep k and the G2P
                                   adjoint of substep k - 1 run as one kernel (the cotangent of state k stays
                                   in registers; the G2P adjoint part is the segment-reduced one). Batched

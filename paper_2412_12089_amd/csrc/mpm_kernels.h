@@ -102,6 +102,10 @@ void launch_g2p_adjoint_seg(const float* st, const float* st_next, const float* 
 
 // G2P of substep k fused with the segment-reduced P2G of substep k + 1
 // (grid_in: substep k's grid, read; grid_out / flags_out: substep k + 1's)
+// G2P of substep k fused with the pull P2G of substep k + 1 (the low particles-per-cell form of launch_g2p2g)
+void launch_g2p2g_pull(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                       const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs, int k_call, int box,
+                       int mat, hipStream_t s);
 void launch_g2p2g(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                   const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs, int runs, int k_call,
                   int box, int mat, hipStream_t s);

@@ -518,6 +518,57 @@ __global__ void __launch_bounds__(256) k_p2g_lds(const float* __restrict__ st, i
   }
 }
 
+// one particle's share of the pull P2G: its payload (m_p v, (m_p C - dt V_p
+// 4 n^2 tau) dx, f, base z) at its sorted position when the block's boxes
+// fit, else its 27 nodes added to the grid with global atomics
+MD void p2g_pull_particle(const EnvDev& e, int mat, const Stencil& sc, bool fits, int pos, const float v[3],
+                          const M3& Cm, const M3& H, float4* pay, float* __restrict__ grid) {
+  const M3 tau = stress(e, H, mat);
+  const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+  const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
+  float mv0[3];
+  for (int a = 0; a < 3; ++a) mv0[a] = e.mp * v[a];
+  if (fits) {
+    float Ad[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) Ad[a][c] = A.m[a][c] * e.dx;
+    pull_store_payload(pay, pos, sc.f, sc.b[2], mv0, Ad);
+  } else {
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          float W, d[3];
+          stencil_offsets(sc, e, ox, oy, oz, W, d);
+          float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          atomicAdd(g, W * e.mp);
+          for (int a = 0; a < 3; ++a)
+            atomicAdd(g + (1 + a) * CH, W * (mv0[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]));
+        }
+  }
+}
+
+// the owners' sums of a block whose payloads are stored (after a barrier):
+// each box node's (m, m v) added to the grid once, the box's tiles flagged
+template <int BOXN>
+MD void p2g_pull_owners(const EnvDev& e, const BoxShared& bsh, const PullShared<BOXN>& ps, int nodes,
+                        float* __restrict__ grid, uint32_t* __restrict__ flags) {
+  for (int idx = threadIdx.x; idx < nodes; idx += blockDim.x) {
+    int r, i, j, k;
+    box_node_run(bsh, idx, r, i, j, k);
+    float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
+    pull_node(bsh, ps.start, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
+    if (wsum == 0.f) continue;   // no particle weight reached the node
+    float* dst = grid + node_base(e, i, j, k);
+    atomicAdd(dst, wsum * e.mp);
+    for (int a = 0; a < 3; ++a)
+      if (acc[a] != 0.f) atomicAdd(dst + (1 + a) * CH, acc[a]);
+  }
+  box_mark_tiles(e, bsh, flags);
+}
+
 // P2G through the pull scatter: the block's particles write (m_p v, A dx, f)
 // to LDS, each box node is summed by its owner thread and added to the grid
 // once; a block whose boxes do not fit scatters with global atomics
@@ -543,51 +594,14 @@ MD void p2g_pull_item(int item_idx, const float* __restrict__ st, int64_t N, con
   const bool fits = bx.fits && pull_index<BOXN>(bsh, ps, bx, sc.b, valid, pos);
   if (valid) {
     const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
-    const M3 Cm = ld_m3(st, N, p, 6);
-    const M3 H = ld_m3(st, N, p, 15);
-    const M3 tau = stress(e, H, mat);
-    const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
-    const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, tau);
-    float mv0[3];
-    for (int a = 0; a < 3; ++a) mv0[a] = e.mp * v[a];
-    if (fits) {
-      float Ad[3][3];
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) Ad[a][c] = A.m[a][c] * e.dx;
-      pull_store_payload(ps.pay, pos, sc.f, sc.b[2], mv0, Ad);
-    } else {
-#pragma unroll 1
-      for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-          for (int oz = 0; oz < 3; ++oz) {
-            float W, d[3];
-            stencil_offsets(sc, e, ox, oy, oz, W, d);
-            float* g = grid + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
-            atomicAdd(g, W * e.mp);
-            for (int a = 0; a < 3; ++a)
-              atomicAdd(g + (1 + a) * CH, W * (mv0[a] + A.m[a][0] * d[0] + A.m[a][1] * d[1] + A.m[a][2] * d[2]));
-          }
-    }
+    p2g_pull_particle(e, mat, sc, fits, pos, v, ld_m3(st, N, p, 6), ld_m3(st, N, p, 15), ps.pay, grid);
   }
   if (!fits) {
     if (valid) mark_particle_tiles(e, sc.b, flags);
     return;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
-    int r, i, j, k;
-    box_node_run(bsh, idx, r, i, j, k);
-    float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
-    pull_node(bsh, ps.start, ps.coff, ps.cext, ps.pay, r, i, j, k, acc, wsum);
-    if (wsum == 0.f) continue;   // no particle weight reached the node
-    float* dst = grid + node_base(e, i, j, k);
-    atomicAdd(dst, wsum * e.mp);
-    for (int a = 0; a < 3; ++a)
-      if (acc[a] != 0.f) atomicAdd(dst + (1 + a) * CH, acc[a]);
-  }
-  box_mark_tiles(e, bsh, flags);
+  p2g_pull_owners<BOXN>(e, bsh, ps, bx.nodes, grid, flags);
 }
 
 // six waves per SIMD: the LDS of six blocks fits a CU, and the registers fit six waves without spills
@@ -1446,6 +1460,136 @@ void launch_g2p2g(const float* st, float* out, int64_t N, const EnvDev* envs, co
     launch_g2p2g_m<kBoxSmall>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, runs, k_call, s, mat);
   else
     launch_g2p2g_m<kBoxNodes>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, runs, k_call, s, mat);
+}
+
+// G2P of substep k fused with the pull P2G of substep k + 1: the new state
+// goes to the tape once and is scattered from registers. The G2P gathers
+// straight from grid k; the P2G boxes come from the new positions.
+template <int BOXN, int MAT>
+MD void g2p2g_pull_item(int item_idx, const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                        const EnvDev* __restrict__ envs, const WorkItem* __restrict__ items,
+                        const float* __restrict__ grid_in, float* __restrict__ grid_out,
+                        uint32_t* __restrict__ flags_out, int32_t* __restrict__ errs, int k_call) {
+  __shared__ BoxShared bsh;
+  __shared__ PullShared<BOXN> ps;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;
+  const int lp = lane_particle(threadIdx.x);
+  const bool valid = lp < it.count;
+  const int64_t p = it.start + (valid ? lp : 0);
+  if (k_call >= e.nsub) {   // frozen env: the substep is the identity
+    if (valid)
+      for (int c = 0; c < 24; ++c) out[c * N + p] = st[c * N + p];
+    return;
+  }
+  // G2P (substep k)
+  float x[3];
+  load_x3(st, N, p, x);
+  const M3 H = ld_m3(st, N, p, 15);
+  float vn[3] = {0.f, 0.f, 0.f};
+  M3 Cn = m3_zero();
+  if (valid) {
+    const Stencil sc = make_stencil(x, e.n, e.fn);
+    const StencilAddr sa = stencil_addr(e, sc.b);
+    const float* genv = grid_in + (int64_t)e.tile_off * 512;
+    float wdz[3];
+    for (int o = 0; o < 3; ++o) wdz[o] = sc.w[2][o] * (((float)o - sc.f[2]) * e.dx);
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox) {
+      const uint32_t ax = ox == 0 ? sa.x[0] : (ox == 1 ? sa.x[1] : sa.x[2]);
+      const float wx = sel3(sc.w[0], ox), d0 = ((float)ox - sc.f[0]) * e.dx;
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy) {
+        const float wxy = wx * sc.w[1][oy], d1 = ((float)oy - sc.f[1]) * e.dx;
+        float col[3] = {0.f, 0.f, 0.f}, colz[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float* g = genv + (ax + sa.y[oy] + sa.z[oz]);
+          const float vi[3] = {g[4 * CH], g[5 * CH], g[6 * CH]};
+          const float W = wxy * sc.w[2][oz], Wd = wxy * wdz[oz];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            col[a] = fmaf(W, vi[a], col[a]);
+            colz[a] = fmaf(Wd, vi[a], colz[a]);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          vn[a] += col[a];
+          Cn.m[a][0] = fmaf(col[a], d0, Cn.m[a][0]);
+          Cn.m[a][1] = fmaf(col[a], d1, Cn.m[a][1]);
+          Cn.m[a][2] += colz[a];
+        }
+      }
+    }
+  }
+  Cn = m3_scale(Cn, 4.f * e.fn * e.fn);
+  float xn[3];
+  for (int a = 0; a < 3; ++a) xn[a] = fmaf(e.dt, vn[a], x[a]);
+  const M3 Hn = project(e, trial_h(e, Cn, H), mat);
+  if (valid) {
+    for (int a = 0; a < 3; ++a) { out[a * N + p] = xn[a]; out[(3 + a) * N + p] = vn[a]; }
+    st_m3(out, N, p, 6, Cn);
+    st_m3(out, N, p, 15, Hn);
+    bool fin = true;
+    for (int a = 0; a < 3; ++a) fin = fin && isfinite(xn[a]) && isfinite(vn[a]);
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) fin = fin && isfinite(Hn.m[i][j]);
+    if (!fin) atomicOr(&errs[it.env], ERR_NONFINITE);
+  }
+  if (k_call + 1 >= e.nsub) return;   // the env stops after this substep (uniform over the block)
+  // pull P2G (substep k + 1) of the state just computed
+  const Stencil sc = make_stencil(xn, e.n, e.fn);
+  if (valid && sc.oob) atomicOr(&errs[it.env], ERR_OUT_OF_DOMAIN);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);
+  int pos = 0;
+  const bool fits = bx.fits && pull_index<BOXN>(bsh, ps, bx, sc.b, valid, pos);
+  if (valid) p2g_pull_particle(e, mat, sc, fits, pos, vn, Cn, Hn, ps.pay, grid_out);
+  if (!fits) {
+    if (valid) mark_particle_tiles(e, sc.b, flags_out);
+    return;
+  }
+  __syncthreads();
+  p2g_pull_owners<BOXN>(e, bsh, ps, bx.nodes, grid_out, flags_out);
+}
+
+template <int BOXN, int MAT>
+__global__ void __launch_bounds__(256) k_g2p2g_pull(const float* __restrict__ st, float* __restrict__ out, int64_t N,
+                                                    const EnvDev* __restrict__ envs,
+                                                    const WorkItem* __restrict__ items,
+                                                    const float* __restrict__ grid_in, float* __restrict__ grid_out,
+                                                    uint32_t* __restrict__ flags_out, int32_t* __restrict__ errs,
+                                                    int k_call) {
+  g2p2g_pull_item<BOXN, MAT>(blockIdx.x, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, k_call);
+}
+
+template <int BOXN>
+static void launch_g2p2g_pull_m(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items,
+                                int n_items, const float* grid_in, float* grid_out, uint32_t* flags_out,
+                                int32_t* errs, int k_call, hipStream_t s, int mat) {
+  const dim3 g(n_items), blk(256);
+#define G2P2G_PULL(M) \
+  hipLaunchKernelGGL((k_g2p2g_pull<BOXN, M>), g, blk, 0, s, st, out, N, envs, items, grid_in, grid_out, flags_out, errs, k_call)
+  switch (mat) {
+    case MAT_NEOHOOKEAN: G2P2G_PULL(MAT_NEOHOOKEAN); break;
+    case MAT_COROTATED: G2P2G_PULL(MAT_COROTATED); break;
+    case MAT_VONMISES: G2P2G_PULL(MAT_VONMISES); break;
+    case MAT_FLUID_TAIT: G2P2G_PULL(MAT_FLUID_TAIT); break;
+    case MAT_FLUID_PAPER: G2P2G_PULL(MAT_FLUID_PAPER); break;
+    case -1: G2P2G_PULL(-1); break;
+    default: break;
+  }
+#undef G2P2G_PULL
+}
+
+void launch_g2p2g_pull(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
+                       const float* grid_in, float* grid_out, uint32_t* flags_out, int32_t* errs, int k_call, int box,
+                       int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_g2p2g_pull_m<kPullSmall>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, k_call, s, mat);
+  else
+    launch_g2p2g_pull_m<kPullNodes>(st, out, N, envs, items, n_items, grid_in, grid_out, flags_out, errs, k_call, s, mat);
 }
 
 // one block per work item, or (PERSIST) a grid that strides over the items

@@ -261,12 +261,20 @@ void batched_g2p2g(mpm_batch* b, const float* in, float* out, int gi_in, int gi_
   const hipStream_t s = b->stream;
   const int runs = b->min_run | (b->max_run << 16);
   Span sp(b, KC_G2P2G);
-  for (const auto& r : launch_ranges(b))
-    launch_g2p2g(in, out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->grid[gi_in],
-                 b->grid[gi_out], b->flags[gi_out], b->errs, runs, kc, b->box, r.mat, s);
+  for (const auto& r : launch_ranges(b)) {
+    if (b->var_p2g == 3)
+      launch_g2p2g_pull(in, out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->grid[gi_in],
+                        b->grid[gi_out], b->flags[gi_out], b->errs, kc, b->box, r.mat, s);
+    else
+      launch_g2p2g(in, out, b->N, b->envs_d, b->items_mat_d + r.first, r.count, b->grid[gi_in],
+                   b->grid[gi_out], b->flags[gi_out], b->errs, runs, kc, b->box, r.mat, s);
+  }
 }
 
-bool fused(const mpm_batch* b) { return b->mode != MPM_MODE_PLAIN && b->fuse && b->var_p2g == 2; }
+// the forward fusion pairs the G2P with the per-cell-run or the pull scatter
+bool fused(const mpm_batch* b) {
+  return b->mode != MPM_MODE_PLAIN && b->fuse && (b->var_p2g == 2 || b->var_p2g == 3);
+}
 
 void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k_rel, int kc) {
   float* g = b->grid[gi];

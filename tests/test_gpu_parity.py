@@ -436,7 +436,7 @@ def test_backward_needs_a_recorded_forward():
 
 # ------------------------------------------------------------------ per-env substep counts and slot reuse
 @pytest.mark.parametrize("counts", [[7, 3], [7, 4]], ids=["stop-at-segment-end", "stop-inside-segment"])
-@pytest.mark.parametrize("fused", [0, 1], ids=["unfused", "fused"])
+@pytest.mark.parametrize("fused", [0, 1, 2], ids=["unfused", "fused", "pull-fused"])
 def test_per_env_substep_counts_match_separate_runs(counts, fused):
     from paper_2412_12089_amd import _capi as C
     from paper_2412_12089_amd.batch import Batch
@@ -446,8 +446,11 @@ def test_per_env_substep_counts_match_separate_runs(counts, fused):
     cots = random_cotangents(envs, seed=92)
     announce(f"forward_envs with counts {counts} (fused kernels {fused}) vs separate runs")
     bt = Batch(envs, max_substeps=8, ckpt_every=3)
-    bt.set_option(C.OPT_FUSE, fused)
-    bt.set_option(C.OPT_FUSE_ADJ, fused)
+    bt.set_option(C.OPT_FUSE, 1 if fused else 0)
+    bt.set_option(C.OPT_FUSE_ADJ, 1 if fused == 1 else 0)
+    if fused == 2:   # the pull scatters, forward fused (G2P + pull P2G)
+        bt.set_option(C.OPT_P2G, 3)
+        bt.set_option(C.OPT_G2P_ADJ, 3)
     bt.set_particles_from_specs()
     bt.forward_envs(counts, record=True)
     st = [t.cpu().double().numpy() for t in bt.get_particles()]
@@ -507,6 +510,8 @@ VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, pe
     # owner-computes (pull) scatters through LDS: both box budgets, persistent grid, generic launch, XCD order
     (3, 1, 3, 1, 0, 0, 1, 0, 0), (3, 1, 3, 1, 0, 1, 1, 0, 0), (3, 0, 3, 0, 5, 0, 0, 0, 0), (3, 1, 3, 1, 0, 1, 0, 0, 0, 1),
     (3, 1, 3, 1, 0, 0, 1, 1, 1),
+    # the pull P2G fused with the G2P: both box budgets, generic launch
+    (3, 0, 3, 1, 0, 1, 1, 1, 0), (3, 1, 3, 1, 0, 0, 0, 1, 0), (3, 1, 3, 1, 0, 0, 1, 1, 0, 1),
 ]
 
 

@@ -283,8 +283,9 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
                                   the autotuner may set it */
 #define MPM_OPT_FUSE_ADJ 12    /* 1: within a segment's backward, the P2G adjoint of substep k and the G2P
                                   adjoint of substep k - 1 run as one kernel (the cotangent of state k stays
-                                  in registers; the G2P adjoint part is the segment-reduced one). Batched
-                                  mode. Default 0; the autotuner may set it */
+                                  in registers; the G2P adjoint part is the pull scatter when
+                                  MPM_OPT_G2P_ADJ = 3, else the segment-reduced one). Batched mode.
+                                  Default 0; the autotuner may set it */
 #define MPM_OPT_XCD 13         /* LDS-staged kernels: 1 = each launch's work items are ordered so that the
                                   blocks one XCD receives (block i goes to XCD i mod 8) take a contiguous
                                   run of items, keeping an env's grid lines in one XCD's L2; 0 = item

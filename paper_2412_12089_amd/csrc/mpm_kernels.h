@@ -114,6 +114,10 @@ void launch_g2p2g(const float* st, float* out, int64_t N, const EnvDev* envs, co
 // substep k's call index; st_prev / st: states k - 1 and k; grid_prev: substep
 // k - 1's grid; gcot: channels 3-6 read, 0-2 scattered into; part: substep k's
 // partials in, substep k - 1's out; cot_end: state-k cotangent of envs frozen at k)
+// P2G adjoint of substep k fused with the pull G2P adjoint of substep k - 1
+void launch_adj_pair_pull(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
+                          const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev, float* gcot,
+                          double* pacc, int k_call, int box, int mat, hipStream_t s);
 void launch_adj_pair(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
                      const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev, float* gcot,
                      double* pacc, int runs, int k_call, int box, int mat, hipStream_t s);

@@ -2090,6 +2090,236 @@ void launch_adj_pair(const float* st_prev, const float* st, float* part, const f
     launch_adj_pair_m<kBoxNodes>(st_prev, st, part, cot_end, N, envs, items, n_items, grid_prev, gcot, pacc, runs, k_call, s, mat);
 }
 
+// P2G adjoint of substep k fused with the pull G2P adjoint of substep k - 1
+// (the low particles-per-cell form of the pair above). Phase A gathers (mbar,
+// Pbar) through an LDS box of half the pull budget; phase B scatters the
+// grid-velocity cotangent through the owner-computes boxes. The two phases
+// use the same LDS: phase B's index is built only after block_box's barriers.
+template <int BOXN>
+union PairPullShared {
+  float box[4 * (BOXN / 2)];
+  PullShared<BOXN> ps;
+};
+
+template <int BOXN, int MAT>
+MD void adj_pair_pull_item(int item_idx, const float* __restrict__ st_prev, const float* __restrict__ st, float* part,
+                           const float* __restrict__ cot_end, int64_t N, const EnvDev* __restrict__ envs,
+                           const WorkItem* __restrict__ items, const float* __restrict__ grid_prev, float* gcot,
+                           double* __restrict__ pacc, int k_call) {
+  __shared__ BoxShared bsh;
+  __shared__ PairPullShared<BOXN> u;
+  const WorkItem it = items[item_idx];
+  const EnvDev& e = envs[it.env];
+  const int mat = MAT >= 0 ? MAT : e.material;
+  if (k_call - 1 >= e.nsub) return;   // frozen at k - 1 and k
+  const int lp = lane_particle(threadIdx.x);
+  const bool valid = lp < it.count;
+  const int64_t p = it.start + (valid ? lp : 0);
+  float pb[PB_COUNT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // cotangent of state k: x, v, C, F
+  float cx[3] = {0.f, 0.f, 0.f}, cv[3] = {0.f, 0.f, 0.f};
+  M3 cC = m3_zero(), cF = m3_zero();
+  if (k_call >= e.nsub) {   // frozen at k (uniform over the block)
+    if (valid) {
+      for (int a = 0; a < 3; ++a) { cx[a] = cot_end[a * N + p]; cv[a] = cot_end[(3 + a) * N + p]; }
+      cC = ld_m3(cot_end, N, p, 6);
+      cF = ld_m3(cot_end, N, p, 15);
+    }
+  } else {
+    // ---- phase A: P2G adjoint of substep k ----
+    float x[3];
+    load_x3(st, N, p, x);
+    const Stencil sc = make_stencil(x, e.n, e.fn);
+    const Box bx = block_box<BOXN / 2>(e, sc.b, valid, lp, it.count, bsh);
+    if (bx.fits) box_load(e, bx, bsh, gcot, 3, 4, u.box);
+    __syncthreads();
+    if (valid) {
+      const float kf = -e.dt * e.vp * 4.f * e.fn * e.fn;
+      const float v[3] = {st[3 * N + p], st[4 * N + p], st[5 * N + p]};
+      const M3 Cm = ld_m3(st, N, p, 6);
+      const M3 H = ld_m3(st, N, p, 15);
+      const M3 A = m3_axpy(m3_scale(Cm, e.mp), kf, stress(e, H, mat));
+      float xb[3] = {part[p], part[N + p], part[2 * N + p]};
+      float sP[3] = {0.f, 0.f, 0.f};   // sum of W Pbar
+      float sm = 0.f;                  // sum of W mbar
+      M3 Ab = m3_zero();               // sum of W Pbar d^T
+#pragma unroll 1
+      for (int ox = 0; ox < 3; ++ox)
+#pragma unroll 1
+        for (int oy = 0; oy < 3; ++oy) {
+          float mb[3], Pb[3][3];
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz) {
+            if (bx.fits) {
+              const int idx = box_index(bx, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+              mb[oz] = u.box[idx];
+              for (int a = 0; a < 3; ++a) Pb[oz][a] = u.box[(1 + a) * bx.nodes + idx];
+            } else {
+              const float* gc = gcot + node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+              mb[oz] = gc[3 * CH];
+              for (int a = 0; a < 3; ++a) Pb[oz][a] = gc[(4 + a) * CH];
+            }
+          }
+          float wx, wy, dwx, dwy;
+          spline_piece(ox, sc.f[0], wx, dwx);
+          spline_piece(oy, sc.f[1], wy, dwy);
+          const float wxy = wx * wy, gxw = e.fn * dwx * wy, gyw = e.fn * wx * dwy;
+          const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+          float uc[3], cP[3] = {0.f, 0.f, 0.f}, cPz[3] = {0.f, 0.f, 0.f};
+          for (int a = 0; a < 3; ++a) uc[a] = fmaf(A.m[a][0], d0, fmaf(A.m[a][1], d1, e.mp * v[a]));
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz) {
+            const float wz = sc.w[2][oz], dz = ((float)oz - sc.f[2]) * e.dx;
+            const float W = wxy * wz, Wd = W * dz;
+            const float gW[3] = {gxw * wz, gyw * wz, wxy * e.fn * sc.dw[2][oz]};
+            float gw = e.mp * mb[oz];
+            for (int a = 0; a < 3; ++a) gw = fmaf(Pb[oz][a], fmaf(A.m[a][2], dz, uc[a]), gw);
+            sm = fmaf(W, mb[oz], sm);
+            for (int a = 0; a < 3; ++a) {
+              cP[a] = fmaf(W, Pb[oz][a], cP[a]);
+              cPz[a] = fmaf(Wd, Pb[oz][a], cPz[a]);
+              xb[a] = fmaf(gW[a], gw, xb[a]);
+            }
+          }
+          for (int a = 0; a < 3; ++a) {
+            sP[a] += cP[a];
+            Ab.m[a][0] = fmaf(cP[a], d0, Ab.m[a][0]);
+            Ab.m[a][1] = fmaf(cP[a], d1, Ab.m[a][1]);
+            Ab.m[a][2] += cPz[a];
+          }
+        }
+      // the stencil sum of -W A^T Pbar is -A^T sP
+      for (int a = 0; a < 3; ++a) xb[a] -= A.m[0][a] * sP[0] + A.m[1][a] * sP[1] + A.m[2][a] * sP[2];
+      const StressPrep spr = stress_prep(e, H, mat);
+      const M3 tau = stress_from(e, spr, mat);
+      const float mpb = sm + v[0] * sP[0] + v[1] * sP[1] + v[2] * sP[2] + m3_ddot(Cm, Ab);
+      for (int a = 0; a < 3; ++a) { cx[a] = xb[a]; cv[a] = e.mp * sP[a]; }
+      cC = m3_scale(Ab, e.mp);
+      const M3 taub = m3_scale(Ab, kf);
+      pb[PB_VP] += (-e.dt * 4.f * e.fn * e.fn) * m3_ddot(Ab, tau);
+      pb[PB_MP] += mpb;
+      cF = ld_m3(part, N, p, 3);
+      stress_vjp_from(e, H, spr, taub, cF, pb, mat);
+    }
+  }
+  // ---- phase B: G2P adjoint of substep k - 1 (state k - 1 -> state k) through the pull scatter ----
+  float x[3];
+  load_x3(st_prev, N, p, x);
+  const Stencil sc = make_stencil(x, e.n, e.fn);
+  const Box bx = block_box<BOXN>(e, sc.b, valid, lp, it.count, bsh);   // synchronizes: phase A is done
+  int pos = 0;
+  const bool fits = bx.fits && pull_index<BOXN>(bsh, u.ps, bx, sc.b, valid, pos);
+  if (valid) {
+    const M3 H = ld_m3(st_prev, N, p, 15);
+    const M3 F = f_of(H);
+    const float D4 = 4.f * e.fn * e.fn;
+    const M3 Cn = load_cnext(st, N, p);   // C of state k, the substep's own output
+    const M3 G = m3_axpy(m3_eye(), e.dt, Cn);
+    const M3 Htr = trial_h(e, Cn, H);
+    float xb[3], vb[3];
+    for (int a = 0; a < 3; ++a) { xb[a] = cx[a]; vb[a] = cv[a] + e.dt * cx[a]; }
+    const M3 Ftrb = project_vjp(e, Htr, cF, pb, mat);
+    const M3 Cb = m3_axpy(cC, e.dt, m3_mul_abt(Ftrb, F));
+    const M3 Fb = m3_mul_atb(G, Ftrb);
+    st_m3(part, N, p, 3, Fb);
+    if (fits) {
+      float Ad[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) Ad[a][c] = D4 * e.dx * Cb.m[a][c];
+      pull_store_payload(u.ps.pay, pos, sc.f, sc.b[2], vb, Ad);
+    }
+    float sv[3] = {0.f, 0.f, 0.f};   // sum of W v_i
+    float gz[3], cz[3];
+    for (int o = 0; o < 3; ++o) gz[o] = e.fn * sc.dw[2][o];
+    for (int a = 0; a < 3; ++a) cz[a] = D4 * Cb.m[a][2];
+#pragma unroll 1
+    for (int ox = 0; ox < 3; ++ox)
+#pragma unroll 1
+      for (int oy = 0; oy < 3; ++oy) {
+        const float wx = sel3(sc.w[0], ox), wy = sel3(sc.w[1], oy);
+        const float wxy = wx * wy, gx = e.fn * sel3(sc.dw[0], ox) * wy, gy = e.fn * wx * sel3(sc.dw[1], oy);
+        const float d0 = ((float)ox - sc.f[0]) * e.dx, d1 = ((float)oy - sc.f[1]) * e.dx;
+        float gc[3];
+        for (int a = 0; a < 3; ++a) gc[a] = fmaf(D4, fmaf(Cb.m[a][0], d0, Cb.m[a][1] * d1), vb[a]);
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+          const float wz = sc.w[2][oz];
+          const float W = wxy * wz;
+          const float gW[3] = {gx * wz, gy * wz, wxy * gz[oz]};
+          const float d2 = ((float)oz - sc.f[2]) * e.dx;
+          float vi[3], gv[3];
+          for (int a = 0; a < 3; ++a) gv[a] = fmaf(cz[a], d2, gc[a]);
+          const int64_t nb = node_base(e, sc.b[0] + ox, sc.b[1] + oy, sc.b[2] + oz);
+          for (int a = 0; a < 3; ++a) vi[a] = grid_prev[nb + (4 + a) * CH];
+          if (!fits)
+            for (int a = 0; a < 3; ++a) atomicAdd(gcot + nb + a * CH, W * gv[a]);
+          const float vg = vi[0] * gv[0] + vi[1] * gv[1] + vi[2] * gv[2];
+          for (int a = 0; a < 3; ++a) {
+            xb[a] = fmaf(gW[a], vg, xb[a]);
+            sv[a] = fmaf(W, vi[a], sv[a]);
+          }
+        }
+      }
+    for (int a = 0; a < 3; ++a) xb[a] -= D4 * (Cb.m[0][a] * sv[0] + Cb.m[1][a] * sv[1] + Cb.m[2][a] * sv[2]);
+    for (int a = 0; a < 3; ++a) part[a * N + p] = xb[a];
+  }
+  if (fits) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < bx.nodes; idx += blockDim.x) {
+      int r, i, j, k;
+      box_node_run(bsh, idx, r, i, j, k);
+      float acc[3] = {0.f, 0.f, 0.f}, wsum = 0.f;
+      pull_node(bsh, u.ps.start, u.ps.coff, u.ps.cext, u.ps.pay, r, i, j, k, acc, wsum);
+      if (wsum == 0.f) continue;
+      float* dst = gcot + node_base(e, i, j, k);
+      for (int a = 0; a < 3; ++a)
+        if (acc[a] != 0.f) atomicAdd(dst + a * CH, acc[a]);
+    }
+  }
+  block_reduce_params_lds(pb, pacc + (int64_t)it.env * 8);
+}
+
+template <int BOXN, int MAT>
+__global__ void __launch_bounds__(256)
+k_adj_pair_pull(const float* __restrict__ st_prev, const float* __restrict__ st, float* part,
+                const float* __restrict__ cot_end, int64_t N, const EnvDev* __restrict__ envs,
+                const WorkItem* __restrict__ items, const float* __restrict__ grid_prev, float* gcot,
+                double* __restrict__ pacc, int k_call) {
+  adj_pair_pull_item<BOXN, MAT>(blockIdx.x, st_prev, st, part, cot_end, N, envs, items, grid_prev, gcot, pacc, k_call);
+}
+
+template <int BOXN>
+static void launch_adj_pair_pull_m(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
+                                   const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev,
+                                   float* gcot, double* pacc, int k_call, hipStream_t s, int mat) {
+  const dim3 g(n_items), blk(256);
+#define ADJ_PAIR_PULL(M) \
+  hipLaunchKernelGGL((k_adj_pair_pull<BOXN, M>), g, blk, 0, s, st_prev, st, part, cot_end, N, envs, items, grid_prev, \
+                     gcot, pacc, k_call)
+  switch (mat) {
+    case MAT_NEOHOOKEAN: ADJ_PAIR_PULL(MAT_NEOHOOKEAN); break;
+    case MAT_COROTATED: ADJ_PAIR_PULL(MAT_COROTATED); break;
+    case MAT_VONMISES: ADJ_PAIR_PULL(MAT_VONMISES); break;
+    case MAT_FLUID_TAIT: ADJ_PAIR_PULL(MAT_FLUID_TAIT); break;
+    case MAT_FLUID_PAPER: ADJ_PAIR_PULL(MAT_FLUID_PAPER); break;
+    case -1: ADJ_PAIR_PULL(-1); break;
+    default: break;
+  }
+#undef ADJ_PAIR_PULL
+}
+
+void launch_adj_pair_pull(const float* st_prev, const float* st, float* part, const float* cot_end, int64_t N,
+                          const EnvDev* envs, const WorkItem* items, int n_items, const float* grid_prev, float* gcot,
+                          double* pacc, int k_call, int box, int mat, hipStream_t s) {
+  if (n_items == 0) return;
+  if (box)
+    launch_adj_pair_pull_m<kPullSmall>(st_prev, st, part, cot_end, N, envs, items, n_items, grid_prev, gcot, pacc,
+                                       k_call, s, mat);
+  else
+    launch_adj_pair_pull_m<kPullNodes>(st_prev, st, part, cot_end, N, envs, items, n_items, grid_prev, gcot, pacc,
+                                       k_call, s, mat);
+}
+
 template <int BOXN, int MAT>
 static void launch_p2g_lds_t(const float* st, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items, float* grid,
                     uint32_t* flags, int32_t* errs, int k_call, int grid_cap, hipStream_t s) {

@@ -334,9 +334,14 @@ void batched_adj_pair(mpm_batch* b, const float* st_prev, const float* st, const
   const hipStream_t s = b->stream;
   const int runs = b->min_run | (b->max_run << 16);
   Span sp(b, KC_ADJ_PAIR);
-  for (const auto& r : launch_ranges(b))
-    launch_adj_pair(st_prev, st, b->part, cot_end, b->N, b->envs_d, b->items_mat_d + r.first,
-                    r.count, b->grid[gi_prev], b->gcot, b->pacc, runs, kc, b->box, r.mat, s);
+  for (const auto& r : launch_ranges(b)) {
+    if (b->var_g2p_adj == 3)
+      launch_adj_pair_pull(st_prev, st, b->part, cot_end, b->N, b->envs_d, b->items_mat_d + r.first, r.count,
+                           b->grid[gi_prev], b->gcot, b->pacc, kc, b->box, r.mat, s);
+    else
+      launch_adj_pair(st_prev, st, b->part, cot_end, b->N, b->envs_d, b->items_mat_d + r.first,
+                      r.count, b->grid[gi_prev], b->gcot, b->pacc, runs, kc, b->box, r.mat, s);
+  }
 }
 
 bool fused_adj(const mpm_batch* b) { return b->mode != MPM_MODE_PLAIN && b->fuse_adj; }

@@ -447,8 +447,8 @@ def test_per_env_substep_counts_match_separate_runs(counts, fused):
     announce(f"forward_envs with counts {counts} (fused kernels {fused}) vs separate runs")
     bt = Batch(envs, max_substeps=8, ckpt_every=3)
     bt.set_option(C.OPT_FUSE, 1 if fused else 0)
-    bt.set_option(C.OPT_FUSE_ADJ, 1 if fused == 1 else 0)
-    if fused == 2:   # the pull scatters, forward fused (G2P + pull P2G)
+    bt.set_option(C.OPT_FUSE_ADJ, 1 if fused else 0)
+    if fused == 2:   # the pull scatters, both fusions (G2P + pull P2G, P2G adjoint + pull G2P adjoint)
         bt.set_option(C.OPT_P2G, 3)
         bt.set_option(C.OPT_G2P_ADJ, 3)
     bt.set_particles_from_specs()
@@ -510,8 +510,10 @@ VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, pe
     # owner-computes (pull) scatters through LDS: both box budgets, persistent grid, generic launch, XCD order
     (3, 1, 3, 1, 0, 0, 1, 0, 0), (3, 1, 3, 1, 0, 1, 1, 0, 0), (3, 0, 3, 0, 5, 0, 0, 0, 0), (3, 1, 3, 1, 0, 1, 0, 0, 0, 1),
     (3, 1, 3, 1, 0, 0, 1, 1, 1),
-    # the pull P2G fused with the G2P: both box budgets, generic launch
+    # the pull P2G fused with the G2P, the P2G adjoint fused with the pull G2P adjoint: both box
+    # budgets, generic launch, XCD order
     (3, 0, 3, 1, 0, 1, 1, 1, 0), (3, 1, 3, 1, 0, 0, 0, 1, 0), (3, 1, 3, 1, 0, 0, 1, 1, 0, 1),
+    (3, 0, 3, 1, 0, 1, 1, 0, 1), (3, 1, 3, 1, 0, 0, 0, 1, 1), (3, 1, 3, 1, 0, 1, 0, 1, 1, 1),
 ]
 
 

@@ -84,7 +84,8 @@ MD FwdLds fwd_lds(float* base, int n, int T) {
 }
 
 // the backward block: x, v of state k [3n each], their cotangents [3n each], u = dt/m vbar_tot [3n], per-element
-// (D_s cotangent, D_v cotangent) columns [18T], lumped volume [n], incidence offsets [n + 1], incidences [4T]
+// cotangent columns [9T] (those of D_s, then of D_v, gathered one after the other), lumped volume [n], incidence
+// offsets [n + 1], incidences [4T]
 struct BwdLds {
   float *xs, *vs, *xb, *vb, *us, *tb, *ws;
   int *ioff, *inc;
@@ -97,7 +98,7 @@ MD BwdLds bwd_lds(float* base, int n, int T) {
   L.vb = L.xb + 3 * n;
   L.us = L.vb + 3 * n;
   L.tb = L.us + 3 * n;
-  L.ws = L.tb + 18 * T;
+  L.ws = L.tb + 9 * T;
   L.ioff = reinterpret_cast<int*>(L.ws + n);
   L.inc = L.ioff + n + 1;
   return L;
@@ -313,13 +314,29 @@ __global__ void __launch_bounds__(kFemThreads) k_fem_backward(FemMesh m, int S, 
   load_own_tets<TPT>(m, e, own);
   // per-thread parameter cotangents: mu, lam, damp, k_e, k_d, k_f, z_g
   float pmu = 0.f, plam = 0.f, pdamp = 0.f, pke = 0.f, pkd = 0.f, pkf = 0.f, pzg = 0.f;
+  // the tape rows of this thread's nodes (n <= 2 * kFemThreads) for the next substep, read one substep ahead
+  float pf[2][6];
+  auto prefetch = [&](int k) {
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int i = threadIdx.x + jn * kFemThreads;
+      if (k >= 0 && i < n) {
+        const float* st = tape + (((int64_t)k * E + e) * n + i) * 6;
+        for (int c = 0; c < 6; ++c) pf[jn][c] = st[c];
+      }
+    }
+  };
+  prefetch(S - 1);
   __syncthreads();
   for (int k = S - 1; k >= 0; --k) {
     // node pass 1: state k from the tape; vbar_tot = vbar' + dt xbar'; u = dt/m vbar_tot (the force
     // cotangent); ground-contact terms
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const float* st = tape + (((int64_t)k * E + e) * n + i) * 6;
-      const float3 xi = ld3(st), vi = ld3(st + 3);
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int i = threadIdx.x + jn * kFemThreads;
+      if (i >= n) continue;
+      const float3 xi = make_float3(pf[jn][0], pf[jn][1], pf[jn][2]);
+      const float3 vi = make_float3(pf[jn][3], pf[jn][4], pf[jn][5]);
       L.xs[3 * i] = xi.x; L.xs[3 * i + 1] = xi.y; L.xs[3 * i + 2] = xi.z;
       L.vs[3 * i] = vi.x; L.vs[3 * i + 1] = vi.y; L.vs[3 * i + 2] = vi.z;
       float3 xb = ld3(L.xb + 3 * i), vb = ld3(L.vb + 3 * i);
@@ -340,13 +357,16 @@ __global__ void __launch_bounds__(kFemThreads) k_fem_backward(FemMesh m, int S, 
       L.xb[3 * i] = xb.x; L.xb[3 * i + 1] = xb.y; L.xb[3 * i + 2] = xb.z;
       L.vb[3 * i] = vb.x; L.vb[3 * i + 1] = vb.y; L.vb[3 * i + 2] = vb.z;
     }
+    prefetch(k - 1);   // in flight during the element pass
     __syncthreads();
     // element pass: with G = Ubar B_m (Ubar the edge differences of u), the element's share of the
     // loss is -W P : G; its cotangents are Fbar = -W dP[G] (the energy Hessian is symmetric),
     // Fdot_bar = -W damp G, and the activation's W lam cof(F) : G
+    M3 dvb[TPT];   // the D_v cotangent columns wait in registers for the second gather
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int t = threadIdx.x + q * kFemThreads;
+      dvb[q] = m3_zero();
       if (t >= T) continue;
       const int64_t ai = ((int64_t)k * E + e) * T + t;
       const float a = tape_act[ai];
@@ -371,24 +391,35 @@ __global__ void __launch_bounds__(kFemThreads) k_fem_backward(FemMesh m, int S, 
           Fb.m[i][j] = -Wt * dP;
           Fdb.m[i][j] = -Wt * p.damp * G.m[i][j];
         }
-      const M3 Dsb = m3_mul_abt(Fb, B), Dvb = m3_mul_abt(Fdb, B);
-      float* h = L.tb + t * 18;
+      const M3 Dsb = m3_mul_abt(Fb, B);
+      dvb[q] = m3_mul_abt(Fdb, B);
+      float* h = L.tb + t * 9;
       for (int c = 0; c < 3; ++c)
-        for (int rr = 0; rr < 3; ++rr) {
-          h[3 * c + rr] = Dsb.m[rr][c];
-          h[9 + 3 * c + rr] = Dvb.m[rr][c];
-        }
+        for (int rr = 0; rr < 3; ++rr) h[3 * c + rr] = Dsb.m[rr][c];
       if (dact) dact[ai] = Wt * p.lam * cG;
       pmu -= Wt * ((1.f - ic1) * FG - 0.75f * cG);
       plam -= Wt * (J - p.alpha - a + 0.75f * p.mu / p.lam) * cG;
       pdamp -= Wt * ddot(Fd, G);
     }
     __syncthreads();
-    // node pass 2: the element cotangents gathered onto the nodes give the cotangent of state k
+    // node pass 2: the element cotangents gathered onto the nodes give the cotangent of state k, the
+    // D_s columns first, then (through the same LDS) the D_v columns
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const float3 sx = gather_columns(L.tb, 18, L.ioff, L.inc, i);
-      const float3 sv = gather_columns(L.tb + 9, 18, L.ioff, L.inc, i);
+      const float3 sx = gather_columns(L.tb, 9, L.ioff, L.inc, i);
       L.xb[3 * i] += sx.x; L.xb[3 * i + 1] += sx.y; L.xb[3 * i + 2] += sx.z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int t = threadIdx.x + q * kFemThreads;
+      if (t >= T) continue;
+      float* h = L.tb + t * 9;
+      for (int c = 0; c < 3; ++c)
+        for (int rr = 0; rr < 3; ++rr) h[3 * c + rr] = dvb[q].m[rr][c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const float3 sv = gather_columns(L.tb, 9, L.ioff, L.inc, i);
       L.vb[3 * i] += sv.x; L.vb[3 * i + 1] += sv.y; L.vb[3 * i + 2] += sv.z;
     }
     // the next iteration's node pass 1 touches only this thread's own nodes, and its element pass
@@ -447,7 +478,7 @@ int tets_per_thread(int T) {
 using namespace fem;
 
 size_t fem_forward_lds(int n, int T) { return sizeof(float) * (size_t)(8 * n + 13 * T + 1); }
-size_t fem_backward_lds(int n, int T) { return sizeof(float) * (size_t)(17 * n + 22 * T + 1); }
+size_t fem_backward_lds(int n, int T) { return sizeof(float) * (size_t)(17 * n + 13 * T + 1); }
 
 void launch_fem_rest(const FemMesh& m, const float* X, float* Bm, float* W, float* wm, int32_t* bad,
                      hipStream_t s) {

@@ -63,7 +63,7 @@ KERNEL_SYMBOL = {"p2g": {0: "k_p2g_direct", 1: "k_p2g_lds", 2: "k_p2g_seg", 3: "
                  "p2g_adj": {0: "k_p2g_adjoint_direct", 1: "k_p2g_adjoint_lds"},
                  "g2p2g": {1: "k_g2p2g", 2: "k_g2p2g_pull"}, "adj_pair": {1: "k_adj_pair"}}
 OPTION_NAMES = ("P2G", "G2P", "G2P_ADJ", "P2G_ADJ", "MIN_RUN", "GRID_CAP", "MAX_RUN", "BOX", "SPECIALIZE", "FUSE",
-                "FUSE_ADJ", "XCD")
+                "FUSE_ADJ", "XCD", "GRID_LIST")
 
 
 def kernel_source_sha() -> str:

@@ -50,7 +50,7 @@ MPM_FEM_PARAMS = 8
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
- OPT_FUSE, OPT_FUSE_ADJ, OPT_XCD) = range(1, 14)
+ OPT_FUSE, OPT_FUSE_ADJ, OPT_XCD, OPT_GRID_LIST) = range(1, 15)
 
 
 class mpm_env_desc(ctypes.Structure):

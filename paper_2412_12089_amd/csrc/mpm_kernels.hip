@@ -557,15 +557,10 @@ MD bool is_wall(const EnvDev& e, int i, int j, int k) {
 }
 
 
-__global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ envs,
-                                                     const int32_t* __restrict__ tile_env, int64_t tile0,
-                                                     int64_t ntiles, float* __restrict__ grid,
-                                                     uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
-                                                     double t0, int k_rel, int clear, const float* __restrict__ motion) {
-  const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
-  if (tile >= tile0 + ntiles) return;
-  if (flags[tile] == 0u) return;
+// one flagged tile (one wave, lane l = node) of the grid update
+MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restrict__ tile_env, int64_t tile, int l,
+                         float* __restrict__ grid, uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
+                         double t0, int k_rel, int clear, const float* __restrict__ motion) {
   const int ei = tile_env[tile];
   const EnvDev& e = envs[ei];
   int i, j, k;
@@ -601,18 +596,49 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
   }
 }
 
-// reads vbar (channels 0-2 of gcot), writes mbar (3) and Pbar (4-6), clears
-// vbar and the tape grid of this substep (and its flag)
-__global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__ envs,
-                                                      const int32_t* __restrict__ tile_env, int64_t tile0,
-                                                      int64_t ntiles, float* __restrict__ grid,
-                                                      uint32_t* __restrict__ flags, float* __restrict__ gcot,
-                                                      const int32_t* __restrict__ clock, double t0, int k_rel,
-                                                      const float* __restrict__ motion, double* __restrict__ gmotion) {
+__global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ envs,
+                                                     const int32_t* __restrict__ tile_env, int64_t tile0,
+                                                     int64_t ntiles, float* __restrict__ grid,
+                                                     uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
+                                                     double t0, int k_rel, int clear, const float* __restrict__ motion) {
   const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
   if (tile >= tile0 + ntiles) return;
   if (flags[tile] == 0u) return;
+  grid_update_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
+}
+
+// the same, 64 tiles per block: one wave's ballot finds the flagged ones and the block's four waves take
+// them in turn (far fewer blocks than one per 4 tiles when few tiles are flagged)
+__global__ void __launch_bounds__(256) k_grid_update_chunk(const EnvDev* __restrict__ envs,
+                                                           const int32_t* __restrict__ tile_env, int64_t ntiles,
+                                                           float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                           const int32_t* __restrict__ clock, double t0, int k_rel,
+                                                           int clear, const float* __restrict__ motion) {
+  __shared__ uint64_t mask_s;
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  if (threadIdx.x < 64) {
+    const int64_t tile = base + threadIdx.x;
+    const uint64_t m = __ballot(tile < ntiles && flags[tile] != 0u);
+    if (threadIdx.x == 0) mask_s = m;
+  }
+  __syncthreads();
+  uint64_t m = mask_s;
+  const int wave = threadIdx.x >> 6;
+  for (int rank = 0; m != 0ull; ++rank) {
+    const int bit = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1ull;
+    if ((rank & 3) == wave)
+      grid_update_tile(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
+  }
+}
+
+// reads vbar (channels 0-2 of gcot), writes mbar (3) and Pbar (4-6), clears
+// vbar and the tape grid of this substep (and its flag)
+// one flagged tile (one wave, lane l = node) of the grid adjoint
+MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __restrict__ tile_env, int64_t tile, int l,
+                          float* __restrict__ grid, uint32_t* __restrict__ flags, float* __restrict__ gcot,
+                          const int32_t* __restrict__ clock, double t0, int k_rel, const float* __restrict__ motion,
+                          double* __restrict__ gmotion) {
   const int ei = tile_env[tile];
   const EnvDev& e = envs[ei];
   int i, j, k;
@@ -728,6 +754,43 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
         if (l == 0 && x != 0.0) atomicAdd(&gmotion[kMotionRow * (int64_t)rw + c], x);
       }
     }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__ envs,
+                                                      const int32_t* __restrict__ tile_env, int64_t tile0,
+                                                      int64_t ntiles, float* __restrict__ grid,
+                                                      uint32_t* __restrict__ flags, float* __restrict__ gcot,
+                                                      const int32_t* __restrict__ clock, double t0, int k_rel,
+                                                      const float* __restrict__ motion, double* __restrict__ gmotion) {
+  const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= tile0 + ntiles) return;
+  if (flags[tile] == 0u) return;
+  grid_adjoint_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
+}
+
+__global__ void __launch_bounds__(256) k_grid_adjoint_chunk(const EnvDev* __restrict__ envs,
+                                                            const int32_t* __restrict__ tile_env, int64_t ntiles,
+                                                            float* __restrict__ grid, uint32_t* __restrict__ flags,
+                                                            float* __restrict__ gcot, const int32_t* __restrict__ clock,
+                                                            double t0, int k_rel, const float* __restrict__ motion,
+                                                            double* __restrict__ gmotion) {
+  __shared__ uint64_t mask_s;
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  if (threadIdx.x < 64) {
+    const int64_t tile = base + threadIdx.x;
+    const uint64_t m = __ballot(tile < ntiles && flags[tile] != 0u);
+    if (threadIdx.x == 0) mask_s = m;
+  }
+  __syncthreads();
+  uint64_t m = mask_s;
+  const int wave = threadIdx.x >> 6;
+  for (int rank = 0; m != 0ull; ++rank) {
+    const int bit = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1ull;
+    if ((rank & 3) == wave)
+      grid_adjoint_tile(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion,
+                        gmotion);
   }
 }
 
@@ -1089,6 +1152,20 @@ void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t ti
   if (ntiles == 0) return;
   hipLaunchKernelGGL(k_grid_adjoint, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid,
                      flags, gcot, clock, t0, k_rel, motion, gmotion);
+}
+void launch_grid_update_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
+                                uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear,
+                                const float* motion, hipStream_t s) {
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_grid_update_chunk, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env, ntiles,
+                     grid, flags, clock, t0, k_rel, clear, motion);
+}
+void launch_grid_adjoint_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
+                                 uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel,
+                                 const float* motion, double* gmotion, hipStream_t s) {
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_grid_adjoint_chunk, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env, ntiles,
+                     grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
 }
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s) {
   if (ntiles == 0) return;

@@ -114,6 +114,7 @@ struct mpm_batch {
   int fuse = 0;       // 1: G2P of substep k and P2G of substep k + 1 in one kernel (with the segment P2G)
   int fuse_adj = 0;   // 1: P2G adjoint of substep k and G2P adjoint of substep k - 1 in one kernel
   int xcd = 0;        // 1: order each launch's items so that the blocks one XCD receives take a contiguous run
+  int grid_list = 0;  // 1: the grid passes take 64 tiles per block and run only the flagged ones
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -241,8 +242,12 @@ void batched_p2g(mpm_batch* b, const float* in, int gi, int kc) {
 
 void batched_grid(mpm_batch* b, int gi, int clear, int k_rel) {
   Span sp(b, KC_GRID);
-  launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0, k_rel, clear,
-                     b->motion_d, b->stream);
+  if (b->grid_list)
+    launch_grid_update_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0,
+                               k_rel, clear, b->motion_d, b->stream);
+  else
+    launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0, k_rel,
+                       clear, b->motion_d, b->stream);
 }
 
 void batched_g2p(mpm_batch* b, const float* in, float* out, int gi, int kc) {
@@ -314,8 +319,12 @@ void batched_g2p_adj(mpm_batch* b, const float* st, const float* st_next, const 
 
 void batched_grid_adj(mpm_batch* b, int gi, int k_rel) {
   Span sp(b, KC_GRID_ADJ);
-  launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock, 0.0, k_rel,
-                      b->motion_d, b->gmotion_d, b->stream);
+  if (b->grid_list)
+    launch_grid_adjoint_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock,
+                                0.0, k_rel, b->motion_d, b->gmotion_d, b->stream);
+  else
+    launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock, 0.0,
+                        k_rel, b->motion_d, b->gmotion_d, b->stream);
 }
 
 void batched_p2g_adj(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int kc) {
@@ -632,7 +641,9 @@ void* batch_stream(const mpm_batch* b) { return (void*)b->stream; }
 
 namespace {
 
-struct TuneChoice { int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj, xcd; };
+struct TuneChoice {
+  int p2g, g2p, g2p_adj, p2g_adj, min_run, grid_cap, max_run, box, specialize, fuse, fuse_adj, xcd, grid_list;
+};
 
 // shape signature -> choice, shared by batches of the same shape in the process
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -656,6 +667,7 @@ void apply_choice(mpm_batch* b, const TuneChoice& c) {
   b->specialize = c.specialize;
   b->fuse = c.fuse;
   b->fuse_adj = c.fuse_adj;
+  b->grid_list = c.grid_list;
   if (b->xcd != c.xcd) {
     b->xcd = c.xcd;
     (void)upload_items(b);
@@ -1227,6 +1239,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE: if (value < 0 || value > 1) break; b->fuse = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE_ADJ: if (value < 0 || value > 1) break; b->fuse_adj = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_GRID_LIST: if (value < 0 || value > 1) break; b->grid_list = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_XCD: {
       if (value < 0 || value > 1) break;
       b->xcd = value;
@@ -1255,6 +1268,7 @@ int mpm_get_option(mpm_batch* b, int32_t option, int32_t* value) {
     case MPM_OPT_FUSE: *value = b->fuse; return MPM_OK;
     case MPM_OPT_FUSE_ADJ: *value = b->fuse_adj; return MPM_OK;
     case MPM_OPT_XCD: *value = b->xcd; return MPM_OK;
+    case MPM_OPT_GRID_LIST: *value = b->grid_list; return MPM_OK;
     default: return fail(b, MPM_INVALID_ARG, "unknown option");
   }
 }
@@ -1332,7 +1346,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() > budget_ms;
   };
   // reference results: one thread per particle, global atomics
-  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0, 0, 0};
+  TuneChoice best{0, 0, 0, 0, b->min_run, 0, b->max_run, 0, 1, 0, 0, 0, 0};
   apply_choice(b, best);
   int rc = run_fwd(ref);
   if (!rc) rc = run_bwd(gref);
@@ -1364,6 +1378,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.fuse, 0, 0, true}, {&best.fuse, 1, 0, true}},
       {{&best.fuse_adj, 0, 0, true}, {&best.fuse_adj, 1, 0, true}},
       {{&best.xcd, 0, 0, true}, {&best.xcd, 1, 0, true}},
+      {{&best.grid_list, 0, 0, true}, {&best.grid_list, 1, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

@@ -131,13 +131,17 @@ def gpu_rollout(envs, S, K, mode="batched", cots=None, timing=False):
 
     Returns dict(state=(x,v,C,F) numpy float64, grads=(dx,dv,dC,dF) or None,
     dparams=[E,8] or None, status=sync code). mode "batched-fused": the batched
-    mode with the fused G2P + P2G and adjoint-pair schedules."""
+    mode with the fused G2P + P2G and adjoint-pair schedules; "batched-pull":
+    the pull scatters with both fusions and the flagged-tile list."""
+    from paper_2412_12089_amd import _capi as C
     b = Batch(envs, max_substeps=max(S, 1), ckpt_every=K, mode=mode.split("-")[0])
     try:
-        if mode == "batched-fused":
-            from paper_2412_12089_amd import _capi as C
+        if mode in ("batched-fused", "batched-pull"):
             b.set_option(C.OPT_FUSE, 1)
             b.set_option(C.OPT_FUSE_ADJ, 1)
+        if mode == "batched-pull":
+            for opt, val in ((C.OPT_P2G, 3), (C.OPT_G2P_ADJ, 3), (C.OPT_GRID_LIST, 1)):
+                b.set_option(opt, val)
         b.set_particles_from_specs()
         b.forward(S, record=cots is not None)
         st = tuple(to_np(t) for t in b.get_particles())

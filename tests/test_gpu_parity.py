@@ -165,8 +165,15 @@ def test_edge_box_has_sliding_edge_nodes():
     assert int(edge.sum()) > 0
 
 
+def set_pull_schedule(b):
+    """The low particles-per-cell schedule: pull scatters, both fusions, the flagged-tile list."""
+    from paper_2412_12089_amd import _capi as C
+    for opt, val in ((C.OPT_P2G, 3), (C.OPT_G2P_ADJ, 3), (C.OPT_FUSE, 1), (C.OPT_FUSE_ADJ, 1), (C.OPT_GRID_LIST, 1)):
+        b.set_option(opt, val)
+
+
 @pytest.mark.parametrize("geom", ["face", "edge"])
-@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused", "batched-pull"])
 def test_collider_actions_forward_and_gradient(mode, geom):
     from paper_2412_12089_amd import _capi as C
     from paper_2412_12089_amd.batch import Batch
@@ -184,6 +191,8 @@ def test_collider_actions_forward_and_gradient(mode, geom):
         if mode == "batched-fused":   # the fused G2P + P2G and adjoint-pair schedules
             b.set_option(C.OPT_FUSE, 1)
             b.set_option(C.OPT_FUSE_ADJ, 1)
+        if mode == "batched-pull":    # the pull scatters, both fusions, grid passes over the flagged-tile list
+            set_pull_schedule(b)
         b.set_particles_from_specs()
         b.set_collider_motion(0, vel)
         b.forward(S, record=True)
@@ -215,7 +224,7 @@ SPIN_BOX = scenes.BoxCollider(center=(0.6, 0.46, 0.46), half=(0.04, 0.12, 0.2), 
                               alpha=64.0, mu_b=0.3, axis=(0.0, 0.6, 0.8), angle=0.4, omega=6.0)
 
 
-@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused", "batched-pull"])
 def test_spinning_box_forward_and_gradient(mode):
     # a box turned about a tilted axis and spinning at a constant rate, against the oracle
     spec = make_env(scenes.FLUID_TAIT, N=3000, seed=160, collider=SPIN_BOX, v_scale=0.2)
@@ -230,7 +239,7 @@ def test_spinning_box_forward_and_gradient(mode):
     check_params(g["dparams"][0], o["dparams"], [5, 2, 3], "spinning box", spec.params())
 
 
-@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused"])
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused", "batched-pull"])
 def test_spin_actions_forward_and_gradient(mode):
     # per-substep velocities and angular speeds drive the turned box; gradients w.r.t. both, the
     # starting center and the starting angle against the oracle
@@ -250,6 +259,8 @@ def test_spin_actions_forward_and_gradient(mode):
         if mode == "batched-fused":
             b.set_option(C.OPT_FUSE, 1)
             b.set_option(C.OPT_FUSE_ADJ, 1)
+        if mode == "batched-pull":
+            set_pull_schedule(b)
         b.set_particles_from_specs()
         b.set_collider_motion(0, vel, om)
         b.forward(S, record=True)
@@ -501,7 +512,7 @@ def test_slot_reconfiguration_matches_oracle():
 
 # ------------------------------------------------------------------ kernel variants and the autotuner
 VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, per-material launches,
-              #  fused G2P+P2G, fused P2G adjoint + G2P adjoint[, XCD-ordered items])
+              #  fused G2P+P2G, fused P2G adjoint + G2P adjoint[, XCD-ordered items[, flagged-tile list]])
     (0, 0, 0, 0, 0, 0, 1, 0, 0), (1, 1, 1, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 0, 0, 1, 0, 0), (2, 1, 2, 1, 7, 0, 1, 0, 0),
     (1, 0, 2, 0, 3, 0, 1, 0, 0), (1, 1, 1, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 0, 1, 1, 0, 0), (2, 1, 2, 1, 5, 1, 1, 0, 0),
     (1, 1, 1, 1, 0, 0, 0, 0, 0), (2, 1, 2, 1, 6, 1, 0, 0, 0), (2, 0, 2, 1, 0, 1, 1, 1, 0), (2, 1, 2, 1, 0, 0, 0, 1, 0),
@@ -514,6 +525,8 @@ VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, pe
     # budgets, generic launch, XCD order
     (3, 0, 3, 1, 0, 1, 1, 1, 0), (3, 1, 3, 1, 0, 0, 0, 1, 0), (3, 1, 3, 1, 0, 0, 1, 1, 0, 1),
     (3, 0, 3, 1, 0, 1, 1, 0, 1), (3, 1, 3, 1, 0, 0, 0, 1, 1), (3, 1, 3, 1, 0, 1, 0, 1, 1, 1),
+    # the grid passes over the compact list of flagged tiles
+    (3, 1, 3, 1, 0, 0, 1, 1, 1, 0, 1), (2, 1, 2, 1, 0, 0, 1, 1, 1, 0, 1), (0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 1),
 ]
 
 
@@ -531,7 +544,7 @@ def test_every_kernel_variant_matches_oracle(var):
     announce(f"variant {var}")
     b = Batch(envs, max_substeps=S, ckpt_every=K)
     for opt, val in zip((C.OPT_P2G, C.OPT_G2P, C.OPT_G2P_ADJ, C.OPT_P2G_ADJ, C.OPT_GRID_CAP, C.OPT_BOX, C.OPT_SPECIALIZE,
-                         C.OPT_FUSE, C.OPT_FUSE_ADJ, C.OPT_XCD), var):
+                         C.OPT_FUSE, C.OPT_FUSE_ADJ, C.OPT_XCD, C.OPT_GRID_LIST), var):
         b.set_option(opt, val)
     b.set_particles_from_specs()
     b.forward(S, record=True)

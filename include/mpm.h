@@ -291,10 +291,10 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
                                   run of items, keeping an env's grid lines in one XCD's L2; 0 = item
                                   order (default). Results are the same up to float summation order; the
                                   autotuner may set it */
-#define MPM_OPT_GRID_LIST 14   /* 1: the grid update and its adjoint take 64 tiles per block, find the flagged
-                                  ones with one wave ballot and run only those, instead of one block per 4
-                                  tiles of the whole grid (fewer, busier blocks when few tiles are
-                                  flagged). Batched mode. Default 0; the autotuner may set it */
+#define MPM_OPT_GRID_LIST 14   /* 1 (2): the grid update and its adjoint take 64 (16) tiles per block, find the
+                                  flagged ones with one wave ballot and run only those, instead of one
+                                  block per 4 tiles of the whole grid (fewer, busier blocks when few tiles
+                                  are flagged). Batched mode. Default 0; the autotuner may set it */
 #define MPM_OPT_SPECIALIZE 10  /* LDS-staged kernels: 1 = one launch per material over that material's work items,
                                   compiled for it (default); 0 = one launch over all items, material read at run time */
 

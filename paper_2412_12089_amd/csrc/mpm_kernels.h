@@ -57,13 +57,13 @@ void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const Wor
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                         uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, const float* motion,
                         hipStream_t s);
-// the grid passes with 64 tiles per block, the flagged ones found by one ballot
+// the grid passes with `tiles` (16 or 64) tiles per block, the flagged ones found by one ballot
 void launch_grid_update_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                 uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear,
-                                const float* motion, hipStream_t s);
+                                const float* motion, int tiles, hipStream_t s);
 void launch_grid_adjoint_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                  uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel,
-                                 const float* motion, double* gmotion, hipStream_t s);
+                                 const float* motion, double* gmotion, int tiles, hipStream_t s);
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                          uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, const float* motion,
                          double* gmotion, hipStream_t s);

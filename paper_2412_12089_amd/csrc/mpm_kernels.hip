@@ -607,24 +607,25 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
   grid_update_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
 }
 
-// the same, 64 tiles per block: one wave's ballot finds the flagged ones and the block's four waves take
-// them in turn (far fewer blocks than one per 4 tiles when few tiles are flagged)
+// the same, TILES (at most 64) tiles per block: one wave's ballot finds the flagged ones and the block's
+// four waves take them in turn (far fewer blocks than one per 4 tiles when few tiles are flagged)
+template <int TILES>
 __global__ void __launch_bounds__(256) k_grid_update_chunk(const EnvDev* __restrict__ envs,
                                                            const int32_t* __restrict__ tile_env, int64_t ntiles,
                                                            float* __restrict__ grid, uint32_t* __restrict__ flags,
                                                            const int32_t* __restrict__ clock, double t0, int k_rel,
                                                            int clear, const float* __restrict__ motion) {
   __shared__ uint64_t mask_s;
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  if (threadIdx.x < 64) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * TILES;
+  if (wave == 0) {
     const int64_t tile = base + threadIdx.x;
-    const uint64_t m = __ballot(tile < ntiles && flags[tile] != 0u);
+    const uint64_t m = __ballot((int)threadIdx.x < TILES && tile < ntiles && flags[tile] != 0u);
     if (threadIdx.x == 0) mask_s = m;
   }
   __syncthreads();
-  uint64_t m = mask_s;
-  const int wave = threadIdx.x >> 6;
-  for (int rank = 0; m != 0ull; ++rank) {
+  int rank = 0;
+  for (uint64_t m = mask_s; m != 0ull; ++rank) {
     const int bit = __ffsll((unsigned long long)m) - 1;
     m &= m - 1ull;
     if ((rank & 3) == wave)
@@ -769,6 +770,7 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   grid_adjoint_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
 }
 
+template <int TILES>
 __global__ void __launch_bounds__(256) k_grid_adjoint_chunk(const EnvDev* __restrict__ envs,
                                                             const int32_t* __restrict__ tile_env, int64_t ntiles,
                                                             float* __restrict__ grid, uint32_t* __restrict__ flags,
@@ -776,16 +778,16 @@ __global__ void __launch_bounds__(256) k_grid_adjoint_chunk(const EnvDev* __rest
                                                             double t0, int k_rel, const float* __restrict__ motion,
                                                             double* __restrict__ gmotion) {
   __shared__ uint64_t mask_s;
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  if (threadIdx.x < 64) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * TILES;
+  if (wave == 0) {
     const int64_t tile = base + threadIdx.x;
-    const uint64_t m = __ballot(tile < ntiles && flags[tile] != 0u);
+    const uint64_t m = __ballot((int)threadIdx.x < TILES && tile < ntiles && flags[tile] != 0u);
     if (threadIdx.x == 0) mask_s = m;
   }
   __syncthreads();
-  uint64_t m = mask_s;
-  const int wave = threadIdx.x >> 6;
-  for (int rank = 0; m != 0ull; ++rank) {
+  int rank = 0;
+  for (uint64_t m = mask_s; m != 0ull; ++rank) {
     const int bit = __ffsll((unsigned long long)m) - 1;
     m &= m - 1ull;
     if ((rank & 3) == wave)
@@ -1155,17 +1157,25 @@ void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t ti
 }
 void launch_grid_update_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                 uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear,
-                                const float* motion, hipStream_t s) {
+                                const float* motion, int tiles, hipStream_t s) {
   if (ntiles == 0) return;
-  hipLaunchKernelGGL(k_grid_update_chunk, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env, ntiles,
-                     grid, flags, clock, t0, k_rel, clear, motion);
+  if (tiles == 16)
+    hipLaunchKernelGGL(k_grid_update_chunk<16>, dim3((unsigned)((ntiles + 15) / 16)), dim3(256), 0, s, envs, tile_env,
+                       ntiles, grid, flags, clock, t0, k_rel, clear, motion);
+  else
+    hipLaunchKernelGGL(k_grid_update_chunk<64>, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env,
+                       ntiles, grid, flags, clock, t0, k_rel, clear, motion);
 }
 void launch_grid_adjoint_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                  uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel,
-                                 const float* motion, double* gmotion, hipStream_t s) {
+                                 const float* motion, double* gmotion, int tiles, hipStream_t s) {
   if (ntiles == 0) return;
-  hipLaunchKernelGGL(k_grid_adjoint_chunk, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env, ntiles,
-                     grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
+  if (tiles == 16)
+    hipLaunchKernelGGL(k_grid_adjoint_chunk<16>, dim3((unsigned)((ntiles + 15) / 16)), dim3(256), 0, s, envs, tile_env,
+                       ntiles, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
+  else
+    hipLaunchKernelGGL(k_grid_adjoint_chunk<64>, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env,
+                       ntiles, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
 }
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s) {
   if (ntiles == 0) return;

@@ -114,7 +114,7 @@ struct mpm_batch {
   int fuse = 0;       // 1: G2P of substep k and P2G of substep k + 1 in one kernel (with the segment P2G)
   int fuse_adj = 0;   // 1: P2G adjoint of substep k and G2P adjoint of substep k - 1 in one kernel
   int xcd = 0;        // 1: order each launch's items so that the blocks one XCD receives take a contiguous run
-  int grid_list = 0;  // 1: the grid passes take 64 tiles per block and run only the flagged ones
+  int grid_list = 0;  // 1 / 2: the grid passes take 64 / 16 tiles per block and run only the flagged ones
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -244,7 +244,7 @@ void batched_grid(mpm_batch* b, int gi, int clear, int k_rel) {
   Span sp(b, KC_GRID);
   if (b->grid_list)
     launch_grid_update_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0,
-                               k_rel, clear, b->motion_d, b->stream);
+                               k_rel, clear, b->motion_d, b->grid_list == 2 ? 16 : 64, b->stream);
   else
     launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0, k_rel,
                        clear, b->motion_d, b->stream);
@@ -321,7 +321,7 @@ void batched_grid_adj(mpm_batch* b, int gi, int k_rel) {
   Span sp(b, KC_GRID_ADJ);
   if (b->grid_list)
     launch_grid_adjoint_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock,
-                                0.0, k_rel, b->motion_d, b->gmotion_d, b->stream);
+                                0.0, k_rel, b->motion_d, b->gmotion_d, b->grid_list == 2 ? 16 : 64, b->stream);
   else
     launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock, 0.0,
                         k_rel, b->motion_d, b->gmotion_d, b->stream);
@@ -1239,7 +1239,7 @@ int mpm_set_option(mpm_batch* b, int32_t option, int32_t value) {
     case MPM_OPT_SPECIALIZE: if (value < 0 || value > 1) break; b->specialize = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE: if (value < 0 || value > 1) break; b->fuse = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_FUSE_ADJ: if (value < 0 || value > 1) break; b->fuse_adj = value; drop_graphs(b); return MPM_OK;
-    case MPM_OPT_GRID_LIST: if (value < 0 || value > 1) break; b->grid_list = value; drop_graphs(b); return MPM_OK;
+    case MPM_OPT_GRID_LIST: if (value < 0 || value > 2) break; b->grid_list = value; drop_graphs(b); return MPM_OK;
     case MPM_OPT_XCD: {
       if (value < 0 || value > 1) break;
       b->xcd = value;
@@ -1378,7 +1378,7 @@ int mpm_autotune(mpm_batch* b, int32_t budget_ms) {
       {{&best.fuse, 0, 0, true}, {&best.fuse, 1, 0, true}},
       {{&best.fuse_adj, 0, 0, true}, {&best.fuse_adj, 1, 0, true}},
       {{&best.xcd, 0, 0, true}, {&best.xcd, 1, 0, true}},
-      {{&best.grid_list, 0, 0, true}, {&best.grid_list, 1, 0, true}},
+      {{&best.grid_list, 0, 0, true}, {&best.grid_list, 1, 0, true}, {&best.grid_list, 2, 0, true}},
       {{&best.grid_cap, 0, 0, true}, {&best.grid_cap, 512, 0, true}, {&best.grid_cap, 1024, 0, true},
        {&best.grid_cap, 2048, 0, true}},
       {{&best.max_run, 4, 0, true}, {&best.max_run, 8, 0, true}, {&best.max_run, 16, 0, true},

@@ -125,6 +125,26 @@ def test_large_mesh_four_elements_per_thread():
         check_env("block", w, e, gpu, o, og)
 
 
+def test_mesh_whose_adjoint_needs_more_than_64_kib_of_lds():
+    """960 elements on 270 nodes: the adjoint block holds 68 KB of LDS (the
+    launch raises the kernel's dynamic-LDS limit) and four elements per thread."""
+    rng = np.random.default_rng(31)
+    Xm, tets = FS.cube_lattice_mesh([(i, j, k) for i in range(4) for j in range(5) for k in range(8)], 0.02)
+    E, S, n, T = 2, 6, Xm.shape[0], tets.shape[0]
+    assert (n, T) == (270, 960)
+    X = np.stack([Xm + [0.2 * e, 0.0, 0.01] for e in range(E)]).astype(np.float32)
+    x0 = (X + 0.0004 * rng.standard_normal(X.shape)).astype(np.float32)
+    v0 = (0.1 * rng.standard_normal((E, n, 3))).astype(np.float32)
+    prm = np.tile([900.0, 1100.0, 1.0, 0.3, 150.0, 0.05, 0.05, 0.0], (E, 1))
+    act = rng.uniform(-0.15, 0.15, size=(S, E, T)).astype(np.float32)
+    w = FS.FemWorkload("big_block", tets, X, x0, v0, prm, act, 1e-4, S)
+    announce(f"big block: E {E} n {n} T {T} S {S}")
+    gpu, gx, gv = run_gpu(w, seed=8)
+    for e in range(E):
+        o, og = oracle_env(w, e, gx, gv)
+        check_env("big_block", w, e, gpu, o, og)
+
+
 def test_zero_substeps_and_missing_activations():
     dev = torch.device("cuda:0")
     w = FS.two_cubes(seed=5, n_envs=2, substeps=4)

@@ -527,6 +527,7 @@ VARIANTS = [  # (P2G, G2P, G2P adjoint, P2G adjoint, grid cap, small LDS box, pe
     (3, 0, 3, 1, 0, 1, 1, 0, 1), (3, 1, 3, 1, 0, 0, 0, 1, 1), (3, 1, 3, 1, 0, 1, 0, 1, 1, 1),
     # the grid passes over the compact list of flagged tiles
     (3, 1, 3, 1, 0, 0, 1, 1, 1, 0, 1), (2, 1, 2, 1, 0, 0, 1, 1, 1, 0, 1), (0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 1),
+    (3, 1, 3, 1, 0, 0, 1, 1, 1, 0, 2), (2, 0, 2, 1, 0, 1, 1, 1, 1, 1, 2),
 ]
 
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpmx.so")
 SOURCES = ["mpm_kernels.hip", "mpm_kernels_lds.hip", "mpm_observe.hip", "mpm_runtime.hip", "mpm_server.hip",
-           "mpm_noalloc.hip", "fem_kernels.hip", "fem_runtime.hip"]
+           "mpm_noalloc.hip", "fem_kernels.hip", "fem_runtime.hip", "rb_kernels.hip", "rb_runtime.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     "-munsafe-fp-atomics",

@@ -1,5 +1,5 @@
-"""ctypes declarations of the C interface in include/mpm.h and include/mpm_fem.h
-(argument marshalling only).
+"""ctypes declarations of the C interface in include/mpm.h, include/mpm_fem.h and
+include/mpm_rb.h (argument marshalling only).
 
 Every function here has the name and argument order of its C counterpart.
 Device arrays are passed as torch CUDA tensors (or None for a NULL pointer);
@@ -43,10 +43,16 @@ EXPORTED = (
     "mpm_fem_create", "mpm_fem_destroy", "mpm_fem_set_rest", "mpm_fem_set_params", "mpm_fem_set_state",
     "mpm_fem_get_state", "mpm_fem_forward", "mpm_fem_backward", "mpm_fem_sync", "mpm_fem_env_errors",
     "mpm_fem_last_error", "mpm_fem_memory_bytes",
+    "mpm_rb_create", "mpm_rb_destroy", "mpm_rb_set_params", "mpm_rb_set_state", "mpm_rb_get_state",
+    "mpm_rb_forward", "mpm_rb_backward", "mpm_rb_sync", "mpm_rb_env_errors", "mpm_rb_last_error",
+    "mpm_rb_memory_bytes",
 )
 MPM_FEM_MAX_NODES = 512
 MPM_FEM_MAX_TETS = 1024
 MPM_FEM_PARAMS = 8
+MPM_RB_MAX_LINKS = 64
+MPM_RB_MAX_CONTACTS = 256
+MPM_RB_PARAMS = 5
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
@@ -101,6 +107,22 @@ class mpm_fem_desc(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("n_nodes", ctypes.c_int32), ("n_tets", ctypes.c_int32),
                 ("max_substeps", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
                 ("reserved", ctypes.c_int32 * 4)]
+
+
+class mpm_rb_desc(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("n_links", ctypes.c_int32), ("n_contacts", ctypes.c_int32),
+                ("max_substeps", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class mpm_rb_link(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("joint_rot", ctypes.c_float * 9), ("joint_pos", ctypes.c_float * 3),
+                ("axis", ctypes.c_float * 3), ("mass", ctypes.c_float), ("com", ctypes.c_float * 3),
+                ("inertia", ctypes.c_float * 6)]
+
+
+class mpm_rb_contact(ctypes.Structure):
+    _fields_ = [("link", ctypes.c_int32), ("centre", ctypes.c_float * 3), ("radius", ctypes.c_float)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -177,6 +199,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_fem_env_errors": (I32, [VP, P(I32)]),
         "mpm_fem_last_error": (ctypes.c_char_p, [VP]),
         "mpm_fem_memory_bytes": (I64, [VP]),
+        "mpm_rb_create": (I32, [P(mpm_rb_desc), P(mpm_rb_link), P(mpm_rb_contact), P(mpm_allocator), VP, P(VP)]),
+        "mpm_rb_destroy": (I32, [VP]),
+        "mpm_rb_set_params": (I32, [VP, D8]),
+        "mpm_rb_set_state": (I32, [VP, VP, VP]),
+        "mpm_rb_get_state": (I32, [VP, VP, VP]),
+        "mpm_rb_forward": (I32, [VP, I32, VP, I32]),
+        "mpm_rb_backward": (I32, [VP, VP, VP, VP, VP, VP, VP]),
+        "mpm_rb_sync": (I32, [VP]),
+        "mpm_rb_env_errors": (I32, [VP, P(I32)]),
+        "mpm_rb_last_error": (ctypes.c_char_p, [VP]),
+        "mpm_rb_memory_bytes": (I64, [VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -197,11 +230,12 @@ class MPMError(RuntimeError):
         self.code = code
 
 
-def check(code: int, where: str, handle=None, server: bool = False, fem: bool = False):
+def check(code: int, where: str, handle=None, server: bool = False, fem: bool = False, rb: bool = False):
     if code != MPM_OK:
         msg = ""
         if _lib is not None:
-            err = _lib.mpm_server_last_error if server else (_lib.mpm_fem_last_error if fem else _lib.mpm_last_error)
+            err = (_lib.mpm_server_last_error if server else _lib.mpm_fem_last_error if fem else
+                   _lib.mpm_rb_last_error if rb else _lib.mpm_last_error)
             raw = err(handle)
             msg = raw.decode() if raw else ""
         raise MPMError(code, where, msg)

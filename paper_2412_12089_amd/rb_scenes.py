@@ -117,3 +117,44 @@ def hand_batch(seed: int = 9, n_envs: int = 8, substeps: int = 16, n_fingers: in
     tau = np.repeat(per, 16, axis=0)[:substeps]
     return RbWorkload("hand", links, q0.astype(np.float32), qd0.astype(np.float32), prm, tau.astype(np.float32), dt,
                       substeps)
+
+
+def random_tree(seed: int, n_links: int, chain: float = 0.5, n_contacts: int = 4) -> List[RbLink]:
+    """A random tree of n_links revolute links: each link hangs from a random
+    earlier one (from the one just before it with probability `chain`), with a
+    random joint frame and axis, 0.1-1 kg, a centre of mass 5-20 cm out and a
+    random positive definite inertia; contact spheres on the last n_contacts
+    links."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    links: List[RbLink] = []
+    for i in range(n_links):
+        parent = -1 if i == 0 else (i - 1 if rng.uniform() < chain else int(rng.integers(0, i)))
+        pos = np.array([0.0, 0.0, 0.5]) if i == 0 else rng.uniform(-0.15, 0.15, 3)
+        jr = rot_about(rng.standard_normal(3), rng.uniform(-np.pi, np.pi))
+        ax = rng.standard_normal(3)
+        ax /= np.linalg.norm(ax)
+        m = rng.uniform(0.1, 1.0)
+        com = rng.uniform(-0.2, 0.2, 3)
+        com *= rng.uniform(0.05, 0.2) / np.linalg.norm(com)
+        Q = rot_about(rng.standard_normal(3), rng.uniform(0, np.pi))
+        I = Q @ np.diag(m * rng.uniform(2e-3, 1e-2, 3)) @ Q.T
+        cts = [(com * 1.5, 0.02)] if i >= n_links - n_contacts else []
+        links.append(RbLink(parent, pos, jr, ax, m, com, I, cts))
+    return links
+
+
+def tree_batch(seed: int, n_links: int, n_envs: int = 4, substeps: int = 6, dt: float = FRAME_DT / 16,
+               ground: float = 0.3) -> RbWorkload:
+    """Random states (angles U(-1, 1), speeds U(-2, 2)) and torques U(-0.5, 0.5)
+    on `random_tree`, joint damping U(0.01, 0.05), a ground at z_g = `ground`
+    with stiffness 2000."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    links = random_tree(seed, n_links)
+    N = len(links)
+    q0 = rng.uniform(-1.0, 1.0, size=(n_envs, N))
+    qd0 = rng.uniform(-2.0, 2.0, size=(n_envs, N))
+    prm = np.column_stack([rng.uniform(0.01, 0.05, n_envs), np.full(n_envs, 2000.0), np.full(n_envs, 5.0),
+                           np.full(n_envs, 1.0), np.full(n_envs, ground)])
+    tau = rng.uniform(-0.5, 0.5, size=(substeps, n_envs, N))
+    return RbWorkload(f"tree{n_links}", links, q0.astype(np.float32), qd0.astype(np.float32), prm,
+                      tau.astype(np.float32), dt, substeps)

@@ -123,3 +123,68 @@ def test_fem_null_arguments_are_rejected():
     assert lib.mpm_fem_forward(None, 1, None, 0) == C.MPM_INVALID_ARG
     assert lib.mpm_fem_memory_bytes(None) == 0
     assert lib.mpm_fem_last_error(None) == b"null FEM batch"
+
+
+def _rb(N=4, C_=2, E=2, S=4, dt=1e-3):
+    from paper_2412_12089_amd import rb_scenes as RS
+    from paper_2412_12089_amd.rb import pack_links
+    links = RS.random_tree(3, N, n_contacts=C_)
+    d = C.mpm_rb_desc()
+    L, K, nc = pack_links(links)
+    d.n_envs, d.n_links, d.n_contacts, d.max_substeps, d.dt = E, N, nc, S, dt
+    d.gravity[:] = [0.0, 0.0, -9.8]
+    return d, L, K
+
+
+@pytest.mark.parametrize("kw", [dict(E=0), dict(N=65), dict(S=-1), dict(dt=0.0), dict(dt=float("nan"))])
+def test_rb_create_rejects_bad_descriptions(kw):
+    lib = C.load()
+    N = kw.pop("N", 4)
+    d, L, K = _rb(N=min(N, 64), **kw)
+    d.n_links = N
+    if N > 64:
+        L = (C.mpm_rb_link * N)(*L, *[L[0]] * (N - 64))
+    out = ctypes.c_void_p()
+    assert lib.mpm_rb_create(ctypes.byref(d), L, K, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    assert not out.value
+
+
+@pytest.mark.parametrize("bad", ["root", "order", "axis", "rotation", "reflection", "mass", "contact_link",
+                                 "radius", "contacts"])
+def test_rb_create_rejects_bad_links(bad):
+    lib = C.load()
+    d, L, K = _rb()
+    if bad == "root":
+        L[0].parent = 1
+    elif bad == "order":
+        L[2].parent = 3
+    elif bad == "axis":
+        L[1].axis[:] = [1.0, 1.0, 0.0]
+    elif bad == "rotation":
+        L[1].joint_rot[0] *= 1.01
+    elif bad == "reflection":
+        L[1].joint_rot[:] = [1, 0, 0, 0, 1, 0, 0, 0, -1]
+    elif bad == "mass":
+        L[3].mass = -0.1
+    elif bad == "contact_link":
+        K[0].link = 4
+    elif bad == "radius":
+        K[1].radius = -0.01
+    elif bad == "contacts":
+        d.n_contacts = 257
+    out = ctypes.c_void_p()
+    assert lib.mpm_rb_create(ctypes.byref(d), L, K, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    assert not out.value
+
+
+def test_rb_null_arguments_are_rejected():
+    lib = C.load()
+    out = ctypes.c_void_p()
+    assert lib.mpm_rb_create(None, None, None, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
+    for fn, nargs in (("mpm_rb_destroy", 0), ("mpm_rb_set_params", 1), ("mpm_rb_set_state", 2),
+                      ("mpm_rb_get_state", 2), ("mpm_rb_backward", 6), ("mpm_rb_sync", 0),
+                      ("mpm_rb_env_errors", 1)):
+        assert getattr(lib, fn)(None, *([None] * nargs)) == C.MPM_INVALID_ARG, fn
+    assert lib.mpm_rb_forward(None, 1, None, 0) == C.MPM_INVALID_ARG
+    assert lib.mpm_rb_memory_bytes(None) == 0
+    assert lib.mpm_rb_last_error(None) == b"null rigid-body batch"

@@ -137,6 +137,9 @@ def parse():
     ap.add_argument("--fem-envs", type=int, default=4096, help="jumper envs of the FEM leg (0: skip)")
     ap.add_argument("--fem-frames", type=int, default=5, help="timed 80-substep frames of the FEM leg")
     ap.add_argument("--fem-only", action="store_true", help="run only the FEM leg and print its JSON (profiling)")
+    ap.add_argument("--rb-envs", type=int, default=16384, help="hand envs of the rigid-body leg (0: skip)")
+    ap.add_argument("--rb-frames", type=int, default=10, help="timed 16-substep frames of the rigid-body leg")
+    ap.add_argument("--rb-only", action="store_true", help="run only the rigid-body leg and print its JSON")
     return ap.parse_args()
 
 
@@ -296,6 +299,58 @@ def fem_leg(n_envs, frames, dev):
     return out
 
 
+def rb_leg(n_envs, frames, dev):
+    """The articulated rigid-body path on 13-link hands (a wrist and four
+    three-link fingers with tip contacts): per 16-substep frame a recorded
+    forward and its adjoint (cotangents of the initial state, the torques and
+    the parameters), timed with HIP events on the library's stream."""
+    import torch
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd import rb_scenes as RS
+    from paper_2412_12089_amd.rb import RbBatch
+    w = RS.hand_batch(seed=9, n_envs=n_envs, substeps=16)
+    E, N, S = w.n_envs, len(w.links), w.substeps
+    b = RbBatch(w.links, E, S, w.dt, w.gravity, dev)
+    b.set_params(w.params)
+    q0, qd0 = torch.from_numpy(w.q0).to(dev), torch.from_numpy(w.qd0).to(dev)
+    tau = torch.from_numpy(w.tau).to(dev)
+    gq = torch.randn(E, N, device=dev)
+    dq, dqd = torch.empty_like(gq), torch.empty_like(gq)
+    dt = torch.empty(S, E, N, device=dev)
+    dp = torch.empty(E, C.MPM_RB_PARAMS, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    lib, h = b.lib, b.h
+
+    def frame(backward=True):
+        lib.mpm_rb_set_state(h, C.ptr(q0), C.ptr(qd0))
+        lib.mpm_rb_forward(h, S, C.ptr(tau), C.MPM_FWD_RECORD if backward else 0)
+        if backward:
+            lib.mpm_rb_backward(h, C.ptr(gq), None, C.ptr(dq), C.ptr(dqd), C.ptr(dt), C.ptr(dp))
+
+    def timed(backward):
+        for _ in range(2):
+            frame(backward)
+        ms = []
+        for _ in range(frames):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            frame(backward)
+            e1.record(b.stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.mean(ms))
+
+    fb_ms = timed(True)
+    f_ms = timed(False)
+    assert b.sync(raise_on_error=False) == C.MPM_OK, "non-finite rigid-body state"
+    out = {"workload": "hand", "envs": E, "links": N, "contacts": b.n_contacts, "substeps": S,
+           "fwd_bwd_ms_per_frame": fb_ms, "fwd_ms_per_frame": f_ms,
+           "env_substeps_per_s": E * S / (fb_ms * 1e-3), "joint_substeps_per_s": E * N * S / (fb_ms * 1e-3),
+           "fwd_env_substeps_per_s": E * S / (f_ms * 1e-3), "hbm_resident_bytes": b.memory_bytes()}
+    b.close()
+    return out
+
+
 def cpu_baseline(wl, substeps, n_envs, runs):
     """The FP64 oracle on a bounded sample: the first n_envs envs, `substeps`
     substeps each, forward + reverse; the median rate over `runs` runs."""
@@ -333,6 +388,9 @@ def main():
 
     if args.fem_only:
         print(json.dumps(fem_leg(max(1, args.fem_envs), args.fem_frames, torch.device("cuda:0"))), flush=True)
+        return
+    if args.rb_only:
+        print(json.dumps(rb_leg(max(1, args.rb_envs), args.rb_frames, torch.device("cuda:0"))), flush=True)
         return
     wl = scenes.WORKLOADS[args.workload]()
     S, K = wl.substeps, wl.ckpt_every
@@ -407,6 +465,11 @@ def main():
         progress(f"FEM leg: {args.fem_envs} jumpers")
         fem = fem_leg(args.fem_envs, args.fem_frames, dev)
 
+    rb = None
+    if args.rb_envs > 0:
+        progress(f"rigid-body leg: {args.rb_envs} hands")
+        rb = rb_leg(args.rb_envs, args.rb_frames, dev)
+
     serving = None
     if args.serve_seconds > 0:
         progress(f"serving a {args.serve_seconds:.0f} s Poisson stream")
@@ -446,6 +509,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "touched_nodes": nodes, "kernel_ms": dom_ms},
         "workloads": extra,
         "fem": fem,
+        "rigid": rb,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -147,6 +147,10 @@ MD M3 m3_rotate_out(const M3& U, const M3& A) { return m3_mul_abt(m3_mul(U, A), 
 // symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (fixed sweeps,
 // no data-dependent loop): A = U diag(s) U^T
 // --------------------------------------------------------------------------
+// Each rotation is the classical Jacobi step in Rutishauser's numerically
+// stable form (the tangent t of the smaller rotation angle from theta, then
+// c = 1/sqrt(1 + t^2), s = t c, tau = s/(1 + c) and updates a - s (b + tau a);
+// Rutishauser 1971, Handbook for Automatic Computation II, contribution II/1).
 // The rotation uses the hardware reciprocal and square root (about 1 ulp) and
 // no branch: c and s are built from t so that the rotation is orthogonal for
 // any t, and an inexact t only leaves a slightly larger off-diagonal entry for

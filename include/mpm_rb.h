@@ -15,7 +15,8 @@
  * at the lowest point x of a sphere while x_z < z_g,
  *   f = (-k_f v_x, -k_f v_y, k_e (z_g - x_z) - k_d v_z),
  * v the velocity of the link's material point at x. qdd comes from a Cholesky
- * factorisation of M. The reverse-mode adjoint maps cotangents of the final
+ * factorisation of M ordered leaves first (M = L^T L, with no fill-in on a
+ * tree). The reverse-mode adjoint maps cotangents of the final
  * (q, qd) to cotangents of the initial (q, qd), of every substep's torques and
  * of each environment's parameters (Appendix D's simulation-gradient chain):
  * per substep lambda = M^-1 qdd_bar is the torque cotangent, and the state

@@ -14,6 +14,9 @@ struct RbModel {
   const float* link;        // [N][kRbLinkF]; root joint_pos already relative to the spatial origin
   const uint64_t* anc;      // [N] bit j: joint j is on the path from the root to link i (i included)
   const uint64_t* desc;     // [N] bit k: link k is in the subtree of link i (i included)
+  const int32_t* level;     // [N] height (longest path down to a leaf) | depth (joints above) << 16
+  const uint64_t* hmask;    // [H] bit k: link k has height h
+  int H, D;                 // height and depth levels
   const int32_t* cbeg;      // [N + 1] contact range of each link
   const float* contact;     // [C][4] sphere centre (link frame), radius
   const float* prm;         // [E][kRbPrm]

@@ -1,6 +1,6 @@
 // Articulated rigid bodies on a fixed base (Appendix D.1): the batched forward
 // substeps (composite rigid body algorithm for the mass matrix, recursive
-// Newton-Euler for the bias forces, a Cholesky solve, semi-implicit Euler) and
+// Newton-Euler for the bias forces, a sparse Cholesky solve, semi-implicit Euler) and
 // their reverse-mode adjoint.
 //
 // One environment per group of G lanes of a wave (G: the link count rounded up
@@ -12,8 +12,13 @@
 // acceleration are sums over the joints on its root path, its subtree force
 // and composite inertia are sums over its subtree, and each lane takes those
 // sums from LDS through the link's ancestor and descendant bit masks. The
-// joint-space mass matrix is M_ij = S_j . (Ic_i S_i) for j on i's root path.
-// A substep touches HBM only for the torques and the tape.
+// joint-space mass matrix is M_ij = S_j . (Ic_i S_i) for j on i's root path
+// and zero between different branches. Factorised leaves first, M = L^T L
+// keeps that sparsity (no fill-in: eliminating a link touches only its root
+// path), so the factorisation and the solve with L^T run one tree height level
+// at a time and the solve with L one depth level at a time: a barrier per
+// level instead of one per joint. A substep touches HBM only for the torques
+// and the tape.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -113,6 +118,7 @@ struct Link {
   float Rt[9], pt[3], ax[3], m, com[3], In[6];
   uint64_t anc, desc;
   int cb, ce;
+  int height, depth;   // levels: longest path down to a leaf, joints above
 };
 MD Link load_link(const RbModel& M, int i, bool live) {
   Link l;
@@ -132,6 +138,8 @@ MD Link load_link(const RbModel& M, int i, bool live) {
   l.desc = live ? M.desc[i] : 0ull;
   l.cb = live ? M.cbeg[i] : 0;
   l.ce = live ? M.cbeg[i + 1] : 0;
+  l.height = live ? (M.level[i] & 0xffff) : -1;
+  l.depth = live ? (M.level[i] >> 16) : -1;
   return l;
 }
 
@@ -154,7 +162,7 @@ struct EnvLds {
   float X[6][G];       // exchange of 6-vectors
   float Y[6][G];
   float Ic[10][G];     // body inertias, summed over subtrees
-  float M[G][G + 1];   // mass matrix, then its Cholesky factor (lower)
+  float M[G][G + 1];   // row i, entries j on i's root path: the mass matrix, then its factor L (M = L^T L)
   float dinv[G];       // 1 / L_kk
   float y[G];          // substitution values
   float x[G];
@@ -202,36 +210,49 @@ MD void contact_point(const RbModel& M, const Frame& F, int c, float* cw, float*
   x[2] = cw[2] - s[3];
 }
 
-// Solves L L^T x = b with the factor in E.M / E.dinv; b and the result are per lane (lane < N).
+// Solves M x = b with M = L^T L in E.M / E.dinv: L^T y = b over the height
+// levels (y_k takes the subtree's y), then L x = y over the depth levels (x_k
+// takes the root path's x); b and x are per lane (lane < N).
 template <int G>
-MD float chol_solve(EnvLds<G>& E, int lane, int N, float b) {
-  float y = b;
-  for (int k = 0; k < N; ++k) {
-    if (lane == k) {
-      y *= E.dinv[k];
-      E.y[k] = y;
+MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool live, float b) {
+  float y = 0.f;
+  for (int h = 0; h < M.H; ++h) {
+    if (live && l.height == h) {
+      float t = b;
+      uint64_t mk = l.desc & ~(1ull << lane);
+      while (mk) {
+        const int c = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        t = fmaf(-E.M[c][lane], E.y[c], t);
+      }
+      y = t * E.dinv[lane];
+      E.y[lane] = y;
     }
     __syncthreads();
-    if (lane > k && lane < N) y = fmaf(-E.M[lane][k], E.y[k], y);
   }
-  float x = y;
-  for (int k = N - 1; k >= 0; --k) {
-    if (lane == k) {
-      x *= E.dinv[k];
-      E.x[k] = x;
+  float x = 0.f;
+  for (int d = 0; d < M.D; ++d) {
+    if (live && l.depth == d) {
+      float t = y;
+      uint64_t mk = l.anc & ~(1ull << lane);
+      while (mk) {
+        const int j = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        t = fmaf(-E.M[lane][j], E.x[j], t);
+      }
+      x = t * E.dinv[lane];
+      E.x[lane] = x;
     }
     __syncthreads();
-    if (lane < k) x = fmaf(-E.M[k][lane], E.x[k], x);
   }
   return x;
 }
 
-// One substep's dynamics of an environment: fills F, leaves M's Cholesky factor in E and returns qdd of the
+// One substep's dynamics of an environment: fills F, leaves M's factor L in E and returns qdd of the
 // lane's joint. Every lane of the block calls it (barriers inside).
 template <int G>
 MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool live, float q, float qd, float tau,
                   const Prm& P, Frame& F) {
-  const int N = M.N;
   // joint blocks B = joint_rot Rot(axis, q) (Rodrigues: c I + s [a]x + (1 - c) a a^T)
   {
     float sn, cs;
@@ -374,38 +395,50 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
     }
   }
   const float rhs = tau - dot6(F.S, Ft) - P.damp * qd;
-  // mass matrix row: M_ij = S_j . (Ic_i S_i) for j on the root path; zero where neither is the other's ancestor
+  // mass matrix row: M_ij = S_j . (Ic_i S_i) for j on the root path (the lane's own row only)
   if (live) {
     const V6 Fc = iapply(Ic, F.S);
-    for (int j = 0; j < N; ++j) {
-      const uint64_t bit = 1ull << j;
-      if (l.anc & bit) {
-        const float v = dot6(get6(E.Y, j), Fc);
-        E.M[lane][j] = v;
-        E.M[j][lane] = v;
-      } else if (!(l.desc & bit)) {
-        E.M[lane][j] = 0.f;
+    uint64_t mk = l.anc;
+    while (mk) {
+      const int j = __builtin_ctzll(mk);
+      mk &= mk - 1;
+      E.M[lane][j] = dot6(get6(E.Y, j), Fc);
+    }
+  }
+  // M = L^T L, leaves first, one height level at a time: the level's links finish their rows (their
+  // subtrees are eliminated), then every link updates its own row with the level's links below it,
+  // M_ij -= L_ki L_kj for j on i's root path. Rows a level reads are never written in that level.
+  for (int h = 0; h < M.H; ++h) {
+    if (live && l.height == h) {
+      const float d = sqrtf(E.M[lane][lane]);   // a non-positive pivot gives NaN: the env is flagged non-finite
+      const float di = 1.f / d;
+      E.M[lane][lane] = d;
+      E.dinv[lane] = di;
+      uint64_t mk = l.anc & ~(1ull << lane);
+      while (mk) {
+        const int j = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        E.M[lane][j] *= di;
+      }
+    }
+    __syncthreads();
+    if (live) {
+      uint64_t mk = l.desc & M.hmask[h] & ~(1ull << lane);
+      while (mk) {
+        const int k = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        const float lki = E.M[k][lane];
+        uint64_t aj = l.anc;
+        while (aj) {
+          const int j = __builtin_ctzll(aj);
+          aj &= aj - 1;
+          E.M[lane][j] = fmaf(-lki, E.M[k][j], E.M[lane][j]);
+        }
       }
     }
   }
   __syncthreads();
-  // Cholesky M = L L^T, left-looking, lane = row
-  for (int k = 0; k < N; ++k) {
-    float t = 0.f;
-    if (lane >= k && lane < N) {
-      t = E.M[lane][k];
-      for (int p = 0; p < k; ++p) t = fmaf(-E.M[lane][p], E.M[k][p], t);
-    }
-    if (lane == k) {
-      const float d = sqrtf(t);   // a non-positive pivot gives NaN: the env is flagged non-finite
-      E.M[k][k] = d;
-      E.dinv[k] = 1.f / d;
-    }
-    __syncthreads();
-    if (lane > k && lane < N) E.M[lane][k] = t * E.dinv[k];
-    __syncthreads();
-  }
-  return chol_solve(E, lane, N, rhs);
+  return tree_solve(M, l, E, lane, live, rhs);
 }
 
 template <int G>
@@ -476,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_backward(RbModel M, int S, const 
     const float qdd = dynamics<G>(M, l, L, lane, live, qi, qdi, ti, P, F);
     // qd' = qd + dt qdd, q' = q + dt qd': the cotangent of qd' is b + dt a, that of qdd dt (b + dt a)
     const float gtot = fmaf(M.dt, a, b);
-    const float lam = chol_solve(L, lane, N, M.dt * gtot);   // torque cotangent M^-1 qdd_bar
+    const float lam = tree_solve(M, l, L, lane, live, M.dt * gtot);   // torque cotangent M^-1 qdd_bar
     if (dtau && live) dtau[(size_t)s * E * N + at] = lam;
     acc[0] -= lam * qdi;
     // phi = lambda . ID(q, qd, qdd): accelerations with qdd, and Lambda_k = sum over k's root path of lambda_i S_i

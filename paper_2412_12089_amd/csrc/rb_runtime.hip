@@ -2,6 +2,7 @@
 // ancestor and descendant masks, device memory, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -26,6 +27,9 @@ struct mpm_rb {
   float* link = nullptr;       // [N][kRbLinkF]
   uint64_t* anc = nullptr;     // [N]
   uint64_t* desc = nullptr;    // [N]
+  int32_t* level = nullptr;    // [N] height | depth << 16
+  uint64_t* hmask = nullptr;   // [H]
+  int H = 0, D = 0;
   int32_t* cbeg = nullptr;     // [N + 1]
   float* contact = nullptr;    // [C][4]
   float* prm = nullptr;        // [E][kRbPrm] FP32 copy of the parameters
@@ -87,6 +91,10 @@ mpmx::RbModel model_of(const mpm_rb* r) {
   m.link = r->link;
   m.anc = r->anc;
   m.desc = r->desc;
+  m.level = r->level;
+  m.hmask = r->hmask;
+  m.H = r->H;
+  m.D = r->D;
   m.cbeg = r->cbeg;
   m.contact = r->contact;
   m.prm = r->prm;
@@ -158,6 +166,19 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   for (int i = 0; i < N; ++i)
     for (int k = 0; k < N; ++k)
       if (anc[k] & (1ull << i)) desc[i] |= 1ull << k;
+  // levels: depth = joints above the link, height = longest path down to a leaf (children have higher indices)
+  std::vector<int32_t> depth(N, 0), height(N, 0), level(N);
+  int H = 1, D = 1;
+  for (int i = 0; i < N; ++i) depth[i] = links[i].parent < 0 ? 0 : depth[links[i].parent] + 1;
+  for (int i = N - 1; i >= 0; --i)
+    if (links[i].parent >= 0) height[links[i].parent] = std::max(height[links[i].parent], height[i] + 1);
+  std::vector<uint64_t> hmask(N, 0);
+  for (int i = 0; i < N; ++i) {
+    level[i] = height[i] | (depth[i] << 16);
+    hmask[height[i]] |= 1ull << i;
+    H = std::max(H, height[i] + 1);
+    D = std::max(D, depth[i] + 1);
+  }
   // contacts grouped by link
   std::vector<int32_t> cbeg(N + 1, 0);
   for (int c = 0; c < C; ++c) {
@@ -188,6 +209,8 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   r->dt = d->dt;
   for (int a = 0; a < 3; ++a) r->g[a] = d->gravity[a];
   r->zref = ref[2];
+  r->H = H;
+  r->D = D;
   r->stream = (hipStream_t)stream;
   if (alloc) {
     r->has_alloc = true;
@@ -198,6 +221,8 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   r->anc = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->desc = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->cbeg = (int32_t*)ralloc(r, sizeof(int32_t) * (N + 1));
+  r->level = (int32_t*)ralloc(r, sizeof(int32_t) * N);
+  r->hmask = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->contact = (float*)ralloc(r, sizeof(float) * ct.size());
   r->prm = (float*)ralloc(r, sizeof(float) * mpmx::kRbPrm * E);
   r->q = (float*)ralloc(r, sizeof(float) * E * N);
@@ -205,7 +230,7 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   r->tape = (float*)ralloc(r, sizeof(float) * 2 * E * N * (size_t)(r->max_S + 1));
   r->tape_tau = (float*)ralloc(r, sizeof(float) * E * N * (size_t)(r->max_S > 0 ? r->max_S : 1));
   r->errs = (int32_t*)ralloc(r, sizeof(int32_t) * E);
-  if (!(r->link && r->anc && r->desc && r->cbeg && r->contact && r->prm && r->q && r->qd && r->tape && r->tape_tau &&
+  if (!(r->link && r->anc && r->desc && r->level && r->hmask && r->cbeg && r->contact && r->prm && r->q && r->qd && r->tape && r->tape_tau &&
         r->errs)) {
     free_all(r);
     delete r;
@@ -220,6 +245,8 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   hipError_t e1 = hipMemcpyAsync(r->link, lk.data(), sizeof(float) * lk.size(), hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->anc, anc.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->desc, desc.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
+  if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->level, level.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, r->stream);
+  if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->hmask, hmask.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->cbeg, cbeg.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->contact, ct.data(), sizeof(float) * ct.size(), hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->prm, prm.data(), sizeof(float) * prm.size(), hipMemcpyHostToDevice, r->stream);

@@ -137,7 +137,7 @@ def parse():
     ap.add_argument("--fem-envs", type=int, default=4096, help="jumper envs of the FEM leg (0: skip)")
     ap.add_argument("--fem-frames", type=int, default=5, help="timed 80-substep frames of the FEM leg")
     ap.add_argument("--fem-only", action="store_true", help="run only the FEM leg and print its JSON (profiling)")
-    ap.add_argument("--rb-envs", type=int, default=16384, help="hand envs of the rigid-body leg (0: skip)")
+    ap.add_argument("--rb-envs", type=int, default=65536, help="hand envs of the rigid-body leg (0: skip)")
     ap.add_argument("--rb-frames", type=int, default=10, help="timed 16-substep frames of the rigid-body leg")
     ap.add_argument("--rb-only", action="store_true", help="run only the rigid-body leg and print its JSON")
     return ap.parse_args()

@@ -155,18 +155,23 @@ MD Prm load_prm(const RbModel& M, int e) {
   return p;
 }
 
-// LDS of one environment (G lanes)
+// LDS of one environment (G lanes). The joint blocks live only while the
+// lanes compose their poses; the inertias and the mass matrix are written after
+// the next barriers, so the two share their space.
 template <int G>
 struct EnvLds {
-  float B[12][G];      // per joint: joint_rot Rot(axis, q) (9), joint_pos (3)
-  float X[6][G];       // exchange of 6-vectors
+  float X[6][G];       // exchange of 6-vectors (and the final parameter-cotangent reduction)
   float Y[6][G];
-  float Ic[10][G];     // body inertias, summed over subtrees
-  float M[G][G + 1];   // row i, entries j on i's root path: the mass matrix, then its factor L (M = L^T L)
   float dinv[G];       // 1 / L_kk
   float y[G];          // substitution values
   float x[G];
-  float red[kRbPrm][G];
+  union {
+    float B[12][G];    // per joint: joint_rot Rot(axis, q) (9), joint_pos (3)
+    struct {
+      float Ic[10][G];     // body inertias, summed over subtrees
+      float M[G][G + 1];   // row i, entries j on i's root path: the mass matrix, then its factor L (M = L^T L)
+    } cm;
+  } u;
 };
 
 // sum of the 6-vectors of the links in a bit mask (a root path or a subtree), in ascending link order
@@ -223,7 +228,7 @@ MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, boo
       while (mk) {
         const int c = __builtin_ctzll(mk);
         mk &= mk - 1;
-        t = fmaf(-E.M[c][lane], E.y[c], t);
+        t = fmaf(-E.u.cm.M[c][lane], E.y[c], t);
       }
       y = t * E.dinv[lane];
       E.y[lane] = y;
@@ -238,7 +243,7 @@ MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, boo
       while (mk) {
         const int j = __builtin_ctzll(mk);
         mk &= mk - 1;
-        t = fmaf(-E.M[lane][j], E.x[j], t);
+        t = fmaf(-E.u.cm.M[lane][j], E.x[j], t);
       }
       x = t * E.dinv[lane];
       E.x[lane] = x;
@@ -267,9 +272,9 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          E.B[3 * r + c][lane] = l.Rt[3 * r] * Rq[c] + l.Rt[3 * r + 1] * Rq[3 + c] + l.Rt[3 * r + 2] * Rq[6 + c];
+          E.u.B[3 * r + c][lane] = l.Rt[3 * r] * Rq[c] + l.Rt[3 * r + 1] * Rq[3 + c] + l.Rt[3 * r + 2] * Rq[6 + c];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) E.B[9 + k][lane] = l.pt[k];
+      for (int k = 0; k < 3; ++k) E.u.B[9 + k][lane] = l.pt[k];
     }
   }
   __syncthreads();
@@ -281,7 +286,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
     while (mk) {
       const int j = __builtin_ctzll(mk);
       mk &= mk - 1;
-      const float t0 = E.B[9][j], t1 = E.B[10][j], t2 = E.B[11][j];
+      const float t0 = E.u.B[9][j], t1 = E.u.B[10][j], t2 = E.u.B[11][j];
 #pragma unroll
       for (int r = 0; r < 3; ++r) p[r] += R[3 * r] * t0 + R[3 * r + 1] * t1 + R[3 * r + 2] * t2;
       float Rn[9];
@@ -289,7 +294,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          Rn[3 * r + c] = R[3 * r] * E.B[c][j] + R[3 * r + 1] * E.B[3 + c][j] + R[3 * r + 2] * E.B[6 + c][j];
+          Rn[3 * r + c] = R[3 * r] * E.u.B[c][j] + R[3 * r + 1] * E.u.B[3 + c][j] + R[3 * r + 2] * E.u.B[6 + c][j];
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = Rn[k];
     }
@@ -364,11 +369,11 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
   __syncthreads();
   if (live) {
     put6(E.X, lane, f);
-    E.Ic[0][lane] = F.I.m;
+    E.u.cm.Ic[0][lane] = F.I.m;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) E.Ic[1 + k][lane] = F.I.h[k];
+    for (int k = 0; k < 3; ++k) E.u.cm.Ic[1 + k][lane] = F.I.h[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) E.Ic[4 + k][lane] = F.I.J[k];
+    for (int k = 0; k < 6; ++k) E.u.cm.Ic[4 + k][lane] = F.I.J[k];
     put6(E.Y, lane, F.S);
   }
   __syncthreads();
@@ -387,11 +392,11 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       mk &= mk - 1;
 #pragma unroll
       for (int a = 0; a < 6; ++a) Ft.c[a] += E.X[a][k];
-      Ic.m += E.Ic[0][k];
+      Ic.m += E.u.cm.Ic[0][k];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) Ic.h[a] += E.Ic[1 + a][k];
+      for (int a = 0; a < 3; ++a) Ic.h[a] += E.u.cm.Ic[1 + a][k];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) Ic.J[a] += E.Ic[4 + a][k];
+      for (int a = 0; a < 6; ++a) Ic.J[a] += E.u.cm.Ic[4 + a][k];
     }
   }
   const float rhs = tau - dot6(F.S, Ft) - P.damp * qd;
@@ -402,7 +407,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
     while (mk) {
       const int j = __builtin_ctzll(mk);
       mk &= mk - 1;
-      E.M[lane][j] = dot6(get6(E.Y, j), Fc);
+      E.u.cm.M[lane][j] = dot6(get6(E.Y, j), Fc);
     }
   }
   // M = L^T L, leaves first, one height level at a time: the level's links finish their rows (their
@@ -410,15 +415,15 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
   // M_ij -= L_ki L_kj for j on i's root path. Rows a level reads are never written in that level.
   for (int h = 0; h < M.H; ++h) {
     if (live && l.height == h) {
-      const float d = sqrtf(E.M[lane][lane]);   // a non-positive pivot gives NaN: the env is flagged non-finite
+      const float d = sqrtf(E.u.cm.M[lane][lane]);   // a non-positive pivot gives NaN: the env is flagged non-finite
       const float di = 1.f / d;
-      E.M[lane][lane] = d;
+      E.u.cm.M[lane][lane] = d;
       E.dinv[lane] = di;
       uint64_t mk = l.anc & ~(1ull << lane);
       while (mk) {
         const int j = __builtin_ctzll(mk);
         mk &= mk - 1;
-        E.M[lane][j] *= di;
+        E.u.cm.M[lane][j] *= di;
       }
     }
     __syncthreads();
@@ -427,12 +432,12 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       while (mk) {
         const int k = __builtin_ctzll(mk);
         mk &= mk - 1;
-        const float lki = E.M[k][lane];
+        const float lki = E.u.cm.M[k][lane];
         uint64_t aj = l.anc;
         while (aj) {
           const int j = __builtin_ctzll(aj);
           aj &= aj - 1;
-          E.M[lane][j] = fmaf(-lki, E.M[k][j], E.M[lane][j]);
+          E.u.cm.M[lane][j] = fmaf(-lki, E.u.cm.M[k][j], E.u.cm.M[lane][j]);
         }
       }
     }
@@ -481,8 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_forward(RbModel M, int S, float* 
   }
 }
 
+// three waves per SIMD (168 VGPRs, three of them spilled): faster than two without spills once the chip is full
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_rb_backward(RbModel M, int S, const float* __restrict__ tape,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_rb_backward(RbModel M, int S, const float* __restrict__ tape,
                                                         const float* __restrict__ tape_tau,
                                                         const float* __restrict__ gq, const float* __restrict__ gqd,
                                                         float* __restrict__ dq0, float* __restrict__ dqd0,
@@ -610,11 +616,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_backward(RbModel M, int S, const 
   if (dprm) {
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kRbPrm; ++c) L.red[c][lane] = live ? acc[c] : 0.f;
+    for (int c = 0; c < kRbPrm; ++c) L.X[c][lane] = live ? acc[c] : 0.f;
     __syncthreads();
     if (lane < kRbPrm && e < E) {
       double s = 0.0;
-      for (int k = 0; k < N; ++k) s += (double)L.red[lane][k];
+      for (int k = 0; k < N; ++k) s += (double)L.X[lane][k];
       dprm[(size_t)e * kRbPrm + lane] = s;
     }
   }

@@ -14,6 +14,7 @@ struct RbModel {
   const float* link;        // [N][kRbLinkF]; root joint_pos already relative to the spatial origin
   const uint64_t* anc;      // [N] bit j: joint j is on the path from the root to link i (i included)
   const uint64_t* desc;     // [N] bit k: link k is in the subtree of link i (i included)
+  const uint64_t* kids;     // [N] bit k: link k's parent is link i
   const int32_t* level;     // [N] height (longest path down to a leaf) | depth (joints above) << 16
   const uint64_t* hmask;    // [H] bit k: link k has height h
   int H, D;                 // height and depth levels

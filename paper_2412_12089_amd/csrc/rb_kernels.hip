@@ -11,7 +11,8 @@
 // tree recursions need no coordinate transforms: a link's velocity and
 // acceleration are sums over the joints on its root path, its subtree force
 // and composite inertia are sums over its subtree, and each lane takes those
-// sums from LDS through the link's ancestor and descendant bit masks. The
+// sums from LDS (through the link's ancestor bit mask, and children first over
+// the tree's height levels). The
 // joint-space mass matrix is M_ij = S_j . (Ic_i S_i) for j on i's root path
 // and zero between different branches. Factorised leaves first, M = L^T L
 // keeps that sparsity (no fill-in: eliminating a link touches only its root
@@ -116,7 +117,7 @@ MD V6 iapply(const Inertia& I, const V6& a) {
 // a lane's own link
 struct Link {
   float Rt[9], pt[3], ax[3], m, com[3], In[6];
-  uint64_t anc, desc;
+  uint64_t anc, desc, kids;
   int cb, ce;
   int height, depth;   // levels: longest path down to a leaf, joints above
 };
@@ -136,6 +137,7 @@ MD Link load_link(const RbModel& M, int i, bool live) {
   for (int k = 0; k < 6; ++k) l.In[k] = s[19 + k];
   l.anc = live ? M.anc[i] : 0ull;
   l.desc = live ? M.desc[i] : 0ull;
+  l.kids = live ? M.kids[i] : 0ull;
   l.cb = live ? M.cbeg[i] : 0;
   l.ce = live ? M.cbeg[i + 1] : 0;
   l.height = live ? (M.level[i] & 0xffff) : -1;
@@ -155,28 +157,54 @@ MD Prm load_prm(const RbModel& M, int e) {
   return p;
 }
 
-// LDS of one environment (G lanes). The joint blocks live only while the
-// lanes compose their poses; the inertias and the mass matrix are written after
-// the next barriers, so the two share their space.
+// LDS of a block. The environments' columns are interleaved (column
+// env * G + link of each row), so the four environments of a wave use
+// different banks when their lanes touch the same link. The joint blocks live
+// only while the lanes compose their poses; the inertias and the mass matrix
+// are written after the next barriers, so the two share their space.
 template <int G>
-struct EnvLds {
-  float X[6][G];       // exchange of 6-vectors (and the final parameter-cotangent reduction)
-  float Y[6][G];
-  float dinv[G];       // 1 / L_kk
-  float y[G];          // substitution values
-  float x[G];
+struct BlockLds {
+  float X[6][kBlock];   // exchange of 6-vectors (and the final parameter-cotangent reduction)
+  float Y[6][kBlock];
+  float dinv[kBlock];   // 1 / L_kk
+  float y[kBlock];      // substitution values
+  float x[kBlock];
   union {
-    float B[12][G];    // per joint: joint_rot Rot(axis, q) (9), joint_pos (3)
+    float B[12][kBlock];   // per joint: joint_rot Rot(axis, q) (9), joint_pos (3)
     struct {
-      float Ic[10][G];     // body inertias, summed over subtrees
-      float M[G][G + 1];   // row i, entries j on i's root path: the mass matrix, then its factor L (M = L^T L)
+      float Ic[10][kBlock];                // body inertias, summed over subtrees
+      float M[kBlock / G][G][G + 1];       // per env, row i, entries j on i's root path: the mass matrix, then L
     } cm;
   } u;
 };
 
-// sum of the 6-vectors of the links in a bit mask (a root path or a subtree), in ascending link order
+// one environment's view of the block's LDS: row pointers offset to its columns
 template <int G>
-MD V6 mask_sum(const float (&A)[6][G], uint64_t mk) {
+struct EnvLds {
+  float (*X)[kBlock];
+  float (*Y)[kBlock];
+  float (*B)[kBlock];
+  float (*Ic)[kBlock];
+  float (*M)[G + 1];
+  float *dinv, *y, *x;
+};
+template <int G>
+MD EnvLds<G> env_lds(BlockLds<G>& s, int grp) {
+  const int c0 = grp * G;
+  EnvLds<G> e;
+  e.X = reinterpret_cast<float(*)[kBlock]>(&s.X[0][c0]);
+  e.Y = reinterpret_cast<float(*)[kBlock]>(&s.Y[0][c0]);
+  e.B = reinterpret_cast<float(*)[kBlock]>(&s.u.B[0][c0]);
+  e.Ic = reinterpret_cast<float(*)[kBlock]>(&s.u.cm.Ic[0][c0]);
+  e.M = s.u.cm.M[grp];
+  e.dinv = s.dinv + c0;
+  e.y = s.y + c0;
+  e.x = s.x + c0;
+  return e;
+}
+
+// sum of the 6-vectors of the links in a bit mask (a root path or a subtree), in ascending link order
+MD V6 mask_sum(const float (*A)[kBlock], uint64_t mk) {
   V6 r = zero6();
   while (mk) {
     const int j = __builtin_ctzll(mk);
@@ -186,17 +214,47 @@ MD V6 mask_sum(const float (&A)[6][G], uint64_t mk) {
   }
   return r;
 }
-template <int G>
-MD void put6(float (&A)[6][G], int lane, const V6& v) {
+MD void put6(float (*A)[kBlock], int lane, const V6& v) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) A[k][lane] = v.c[k];
 }
-template <int G>
-MD V6 get6(const float (&A)[6][G], int j) {
+MD V6 get6(const float (*A)[kBlock], int j) {
   V6 r;
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.c[k] = A[k][j];
   return r;
+}
+
+// Subtree sums in place: every lane's column of the NA rows of A and the NB
+// rows of B holds its link's own values on entry (visible after a barrier) and
+// the sum over its subtree on return. One height level at a time, a link adds
+// its children's finished sums, so a level costs the most children of any of
+// its links (not the size of the largest subtree).
+template <int NA, int NB>
+MD void subtree_sums(const RbModel& M, const Link& l, int lane, bool live, float (*A)[kBlock], float (*B)[kBlock]) {
+  for (int h = 1; h < M.H; ++h) {
+    if (live && l.height == h) {
+      float a[NA], b[NB > 0 ? NB : 1];
+#pragma unroll
+      for (int k = 0; k < NA; ++k) a[k] = A[k][lane];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) b[k] = B[k][lane];
+      uint64_t mk = l.kids;
+      while (mk) {
+        const int c = __builtin_ctzll(mk);
+        mk &= mk - 1;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) a[k] += A[k][c];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) b[k] += B[k][c];
+      }
+#pragma unroll
+      for (int k = 0; k < NA; ++k) A[k][lane] = a[k];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) B[k][lane] = b[k];
+    }
+    __syncthreads();
+  }
 }
 
 // what the adjoint needs of one substep's forward, per lane
@@ -228,7 +286,7 @@ MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, boo
       while (mk) {
         const int c = __builtin_ctzll(mk);
         mk &= mk - 1;
-        t = fmaf(-E.u.cm.M[c][lane], E.y[c], t);
+        t = fmaf(-E.M[c][lane], E.y[c], t);
       }
       y = t * E.dinv[lane];
       E.y[lane] = y;
@@ -243,7 +301,7 @@ MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, boo
       while (mk) {
         const int j = __builtin_ctzll(mk);
         mk &= mk - 1;
-        t = fmaf(-E.u.cm.M[lane][j], E.x[j], t);
+        t = fmaf(-E.M[lane][j], E.x[j], t);
       }
       x = t * E.dinv[lane];
       E.x[lane] = x;
@@ -272,9 +330,9 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          E.u.B[3 * r + c][lane] = l.Rt[3 * r] * Rq[c] + l.Rt[3 * r + 1] * Rq[3 + c] + l.Rt[3 * r + 2] * Rq[6 + c];
+          E.B[3 * r + c][lane] = l.Rt[3 * r] * Rq[c] + l.Rt[3 * r + 1] * Rq[3 + c] + l.Rt[3 * r + 2] * Rq[6 + c];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) E.u.B[9 + k][lane] = l.pt[k];
+      for (int k = 0; k < 3; ++k) E.B[9 + k][lane] = l.pt[k];
     }
   }
   __syncthreads();
@@ -286,7 +344,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
     while (mk) {
       const int j = __builtin_ctzll(mk);
       mk &= mk - 1;
-      const float t0 = E.u.B[9][j], t1 = E.u.B[10][j], t2 = E.u.B[11][j];
+      const float t0 = E.B[9][j], t1 = E.B[10][j], t2 = E.B[11][j];
 #pragma unroll
       for (int r = 0; r < 3; ++r) p[r] += R[3 * r] * t0 + R[3 * r + 1] * t1 + R[3 * r + 2] * t2;
       float Rn[9];
@@ -294,7 +352,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          Rn[3 * r + c] = R[3 * r] * E.u.B[c][j] + R[3 * r + 1] * E.u.B[3 + c][j] + R[3 * r + 2] * E.u.B[6 + c][j];
+          Rn[3 * r + c] = R[3 * r] * E.B[c][j] + R[3 * r + 1] * E.B[3 + c][j] + R[3 * r + 2] * E.B[6 + c][j];
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = Rn[k];
     }
@@ -369,36 +427,23 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
   __syncthreads();
   if (live) {
     put6(E.X, lane, f);
-    E.u.cm.Ic[0][lane] = F.I.m;
+    E.Ic[0][lane] = F.I.m;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) E.u.cm.Ic[1 + k][lane] = F.I.h[k];
+    for (int k = 0; k < 3; ++k) E.Ic[1 + k][lane] = F.I.h[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) E.u.cm.Ic[4 + k][lane] = F.I.J[k];
+    for (int k = 0; k < 6; ++k) E.Ic[4 + k][lane] = F.I.J[k];
     put6(E.Y, lane, F.S);
   }
   __syncthreads();
   // subtree sums: force (bias torque S_i . F_i) and composite inertia
-  V6 Ft = zero6();
+  subtree_sums<6, 10>(M, l, lane, live, E.X, E.Ic);
+  const V6 Ft = get6(E.X, lane);
   Inertia Ic;
-  Ic.m = 0.f;
+  Ic.m = E.Ic[0][lane];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) Ic.h[k] = 0.f;
+  for (int k = 0; k < 3; ++k) Ic.h[k] = E.Ic[1 + k][lane];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) Ic.J[k] = 0.f;
-  {
-    uint64_t mk = l.desc;
-    while (mk) {
-      const int k = __builtin_ctzll(mk);
-      mk &= mk - 1;
-#pragma unroll
-      for (int a = 0; a < 6; ++a) Ft.c[a] += E.X[a][k];
-      Ic.m += E.u.cm.Ic[0][k];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) Ic.h[a] += E.u.cm.Ic[1 + a][k];
-#pragma unroll
-      for (int a = 0; a < 6; ++a) Ic.J[a] += E.u.cm.Ic[4 + a][k];
-    }
-  }
+  for (int k = 0; k < 6; ++k) Ic.J[k] = E.Ic[4 + k][lane];
   const float rhs = tau - dot6(F.S, Ft) - P.damp * qd;
   // mass matrix row: M_ij = S_j . (Ic_i S_i) for j on the root path (the lane's own row only)
   if (live) {
@@ -407,7 +452,7 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
     while (mk) {
       const int j = __builtin_ctzll(mk);
       mk &= mk - 1;
-      E.u.cm.M[lane][j] = dot6(get6(E.Y, j), Fc);
+      E.M[lane][j] = dot6(get6(E.Y, j), Fc);
     }
   }
   // M = L^T L, leaves first, one height level at a time: the level's links finish their rows (their
@@ -415,15 +460,15 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
   // M_ij -= L_ki L_kj for j on i's root path. Rows a level reads are never written in that level.
   for (int h = 0; h < M.H; ++h) {
     if (live && l.height == h) {
-      const float d = sqrtf(E.u.cm.M[lane][lane]);   // a non-positive pivot gives NaN: the env is flagged non-finite
+      const float d = sqrtf(E.M[lane][lane]);   // a non-positive pivot gives NaN: the env is flagged non-finite
       const float di = 1.f / d;
-      E.u.cm.M[lane][lane] = d;
+      E.M[lane][lane] = d;
       E.dinv[lane] = di;
       uint64_t mk = l.anc & ~(1ull << lane);
       while (mk) {
         const int j = __builtin_ctzll(mk);
         mk &= mk - 1;
-        E.u.cm.M[lane][j] *= di;
+        E.M[lane][j] *= di;
       }
     }
     __syncthreads();
@@ -432,12 +477,12 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
       while (mk) {
         const int k = __builtin_ctzll(mk);
         mk &= mk - 1;
-        const float lki = E.u.cm.M[k][lane];
+        const float lki = E.M[k][lane];
         uint64_t aj = l.anc;
         while (aj) {
           const int j = __builtin_ctzll(aj);
           aj &= aj - 1;
-          E.u.cm.M[lane][j] = fmaf(-lki, E.u.cm.M[k][j], E.u.cm.M[lane][j]);
+          E.M[lane][j] = fmaf(-lki, E.M[k][j], E.M[lane][j]);
         }
       }
     }
@@ -452,12 +497,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_forward(RbModel M, int S, float* 
                                                        float* __restrict__ tape, float* __restrict__ tape_tau,
                                                        int32_t* __restrict__ errs) {
   constexpr int EPB = kBlock / G;
-  __shared__ EnvLds<G> lds[EPB];
+  __shared__ BlockLds<G> lds;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
   const int e = blockIdx.x * EPB + grp;
   const int N = M.N, E = M.E;
   const bool live = e < E && lane < N;
-  EnvLds<G>& L = lds[grp];
+  EnvLds<G> L = env_lds(lds, grp);
   const Link l = load_link(M, lane, live);
   const Prm P = load_prm(M, e);
   const size_t at = (size_t)e * N + lane;
@@ -494,12 +539,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                                                         float* __restrict__ dq0, float* __restrict__ dqd0,
                                                         float* __restrict__ dtau, double* __restrict__ dprm) {
   constexpr int EPB = kBlock / G;
-  __shared__ EnvLds<G> lds[EPB];
+  __shared__ BlockLds<G> lds;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
   const int e = blockIdx.x * EPB + grp;
   const int N = M.N, E = M.E;
   const bool live = e < E && lane < N;
-  EnvLds<G>& L = lds[grp];
+  EnvLds<G> L = env_lds(lds, grp);
   const Link l = load_link(M, lane, live);
   const Prm P = load_prm(M, e);
   const size_t at = (size_t)e * N + lane;
@@ -579,33 +624,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     __syncthreads();
     // phi = sum_i lambda_i S_i . F_i (F_i the subtree force) and A_i = A_0 + sum over the root path of
     // (S_j qdd_j + V_j x S_j qd_j): subtree sums of f and of A_bar
-    V6 Ft = zero6(), DA = zero6();
-    {
-      uint64_t mk = l.desc;
-      while (mk) {
-        const int k = __builtin_ctzll(mk);
-        mk &= mk - 1;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          Ft.c[c] += L.X[c][k];
-          DA.c[c] += L.Y[c][k];
-        }
-      }
-    }
+    subtree_sums<6, 6>(M, l, lane, live, L.X, L.Y);
+    const V6 Ft = get6(L.X, lane), DA = get6(L.Y, lane);
     V6 Sbar = add6(scale6(Ft, lam), scale6(DA, qdd));
     Vbar = add6(Vbar, crf(F.u, DA));
     __syncthreads();
     if (live) put6(L.X, lane, Vbar);
     __syncthreads();
     // V_i = sum over the root path of u_j, u_j = S_j qd_j
-    const V6 ubar = sub6(mask_sum(L.X, l.desc), crf(F.V, DA));
+    subtree_sums<6, 0>(M, l, lane, live, L.X, nullptr);
+    const V6 ubar = sub6(get6(L.X, lane), crf(F.V, DA));
     Sbar = add6(Sbar, scale6(ubar, qdi));
     const float dphi_qd = dot6(F.S, ubar);
     W = add6(W, crf(F.S, Sbar));
     if (live) put6(L.Y, lane, W);
     __syncthreads();
     // turning joint j moves its whole subtree: dphi/dq_j = S_j . (subtree sum of the wrenches)
-    const float dphi_q = dot6(F.S, mask_sum(L.Y, l.desc));
+    subtree_sums<6, 0>(M, l, lane, live, L.Y, nullptr);
+    const float dphi_q = dot6(F.S, get6(L.Y, lane));
     a = a - dphi_q;
     b = gtot - P.damp * lam - dphi_qd;
   }

@@ -27,6 +27,7 @@ struct mpm_rb {
   float* link = nullptr;       // [N][kRbLinkF]
   uint64_t* anc = nullptr;     // [N]
   uint64_t* desc = nullptr;    // [N]
+  uint64_t* kids = nullptr;    // [N]
   int32_t* level = nullptr;    // [N] height | depth << 16
   uint64_t* hmask = nullptr;   // [H]
   int H = 0, D = 0;
@@ -91,6 +92,7 @@ mpmx::RbModel model_of(const mpm_rb* r) {
   m.link = r->link;
   m.anc = r->anc;
   m.desc = r->desc;
+  m.kids = r->kids;
   m.level = r->level;
   m.hmask = r->hmask;
   m.H = r->H;
@@ -172,7 +174,9 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   for (int i = 0; i < N; ++i) depth[i] = links[i].parent < 0 ? 0 : depth[links[i].parent] + 1;
   for (int i = N - 1; i >= 0; --i)
     if (links[i].parent >= 0) height[links[i].parent] = std::max(height[links[i].parent], height[i] + 1);
-  std::vector<uint64_t> hmask(N, 0);
+  std::vector<uint64_t> hmask(N, 0), kids(N, 0);
+  for (int i = 0; i < N; ++i)
+    if (links[i].parent >= 0) kids[links[i].parent] |= 1ull << i;
   for (int i = 0; i < N; ++i) {
     level[i] = height[i] | (depth[i] << 16);
     hmask[height[i]] |= 1ull << i;
@@ -222,6 +226,7 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   r->desc = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->cbeg = (int32_t*)ralloc(r, sizeof(int32_t) * (N + 1));
   r->level = (int32_t*)ralloc(r, sizeof(int32_t) * N);
+  r->kids = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->hmask = (uint64_t*)ralloc(r, sizeof(uint64_t) * N);
   r->contact = (float*)ralloc(r, sizeof(float) * ct.size());
   r->prm = (float*)ralloc(r, sizeof(float) * mpmx::kRbPrm * E);
@@ -230,7 +235,7 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   r->tape = (float*)ralloc(r, sizeof(float) * 2 * E * N * (size_t)(r->max_S + 1));
   r->tape_tau = (float*)ralloc(r, sizeof(float) * E * N * (size_t)(r->max_S > 0 ? r->max_S : 1));
   r->errs = (int32_t*)ralloc(r, sizeof(int32_t) * E);
-  if (!(r->link && r->anc && r->desc && r->level && r->hmask && r->cbeg && r->contact && r->prm && r->q && r->qd && r->tape && r->tape_tau &&
+  if (!(r->link && r->anc && r->desc && r->kids && r->level && r->hmask && r->cbeg && r->contact && r->prm && r->q && r->qd && r->tape && r->tape_tau &&
         r->errs)) {
     free_all(r);
     delete r;
@@ -245,6 +250,7 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
   hipError_t e1 = hipMemcpyAsync(r->link, lk.data(), sizeof(float) * lk.size(), hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->anc, anc.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->desc, desc.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
+  if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->kids, kids.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->level, level.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->hmask, hmask.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, r->stream);
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(r->cbeg, cbeg.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, r->stream);

@@ -144,12 +144,23 @@ def random_tree(seed: int, n_links: int, chain: float = 0.5, n_contacts: int = 4
 
 
 def tree_batch(seed: int, n_links: int, n_envs: int = 4, substeps: int = 6, dt: float = FRAME_DT / 16,
-               ground: float = 0.3) -> RbWorkload:
+               ground: float = 0.3, n_contacts: int = 4, roots: int = 1) -> RbWorkload:
     """Random states (angles U(-1, 1), speeds U(-2, 2)) and torques U(-0.5, 0.5)
     on `random_tree`, joint damping U(0.01, 0.05), a ground at z_g = `ground`
-    with stiffness 2000."""
+    with stiffness 2000. With roots > 1 the links are split into that many
+    trees (a forest: link k * n_links // roots starts a new tree)."""
     rng = np.random.Generator(np.random.PCG64(seed + 1000))
-    links = random_tree(seed, n_links)
+    links = random_tree(seed, n_links, n_contacts=n_contacts)
+    for r in range(1, roots):
+        k = r * n_links // roots
+        links[k].parent = -1
+        links[k].joint_pos = np.array([0.4 * r, 0.0, 0.5])
+        for i in range(k + 1, n_links):
+            if links[i].parent < k:
+                links[i].parent = k if links[i].parent >= 0 else -1
+        for i in range(k + 1, n_links):
+            if links[i].parent == -1:
+                links[i].parent = k
     N = len(links)
     q0 = rng.uniform(-1.0, 1.0, size=(n_envs, N))
     qd0 = rng.uniform(-2.0, 2.0, size=(n_envs, N))

@@ -93,16 +93,27 @@ def test_hand_matches_oracle():
     check("hand", w, gpu, o, og)
 
 
-@pytest.mark.parametrize("n_links,n_envs", [(5, 11), (16, 5), (24, 3), (40, 2)])
+@pytest.mark.parametrize("n_links,n_envs", [(5, 11), (8, 3), (16, 5), (24, 3), (40, 2), (64, 2)])
 def test_random_trees_match_oracle(n_links, n_envs):
-    """Random trees filling lane groups of 8, 16 (exactly full), 32 and 64,
-    with env counts that leave the last block ragged; contacts, damping and
-    torques active."""
-    w = RS.tree_batch(seed=n_links, n_links=n_links, n_envs=n_envs, substeps=6)
+    """Random trees in lane groups of 8, 16, 32 and 64 (8, 16 and 64 links fill
+    theirs exactly; 64 uses the last bit of the masks), with env counts that
+    leave the last block ragged; contacts, damping and torques active."""
+    w = RS.tree_batch(seed=n_links, n_links=n_links, n_envs=n_envs, substeps=6 if n_links < 64 else 4)
     announce(f"tree: E {w.n_envs} N {n_links} S {w.substeps}")
     gpu, gq, gqd = run_gpu(w, seed=n_links)
     o, og = oracle(w, gq, gqd)
     check(f"tree{n_links}", w, gpu, o, og)
+
+
+@pytest.mark.parametrize("roots,n_contacts", [(2, 4), (3, 0)])
+def test_forests_and_no_contacts_match_oracle(roots, n_contacts):
+    """Several independent trees in one model (the factorisation's levels span
+    them all), and a model without contact spheres."""
+    w = RS.tree_batch(seed=20 + roots, n_links=18, n_envs=3, substeps=6, roots=roots, n_contacts=n_contacts)
+    announce(f"forest: roots {roots} contacts {n_contacts} E {w.n_envs} N 18 S {w.substeps}")
+    gpu, gq, gqd = run_gpu(w, seed=roots)
+    o, og = oracle(w, gq, gqd)
+    check(f"forest{roots}", w, gpu, o, og)
 
 
 def test_textbook_two_link_arm_free_swing():

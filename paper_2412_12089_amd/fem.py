@@ -3,7 +3,8 @@
 `FemBatch` owns a library handle and passes torch CUDA tensors by address;
 every step runs in the library's HIP kernels. `FEMRollout` makes a recorded
 forward and its adjoint an autograd Function, differentiable in the initial
-state, the activations and the per-env parameters.
+state, the activations and the per-env parameters; calls on one batch can be
+chained (a backward whose record was replaced re-runs its forward first).
 """
 from __future__ import annotations
 
@@ -40,6 +41,7 @@ class FemBatch:
         C.check(code, "mpm_fem_create")
         self.recorded = None
         self._keep = None
+        self.record_token = 0   # changes whenever the library's record is replaced or dropped
 
     def close(self):
         if self.h:
@@ -66,11 +68,14 @@ class FemBatch:
         X = _f32(X, self.device)
         self._sync_in()
         self._chk(self.lib.mpm_fem_set_rest(self.h, C.ptr(X)), "mpm_fem_set_rest")
+        self.recorded = None
+        self.record_token += 1
 
     def set_params(self, params) -> None:
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.E, C.MPM_FEM_PARAMS))
         self._chk(self.lib.mpm_fem_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                   "mpm_fem_set_params")
+        self.record_token += 1
 
     def set_state(self, x, v=None) -> None:
         x = _f32(x, self.device)
@@ -79,6 +84,7 @@ class FemBatch:
         self._sync_in()
         self._chk(self.lib.mpm_fem_set_state(self.h, C.ptr(x), C.ptr(v)), "mpm_fem_set_state")
         self.recorded = None
+        self.record_token += 1
 
     def get_state(self):
         x = torch.empty(self.E, self.n, 3, device=self.device)
@@ -97,6 +103,7 @@ class FemBatch:
         self._chk(self.lib.mpm_fem_forward(self.h, int(S), C.ptr(a), C.MPM_FWD_RECORD if record else 0),
                   "mpm_fem_forward")
         self.recorded = int(S) if record else None
+        self.record_token += 1
 
     def backward(self, gx=None, gv=None, want_act: bool = True, want_params: bool = True):
         if self.recorded is None:
@@ -132,27 +139,34 @@ class FemBatch:
 class FEMRollout(torch.autograd.Function):
     """(x_S, v_S) = S substeps of the batch from (x0, v0) with activations act
     [S, E, T] and per-env parameters params [E, 8] (float64), differentiable
-    in all four. The batch's rest shape is fixed; the backward uses the
-    batch's record, so the batch must not be stepped again in between."""
+    in all four. The batch's rest shape is fixed. If the batch has been used
+    since this call's forward, the backward first re-runs the forward from
+    the saved inputs, so calls can be chained in one graph."""
 
     @staticmethod
-    def forward(ctx, batch: FemBatch, S: int, x0, v0, act, params):
+    def _run(batch: FemBatch, S: int, x0, v0, act, params):
         batch.set_params(params.detach().cpu().numpy())
         batch.set_state(x0.detach(), v0.detach())
         batch.forward(S, act.detach(), record=True)
+
+    @staticmethod
+    def forward(ctx, batch: FemBatch, S: int, x0, v0, act, params):
+        FEMRollout._run(batch, S, x0, v0, act, params)
         x, v = batch.get_state()
-        ctx.batch = batch
-        ctx.token = batch._keep
-        ctx.prm_device = params.device
+        ctx.batch, ctx.S = batch, S
+        ctx.token = batch.record_token
+        ctx.save_for_backward(x0, v0, act, params)
         return x, v
 
     @staticmethod
     def backward(ctx, gx, gv):
         b = ctx.batch
-        if b._keep is not ctx.token or b.recorded is None:
-            raise RuntimeError("the FEM batch was stepped again after this rollout's forward")
+        x0, v0, act, params = ctx.saved_tensors
+        if b.record_token != ctx.token:
+            FEMRollout._run(b, ctx.S, x0, v0, act, params)
+            ctx.token = b.record_token
         dx, dv, da, dp = b.backward(gx, gv)
-        return None, None, dx, dv, da, dp.to(device=ctx.prm_device, dtype=torch.float64)
+        return None, None, dx, dv, da, dp.to(device=params.device, dtype=torch.float64)
 
 
 def rollout(batch: FemBatch, S: int, x0, v0, act, params):

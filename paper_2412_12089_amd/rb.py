@@ -3,7 +3,8 @@
 `RbBatch` owns a library handle and passes torch CUDA tensors by address;
 every step runs in the library's HIP kernels. `RBRollout` makes a recorded
 forward and its adjoint an autograd Function, differentiable in the initial
-state, the torques and the per-env parameters.
+state, the torques and the per-env parameters; calls on one batch can be
+chained (a backward whose record was replaced re-runs its forward first).
 """
 from __future__ import annotations
 
@@ -66,6 +67,7 @@ class RbBatch:
         C.check(code, "mpm_rb_create")
         self.recorded = None
         self._keep = None
+        self.record_token = 0   # changes whenever the library's record is replaced or dropped
 
     def close(self):
         if self.h:
@@ -91,6 +93,7 @@ class RbBatch:
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.E, C.MPM_RB_PARAMS))
         self._chk(self.lib.mpm_rb_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                   "mpm_rb_set_params")
+        self.record_token += 1
 
     def set_state(self, q, qd=None) -> None:
         q = _f32(q, self.device)
@@ -99,6 +102,7 @@ class RbBatch:
         self._sync_in()
         self._chk(self.lib.mpm_rb_set_state(self.h, C.ptr(q), C.ptr(qd)), "mpm_rb_set_state")
         self.recorded = None
+        self.record_token += 1
 
     def get_state(self):
         q = torch.empty(self.E, self.N, device=self.device)
@@ -117,6 +121,7 @@ class RbBatch:
         self._chk(self.lib.mpm_rb_forward(self.h, int(S), C.ptr(t), C.MPM_FWD_RECORD if record else 0),
                   "mpm_rb_forward")
         self.recorded = int(S) if record else None
+        self.record_token += 1
 
     def backward(self, gq=None, gqd=None, want_tau: bool = True, want_params: bool = True):
         if self.recorded is None:
@@ -152,27 +157,34 @@ class RbBatch:
 class RBRollout(torch.autograd.Function):
     """(q_S, qd_S) = S substeps of the batch from (q0, qd0) with torques tau
     [S, E, N] and per-env parameters params [E, 5] (float64), differentiable
-    in all four. The backward uses the batch's record, so the batch must not
-    be stepped again in between."""
+    in all four. If the batch has been used since this call's forward, the
+    backward first re-runs the forward from the saved inputs, so calls can be
+    chained (one env step after another) in one graph."""
 
     @staticmethod
-    def forward(ctx, batch: RbBatch, S: int, q0, qd0, tau, params):
+    def _run(batch: RbBatch, S: int, q0, qd0, tau, params):
         batch.set_params(params.detach().cpu().numpy())
         batch.set_state(q0.detach(), qd0.detach())
         batch.forward(S, tau.detach(), record=True)
+
+    @staticmethod
+    def forward(ctx, batch: RbBatch, S: int, q0, qd0, tau, params):
+        RBRollout._run(batch, S, q0, qd0, tau, params)
         q, qd = batch.get_state()
-        ctx.batch = batch
-        ctx.token = batch._keep
-        ctx.prm_device = params.device
+        ctx.batch, ctx.S = batch, S
+        ctx.token = batch.record_token
+        ctx.save_for_backward(q0, qd0, tau, params)
         return q, qd
 
     @staticmethod
     def backward(ctx, gq, gqd):
         b = ctx.batch
-        if b._keep is not ctx.token or b.recorded is None:
-            raise RuntimeError("the rigid-body batch was stepped again after this rollout's forward")
+        q0, qd0, tau, params = ctx.saved_tensors
+        if b.record_token != ctx.token:
+            RBRollout._run(b, ctx.S, q0, qd0, tau, params)
+            ctx.token = b.record_token
         dq, dqd, dt, dp = b.backward(gq, gqd)
-        return None, None, dq, dqd, dt, dp.to(device=ctx.prm_device, dtype=torch.float64)
+        return None, None, dq, dqd, dt, dp.to(device=params.device, dtype=torch.float64)
 
 
 def rollout(batch: RbBatch, S: int, q0, qd0, tau, params):

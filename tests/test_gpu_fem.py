@@ -145,6 +145,35 @@ def test_mesh_whose_adjoint_needs_more_than_64_kib_of_lds():
         check_env("big_block", w, e, gpu, o, og)
 
 
+def test_chained_rollouts_match_one_rollout():
+    """Two env steps through one batch in one autograd graph (the first step's
+    backward re-runs its forward, its record having been replaced) against one
+    rollout over both: the same states, and the same gradients of the initial
+    state, the activations and the parameters."""
+    from paper_2412_12089_amd.fem import rollout
+    dev = torch.device("cuda:0")
+    w = FS.two_cubes(seed=9, n_envs=3, substeps=12)
+    b = make_batch(w)
+    S1 = 5
+
+    def leaves():
+        return (torch.from_numpy(w.x0).to(dev).requires_grad_(True), torch.from_numpy(w.v0).to(dev).requires_grad_(True),
+                torch.from_numpy(w.act).to(dev).requires_grad_(True), torch.from_numpy(w.params).requires_grad_(True))
+
+    x0, v0, act, prm = leaves()
+    x1, v1 = rollout(b, S1, x0, v0, act[:S1], prm)
+    x2, v2 = rollout(b, w.substeps - S1, x1, v1, act[S1:], prm)
+    ((x2 - x2.detach().mean()) ** 2).sum().backward()
+    g_chain = [t.grad.clone() for t in (x0, v0, act, prm)]
+    r0, rv0, ra, rp = leaves()
+    xa, va = rollout(b, w.substeps, r0, rv0, ra, rp)
+    ((xa - xa.detach().mean()) ** 2).sum().backward()
+    assert torch.equal(x2, xa) and torch.equal(v2, va)
+    for name, g, r in zip(("x0", "v0", "act", "params"), g_chain, (r0.grad, rv0.grad, ra.grad, rp.grad)):
+        assert torch.allclose(g, r, rtol=1e-5, atol=1e-6 * float(r.abs().max())), name
+    b.close()
+
+
 def test_zero_substeps_and_missing_activations():
     dev = torch.device("cuda:0")
     w = FS.two_cubes(seed=5, n_envs=2, substeps=4)

@@ -221,3 +221,32 @@ def test_interface_errors():
     assert ei.value.code == C.MPM_INVALID_ARG
     assert b.memory_bytes() > 0
     b.close()
+
+
+def test_chained_rollouts_match_one_rollout():
+    """Two env steps through one batch in one autograd graph (the first step's
+    backward re-runs its forward, its record having been replaced) against one
+    rollout over both: the same states, and the same gradients of the initial
+    state, the torques and the parameters."""
+    from paper_2412_12089_amd.rb import rollout
+    dev = torch.device("cuda:0")
+    w = RS.hand_batch(seed=13, n_envs=5, substeps=16)
+    b = make_batch(w)
+    S1 = 6
+
+    def leaves():
+        return (torch.from_numpy(w.q0).to(dev).requires_grad_(True), torch.from_numpy(w.qd0).to(dev).requires_grad_(True),
+                torch.from_numpy(w.tau).to(dev).requires_grad_(True), torch.from_numpy(w.params).requires_grad_(True))
+
+    q0, qd0, tau, prm = leaves()
+    q1, qd1 = rollout(b, S1, q0, qd0, tau[:S1], prm)
+    q2, qd2 = rollout(b, w.substeps - S1, q1, qd1, tau[S1:], prm)
+    (q2 * q2).sum().backward()
+    g_chain = [t.grad.clone() for t in (q0, qd0, tau, prm)]
+    r0, rd0, rt, rp = leaves()
+    qa, qda = rollout(b, w.substeps, r0, rd0, rt, rp)
+    (qa * qa).sum().backward()
+    assert torch.equal(q2, qa) and torch.equal(qd2, qda)
+    for name, g, r in zip(("q0", "qd0", "tau", "params"), g_chain, (r0.grad, rd0.grad, rt.grad, rp.grad)):
+        assert torch.allclose(g, r, rtol=1e-5, atol=1e-6 * float(r.abs().max())), name
+    b.close()

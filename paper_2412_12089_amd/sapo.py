@@ -12,7 +12,8 @@ to a target entropy of -dim(A)/2 and the entropy is normalized by it. Design
 choices follow Section 4.2: squashed-Normal policy with state-dependent
 variance, LayerNorm + SiLU MLPs, AdamW, gradient norm clipping at 0.5.
 
-The task (`PushTask`) stands in for the paper's manipulation scenes, whose
+`HandEnv` is a second task on the articulated rigid-body path (see its
+docstring). The first task (`PushTask`) stands in for the paper's manipulation scenes, whose
 assets are not available: E envs, each a neo-Hookean block of dough with a box
 pusher beside it; an action a in [-1, 1]^3 sets the box velocity
 (max_speed * a) for the substeps of one env step; the reward is the progress of
@@ -105,6 +106,65 @@ class PushEnv:
         self.batch.close()
 
 
+@dataclasses.dataclass
+class HandTask:
+    n_envs: int = 16
+    substeps: int = 16          # rigid-body substeps per env step (one 1/60 s frame)
+    max_torque: float = 1e-2    # joint torque at |a| = 1 (N m)
+    reward_scale: float = 10.0
+    action_cost: float = 1e-3
+    seed: int = 0
+
+
+class HandEnv:
+    """A second task, on the articulated rigid-body path: E 13-link hands
+    (`rb_scenes.hand_batch`, finger tips over a ground) start at random joint
+    angles and speeds; an action a in [-1, 1]^13 sets the joint torques
+    (max_torque * a) for the substeps of one env step; the reward is the
+    progress of the joints toward a curled target pose (mean squared angle
+    error, wrist 0.3 rad, finger joints 0.8 rad) minus a small action cost.
+    Observations: the angle errors and the joint speeds. Env steps are chained
+    `RBRollout` calls, so the actor's gradient runs through the rigid-body
+    adjoint."""
+    act_dim = 13
+    obs_dim = 26
+
+    def __init__(self, task: HandTask, device=None):
+        from . import rb_scenes
+        from .rb import RbBatch
+        self.task = task
+        self.device = device or torch.device("cuda:0")
+        w = rb_scenes.hand_batch(seed=task.seed, n_envs=task.n_envs, substeps=task.substeps)
+        self.batch = RbBatch(w.links, task.n_envs, task.substeps, w.dt, w.gravity, self.device)
+        self.params = torch.from_numpy(w.params)
+        self.init_state = (torch.from_numpy(w.q0).to(self.device), torch.from_numpy(w.qd0).to(self.device))
+        tgt = np.full(len(w.links), 0.8, dtype=np.float32)
+        tgt[0] = 0.3
+        self.target = torch.from_numpy(tgt).to(self.device)
+        self.none = torch.zeros(task.n_envs, 1)
+
+    def reset(self):
+        return tuple(t.clone() for t in self.init_state), self.none
+
+    def obs(self, state, _):
+        q, qd = state
+        return torch.cat([q - self.target, 0.1 * qd], 1).float()
+
+    def step(self, state, _, a):
+        """One env step, differentiable in state and a [E, 13] (on the CPU, float32)."""
+        from .rb import rollout
+        T = self.task
+        tau = (T.max_torque * a.to(self.device))[None].expand(T.substeps, -1, -1).contiguous()
+        d0 = ((state[0] - self.target) ** 2).mean(1)
+        nxt = rollout(self.batch, T.substeps, state[0], state[1], tau, self.params)
+        d1 = ((nxt[0] - self.target) ** 2).mean(1)
+        r = T.reward_scale * (d0 - d1).float().cpu() - T.action_cost * (a ** 2).sum(1)
+        return nxt, self.none, r
+
+    def close(self):
+        self.batch.close()
+
+
 def td_lambda_targets(r, v_next, gamma: float, lam: float):
     """lambda-returns of an H-step window (TD(lambda) of the SHAC/SAPO critic):
     r [H, E] the (soft) rewards, v_next [H, E] the value of s_{t+1}; returns
@@ -144,7 +204,7 @@ class Actor(nn.Module):
 
 
 class SAPO:
-    def __init__(self, env: PushEnv, horizon: int = 6, gamma: float = 0.99, lam: float = 0.95, n_critics: int = 2,
+    def __init__(self, env, horizon: int = 6, gamma: float = 0.99, lam: float = 0.95, n_critics: int = 2,
                  critic_iters: int = 8, lr_actor: float = 2e-3, lr_critic: float = 2e-3, lr_alpha: float = 5e-3,
                  seed: int = 0):
         torch.manual_seed(seed)

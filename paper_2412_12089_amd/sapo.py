@@ -12,8 +12,8 @@ to a target entropy of -dim(A)/2 and the entropy is normalized by it. Design
 choices follow Section 4.2: squashed-Normal policy with state-dependent
 variance, LayerNorm + SiLU MLPs, AdamW, gradient norm clipping at 0.5.
 
-`HandEnv` is a second task on the articulated rigid-body path (see its
-docstring). The first task (`PushTask`) stands in for the paper's manipulation scenes, whose
+`HandEnv` and `JumperEnv` are tasks on the articulated rigid-body and the
+tetrahedral FEM paths (see their docstrings). The first task (`PushTask`) stands in for the paper's manipulation scenes, whose
 assets are not available: E envs, each a neo-Hookean block of dough with a box
 pusher beside it; an action a in [-1, 1]^3 sets the box velocity
 (max_speed * a) for the substeps of one env step; the reward is the progress of
@@ -159,6 +159,74 @@ class HandEnv:
         nxt = rollout(self.batch, T.substeps, state[0], state[1], tau, self.params)
         d1 = ((nxt[0] - self.target) ** 2).mean(1)
         r = T.reward_scale * (d0 - d1).float().cpu() - T.action_cost * (a ** 2).sum(1)
+        return nxt, self.none, r
+
+    def close(self):
+        self.batch.close()
+
+
+@dataclasses.dataclass
+class JumperTask:
+    n_envs: int = 16
+    substeps: int = 80          # FEM substeps per env step (one 1/60 s frame)
+    act_scale: float = 0.3      # element activation at |a| = 1
+    reward_scale: float = 300.0
+    action_cost: float = 1e-3
+    seed: int = 0
+
+
+class JumperEnv:
+    """A third task, on the tetrahedral FEM path: E soft jumpers
+    (`fem_scenes.soft_jumper`) standing on the ground; the elements form eight
+    muscle groups (the octants of the rest shape about its centre), and an
+    action a in [-1, 1]^8 sets every element's activation to act_scale times
+    its group's entry for the substeps of one env step; the reward is the
+    rise plus the forward (+x) progress of the mean node position (a jump;
+    the ground's viscous friction is too weak to walk on) minus a small
+    action cost.
+    Observations: the mean node position relative to the start and the mean
+    node velocity. Env steps are chained `FEMRollout` calls."""
+    act_dim = 8
+    obs_dim = 6
+
+    def __init__(self, task: JumperTask, device=None):
+        from . import fem_scenes
+        from .fem import FemBatch
+        self.task = task
+        self.device = device or torch.device("cuda:0")
+        w = fem_scenes.soft_jumper(seed=task.seed, n_envs=task.n_envs, substeps=task.substeps)
+        n = w.X.shape[1]
+        self.batch = FemBatch(w.tets, task.n_envs, n, task.substeps, w.dt, w.gravity, self.device)
+        self.batch.set_rest(torch.from_numpy(w.X).to(self.device))
+        self.params = torch.from_numpy(w.params)
+        self.init_state = (torch.from_numpy(w.x0).to(self.device), torch.from_numpy(w.v0).to(self.device))
+        X0 = w.X[0].astype(np.float64)
+        cen = X0[w.tets].mean(1)                       # element centroids of env 0's rest shape
+        mid = X0.mean(0)
+        grp = ((cen[:, 0] > mid[0]) * 4 + (cen[:, 1] > mid[1]) * 2 + (cen[:, 2] > mid[2])).astype(np.int64)
+        onehot = np.zeros((w.tets.shape[0], 8), dtype=np.float32)
+        onehot[np.arange(len(grp)), grp] = 1.0
+        self.groups = torch.from_numpy(onehot).to(self.device)     # [T, 8]
+        self.start = self.init_state[0].mean(1)
+        self.none = torch.zeros(task.n_envs, 1)
+
+    def reset(self):
+        return tuple(t.clone() for t in self.init_state), self.none
+
+    def obs(self, state, _):
+        x, v = state
+        return torch.cat([10.0 * (x.mean(1) - self.start), v.mean(1)], 1).float()
+
+    def step(self, state, _, a):
+        """One env step, differentiable in state and a [E, 8] (on the CPU, float32)."""
+        from .fem import rollout
+        T = self.task
+        act = (T.act_scale * a.to(self.device)) @ self.groups.T                  # [E, T]
+        act = act[None].expand(T.substeps, -1, -1).contiguous()
+        c0 = (state[0][:, :, 0] + state[0][:, :, 2]).mean(1)
+        nxt = rollout(self.batch, T.substeps, state[0], state[1], act, self.params)
+        c1 = (nxt[0][:, :, 0] + nxt[0][:, :, 2]).mean(1)
+        r = T.reward_scale * (c1 - c0).float().cpu() - T.action_cost * (a ** 2).sum(1)
         return nxt, self.none, r
 
     def close(self):

@@ -142,22 +142,31 @@ MD M3 edge_matrix(const float* p, int4 t) {
   return from_cols(sub3(ld3(p + 3 * t.y), p0), sub3(ld3(p + 3 * t.z), p0), sub3(ld3(p + 3 * t.w), p0));
 }
 
+// one incidence's term: the element's column of the node's corner (corners 1..3), or minus the sum of its three
+// columns (corner 0); `code` is tet * 4 + corner
+MD float3 column_term(const float* cols, int stride, int code) {
+  const float* h = cols + (int64_t)(code >> 2) * stride;
+  const int c = code & 3;
+  if (c > 0) return make_float3(h[3 * (c - 1)], h[3 * (c - 1) + 1], h[3 * (c - 1) + 2]);
+  return make_float3(-(h[0] + h[3] + h[6]), -(h[1] + h[4] + h[7]), -(h[2] + h[5] + h[8]));
+}
+
 // sum over node i's incidences of the per-element columns cols[(tet * stride + c) * 3 ..] for corners c = 1..3,
-// corner 0 taking minus the sum of its element's three columns
+// corner 0 taking minus the sum of its element's three columns; two incidences per iteration, so that their
+// index and column reads overlap (the sum is taken in incidence order all the same)
 MD float3 gather_columns(const float* cols, int stride, const int* ioff, const int* inc, int i) {
   float3 s = make_float3(0.f, 0.f, 0.f);
-  for (int q = ioff[i]; q < ioff[i + 1]; ++q) {
-    const int tet = inc[q] >> 2, c = inc[q] & 3;
-    const float* h = cols + (int64_t)tet * stride;
-    if (c > 0) {
-      s.x += h[3 * (c - 1)];
-      s.y += h[3 * (c - 1) + 1];
-      s.z += h[3 * (c - 1) + 2];
-    } else {
-      s.x -= h[0] + h[3] + h[6];
-      s.y -= h[1] + h[4] + h[7];
-      s.z -= h[2] + h[5] + h[8];
-    }
+  int q = ioff[i];
+  const int qe = ioff[i + 1];
+  for (; q + 1 < qe; q += 2) {
+    const int c0 = inc[q], c1 = inc[q + 1];
+    const float3 a = column_term(cols, stride, c0), b = column_term(cols, stride, c1);
+    s.x += a.x; s.y += a.y; s.z += a.z;
+    s.x += b.x; s.y += b.y; s.z += b.z;
+  }
+  if (q < qe) {
+    const float3 a = column_term(cols, stride, inc[q]);
+    s.x += a.x; s.y += a.y; s.z += a.z;
   }
   return s;
 }

@@ -105,6 +105,18 @@ def test_jumper_full_size_matches_oracle():
         check_env("jumper", w, e, gpu, o, og)
 
 
+def test_bench_size_sampled_envs_match_oracle():
+    """The bench's FEM configuration (4096 jumpers, one 80-substep frame, the
+    same seed), forward and backward in one launch each; envs at both ends of
+    the batch against the oracle."""
+    w = FS.soft_jumper(seed=7, n_envs=4096, substeps=80)
+    announce(f"bench size: E {w.n_envs} n {w.X.shape[1]} T {w.tets.shape[0]} S {w.substeps}")
+    gpu, gx, gv = run_gpu(w, seed=6)
+    for e in (0, 4095):
+        o, og = oracle_env(w, e, gx, gv)
+        check_env("bench-size", w, e, gpu, o, og)
+
+
 def test_large_mesh_four_elements_per_thread():
     """A 4 x 4 x 6 block of cubes (175 nodes, 576 elements: the launch with
     four per thread), stretched and moving, standing on the ground."""

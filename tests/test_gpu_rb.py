@@ -250,3 +250,19 @@ def test_chained_rollouts_match_one_rollout():
     for name, g, r in zip(("q0", "qd0", "tau", "params"), g_chain, (r0.grad, rd0.grad, rt.grad, rp.grad)):
         assert torch.allclose(g, r, rtol=1e-5, atol=1e-6 * float(r.abs().max())), name
     b.close()
+
+
+def test_bench_size_sampled_envs_match_oracle():
+    """The bench's rigid-body configuration (65536 hands, one 16-substep frame,
+    the same seed), forward and backward in one launch each; envs at both ends
+    and inside the batch against the oracle."""
+    dev = torch.device("cuda:0")
+    w = RS.hand_batch(seed=9, n_envs=65536, substeps=16)
+    announce(f"bench size: E {w.n_envs} N {len(w.links)} S {w.substeps}")
+    gpu, gq, gqd = run_gpu(w, seed=3)
+    picks = [0, 1, 4097, 40000, 65535]
+    sub = RS.RbWorkload(w.name, w.links, w.q0[picks], w.qd0[picks], w.params[picks], w.tau[:, picks], w.dt,
+                        w.substeps)
+    o, og = oracle(sub, gq[picks], gqd[picks])
+    q, qd, dq, dqd, dt, dp = gpu
+    check("bench-size", sub, [q[picks], qd[picks], dq[picks], dqd[picks], dt[:, picks], dp[picks]], o, og)

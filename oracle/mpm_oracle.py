@@ -70,6 +70,7 @@ class Box:
     axis: Tuple[float, float, float] = (0.0, 0.0, 1.0)   # unit rotation axis (world)
     angle: float = 0.0                     # rotation about the axis at t = 0 (rad)
     omega: float = 0.0                     # constant angular speed about the axis (rad/s)
+    shape: str = "box"                     # "box", or "sphere": a ball of radius half[0] about the center
 
 
 @dataclass
@@ -90,7 +91,7 @@ def env_from_spec(spec) -> Tuple[Env, torch.Tensor, Tuple[torch.Tensor, ...]]:
         c = spec.collider
         box = Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b),
                   tuple(getattr(c, "axis", (0.0, 0.0, 1.0))), float(getattr(c, "angle", 0.0)),
-                  float(getattr(c, "omega", 0.0)))
+                  float(getattr(c, "omega", 0.0)), str(getattr(c, "shape", "box")))
     env = Env(n=spec.n, dt=spec.dt, material=spec.material, gravity=tuple(spec.gravity),
               wall=spec.wall, collider=box)
     prm = torch.tensor([spec.E, spec.nu, spec.rho, spec.Vp, spec.sigma_y, spec.K, spec.gamma], dtype=DT)
@@ -364,6 +365,16 @@ def box_sdf(p, center, half):
     return d, nrm
 
 
+def sphere_sdf(p, center, radius):
+    """Signed distance to a ball, |p - c| - r, and its outward unit normal
+    (p - c) / |p - c| (the +z axis at the center itself, where it is undefined)."""
+    rel = p - center
+    L = rel.norm(dim=1)
+    at_c = L == 0
+    nrm = torch.where(at_c[:, None], torch.tensor([0.0, 0.0, 1.0], dtype=DT), rel / torch.where(at_c, 1.0, L)[:, None])
+    return L - radius, nrm
+
+
 def rotation(axis, theta):
     """Rotation by theta about the unit axis (Rodrigues): I + sin t K + (1 - cos t) K^2, K = [axis]x."""
     a = torch.as_tensor(axis, dtype=DT)
@@ -381,13 +392,18 @@ def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     (tensors, so that derivatives reach a prescribed collider motion). The box
     is axis-aligned in its own frame: a node's distance and normal come from
     its position R^T (x - c) in that frame, rotated back to the world, and the
-    box surface moves at vb + omega axis x (x - c)."""
+    box surface moves at vb + omega axis x (x - c). A sphere collider's
+    distance and normal do not depend on its angle; its spin still moves its
+    surface."""
     box = env.collider
     n = env.n
-    R = rotation(box.axis, theta)
     p = node_positions(n)
-    d, nh = box_sdf((p - center) @ R, torch.zeros(3, dtype=DT), torch.tensor(box.half, dtype=DT))
-    nh = nh @ R.T
+    if box.shape == "sphere":
+        d, nh = sphere_sdf(p, center, float(box.half[0]))
+    else:
+        R = rotation(box.axis, theta)
+        d, nh = box_sdf((p - center) @ R, torch.zeros(3, dtype=DT), torch.tensor(box.half, dtype=DT))
+        nh = nh @ R.T
     a = torch.tensor(box.axis, dtype=DT)
     vb = vb + omega * torch.linalg.cross(a.expand_as(p), p - center)
     s = torch.clamp(torch.exp(-box.alpha * d), max=1.0)

@@ -830,3 +830,59 @@ def test_angular_action_gradients_match_forward_mode_and_central_differences():
         assert abs(fd - gom[k].item()) <= 1e-5 * max(1.0, abs(fd)), (k, fd, gom[k].item())
     fd = (loss(ang=env.collider.angle + h) - loss(ang=env.collider.angle - h)) / (2 * h)
     assert abs(fd - gang0.item()) <= 1e-5 * max(1.0, abs(fd)), (fd, gang0.item())
+
+
+def test_sphere_sdf_hand_values():
+    # ball of radius 0.2 about c: points at 3-4-5 and 2-3-6-7 offsets, inside, and at the center
+    c = torch.tensor([0.5, 0.5, 0.5], dtype=DT)
+    cases = [
+        ((0.15, 0.2, 0.0), 0.05, (0.6, 0.8, 0.0)),
+        ((-0.06, 0.09, -0.18), 0.01, (-2 / 7, 3 / 7, -6 / 7)),
+        ((0.0, 0.0, -0.05), -0.15, (0.0, 0.0, -1.0)),
+        ((0.0, 0.0, 0.0), -0.2, (0.0, 0.0, 1.0)),          # the center: the normal is taken as +z
+    ]
+    p = c + torch.tensor([o for o, _, _ in cases], dtype=DT)
+    d, nrm = O.sphere_sdf(p, c, 0.2)
+    np.testing.assert_allclose(d.numpy(), [dd for _, dd, _ in cases], atol=1e-14)
+    np.testing.assert_allclose(nrm.numpy(), [nn for _, _, nn in cases], atol=1e-14)
+
+
+def test_sphere_contact_hand_values():
+    # one node inside a static ball (s = 1) on its +x +y diagonal (normal (0.6, 0.8, 0)), moving in;
+    # and the same ball spinning about z: its surface at the node moves at omega z x (x - c)
+    n = 32
+    r = 0.2
+    ball = O.Box(center=(0.5, 0.5, 0.5), half=(r, r, r), velocity=(0.0, 0.0, 0.0), alpha=32.0, mu_b=0.5,
+                 shape="sphere")
+    env = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=ball)
+    pos = O.node_positions(n)
+    target = torch.tensor([0.5 + 0.09375, 0.5 + 0.125, 0.5], dtype=DT)   # |w| = 0.15625: inside, normal (0.6, 0.8, 0)
+    i = int((pos - target).abs().sum(1).argmin())
+    assert torch.allclose(pos[i], target, atol=1e-12)
+    nrm = np.array([0.6, 0.8, 0.0])
+    tang = np.array([-0.8, 0.6, 0.0])
+    v = torch.zeros(n ** 3, 3, dtype=DT)
+    act = torch.ones(n ** 3, dtype=torch.bool)
+    cases = [(-1.0 * nrm + 0.2 * tang, np.zeros(3)),              # |u_t| = 0.2 <= 0.5: sticks
+             (-1.0 * nrm + 2.0 * tang, 1.5 * tang),               # slides: u_t (1 - 0.5 * 1 / 2)
+             (1.0 * nrm + 2.0 * tang, 1.0 * nrm + 2.0 * tang)]    # separating: unchanged
+    for vin, vout in cases:
+        v[i] = torch.tensor(vin, dtype=DT)
+        out = O.collide(env, v, *O.collider_motion(env, 0.0)[:2], act)
+        np.testing.assert_allclose(out[i].numpy(), vout, atol=1e-14)
+    # spinning at omega about z: the surface velocity at the node is omega (-0.125, 0.09375, 0); a node at
+    # rest relative to the world approaches nothing (u . n = 0) and keeps its velocity
+    om = 4.0
+    vs = om * np.array([-0.125, 0.09375, 0.0])
+    v[i] = 0.0
+    center, vb = O.collider_motion(env, 0.0)[:2]
+    out = O.collide(env, v, center, vb, act, theta=0.7, omega=torch.tensor(om, dtype=DT))
+    np.testing.assert_allclose(out[i].numpy(), vs + (-vs), atol=1e-14)   # u_n = 0: not approaching, unchanged
+    v[i] = torch.tensor(-1.0 * nrm, dtype=DT)
+    out = O.collide(env, v, center, vb, act, theta=0.7, omega=torch.tensor(om, dtype=DT))
+    u = -1.0 * nrm - vs                       # relative velocity: u_n = -1, u_t = -vs (|u_t| = 0.625 > 0.5)
+    ut = u - (u @ nrm) * nrm
+    np.testing.assert_allclose(out[i].numpy(), vs + ut * (1.0 - 0.5 / np.linalg.norm(ut)), atol=1e-14)
+    # the angle moves nothing: the same result at another angle
+    out2 = O.collide(env, v, center, vb, act, theta=-2.1, omega=torch.tensor(om, dtype=DT))
+    assert torch.equal(out, out2)

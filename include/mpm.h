@@ -141,6 +141,16 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
 int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const float half[3], const float vel[3],
                          float alpha, float mu_b);
 
+/* The same contact with a ball of radius `radius` about the centre instead of
+ * a box (Appendix D.3's softened contact takes the collider's signed distance
+ * and normal: d = |x - c| - radius, n = (x - c) / |x - c|, +z at the centre).
+ * The rotation, the prescribed motion and the gradients below apply to it as
+ * to the box: the ball's angle moves nothing, its spin moves its surface.
+ * Errors: those of mpm_set_box_collider, INVALID_ARG for a negative or
+ * non-finite radius. */
+int mpm_set_sphere_collider(mpm_batch* b, int32_t env, const float center[3], float radius, const float vel[3],
+                            float alpha, float mu_b);
+
 /* Lets env's box (env = -1: every env's) rotate about a fixed axis through its
  * centre: the tools and hands of the paper's manipulation tasks turn as well
  * as translate (Section 5 task descriptions; contact of Appendix D.3). The box
@@ -412,7 +422,7 @@ typedef struct {
 typedef struct {
   mpm_env_desc env;        /* n <= n_cap, n_particles <= n_cap_particles, material */
   double params[8];        /* as mpm_set_material */
-  int32_t has_collider;    /* 1: the box below (as mpm_set_box_collider) */
+  int32_t has_collider;    /* 1: the box below (as mpm_set_box_collider); 2: a ball of radius c_half[0] */
   int32_t substeps;        /* S >= 1 */
   float c_center[3], c_half[3], c_vel[3], c_alpha, c_mu;
   int32_t backward;        /* 1: run the backward pass after the forward */

@@ -111,14 +111,25 @@ class Batch:
         self._chk(self.lib.mpm_set_box_collider(self.h, env, f3(center), f3(half), f3(velocity),
                                                 float(alpha), float(mu_b)), "mpm_set_box_collider")
 
+    def set_sphere_collider(self, env: int, center, radius: float, velocity, alpha: float, mu_b: float) -> None:
+        self.record_token += 1   # the library drops its recorded tape
+        f3 = lambda a: (ctypes.c_float * 3)(*[float(x) for x in a])
+        self._chk(self.lib.mpm_set_sphere_collider(self.h, env, f3(center), float(radius), f3(velocity),
+                                                   float(alpha), float(mu_b)), "mpm_set_sphere_collider")
+
     def set_box_rotation(self, env: int, axis, angle: float, omega: float) -> None:
         self.record_token += 1   # the library drops its recorded tape
         f3 = (ctypes.c_float * 3)(*[float(x) for x in axis])
         self._chk(self.lib.mpm_set_box_rotation(self.h, env, f3, float(angle), float(omega)), "mpm_set_box_rotation")
 
     def set_collider(self, env: int, c, center=None, angle=None) -> None:
-        """The box collider c (scenes.BoxCollider) of env, optionally with another start center / angle."""
-        self.set_box_collider(env, c.center if center is None else center, c.half, c.velocity, c.alpha, c.mu_b)
+        """The collider c (scenes.BoxCollider: a box, or a ball) of env, optionally with another start center /
+        angle."""
+        cen = c.center if center is None else center
+        if getattr(c, "shape", "box") == "sphere":
+            self.set_sphere_collider(env, cen, c.half[0], c.velocity, c.alpha, c.mu_b)
+        else:
+            self.set_box_collider(env, cen, c.half, c.velocity, c.alpha, c.mu_b)
         if c.rotates or angle is not None:
             self.set_box_rotation(env, c.axis, c.angle if angle is None else angle, c.omega)
 

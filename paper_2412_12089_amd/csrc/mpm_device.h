@@ -30,7 +30,8 @@ constexpr float kYieldScale = 2.0f;  // numerator of the printed yield offset kY
 // written by the host; the derived block by the parameter-preparation kernel.
 struct EnvDev {
   int32_t n, T, material, wall;          // nodes per axis, 4^3 tiles per axis
-  int32_t has_collider, nsub;         // nsub: substeps this env takes in the current forward call
+  int32_t has_collider, nsub;         // collider: 0 none, kColliderBox, kColliderSphere; nsub: substeps this env
+                                      // takes in the current forward call
   int64_t p_off, p_cnt;                  // particle range in the batch arrays
   int64_t tile_off;                      // first tile of this env in the grid buffers
   float dt, fn, dx, gx, gy, gz;
@@ -46,6 +47,9 @@ struct EnvDev {
   float c_axis[3];                       // box rotation: unit axis (world), angle at t = 0, constant angular
   float c_angle, c_omega, c_pad;         // speed (the box is axis-aligned in its own frame)
 };
+
+constexpr int32_t kColliderBox = 1;      // box of half extents ch, axis-aligned in its own frame
+constexpr int32_t kColliderSphere = 2;   // ball of radius ch[0]
 
 // a row of the prescribed collider motion table: center (3), velocity (3),
 // angle about the box's axis, angular speed

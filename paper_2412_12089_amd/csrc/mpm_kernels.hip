@@ -494,6 +494,30 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], const float R[3][
   Contact ct;
   ct.pos = 0;
   for (int a = 0; a < 3; ++a) ct.w[a] = p[a] - c[a];
+  if (e.has_collider == kColliderSphere) {
+    // a ball of radius ch[0]: d = |w| - r, n = w / |w| (+z at the center). In the turned frame nb = r / |r| with
+    // every axis "outside" and L = |r|, so the adjoint's terms for a normal that turns with r (the box's edges
+    // and corners) give the ball's dn/dc = -(I - n n^T) / |w| and cancel its rigid turn with the angle.
+    for (int a = 0; a < 3; ++a) ct.rb[a] = R[0][a] * ct.w[0] + R[1][a] * ct.w[1] + R[2][a] * ct.w[2];
+    const float L = sqrtf(ct.w[0] * ct.w[0] + ct.w[1] * ct.w[1] + ct.w[2] * ct.w[2]);
+    ct.d = L - e.ch[0];
+    ct.L = L;
+    if (L > 0.f) {
+      const float il = 1.f / L;
+      for (int a = 0; a < 3; ++a) {
+        ct.nb[a] = ct.rb[a] * il;
+        ct.n[a] = ct.w[a] * il;
+      }
+      ct.pos = 7;
+    } else {   // the normal is taken fixed (+z) at the center: no derivative through it
+      for (int a = 0; a < 3; ++a) {
+        ct.n[a] = a == 2 ? 1.f : 0.f;
+        ct.nb[a] = R[2][a];
+      }
+    }
+    ct.s = fminf(expf(-e.c_alpha * ct.d), 1.f);
+    return ct;
+  }
   for (int a = 0; a < 3; ++a) {
     rel[a] = R[0][a] * ct.w[0] + R[1][a] * ct.w[1] + R[2][a] * ct.w[2];
     ct.rb[a] = rel[a];

@@ -926,17 +926,19 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
   return upload_envs(b);
 }
 
-int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const float h[3], const float v[3], float alpha,
-                         float mu_b) {
+static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[3], const float h[3], const float v[3],
+                 float alpha, float mu_b) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
   if (alpha > 0.f && (!c || !h || !v)) return fail(b, MPM_INVALID_ARG, "null collider array");
   if (alpha > 0.f && !(mu_b >= 0.f)) return fail(b, MPM_INVALID_ARG, "mu_b must be >= 0");
+  if (alpha > 0.f && shape == kColliderSphere && !(h[0] >= 0.f && std::isfinite(h[0])))
+    return fail(b, MPM_INVALID_ARG, "the sphere radius must be finite and >= 0");
   const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
   for (int e = e0; e < e1; ++e) {
     EnvDev& d = b->envs_h[e];
-    d.has_collider = alpha > 0.f ? 1 : 0;
+    d.has_collider = alpha > 0.f ? shape : 0;
     if (d.has_collider) {
       for (int a = 0; a < 3; ++a) { d.cc[a] = c[a]; d.ch[a] = h[a]; d.cv[a] = v[a]; }
       d.c_alpha = alpha;
@@ -949,6 +951,17 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const floa
   }
   b->recorded = false;
   return upload_envs(b);
+}
+
+int mpm_set_box_collider(mpm_batch* b, int32_t env, const float c[3], const float h[3], const float v[3], float alpha,
+                         float mu_b) {
+  return set_collider(b, env, kColliderBox, c, h, v, alpha, mu_b);
+}
+
+int mpm_set_sphere_collider(mpm_batch* b, int32_t env, const float c[3], float radius, const float v[3], float alpha,
+                            float mu_b) {
+  const float h[3] = {radius, radius, radius};
+  return set_collider(b, env, kColliderSphere, c, h, v, alpha, mu_b);
 }
 
 int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float angle, float omega) {

@@ -47,8 +47,8 @@ WALL = 3                    # sticky boundary thickness in nodes
 
 @dataclass
 class BoxCollider:
-    """A kinematic box moving at constant velocity and spinning at a constant
-    rate about a fixed axis through its center (one-way coupling)."""
+    """A kinematic box (or ball) moving at constant velocity and spinning at a
+    constant rate about a fixed axis through its center (one-way coupling)."""
     center: tuple
     half: tuple
     velocity: tuple
@@ -57,10 +57,18 @@ class BoxCollider:
     axis: tuple = (0.0, 0.0, 1.0)   # rotation axis (unit)
     angle: float = 0.0              # rotation about the axis at t = 0 (rad)
     omega: float = 0.0              # angular speed (rad/s)
+    shape: str = "box"              # "box", or "sphere": a ball of radius half[0]
 
     @property
     def rotates(self) -> bool:
         return self.angle != 0.0 or self.omega != 0.0
+
+
+def sphere_collider(center, radius: float, velocity, alpha: float, mu_b: float, **kw) -> BoxCollider:
+    """A kinematic ball of the given radius (the collider with shape "sphere")."""
+    r = float(radius)
+    return BoxCollider(center=tuple(center), half=(r, r, r), velocity=tuple(velocity), alpha=alpha, mu_b=mu_b,
+                       shape="sphere", **kw)
 
 
 @dataclass

@@ -288,6 +288,79 @@ def test_spin_actions_forward_and_gradient(mode):
     assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3 and ea < 1e-3
 
 
+SPIN_BALL = scenes.sphere_collider(center=(0.62, 0.5, 0.48), radius=0.1, velocity=(-0.4, 0.0, 0.0), alpha=64.0,
+                                   mu_b=0.3, axis=(0.0, 0.6, 0.8), angle=0.4, omega=6.0)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused", "batched-pull"])
+def test_sphere_collider_actions_forward_and_gradient(mode):
+    # a spinning ball driven by per-substep velocities and angular speeds (its normal turns with every node's
+    # position relative to the center); gradients w.r.t. both actions and the starting center against the
+    # oracle, and none w.r.t. the starting angle (a ball's angle moves nothing)
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd.batch import Batch
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=170, collider=SPIN_BALL, v_scale=0.2)
+    other = make_env(scenes.NEOHOOKEAN, N=1000, seed=171, collider=BOXES["face"])   # a box in the same batch
+    S, K = 10, 4
+    rng = np.random.default_rng(172)
+    vel = (np.array(SPIN_BALL.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+    om = (SPIN_BALL.omega + 4.0 * rng.standard_normal(S)).astype(np.float32)
+    announce(f"spinning ball driven by {S} velocity and angular-speed actions, {mode}")
+    envs = [spec, other]
+    cots = random_cotangents(envs, seed=173)
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode.split("-")[0])
+    try:
+        if mode == "batched-fused":
+            b.set_option(C.OPT_FUSE, 1)
+            b.set_option(C.OPT_FUSE_ADJ, 1)
+        if mode == "batched-pull":
+            set_pull_schedule(b)
+        b.set_particles_from_specs()
+        b.set_collider_motion(0, vel, om)
+        b.forward(S, record=True)
+        st = tuple(to_np(t) for t in b.get_particles(env=0))
+        cat = lambda i: torch.from_numpy(np.concatenate([c[i] for c in cots], axis=0))
+        dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+        N0 = spec.n_particles
+        gr = tuple(to_np(t)[:N0] for t in (dx, dv, dC, dF))
+        dvel, dc0, dom, dang = b.collider_grad(0, S, spin=True)
+        assert b.sync(raise_on_error=False) == 0
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    assert env.collider.shape == "sphere"
+    velt, omt = torch.from_numpy(vel).double(), torch.from_numpy(om).double()
+    (x, v, Cm, F), _ = O.rollout(env, prm, st0, S, vel=velt, omega=omt)
+    c = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).double() for a in cots[0])
+    g, gp, gvel, gc0, gom, gang = O.rollout_vjp(env, prm, st0, S, c, vel=velt, omega=omt)
+    check_state(st, tuple(t.numpy() for t in (x, v, Cm, F)), "ball actions", spec.x, S)
+    check_grads(gr, tuple(t.numpy() for t in g), "ball actions")
+    ev, ec, eo = relerr(dvel, gvel.numpy()), relerr(dc0, gc0.numpy()), relerr(dom, gom.numpy())
+    announce(f"ball actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {dang:.2e} "
+             f"(oracle {float(gang):.1e}), |dL/domega| {np.abs(gom.numpy()).max():.3e}")
+    assert np.abs(gom.numpy()).max() > 0 and float(gang) == 0.0
+    assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3
+    assert abs(dang) < 1e-3 * float(np.linalg.norm(gc0.numpy()))
+
+
+def test_sphere_collider_has_sliding_curved_contacts():
+    # the oracle's view: active nodes inside the ball's contact band that slide, where the normal differs
+    # from node to node (so the normal's dependence on the center is exercised)
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=170, collider=SPIN_BALL, v_scale=0.2)
+    env, prm, (x, v, C, F) = O.env_from_spec(spec)
+    gm, gP, _ = O.p2g(env, prm, x, v, C, F)
+    pos = gm > 0
+    center, vb = O.collider_motion(env, 0.0)[:2]
+    d, nh = O.sphere_sdf(O.node_positions(env.n), center, env.collider.half[0])
+    vel = torch.where(pos[:, None], gP / torch.where(pos, gm, torch.ones_like(gm))[:, None], torch.zeros_like(gP))
+    u = vel - vb
+    un = (u * nh).sum(1)
+    ut = (u - un[:, None] * nh).norm(dim=1)
+    slide = pos & (un < 0) & (ut > -env.collider.mu_b * un) & (d < 4.0 / env.collider.alpha)
+    assert int(slide.sum()) > 10
+    assert float(nh[slide].std(0).norm()) > 0.1
+
+
 def test_rollout_function_with_spins_matches_oracle():
     # the autograd Function carries the angular-speed actions' gradient
     from paper_2412_12089_amd.batch import Batch, rollout

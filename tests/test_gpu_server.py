@@ -37,6 +37,10 @@ def requests(n=8, seed=11):
         if i == 3:   # a box moving into the particles
             collider = scenes.BoxCollider(center=(float(lo[0]) + side + 0.03, 0.5, 0.5), half=(0.02, 0.3, 0.3),
                                           velocity=(-0.6, 0.0, 0.0), alpha=2.0 * grid, mu_b=0.5)
+        if i == 6:   # a ball moving into the particles
+            collider = scenes.sphere_collider(center=(float(lo[0]) + side + 0.04, float(lo[1]) + 0.09,
+                                                      float(lo[2]) + 0.09), radius=0.06, velocity=(-0.6, 0.0, 0.0),
+                                              alpha=2.0 * grid, mu_b=0.5)
         env = scenes.EnvSpec(n=grid, dt=5e-5, rho=1e3, Vp=side ** 3 / N, x=x, v=v, C=C, F=F, collider=collider, **mat)
         w = scenes._f32(rng.standard_normal((N, 3)))
         S = 80 if i == 0 else int(rng.integers(12, 36))
@@ -83,11 +87,11 @@ def test_each_request_is_the_same_alone_and_in_the_mix():
             np.testing.assert_allclose(m["dparams"][[0, 1, 2, 4, 5, 6]], a["dparams"][[0, 1, 2, 4, 5, 6]],
                                        rtol=1e-4, atol=1e-30)
             assert m["dparams"][3] == 0.0 and a["dparams"][3] == 0.0
-    # against the oracle: the 80-substep backward (8 chunks), the moving box, a forward-only request
-    for r in (reqs[0], reqs[3], reqs[1]):
+    # against the oracle: the 80-substep backward (8 chunks), the moving box, the moving ball, a forward-only request
+    for r in (reqs[0], reqs[3], reqs[6], reqs[1]):
         cot = loss_cot(r) if r.backward else None
         o = oracle_rollout(r.env, r.substeps, cot)
-        tag = f"served request {r.rid} (S={r.substeps}{', moving box' if r.env.collider else ''})"
+        tag = f"served request {r.rid} (S={r.substeps}{', moving ' + r.env.collider.shape if r.env.collider else ''})"
         assert_state(mix[r.rid]["state"], o["state"], r.env.x, tag, announce, S=r.substeps)
         if cot is not None:
             assert_grads(mix[r.rid]["grads"], o["grads"], tag, announce)

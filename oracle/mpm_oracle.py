@@ -71,6 +71,8 @@ class Box:
     angle: float = 0.0                     # rotation about the axis at t = 0 (rad)
     omega: float = 0.0                     # constant angular speed about the axis (rad/s)
     shape: str = "box"                     # "box", or "sphere": a ball of radius half[0] about the center
+    rounding: float = 0.0                  # a box's distance less this radius: a rounded box (half (h, 0, 0):
+                                           # a capsule along the box's x axis)
 
 
 @dataclass
@@ -91,7 +93,8 @@ def env_from_spec(spec) -> Tuple[Env, torch.Tensor, Tuple[torch.Tensor, ...]]:
         c = spec.collider
         box = Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b),
                   tuple(getattr(c, "axis", (0.0, 0.0, 1.0))), float(getattr(c, "angle", 0.0)),
-                  float(getattr(c, "omega", 0.0)), str(getattr(c, "shape", "box")))
+                  float(getattr(c, "omega", 0.0)), str(getattr(c, "shape", "box")),
+                  float(getattr(c, "rounding", 0.0)))
     env = Env(n=spec.n, dt=spec.dt, material=spec.material, gravity=tuple(spec.gravity),
               wall=spec.wall, collider=box)
     prm = torch.tensor([spec.E, spec.nu, spec.rho, spec.Vp, spec.sigma_y, spec.K, spec.gamma], dtype=DT)
@@ -394,7 +397,8 @@ def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     its position R^T (x - c) in that frame, rotated back to the world, and the
     box surface moves at vb + omega axis x (x - c). A sphere collider's
     distance and normal do not depend on its angle; its spin still moves its
-    surface."""
+    surface. A rounded box's distance is the box's less the rounding radius,
+    its normal the box's."""
     box = env.collider
     n = env.n
     p = node_positions(n)
@@ -403,6 +407,7 @@ def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     else:
         R = rotation(box.axis, theta)
         d, nh = box_sdf((p - center) @ R, torch.zeros(3, dtype=DT), torch.tensor(box.half, dtype=DT))
+        d = d - box.rounding
         nh = nh @ R.T
     a = torch.tensor(box.axis, dtype=DT)
     vb = vb + omega * torch.linalg.cross(a.expand_as(p), p - center)

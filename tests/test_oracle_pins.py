@@ -886,3 +886,38 @@ def test_sphere_contact_hand_values():
     # the angle moves nothing: the same result at another angle
     out2 = O.collide(env, v, center, vb, act, theta=-2.1, omega=torch.tensor(om, dtype=DT))
     assert torch.equal(out, out2)
+
+
+def test_capsule_contact_hand_values():
+    # a capsule (box of half extents (0.15, 0, 0) rounded by 0.1) turned by 90 degrees about z, so its segment
+    # runs along world y from c - 0.15 y to c + 0.15 y. Nodes (offsets from c, multiples of 1/32) beside the
+    # segment and past its end: distance to the segment less 0.1, normal radial from the nearest segment point
+    n = 32
+    cap = O.Box(center=(0.5, 0.5, 0.5), half=(0.15, 0.0, 0.0), velocity=(0.0, 0.0, 0.0), alpha=32.0, mu_b=0.0,
+                axis=(0.0, 0.0, 1.0), angle=math.pi / 2, rounding=0.1)
+    env = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=cap)
+    pos = O.node_positions(n)
+    act = torch.ones(n ** 3, dtype=torch.bool)
+    q_end = np.array([0.0625, 0.1875 - 0.15, 0.0])          # from the +y end point to the node
+    cases = [
+        ((0.0625, 0.09375, 0.0), 0.0625 - 0.1, (1.0, 0.0, 0.0)),             # beside the segment, inside
+        ((0.0, -0.03125, -0.09375), 0.09375 - 0.1, (0.0, 0.0, -1.0)),        # beside the segment, inside
+        ((0.125, 0.0, 0.0), 0.125 - 0.1, (1.0, 0.0, 0.0)),                   # beside the segment, outside
+        ((0.0625, 0.1875, 0.0), float(np.linalg.norm(q_end)) - 0.1,           # past the +y end, inside
+         tuple(q_end / np.linalg.norm(q_end))),
+        ((0.0, -0.25, 0.0), 0.1 - 0.1, (0.0, -1.0, 0.0)),                    # on the -y cap's surface
+    ]
+    center, vb, th, om = O.collider_motion(env, 0.0)
+    for off, dist, nrm in cases:
+        i = int((pos - (center + torch.tensor(off, dtype=DT))).abs().sum(1).argmin())
+        assert torch.allclose(pos[i], center + torch.tensor(off, dtype=DT), atol=1e-12)
+        # moving into the capsule with no friction: the projected velocity keeps only the tangential part,
+        # blended by s = min(exp(-alpha d), 1)
+        nv = np.array(nrm)
+        tang = np.cross(nv, [0.0, 0.0, 1.0]) if abs(nv[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+        tang = tang / np.linalg.norm(tang)
+        v = torch.zeros(n ** 3, 3, dtype=DT)
+        v[i] = torch.tensor(-nv + 0.3 * tang, dtype=DT)
+        out = O.collide(env, v, center, vb, act, th, om)[i].numpy()
+        s = min(math.exp(-32.0 * dist), 1.0)
+        np.testing.assert_allclose(out, s * 0.3 * tang + (1 - s) * (-nv + 0.3 * tang), atol=1e-13)

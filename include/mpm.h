@@ -151,6 +151,15 @@ int mpm_set_box_collider(mpm_batch* b, int32_t env, const float center[3], const
 int mpm_set_sphere_collider(mpm_batch* b, int32_t env, const float center[3], float radius, const float vel[3],
                             float alpha, float mu_b);
 
+/* The box of mpm_set_box_collider rounded by `radius`: its signed distance
+ * less the radius, its normal unchanged (the contact of Appendix D.3 needs
+ * only the two). half = (h, 0, 0) gives a capsule, a segment of half length h
+ * along the box's own x axis inflated by the radius (a finger or a rod); the
+ * rotation, motion and gradients below apply as to the box. Errors: those of
+ * mpm_set_box_collider, INVALID_ARG for a negative or non-finite radius. */
+int mpm_set_rounded_box_collider(mpm_batch* b, int32_t env, const float center[3], const float half[3], float radius,
+                                 const float vel[3], float alpha, float mu_b);
+
 /* Lets env's box (env = -1: every env's) rotate about a fixed axis through its
  * centre: the tools and hands of the paper's manipulation tasks turn as well
  * as translate (Section 5 task descriptions; contact of Appendix D.3). The box
@@ -422,11 +431,12 @@ typedef struct {
 typedef struct {
   mpm_env_desc env;        /* n <= n_cap, n_particles <= n_cap_particles, material */
   double params[8];        /* as mpm_set_material */
-  int32_t has_collider;    /* 1: the box below (as mpm_set_box_collider); 2: a ball of radius c_half[0] */
+  int32_t has_collider;    /* 1: the box below (as mpm_set_box_collider); 2: a ball of radius c_half[0];
+                              3: the box rounded by c_round (as mpm_set_rounded_box_collider) */
   int32_t substeps;        /* S >= 1 */
   float c_center[3], c_half[3], c_vel[3], c_alpha, c_mu;
   int32_t backward;        /* 1: run the backward pass after the forward */
-  int32_t reserved;
+  float c_round;           /* rounding radius of a has_collider = 3 box */
   double arrival;          /* seconds on the server clock (mpm_server_now); < 0 = at submission */
   /* DEVICE arrays owned by the caller, AoS as for mpm_set_particles; they must
    * stay valid and unchanged until the request reaches a final state. */

@@ -40,7 +40,7 @@ EXPORTED = (
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
     "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp", "mpm_set_box_rotation",
-    "mpm_set_sphere_collider",
+    "mpm_set_sphere_collider", "mpm_set_rounded_box_collider",
     "mpm_fem_create", "mpm_fem_destroy", "mpm_fem_set_rest", "mpm_fem_set_params", "mpm_fem_set_state",
     "mpm_fem_get_state", "mpm_fem_forward", "mpm_fem_backward", "mpm_fem_sync", "mpm_fem_env_errors",
     "mpm_fem_last_error", "mpm_fem_memory_bytes",
@@ -87,7 +87,7 @@ class mpm_request(ctypes.Structure):
     _fields_ = [("env", mpm_env_desc), ("params", ctypes.c_double * 8), ("has_collider", ctypes.c_int32),
                 ("substeps", ctypes.c_int32), ("c_center", ctypes.c_float * 3), ("c_half", ctypes.c_float * 3),
                 ("c_vel", ctypes.c_float * 3), ("c_alpha", ctypes.c_float), ("c_mu", ctypes.c_float),
-                ("backward", ctypes.c_int32), ("reserved", ctypes.c_int32), ("arrival", ctypes.c_double)] + \
+                ("backward", ctypes.c_int32), ("c_round", ctypes.c_float), ("arrival", ctypes.c_double)] + \
                [(k, ctypes.c_void_p) for k in ("x", "v", "C", "F", "gx", "gv", "gC", "gF", "out_x", "out_v", "out_C",
                                                 "out_F", "dx0", "dv0", "dC0", "dF0")]
 
@@ -156,6 +156,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_set_material": (I32, [VP, I32, I32, D8]),
         "mpm_set_box_collider": (I32, [VP, I32, F3, F3, F3, ctypes.c_float, ctypes.c_float]),
         "mpm_set_sphere_collider": (I32, [VP, I32, F3, ctypes.c_float, F3, ctypes.c_float, ctypes.c_float]),
+        "mpm_set_rounded_box_collider": (I32, [VP, I32, F3, F3, ctypes.c_float, F3, ctypes.c_float, ctypes.c_float]),
         "mpm_forward": (I32, [VP, I32, I32]),
         "mpm_backward": (I32, [VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
         "mpm_autotune": (I32, [VP, I32]),

@@ -117,6 +117,14 @@ class Batch:
         self._chk(self.lib.mpm_set_sphere_collider(self.h, env, f3(center), float(radius), f3(velocity),
                                                    float(alpha), float(mu_b)), "mpm_set_sphere_collider")
 
+    def set_rounded_box_collider(self, env: int, center, half, radius: float, velocity, alpha: float,
+                                 mu_b: float) -> None:
+        self.record_token += 1   # the library drops its recorded tape
+        f3 = lambda a: (ctypes.c_float * 3)(*[float(x) for x in a])
+        self._chk(self.lib.mpm_set_rounded_box_collider(self.h, env, f3(center), f3(half), float(radius),
+                                                        f3(velocity), float(alpha), float(mu_b)),
+                  "mpm_set_rounded_box_collider")
+
     def set_box_rotation(self, env: int, axis, angle: float, omega: float) -> None:
         self.record_token += 1   # the library drops its recorded tape
         f3 = (ctypes.c_float * 3)(*[float(x) for x in axis])
@@ -128,6 +136,8 @@ class Batch:
         cen = c.center if center is None else center
         if getattr(c, "shape", "box") == "sphere":
             self.set_sphere_collider(env, cen, c.half[0], c.velocity, c.alpha, c.mu_b)
+        elif getattr(c, "rounding", 0.0) > 0.0:
+            self.set_rounded_box_collider(env, cen, c.half, c.rounding, c.velocity, c.alpha, c.mu_b)
         else:
             self.set_box_collider(env, cen, c.half, c.velocity, c.alpha, c.mu_b)
         if c.rotates or angle is not None:

@@ -45,7 +45,8 @@ struct EnvDev {
   int32_t motion_off, motion_len;        // prescribed collider motion: rows [motion_off, + motion_len) of the
                                          // motion table, one per substep (len 0: constant velocity cv)
   float c_axis[3];                       // box rotation: unit axis (world), angle at t = 0, constant angular
-  float c_angle, c_omega, c_pad;         // speed (the box is axis-aligned in its own frame)
+  float c_angle, c_omega, c_round;       // speed (the box is axis-aligned in its own frame); the box's rounding
+                                         // radius (its distance less c_round)
 };
 
 constexpr int32_t kColliderBox = 1;      // box of half extents ch, axis-aligned in its own frame

@@ -527,7 +527,7 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], const float R[3][
   }
   const float out_len = sqrtf(qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2]);
   const float inside = fmaxf(q[0], fmaxf(q[1], q[2]));
-  ct.d = out_len + fminf(inside, 0.f);
+  ct.d = out_len + fminf(inside, 0.f) - e.c_round;   // a rounded box (a capsule with half (h, 0, 0)): same normal
   ct.L = out_len;
   if (out_len > 0.f) {
     for (int a = 0; a < 3; ++a) ct.nb[a] = (rel[a] >= 0.f ? 1.f : -1.f) * qp[a] / out_len;

@@ -927,7 +927,7 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
 }
 
 static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[3], const float h[3], const float v[3],
-                 float alpha, float mu_b) {
+                        float alpha, float mu_b, float rounding = 0.f) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
@@ -935,6 +935,8 @@ static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[
   if (alpha > 0.f && !(mu_b >= 0.f)) return fail(b, MPM_INVALID_ARG, "mu_b must be >= 0");
   if (alpha > 0.f && shape == kColliderSphere && !(h[0] >= 0.f && std::isfinite(h[0])))
     return fail(b, MPM_INVALID_ARG, "the sphere radius must be finite and >= 0");
+  if (!(rounding >= 0.f) || !std::isfinite(rounding))
+    return fail(b, MPM_INVALID_ARG, "the rounding radius must be finite and >= 0");
   const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
   for (int e = e0; e < e1; ++e) {
     EnvDev& d = b->envs_h[e];
@@ -944,6 +946,7 @@ static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[
       d.c_alpha = alpha;
       d.c_mu = mu_b;
     }
+    d.c_round = d.has_collider == kColliderBox ? rounding : 0.f;
     d.c_axis[0] = d.c_axis[1] = 0.f;   // no rotation until mpm_set_box_rotation
     d.c_axis[2] = 1.f;
     d.c_angle = d.c_omega = 0.f;
@@ -962,6 +965,11 @@ int mpm_set_sphere_collider(mpm_batch* b, int32_t env, const float c[3], float r
                             float mu_b) {
   const float h[3] = {radius, radius, radius};
   return set_collider(b, env, kColliderSphere, c, h, v, alpha, mu_b);
+}
+
+int mpm_set_rounded_box_collider(mpm_batch* b, int32_t env, const float c[3], const float h[3], float radius,
+                                 const float v[3], float alpha, float mu_b) {
+  return set_collider(b, env, kColliderBox, c, h, v, alpha, mu_b, radius);
 }
 
 int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float angle, float omega) {

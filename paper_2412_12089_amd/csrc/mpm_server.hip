@@ -192,6 +192,8 @@ int load_slot(mpm_server* s, Req& q) {
   SCHK(s, mpm_set_material(b, q.slot, r.env.material, r.params));
   if (r.has_collider == 2)
     SCHK(s, mpm_set_sphere_collider(b, q.slot, r.c_center, r.c_half[0], r.c_vel, r.c_alpha, r.c_mu));
+  else if (r.has_collider == 3)
+    SCHK(s, mpm_set_rounded_box_collider(b, q.slot, r.c_center, r.c_half, r.c_round, r.c_vel, r.c_alpha, r.c_mu));
   else if (r.has_collider)
     SCHK(s, mpm_set_box_collider(b, q.slot, r.c_center, r.c_half, r.c_vel, r.c_alpha, r.c_mu));
   SCHK(s, mpm_set_particles(b, q.slot, r.x, r.v, r.C, r.F, r.env.n_particles));

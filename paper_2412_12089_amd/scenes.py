@@ -58,6 +58,7 @@ class BoxCollider:
     angle: float = 0.0              # rotation about the axis at t = 0 (rad)
     omega: float = 0.0              # angular speed (rad/s)
     shape: str = "box"              # "box", or "sphere": a ball of radius half[0]
+    rounding: float = 0.0           # a box's distance less this radius (half (h, 0, 0): a capsule)
 
     @property
     def rotates(self) -> bool:
@@ -69,6 +70,14 @@ def sphere_collider(center, radius: float, velocity, alpha: float, mu_b: float, 
     r = float(radius)
     return BoxCollider(center=tuple(center), half=(r, r, r), velocity=tuple(velocity), alpha=alpha, mu_b=mu_b,
                        shape="sphere", **kw)
+
+
+def capsule_collider(center, half_length: float, radius: float, velocity, alpha: float, mu_b: float,
+                     **kw) -> BoxCollider:
+    """A kinematic capsule: a segment of the given half length along the collider's own x axis, inflated by
+    `radius` (the box of half extents (half_length, 0, 0) rounded by the radius)."""
+    return BoxCollider(center=tuple(center), half=(float(half_length), 0.0, 0.0), velocity=tuple(velocity),
+                       alpha=alpha, mu_b=mu_b, rounding=float(radius), **kw)
 
 
 @dataclass

@@ -95,7 +95,9 @@ class Server:
         r.arrival = -1.0 if arrival is None else float(arrival)
         if e.collider is not None:
             c = e.collider
-            r.has_collider = 2 if getattr(c, "shape", "box") == "sphere" else 1
+            r.has_collider = 2 if getattr(c, "shape", "box") == "sphere" else (
+                3 if getattr(c, "rounding", 0.0) > 0.0 else 1)
+            r.c_round = float(getattr(c, "rounding", 0.0))
             r.c_center[:], r.c_half[:], r.c_vel[:] = list(c.center), list(c.half), list(c.velocity)
             r.c_alpha, r.c_mu = float(c.alpha), float(c.mu_b)
         keep, outs = [], None

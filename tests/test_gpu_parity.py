@@ -290,22 +290,30 @@ def test_spin_actions_forward_and_gradient(mode):
 
 SPIN_BALL = scenes.sphere_collider(center=(0.62, 0.5, 0.48), radius=0.1, velocity=(-0.4, 0.0, 0.0), alpha=64.0,
                                    mu_b=0.3, axis=(0.0, 0.6, 0.8), angle=0.4, omega=6.0)
+# a finger: a capsule along its own x axis, turned about a tilted axis and spinning
+SPIN_CAPSULE = scenes.capsule_collider(center=(0.6, 0.47, 0.47), half_length=0.1, radius=0.04,
+                                       velocity=(-0.4, 0.0, 0.0), alpha=64.0, mu_b=0.3, axis=(0.6, 0.0, 0.8),
+                                       angle=1.2, omega=5.0)
+ROUNDED = {"ball": SPIN_BALL, "capsule": SPIN_CAPSULE}
 
 
+@pytest.mark.parametrize("geom", ["ball", "capsule"])
 @pytest.mark.parametrize("mode", ["plain", "batched", "batched-fused", "batched-pull"])
-def test_sphere_collider_actions_forward_and_gradient(mode):
-    # a spinning ball driven by per-substep velocities and angular speeds (its normal turns with every node's
-    # position relative to the center); gradients w.r.t. both actions and the starting center against the
-    # oracle, and none w.r.t. the starting angle (a ball's angle moves nothing)
+def test_rounded_collider_actions_forward_and_gradient(mode, geom):
+    # a spinning ball or capsule driven by per-substep velocities and angular speeds (their normals turn with
+    # the nodes' positions relative to the center or the segment); gradients w.r.t. both actions, the
+    # starting center and the starting angle against the oracle (none for the ball's angle, which moves
+    # nothing)
     from paper_2412_12089_amd import _capi as C
     from paper_2412_12089_amd.batch import Batch
-    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=170, collider=SPIN_BALL, v_scale=0.2)
+    col = ROUNDED[geom]
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=170, collider=col, v_scale=0.2)
     other = make_env(scenes.NEOHOOKEAN, N=1000, seed=171, collider=BOXES["face"])   # a box in the same batch
     S, K = 10, 4
     rng = np.random.default_rng(172)
-    vel = (np.array(SPIN_BALL.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
-    om = (SPIN_BALL.omega + 4.0 * rng.standard_normal(S)).astype(np.float32)
-    announce(f"spinning ball driven by {S} velocity and angular-speed actions, {mode}")
+    vel = (np.array(col.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+    om = (col.omega + 4.0 * rng.standard_normal(S)).astype(np.float32)
+    announce(f"spinning {geom} driven by {S} velocity and angular-speed actions, {mode}")
     envs = [spec, other]
     cots = random_cotangents(envs, seed=173)
     b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode.split("-")[0])
@@ -328,19 +336,22 @@ def test_sphere_collider_actions_forward_and_gradient(mode):
     finally:
         b.close()
     env, prm, st0 = O.env_from_spec(spec)
-    assert env.collider.shape == "sphere"
+    assert env.collider.shape == ("sphere" if geom == "ball" else "box") and (geom == "ball") == (env.collider.rounding == 0)
     velt, omt = torch.from_numpy(vel).double(), torch.from_numpy(om).double()
     (x, v, Cm, F), _ = O.rollout(env, prm, st0, S, vel=velt, omega=omt)
     c = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).double() for a in cots[0])
     g, gp, gvel, gc0, gom, gang = O.rollout_vjp(env, prm, st0, S, c, vel=velt, omega=omt)
-    check_state(st, tuple(t.numpy() for t in (x, v, Cm, F)), "ball actions", spec.x, S)
-    check_grads(gr, tuple(t.numpy() for t in g), "ball actions")
+    check_state(st, tuple(t.numpy() for t in (x, v, Cm, F)), f"{geom} actions", spec.x, S)
+    check_grads(gr, tuple(t.numpy() for t in g), f"{geom} actions")
     ev, ec, eo = relerr(dvel, gvel.numpy()), relerr(dc0, gc0.numpy()), relerr(dom, gom.numpy())
-    announce(f"ball actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {dang:.2e} "
-             f"(oracle {float(gang):.1e}), |dL/domega| {np.abs(gom.numpy()).max():.3e}")
-    assert np.abs(gom.numpy()).max() > 0 and float(gang) == 0.0
+    announce(f"{geom} actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {dang:.2e} "
+             f"(oracle {float(gang):.2e}), |dL/domega| {np.abs(gom.numpy()).max():.3e}")
+    assert np.abs(gom.numpy()).max() > 0
     assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3
-    assert abs(dang) < 1e-3 * float(np.linalg.norm(gc0.numpy()))
+    if geom == "ball":
+        assert float(gang) == 0.0 and abs(dang) < 1e-3 * float(np.linalg.norm(gc0.numpy()))
+    else:
+        assert abs(float(gang)) > 0 and abs(dang - float(gang)) < 1e-3 * abs(float(gang))
 
 
 def test_sphere_collider_has_sliding_curved_contacts():

@@ -20,8 +20,8 @@ its angular velocity; the second derivatives of T come from automatic
 differentiation.
 
 Readings (each listed in the design notes): every joint is a revolute joint
-about a body-fixed axis through the joint origin, on a fixed base (the robot
-hands' case); joint damping is viscous, -damp qd; contact is the ground
+about a body-fixed axis through the joint origin, or a prismatic joint
+sliding along one, on a fixed base (the robot hands' case); joint damping is viscous, -damp qd; contact is the ground
 half-space z >= z_g acting on spheres fixed to the bodies, at the lowest point
 of each sphere, with normal force k_e (z_g - z) - k_d v_z and viscous friction
 -k_f v_t while that point is below z_g, v the velocity of the body's material
@@ -30,9 +30,11 @@ point there; it enters the joints as the generalised force J^T f.
 Kinematics: body i's frame is its joint frame (placed in the parent body's
 frame by a fixed rotation Rt_i and offset pt_i; in the world for a root)
 turned by q_i about the joint axis a_i: R_i = R_parent Rt_i Rot(a_i, q_i),
-p_i = p_parent + R_parent pt_i. Joint j moves a point x of a body below it at
-w_j x (x - o_j) per unit qd_j and turns the body at w_j (w_j the world joint
-axis, o_j the joint origin).
+p_i = p_parent + R_parent pt_i; or, for a prismatic joint, slid by q_i along
+it: R_i = R_parent Rt_i, p_i = p_parent + R_parent (pt_i + Rt_i a_i q_i).
+A revolute joint j moves a point x of a body below it at w_j x (x - o_j) per
+unit qd_j and turns the body at w_j (w_j the world joint axis, o_j the joint
+origin); a prismatic one moves it at w_j and turns nothing.
 
 Every function takes a batch of environments: q, qd, tau [E, N], params
 [E, 5] (damp, k_e, k_d, k_f, z_g); the links are shared.
@@ -63,6 +65,10 @@ def rot(axis, angle):
     return torch.eye(3, dtype=DT) + s * K + (1.0 - c) * (K @ K)
 
 
+def prismatic(L) -> bool:
+    return getattr(L, "joint", "revolute") == "prismatic"
+
+
 def kinematics(links, q):
     """World rotation [E, 3, 3] and origin [E, 3] of every body frame."""
     E = q.shape[0]
@@ -72,8 +78,13 @@ def kinematics(links, q):
             Rp, pp = torch.eye(3, dtype=DT).expand(E, 3, 3), torch.zeros(E, 3, dtype=DT)
         else:
             Rp, pp = R[L.parent], p[L.parent]
-        R.append(Rp @ _t(L.joint_rot) @ rot(L.axis, q[:, i]))
-        p.append(pp + Rp @ _t(L.joint_pos))
+        Rt = _t(L.joint_rot)
+        if prismatic(L):
+            R.append(Rp @ Rt)
+            p.append(pp + Rp @ _t(L.joint_pos) + q[:, i:i + 1] * (Rp @ (Rt @ _t(L.axis))))
+        else:
+            R.append(Rp @ Rt @ rot(L.axis, q[:, i]))
+            p.append(pp + Rp @ _t(L.joint_pos))
     return R, p
 
 
@@ -93,20 +104,24 @@ def world_axis(links, R, j):
 
 def point_jacobian(links, R, p, i: int, x):
     """d x / d q [E, 3, N] of a point x [E, 3] fixed to body i: column j (a
-    joint above the body) is w_j x (x - o_j); other columns are zero."""
+    joint above the body) is w_j x (x - o_j), or w_j for a prismatic joint;
+    other columns are zero."""
     E, N = x.shape[0], len(links)
     cols = [torch.zeros(E, 3, dtype=DT)] * N
     for j in ancestors(links, i):
-        cols[j] = torch.linalg.cross(world_axis(links, R, j), x - p[j])
+        w = world_axis(links, R, j)
+        cols[j] = w.expand(E, 3) if prismatic(links[j]) else torch.linalg.cross(w, x - p[j])
     return torch.stack(cols, dim=2)
 
 
 def angular_jacobian(links, R, i: int):
-    """d w_i / d qd [E, 3, N]: column j (a joint above the body) is w_j."""
+    """d w_i / d qd [E, 3, N]: column j (a revolute joint above the body) is
+    w_j; a prismatic joint turns nothing."""
     E, N = R[0].shape[0], len(links)
     cols = [torch.zeros(E, 3, dtype=DT)] * N
     for j in ancestors(links, i):
-        cols[j] = world_axis(links, R, j)
+        if not prismatic(links[j]):
+            cols[j] = world_axis(links, R, j)
     return torch.stack(cols, dim=2)
 
 

@@ -26,6 +26,7 @@ class RbLink:
     com: np.ndarray
     inertia: np.ndarray
     contacts: List[Tuple[np.ndarray, float]]
+    joint: str = "revolute"     # or "prismatic": the link slides along the axis
 
 
 def rod_inertia(mass: float, length: float, radius: float, axis: int) -> np.ndarray:
@@ -54,6 +55,15 @@ def two_link_arm(l1=0.6, l2=0.4, m1=1.5, m2=0.8) -> List[RbLink]:
                    np.zeros((3, 3)), []),
             RbLink(0, np.array([0, 0, -l1]), np.eye(3), np.array([1.0, 0, 0]), m2, np.array([0, 0, -l2]),
                    np.zeros((3, 3)), [])]
+
+
+def cart_pole(m_cart: float = 1.2, m_pole: float = 0.4, l: float = 0.5) -> List[RbLink]:
+    """A cart sliding along x (prismatic) carrying a pole hinged about y, a point-like mass at distance l
+    along the pole's -z axis."""
+    return [RbLink(-1, np.zeros(3), np.eye(3), np.array([1.0, 0, 0]), m_cart, np.zeros(3), np.zeros((3, 3)), [],
+                   joint="prismatic"),
+            RbLink(0, np.zeros(3), np.eye(3), np.array([0, 1.0, 0]), m_pole, np.array([0, 0, -l]), np.zeros((3, 3)),
+                   [])]
 
 
 def hand(n_fingers: int = 4, seg: Tuple[float, ...] = (0.05, 0.035, 0.025), palm: float = 0.09,
@@ -119,12 +129,14 @@ def hand_batch(seed: int = 9, n_envs: int = 8, substeps: int = 16, n_fingers: in
                       substeps)
 
 
-def random_tree(seed: int, n_links: int, chain: float = 0.5, n_contacts: int = 4) -> List[RbLink]:
-    """A random tree of n_links revolute links: each link hangs from a random
-    earlier one (from the one just before it with probability `chain`), with a
-    random joint frame and axis, 0.1-1 kg, a centre of mass 5-20 cm out and a
-    random positive definite inertia; contact spheres on the last n_contacts
-    links."""
+def random_tree(seed: int, n_links: int, chain: float = 0.5, n_contacts: int = 4,
+                prismatic: float = 0.0) -> List[RbLink]:
+    """A random tree of n_links links: each link hangs from a random earlier
+    one (from the one just before it with probability `chain`), with a random
+    joint frame and axis, 0.1-1 kg, a centre of mass 5-20 cm out and a random
+    positive definite inertia; contact spheres on the last n_contacts links.
+    Joints are revolute, or prismatic with probability `prismatic` (drawn
+    after the rest of the tree, so the other draws do not depend on it)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     links: List[RbLink] = []
     for i in range(n_links):
@@ -140,17 +152,22 @@ def random_tree(seed: int, n_links: int, chain: float = 0.5, n_contacts: int = 4
         I = Q @ np.diag(m * rng.uniform(2e-3, 1e-2, 3)) @ Q.T
         cts = [(com * 1.5, 0.02)] if i >= n_links - n_contacts else []
         links.append(RbLink(parent, pos, jr, ax, m, com, I, cts))
+    if prismatic > 0.0:
+        kinds = np.random.Generator(np.random.PCG64(seed + 7)).uniform(size=n_links)
+        for L, u in zip(links, kinds):
+            if u < prismatic:
+                L.joint = "prismatic"
     return links
 
 
 def tree_batch(seed: int, n_links: int, n_envs: int = 4, substeps: int = 6, dt: float = FRAME_DT / 16,
-               ground: float = 0.3, n_contacts: int = 4, roots: int = 1) -> RbWorkload:
+               ground: float = 0.3, n_contacts: int = 4, roots: int = 1, prismatic: float = 0.0) -> RbWorkload:
     """Random states (angles U(-1, 1), speeds U(-2, 2)) and torques U(-0.5, 0.5)
     on `random_tree`, joint damping U(0.01, 0.05), a ground at z_g = `ground`
     with stiffness 2000. With roots > 1 the links are split into that many
     trees (a forest: link k * n_links // roots starts a new tree)."""
     rng = np.random.Generator(np.random.PCG64(seed + 1000))
-    links = random_tree(seed, n_links, n_contacts=n_contacts)
+    links = random_tree(seed, n_links, n_contacts=n_contacts, prismatic=prismatic)
     for r in range(1, roots):
         k = r * n_links // roots
         links[k].parent = -1

@@ -236,3 +236,62 @@ def test_free_fall_of_released_wrist():
     a = tau / Izz
     assert q[0, 0].item() == pytest.approx(0.2 + dt * dt * a * S * (S + 1) / 2, rel=1e-13)
     assert qd[0, 0].item() == pytest.approx(dt * a * S, rel=1e-13)
+
+
+def test_cart_pole_textbook():
+    """A cart sliding along x (prismatic joint) carrying a pole hinged about y
+    with a point mass m_p at distance l below the hinge: the pole's mass sits
+    at (x - l s, 0, -l c), so T = 1/2 (m_c + m_p) xd^2 - m_p l c xd thd + 1/2 m_p l^2 thd^2
+    and V = -m_p g l c, giving M = [[m_c + m_p, -m_p l c], [-m_p l c, m_p l^2]],
+    b_x = m_p l s thd^2, b_theta = m_p g l s."""
+    mc, mp, l = 1.2, 0.4, 0.5
+    L = RS.cart_pole(mc, mp, l)
+    rng = np.random.default_rng(11)
+    q = t64(np.column_stack([rng.uniform(-1, 1, 6), rng.uniform(-3, 3, 6)]))
+    qd = t64(rng.uniform(-2, 2, (6, 2)))
+    M = RO.mass_matrix(L, q).numpy()
+    b = RO.bias(L, q, qd, (0.0, 0.0, -G)).detach().numpy()
+    qdd = RO.accel(L, q, qd, torch.zeros_like(q), t64([NO_GROUND] * 6), (0.0, 0.0, -G)).detach().numpy()
+    for e in range(6):
+        th, dth = q[e, 1].item(), qd[e, 1].item()
+        s, c = math.sin(th), math.cos(th)
+        Mt = np.array([[mc + mp, -mp * l * c], [-mp * l * c, mp * l * l]])
+        bt = np.array([mp * l * s * dth * dth, mp * G * l * s])
+        np.testing.assert_allclose(M[e], Mt, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(b[e], bt, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(qdd[e], np.linalg.solve(Mt, -bt), rtol=1e-11, atol=1e-12)
+    # the cart's position does not enter: a shifted cart has the same M and b
+    q2 = q.clone()
+    q2[:, 0] += 3.0
+    assert torch.allclose(RO.mass_matrix(L, q2), torch.as_tensor(M), rtol=0, atol=1e-15)
+
+
+def test_prismatic_tree_energy_and_power():
+    """A random tree with about half its joints prismatic: M is the Hessian of
+    the kinetic energy of differentiated kinematics, and the exact dynamics
+    keep the power balance with contacts, damping and torques active."""
+    wl = RS.tree_batch(seed=21, n_links=9, n_envs=3, prismatic=0.5, ground=0.0)
+    L = wl.links
+    kinds = [RO.prismatic(k) for k in L]
+    assert 2 <= sum(kinds) <= 7, kinds
+    q, qd = t64(wl.q0), t64(wl.qd0)
+    M = RO.mass_matrix(L, q)
+    for e in range(3):
+        H = torch.autograd.functional.hessian(
+            lambda v: _kinetic_from_motion(L, q[e:e + 1], v[None])[0], torch.zeros(len(L), dtype=DT64))
+        assert torch.allclose(M[e], H, rtol=1e-10, atol=1e-14)
+        assert torch.linalg.eigvalsh(M[e]).min() > 0
+    prm = t64(wl.params)
+    prm[:, 0] = 0.05
+    pts = torch.stack([x[:, 2] for _, x in RO.contact_points(L, *RO.kinematics(L, q))], 1)
+    prm[:, 4] = pts.median(1).values          # about half the contact spheres below the ground
+    tau = t64(np.random.default_rng(22).standard_normal(q.shape))
+    Qc = RO.contact_force(L, q, qd, prm)
+    assert (Qc.abs().sum(1) > 0).all()
+    qdd = RO.accel(L, q, qd, tau, prm, wl.gravity).detach()
+    qa, qda = q.clone().requires_grad_(True), qd.clone().requires_grad_(True)
+    En = (RO.kinetic(L, qa, qda) + RO.potential(L, qa, wl.gravity)).sum()
+    gq, gqd = torch.autograd.grad(En, (qa, qda))
+    dE = (gq * qd).sum(1) + (gqd * qdd).sum(1)
+    power = (qd * (tau - prm[:, 0:1] * qd + Qc)).sum(1)
+    assert torch.allclose(dE, power, rtol=1e-9, atol=1e-12)

@@ -4,7 +4,7 @@
  *
  * What it computes (paper: Appendix D.1 "Composite rigid body algorithm").
  * Every environment of a batch is one tree of rigid links joined by revolute
- * joints on a fixed base (shared links; states, torques and parameters per
+ * or prismatic joints on a fixed base (shared links; states, torques and parameters per
  * environment). One substep, per environment:
  *   M(q) qdd = tau - c(q, qd) - damp qd + J^T f_contact
  *   qd' = qd + dt qdd,  q' = q + dt qd'                  (semi-implicit Euler)
@@ -27,7 +27,9 @@
  * frame (the world's for a root) by a fixed rotation joint_rot and offset
  * joint_pos, turned by q_i about the unit joint axis (joint-frame
  * coordinates): R_i = R_parent joint_rot_i Rot(axis_i, q_i),
- * p_i = p_parent + R_parent joint_pos_i.
+ * p_i = p_parent + R_parent joint_pos_i; a prismatic joint slides the link
+ * by q_i along the axis instead: R_i = R_parent joint_rot_i,
+ * p_i = p_parent + R_parent (joint_pos_i + q_i joint_rot_i axis_i).
  *
  * Conventions are those of mpm.h: status codes, device pointers owned by the
  * caller and used only during the call's stream work, asynchronous calls on
@@ -49,6 +51,9 @@ typedef struct mpm_rb mpm_rb;
 #define MPM_RB_MAX_CONTACTS 256   /* contact spheres per environment */
 #define MPM_RB_PARAMS 5           /* per-env parameter row: damp, k_e, k_d, k_f, z_g */
 
+#define MPM_RB_REVOLUTE 0         /* joint kinds (mpm_rb_link.joint) */
+#define MPM_RB_PRISMATIC 1
+
 typedef struct {
   int32_t n_envs;        /* >= 1 */
   int32_t n_links;       /* 1 .. MPM_RB_MAX_LINKS */
@@ -67,6 +72,7 @@ typedef struct {
   float mass;            /* >= 0 */
   float com[3];          /* centre of mass in the link frame */
   float inertia[6];      /* rotational inertia about the centre of mass, link frame: xx yy zz xy xz yz */
+  int32_t joint;         /* MPM_RB_REVOLUTE (0: q is an angle) or MPM_RB_PRISMATIC (q is a length) */
 } mpm_rb_link;
 
 typedef struct {
@@ -82,8 +88,8 @@ typedef struct {
  * (through `alloc` if given; see mpm.h). `stream` is a hipStream_t.
  * Parameters start with no damping and no ground (z_g = -inf); states at 0.
  * Errors: INVALID_ARG (sizes, a parent index out of order, a non-unit axis,
- * a joint_rot that is not a rotation to 1e-4, a negative mass or radius, a
- * contact on no link), OUT_OF_MEMORY, DEVICE_ERROR. */
+ * a joint_rot that is not a rotation to 1e-4, an unknown joint kind, a
+ * negative mass or radius, a contact on no link), OUT_OF_MEMORY, DEVICE_ERROR. */
 int mpm_rb_create(const mpm_rb_desc* desc, const mpm_rb_link* links, const mpm_rb_contact* contacts,
                   const mpm_allocator* alloc, void* stream, mpm_rb** out);
 

@@ -54,6 +54,8 @@ MPM_FEM_PARAMS = 8
 MPM_RB_MAX_LINKS = 64
 MPM_RB_MAX_CONTACTS = 256
 MPM_RB_PARAMS = 5
+MPM_RB_REVOLUTE = 0
+MPM_RB_PRISMATIC = 1
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
@@ -119,7 +121,7 @@ class mpm_rb_desc(ctypes.Structure):
 class mpm_rb_link(ctypes.Structure):
     _fields_ = [("parent", ctypes.c_int32), ("joint_rot", ctypes.c_float * 9), ("joint_pos", ctypes.c_float * 3),
                 ("axis", ctypes.c_float * 3), ("mass", ctypes.c_float), ("com", ctypes.c_float * 3),
-                ("inertia", ctypes.c_float * 6)]
+                ("inertia", ctypes.c_float * 6), ("joint", ctypes.c_int32)]
 
 
 class mpm_rb_contact(ctypes.Structure):

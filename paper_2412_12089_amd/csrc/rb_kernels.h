@@ -6,7 +6,8 @@
 namespace mpmx {
 
 constexpr int kRbPrm = 5;      // damp, k_e, k_d, k_f, z_g
-constexpr int kRbLinkF = 25;   // per link: joint_rot (9), joint_pos (3), axis (3), mass, com (3), inertia (6)
+constexpr int kRbLinkF = 26;   // per link: joint_rot (9), joint_pos (3), axis (3), mass, com (3), inertia (6),
+                               // prismatic (1) or revolute (0)
 
 // shared links of a rigid-body batch and its per-env parameters
 struct RbModel {

@@ -120,6 +120,7 @@ struct Link {
   uint64_t anc, desc, kids;
   int cb, ce;
   int height, depth;   // levels: longest path down to a leaf, joints above
+  bool prism;          // the joint slides along its axis instead of turning about it
 };
 MD Link load_link(const RbModel& M, int i, bool live) {
   Link l;
@@ -142,6 +143,7 @@ MD Link load_link(const RbModel& M, int i, bool live) {
   l.ce = live ? M.cbeg[i + 1] : 0;
   l.height = live ? (M.level[i] & 0xffff) : -1;
   l.depth = live ? (M.level[i] >> 16) : -1;
+  l.prism = s[25] != 0.f;
   return l;
 }
 
@@ -316,10 +318,11 @@ MD float tree_solve(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, boo
 template <int G>
 MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool live, float q, float qd, float tau,
                   const Prm& P, Frame& F) {
-  // joint blocks B = joint_rot Rot(axis, q) (Rodrigues: c I + s [a]x + (1 - c) a a^T)
+  // joint blocks B = joint_rot Rot(axis, q) (Rodrigues: c I + s [a]x + (1 - c) a a^T) and joint_pos; a
+  // prismatic joint turns nothing (Rot = I) and shifts joint_pos by q joint_rot axis
   {
-    float sn, cs;
-    sincosf(q, &sn, &cs);
+    float sn = 0.f, cs = 1.f;
+    if (!l.prism) sincosf(q, &sn, &cs);
     const float* a = l.ax;
     const float oc = 1.f - cs;
     float Rq[9] = {cs + oc * a[0] * a[0], oc * a[0] * a[1] - sn * a[2], oc * a[0] * a[2] + sn * a[1],
@@ -331,8 +334,10 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
 #pragma unroll
         for (int c = 0; c < 3; ++c)
           E.B[3 * r + c][lane] = l.Rt[3 * r] * Rq[c] + l.Rt[3 * r + 1] * Rq[3 + c] + l.Rt[3 * r + 2] * Rq[6 + c];
+      const float qs = l.prism ? q : 0.f;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) E.B[9 + k][lane] = l.pt[k];
+      for (int k = 0; k < 3; ++k)
+        E.B[9 + k][lane] = fmaf(qs, l.Rt[3 * k] * a[0] + l.Rt[3 * k + 1] * a[1] + l.Rt[3 * k + 2] * a[2], l.pt[k]);
     }
   }
   __syncthreads();
@@ -361,14 +366,20 @@ MD float dynamics(const RbModel& M, const Link& l, EnvLds<G>& E, int lane, bool 
 #pragma unroll
     for (int k = 0; k < 3; ++k) F.p[k] = p[k];
   }
-  // joint motion S = (s, p x s), s = R axis; body inertia about the origin
+  // joint motion S = (s, p x s) for a revolute joint, (0, s) for a prismatic one, s = R axis; body inertia
+  // about the origin
   {
     const float* R = F.R;
     float s[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) s[r] = R[3 * r] * l.ax[0] + R[3 * r + 1] * l.ax[1] + R[3 * r + 2] * l.ax[2];
-    F.S.c[0] = s[0]; F.S.c[1] = s[1]; F.S.c[2] = s[2];
-    cross3(F.p, s, F.S.c + 3);
+    if (l.prism) {
+      F.S.c[0] = 0.f; F.S.c[1] = 0.f; F.S.c[2] = 0.f;
+      F.S.c[3] = s[0]; F.S.c[4] = s[1]; F.S.c[5] = s[2];
+    } else {
+      F.S.c[0] = s[0]; F.S.c[1] = s[1]; F.S.c[2] = s[2];
+      cross3(F.p, s, F.S.c + 3);
+    }
     float c[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) c[r] = F.p[r] + R[3 * r] * l.com[0] + R[3 * r + 1] * l.com[1] + R[3 * r + 2] * l.com[2];

@@ -148,7 +148,8 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
     const mpm_rb_link& L = links[i];
     if (L.parent < -1 || L.parent >= i) return MPM_INVALID_ARG;
     if (!finite_n(L.joint_rot, 9) || !finite_n(L.joint_pos, 3) || !finite_n(L.axis, 3) || !std::isfinite(L.mass) ||
-        !finite_n(L.com, 3) || !finite_n(L.inertia, 6) || L.mass < 0.f || !is_rotation(L.joint_rot))
+        !finite_n(L.com, 3) || !finite_n(L.inertia, 6) || L.mass < 0.f || !is_rotation(L.joint_rot) ||
+        (L.joint != MPM_RB_REVOLUTE && L.joint != MPM_RB_PRISMATIC))
       return MPM_INVALID_ARG;
     const double an = std::sqrt((double)L.axis[0] * L.axis[0] + (double)L.axis[1] * L.axis[1] +
                                 (double)L.axis[2] * L.axis[2]);
@@ -163,6 +164,7 @@ int mpm_rb_create(const mpm_rb_desc* d, const mpm_rb_link* links, const mpm_rb_c
     }
     row[15] = L.mass;
     std::memcpy(row + 19, L.inertia, 6 * sizeof(float));
+    row[25] = L.joint == MPM_RB_PRISMATIC ? 1.f : 0.f;
     anc[i] = (L.parent >= 0 ? anc[L.parent] : 0ull) | (1ull << i);
   }
   for (int i = 0; i < N; ++i)

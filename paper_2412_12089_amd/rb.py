@@ -24,7 +24,8 @@ def _f32(t, device) -> torch.Tensor:
 def pack_links(links: Sequence) -> tuple:
     """C arrays of links and contact spheres from objects with the fields of
     `rb_scenes.RbLink` (parent, joint_rot [3, 3], joint_pos, axis, mass, com,
-    inertia [3, 3] about the COM, contacts [(centre, radius)])."""
+    inertia [3, 3] about the COM, contacts [(centre, radius)], and optionally
+    joint = "revolute" | "prismatic"))."""
     n = len(links)
     L = (C.mpm_rb_link * n)()
     cts = []
@@ -37,6 +38,10 @@ def pack_links(links: Sequence) -> tuple:
         L[i].com[:] = [float(v) for v in np.asarray(k.com, dtype=np.float64)]
         I = np.asarray(k.inertia, dtype=np.float64)
         L[i].inertia[:] = [I[0, 0], I[1, 1], I[2, 2], I[0, 1], I[0, 2], I[1, 2]]
+        kind = getattr(k, "joint", "revolute")
+        if kind not in ("revolute", "prismatic"):
+            raise ValueError(f"link {i}: unknown joint kind {kind!r}")
+        L[i].joint = C.MPM_RB_PRISMATIC if kind == "prismatic" else C.MPM_RB_REVOLUTE
         for (c, r) in k.contacts:
             cts.append((i, np.asarray(c, dtype=np.float64), float(r)))
     K = (C.mpm_rb_contact * max(len(cts), 1))()

@@ -150,7 +150,7 @@ def test_rb_create_rejects_bad_descriptions(kw):
 
 
 @pytest.mark.parametrize("bad", ["root", "order", "axis", "rotation", "reflection", "mass", "contact_link",
-                                 "radius", "contacts"])
+                                 "radius", "contacts", "joint"])
 def test_rb_create_rejects_bad_links(bad):
     lib = C.load()
     d, L, K = _rb()
@@ -172,6 +172,8 @@ def test_rb_create_rejects_bad_links(bad):
         K[1].radius = -0.01
     elif bad == "contacts":
         d.n_contacts = 257
+    elif bad == "joint":
+        L[2].joint = 2
     out = ctypes.c_void_p()
     assert lib.mpm_rb_create(ctypes.byref(d), L, K, None, None, ctypes.byref(out)) == C.MPM_INVALID_ARG
     assert not out.value

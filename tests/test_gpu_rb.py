@@ -105,6 +105,36 @@ def test_random_trees_match_oracle(n_links, n_envs):
     check(f"tree{n_links}", w, gpu, o, og)
 
 
+@pytest.mark.parametrize("n_links,n_envs", [(9, 5), (20, 3), (40, 2)])
+def test_prismatic_trees_match_oracle(n_links, n_envs):
+    """Random trees with about half their joints prismatic (sliding links),
+    in lane groups of 16, 32 and 64, contacts, damping and torques active."""
+    w = RS.tree_batch(seed=100 + n_links, n_links=n_links, n_envs=n_envs, substeps=6, prismatic=0.5)
+    kinds = sum(RO.prismatic(k) for k in w.links)
+    assert 0 < kinds < n_links
+    announce(f"prismatic tree: E {w.n_envs} N {n_links} ({kinds} prismatic) S {w.substeps}")
+    gpu, gq, gqd = run_gpu(w, seed=n_links)
+    o, og = oracle(w, gq, gqd)
+    check(f"ptree{n_links}", w, gpu, o, og)
+
+
+def test_cart_pole_matches_oracle():
+    """A cart on a prismatic joint pushed by a force under a swinging pole
+    (the oracle's cart-pole follows the textbook equations), 64 substeps."""
+    links = RS.cart_pole()
+    E, S = 4, 64
+    rng = np.random.default_rng(31)
+    q0 = np.column_stack([rng.uniform(-0.5, 0.5, E), rng.uniform(-2.5, 2.5, E)]).astype(np.float32)
+    qd0 = rng.uniform(-1, 1, (E, 2)).astype(np.float32)
+    tau = np.zeros((S, E, 2), np.float32)
+    tau[:, :, 0] = rng.uniform(-3, 3, (S, E))
+    prm = np.tile([0.01, 0.0, 0.0, 0.0, -1e9], (E, 1))
+    w = RS.RbWorkload("cart_pole", links, q0, qd0, prm, tau, 2e-3, S)
+    gpu, gq, gqd = run_gpu(w, seed=5)
+    o, og = oracle(w, gq, gqd)
+    check("cart_pole", w, gpu, o, og)
+
+
 @pytest.mark.parametrize("roots,n_contacts", [(2, 4), (3, 0)])
 def test_forests_and_no_contacts_match_oracle(roots, n_contacts):
     """Several independent trees in one model (the factorisation's levels span

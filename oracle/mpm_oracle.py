@@ -44,7 +44,7 @@ from __future__ import annotations
 import math
 from dataclasses import dataclass
 from fractions import Fraction
-from typing import Optional, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -84,19 +84,26 @@ class Env:
     gravity: Tuple[float, float, float] = (0.0, 0.0, -9.8)
     wall: int = 3
     collider: Optional[Box] = None
+    more: Tuple[Box, ...] = ()   # further colliders, applied after the first one, in order
+
+    @property
+    def colliders(self) -> List[Box]:
+        """Every collider of the env in the order the grid update applies them."""
+        return ([self.collider] if self.collider is not None else []) + list(self.more)
+
+
+def _box_from(c) -> Box:
+    return Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b),
+               tuple(getattr(c, "axis", (0.0, 0.0, 1.0))), float(getattr(c, "angle", 0.0)),
+               float(getattr(c, "omega", 0.0)), str(getattr(c, "shape", "box")), float(getattr(c, "rounding", 0.0)))
 
 
 def env_from_spec(spec) -> Tuple[Env, torch.Tensor, Tuple[torch.Tensor, ...]]:
     """Convert a scene EnvSpec into (Env, params[7], state) in float64."""
-    box = None
-    if spec.collider is not None:
-        c = spec.collider
-        box = Box(tuple(c.center), tuple(c.half), tuple(c.velocity), float(c.alpha), float(c.mu_b),
-                  tuple(getattr(c, "axis", (0.0, 0.0, 1.0))), float(getattr(c, "angle", 0.0)),
-                  float(getattr(c, "omega", 0.0)), str(getattr(c, "shape", "box")),
-                  float(getattr(c, "rounding", 0.0)))
+    box = None if spec.collider is None else _box_from(spec.collider)
+    more = tuple(_box_from(c) for c in getattr(spec, "more_colliders", ()))
     env = Env(n=spec.n, dt=spec.dt, material=spec.material, gravity=tuple(spec.gravity),
-              wall=spec.wall, collider=box)
+              wall=spec.wall, collider=box, more=more)
     prm = torch.tensor([spec.E, spec.nu, spec.rho, spec.Vp, spec.sigma_y, spec.K, spec.gamma], dtype=DT)
     st = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).to(DT) for a in (spec.x, spec.v, spec.C, spec.F))
     return env, prm, st
@@ -387,7 +394,7 @@ def rotation(axis, theta):
     return torch.eye(3, dtype=DT) + torch.sin(theta) * K + (1.0 - torch.cos(theta)) * (K @ K)
 
 
-def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
+def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0, box: Optional[Box] = None):
     """Softened one-way contact (Appendix D.3): blend pre/post projection by s = min(exp(-alpha d), 1).
 
     ``center``, ``vb``, ``theta`` and ``omega`` are the box's center, velocity,
@@ -398,8 +405,8 @@ def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     box surface moves at vb + omega axis x (x - c). A sphere collider's
     distance and normal do not depend on its angle; its spin still moves its
     surface. A rounded box's distance is the box's less the rounding radius,
-    its normal the box's."""
-    box = env.collider
+    its normal the box's. ``box`` defaults to the env's first collider."""
+    box = env.collider if box is None else box
     n = env.n
     p = node_positions(n)
     if box.shape == "sphere":
@@ -428,7 +435,7 @@ def collide(env: Env, v, center, vb, active, theta=0.0, omega=0.0):
     return s_eff * (vb + u_proj) + (1.0 - s_eff) * v
 
 
-def collider_motion(env: Env, t: float, motion=None):
+def collider_motion(env: Env, t: float, motion=None, box: Optional[Box] = None):
     """(center, velocity, angle, angular speed) of the box during the substep
     that starts at time t.
 
@@ -438,34 +445,40 @@ def collider_motion(env: Env, t: float, motion=None):
     collider_path."""
     if motion is not None:
         return motion
-    box = env.collider
+    box = env.collider if box is None else box
     vb = torch.tensor(box.velocity, dtype=DT)
     om = torch.tensor(box.omega, dtype=DT)
     return torch.tensor(box.center, dtype=DT) + t * vb, vb, box.angle + t * om, om
 
 
-def collider_path(env: Env, vel, omega=None):
-    """Centers (and angles) of a box driven by per-substep velocities vel [S, 3]
-    and angular speeds omega [S] (the actions): during substep k the center is
-    c0 + dt sum_{j<k} vel_j and the angle angle0 + dt sum_{j<k} omega_j."""
-    c0 = torch.tensor(env.collider.center, dtype=DT)
+def collider_path(env: Env, vel, omega=None, col: int = 0):
+    """Centers (and angles) of collider `col` driven by per-substep velocities
+    vel [S, 3] and angular speeds omega [S] (the actions): during substep k the
+    center is c0 + dt sum_{j<k} vel_j and the angle angle0 + dt sum_{j<k} omega_j."""
+    box = env.colliders[col]
+    c0 = torch.tensor(box.center, dtype=DT)
     steps = torch.cat([torch.zeros(1, 3, dtype=vel.dtype), env.dt * vel[:-1]], 0)
     centers = c0 + torch.cumsum(steps, 0)
     if omega is None:
         return centers
     ast = torch.cat([torch.zeros(1, dtype=omega.dtype), env.dt * omega[:-1]], 0)
-    return centers, env.collider.angle + torch.cumsum(ast, 0)
+    return centers, box.angle + torch.cumsum(ast, 0)
 
 
 def grid_update(env: Env, gm, gP, t: float, motion=None):
-    """a5: v = P/m + dt g where m > 0 (else 0), contact blend, then sticky walls."""
+    """a5: v = P/m + dt g where m > 0 (else 0), contact blend with each
+    collider in turn (each one's output feeds the next), then sticky walls.
+    ``motion``: None, one collider's (center, v_b, angle, omega) for the first
+    collider, or a list with such an entry (or None) per collider."""
     g = torch.tensor(env.gravity, dtype=DT)
     pos = gm > 0
     msafe = torch.where(pos, gm, torch.ones_like(gm))
     v = torch.where(pos[:, None], gP / msafe[:, None] + env.dt * g, torch.zeros_like(gP))
-    if env.collider is not None:
-        center, vb, theta, om = collider_motion(env, t, motion)
-        v = collide(env, v, center, vb, pos, theta, om)
+    motions = motion if isinstance(motion, list) else [motion]
+    for ci, box in enumerate(env.colliders):
+        mo = motions[ci] if ci < len(motions) else None
+        center, vb, theta, om = collider_motion(env, t, mo, box)
+        v = collide(env, v, center, vb, pos, theta, om, box)
     wm = wall_mask(env.n, env.wall)
     return torch.where(wm[:, None], torch.zeros_like(v), v)
 
@@ -493,31 +506,40 @@ def substep(env: Env, prm, x, v, C, F, t: float, motion=None):
     return xn, vn, Cn, Fn, bool(oob.any().item())
 
 
-def motion_path(env: Env, vel, omega=None):
-    """Per-substep (center, velocity, angle, angular speed) of a box driven by
-    actions: velocities vel [>= S, 3] and angular speeds omega [>= S] (None: the
-    box's constant angular speed)."""
+def motion_path(env: Env, vel, omega=None, col: int = 0):
+    """Per-substep (center, velocity, angle, angular speed) of collider `col`
+    driven by actions: velocities vel [>= S, 3] and angular speeds omega [>= S]
+    (None: the collider's constant angular speed)."""
     if omega is None:
-        omega = torch.full((vel.shape[0],), float(env.collider.omega), dtype=vel.dtype)
-    centers, angles = collider_path(env, vel, omega)
+        omega = torch.full((vel.shape[0],), float(env.colliders[col].omega), dtype=vel.dtype)
+    centers, angles = collider_path(env, vel, omega, col)
     return centers, angles, omega
 
 
-def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=None, omega=None):
+def _motion_at(path, vel, k: int, col: int):
+    """Substep k's motion argument of grid_update with collider `col` driven."""
+    if path is None:
+        return None
+    out = [None] * (col + 1)
+    out[col] = (path[0][k], vel[k], path[1][k], path[2][k])
+    return out
+
+
+def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=None, omega=None, col: int = 0):
     """Run S substeps; returns the final state (and every state if keep_all).
 
-    ``vel`` [>= S, 3] and ``omega`` [>= S]: per-substep collider velocities and
-    angular speeds (actions) of a box whose path starts at its configured
+    ``vel`` [>= S, 3] and ``omega`` [>= S]: per-substep velocities and angular
+    speeds (actions) of collider `col`, whose path starts at its configured
     center and angle at the first substep (t0 = 0)."""
     x, v, C, F = state
     states = [state]
     any_oob = False
     path = None
     if vel is not None:
-        assert t0 == 0.0 and env.collider is not None
-        path = motion_path(env, vel, omega)
+        assert t0 == 0.0 and col < len(env.colliders)
+        path = motion_path(env, vel, omega, col)
     for k in range(S):
-        motion = None if path is None else (path[0][k], vel[k], path[1][k], path[2][k])
+        motion = _motion_at(path, vel, k, col)
         x, v, C, F, oob = substep(env, prm, x, v, C, F, t0 + k * env.dt, motion)
         any_oob |= oob
         if keep_all:
@@ -527,7 +549,7 @@ def rollout(env: Env, prm, state, S: int, t0: float = 0.0, keep_all=False, vel=N
     return (x, v, C, F), any_oob
 
 
-def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None, omega=None):
+def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None, omega=None, col: int = 0):
     """Reverse-mode cotangents of the initial state and of the 7 parameters.
 
     ``cot`` = (x_bar, v_bar, C_bar, F_bar) of the final state (None entries = 0).
@@ -538,11 +560,12 @@ def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None, om
     (center_k, v_k), and center_k = c0 + dt sum_{j<k} vel_j passes its part to
     every earlier velocity and to c0. With angular speeds ``omega`` as well it
     further returns those of omega [S] and of the starting angle, by the same
-    chain through angle_k = angle0 + dt sum_{j<k} omega_j.
+    chain through angle_k = angle0 + dt sum_{j<k} omega_j. The actions drive
+    collider `col`.
     """
     with torch.no_grad():
-        states, _ = rollout(env, prm, state, S, t0, keep_all=True, vel=vel, omega=omega)
-        path = None if vel is None else motion_path(env, vel, omega)
+        states, _ = rollout(env, prm, state, S, t0, keep_all=True, vel=vel, omega=omega, col=col)
+        path = None if vel is None else motion_path(env, vel, omega, col)
     g = [torch.zeros_like(s) if c is None else c.to(DT) for s, c in zip(state, cot)]
     gprm = torch.zeros_like(prm)
     gcen = torch.zeros(S, 3, dtype=DT)
@@ -555,9 +578,9 @@ def rollout_vjp(env: Env, prm, state, S: int, cot, t0: float = 0.0, vel=None, om
         leaves = s_in + [p_in]
         motion = None
         if path is not None:
-            motion = tuple(a.detach().clone().requires_grad_(True)
-                           for a in (path[0][k], vel[k], path[1][k], path[2][k]))
-            leaves = leaves + list(motion)
+            mk = tuple(a.detach().clone().requires_grad_(True) for a in (path[0][k], vel[k], path[1][k], path[2][k]))
+            leaves = leaves + list(mk)
+            motion = [None] * col + [mk]
         with torch.enable_grad():
             out = substep(env, p_in, *s_in, t0 + k * env.dt, motion)[:4]
             grads = torch.autograd.grad(out, leaves, grad_outputs=g, allow_unused=True)

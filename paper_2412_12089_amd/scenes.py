@@ -95,6 +95,7 @@ class EnvSpec:
     gravity: tuple = GRAVITY
     wall: int = WALL
     collider: Optional[BoxCollider] = None
+    more_colliders: tuple = ()   # further colliders, applied after `collider` in order
     x: np.ndarray = None         # [N,3] float32
     v: np.ndarray = None         # [N,3] float32
     C: np.ndarray = None         # [N,3,3] float32

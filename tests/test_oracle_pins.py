@@ -921,3 +921,98 @@ def test_capsule_contact_hand_values():
         out = O.collide(env, v, center, vb, act, th, om)[i].numpy()
         s = min(math.exp(-32.0 * dist), 1.0)
         np.testing.assert_allclose(out, s * 0.3 * tang + (1 - s) * (-nv + 0.3 * tang), atol=1e-13)
+
+
+# ---------------------------------------------------------------- several colliders per env
+def test_two_coincident_sticky_boxes_compose_their_blends():
+    """Two identical static boxes with friction high enough to stick: a node
+    approaching them ends at s vb + (1 - s) v after the first and at
+    (1 - (1 - s)^2) vb + (1 - s)^2 v after both (vb = 0 here); a separating
+    node keeps its velocity through both."""
+    import dataclasses
+    n = 16
+    box = O.Box(center=(0.5, 0.5, 0.5), half=(0.2, 0.2, 0.2), velocity=(0.0, 0.0, 0.0), alpha=32.0, mu_b=50.0)
+    one = O.Env(n=n, dt=1e-4, material=0, gravity=(0, 0, 0), collider=box)
+    two = dataclasses.replace(one, more=(box,))
+    pos = O.node_positions(n)
+    i_out = int(((pos - torch.tensor([0.75, 0.5, 0.5], dtype=DT)).abs().sum(1)).argmin())   # d = 0.05, normal +x
+    s = math.exp(-32.0 * 0.05)
+    gm = torch.ones(n ** 3, dtype=DT)
+    for vin, expect in [((-1.0, 0.2, 0.0), (1 - s) ** 2), ((1.0, 0.2, 0.0), 1.0)]:
+        gP = torch.zeros(n ** 3, 3, dtype=DT)
+        gP[i_out] = torch.tensor(vin, dtype=DT)
+        v1 = O.grid_update(one, gm, gP, 0.0)
+        v2 = O.grid_update(two, gm, gP, 0.0)
+        if expect == 1.0:
+            np.testing.assert_allclose(v2[i_out].numpy(), vin, atol=1e-14)
+        else:
+            np.testing.assert_allclose(v1[i_out].numpy(), (1 - s) * np.array(vin), atol=1e-14)
+            np.testing.assert_allclose(v2[i_out].numpy(), expect * np.array(vin), atol=1e-14)
+
+
+def test_far_apart_colliders_act_locally_and_in_order():
+    """A box and a ball far apart (sharp blends): near each one the grid
+    update with both equals the update with that one alone (the other's blend
+    weight is below 1e-12 there); swapping their order changes nothing
+    anywhere to that accuracy; nodes far from both keep the free velocity."""
+    import dataclasses
+    n = 24
+    box = O.Box(center=(0.3, 0.5, 0.5), half=(0.08, 0.1, 0.06), velocity=(0.2, 0.0, -0.1), alpha=600.0, mu_b=0.4,
+                axis=(0.0, 0.6, 0.8), angle=0.5, omega=3.0)
+    ball = O.Box(center=(0.72, 0.5, 0.5), half=(0.07, 0.07, 0.07), velocity=(0.0, 0.3, 0.0), alpha=600.0, mu_b=0.2,
+                 shape="sphere", omega=-2.0)
+    rng = np.random.default_rng(3)
+    gm = torch.from_numpy(rng.uniform(0.5, 2.0, n ** 3))
+    gP = torch.from_numpy(rng.standard_normal((n ** 3, 3)))
+    env_b = O.Env(n=n, dt=1e-4, material=0, collider=box)
+    env_s = O.Env(n=n, dt=1e-4, material=0, collider=ball)
+    both = O.Env(n=n, dt=1e-4, material=0, collider=box, more=(ball,))
+    swapped = O.Env(n=n, dt=1e-4, material=0, collider=ball, more=(box,))
+    t = 3e-4
+    vb, vs, v2, vw = (O.grid_update(e, gm, gP, t) for e in (env_b, env_s, both, swapped))
+    free = O.grid_update(O.Env(n=n, dt=1e-4, material=0), gm, gP, t)
+    p = O.node_positions(n)
+    near_box = (p[:, 0] < 0.5)
+    near_ball = (p[:, 0] > 0.55)
+    assert (vb - free)[near_box].abs().max() > 1e-2 and (vs - free)[near_ball].abs().max() > 1e-2
+    np.testing.assert_allclose(v2[near_box].numpy(), vb[near_box].numpy(), atol=1e-12)
+    np.testing.assert_allclose(v2[near_ball].numpy(), vs[near_ball].numpy(), atol=1e-12)
+    np.testing.assert_allclose(v2.numpy(), vw.numpy(), atol=1e-12)
+    assert dataclasses.replace(both).colliders == [box, ball]
+
+
+def test_second_collider_action_gradients_match_central_differences():
+    """Actions driving the second of two colliders (a static sticky box
+    first, a ball pushed by the actions second): the reverse-mode cotangents
+    of its velocities, angular speeds, start center and angle against central
+    differences of the forward."""
+    import dataclasses
+    env, prm, st = tiny(O.FLUID_TAIT, collider=True)
+    ball = O.Box(center=(0.45, 0.5, 0.42), half=(0.08, 0.08, 0.08), velocity=(0.0, 0.0, 0.0), alpha=40.0,
+                 mu_b=0.3, shape="sphere")
+    env = dataclasses.replace(env, more=(ball,))
+    S = 3
+    rng = np.random.default_rng(44)
+    vel = 0.3 * torch.from_numpy(rng.standard_normal((S, 3)))
+    om = torch.from_numpy(rng.standard_normal(S))
+    cot = [torch.from_numpy(rng.standard_normal(s.shape)) for s in st]
+    g, gp, gvel, gc0, gom, gang = O.rollout_vjp(env, prm, st, S, cot, vel=vel, omega=om, col=1)
+    assert gvel.abs().max().item() > 0
+
+    def loss(e, v_, o_):
+        out, _ = O.rollout(e, prm, st, S, vel=v_, omega=o_, col=1)
+        return sum((a * b).sum() for a, b in zip(out, cot)).item()
+
+    h = 1e-6
+    for _ in range(2):
+        d = torch.from_numpy(rng.standard_normal((S, 3)))
+        fd = (loss(env, vel + h * d, om) - loss(env, vel - h * d, om)) / (2 * h)
+        assert (gvel * d).sum().item() == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    d = torch.from_numpy(rng.standard_normal(S))
+    fd = (loss(env, vel, om + h * d) - loss(env, vel, om - h * d)) / (2 * h)
+    assert (gom * d).sum().item() == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    dc = rng.standard_normal(3)
+    shift = lambda sgn: dataclasses.replace(env, more=(dataclasses.replace(
+        ball, center=tuple(np.array(ball.center) + sgn * h * dc)),))
+    fd = (loss(shift(1), vel, om) - loss(shift(-1), vel, om)) / (2 * h)
+    assert float(gc0 @ torch.from_numpy(dc)) == pytest.approx(fd, rel=1e-6, abs=1e-9)

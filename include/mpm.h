@@ -197,6 +197,38 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const f
 int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, double* domega, double* dangle0,
                           int32_t n);
 
+/* Several colliders per environment (paper Section 5: a hand or a gripper is
+ * several rigid bodies; Appendix D.3's contact applies to each). An env holds
+ * up to MPM_MAX_COLLIDERS colliders; the grid update applies them in index
+ * order, each one's blended velocity the next one's input. The functions
+ * above address collider 0; those below take its index. A removed collider
+ * (alpha <= 0) is skipped. */
+#define MPM_MAX_COLLIDERS 4
+#define MPM_COLLIDER_BOX 1           /* shapes of mpm_set_collider */
+#define MPM_COLLIDER_SPHERE 2
+#define MPM_COLLIDER_ROUNDED_BOX 3
+
+/* Collider `index` of env (env = -1: all) as mpm_set_box_collider (shape
+ * MPM_COLLIDER_BOX; radius ignored), mpm_set_sphere_collider (SPHERE; half
+ * ignored, may be NULL) or mpm_set_rounded_box_collider (ROUNDED_BOX).
+ * Errors: those of those functions, INVALID_ARG for an index outside
+ * [0, MPM_MAX_COLLIDERS) or an unknown shape. */
+int mpm_set_collider(mpm_batch* b, int32_t env, int32_t index, int32_t shape, const float center[3],
+                     const float half[3], float radius, const float vel[3], float alpha, float mu_b);
+
+/* mpm_set_box_rotation for collider `index`. */
+int mpm_set_collider_rotation(mpm_batch* b, int32_t env, int32_t index, const float axis[3], float angle,
+                              float omega);
+
+/* mpm_set_collider_motion for collider `index` (each collider keeps its own
+ * motion; a forward fails if any is shorter than the rollout). */
+int mpm_set_collider_motion_at(mpm_batch* b, int32_t env, int32_t index, const float* vel, const float* omega,
+                               int32_t n);
+
+/* mpm_get_collider_grad for collider `index`. */
+int mpm_get_collider_grad_at(mpm_batch* b, int32_t env, int32_t index, double* dvel, double* dc0, double* domega,
+                             double* dangle0, int32_t n);
+
 #define MPM_MOMENTS 20   /* stride of one env's moments */
 
 /* Per-env weighted moments of particle positions and velocities: the

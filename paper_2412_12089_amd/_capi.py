@@ -40,7 +40,8 @@ EXPORTED = (
     "mpm_server_create", "mpm_server_destroy", "mpm_server_submit", "mpm_server_step", "mpm_server_poll",
     "mpm_server_cancel", "mpm_server_now", "mpm_server_idle", "mpm_server_stats_get", "mpm_server_last_error",
     "mpm_sort_keys_noalloc", "mpm_pair_distance", "mpm_pair_distance_vjp", "mpm_set_box_rotation",
-    "mpm_set_sphere_collider", "mpm_set_rounded_box_collider",
+    "mpm_set_sphere_collider", "mpm_set_rounded_box_collider", "mpm_set_collider", "mpm_set_collider_rotation",
+    "mpm_set_collider_motion_at", "mpm_get_collider_grad_at",
     "mpm_fem_create", "mpm_fem_destroy", "mpm_fem_set_rest", "mpm_fem_set_params", "mpm_fem_set_state",
     "mpm_fem_get_state", "mpm_fem_forward", "mpm_fem_backward", "mpm_fem_sync", "mpm_fem_env_errors",
     "mpm_fem_last_error", "mpm_fem_memory_bytes",
@@ -56,6 +57,8 @@ MPM_RB_MAX_CONTACTS = 256
 MPM_RB_PARAMS = 5
 MPM_RB_REVOLUTE = 0
 MPM_RB_PRISMATIC = 1
+MPM_MAX_COLLIDERS = 4
+MPM_COLLIDER_BOX, MPM_COLLIDER_SPHERE, MPM_COLLIDER_ROUNDED_BOX = 1, 2, 3
 MPM_SORT_NOALLOC_MAX = 1 << 20
 MPM_MOMENTS = 20
 (OPT_GRAPHS, OPT_P2G, OPT_G2P, OPT_G2P_ADJ, OPT_P2G_ADJ, OPT_MIN_RUN, OPT_GRID_CAP, OPT_MAX_RUN, OPT_BOX, OPT_SPECIALIZE,
@@ -177,6 +180,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mpm_set_collider_motion": (I32, [VP, I32, F3, F3, I32]),
         "mpm_get_collider_grad": (I32, [VP, I32, D8, D8, D8, D8, I32]),
         "mpm_set_box_rotation": (I32, [VP, I32, F3, ctypes.c_float, ctypes.c_float]),
+        "mpm_set_collider": (I32, [VP, I32, I32, I32, F3, F3, ctypes.c_float, F3, ctypes.c_float, ctypes.c_float]),
+        "mpm_set_collider_rotation": (I32, [VP, I32, I32, F3, ctypes.c_float, ctypes.c_float]),
+        "mpm_set_collider_motion_at": (I32, [VP, I32, I32, F3, F3, I32]),
+        "mpm_get_collider_grad_at": (I32, [VP, I32, I32, D8, D8, D8, D8, I32]),
         "mpm_moments": (I32, [VP, VP, VP, VP, VP]),
         "mpm_moments_vjp": (I32, [VP, VP, VP, VP, VP, VP, VP]),
         "mpm_server_create": (I32, [P(mpm_server_desc), P(mpm_allocator), VP, P(VP)]),

@@ -81,8 +81,13 @@ class Batch:
         self.record_token = 0
         for i, e in enumerate(self.envs):
             self.set_material(i, e.material, e.params())
-            if e.collider is not None:
-                self.set_collider(i, e.collider)
+            self._set_all_colliders(i, e)
+
+    def _set_all_colliders(self, env: int, spec) -> None:
+        if spec.collider is not None:
+            self.set_collider(env, spec.collider)
+        for k, c in enumerate(getattr(spec, "more_colliders", ()), start=1):
+            self.set_collider(env, c, index=k)
 
     # -- lifetime
     def close(self):
@@ -125,30 +130,36 @@ class Batch:
                                                         f3(velocity), float(alpha), float(mu_b)),
                   "mpm_set_rounded_box_collider")
 
-    def set_box_rotation(self, env: int, axis, angle: float, omega: float) -> None:
+    def set_box_rotation(self, env: int, axis, angle: float, omega: float, index: int = 0) -> None:
         self.record_token += 1   # the library drops its recorded tape
         f3 = (ctypes.c_float * 3)(*[float(x) for x in axis])
-        self._chk(self.lib.mpm_set_box_rotation(self.h, env, f3, float(angle), float(omega)), "mpm_set_box_rotation")
+        self._chk(self.lib.mpm_set_collider_rotation(self.h, env, int(index), f3, float(angle), float(omega)),
+                  "mpm_set_collider_rotation")
 
-    def set_collider(self, env: int, c, center=None, angle=None) -> None:
-        """The collider c (scenes.BoxCollider: a box, or a ball) of env, optionally with another start center /
-        angle."""
+    def set_collider(self, env: int, c, center=None, angle=None, index: int = 0) -> None:
+        """Collider `index` (0 .. MPM_MAX_COLLIDERS - 1) of env: c is a scenes.BoxCollider (a box, a rounded
+        box or a ball), optionally with another start center / angle."""
+        self.record_token += 1   # the library drops its recorded tape
         cen = c.center if center is None else center
+        f3 = lambda a: (ctypes.c_float * 3)(*[float(x) for x in a])
         if getattr(c, "shape", "box") == "sphere":
-            self.set_sphere_collider(env, cen, c.half[0], c.velocity, c.alpha, c.mu_b)
+            shape, radius = C.MPM_COLLIDER_SPHERE, c.half[0]
         elif getattr(c, "rounding", 0.0) > 0.0:
-            self.set_rounded_box_collider(env, cen, c.half, c.rounding, c.velocity, c.alpha, c.mu_b)
+            shape, radius = C.MPM_COLLIDER_ROUNDED_BOX, c.rounding
         else:
-            self.set_box_collider(env, cen, c.half, c.velocity, c.alpha, c.mu_b)
+            shape, radius = C.MPM_COLLIDER_BOX, 0.0
+        self._chk(self.lib.mpm_set_collider(self.h, env, int(index), shape, f3(cen), f3(c.half), float(radius),
+                                            f3(c.velocity), float(c.alpha), float(c.mu_b)), "mpm_set_collider")
         if c.rotates or angle is not None:
-            self.set_box_rotation(env, c.axis, c.angle if angle is None else angle, c.omega)
+            self.set_box_rotation(env, c.axis, c.angle if angle is None else angle, c.omega, index=index)
 
-    def set_collider_motion(self, env: int, vel, omega=None) -> None:
-        """Per-substep box velocities [n, 3] and angular speeds [n] (None: the box's constant one),
-        the actions; vel None or empty clears them."""
+    def set_collider_motion(self, env: int, vel, omega=None, index: int = 0) -> None:
+        """Per-substep velocities [n, 3] and angular speeds [n] (None: the collider's constant one) of
+        collider `index`, the actions; vel None or empty clears them."""
         self.record_token += 1   # the library drops its recorded tape
         if vel is None or len(vel) == 0:
-            self._chk(self.lib.mpm_set_collider_motion(self.h, env, None, None, 0), "mpm_set_collider_motion")
+            self._chk(self.lib.mpm_set_collider_motion_at(self.h, env, int(index), None, None, 0),
+                      "mpm_set_collider_motion_at")
             return
         v = np.ascontiguousarray(np.asarray(vel, dtype=np.float32).reshape(-1, 3))
         buf = v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
@@ -157,7 +168,8 @@ class Batch:
             o = np.ascontiguousarray(np.asarray(omega, dtype=np.float32).reshape(-1))
             assert o.shape[0] == v.shape[0]
             ob = o.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        self._chk(self.lib.mpm_set_collider_motion(self.h, env, buf, ob, v.shape[0]), "mpm_set_collider_motion")
+        self._chk(self.lib.mpm_set_collider_motion_at(self.h, env, int(index), buf, ob, v.shape[0]),
+                  "mpm_set_collider_motion_at")
 
     def moments(self, x, v, w=None):
         """Per-env weighted moments [E, 20] float64 of caller-order x, v (device)."""
@@ -196,17 +208,17 @@ class Batch:
                                                  C.ptr(g), C.ptr(gx)), "mpm_pair_distance_vjp")
         return gx
 
-    def collider_grad(self, env: int, n: int, spin: bool = False):
-        """After backward: (dL/dvel [n, 3], dL/dc0 [3]) in float64, and with spin=True also
-        (dL/domega [n], dL/dangle0)."""
+    def collider_grad(self, env: int, n: int, spin: bool = False, index: int = 0):
+        """After backward, of collider `index`: (dL/dvel [n, 3], dL/dc0 [3]) in float64, and with spin=True
+        also (dL/domega [n], dL/dangle0)."""
         dvel = np.zeros((n, 3), np.float64)
         dc0 = np.zeros(3, np.float64)
         dom = np.zeros(n, np.float64)
         dang = np.zeros(1, np.float64)
         P = ctypes.POINTER(ctypes.c_double)
-        self._chk(self.lib.mpm_get_collider_grad(self.h, env, dvel.ctypes.data_as(P), dc0.ctypes.data_as(P),
-                                                 dom.ctypes.data_as(P), dang.ctypes.data_as(P), n),
-                  "mpm_get_collider_grad")
+        self._chk(self.lib.mpm_get_collider_grad_at(self.h, env, int(index), dvel.ctypes.data_as(P),
+                                                    dc0.ctypes.data_as(P), dom.ctypes.data_as(P),
+                                                    dang.ctypes.data_as(P), n), "mpm_get_collider_grad_at")
         return (dvel, dc0, dom, float(dang[0])) if spin else (dvel, dc0)
 
     # -- state
@@ -256,8 +268,7 @@ class Batch:
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
         self.envs[env] = spec
         self.set_material(env, spec.material, spec.params())
-        if spec.collider is not None:
-            self.set_collider(env, spec.collider)
+        self._set_all_colliders(env, spec)
 
     def backward(self, gx=None, gv=None, gC=None, gF=None, want_params: bool = True):
         d = self.device

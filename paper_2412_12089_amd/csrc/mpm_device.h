@@ -26,31 +26,39 @@ enum : int { PB_MU = 0, PB_LAM, PB_SY, PB_K, PB_GAMMA, PB_MP, PB_VP, PB_COUNT };
 constexpr float kSigmaMin = 1e-4f;   // singular values are clamped below this before the log
 constexpr float kYieldScale = 2.0f;  // numerator of the printed yield offset kYieldScale*sigma_y/(2 mu)
 
+constexpr int32_t kColliderBox = 1;      // box of half extents ch, axis-aligned in its own frame
+constexpr int32_t kColliderSphere = 2;   // ball of radius ch[0]
+
+// One kinematic collider of an environment (its grid update applies them in turn).
+struct ColDev {
+  int32_t has_collider;                  // 0 none, kColliderBox, kColliderSphere
+  int32_t motion_off, motion_len;        // prescribed motion: rows [motion_off, + motion_len) of the motion
+                                         // table, one per substep (len 0: constant velocity cv)
+  float cc[3], ch[3], cv[3], c_alpha, c_mu;   // centre at t=0, half extents, velocity, contact softness, friction
+  float c_axis[3];                       // rotation: unit axis (world), angle at t = 0, constant angular speed
+  float c_angle, c_omega, c_round;       // (the box is axis-aligned in its own frame); the box's rounding radius
+                                         // (its distance less c_round)
+};
+constexpr int kMaxColliders = 4;         // colliders per environment
+
 // Per-environment settings as the kernels see them. The first block is
 // written by the host; the derived block by the parameter-preparation kernel.
 struct EnvDev {
   int32_t n, T, material, wall;          // nodes per axis, 4^3 tiles per axis
-  int32_t has_collider, nsub;         // collider: 0 none, kColliderBox, kColliderSphere; nsub: substeps this env
-                                      // takes in the current forward call
+  int32_t n_col, nsub;                   // colliders in use (col[0, n_col), some may be off); nsub: substeps this
+                                         // env takes in the current forward call
   int64_t p_off, p_cnt;                  // particle range in the batch arrays
   int64_t tile_off;                      // first tile of this env in the grid buffers
   float dt, fn, dx, gx, gy, gz;
-  float cc[3], ch[3], cv[3], c_alpha, c_mu;   // box collider: centre at t=0, half extents, velocity
   double E, nu, rho, Vp, sigma_y, K, gamma;   // user parameters (FP64 as given)
   // derived (a1): Lame parameters and constants in FP32
   float mu, lam, alpha_nh, mp, vp, sy, bulk, gam, yieldY;
   float pad1[3];
   int64_t row_off;                       // first row of this env in the caller's concatenated arrays
   int64_t p_cap;                         // particle capacity (positions [p_off, p_off + p_cap))
-  int32_t motion_off, motion_len;        // prescribed collider motion: rows [motion_off, + motion_len) of the
-                                         // motion table, one per substep (len 0: constant velocity cv)
-  float c_axis[3];                       // box rotation: unit axis (world), angle at t = 0, constant angular
-  float c_angle, c_omega, c_round;       // speed (the box is axis-aligned in its own frame); the box's rounding
-                                         // radius (its distance less c_round)
+  ColDev col[kMaxColliders];
 };
 
-constexpr int32_t kColliderBox = 1;      // box of half extents ch, axis-aligned in its own frame
-constexpr int32_t kColliderSphere = 2;   // ball of radius ch[0]
 
 // a row of the prescribed collider motion table: center (3), velocity (3),
 // angle about the box's axis, angular speed

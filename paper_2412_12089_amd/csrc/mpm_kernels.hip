@@ -469,7 +469,7 @@ struct Contact {
 
 // rotation by th about the box's unit axis a (Rodrigues): I + sin th K + (1 - cos th) K^2,
 // K = [a]x; exactly I at th = 0
-MD void box_rotation(const EnvDev& e, float th, float R[3][3]) {
+MD void box_rotation(const ColDev& e, float th, float R[3][3]) {
   float sn, cs;
   sincosf(th, &sn, &cs);
   const float oc = 1.f - cs;
@@ -488,8 +488,8 @@ MD void cross3(const float a[3], const float b[3], float out[3]) {
   out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-MD Contact contact_geometry(const EnvDev& e, const float c[3], const float R[3][3], int i, int j, int k) {
-  const float p[3] = {i * e.dx, j * e.dx, k * e.dx};
+MD Contact contact_geometry(const ColDev& e, float dx, const float c[3], const float R[3][3], int i, int j, int k) {
+  const float p[3] = {i * dx, j * dx, k * dx};
   float rel[3], q[3], qp[3];
   Contact ct;
   ct.pos = 0;
@@ -543,8 +543,8 @@ MD Contact contact_geometry(const EnvDev& e, const float c[3], const float R[3][
 // the box's center and velocity during substep clock[0] + k_rel (clock: this
 // env's substep clock): a row of the prescribed motion table, or the constant
 // velocity from the center at t = 0
-MD void box_motion(const EnvDev& e, const float* __restrict__ motion, double t0, const int32_t* clock, int k_rel,
-                   float c[3], float vb[3], float& th, float& om, int& row) {
+MD void box_motion(const ColDev& e, float dt, const float* __restrict__ motion, double t0, const int32_t* clock,
+                   int k_rel, float c[3], float vb[3], float& th, float& om, int& row) {
   row = -1;
   if (e.motion_len > 0) {
     int k = clock[0] + k_rel;
@@ -556,14 +556,14 @@ MD void box_motion(const EnvDev& e, const float* __restrict__ motion, double t0,
     om = m[7];
     return;
   }
-  const float t = (float)(t0 + (double)(clock[0] + k_rel) * (double)e.dt);
+  const float t = (float)(t0 + (double)(clock[0] + k_rel) * (double)dt);
   for (int a = 0; a < 3; ++a) { vb[a] = e.cv[a]; c[a] = fmaf(t, e.cv[a], e.cc[a]); }
   th = fmaf(t, e.c_omega, e.c_angle);
   om = e.c_omega;
 }
 
 // friction projection of the velocity relative to the box; returns the case (0 free, 1 stick, 2 slide)
-MD int contact_project(const EnvDev& e, const Contact& c, const float u[3], float up[3], float& un, float ut[3],
+MD int contact_project(const ColDev& e, const Contact& c, const float u[3], float up[3], float& un, float ut[3],
                        float& utn) {
   un = u[0] * c.n[0] + u[1] * c.n[1] + u[2] * c.n[2];
   for (int a = 0; a < 3; ++a) ut[a] = u[a] - un * c.n[a];
@@ -581,6 +581,22 @@ MD bool is_wall(const EnvDev& e, int i, int j, int k) {
 }
 
 
+// one collider's contact blend of the velocity v of node (i, j, k), in place: the velocity relative to the
+// collider's surface is projected (free, stick or slide) and blended with the free one by s(d)
+MD void collider_blend(const EnvDev& e, const ColDev& cd, const float* __restrict__ motion, double t0,
+                       const int32_t* clock, int k_rel, int i, int j, int k, float v[3]) {
+  float bc[3], bv[3], th, om, R[3][3], spin[3];
+  int row;
+  box_motion(cd, e.dt, motion, t0, clock, k_rel, bc, bv, th, om, row);
+  box_rotation(cd, th, R);
+  const Contact c = contact_geometry(cd, e.dx, bc, R, i, j, k);
+  cross3(cd.c_axis, c.w, spin);
+  float vs[3], u[3], up[3], ut[3], un, utn;   // vs: the collider surface's velocity at the node
+  for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = v[a] - vs[a]; }
+  contact_project(cd, c, u, up, un, ut, utn);
+  for (int a = 0; a < 3; ++a) v[a] = c.s * (vs[a] + up[a]) + (1.f - c.s) * v[a];
+}
+
 // one flagged tile (one wave, lane l = node) of the grid update
 MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restrict__ tile_env, int64_t tile, int l,
                          float* __restrict__ grid, uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
@@ -597,18 +613,9 @@ MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restr
     v[0] = fmaf(g[CH], inv, e.dt * e.gx);
     v[1] = fmaf(g[2 * CH], inv, e.dt * e.gy);
     v[2] = fmaf(g[3 * CH], inv, e.dt * e.gz);
-    if (e.has_collider) {
-      float bc[3], bv[3], th, om, R[3][3], spin[3];
-      int row;
-      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, th, om, row);
-      box_rotation(e, th, R);
-      const Contact c = contact_geometry(e, bc, R, i, j, k);
-      cross3(e.c_axis, c.w, spin);
-      float vs[3], u[3], up[3], ut[3], un, utn;   // vs: the box surface's velocity at the node
-      for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = v[a] - vs[a]; }
-      contact_project(e, c, u, up, un, ut, utn);
-      for (int a = 0; a < 3; ++a) v[a] = c.s * (vs[a] + up[a]) + (1.f - c.s) * v[a];
-    }
+#pragma unroll 1
+    for (int ci = 0; ci < e.n_col; ++ci)
+      if (e.col[ci].has_collider) collider_blend(e, e.col[ci], motion, t0, clock + ei, k_rel, i, j, k, v);
   }
   if (is_wall(e, i, j, k)) v[0] = v[1] = v[2] = 0.f;
   g[4 * CH] = v[0];
@@ -657,6 +664,85 @@ __global__ void __launch_bounds__(256) k_grid_update_chunk(const EnvDev* __restr
   }
 }
 
+// reverse of collider_blend at node (i, j, k) with input velocity vpre: maps the cotangent vb of the blended
+// velocity to that of vpre (in place), and puts the cotangents of the collider's motion row of this substep
+// (center 0-2, velocity 3-5, angle 6, angular speed 7) in gmo and the row in row (-1: no prescribed motion)
+MD void collider_blend_adjoint(const EnvDev& e, const ColDev& cd, const float* __restrict__ motion, double t0,
+                               const int32_t* clock, int k_rel, int i, int j, int k, const float vpre[3], float vb[3],
+                               float gmo[kMotionRow], int& row) {
+  float bc[3], bv[3], th, om, R[3][3], spin[3];
+  box_motion(cd, e.dt, motion, t0, clock, k_rel, bc, bv, th, om, row);
+  box_rotation(cd, th, R);
+  const Contact c = contact_geometry(cd, e.dx, bc, R, i, j, k);
+  cross3(cd.c_axis, c.w, spin);
+  float vs[3], u[3], up[3], ut[3], un, utn;
+  for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = vpre[a] - vs[a]; }
+  const int kase = contact_project(cd, c, u, up, un, ut, utn);
+  float ub[3];
+  float uh[3] = {0.f, 0.f, 0.f};
+  if (kase == 0) {
+    for (int a = 0; a < 3; ++a) ub[a] = vb[a];
+  } else if (kase == 1) {
+    ub[0] = ub[1] = ub[2] = 0.f;
+  } else {
+    for (int a = 0; a < 3; ++a) uh[a] = ut[a] / utn;
+    const float nd = c.n[0] * vb[0] + c.n[1] * vb[1] + c.n[2] * vb[2];
+    const float ud = uh[0] * vb[0] + uh[1] * vb[1] + uh[2] * vb[2];
+    const float r = un / utn;
+    for (int a = 0; a < 3; ++a) {
+      const float pv = vb[a] - c.n[a] * nd;  // (I - n n^T) vbar
+      ub[a] = pv + cd.c_mu * (c.n[a] * ud + r * (pv - uh[a] * ud));
+    }
+  }
+  if (row >= 0) {
+    // v' = s (v_s + u') + (1 - s) v with u = v - v_s and the surface velocity
+    // v_s = v_b + omega a x w, w = x - c: v_b and omega enter through v_s; the
+    // center through s(d), through n and through w; the angle through s(d)
+    // and n, both functions of the box-frame position r = R^T w
+    float sbar = 0.f, vsb[3];
+    for (int a = 0; a < 3; ++a) {
+      vsb[a] = c.s * (vb[a] - ub[a]);   // cotangent of v_s
+      gmo[3 + a] = vsb[a];
+      sbar += vb[a] * (vs[a] + up[a] - vpre[a]);
+    }
+    float axr[3], axv[3];
+    cross3(cd.c_axis, c.rb, axr);        // d r / d angle = -a x r (a is fixed by the rotation)
+    cross3(cd.c_axis, vsb, axv);
+    gmo[7] = vsb[0] * spin[0] + vsb[1] * spin[1] + vsb[2] * spin[2];
+    for (int a = 0; a < 3; ++a) gmo[a] += om * axv[a];
+    if (c.d > 0.f) {   // s = exp(-alpha d) below its cap; d(d)/d(center) = -n, d(d)/d(angle) = -nb . (a x r)
+      const float sa = sbar * cd.c_alpha * c.s;
+      for (int a = 0; a < 3; ++a) gmo[a] += sa * c.n[a];
+      gmo[6] += sa * (c.nb[0] * axr[0] + c.nb[1] * axr[1] + c.nb[2] * axr[2]);
+    }
+    if (kase == 2) {
+      // sliding: u' depends on n = R nb(r). n turns rigidly with the angle
+      // (d n = a x n d angle), and nb = sgn (|r| - h)^+ / L turns with r near
+      // edges and corners: d nb / d r = (I_A - nb nb^T) / L
+      float w[3], Pw[3];
+      for (int a = 0; a < 3; ++a) w[a] = c.s * vb[a];
+      const float wu = w[0] * uh[0] + w[1] * uh[1] + w[2] * uh[2];
+      const float wn = w[0] * c.n[0] + w[1] * c.n[1] + w[2] * c.n[2];
+      const float r = un / utn;
+      for (int a = 0; a < 3; ++a) Pw[a] = w[a] - wu * uh[a];
+      float nbar[3], axn[3];
+      for (int a = 0; a < 3; ++a)
+        nbar[a] = -(1.f + cd.c_mu * r) * wn * u[a] - un * (w[a] + cd.c_mu * r * Pw[a]) + cd.c_mu * wu * u[a];
+      cross3(cd.c_axis, c.n, axn);
+      gmo[6] += nbar[0] * axn[0] + nbar[1] * axn[1] + nbar[2] * axn[2];
+      if (__popc(c.pos) >= 2) {
+        float nbb[3], mm[3];
+        for (int a = 0; a < 3; ++a) nbb[a] = R[0][a] * nbar[0] + R[1][a] * nbar[1] + R[2][a] * nbar[2];
+        const float nn = c.nb[0] * nbb[0] + c.nb[1] * nbb[1] + c.nb[2] * nbb[2];
+        for (int a = 0; a < 3; ++a) mm[a] = (c.pos & (1 << a)) ? (nbb[a] - c.nb[a] * nn) / c.L : 0.f;
+        for (int a = 0; a < 3; ++a) gmo[a] -= R[a][0] * mm[0] + R[a][1] * mm[1] + R[a][2] * mm[2];
+        gmo[6] -= mm[0] * axr[0] + mm[1] * axr[1] + mm[2] * axr[2];
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) vb[a] = (1.f - c.s) * vb[a] + c.s * ub[a];
+}
+
 // reads vbar (channels 0-2 of gcot), writes mbar (3) and Pbar (4-6), clears
 // vbar and the tape grid of this substep (and its flag)
 // one flagged tile (one wave, lane l = node) of the grid adjoint
@@ -674,85 +760,42 @@ MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __rest
   const float P[3] = {g[CH], g[2 * CH], g[3 * CH]};
   float vb[3] = {gc[0], gc[CH], gc[2 * CH]};   // cotangent of the node velocity
   float mb = 0.f, Pb[3] = {0.f, 0.f, 0.f};
-  // cotangents of the box center (0-2), velocity (3-5), angle (6) and angular speed (7)
-  float gmo[kMotionRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int row = -1;
-  if (!is_wall(e, i, j, k) && m > 0.f) {
-    const float inv = 1.f / m;
-    const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
-    if (e.has_collider) {
-      float bc[3], bv[3], th, om, R[3][3], spin[3];
-      box_motion(e, motion, t0, clock + ei, k_rel, bc, bv, th, om, row);
-      box_rotation(e, th, R);
-      const Contact c = contact_geometry(e, bc, R, i, j, k);
-      cross3(e.c_axis, c.w, spin);
-      float vs[3], u[3], up[3], ut[3], un, utn;
-      for (int a = 0; a < 3; ++a) { vs[a] = fmaf(om, spin[a], bv[a]); u[a] = vpre[a] - vs[a]; }
-      const int kase = contact_project(e, c, u, up, un, ut, utn);
-      float ub[3];
-      float uh[3] = {0.f, 0.f, 0.f};
-      if (kase == 0) {
-        for (int a = 0; a < 3; ++a) ub[a] = vb[a];
-      } else if (kase == 1) {
-        ub[0] = ub[1] = ub[2] = 0.f;
-      } else {
-        for (int a = 0; a < 3; ++a) uh[a] = ut[a] / utn;
-        const float nd = c.n[0] * vb[0] + c.n[1] * vb[1] + c.n[2] * vb[2];
-        const float ud = uh[0] * vb[0] + uh[1] * vb[1] + uh[2] * vb[2];
-        const float r = un / utn;
-        for (int a = 0; a < 3; ++a) {
-          const float pv = vb[a] - c.n[a] * nd;  // (I - n n^T) vbar
-          ub[a] = pv + e.c_mu * (c.n[a] * ud + r * (pv - uh[a] * ud));
-        }
-      }
-      if (row >= 0) {
-        // v' = s (v_s + u') + (1 - s) v with u = v - v_s and the surface velocity
-        // v_s = v_b + omega a x w, w = x - c: v_b and omega enter through v_s; the
-        // center through s(d), through n and through w; the angle through s(d)
-        // and n, both functions of the box-frame position r = R^T w
-        float sbar = 0.f, vsb[3];
-        for (int a = 0; a < 3; ++a) {
-          vsb[a] = c.s * (vb[a] - ub[a]);   // cotangent of v_s
-          gmo[3 + a] = vsb[a];
-          sbar += vb[a] * (vs[a] + up[a] - vpre[a]);
-        }
-        float axr[3], axv[3];
-        cross3(e.c_axis, c.rb, axr);        // d r / d angle = -a x r (a is fixed by the rotation)
-        cross3(e.c_axis, vsb, axv);
-        gmo[7] = vsb[0] * spin[0] + vsb[1] * spin[1] + vsb[2] * spin[2];
-        for (int a = 0; a < 3; ++a) gmo[a] += om * axv[a];
-        if (c.d > 0.f) {   // s = exp(-alpha d) below its cap; d(d)/d(center) = -n, d(d)/d(angle) = -nb . (a x r)
-          const float sa = sbar * e.c_alpha * c.s;
-          for (int a = 0; a < 3; ++a) gmo[a] += sa * c.n[a];
-          gmo[6] += sa * (c.nb[0] * axr[0] + c.nb[1] * axr[1] + c.nb[2] * axr[2]);
-        }
-        if (kase == 2) {
-          // sliding: u' depends on n = R nb(r). n turns rigidly with the angle
-          // (d n = a x n d angle), and nb = sgn (|r| - h)^+ / L turns with r near
-          // edges and corners: d nb / d r = (I_A - nb nb^T) / L
-          float w[3], Pw[3];
-          for (int a = 0; a < 3; ++a) w[a] = c.s * vb[a];
-          const float wu = w[0] * uh[0] + w[1] * uh[1] + w[2] * uh[2];
-          const float wn = w[0] * c.n[0] + w[1] * c.n[1] + w[2] * c.n[2];
-          const float r = un / utn;
-          for (int a = 0; a < 3; ++a) Pw[a] = w[a] - wu * uh[a];
-          float nbar[3], axn[3];
-          for (int a = 0; a < 3; ++a)
-            nbar[a] = -(1.f + e.c_mu * r) * wn * u[a] - un * (w[a] + e.c_mu * r * Pw[a]) + e.c_mu * wu * u[a];
-          cross3(e.c_axis, c.n, axn);
-          gmo[6] += nbar[0] * axn[0] + nbar[1] * axn[1] + nbar[2] * axn[2];
-          if (__popc(c.pos) >= 2) {
-            float nbb[3], mm[3];
-            for (int a = 0; a < 3; ++a) nbb[a] = R[0][a] * nbar[0] + R[1][a] * nbar[1] + R[2][a] * nbar[2];
-            const float nn = c.nb[0] * nbb[0] + c.nb[1] * nbb[1] + c.nb[2] * nbb[2];
-            for (int a = 0; a < 3; ++a) mm[a] = (c.pos & (1 << a)) ? (nbb[a] - c.nb[a] * nn) / c.L : 0.f;
-            for (int a = 0; a < 3; ++a) gmo[a] -= R[a][0] * mm[0] + R[a][1] * mm[1] + R[a][2] * mm[2];
-            gmo[6] -= mm[0] * axr[0] + mm[1] * axr[1] + mm[2] * axr[2];
-          }
-        }
-      }
-      for (int a = 0; a < 3; ++a) vb[a] = (1.f - c.s) * vb[a] + c.s * ub[a];
+  const bool act = !is_wall(e, i, j, k) && m > 0.f;
+  const float inv = act ? 1.f / m : 0.f;
+  const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
+  // the colliders in reverse order (the loop is uniform over the wave, one tile of one env); each one's input
+  // velocity comes from the forward chain of the ones before it, recomputed
+#pragma unroll 1
+  for (int ci = e.n_col - 1; ci >= 0; --ci) {
+    const ColDev& cd = e.col[ci];
+    if (!cd.has_collider) continue;
+    // cotangents of the collider's center (0-2), velocity (3-5), angle (6) and angular speed (7) at this node
+    float gmo[kMotionRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int row = -1;
+    if (act) {
+      float vin[3] = {vpre[0], vpre[1], vpre[2]};
+#pragma unroll 1
+      for (int cj = 0; cj < ci; ++cj)
+        if (e.col[cj].has_collider) collider_blend(e, e.col[cj], motion, t0, clock + ei, k_rel, i, j, k, vin);
+      collider_blend_adjoint(e, cd, motion, t0, clock + ei, k_rel, i, j, k, vin, vb, gmo, row);
     }
+    // sum the wave's (one tile of one env) cotangents and add them to the collider's row of this substep in FP64
+    if (cd.motion_len > 0) {
+      bool nz = false;
+      for (int c = 0; c < kMotionRow; ++c) nz |= gmo[c] != 0.f;
+      const bool any = __ballot(row >= 0 && nz) != 0ull;
+      if (any) {
+        int rw = row;
+        for (int off = 32; off > 0; off >>= 1) rw = max(rw, __shfl_xor(rw, off, 64));
+        for (int c = 0; c < kMotionRow; ++c) {
+          double x = (double)gmo[c];
+          for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+          if (l == 0 && x != 0.0) atomicAdd(&gmotion[kMotionRow * (int64_t)rw + c], x);
+        }
+      }
+    }
+  }
+  if (act) {
     for (int a = 0; a < 3; ++a) Pb[a] = vb[a] * inv;
     mb = -(vb[0] * P[0] + vb[1] * P[1] + vb[2] * P[2]) * inv * inv;
   }
@@ -764,22 +807,6 @@ MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __rest
 #pragma unroll
   for (int c = 0; c < 7; ++c) g[c * CH] = 0.f;
   if (l == 0) flags[tile] = 0u;
-  // the wave is one tile of one env: sum its nodes' collider cotangents and add
-  // them to this substep's row in FP64
-  if (e.has_collider && e.motion_len > 0) {
-    bool nz = false;
-    for (int c = 0; c < kMotionRow; ++c) nz |= gmo[c] != 0.f;
-    const bool any = __ballot(row >= 0 && nz) != 0ull;
-    if (any) {
-      int rw = row;
-      for (int off = 32; off > 0; off >>= 1) rw = max(rw, __shfl_xor(rw, off, 64));
-      for (int c = 0; c < kMotionRow; ++c) {
-        double x = (double)gmo[c];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (l == 0 && x != 0.0) atomicAdd(&gmotion[kMotionRow * (int64_t)rw + c], x);
-      }
-    }
-  }
 }
 
 __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__ envs,

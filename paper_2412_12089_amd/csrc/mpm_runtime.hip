@@ -89,7 +89,8 @@ struct mpm_batch {
   int32_t* errs = nullptr;
   int32_t* clock = nullptr;       // [E] per-env substep clocks (collider motion time)
   int32_t* clock_rec = nullptr;   // [E] the clocks at the start of the recorded forward
-  float* motion_d = nullptr;     // prescribed collider motions: [E][max_substeps] rows of kMotionRow floats
+  float* motion_d = nullptr;     // prescribed collider motions: [E][kMaxColliders][max_substeps] rows of kMotionRow
+                                 // floats
   double* gmotion_d = nullptr;   // their cotangents, same layout, FP64
   std::vector<float> motion_h;
 
@@ -736,7 +737,7 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     h.n = v.n; h.T = v.n / 4; h.material = v.material; h.wall = v.wall;
     h.p_off = p_off; h.p_cnt = v.n_particles; h.p_cap = v.n_particles; h.tile_off = t_off;
     h.row_off = p_off; h.nsub = 0;
-    h.motion_off = e * b->max_substeps; h.motion_len = 0;
+    for (int ci = 0; ci < kMaxColliders; ++ci) h.col[ci].motion_off = (e * kMaxColliders + ci) * b->max_substeps;
     h.dt = v.dt; h.fn = (float)v.n; h.dx = 1.f / (float)v.n;
     h.gx = v.gravity[0]; h.gy = v.gravity[1]; h.gz = v.gravity[2];
     h.rho = 1.0; h.nu = 0.0;  // inert until mpm_set_material
@@ -804,8 +805,9 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
   b->errs = (int32_t*)A(sizeof(int32_t) * b->E);
   b->clock = (int32_t*)A(sizeof(int32_t) * b->E);
   b->clock_rec = (int32_t*)A(sizeof(int32_t) * b->E);
-  b->motion_d = (float*)A(sizeof(float) * kMotionRow * (size_t)b->E * b->max_substeps);
-  b->gmotion_d = (double*)A(sizeof(double) * kMotionRow * (size_t)b->E * b->max_substeps);
+  const size_t motion_rows = (size_t)kMaxColliders * b->E * b->max_substeps;
+  b->motion_d = (float*)A(sizeof(float) * kMotionRow * motion_rows);
+  b->gmotion_d = (double*)A(sizeof(double) * kMotionRow * motion_rows);
   if (!ok) {
     free_all(b);
     delete b;
@@ -826,8 +828,8 @@ int mpm_batch_create(const mpm_batch_desc* d, const mpm_allocator* a, void* stre
     zero(b->errs, sizeof(int32_t) * b->E);
     zero(b->clock, sizeof(int32_t) * b->E);
     zero(b->clock_rec, sizeof(int32_t) * b->E);
-    zero(b->motion_d, sizeof(float) * kMotionRow * (size_t)b->E * b->max_substeps);
-    zero(b->gmotion_d, sizeof(double) * kMotionRow * (size_t)b->E * b->max_substeps);
+    zero(b->motion_d, sizeof(float) * kMotionRow * motion_rows);
+    zero(b->gmotion_d, sizeof(double) * kMotionRow * motion_rows);
     // identity ids and an F = I rest state until particles are set
     rc = upload_envs(b);
   } while (0);
@@ -896,8 +898,8 @@ int mpm_configure_env(mpm_batch* b, int32_t env, const mpm_env_desc* d) {
   h.dt = d->dt; h.fn = (float)d->n; h.dx = 1.f / (float)d->n;
   h.gx = d->gravity[0]; h.gy = d->gravity[1]; h.gz = d->gravity[2];
   h.p_cnt = d->n_particles;
-  h.has_collider = 0;
-  h.motion_len = 0;
+  h.n_col = 0;
+  for (int ci = 0; ci < kMaxColliders; ++ci) { h.col[ci].has_collider = 0; h.col[ci].motion_len = 0; }
   refresh_layout(b);
   HIPC(b, hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice, b->stream));
   b->recorded = false;
@@ -926,11 +928,23 @@ int mpm_set_material(mpm_batch* b, int32_t env, int32_t material, const double p
   return upload_envs(b);
 }
 
+static void count_colliders(EnvDev& d) {
+  d.n_col = 0;
+  for (int ci = 0; ci < kMaxColliders; ++ci)
+    if (d.col[ci].has_collider) d.n_col = ci + 1;
+}
+
+static int check_collider_index(mpm_batch* b, int32_t index) {
+  if (index < 0 || index >= kMaxColliders) return fail(b, MPM_INVALID_ARG, "collider index outside [0, MPM_MAX_COLLIDERS)");
+  return MPM_OK;
+}
+
 static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[3], const float h[3], const float v[3],
-                        float alpha, float mu_b, float rounding = 0.f) {
+                        float alpha, float mu_b, float rounding = 0.f, int32_t index = 0) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
+  if ((rc = check_collider_index(b, index))) return rc;
   if (alpha > 0.f && (!c || !h || !v)) return fail(b, MPM_INVALID_ARG, "null collider array");
   if (alpha > 0.f && !(mu_b >= 0.f)) return fail(b, MPM_INVALID_ARG, "mu_b must be >= 0");
   if (alpha > 0.f && shape == kColliderSphere && !(h[0] >= 0.f && std::isfinite(h[0])))
@@ -939,7 +953,7 @@ static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[
     return fail(b, MPM_INVALID_ARG, "the rounding radius must be finite and >= 0");
   const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
   for (int e = e0; e < e1; ++e) {
-    EnvDev& d = b->envs_h[e];
+    ColDev& d = b->envs_h[e].col[index];
     d.has_collider = alpha > 0.f ? shape : 0;
     if (d.has_collider) {
       for (int a = 0; a < 3; ++a) { d.cc[a] = c[a]; d.ch[a] = h[a]; d.cv[a] = v[a]; }
@@ -951,6 +965,7 @@ static int set_collider(mpm_batch* b, int32_t env, int32_t shape, const float c[
     d.c_axis[2] = 1.f;
     d.c_angle = d.c_omega = 0.f;
     d.motion_len = 0;   // a prescribed motion starts from the collider it was set for
+    count_colliders(b->envs_h[e]);
   }
   b->recorded = false;
   return upload_envs(b);
@@ -972,19 +987,38 @@ int mpm_set_rounded_box_collider(mpm_batch* b, int32_t env, const float c[3], co
   return set_collider(b, env, kColliderBox, c, h, v, alpha, mu_b, radius);
 }
 
+int mpm_set_collider(mpm_batch* b, int32_t env, int32_t index, int32_t shape, const float center[3],
+                     const float half[3], float radius, const float vel[3], float alpha, float mu_b) {
+  if (!b) return MPM_INVALID_ARG;
+  if (alpha > 0.f && shape == MPM_COLLIDER_SPHERE) {
+    const float h[3] = {radius, radius, radius};
+    return set_collider(b, env, kColliderSphere, center, h, vel, alpha, mu_b, 0.f, index);
+  }
+  if (alpha > 0.f && shape != MPM_COLLIDER_BOX && shape != MPM_COLLIDER_ROUNDED_BOX)
+    return fail(b, MPM_INVALID_ARG, "unknown collider shape");
+  return set_collider(b, env, kColliderBox, center, half, vel, alpha, mu_b,
+                      shape == MPM_COLLIDER_ROUNDED_BOX ? radius : 0.f, index);
+}
+
 int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float angle, float omega) {
+  return mpm_set_collider_rotation(b, env, 0, axis, angle, omega);
+}
+
+int mpm_set_collider_rotation(mpm_batch* b, int32_t env, int32_t index, const float axis[3], float angle,
+                              float omega) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, true);
   if (rc) return rc;
+  if ((rc = check_collider_index(b, index))) return rc;
   if (!axis) return fail(b, MPM_INVALID_ARG, "null axis");
   const double len = std::sqrt((double)axis[0] * axis[0] + (double)axis[1] * axis[1] + (double)axis[2] * axis[2]);
   if (!(len > 0.0) || !std::isfinite(len) || !std::isfinite(angle) || !std::isfinite(omega))
     return fail(b, MPM_INVALID_ARG, "the axis must be nonzero and the values finite");
   const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->E : env + 1;
   for (int e = e0; e < e1; ++e)
-    if (!b->envs_h[e].has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no collider");
+    if (!b->envs_h[e].col[index].has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no such collider");
   for (int e = e0; e < e1; ++e) {
-    EnvDev& d = b->envs_h[e];
+    ColDev& d = b->envs_h[e].col[index];
     for (int a = 0; a < 3; ++a) d.c_axis[a] = (float)(axis[a] / len);
     d.c_angle = angle;
     d.c_omega = omega;
@@ -995,13 +1029,20 @@ int mpm_set_box_rotation(mpm_batch* b, int32_t env, const float axis[3], float a
 }
 
 int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const float* omega, int32_t n) {
+  return mpm_set_collider_motion_at(b, env, 0, vel, omega, n);
+}
+
+int mpm_set_collider_motion_at(mpm_batch* b, int32_t env, int32_t index, const float* vel, const float* omega,
+                               int32_t n) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, false);
   if (rc) return rc;
-  EnvDev& d = b->envs_h[env];
+  if ((rc = check_collider_index(b, index))) return rc;
+  ColDev& d = b->envs_h[env].col[index];
+  const float dt = b->envs_h[env].dt;
   if (n < 0 || n > b->max_substeps) return fail(b, MPM_INVALID_ARG, "motion length outside [0, max_substeps]");
   if (n > 0 && !vel) return fail(b, MPM_INVALID_ARG, "null velocity array");
-  if (n > 0 && !d.has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no collider");
+  if (n > 0 && !d.has_collider) return fail(b, MPM_INVALID_ARG, "the environment has no such collider");
   for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
     if (!std::isfinite(vel[i])) return fail(b, MPM_NONFINITE, "non-finite collider velocity");
   for (int64_t i = 0; omega && i < (int64_t)n; ++i)
@@ -1020,8 +1061,8 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const f
       }
       b->motion_h[W * k + 6] = (float)th;
       b->motion_h[W * k + 7] = (float)om;
-      for (int a = 0; a < 3; ++a) c[a] += (double)d.dt * (double)vel[3 * k + a];
-      th += (double)d.dt * om;
+      for (int a = 0; a < 3; ++a) c[a] += (double)dt * (double)vel[3 * k + a];
+      th += (double)dt * om;
     }
     HIPC(b, hipMemcpyAsync(b->motion_d + W * (size_t)d.motion_off, b->motion_h.data(), sizeof(float) * W * (size_t)n,
                            hipMemcpyHostToDevice, b->stream));
@@ -1034,11 +1075,18 @@ int mpm_set_collider_motion(mpm_batch* b, int32_t env, const float* vel, const f
 
 int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, double* domega, double* dangle0,
                           int32_t n) {
+  return mpm_get_collider_grad_at(b, env, 0, dvel, dc0, domega, dangle0, n);
+}
+
+int mpm_get_collider_grad_at(mpm_batch* b, int32_t env, int32_t index, double* dvel, double* dc0, double* domega,
+                             double* dangle0, int32_t n) {
   if (!b) return MPM_INVALID_ARG;
   int rc = check_env(b, env, false);
   if (rc) return rc;
-  const EnvDev& d = b->envs_h[env];
-  if (d.motion_len == 0) return fail(b, MPM_BAD_STATE, "the environment has no prescribed collider motion");
+  if ((rc = check_collider_index(b, index))) return rc;
+  const ColDev& d = b->envs_h[env].col[index];
+  const float dt = b->envs_h[env].dt;
+  if (d.motion_len == 0) return fail(b, MPM_BAD_STATE, "the collider has no prescribed motion");
   if (n < 0 || n > d.motion_len) return fail(b, MPM_INVALID_ARG, "n outside [0, motion length]");
   const int L = d.motion_len;
   constexpr int W = kMotionRow;
@@ -1052,8 +1100,8 @@ int mpm_get_collider_grad(mpm_batch* b, int32_t env, double* dvel, double* dc0, 
   double later[3] = {0.0, 0.0, 0.0}, later_th = 0.0;   // sums over k > j of the center / angle cotangents
   for (int j = L - 1; j >= 0; --j) {
     if (j < n && dvel)
-      for (int a = 0; a < 3; ++a) dvel[3 * j + a] = g[W * j + 3 + a] + (double)d.dt * later[a];
-    if (j < n && domega) domega[j] = g[W * j + 7] + (double)d.dt * later_th;
+      for (int a = 0; a < 3; ++a) dvel[3 * j + a] = g[W * j + 3 + a] + (double)dt * later[a];
+    if (j < n && domega) domega[j] = g[W * j + 7] + (double)dt * later_th;
     for (int a = 0; a < 3; ++a) later[a] += g[W * j + a];
     later_th += g[W * j + 6];
   }
@@ -1107,8 +1155,9 @@ int mpm_forward_envs(mpm_batch* b, const int32_t* n_substeps, int32_t flags) {
     S = std::max(S, n_substeps[e]);
   }
   for (int e = 0; e < b->E; ++e)
-    if (b->envs_h[e].motion_len > 0 && n_substeps[e] > 0 && b->env_steps[e] + n_substeps[e] > b->envs_h[e].motion_len)
-      return fail(b, MPM_INVALID_ARG, "the collider motion of an environment is shorter than the rollout");
+    for (const ColDev& cd : b->envs_h[e].col)
+      if (cd.has_collider && cd.motion_len > 0 && n_substeps[e] > 0 && b->env_steps[e] + n_substeps[e] > cd.motion_len)
+        return fail(b, MPM_INVALID_ARG, "the collider motion of an environment is shorter than the rollout");
   bool changed = false;
   for (int e = 0; e < b->E; ++e) {
     changed |= b->envs_h[e].nsub != n_substeps[e];
@@ -1165,7 +1214,7 @@ int mpm_backward(mpm_batch* b, const float* gx, const float* gv, const float* gC
   const hipStream_t s = b->stream;
   if (b->timing) { b->spans.clear(); b->event_next = 0; }
   launch_fill_u32(b->pacc, 0u, 2 * 8 * (int64_t)b->E, s);
-  launch_fill_u32(b->gmotion_d, 0u, 2 * kMotionRow * (int64_t)b->E * b->max_substeps, s);
+  launch_fill_u32(b->gmotion_d, 0u, 2 * kMotionRow * (int64_t)kMaxColliders * b->E * b->max_substeps, s);
   const int S = b->rec_S;
   const int nseg = (S + b->K - 1) / b->K;
   int c = 0;

@@ -59,6 +59,10 @@ int main(void) {
   if (mpm_rb_create(&rd, links, NULL, NULL, NULL, &r) != MPM_INVALID_ARG || r != NULL) return 8;
   if (mpm_rb_backward(NULL, NULL, NULL, NULL, NULL, NULL, NULL) != MPM_INVALID_ARG) return 9;
   if (MPM_RB_PARAMS != 5 || MPM_FEM_PARAMS != 8) return 10;
+  /* several colliders per env: the indexed setters check their handle first */
+  const float c3[3] = {0.5f, 0.5f, 0.5f};
+  if (MPM_MAX_COLLIDERS < 2 || mpm_set_collider(NULL, 0, 1, MPM_COLLIDER_BOX, c3, c3, 0.f, c3, 10.f, 0.1f) !=
+      MPM_INVALID_ARG) return 11;
   printf("ok %s\n", mpm_version());
   return 0;
 }

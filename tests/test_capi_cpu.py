@@ -63,6 +63,11 @@ def test_null_arguments_are_rejected():
     assert lib.mpm_batch_destroy(None) == C.MPM_INVALID_ARG
     assert lib.mpm_last_error(None) == b"null batch"
     assert lib.mpm_memory_bytes(None) == 0
+    f3 = (ctypes.c_float * 3)(0.5, 0.5, 0.5)
+    assert lib.mpm_set_collider(None, 0, 1, C.MPM_COLLIDER_SPHERE, f3, f3, 0.1, f3, 10.0, 0.1) == C.MPM_INVALID_ARG
+    assert lib.mpm_set_collider_rotation(None, 0, 1, f3, 0.0, 1.0) == C.MPM_INVALID_ARG
+    assert lib.mpm_set_collider_motion_at(None, 0, 1, None, None, 0) == C.MPM_INVALID_ARG
+    assert lib.mpm_get_collider_grad_at(None, 0, 1, None, None, None, None, 0) == C.MPM_INVALID_ARG
 
 
 def test_key_width_limit():

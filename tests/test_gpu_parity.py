@@ -732,3 +732,65 @@ def test_run_to_run_spread_is_rounding_level():
     announce(f"run-to-run spread: state {st:.2e}, gradients {gr:.2e} "
              f"({'bit-identical' if st == 0 and gr == 0 else 'atomic reordering'})")
     assert st < 1e-6 and gr < 1e-5
+
+
+# a gripper: a left jaw (a box), a right finger (a capsule, driven by actions) and a ball pressing from above
+GRIP = (scenes.BoxCollider(center=(0.31, 0.46, 0.46), half=(0.04, 0.12, 0.12), velocity=(0.4, 0.0, 0.0),
+                           alpha=64.0, mu_b=0.5),
+        SPIN_CAPSULE,
+        scenes.sphere_collider(center=(0.46, 0.46, 0.64), radius=0.06, velocity=(0.0, 0.0, -0.3), alpha=64.0,
+                               mu_b=0.2, omega=-3.0))
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched", "batched-pull"])
+def test_several_colliders_with_actions_forward_and_gradient(mode):
+    # three colliders in one env, applied in turn by the grid update; the second one is driven by
+    # per-substep velocities and angular speeds: states, state cotangents and the cotangents of that
+    # collider's actions, start center and angle against the oracle; an env with one collider beside it
+    import dataclasses
+    from paper_2412_12089_amd.batch import Batch
+    spec = make_env(scenes.FLUID_TAIT, N=3000, seed=180, collider=GRIP[0], v_scale=0.2)
+    spec = dataclasses.replace(spec, more_colliders=GRIP[1:])
+    other = make_env(scenes.NEOHOOKEAN, N=1000, seed=181, collider=BOXES["face"])
+    S, K = 10, 4
+    rng = np.random.default_rng(182)
+    col = GRIP[1]
+    vel = (np.array(col.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+    om = (col.omega + 4.0 * rng.standard_normal(S)).astype(np.float32)
+    announce(f"three colliders, the second driven by {S} actions, {mode}")
+    envs = [spec, other]
+    cots = random_cotangents(envs, seed=183)
+    b = Batch(envs, max_substeps=S, ckpt_every=K, mode=mode.split("-")[0])
+    try:
+        if mode == "batched-pull":
+            set_pull_schedule(b)
+        b.set_particles_from_specs()
+        b.set_collider_motion(0, vel, om, index=1)
+        b.forward(S, record=True)
+        st = tuple(to_np(t) for t in b.get_particles(env=0))
+        cat = lambda i: torch.from_numpy(np.concatenate([c[i] for c in cots], axis=0))
+        dx, dv, dC, dF, dp = b.backward(cat(0), cat(1), cat(2), cat(3))
+        N0 = spec.n_particles
+        gr = tuple(to_np(t)[:N0] for t in (dx, dv, dC, dF))
+        dvel, dc0, dom, dang = b.collider_grad(0, S, spin=True, index=1)
+        assert b.sync(raise_on_error=False) == 0
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    assert len(env.colliders) == 3
+    velt, omt = torch.from_numpy(vel).double(), torch.from_numpy(om).double()
+    (x, v, Cm, F), _ = O.rollout(env, prm, st0, S, vel=velt, omega=omt, col=1)
+    c = tuple(torch.from_numpy(np.asarray(a, dtype=np.float32)).double() for a in cots[0])
+    g, gp, gvel, gc0, gom, gang = O.rollout_vjp(env, prm, st0, S, c, vel=velt, omega=omt, col=1)
+    # every collider touches the blob: dropping any one of them changes the oracle's final velocities
+    for drop in range(3):
+        cs = [cc for k, cc in enumerate(env.colliders) if k != drop]
+        e2 = dataclasses.replace(env, collider=cs[0], more=tuple(cs[1:]))
+        (_, v2, _, _), _ = O.rollout(e2, prm, st0, S)
+        assert np.abs(v2.numpy() - v.numpy()).max() > 1e-3, drop
+    check_state(st, tuple(t.numpy() for t in (x, v, Cm, F)), "gripper actions", spec.x, S)
+    check_grads(gr, tuple(t.numpy() for t in g), "gripper actions")
+    ev, ec, eo = relerr(dvel, gvel.numpy()), relerr(dc0, gc0.numpy()), relerr(dom, gom.numpy())
+    ea = abs(dang - float(gang)) / abs(float(gang))
+    announce(f"gripper actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {ea:.2e}")
+    assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3 and ea < 1e-3

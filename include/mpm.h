@@ -460,6 +460,13 @@ typedef struct {
 
 #define MPM_SERVER_DRY 1
 
+/* a further collider of a request (as mpm_set_collider: shape MPM_COLLIDER_*,
+ * radius of a SPHERE or ROUNDED_BOX) */
+typedef struct {
+  int32_t shape;
+  float center[3], half[3], radius, vel[3], alpha, mu_b;
+} mpm_collider;
+
 typedef struct {
   mpm_env_desc env;        /* n <= n_cap, n_particles <= n_cap_particles, material */
   double params[8];        /* as mpm_set_material */
@@ -476,6 +483,9 @@ typedef struct {
   const float *gx, *gv, *gC, *gF;    /* cotangents of the final state (backward; NULL = 0), read when it starts */
   float *out_x, *out_v, *out_C, *out_F;  /* final state, written when the forward ends (NULL = not wanted) */
   float *dx0, *dv0, *dC0, *dF0;          /* initial-state cotangents, written when the backward ends (NULL = skip) */
+  int32_t n_more;                        /* further colliders, 0 .. MPM_MAX_COLLIDERS - 1, applied after the one
+                                            above (slots 1 ..), held by value */
+  mpm_collider more[MPM_MAX_COLLIDERS - 1];
 } mpm_request;
 
 /* request states */

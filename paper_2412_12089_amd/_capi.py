@@ -88,13 +88,20 @@ class mpm_server_desc(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32), ("budget_bytes", ctypes.c_int64)]
 
 
+class mpm_collider(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("center", ctypes.c_float * 3), ("half", ctypes.c_float * 3),
+                ("radius", ctypes.c_float), ("vel", ctypes.c_float * 3), ("alpha", ctypes.c_float),
+                ("mu_b", ctypes.c_float)]
+
+
 class mpm_request(ctypes.Structure):
     _fields_ = [("env", mpm_env_desc), ("params", ctypes.c_double * 8), ("has_collider", ctypes.c_int32),
                 ("substeps", ctypes.c_int32), ("c_center", ctypes.c_float * 3), ("c_half", ctypes.c_float * 3),
                 ("c_vel", ctypes.c_float * 3), ("c_alpha", ctypes.c_float), ("c_mu", ctypes.c_float),
                 ("backward", ctypes.c_int32), ("c_round", ctypes.c_float), ("arrival", ctypes.c_double)] + \
                [(k, ctypes.c_void_p) for k in ("x", "v", "C", "F", "gx", "gv", "gC", "gF", "out_x", "out_v", "out_C",
-                                                "out_F", "dx0", "dv0", "dC0", "dF0")]
+                                                "out_F", "dx0", "dv0", "dC0", "dF0")] + \
+               [("n_more", ctypes.c_int32), ("more", mpm_collider * 3)]
 
 
 class mpm_request_status(ctypes.Structure):

@@ -150,7 +150,7 @@ class Batch:
             shape, radius = C.MPM_COLLIDER_BOX, 0.0
         self._chk(self.lib.mpm_set_collider(self.h, env, int(index), shape, f3(cen), f3(c.half), float(radius),
                                             f3(c.velocity), float(c.alpha), float(c.mu_b)), "mpm_set_collider")
-        if c.rotates or angle is not None:
+        if c.alpha > 0.0 and (c.rotates or angle is not None):   # alpha <= 0 removed the collider
             self.set_box_rotation(env, c.axis, c.angle if angle is None else angle, c.omega, index=index)
 
     def set_collider_motion(self, env: int, vel, omega=None, index: int = 0) -> None:

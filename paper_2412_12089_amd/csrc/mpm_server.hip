@@ -196,6 +196,10 @@ int load_slot(mpm_server* s, Req& q) {
     SCHK(s, mpm_set_rounded_box_collider(b, q.slot, r.c_center, r.c_half, r.c_round, r.c_vel, r.c_alpha, r.c_mu));
   else if (r.has_collider)
     SCHK(s, mpm_set_box_collider(b, q.slot, r.c_center, r.c_half, r.c_vel, r.c_alpha, r.c_mu));
+  for (int k = 0; k < r.n_more; ++k) {
+    const mpm_collider& c = r.more[k];
+    SCHK(s, mpm_set_collider(b, q.slot, k + 1, c.shape, c.center, c.half, c.radius, c.vel, c.alpha, c.mu_b));
+  }
   SCHK(s, mpm_set_particles(b, q.slot, r.x, r.v, r.C, r.F, r.env.n_particles));
   return MPM_OK;
 }
@@ -475,6 +479,11 @@ int mpm_server_submit(mpm_server* s, const mpm_request* r, int64_t* id) {
   if (e.material < 0 || e.material > MPM_FLUID_PAPER) return sfail(s, MPM_INVALID_ARG, "unknown material");
   if (!(r->params[1] > -1.0 && r->params[1] < 0.5)) return sfail(s, MPM_INVALID_ARG, "nu must lie in (-1, 0.5)");
   if (!(e.dt > 0.f)) return sfail(s, MPM_INVALID_ARG, "dt must be > 0");
+  if (r->n_more < 0 || r->n_more > MPM_MAX_COLLIDERS - 1)
+    return sfail(s, MPM_INVALID_ARG, "n_more outside [0, MPM_MAX_COLLIDERS - 1]");
+  for (int k = 0; k < r->n_more; ++k)
+    if (r->more[k].shape < MPM_COLLIDER_BOX || r->more[k].shape > MPM_COLLIDER_ROUNDED_BOX)
+      return sfail(s, MPM_INVALID_ARG, "unknown collider shape");
   Req q;
   q.id = s->next_id++;
   q.r = *r;

@@ -100,6 +100,21 @@ class Server:
             r.c_round = float(getattr(c, "rounding", 0.0))
             r.c_center[:], r.c_half[:], r.c_vel[:] = list(c.center), list(c.half), list(c.velocity)
             r.c_alpha, r.c_mu = float(c.alpha), float(c.mu_b)
+        more = list(getattr(e, "more_colliders", ()))
+        if len(more) > C.MPM_MAX_COLLIDERS - 1:
+            raise ValueError(f"at most {C.MPM_MAX_COLLIDERS - 1} further colliders per request")
+        r.n_more = len(more)
+        for k, c in enumerate(more):
+            if c.rotates:
+                raise ValueError("served requests take colliders that translate only")
+            m = r.more[k]
+            sphere = getattr(c, "shape", "box") == "sphere"
+            rounding = float(getattr(c, "rounding", 0.0))
+            m.shape = (C.MPM_COLLIDER_SPHERE if sphere else
+                       C.MPM_COLLIDER_ROUNDED_BOX if rounding > 0.0 else C.MPM_COLLIDER_BOX)
+            m.radius = float(c.half[0]) if sphere else rounding
+            m.center[:], m.half[:], m.vel[:] = list(c.center), list(c.half), list(c.velocity)
+            m.alpha, m.mu_b = float(c.alpha), float(c.mu_b)
         keep, outs = [], None
         if self.dry:
             addr = self._dummy.ctypes.data

@@ -794,3 +794,46 @@ def test_several_colliders_with_actions_forward_and_gradient(mode):
     ea = abs(dang - float(gang)) / abs(float(gang))
     announce(f"gripper actions: dL/dvel {ev:.2e}, dL/dc0 {ec:.2e}, dL/domega {eo:.2e}, dL/dangle0 {ea:.2e}")
     assert ev < 1e-3 and ec < 1e-3 and eo < 1e-3 and ea < 1e-3
+
+
+def test_collider_slots_gaps_removal_and_errors():
+    # colliders in slots 0 and 2 with slot 1 empty equal the oracle's two-collider env; removing slot 2
+    # (alpha 0) leaves the one-collider env; a slot outside [0, 4), an unknown shape, a motion on an
+    # empty slot and a motion shorter than the rollout are refused
+    import ctypes
+    import dataclasses
+    from paper_2412_12089_amd import _capi as C
+    from paper_2412_12089_amd._capi import MPMError
+    from paper_2412_12089_amd.batch import Batch
+    spec = make_env(scenes.FLUID_TAIT, N=2000, seed=190, collider=GRIP[0], v_scale=0.2)
+    S = 6
+    b = Batch([spec], max_substeps=S, ckpt_every=3)
+    try:
+        b.set_collider(0, GRIP[2], index=2)
+        b.set_particles_from_specs()
+        b.forward(S)
+        st2 = tuple(to_np(t) for t in b.get_particles(env=0))
+        b.set_collider(0, dataclasses.replace(GRIP[2], alpha=0.0), index=2)
+        b.set_particles_from_specs()
+        b.forward(S)
+        st1 = tuple(to_np(t) for t in b.get_particles(env=0))
+        f3 = (ctypes.c_float * 3)(0.5, 0.5, 0.5)
+        for idx, shape in ((4, C.MPM_COLLIDER_BOX), (-1, C.MPM_COLLIDER_BOX), (1, 7)):
+            assert b.lib.mpm_set_collider(b.h, 0, idx, shape, f3, f3, 0.05, f3, 10.0, 0.1) == C.MPM_INVALID_ARG
+        with pytest.raises(MPMError):
+            b.set_collider_motion(0, np.zeros((S, 3), np.float32), index=1)     # slot 1 is empty
+        b.set_collider_motion(0, np.zeros((S - 2, 3), np.float32), index=0)
+        b.set_particles_from_specs()
+        with pytest.raises(MPMError):
+            b.forward(S)
+        assert b.sync(raise_on_error=False) == 0
+    finally:
+        b.close()
+    env, prm, st0 = O.env_from_spec(spec)
+    two = dataclasses.replace(env, more=(O.env_from_spec(dataclasses.replace(spec, collider=GRIP[2]))[0].collider,))
+    announce("collider slots 0 and 2, then slot 2 removed")
+    (x, v, Cm, F), _ = O.rollout(two, prm, st0, S)
+    check_state(st2, tuple(t.numpy() for t in (x, v, Cm, F)), "slots 0 and 2", spec.x, S)
+    (x, v, Cm, F), _ = O.rollout(env, prm, st0, S)
+    check_state(st1, tuple(t.numpy() for t in (x, v, Cm, F)), "slot 2 removed", spec.x, S)
+    assert np.abs(st2[1] - st1[1]).max() > 1e-3

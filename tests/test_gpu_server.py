@@ -1,8 +1,9 @@
 """The library's continuous-batching server on the GPU: each request's result
 is the same alone and in the mix, and matches the oracle -- including an
 80-substep backward (8 chunks, each recomputed from its checkpoint) with the
-parameter cotangents, and a request whose box collider moves, whose clock must
-follow it through its chunks while other slots are loaded and restored."""
+parameter cotangents, a request whose box collider moves, whose clock must
+follow it through its chunks while other slots are loaded and restored, and a
+request with two colliders (a ball and a plate)."""
 import dataclasses
 
 import numpy as np
@@ -33,7 +34,7 @@ def requests(n=8, seed=11):
         x = scenes._f32(lo + rng.uniform(0, side, size=(N, 3)))
         v = scenes._f32(rng.uniform(-0.5, 0.5, size=(N, 3)))
         C, F = scenes._rest_state(N)
-        collider = None
+        collider, more = None, ()
         if i == 3:   # a box moving into the particles
             collider = scenes.BoxCollider(center=(float(lo[0]) + side + 0.03, 0.5, 0.5), half=(0.02, 0.3, 0.3),
                                           velocity=(-0.6, 0.0, 0.0), alpha=2.0 * grid, mu_b=0.5)
@@ -41,7 +42,11 @@ def requests(n=8, seed=11):
             collider = scenes.sphere_collider(center=(float(lo[0]) + side + 0.04, float(lo[1]) + 0.09,
                                                       float(lo[2]) + 0.09), radius=0.06, velocity=(-0.6, 0.0, 0.0),
                                               alpha=2.0 * grid, mu_b=0.5)
-        env = scenes.EnvSpec(n=grid, dt=5e-5, rho=1e3, Vp=side ** 3 / N, x=x, v=v, C=C, F=F, collider=collider, **mat)
+            # and a second collider, a plate pushing from the other side
+            more = (scenes.BoxCollider(center=(float(lo[0]) - 0.03, 0.5, 0.5), half=(0.02, 0.3, 0.3),
+                                       velocity=(0.5, 0.0, 0.0), alpha=2.0 * grid, mu_b=0.3),)
+        env = scenes.EnvSpec(n=grid, dt=5e-5, rho=1e3, Vp=side ** 3 / N, x=x, v=v, C=C, F=F, collider=collider,
+                             more_colliders=more, **mat)
         w = scenes._f32(rng.standard_normal((N, 3)))
         S = 80 if i == 0 else int(rng.integers(12, 36))
         out.append(scenes.Request(i, 0.0, env, S, bool(i % 2 == 0) or i == 3, w))

@@ -153,6 +153,12 @@ def test_invalid_requests_are_refused():
     r.env.material = 9
     assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG
     r.env.material = 0
+    r.n_more = C.MPM_MAX_COLLIDERS                                                                   # too many
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG
+    r.n_more = 1
+    r.more[0].shape = 5                                                                              # no shape
+    assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_INVALID_ARG
+    r.more[0].shape = C.MPM_COLLIDER_SPHERE
     assert lib.mpm_server_submit(srv.h, ctypes.byref(r), ctypes.byref(sid)) == C.MPM_OK
     assert lib.mpm_server_cancel(srv.h, 12345) == C.MPM_INVALID_ARG
     st = C.mpm_request_status()

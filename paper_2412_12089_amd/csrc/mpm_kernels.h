@@ -56,17 +56,18 @@ void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const Wor
 // gmotion: FP64 cotangents of those rows, accumulated by the grid adjoint
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                         uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, const float* motion,
-                        hipStream_t s);
-// the grid passes with `tiles` (16 or 64) tiles per block, the flagged ones found by one ballot
+                        hipStream_t s, int cols = kMaxColliders);
+// the grid passes with `tiles` (16 or 64) tiles per block, the flagged ones found by one ballot; cols = the
+// most colliders an env of the launch holds (0 and 1 launch variants compiled for them)
 void launch_grid_update_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                 uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear,
-                                const float* motion, int tiles, hipStream_t s);
+                                const float* motion, int tiles, hipStream_t s, int cols = kMaxColliders);
 void launch_grid_adjoint_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                  uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel,
-                                 const float* motion, double* gmotion, int tiles, hipStream_t s);
+                                 const float* motion, double* gmotion, int tiles, hipStream_t s, int cols = kMaxColliders);
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                          uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, const float* motion,
-                         double* gmotion, hipStream_t s);
+                         double* gmotion, hipStream_t s, int cols = kMaxColliders);
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s);
 void launch_g2p_direct(const float* st, float* out, int64_t N, const EnvDev* envs, const WorkItem* items, int n_items,
                        const float* grid, int32_t* errs, int k_call, hipStream_t s);

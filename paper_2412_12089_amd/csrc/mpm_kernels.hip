@@ -597,7 +597,9 @@ MD void collider_blend(const EnvDev& e, const ColDev& cd, const float* __restric
   for (int a = 0; a < 3; ++a) v[a] = c.s * (vs[a] + up[a]) + (1.f - c.s) * v[a];
 }
 
-// one flagged tile (one wave, lane l = node) of the grid update
+// one flagged tile (one wave, lane l = node) of the grid update. COLS bounds the colliders an env of the
+// launch holds: 0 compiles them out, 1 takes slot 0 alone, kMaxColliders any number
+template <int COLS>
 MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restrict__ tile_env, int64_t tile, int l,
                          float* __restrict__ grid, uint32_t* __restrict__ flags, const int32_t* __restrict__ clock,
                          double t0, int k_rel, int clear, const float* __restrict__ motion) {
@@ -613,8 +615,9 @@ MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restr
     v[0] = fmaf(g[CH], inv, e.dt * e.gx);
     v[1] = fmaf(g[2 * CH], inv, e.dt * e.gy);
     v[2] = fmaf(g[3 * CH], inv, e.dt * e.gz);
+    const int nc = COLS == 0 ? 0 : COLS == 1 ? min(e.n_col, 1) : e.n_col;
 #pragma unroll 1
-    for (int ci = 0; ci < e.n_col; ++ci)
+    for (int ci = 0; ci < nc; ++ci)
       if (e.col[ci].has_collider) collider_blend(e, e.col[ci], motion, t0, clock + ei, k_rel, i, j, k, v);
   }
   if (is_wall(e, i, j, k)) v[0] = v[1] = v[2] = 0.f;
@@ -627,6 +630,7 @@ MD void grid_update_tile(const EnvDev* __restrict__ envs, const int32_t* __restr
   }
 }
 
+template <int COLS>
 __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ envs,
                                                      const int32_t* __restrict__ tile_env, int64_t tile0,
                                                      int64_t ntiles, float* __restrict__ grid,
@@ -635,12 +639,12 @@ __global__ void __launch_bounds__(256) k_grid_update(const EnvDev* __restrict__ 
   const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (tile >= tile0 + ntiles) return;
   if (flags[tile] == 0u) return;
-  grid_update_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
+  grid_update_tile<COLS>(envs, tile_env, tile, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
 }
 
 // the same, TILES (at most 64) tiles per block: one wave's ballot finds the flagged ones and the block's
 // four waves take them in turn (far fewer blocks than one per 4 tiles when few tiles are flagged)
-template <int TILES>
+template <int TILES, int COLS>
 __global__ void __launch_bounds__(256) k_grid_update_chunk(const EnvDev* __restrict__ envs,
                                                            const int32_t* __restrict__ tile_env, int64_t ntiles,
                                                            float* __restrict__ grid, uint32_t* __restrict__ flags,
@@ -660,7 +664,8 @@ __global__ void __launch_bounds__(256) k_grid_update_chunk(const EnvDev* __restr
     const int bit = __ffsll((unsigned long long)m) - 1;
     m &= m - 1ull;
     if ((rank & 3) == wave)
-      grid_update_tile(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear, motion);
+      grid_update_tile<COLS>(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, clock, t0, k_rel, clear,
+                            motion);
   }
 }
 
@@ -745,7 +750,8 @@ MD void collider_blend_adjoint(const EnvDev& e, const ColDev& cd, const float* _
 
 // reads vbar (channels 0-2 of gcot), writes mbar (3) and Pbar (4-6), clears
 // vbar and the tape grid of this substep (and its flag)
-// one flagged tile (one wave, lane l = node) of the grid adjoint
+// one flagged tile (one wave, lane l = node) of the grid adjoint (COLS as for the update)
+template <int COLS>
 MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __restrict__ tile_env, int64_t tile, int l,
                           float* __restrict__ grid, uint32_t* __restrict__ flags, float* __restrict__ gcot,
                           const int32_t* __restrict__ clock, double t0, int k_rel, const float* __restrict__ motion,
@@ -765,8 +771,9 @@ MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __rest
   const float vpre[3] = {fmaf(P[0], inv, e.dt * e.gx), fmaf(P[1], inv, e.dt * e.gy), fmaf(P[2], inv, e.dt * e.gz)};
   // the colliders in reverse order (the loop is uniform over the wave, one tile of one env); each one's input
   // velocity comes from the forward chain of the ones before it, recomputed
+  const int nc = COLS == 0 ? 0 : COLS == 1 ? min(e.n_col, 1) : e.n_col;
 #pragma unroll 1
-  for (int ci = e.n_col - 1; ci >= 0; --ci) {
+  for (int ci = nc - 1; ci >= 0; --ci) {
     const ColDev& cd = e.col[ci];
     if (!cd.has_collider) continue;
     // cotangents of the collider's center (0-2), velocity (3-5), angle (6) and angular speed (7) at this node
@@ -774,9 +781,11 @@ MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __rest
     int row = -1;
     if (act) {
       float vin[3] = {vpre[0], vpre[1], vpre[2]};
+      if (COLS > 1) {
 #pragma unroll 1
-      for (int cj = 0; cj < ci; ++cj)
-        if (e.col[cj].has_collider) collider_blend(e, e.col[cj], motion, t0, clock + ei, k_rel, i, j, k, vin);
+        for (int cj = 0; cj < ci; ++cj)
+          if (e.col[cj].has_collider) collider_blend(e, e.col[cj], motion, t0, clock + ei, k_rel, i, j, k, vin);
+      }
       collider_blend_adjoint(e, cd, motion, t0, clock + ei, k_rel, i, j, k, vin, vb, gmo, row);
     }
     // sum the wave's (one tile of one env) cotangents and add them to the collider's row of this substep in FP64
@@ -809,6 +818,7 @@ MD void grid_adjoint_tile(const EnvDev* __restrict__ envs, const int32_t* __rest
   if (l == 0) flags[tile] = 0u;
 }
 
+template <int COLS>
 __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__ envs,
                                                       const int32_t* __restrict__ tile_env, int64_t tile0,
                                                       int64_t ntiles, float* __restrict__ grid,
@@ -818,10 +828,11 @@ __global__ void __launch_bounds__(256) k_grid_adjoint(const EnvDev* __restrict__
   const int64_t tile = tile0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (tile >= tile0 + ntiles) return;
   if (flags[tile] == 0u) return;
-  grid_adjoint_tile(envs, tile_env, tile, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
+  grid_adjoint_tile<COLS>(envs, tile_env, tile, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion,
+                         gmotion);
 }
 
-template <int TILES>
+template <int TILES, int COLS>
 __global__ void __launch_bounds__(256) k_grid_adjoint_chunk(const EnvDev* __restrict__ envs,
                                                             const int32_t* __restrict__ tile_env, int64_t ntiles,
                                                             float* __restrict__ grid, uint32_t* __restrict__ flags,
@@ -842,8 +853,8 @@ __global__ void __launch_bounds__(256) k_grid_adjoint_chunk(const EnvDev* __rest
     const int bit = __ffsll((unsigned long long)m) - 1;
     m &= m - 1ull;
     if ((rank & 3) == wave)
-      grid_adjoint_tile(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel, motion,
-                        gmotion);
+      grid_adjoint_tile<COLS>(envs, tile_env, base + bit, threadIdx.x & 63, grid, flags, gcot, clock, t0, k_rel,
+                             motion, gmotion);
   }
 }
 
@@ -1192,42 +1203,61 @@ void launch_p2g_direct(const float* st, int64_t N, const EnvDev* envs, const Wor
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_p2g_direct, dim3(n_items), dim3(256), 0, s, st, N, envs, items, grid, flags, errs, k_call);
 }
+#define MPMX_BY_COLS(cols, LAUNCH) \
+  do {                                \
+    if ((cols) == 0) LAUNCH(0);       \
+    else if ((cols) == 1) LAUNCH(1);  \
+    else LAUNCH(kMaxColliders);       \
+  } while (0)
 void launch_grid_update(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                         uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear, const float* motion,
-                        hipStream_t s) {
+                        hipStream_t s, int cols) {
   if (ntiles == 0) return;
-  hipLaunchKernelGGL(k_grid_update, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid, flags,
-                     clock, t0, k_rel, clear, motion);
+  const dim3 g(nblk(ntiles, 4));
+#define MPMX_L(C) hipLaunchKernelGGL(k_grid_update<C>, g, dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid, flags, \
+                                     clock, t0, k_rel, clear, motion)
+  MPMX_BY_COLS(cols, MPMX_L);
+#undef MPMX_L
 }
 void launch_grid_adjoint(const EnvDev* envs, const int32_t* tile_env, int64_t tile0, int64_t ntiles, float* grid,
                          uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel, const float* motion,
-                         double* gmotion, hipStream_t s) {
+                         double* gmotion, hipStream_t s, int cols) {
   if (ntiles == 0) return;
-  hipLaunchKernelGGL(k_grid_adjoint, dim3(nblk(ntiles, 4)), dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid,
-                     flags, gcot, clock, t0, k_rel, motion, gmotion);
+  const dim3 g(nblk(ntiles, 4));
+#define MPMX_L(C) hipLaunchKernelGGL(k_grid_adjoint<C>, g, dim3(256), 0, s, envs, tile_env, tile0, ntiles, grid, flags, \
+                                     gcot, clock, t0, k_rel, motion, gmotion)
+  MPMX_BY_COLS(cols, MPMX_L);
+#undef MPMX_L
 }
 void launch_grid_update_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                 uint32_t* flags, const int32_t* clock, double t0, int k_rel, int clear,
-                                const float* motion, int tiles, hipStream_t s) {
+                                const float* motion, int tiles, hipStream_t s, int cols) {
   if (ntiles == 0) return;
-  if (tiles == 16)
-    hipLaunchKernelGGL(k_grid_update_chunk<16>, dim3((unsigned)((ntiles + 15) / 16)), dim3(256), 0, s, envs, tile_env,
-                       ntiles, grid, flags, clock, t0, k_rel, clear, motion);
-  else
-    hipLaunchKernelGGL(k_grid_update_chunk<64>, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env,
-                       ntiles, grid, flags, clock, t0, k_rel, clear, motion);
+  const dim3 g((unsigned)((ntiles + tiles - 1) / tiles));
+#define MPMX_L16(C) hipLaunchKernelGGL((k_grid_update_chunk<16, C>), g, dim3(256), 0, s, envs, tile_env, ntiles, grid, \
+                                       flags, clock, t0, k_rel, clear, motion)
+#define MPMX_L64(C) hipLaunchKernelGGL((k_grid_update_chunk<64, C>), g, dim3(256), 0, s, envs, tile_env, ntiles, grid, \
+                                       flags, clock, t0, k_rel, clear, motion)
+  if (tiles == 16) MPMX_BY_COLS(cols, MPMX_L16);
+  else MPMX_BY_COLS(cols, MPMX_L64);
+#undef MPMX_L16
+#undef MPMX_L64
 }
 void launch_grid_adjoint_chunked(const EnvDev* envs, const int32_t* tile_env, int64_t ntiles, float* grid,
                                  uint32_t* flags, float* gcot, const int32_t* clock, double t0, int k_rel,
-                                 const float* motion, double* gmotion, int tiles, hipStream_t s) {
+                                 const float* motion, double* gmotion, int tiles, hipStream_t s, int cols) {
   if (ntiles == 0) return;
-  if (tiles == 16)
-    hipLaunchKernelGGL(k_grid_adjoint_chunk<16>, dim3((unsigned)((ntiles + 15) / 16)), dim3(256), 0, s, envs, tile_env,
-                       ntiles, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
-  else
-    hipLaunchKernelGGL(k_grid_adjoint_chunk<64>, dim3((unsigned)((ntiles + 63) / 64)), dim3(256), 0, s, envs, tile_env,
-                       ntiles, grid, flags, gcot, clock, t0, k_rel, motion, gmotion);
+  const dim3 g((unsigned)((ntiles + tiles - 1) / tiles));
+#define MPMX_L16(C) hipLaunchKernelGGL((k_grid_adjoint_chunk<16, C>), g, dim3(256), 0, s, envs, tile_env, ntiles, grid, \
+                                       flags, gcot, clock, t0, k_rel, motion, gmotion)
+#define MPMX_L64(C) hipLaunchKernelGGL((k_grid_adjoint_chunk<64, C>), g, dim3(256), 0, s, envs, tile_env, ntiles, grid, \
+                                       flags, gcot, clock, t0, k_rel, motion, gmotion)
+  if (tiles == 16) MPMX_BY_COLS(cols, MPMX_L16);
+  else MPMX_BY_COLS(cols, MPMX_L64);
+#undef MPMX_L16
+#undef MPMX_L64
 }
+#undef MPMX_BY_COLS
 void launch_grid_clear_flagged(int64_t ntiles, float* grid, uint32_t* flags, hipStream_t s) {
   if (ntiles == 0) return;
   hipLaunchKernelGGL(k_grid_clear_flagged, dim3(nblk(ntiles, 4)), dim3(256), 0, s, ntiles, grid, flags);

@@ -116,6 +116,7 @@ struct mpm_batch {
   int fuse_adj = 0;   // 1: P2G adjoint of substep k and G2P adjoint of substep k - 1 in one kernel
   int xcd = 0;        // 1: order each launch's items so that the blocks one XCD receives take a contiguous run
   int grid_list = 0;  // 1 / 2: the grid passes take 64 / 16 tiles per block and run only the flagged ones
+  int max_col = 0;     // most colliders an env holds (slots in use): picks the grid passes' compiled variant
 
   // hipGraph replay of whole segments (batched mode): captured on a private
   // stream, replayed on the caller's stream, keyed by what the launches depend on
@@ -245,10 +246,10 @@ void batched_grid(mpm_batch* b, int gi, int clear, int k_rel) {
   Span sp(b, KC_GRID);
   if (b->grid_list)
     launch_grid_update_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0,
-                               k_rel, clear, b->motion_d, b->grid_list == 2 ? 16 : 64, b->stream);
+                               k_rel, clear, b->motion_d, b->grid_list == 2 ? 16 : 64, b->stream, b->max_col);
   else
     launch_grid_update(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->clock, 0.0, k_rel,
-                       clear, b->motion_d, b->stream);
+                       clear, b->motion_d, b->stream, b->max_col);
 }
 
 void batched_g2p(mpm_batch* b, const float* in, float* out, int gi, int kc) {
@@ -292,7 +293,7 @@ void substep(mpm_batch* b, const float* in, float* out, int gi, int clear, int k
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
       { Span sp(b, KC_P2G); launch_p2g_direct(in, b->N, b->envs_d, b->items_d + i0, ni, g, fl, b->errs, kc, s); }
-      { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, b->motion_d, s); }
+      { Span sp(b, KC_GRID); launch_grid_update(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->clock, 0.0, k_rel, clear, b->motion_d, s, b->max_col); }
       { Span sp(b, KC_G2P); launch_g2p_direct(in, out, b->N, b->envs_d, b->items_d + i0, ni, g, b->errs, kc, s); }
     }
   } else {
@@ -322,10 +323,11 @@ void batched_grid_adj(mpm_batch* b, int gi, int k_rel) {
   Span sp(b, KC_GRID_ADJ);
   if (b->grid_list)
     launch_grid_adjoint_chunked(b->envs_d, b->tile_env_d, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock,
-                                0.0, k_rel, b->motion_d, b->gmotion_d, b->grid_list == 2 ? 16 : 64, b->stream);
+                                0.0, k_rel, b->motion_d, b->gmotion_d, b->grid_list == 2 ? 16 : 64, b->stream,
+                                b->max_col);
   else
     launch_grid_adjoint(b->envs_d, b->tile_env_d, 0, b->n_tiles, b->grid[gi], b->flags[gi], b->gcot, b->clock, 0.0,
-                        k_rel, b->motion_d, b->gmotion_d, b->stream);
+                        k_rel, b->motion_d, b->gmotion_d, b->stream, b->max_col);
 }
 
 void batched_p2g_adj(mpm_batch* b, const float* st, const float* cot_in, float* cot_out, int kc) {
@@ -367,7 +369,7 @@ void adjoint_substep(mpm_batch* b, const float* st, const float* st_next, const 
       const EnvDev& eh = b->envs_h[e];
       const int64_t nt = (int64_t)eh.T * eh.T * eh.T;
       { Span sp(b, KC_G2P_ADJ); launch_g2p_adjoint_direct(st, st_next, cot_in, b->part, b->N, b->envs_d, b->items_d + i0, ni, g, b->gcot, b->pacc, kc, s); }
-      { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, b->motion_d, b->gmotion_d, s); }
+      { Span sp(b, KC_GRID_ADJ); launch_grid_adjoint(b->envs_d, b->tile_env_d, eh.tile_off, nt, g, fl, b->gcot, b->clock, 0.0, k_rel, b->motion_d, b->gmotion_d, s, b->max_col); }
       { Span sp(b, KC_P2G_ADJ); launch_p2g_adjoint_direct(st, b->part, cot_out, b->N, b->envs_d, b->items_d + i0, ni, b->gcot, b->pacc, kc, cot_in, s); }
     }
   } else {
@@ -574,6 +576,12 @@ int upload_items(mpm_batch* b) {
 }
 
 int upload_envs(mpm_batch* b) {
+  int most = 0;
+  for (const EnvDev& e : b->envs_h) most = std::max(most, (int)e.n_col);
+  if (most != b->max_col) {
+    b->max_col = most;
+    drop_graphs(b);   // captured grid passes name their kernel variant
+  }
   HIPC(b, hipMemcpyAsync(b->envs_d, b->envs_h.data(), sizeof(EnvDev) * b->E, hipMemcpyHostToDevice, b->stream));
   const int rc = upload_items(b);
   if (rc != MPM_OK) return rc;

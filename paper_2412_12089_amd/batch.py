@@ -329,37 +329,56 @@ class Batch:
         return ms.value, int(n)
 
 
+def _slots(spec) -> list:
+    """The env's colliders by slot (slot 0: `collider`, then `more_colliders`; None where a slot is empty)."""
+    return [spec.collider] + list(getattr(spec, "more_colliders", ()))
+
+
 class MPMRollout(torch.autograd.Function):
     """s_S = f^S(s_0; params, actions, centers, spins) through the library,
     differentiable in s_0, params, actions, centers and spins.
 
     params: [E, 8] float64 (E, nu, rho, Vp, sigma_y, K, gamma, 0) per env.
-    actions: None or [E, S, 3] per-substep velocities of each env's box
-    collider; spins: None or [E, S] per-substep angular speeds about the box's
-    axis (needs actions; default: the box's constant angular speed); centers:
-    None or [E, 3] the boxes' centers at the first substep (default: the
-    centers the envs were created with). Rows of envs without a collider are
+    actions: None, [E, S, 3] per-substep velocities of each env's first
+    collider, or [E, K, S, 3] of its colliders in slots 0 .. K-1; spins: None,
+    [E, S] or [E, K, S] per-substep angular speeds about each collider's axis
+    (needs actions; default: the collider's constant angular speed); centers:
+    None, [E, 3] or [E, K, 3] the colliders' centers at the first substep
+    (default: the centers the envs were created with). Rows of empty slots are
     ignored and get zero gradients. If the batch has been re-used since this
     call's forward, the backward first re-runs the forward from the saved
     inputs (frame-level checkpoint), so calls can be chained.
     """
 
     @staticmethod
+    def _per_slot(t, dims):
+        """[E, K, ...] view of an input given per slot or for slot 0 alone."""
+        if t is None:
+            return None
+        return t if t.dim() == dims + 1 else t.unsqueeze(1)
+
+    @staticmethod
     def _setup(batch: Batch, n_substeps: int, x, v, Cm, F, params, actions, centers, spins):
         prm = params.detach().to("cpu", torch.float64).numpy()
         for i, e in enumerate(batch.envs):
             batch.set_material(i, e.material, prm[i])
-        if centers is not None:
-            cen = centers.detach().to("cpu", torch.float64).numpy()
+        cen = MPMRollout._per_slot(centers, 2)
+        if cen is not None:
+            cen = cen.detach().to("cpu", torch.float64).numpy()
             for i, e in enumerate(batch.envs):
-                if e.collider is not None:
-                    batch.set_collider(i, e.collider, center=cen[i])
-        if actions is not None:
-            act = actions.detach().to("cpu", torch.float32).numpy()
-            spn = None if spins is None else spins.detach().to("cpu", torch.float32).numpy()
+                for k, c in enumerate(_slots(e)[:cen.shape[1]]):
+                    if c is not None:
+                        batch.set_collider(i, c, center=cen[i, k], index=k)
+        act = MPMRollout._per_slot(actions, 3)
+        if act is not None:
+            act = act.detach().to("cpu", torch.float32).numpy()
+            spn = MPMRollout._per_slot(spins, 2)
+            spn = None if spn is None else spn.detach().to("cpu", torch.float32).numpy()
             for i, e in enumerate(batch.envs):
-                if e.collider is not None:
-                    batch.set_collider_motion(i, act[i, :n_substeps], None if spn is None else spn[i, :n_substeps])
+                for k, c in enumerate(_slots(e)[:act.shape[1]]):
+                    if c is not None:
+                        batch.set_collider_motion(i, act[i, k, :n_substeps],
+                                                  None if spn is None else spn[i, k, :n_substeps], index=k)
         batch.set_particles(x, v, Cm, F)
         batch.forward(n_substeps, record=True)
 
@@ -390,23 +409,31 @@ class MPMRollout(torch.autograd.Function):
         dx, dv, dC, dF, dp = b.backward(gx, gv, gC, gF)
         da = dcen = dsp = None
         if actions is not None:
-            da = torch.zeros(actions.shape, dtype=torch.float64)
-            dcen = torch.zeros(b.E, 3, dtype=torch.float64)
-            dsp = torch.zeros(b.E, actions.shape[1], dtype=torch.float64)
+            act = MPMRollout._per_slot(actions, 3)
+            K, S = act.shape[1], act.shape[2]
+            da = torch.zeros(b.E, K, S, 3, dtype=torch.float64)
+            dcen = torch.zeros(b.E, K, 3, dtype=torch.float64)
+            dsp = torch.zeros(b.E, K, S, dtype=torch.float64)
             for i, e in enumerate(b.envs):
-                if e.collider is not None:
-                    dvel, dc0, dom, _ = b.collider_grad(i, ctx.n_substeps, spin=True)
-                    da[i, :ctx.n_substeps] = torch.from_numpy(dvel)
-                    dcen[i] = torch.from_numpy(dc0)
-                    dsp[i, :ctx.n_substeps] = torch.from_numpy(dom)
-            da = da.to(actions.device, actions.dtype)
+                for k, c in enumerate(_slots(e)[:K]):
+                    if c is not None:
+                        dvel, dc0, dom, _ = b.collider_grad(i, ctx.n_substeps, spin=True, index=k)
+                        da[i, k, :ctx.n_substeps] = torch.from_numpy(dvel)
+                        dcen[i, k] = torch.from_numpy(dc0)
+                        dsp[i, k, :ctx.n_substeps] = torch.from_numpy(dom)
+            da = da.reshape(actions.shape).to(actions.device, actions.dtype)
         if centers is None:
             dcen = None
         else:
-            if dcen is None:   # a fixed-velocity box: the start center matters, its gradient is not computed
+            if dcen is None:   # a fixed-velocity collider: the start center matters, its gradient is not computed
                 raise ValueError("gradients w.r.t. centers need actions (a prescribed motion)")
+            dcen = dcen[:, :MPMRollout._per_slot(centers, 2).shape[1]].reshape(centers.shape)
             dcen = dcen.to(centers.device, centers.dtype)
-        dsp = None if spins is None else dsp[:, :spins.shape[1]].to(spins.device, spins.dtype)
+        if spins is None:
+            dsp = None
+        else:
+            sp = MPMRollout._per_slot(spins, 2)
+            dsp = dsp[:, :sp.shape[1], :sp.shape[2]].reshape(spins.shape).to(spins.device, spins.dtype)
         return None, None, dx, dv, dC, dF, dp.to(params.device, params.dtype), da, dcen, dsp
 
 

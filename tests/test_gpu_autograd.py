@@ -115,3 +115,46 @@ def test_autograd_function_matches_central_differences():
             assert abs(fd - an) <= 1e-2 * abs(an)
     finally:
         batch.close()
+
+
+def test_autograd_drives_several_colliders():
+    # actions [E, K, S, 3] and spins [E, K, S] on a gripper's first two slots (a jaw and a finger) through the
+    # autograd Function: each slot's action cotangents against the oracle with that slot driven alone (the
+    # other slot keeps its constant motion in both)
+    import dataclasses
+    from test_gpu_parity import GRIP
+    from paper_2412_12089_amd.batch import Batch, rollout
+    dev = torch.device("cuda:0")
+    spec = make_env(scenes.FLUID_TAIT, N=2500, seed=70, collider=GRIP[0], v_scale=0.2)
+    spec = dataclasses.replace(spec, more_colliders=GRIP[1:])
+    rng = np.random.default_rng(71)
+    wx = rng.standard_normal((spec.n_particles, 3)).astype(np.float32)
+    wxt = torch.from_numpy(wx).to(dev)
+    for slot in (0, 1):
+        col = GRIP[slot]
+        vel = (np.array(col.velocity) + 0.3 * rng.standard_normal((S, 3))).astype(np.float32)
+        om = (col.omega + 2.0 * rng.standard_normal(S)).astype(np.float32)
+        act = np.zeros((1, 2, S, 3), np.float32)
+        spn = np.zeros((1, 2, S), np.float32)
+        for k in (0, 1):   # the other slot moves at its constant velocity and spin
+            act[0, k] = GRIP[k].velocity
+            spn[0, k] = GRIP[k].omega
+        act[0, slot], spn[0, slot] = vel, om
+        st = [torch.from_numpy(np.asarray(a, np.float32)).to(dev).requires_grad_(True) for a in (spec.x, spec.v, spec.C, spec.F)]
+        params = torch.from_numpy(spec.params()[None]).to(dev).requires_grad_(True)
+        at = torch.from_numpy(act).to(dev).requires_grad_(True)
+        sp = torch.from_numpy(spn).to(dev).requires_grad_(True)
+        batch = Batch([spec], max_substeps=S, ckpt_every=K)
+        try:
+            out = rollout(batch, S, *st, params, at, None, sp)
+            (out[0] * wxt).sum().backward()
+        finally:
+            batch.close()
+        env, prm, st0 = O.env_from_spec(spec)
+        cot = (torch.from_numpy(wx).double(), None, None, None)
+        _, _, gvel, _, gom, _ = O.rollout_vjp(env, prm, st0, S, cot, vel=torch.from_numpy(vel).double(),
+                                               omega=torch.from_numpy(om).double(), col=slot)
+        ea = relerr(at.grad[0, slot].cpu().numpy(), gvel.numpy())
+        es = relerr(sp.grad[0, slot].cpu().numpy(), gom.numpy())
+        announce(f"slot {slot} driven: actions rel {ea:.2e}, spins rel {es:.2e}")
+        assert ea < 1e-3 and es < 1e-3

@@ -809,6 +809,11 @@ def test_collider_slots_gaps_removal_and_errors():
     S = 6
     b = Batch([spec], max_substeps=S, ckpt_every=3)
     try:
+        # one collider first (its launches are captured in graphs), then a second one in slot 2: the grid
+        # passes must switch to the variant for several colliders
+        b.set_particles_from_specs()
+        b.forward(S)
+        st_one = tuple(to_np(t) for t in b.get_particles(env=0))
         b.set_collider(0, GRIP[2], index=2)
         b.set_particles_from_specs()
         b.forward(S)
@@ -836,4 +841,5 @@ def test_collider_slots_gaps_removal_and_errors():
     check_state(st2, tuple(t.numpy() for t in (x, v, Cm, F)), "slots 0 and 2", spec.x, S)
     (x, v, Cm, F), _ = O.rollout(env, prm, st0, S)
     check_state(st1, tuple(t.numpy() for t in (x, v, Cm, F)), "slot 2 removed", spec.x, S)
+    check_state(st_one, tuple(t.numpy() for t in (x, v, Cm, F)), "slot 0 alone", spec.x, S)
     assert np.abs(st2[1] - st1[1]).max() > 1e-3

@@ -107,6 +107,82 @@ class PushEnv:
 
 
 @dataclasses.dataclass
+class SqueezeTask:
+    n_envs: int = 8
+    n: int = 32
+    n_particles: int = 1500
+    substeps: int = 20          # simulation substeps per env step
+    dt: float = 2e-4
+    max_speed: float = 1.5      # jaw speed at |a| = 1 (m/s)
+    subsample: int = 4          # every subsample-th particle enters the observation and reward
+    reward_scale: float = 300.0
+    action_cost: float = 1e-3
+    seed: int = 0
+
+
+class SqueezeEnv:
+    """A soft cube between two jaws (two box colliders of one env, slots 0 and
+    1), each driven by its own velocity: the actions are both jaws' velocities
+    and the reward is the rise of the cube's centre of mass (squeezing it
+    makes it bulge up, dragging it lifts it by friction)."""
+    obs_dim = 13
+    act_dim = 6
+
+    def __init__(self, task: SqueezeTask, device=None):
+        self.task = task
+        self.device = device or torch.device("cuda:0")
+        rng = np.random.Generator(np.random.PCG64(task.seed))
+        specs = []
+        for _ in range(task.n_envs):
+            lo = np.array([0.42, 0.42, 0.16]) + rng.uniform(-0.02, 0.02, size=3)
+            side = np.array([0.12, 0.12, 0.12])
+            x = scenes.uniform_points(rng, lo, side, task.n_particles)
+            C, F = scenes._rest_state(task.n_particles)
+            jaw = lambda cx: scenes.BoxCollider(center=(float(cx), float(lo[1] + 0.06), float(lo[2] + 0.06)),
+                                                half=(0.03, 0.07, 0.07), velocity=(0.0, 0.0, 0.0),
+                                                alpha=2.0 * task.n, mu_b=0.8)
+            specs.append(scenes.EnvSpec(n=task.n, dt=task.dt, material=scenes.NEOHOOKEAN, E=5e3, nu=0.3, rho=1e3,
+                                        Vp=float(np.prod(side)) / task.n_particles, x=x, v=np.zeros_like(x), C=C,
+                                        F=F, collider=jaw(lo[0] - 0.04), more_colliders=(jaw(lo[0] + 0.16),)))
+        self.specs = specs
+        self.batch = Batch(specs, max_substeps=task.substeps, ckpt_every=task.substeps, mode="batched",
+                           device=self.device)
+        self.params = torch.tensor(np.stack([e.params() for e in specs]), dtype=torch.float64)
+        self.w = observe.subsample_weights(self.batch, task.subsample)
+        cat = lambda k: torch.from_numpy(np.concatenate([getattr(e, k) for e in specs], axis=0)).to(self.device)
+        self.init_state = tuple(cat(k) for k in ("x", "v", "C", "F"))
+        self.init_centers = torch.tensor([[e.collider.center, e.more_colliders[0].center] for e in specs],
+                                         dtype=torch.float32)
+
+    def reset(self):
+        return tuple(t.clone() for t in self.init_state), self.init_centers.clone()
+
+    def stats(self, state):
+        m = observe.moments(self.batch, state[0], state[1], self.w)
+        return observe.center_of_mass(m), observe.mean_velocity(m), observe.height_variance(m)
+
+    def obs(self, state, centers):
+        com, vbar, var_z = self.stats(state)
+        jaws = (centers.to(com.device).double().reshape(-1, 6) - 0.4) * 10.0
+        return torch.cat([(com - 0.4) * 10.0, vbar, var_z[:, None] * 1e3, jaws], 1).float()
+
+    def step(self, state, centers, a):
+        """One env step, differentiable in state, centers [E, 2, 3] and a [E, 6] (on the CPU, float32)."""
+        T = self.task
+        a2 = a.reshape(-1, 2, 3)
+        vel = (T.max_speed * a2)[:, :, None, :].expand(-1, -1, T.substeps, -1).contiguous()
+        z0 = self.stats(state)[0][:, 2]
+        nxt = rollout(self.batch, T.substeps, *state, self.params, vel, centers)
+        new_centers = centers + (T.dt * T.substeps * T.max_speed) * a2
+        z1 = self.stats(nxt)[0][:, 2]
+        r = T.reward_scale * (z1 - z0).float().cpu() - T.action_cost * (a ** 2).sum(1)
+        return nxt, new_centers, r
+
+    def close(self):
+        self.batch.close()
+
+
+@dataclasses.dataclass
 class HandTask:
     n_envs: int = 16
     substeps: int = 16          # rigid-body substeps per env step (one 1/60 s frame)

@@ -117,7 +117,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dam_break",
-                    choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh", "handflip_shape"])
+                    choices=["batched_corot", "uneven_mixed", "dam_break", "single_nh", "handflip_shape",
+                             "handflip_gripper"])
     ap.add_argument("--extra", default="batched_corot,uneven_mixed",
                     help="further workloads timed (autotuned, batched, fwd+bwd) and reported beside the headline")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-env mode (0: skip)")

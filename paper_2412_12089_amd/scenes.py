@@ -22,6 +22,7 @@ tool assets are not available. Sizes follow the five benchmark workloads:
 from __future__ import annotations
 
 import dataclasses
+import math
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -209,6 +210,26 @@ def handflip_shape(seed: int = 6, n_envs: int = 128, n_per_env: int = 2500, n_su
     return Workload("handflip_shape", envs, n_substeps, ckpt_every, ws)
 
 
+def handflip_gripper(seed: int = 6, n_envs: int = 128, n_per_env: int = 2500, n_substeps: int = 40,
+                     ckpt_every: int = 10) -> Workload:
+    """handflip_shape with a four-finger gripper in every env: four capsules
+    (half length 0.06, radius 0.02) around the dough block, closing in on it
+    from four sides and turning slowly about their own axis, so the grid
+    passes run their several-collider variant."""
+    wl = handflip_shape(seed, n_envs, n_per_env, n_substeps, ckpt_every)
+    envs = []
+    for e in wl.envs:
+        c = e.x.mean(0).astype(np.float64)
+        fingers = []
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            ctr = (float(c[0] + 0.1 * dx), float(c[1] + 0.1 * dy), float(c[2]))
+            fingers.append(capsule_collider(center=ctr, half_length=0.06, radius=0.02,
+                                            velocity=(-0.3 * dx, -0.3 * dy, 0.0), alpha=96.0, mu_b=0.5,
+                                            axis=(0.0, 0.0, 1.0), angle=0.5 * math.pi * abs(dy), omega=0.5))
+        envs.append(dataclasses.replace(e, collider=fingers[0], more_colliders=tuple(fingers[1:])))
+    return Workload("handflip_gripper", envs, n_substeps, ckpt_every, wl.loss_weights)
+
+
 MIXED_MATERIALS = (
     dict(material=NEOHOOKEAN, E=5e3, nu=0.3),
     dict(material=VONMISES, E=5e3, nu=0.2, sigma_y=50.0),
@@ -302,6 +323,7 @@ def serving_stream(seed: int = 5, rate: float = 200.0, duration: float = 60.0,
 WORKLOADS = {
     "single_nh": single_nh,
     "handflip_shape": handflip_shape,
+    "handflip_gripper": handflip_gripper,
     "batched_corot": batched_corot,
     "uneven_mixed": uneven_mixed,
     "dam_break": dam_break,
